@@ -1,0 +1,1012 @@
+/*
+ * oracle.c -- plain CPU FP64 reference for the coupled block-sparse solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no code, header or helper with the GPU
+ * path.
+ *
+ * What it computes (paper: arXiv 2403.07882):
+ *   - the coupled system A_ii U_i + sum_N A_ij U_j = b_i of Eq. (coupl_system)
+ *     with n x n blocks on a face-neighbour stencil (Sec. 2);
+ *   - the conversion of face-addressed LDU blocks (row-major n x n, packed
+ *     block after block) into block CSR, i.e. the permutation step of
+ *     Algorithm amgxFoam and Fig. block_amgx (Sec. 2.3): same pattern, indices
+ *     referring to blocks instead of scalars;
+ *   - preconditioned Krylov solves of that system (BiCGStab, flexible
+ *     GMRES) with block-Jacobi, DILU-smoothed or block-Jacobi-smoothed
+ *     aggregation AMG (the solver families named in Sec. 2.3 and used in
+ *     Sec. 4.1), plus the transposed solve and the LDU gradient of
+ *     L(x(A, b)).
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   R1  upper[f] = A(lower_addr[f], upper_addr[f]);
+ *       lower[f] = A(upper_addr[f], lower_addr[f]).
+ *   R2  block-CSR rows hold their columns in ascending order, diagonal inline.
+ *   R9  strength w_ij = 1/2 (|A_ij|_F + |A_ji|_F) / max(|A_ii|_F, |A_jj|_F).
+ *   R10 coarse operator: Galerkin P^T A P with piecewise-constant P.
+ *
+ * Parity pins: every public function here is checked by the CPU tests
+ * against brute force, closed forms or textbook special cases.  The
+ * aggregation heuristic (orc_match) has no unique answer: "parity unpinned"
+ * for its exact output; only its properties are tested.
+ *
+ * Everything is FP64, sequential except for OpenMP loops over rows.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_NOT_CONVERGED 1
+#define ORC_ERR_ARG (-1)
+#define ORC_ERR_PATTERN (-2)
+#define ORC_ERR_SINGULAR (-3)
+#define ORC_ERR_BREAKDOWN (-4)
+#define ORC_ERR_OOM (-7)
+
+#define MAXLEV 32
+
+/* ------------------------------------------------------------------ */
+/* small dense helpers                                                 */
+/* ------------------------------------------------------------------ */
+
+/* Inverse of one n x n row-major block by Gauss-Jordan elimination with
+ * partial pivoting.  Returns 0, or -1 when a pivot is exactly zero or not
+ * finite. */
+static int inv_block(int n, const double *D, double *out)
+{
+    double a[8][16];
+    for (int r = 0; r < n; r++)
+        for (int c = 0; c < 2 * n; c++)
+            a[r][c] = (c < n) ? D[r * n + c] : (c - n == r ? 1.0 : 0.0);
+    for (int k = 0; k < n; k++) {
+        int p = k;
+        for (int r = k + 1; r < n; r++)
+            if (fabs(a[r][k]) > fabs(a[p][k])) p = r;
+        if (!(fabs(a[p][k]) > 0.0) || !isfinite(a[p][k])) return -1;
+        if (p != k)
+            for (int c = 0; c < 2 * n; c++) {
+                double t = a[k][c]; a[k][c] = a[p][c]; a[p][c] = t;
+            }
+        double piv = a[k][k];
+        for (int c = 0; c < 2 * n; c++) a[k][c] /= piv;
+        for (int r = 0; r < n; r++) {
+            if (r == k) continue;
+            double m = a[r][k];
+            if (m != 0.0)
+                for (int c = 0; c < 2 * n; c++) a[r][c] -= m * a[k][c];
+        }
+    }
+    for (int r = 0; r < n; r++)
+        for (int c = 0; c < n; c++) out[r * n + c] = a[r][n + c];
+    return 0;
+}
+
+/* y = B x for an n x n block */
+static void blk_mv(int n, const double *B, const double *x, double *y)
+{
+    for (int r = 0; r < n; r++) {
+        double s = 0.0;
+        for (int c = 0; c < n; c++) s += B[r * n + c] * x[c];
+        y[r] = s;
+    }
+}
+
+/* C = A B for n x n blocks */
+static void blk_mm(int n, const double *A, const double *B, double *C)
+{
+    for (int r = 0; r < n; r++)
+        for (int c = 0; c < n; c++) {
+            double s = 0.0;
+            for (int k = 0; k < n; k++) s += A[r * n + k] * B[k * n + c];
+            C[r * n + c] = s;
+        }
+}
+
+static double blk_frob(int n, const double *B)
+{
+    double s = 0.0;
+    for (int k = 0; k < n * n; k++) s += B[k] * B[k];
+    return sqrt(s);
+}
+
+/* slot of column j in row i of a block-CSR pattern with ascending columns,
+ * or -1 */
+static long find_slot(const int *rp, const int *col, int i, int j)
+{
+    int lo = rp[i], hi = rp[i + 1] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) / 2;
+        if (col[mid] == j) return mid;
+        if (col[mid] < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------ */
+/* vector kernels                                                      */
+/* ------------------------------------------------------------------ */
+static double dot(long m, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (long k = 0; k < m; k++) s += a[k] * b[k];
+    return s;
+}
+
+static double nrm2(long m, const double *a) { return sqrt(dot(m, a, a)); }
+
+/* ------------------------------------------------------------------ */
+/* a1: field packing (SoA fields <-> block AoS vector), Alg. amgxFoam  */
+/* ------------------------------------------------------------------ */
+void orc_pack(int N, int n, const double *soa, double *aos)
+{
+    for (int i = 0; i < N; i++)
+        for (int v = 0; v < n; v++) aos[(long)i * n + v] = soa[(long)v * N + i];
+}
+
+void orc_unpack(int N, int n, const double *aos, double *soa)
+{
+    for (int i = 0; i < N; i++)
+        for (int v = 0; v < n; v++) soa[(long)v * N + i] = aos[(long)i * n + v];
+}
+
+/* ------------------------------------------------------------------ */
+/* a2/a3: LDU -> block CSR (Sec. 2.3, Fig. block_amgx)                 */
+/* ------------------------------------------------------------------ */
+
+/* Validates the face list.  Returns ORC_OK or ORC_ERR_PATTERN (index out of
+ * range, self face, or the same unordered cell pair twice). */
+int orc_ldu_to_bcsr(int N, int F, int n, const int *la, const int *ua,
+                    const double *diag, const double *upper, const double *lower,
+                    int *row_ptr, int *col, double *val,
+                    int *diag_slot, int *upper_slot, int *lower_slot)
+{
+    if (N < 0 || F < 0 || n < 1 || n > 8) return ORC_ERR_ARG;
+    for (int f = 0; f < F; f++) {
+        if (la[f] < 0 || la[f] >= N || ua[f] < 0 || ua[f] >= N || la[f] == ua[f])
+            return ORC_ERR_PATTERN;
+    }
+    /* 1. count blocks per row: the diagonal plus one per face touching it */
+    for (int i = 0; i <= N; i++) row_ptr[i] = 0;
+    for (int i = 0; i < N; i++) row_ptr[i + 1] += 1;
+    for (int f = 0; f < F; f++) { row_ptr[la[f] + 1] += 1; row_ptr[ua[f] + 1] += 1; }
+    for (int i = 0; i < N; i++) row_ptr[i + 1] += row_ptr[i];
+    long nnzb = row_ptr[N];
+
+    /* 2. place every block into its row: source code s >= 0 is
+     *    diag (s = i), upper face (N + f) or lower face (N + F + f) */
+    long *src = (long *)malloc(sizeof(long) * (nnzb > 0 ? nnzb : 1));
+    int *fill = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
+    if (!src || !fill) { free(src); free(fill); return ORC_ERR_OOM; }
+    for (int i = 0; i < N; i++) fill[i] = row_ptr[i];
+    for (int i = 0; i < N; i++) { col[fill[i]] = i; src[fill[i]] = i; fill[i]++; }
+    for (int f = 0; f < F; f++) {
+        int r = la[f];
+        col[fill[r]] = ua[f]; src[fill[r]] = (long)N + f; fill[r]++;
+        r = ua[f];
+        col[fill[r]] = la[f]; src[fill[r]] = (long)N + F + f; fill[r]++;
+    }
+    /* 3. order each row by column (insertion sort) and reject duplicates */
+    int rc = ORC_OK;
+    for (int i = 0; i < N && rc == ORC_OK; i++) {
+        for (int a = row_ptr[i] + 1; a < row_ptr[i + 1]; a++) {
+            int c = col[a]; long s = src[a]; int b = a - 1;
+            while (b >= row_ptr[i] && col[b] > c) { col[b + 1] = col[b]; src[b + 1] = src[b]; b--; }
+            col[b + 1] = c; src[b + 1] = s;
+        }
+        for (int a = row_ptr[i] + 1; a < row_ptr[i + 1]; a++)
+            if (col[a] == col[a - 1]) { rc = ORC_ERR_PATTERN; break; }
+    }
+    if (rc == ORC_OK) {
+        /* 4. copy blocks into their slots and record the slot maps */
+        long bs = (long)n * n;
+        for (long k = 0; k < nnzb; k++) {
+            long s = src[k];
+            const double *from;
+            if (s < N) { from = diag + s * bs; if (diag_slot) diag_slot[s] = (int)k; }
+            else if (s < (long)N + F) { from = upper + (s - N) * bs; if (upper_slot) upper_slot[s - N] = (int)k; }
+            else { from = lower + (s - N - F) * bs; if (lower_slot) lower_slot[s - N - F] = (int)k; }
+            memcpy(val + k * bs, from, sizeof(double) * bs);
+        }
+    }
+    free(src); free(fill);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* a8: block SpMV, three independent routes                            */
+/* ------------------------------------------------------------------ */
+void orc_spmv_bcsr(int N, int n, const int *rp, const int *col, const double *val,
+                   const double *x, double *y)
+{
+    long bs = (long)n * n;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; i++) {
+        double acc[8] = {0};
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            const double *B = val + (long)k * bs;
+            const double *xj = x + (long)col[k] * n;
+            for (int r = 0; r < n; r++)
+                for (int c = 0; c < n; c++) acc[r] += B[r * n + c] * xj[c];
+        }
+        for (int r = 0; r < n; r++) y[(long)i * n + r] = acc[r];
+    }
+}
+
+/* y = A^T x: y_j = sum_i A_ij^T x_i (scatter form, sequential) */
+void orc_spmv_bcsr_t(int N, int n, const int *rp, const int *col, const double *val,
+                     const double *x, double *y)
+{
+    long bs = (long)n * n;
+    for (long k = 0; k < (long)N * n; k++) y[k] = 0.0;
+    for (int i = 0; i < N; i++)
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            const double *B = val + (long)k * bs;
+            int j = col[k];
+            for (int r = 0; r < n; r++)
+                for (int c = 0; c < n; c++) y[(long)j * n + c] += B[r * n + c] * x[(long)i * n + r];
+        }
+}
+
+/* Textbook face loop on the LDU form:
+ * y_i = D_i x_i + sum_{f: l(f)=i} U_f x_u(f) + sum_{f: u(f)=i} L_f x_l(f). */
+void orc_spmv_ldu(int N, int F, int n, const int *la, const int *ua,
+                  const double *diag, const double *upper, const double *lower,
+                  const double *x, double *y)
+{
+    long bs = (long)n * n;
+    double t[8];
+    for (int i = 0; i < N; i++) blk_mv(n, diag + (long)i * bs, x + (long)i * n, y + (long)i * n);
+    for (int f = 0; f < F; f++) {
+        blk_mv(n, upper + (long)f * bs, x + (long)ua[f] * n, t);
+        for (int r = 0; r < n; r++) y[(long)la[f] * n + r] += t[r];
+        blk_mv(n, lower + (long)f * bs, x + (long)la[f] * n, t);
+        for (int r = 0; r < n; r++) y[(long)ua[f] * n + r] += t[r];
+    }
+}
+
+/* Transposed block-CSR: column j of A becomes row j of A^T, each block
+ * transposed.  Rows of the result come out with ascending columns because
+ * rows of A are visited in ascending order. */
+void orc_transpose(int N, int n, const int *rp, const int *col, const double *val,
+                   int *rpT, int *colT, double *valT)
+{
+    long bs = (long)n * n;
+    for (int i = 0; i <= N; i++) rpT[i] = 0;
+    for (long k = 0; k < rp[N]; k++) rpT[col[k] + 1]++;
+    for (int i = 0; i < N; i++) rpT[i + 1] += rpT[i];
+    int *fill = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
+    for (int i = 0; i < N; i++) fill[i] = rpT[i];
+    for (int i = 0; i < N; i++)
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            int j = col[k], d = fill[j]++;
+            colT[d] = i;
+            for (int r = 0; r < n; r++)
+                for (int c = 0; c < n; c++) valT[(long)d * bs + c * n + r] = val[(long)k * bs + r * n + c];
+        }
+    free(fill);
+}
+
+/* ------------------------------------------------------------------ */
+/* a4: block inversion; dense LU for tiny systems and coarsest levels  */
+/* ------------------------------------------------------------------ */
+int orc_blockinv(long nb, int n, const double *D, double *Dinv, long *bad)
+{
+    long bs = (long)n * n;
+    for (long i = 0; i < nb; i++)
+        if (inv_block(n, D + i * bs, Dinv + i * bs)) { if (bad) *bad = i; return ORC_ERR_SINGULAR; }
+    return ORC_OK;
+}
+
+/* LU factorisation with partial pivoting, in place (row-major m x m). */
+static int lu_factor(int m, double *A, int *piv)
+{
+    for (int k = 0; k < m; k++) {
+        int p = k;
+        for (int r = k + 1; r < m; r++)
+            if (fabs(A[(long)r * m + k]) > fabs(A[(long)p * m + k])) p = r;
+        piv[k] = p;
+        if (!(fabs(A[(long)p * m + k]) > 0.0)) return -1;
+        if (p != k)
+            for (int c = 0; c < m; c++) {
+                double t = A[(long)k * m + c]; A[(long)k * m + c] = A[(long)p * m + c]; A[(long)p * m + c] = t;
+            }
+        for (int r = k + 1; r < m; r++) {
+            double l = A[(long)r * m + k] / A[(long)k * m + k];
+            A[(long)r * m + k] = l;
+            for (int c = k + 1; c < m; c++) A[(long)r * m + c] -= l * A[(long)k * m + c];
+        }
+    }
+    return 0;
+}
+
+static void lu_solve(int m, const double *LU, const int *piv, double *x)
+{
+    for (int k = 0; k < m; k++) {
+        int p = piv[k];
+        if (p != k) { double t = x[k]; x[k] = x[p]; x[p] = t; }
+    }
+    for (int r = 0; r < m; r++) {
+        double s = x[r];
+        for (int c = 0; c < r; c++) s -= LU[(long)r * m + c] * x[c];
+        x[r] = s;
+    }
+    for (int r = m - 1; r >= 0; r--) {
+        double s = x[r];
+        for (int c = r + 1; c < m; c++) s -= LU[(long)r * m + c] * x[c];
+        x[r] = s / LU[(long)r * m + r];
+    }
+}
+
+int orc_dense_solve(int m, const double *A, const double *b, double *x)
+{
+    double *LU = (double *)malloc(sizeof(double) * (size_t)m * m + 8);
+    int *piv = (int *)malloc(sizeof(int) * (m + 1));
+    memcpy(LU, A, sizeof(double) * (size_t)m * m);
+    int rc = lu_factor(m, LU, piv);
+    if (rc == 0) { memcpy(x, b, sizeof(double) * m); lu_solve(m, LU, piv, x); }
+    free(LU); free(piv);
+    return rc ? ORC_ERR_SINGULAR : ORC_OK;
+}
+
+/* dense row-major copy of a block-CSR matrix (m = N n) */
+static void to_dense(int N, int n, const int *rp, const int *col, const double *val, double *A)
+{
+    long m = (long)N * n, bs = (long)n * n;
+    memset(A, 0, sizeof(double) * m * m);
+    for (int i = 0; i < N; i++)
+        for (int k = rp[i]; k < rp[i + 1]; k++)
+            for (int r = 0; r < n; r++)
+                for (int c = 0; c < n; c++)
+                    A[((long)i * n + r) * m + (long)col[k] * n + c] = val[(long)k * bs + r * n + c];
+}
+
+/* ------------------------------------------------------------------ */
+/* a9: smoothers                                                       */
+/* ------------------------------------------------------------------ */
+
+/* extract the diagonal blocks and invert them */
+static int diag_inverse(int N, int n, const int *rp, const int *col, const double *val, double *Dinv)
+{
+    long bs = (long)n * n;
+    for (int i = 0; i < N; i++) {
+        long k = find_slot(rp, col, i, i);
+        if (k < 0 || inv_block(n, val + k * bs, Dinv + (long)i * bs)) return ORC_ERR_SINGULAR;
+    }
+    return ORC_OK;
+}
+
+/* One damped block-Jacobi sweep: x_out = x_in + omega D^{-1} (b - A x_in). */
+void orc_bjacobi_sweep(int N, int n, const int *rp, const int *col, const double *val,
+                       const double *Dinv, const double *b, const double *x_in,
+                       double *x_out, double omega)
+{
+    long bs = (long)n * n;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; i++) {
+        double r[8], z[8];
+        for (int q = 0; q < n; q++) r[q] = b[(long)i * n + q];
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            const double *B = val + (long)k * bs;
+            const double *xj = x_in + (long)col[k] * n;
+            for (int q = 0; q < n; q++)
+                for (int c = 0; c < n; c++) r[q] -= B[q * n + c] * xj[c];
+        }
+        blk_mv(n, Dinv + (long)i * bs, r, z);
+        for (int q = 0; q < n; q++) x_out[(long)i * n + q] = x_in[(long)i * n + q] + omega * z[q];
+    }
+}
+
+/* DILU (diagonal incomplete LU) for the ordering given by rank[]:
+ * j precedes i when rank[j] < rank[i].
+ *   E_i = A_ii - sum_{j precedes i, j adjacent} A_ij E_j^{-1} A_ji
+ * stores E_i^{-1}.  M = (E + L) E^{-1} (E + U) then has diag(M) = diag(A). */
+int orc_dilu_setup(int N, int n, const int *rp, const int *col, const double *val,
+                   const int *rank, double *Einv)
+{
+    long bs = (long)n * n;
+    int *order = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
+    for (int i = 0; i < N; i++) order[rank[i]] = i;
+    double E[64], T[64], U[64];
+    int rc = ORC_OK;
+    for (int q = 0; q < N && rc == ORC_OK; q++) {
+        int i = order[q];
+        long kd = find_slot(rp, col, i, i);
+        if (kd < 0) { rc = ORC_ERR_SINGULAR; break; }
+        memcpy(E, val + kd * bs, sizeof(double) * bs);
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            int j = col[k];
+            if (j == i || rank[j] >= rank[i]) continue;
+            long kji = find_slot(rp, col, j, i);
+            if (kji < 0) continue;              /* structurally one-sided entry */
+            blk_mm(n, val + (long)k * bs, Einv + (long)j * bs, T);    /* A_ij E_j^-1 */
+            blk_mm(n, T, val + kji * bs, U);                          /* ... A_ji    */
+            for (int e = 0; e < bs; e++) E[e] -= U[e];
+        }
+        if (inv_block(n, E, Einv + (long)i * bs)) rc = ORC_ERR_SINGULAR;
+    }
+    free(order);
+    return rc;
+}
+
+/* z = M^{-1} r for the DILU factorisation of orc_dilu_setup:
+ *   forward:  y_i = E_i^{-1} (r_i - sum_{j precedes i} A_ij y_j)
+ *   backward: z_i = y_i - E_i^{-1} sum_{j follows i} A_ij z_j            */
+void orc_dilu_apply(int N, int n, const int *rp, const int *col, const double *val,
+                    const int *rank, const double *Einv, const double *r, double *z)
+{
+    long bs = (long)n * n;
+    int *order = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
+    for (int i = 0; i < N; i++) order[rank[i]] = i;
+    double t[8], u[8];
+    for (int q = 0; q < N; q++) {
+        int i = order[q];
+        for (int e = 0; e < n; e++) t[e] = r[(long)i * n + e];
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            int j = col[k];
+            if (j == i || rank[j] >= rank[i]) continue;
+            blk_mv(n, val + (long)k * bs, z + (long)j * n, u);
+            for (int e = 0; e < n; e++) t[e] -= u[e];
+        }
+        blk_mv(n, Einv + (long)i * bs, t, z + (long)i * n);
+    }
+    for (int q = N - 1; q >= 0; q--) {
+        int i = order[q];
+        for (int e = 0; e < n; e++) t[e] = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            int j = col[k];
+            if (j == i || rank[j] <= rank[i]) continue;
+            blk_mv(n, val + (long)k * bs, z + (long)j * n, u);
+            for (int e = 0; e < n; e++) t[e] += u[e];
+        }
+        blk_mv(n, Einv + (long)i * bs, t, u);
+        for (int e = 0; e < n; e++) z[(long)i * n + e] -= u[e];
+    }
+    free(order);
+}
+
+/* ------------------------------------------------------------------ */
+/* a5/a6/a10: aggregation, Galerkin coarse operator, transfers         */
+/* ------------------------------------------------------------------ */
+
+/* per-slot strength weights (R9); diagonal slots get 0 */
+void orc_strength(int N, int n, const int *rp, const int *col, const double *val, double *w)
+{
+    long bs = (long)n * n;
+    for (int i = 0; i < N; i++) {
+        long kii = find_slot(rp, col, i, i);
+        double di = kii >= 0 ? blk_frob(n, val + kii * bs) : 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            int j = col[k];
+            if (j == i) { w[k] = 0.0; continue; }
+            long kji = find_slot(rp, col, j, i), kjj = find_slot(rp, col, j, j);
+            double aij = blk_frob(n, val + (long)k * bs);
+            double aji = kji >= 0 ? blk_frob(n, val + kji * bs) : 0.0;
+            double dj = kjj >= 0 ? blk_frob(n, val + kjj * bs) : 0.0;
+            double den = di > dj ? di : dj;
+            w[k] = den > 0.0 ? 0.5 * (aij + aji) / den : 0.0;
+        }
+    }
+}
+
+/* Sequential greedy pairwise matching on the weighted graph (rp, col, w).
+ * Nodes are visited in index order; an unmatched node pairs with its
+ * strongest unmatched neighbour (ties: smaller index).  A node left without
+ * an unmatched neighbour joins the aggregate of its strongest neighbour, or
+ * stays alone.  Returns the number of aggregates.  (Heuristic: exact output
+ * is parity unpinned; properties are tested.) */
+int orc_match(int N, const int *rp, const int *col, const double *w, int *agg)
+{
+    int nc = 0;
+    for (int i = 0; i < N; i++) agg[i] = -1;
+    for (int i = 0; i < N; i++) {
+        if (agg[i] >= 0) continue;
+        int best = -1; double bw = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            int j = col[k];
+            if (j == i || agg[j] >= 0 || !(w[k] > 0.0)) continue;
+            if (w[k] > bw || (w[k] == bw && j < best)) { bw = w[k]; best = j; }
+        }
+        if (best >= 0) { agg[i] = agg[best] = nc++; continue; }
+        for (int k = rp[i]; k < rp[i + 1]; k++) {
+            int j = col[k];
+            if (j == i || agg[j] < 0 || !(w[k] > 0.0)) continue;
+            if (w[k] > bw || (w[k] == bw && j < best)) { bw = w[k]; best = j; }
+        }
+        agg[i] = best >= 0 ? agg[best] : nc++;
+    }
+    return nc;
+}
+
+/* members of each aggregate, ascending: mp[nc+1], mem[N] */
+static void members(int N, const int *agg, int nc, int *mp, int *mem)
+{
+    for (int I = 0; I <= nc; I++) mp[I] = 0;
+    for (int i = 0; i < N; i++) mp[agg[i] + 1]++;
+    for (int I = 0; I < nc; I++) mp[I + 1] += mp[I];
+    int *fill = (int *)malloc(sizeof(int) * (nc > 0 ? nc : 1));
+    for (int I = 0; I < nc; I++) fill[I] = mp[I];
+    for (int i = 0; i < N; i++) mem[fill[agg[i]]++] = i;
+    free(fill);
+}
+
+/* Coarse pattern of P^T A P: row I holds every aggregate J reached from a
+ * member of I.  Fills rpc[nc+1]; returns the number of coarse blocks. */
+long orc_rap_count(int N, const int *rp, const int *col, const int *agg, int nc, int *rpc)
+{
+    int *mp = (int *)malloc(sizeof(int) * (nc + 1)), *mem = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
+    int *mark = (int *)malloc(sizeof(int) * (nc > 0 ? nc : 1));
+    members(N, agg, nc, mp, mem);
+    for (int J = 0; J < nc; J++) mark[J] = -1;
+    rpc[0] = 0;
+    for (int I = 0; I < nc; I++) {
+        int cnt = 0;
+        for (int m = mp[I]; m < mp[I + 1]; m++) {
+            int i = mem[m];
+            for (int k = rp[i]; k < rp[i + 1]; k++) {
+                int J = agg[col[k]];
+                if (mark[J] != I) { mark[J] = I; cnt++; }
+            }
+        }
+        rpc[I + 1] = rpc[I] + cnt;
+    }
+    long nnz = rpc[nc];
+    free(mp); free(mem); free(mark);
+    return nnz;
+}
+
+/* A_c(I, J) = sum_{i in I, j in J} A(i, j)  (R10), columns ascending.
+ * Sums are taken in the order: members of I ascending, then row slots. */
+void orc_rap_fill(int N, int n, const int *rp, const int *col, const double *val,
+                  const int *agg, int nc, const int *rpc, int *colc, double *valc)
+{
+    long bs = (long)n * n;
+    int *mp = (int *)malloc(sizeof(int) * (nc + 1)), *mem = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
+    long *pos = (long *)malloc(sizeof(long) * (nc > 0 ? nc : 1));
+    members(N, agg, nc, mp, mem);
+    for (int J = 0; J < nc; J++) pos[J] = -1;
+    for (int I = 0; I < nc; I++) {
+        /* collect the distinct coarse columns, then sort them */
+        int cnt = rpc[I];
+        for (int m = mp[I]; m < mp[I + 1]; m++) {
+            int i = mem[m];
+            for (int k = rp[i]; k < rp[i + 1]; k++) {
+                int J = agg[col[k]];
+                if (pos[J] < 0) { pos[J] = 1; colc[cnt++] = J; }
+            }
+        }
+        for (int a = rpc[I] + 1; a < rpc[I + 1]; a++) {
+            int c = colc[a], b = a - 1;
+            while (b >= rpc[I] && colc[b] > c) { colc[b + 1] = colc[b]; b--; }
+            colc[b + 1] = c;
+        }
+        for (int a = rpc[I]; a < rpc[I + 1]; a++) {
+            pos[colc[a]] = a;
+            memset(valc + (long)a * bs, 0, sizeof(double) * bs);
+        }
+        for (int m = mp[I]; m < mp[I + 1]; m++) {
+            int i = mem[m];
+            for (int k = rp[i]; k < rp[i + 1]; k++) {
+                long a = pos[agg[col[k]]];
+                for (long e = 0; e < bs; e++) valc[a * bs + e] += val[(long)k * bs + e];
+            }
+        }
+        for (int a = rpc[I]; a < rpc[I + 1]; a++) pos[colc[a]] = -1;
+    }
+    free(mp); free(mem); free(pos);
+}
+
+/* r_c = P^T r: r_c[I] = sum_{i in I} r_i (ascending i) */
+void orc_restrict(int N, int n, const int *agg, const double *r, int nc, double *rc)
+{
+    memset(rc, 0, sizeof(double) * (size_t)nc * n);
+    for (int i = 0; i < N; i++)
+        for (int e = 0; e < n; e++) rc[(long)agg[i] * n + e] += r[(long)i * n + e];
+}
+
+/* x += P e: x_i += e[agg(i)] */
+void orc_prolong_add(int N, int n, const int *agg, const double *e, double *x)
+{
+    for (int i = 0; i < N; i++)
+        for (int q = 0; q < n; q++) x[(long)i * n + q] += e[(long)agg[i] * n + q];
+}
+
+/* ------------------------------------------------------------------ */
+/* a11: aggregation AMG hierarchy and V-cycle                          */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int N; int *rp, *col; double *val;
+    double *Dinv;            /* block-Jacobi smoother */
+    int *rank; double *Einv; /* DILU smoother */
+    int *agg; int nc;        /* map to the next level */
+    double *b, *x, *r;
+} olevel;
+
+typedef struct {
+    int n, nlev, smoother, nu1, nu2;
+    double omega;
+    olevel L[MAXLEV];
+    double *LU; int *piv; int m;   /* coarsest level, dense LU */
+} oamg;
+
+static void free_level(olevel *l)
+{
+    free(l->rp); free(l->col); free(l->val); free(l->Dinv); free(l->rank); free(l->Einv);
+    free(l->agg); free(l->b); free(l->x); free(l->r);
+}
+
+void orc_amg_free(void *h)
+{
+    oamg *A = (oamg *)h;
+    if (!A) return;
+    for (int l = 0; l < A->nlev; l++) free_level(&A->L[l]);
+    free(A->LU); free(A->piv); free(A);
+}
+
+/* Build the hierarchy.  smoother: 0 = damped block Jacobi, 1 = DILU.
+ * If aggs != NULL, level l uses the aggregate map aggs[off_l .. off_l+N_l)
+ * (concatenated in level order, n_agg_levels maps in total) instead of its
+ * own matching; ranks (same layout, one per row of every smoothed level)
+ * give the DILU ordering, else the natural order is used.
+ * Coarsening stops when N_l <= coarse_max, when matching stalls, or when
+ * the given maps run out.  Returns NULL on failure (singular blocks). */
+void *orc_amg_create(int N, int n, const int *rp, const int *col, const double *val,
+                     int coarse_max, int passes, int smoother, int nu1, int nu2,
+                     double omega, const int *aggs, int n_agg_levels, const int *ranks)
+{
+    oamg *A = (oamg *)calloc(1, sizeof(oamg));
+    long bs = (long)n * n;
+    A->n = n; A->smoother = smoother; A->nu1 = nu1; A->nu2 = nu2; A->omega = omega;
+    /* level 0: own copy */
+    olevel *L0 = &A->L[0];
+    L0->N = N;
+    long nnz = rp[N];
+    L0->rp = (int *)malloc(sizeof(int) * (N + 1)); memcpy(L0->rp, rp, sizeof(int) * (N + 1));
+    L0->col = (int *)malloc(sizeof(int) * (nnz + 1)); memcpy(L0->col, col, sizeof(int) * nnz);
+    L0->val = (double *)malloc(sizeof(double) * (nnz * bs + 1)); memcpy(L0->val, val, sizeof(double) * nnz * bs);
+    long aoff = 0, roff = 0;
+    int l = 0;
+    for (;;) {
+        olevel *c = &A->L[l];
+        int Nl = c->N;
+        c->b = (double *)calloc((size_t)Nl * n + 1, sizeof(double));
+        c->x = (double *)calloc((size_t)Nl * n + 1, sizeof(double));
+        c->r = (double *)calloc((size_t)Nl * n + 1, sizeof(double));
+        int last = (l + 1 >= MAXLEV);
+        if (aggs) last = last || (l >= n_agg_levels);
+        else last = last || (Nl <= coarse_max);
+        int *agg = NULL; int nc = 0;
+        if (!last) {
+            agg = (int *)malloc(sizeof(int) * (Nl > 0 ? Nl : 1));
+            if (aggs) {
+                nc = 0;
+                for (int i = 0; i < Nl; i++) { agg[i] = aggs[aoff + i]; if (agg[i] + 1 > nc) nc = agg[i] + 1; }
+                aoff += Nl;
+            } else {
+                /* `passes` rounds of pairwise matching, composed */
+                for (int i = 0; i < Nl; i++) agg[i] = i;
+                nc = Nl;
+                int *grp = c->rp, *gcol = c->col; double *gw = (double *)malloc(sizeof(double) * ((long)c->rp[Nl] + 1));
+                orc_strength(Nl, n, c->rp, c->col, c->val, gw);
+                int *own_rp = NULL, *own_col = NULL;
+                for (int p = 0; p < passes && nc > 1; p++) {
+                    int *a2 = (int *)malloc(sizeof(int) * nc);
+                    int nc2 = orc_match(nc, grp, gcol, gw, a2);
+                    for (int i = 0; i < Nl; i++) agg[i] = a2[agg[i]];
+                    if (p + 1 < passes) {
+                        /* coarse weight graph: sums of weights (scalar RAP) */
+                        int *rp2 = (int *)malloc(sizeof(int) * (nc2 + 1));
+                        long nz2 = orc_rap_count(nc, grp, gcol, a2, nc2, rp2);
+                        int *col2 = (int *)malloc(sizeof(int) * (nz2 + 1));
+                        double *w2 = (double *)malloc(sizeof(double) * (nz2 + 1));
+                        orc_rap_fill(nc, 1, grp, gcol, gw, a2, nc2, rp2, col2, w2);
+                        for (int I = 0; I < nc2; I++)
+                            for (int k = rp2[I]; k < rp2[I + 1]; k++) if (col2[k] == I) w2[k] = 0.0;
+                        free(own_rp); free(own_col); free(gw);
+                        own_rp = rp2; own_col = col2; grp = rp2; gcol = col2; gw = w2;
+                    }
+                    free(a2);
+                    nc = nc2;
+                }
+                free(own_rp); free(own_col); free(gw);
+                if (nc >= Nl) { free(agg); agg = NULL; last = 1; }   /* stalled */
+            }
+        }
+        if (last) break;
+        c->agg = agg; c->nc = nc;
+        olevel *d = &A->L[l + 1];
+        d->N = nc;
+        d->rp = (int *)malloc(sizeof(int) * (nc + 1));
+        long nz = orc_rap_count(Nl, c->rp, c->col, agg, nc, d->rp);
+        d->col = (int *)malloc(sizeof(int) * (nz + 1));
+        d->val = (double *)malloc(sizeof(double) * (nz * bs + 1));
+        orc_rap_fill(Nl, n, c->rp, c->col, c->val, agg, nc, d->rp, d->col, d->val);
+        l++;
+    }
+    A->nlev = l + 1;
+    /* smoothers on every level but the coarsest */
+    for (int q = 0; q + 1 < A->nlev; q++) {
+        olevel *c = &A->L[q];
+        if (smoother == 0) {
+            c->Dinv = (double *)malloc(sizeof(double) * ((long)c->N * bs + 1));
+            if (diag_inverse(c->N, n, c->rp, c->col, c->val, c->Dinv)) { orc_amg_free(A); return NULL; }
+        } else {
+            c->rank = (int *)malloc(sizeof(int) * (c->N + 1));
+            if (ranks) { for (int i = 0; i < c->N; i++) c->rank[i] = ranks[roff + i]; roff += c->N; }
+            else for (int i = 0; i < c->N; i++) c->rank[i] = i;
+            c->Einv = (double *)malloc(sizeof(double) * ((long)c->N * bs + 1));
+            if (orc_dilu_setup(c->N, n, c->rp, c->col, c->val, c->rank, c->Einv)) { orc_amg_free(A); return NULL; }
+        }
+    }
+    /* coarsest: dense LU */
+    olevel *cl = &A->L[A->nlev - 1];
+    A->m = cl->N * n;
+    A->LU = (double *)malloc(sizeof(double) * ((size_t)A->m * A->m + 1));
+    A->piv = (int *)malloc(sizeof(int) * (A->m + 1));
+    to_dense(cl->N, n, cl->rp, cl->col, cl->val, A->LU);
+    if (lu_factor(A->m, A->LU, A->piv)) { orc_amg_free(A); return NULL; }
+    return A;
+}
+
+int orc_amg_levels(void *h) { return ((oamg *)h)->nlev; }
+
+void orc_amg_level_info(void *h, int l, int *N, long *nnzb)
+{
+    oamg *A = (oamg *)h;
+    *N = A->L[l].N; *nnzb = A->L[l].rp[A->L[l].N];
+}
+
+static void smooth(oamg *A, olevel *c, const double *b, double *x)
+{
+    int n = A->n;
+    long m = (long)c->N * n;
+    if (A->smoother == 0) {
+        orc_bjacobi_sweep(c->N, n, c->rp, c->col, c->val, c->Dinv, b, x, c->r, A->omega);
+        memcpy(x, c->r, sizeof(double) * m);
+    } else {
+        double *d = (double *)malloc(sizeof(double) * (m + 1));
+        orc_spmv_bcsr(c->N, n, c->rp, c->col, c->val, x, c->r);
+        for (long k = 0; k < m; k++) c->r[k] = b[k] - c->r[k];
+        orc_dilu_apply(c->N, n, c->rp, c->col, c->val, c->rank, c->Einv, c->r, d);
+        for (long k = 0; k < m; k++) x[k] += d[k];
+        free(d);
+    }
+}
+
+/* x = V(b) on level l, zero initial guess:
+ * pre-smooth nu1, residual, restrict, recurse, prolong, post-smooth nu2. */
+static void vcycle(oamg *A, int l, const double *b, double *x)
+{
+    olevel *c = &A->L[l];
+    int n = A->n;
+    long m = (long)c->N * n;
+    if (l == A->nlev - 1) {
+        memcpy(x, b, sizeof(double) * m);
+        lu_solve(A->m, A->LU, A->piv, x);
+        return;
+    }
+    memset(x, 0, sizeof(double) * m);
+    for (int s = 0; s < A->nu1; s++) smooth(A, c, b, x);
+    orc_spmv_bcsr(c->N, n, c->rp, c->col, c->val, x, c->r);
+    for (long k = 0; k < m; k++) c->r[k] = b[k] - c->r[k];
+    olevel *d = &A->L[l + 1];
+    orc_restrict(c->N, n, c->agg, c->r, c->nc, d->b);
+    vcycle(A, l + 1, d->b, d->x);
+    orc_prolong_add(c->N, n, c->agg, d->x, x);
+    for (int s = 0; s < A->nu2; s++) smooth(A, c, b, x);
+}
+
+void orc_amg_apply(void *h, const double *r, double *z)
+{
+    oamg *A = (oamg *)h;
+    vcycle(A, 0, r, z);
+}
+
+/* ------------------------------------------------------------------ */
+/* a12: preconditioned Krylov solvers                                  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int kind;          /* 0 identity, 1 block-Jacobi, 2 AMG V-cycle */
+    int N, n;
+    double *Dinv;
+    void *amg;
+} oprec;
+
+static void prec_apply(const oprec *P, const double *r, double *z)
+{
+    long m = (long)P->N * P->n, bs = (long)P->n * P->n;
+    if (P->kind == 0) memcpy(z, r, sizeof(double) * m);
+    else if (P->kind == 1) {
+        for (int i = 0; i < P->N; i++) blk_mv(P->n, P->Dinv + (long)i * bs, r + (long)i * P->n, z + (long)i * P->n);
+    } else orc_amg_apply(P->amg, r, z);
+}
+
+static int prec_init(oprec *P, int kind, void *amg, int N, int n, const int *rp, const int *col, const double *val)
+{
+    P->kind = kind; P->N = N; P->n = n; P->Dinv = NULL; P->amg = amg;
+    if (kind == 1) {
+        P->Dinv = (double *)malloc(sizeof(double) * ((long)N * n * n + 1));
+        if (diag_inverse(N, n, rp, col, val, P->Dinv)) { free(P->Dinv); P->Dinv = NULL; return ORC_ERR_SINGULAR; }
+    }
+    if (kind == 2 && !amg) return ORC_ERR_ARG;
+    return ORC_OK;
+}
+
+static double true_relres(int N, int n, const int *rp, const int *col, const double *val,
+                          const double *b, const double *x, double *tmp, double bn)
+{
+    long m = (long)N * n;
+    orc_spmv_bcsr(N, n, rp, col, val, x, tmp);
+    for (long k = 0; k < m; k++) tmp[k] = b[k] - tmp[k];
+    return nrm2(m, tmp) / bn;
+}
+
+/* Right-preconditioned BiCGStab (van der Vorst).  x: initial guess in,
+ * solution out.  Stops when the true relative residual ||b-Ax||/||b|| <= tol
+ * (checked whenever the recursive residual says so; the iteration restarts
+ * from the true residual otherwise).  On breakdown it restarts once with
+ * rhat = r, then reports ORC_ERR_BREAKDOWN. */
+int orc_bicgstab(int N, int n, const int *rp, const int *col, const double *val,
+                 int prec_kind, void *amg, const double *b, double *x,
+                 double tol, int maxit, int *iters, double *relres)
+{
+    long m = (long)N * n;
+    oprec P;
+    int rc = prec_init(&P, prec_kind, amg, N, n, rp, col, val);
+    if (rc) return rc;
+    double *r = calloc(m + 1, 8), *rh = calloc(m + 1, 8), *p = calloc(m + 1, 8), *v = calloc(m + 1, 8);
+    double *ph = calloc(m + 1, 8), *s = calloc(m + 1, 8), *sh = calloc(m + 1, 8), *t = calloc(m + 1, 8);
+    double bn = nrm2(m, b);
+    int it = 0, restarts_bd = 0;
+    rc = ORC_NOT_CONVERGED;
+    if (bn == 0.0) {
+        memset(x, 0, sizeof(double) * m); *iters = 0; *relres = 0.0; rc = ORC_OK; goto done;
+    }
+    for (;;) {
+        double res = true_relres(N, n, rp, col, val, b, x, r, bn);
+        *relres = res;
+        if (res <= tol) { rc = ORC_OK; break; }
+        if (it >= maxit) break;
+        memcpy(rh, r, sizeof(double) * m);
+        memset(p, 0, sizeof(double) * m); memset(v, 0, sizeof(double) * m);
+        double rho0 = 1.0, alpha = 1.0, omega = 1.0;
+        int broke = 0;
+        while (it < maxit) {
+            double rho = dot(m, rh, r);
+            if (fabs(rho) < 1e-300 * nrm2(m, r) * nrm2(m, rh) || rho == 0.0) { broke = 1; break; }
+            double beta = (rho / rho0) * (alpha / omega);
+            for (long k = 0; k < m; k++) p[k] = r[k] + beta * (p[k] - omega * v[k]);
+            prec_apply(&P, p, ph);
+            orc_spmv_bcsr(N, n, rp, col, val, ph, v);
+            double rv = dot(m, rh, v);
+            if (fabs(rv) < 1e-300 * nrm2(m, r) * nrm2(m, rh) || rv == 0.0) { broke = 1; break; }
+            alpha = rho / rv;
+            for (long k = 0; k < m; k++) s[k] = r[k] - alpha * v[k];
+            it++;
+            if (nrm2(m, s) / bn <= tol) {
+                for (long k = 0; k < m; k++) x[k] += alpha * ph[k];
+                break;
+            }
+            prec_apply(&P, s, sh);
+            orc_spmv_bcsr(N, n, rp, col, val, sh, t);
+            double tt = dot(m, t, t);
+            omega = tt > 0.0 ? dot(m, t, s) / tt : 0.0;
+            for (long k = 0; k < m; k++) x[k] += alpha * ph[k] + omega * sh[k];
+            for (long k = 0; k < m; k++) r[k] = s[k] - omega * t[k];
+            if (omega == 0.0) { broke = 1; break; }
+            if (nrm2(m, r) / bn <= tol) break;
+            rho0 = rho;
+        }
+        if (broke) {
+            if (restarts_bd >= 1) { rc = ORC_ERR_BREAKDOWN; *relres = true_relres(N, n, rp, col, val, b, x, r, bn); break; }
+            restarts_bd++;
+        }
+    }
+done:
+    *iters = it;
+    free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t); free(P.Dinv);
+    return rc;
+}
+
+/* Flexible GMRES(mr) (Saad 1993): Arnoldi on A M^{-1} storing z_j = M^{-1} v_j,
+ * modified Gram-Schmidt with one re-orthogonalisation when the norm drops by
+ * more than 10x, Givens rotations, x += Z y at every restart.  Same stopping
+ * rule as orc_bicgstab (true relative residual). */
+int orc_fgmres(int N, int n, const int *rp, const int *col, const double *val,
+               int prec_kind, void *amg, const double *b, double *x,
+               double tol, int maxit, int mr, int *iters, double *relres)
+{
+    long m = (long)N * n;
+    oprec P;
+    int rc = prec_init(&P, prec_kind, amg, N, n, rp, col, val);
+    if (rc) return rc;
+    if (mr < 1) mr = 1;
+    double *V = calloc((size_t)(mr + 1) * m + 1, 8), *Z = calloc((size_t)mr * m + 1, 8);
+    double *H = calloc((size_t)(mr + 1) * mr + 1, 8), *cs = calloc(mr + 1, 8), *sn = calloc(mr + 1, 8);
+    double *g = calloc(mr + 2, 8), *y = calloc(mr + 1, 8), *r = calloc(m + 1, 8);
+    double bn = nrm2(m, b);
+    int it = 0;
+    rc = ORC_NOT_CONVERGED;
+    if (bn == 0.0) { memset(x, 0, sizeof(double) * m); *iters = 0; *relres = 0.0; rc = ORC_OK; goto done; }
+    for (;;) {
+        double res = true_relres(N, n, rp, col, val, b, x, r, bn);
+        *relres = res;
+        if (res <= tol) { rc = ORC_OK; break; }
+        if (it >= maxit) break;
+        double beta = res * bn;
+        for (long k = 0; k < m; k++) V[k] = r[k] / beta;
+        memset(g, 0, sizeof(double) * (mr + 2)); g[0] = beta;
+        int j = 0;
+        for (; j < mr && it < maxit; j++) {
+            double *vj = V + (size_t)j * m, *zj = Z + (size_t)j * m, *w = V + (size_t)(j + 1) * m;
+            prec_apply(&P, vj, zj);
+            orc_spmv_bcsr(N, n, rp, col, val, zj, w);
+            double n0 = nrm2(m, w);
+            for (int i = 0; i <= j; i++) {
+                double h = dot(m, w, V + (size_t)i * m);
+                H[(size_t)i * mr + j] = h;
+                for (long k = 0; k < m; k++) w[k] -= h * V[(size_t)i * m + k];
+            }
+            double hn = nrm2(m, w);
+            if (hn < 0.1 * n0) {               /* re-orthogonalise once */
+                for (int i = 0; i <= j; i++) {
+                    double h = dot(m, w, V + (size_t)i * m);
+                    H[(size_t)i * mr + j] += h;
+                    for (long k = 0; k < m; k++) w[k] -= h * V[(size_t)i * m + k];
+                }
+                hn = nrm2(m, w);
+            }
+            H[(size_t)(j + 1) * mr + j] = hn;
+            if (hn > 0.0) for (long k = 0; k < m; k++) w[k] /= hn;
+            /* apply previous rotations, then make a new one */
+            for (int i = 0; i < j; i++) {
+                double a = H[(size_t)i * mr + j], c = H[(size_t)(i + 1) * mr + j];
+                H[(size_t)i * mr + j] = cs[i] * a + sn[i] * c;
+                H[(size_t)(i + 1) * mr + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = H[(size_t)j * mr + j], c = H[(size_t)(j + 1) * mr + j];
+            double den = sqrt(a * a + c * c);
+            cs[j] = den > 0.0 ? a / den : 1.0; sn[j] = den > 0.0 ? c / den : 0.0;
+            H[(size_t)j * mr + j] = den; H[(size_t)(j + 1) * mr + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j]; g[j] = cs[j] * g[j];
+            it++;
+            if (fabs(g[j + 1]) / bn <= tol || hn == 0.0) { j++; break; }
+        }
+        /* solve the j x j triangular system, update x += Z y */
+        for (int i = j - 1; i >= 0; i--) {
+            double s = g[i];
+            for (int k = i + 1; k < j; k++) s -= H[(size_t)i * mr + k] * y[k];
+            y[i] = H[(size_t)i * mr + i] != 0.0 ? s / H[(size_t)i * mr + i] : 0.0;
+        }
+        for (int i = 0; i < j; i++)
+            for (long k = 0; k < m; k++) x[k] += y[i] * Z[(size_t)i * m + k];
+    }
+done:
+    *iters = it;
+    free(V); free(Z); free(H); free(cs); free(sn); free(g); free(y); free(r); free(P.Dinv);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* a15: gradient of L(x) with x = A^{-1} b, given lambda = A^{-T} dL/dx */
+/* dL/dA_ij = -lambda_i x_j^T on the pattern, written in LDU layout;   */
+/* dL/db = lambda.                                                     */
+/* ------------------------------------------------------------------ */
+void orc_grad(int N, int F, int n, const int *la, const int *ua,
+              const double *lam, const double *x,
+              double *gdiag, double *gupper, double *glower)
+{
+    long bs = (long)n * n;
+    for (int i = 0; i < N; i++)
+        for (int r = 0; r < n; r++)
+            for (int c = 0; c < n; c++)
+                gdiag[(long)i * bs + r * n + c] = -lam[(long)i * n + r] * x[(long)i * n + c];
+    for (int f = 0; f < F; f++)
+        for (int r = 0; r < n; r++)
+            for (int c = 0; c < n; c++) {
+                gupper[(long)f * bs + r * n + c] = -lam[(long)la[f] * n + r] * x[(long)ua[f] * n + c];
+                glower[(long)f * bs + r * n + c] = -lam[(long)ua[f] * n + r] * x[(long)la[f] * n + c];
+            }
+}

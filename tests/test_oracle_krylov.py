@@ -1,0 +1,104 @@
+"""Pins for the oracle's Krylov solvers, transposed solve and LDU gradient."""
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import jacobian_box, pressure_velocity
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "fgmres"])
+@pytest.mark.parametrize("prec", [O.PREC_NONE, O.PREC_BJACOBI, O.PREC_AMG])
+def test_tiny_systems_match_dense_lu(solver, prec):
+    for s in (jacobian_box(4, 3, 3, seed=1), pressure_velocity(4, 3, 3, seed=1)):
+        A = O.from_system(s)
+        amg = O.AMG(A, coarse_max=4) if prec == O.PREC_AMG else None
+        fn = getattr(O, solver)
+        x, st = fn(A, s["b"], prec=prec, amg=amg, tol=1e-10, maxit=2000)
+        assert st["status"] == O.OK and st["relres"] <= 1e-10
+        Ad = A.dense()
+        xd = np.linalg.solve(Ad, s["b"].ravel())
+        kappa = np.linalg.cond(Ad)
+        assert np.linalg.norm(x.ravel() - xd) <= 10 * kappa * 1e-10 * np.linalg.norm(xd)
+        # the reported residual is the true one
+        assert abs(O.relres(A, s["b"], x) - st["relres"]) <= 1e-12
+
+
+def test_scaled_identity_converges_in_one_iteration():
+    N, n = 20, 4
+    D = np.tile(3.5 * np.eye(n), (N, 1, 1))
+    A = O.ldu_to_bcsr(N, n, [], [], D, np.zeros((0, n, n)), np.zeros((0, n, n)))[0]
+    b = np.random.default_rng(0).standard_normal((N, n))
+    for fn in (O.bicgstab, O.fgmres):
+        x, st = fn(A, b, prec=O.PREC_NONE, tol=1e-12)
+        assert st["iterations"] == 1
+        assert np.allclose(x, b / 3.5, rtol=1e-14)
+
+
+def test_fgmres_finite_termination():
+    s = jacobian_box(3, 2, 2, n=2, seed=3)     # 24 unknowns
+    A = O.from_system(s)
+    m = A.N * A.n
+    x, st = O.fgmres(A, s["b"], prec=O.PREC_NONE, tol=1e-13, maxit=m, restart=m)
+    assert st["status"] == O.OK and st["iterations"] <= m
+
+
+def test_zero_rhs_gives_zero():
+    s = jacobian_box(3, 3, 3, seed=0)
+    A = O.from_system(s)
+    for fn in (O.bicgstab, O.fgmres):
+        x, st = fn(A, np.zeros_like(s["b"]), x0=np.ones_like(s["b"]))
+        assert st["iterations"] == 0 and np.all(x == 0)
+
+
+def test_iteration_cap_reports_not_converged():
+    s = pressure_velocity(6, 6, 6, seed=0)
+    A = O.from_system(s)
+    x, st = O.bicgstab(A, s["b"], prec=O.PREC_NONE, tol=1e-14, maxit=2)
+    assert st["status"] == O.NOT_CONVERGED
+    assert abs(O.relres(A, s["b"], x) - st["relres"]) <= 1e-14
+
+
+def test_transposed_solve_and_gradient_by_finite_differences():
+    # L = c^T x, x = A^{-1} b.  lambda = A^{-T} c; dL/db = lambda; dL/dA_ij = -lambda_i x_j^T.
+    s = pressure_velocity(3, 3, 2, seed=4)
+    A = O.from_system(s)
+    N, n, F = s["N"], 4, s["F"]
+    rng = np.random.default_rng(4)
+    c = rng.standard_normal((N, n))
+    x, _ = O.bicgstab(A, s["b"], tol=1e-14, maxit=5000)
+    lam, st = O.bicgstab(O.transpose(A), c, tol=1e-14, maxit=5000)
+    assert st["status"] == O.OK
+    assert np.allclose(O.spmv_t(A, lam), c, rtol=0, atol=1e-12)
+    gd, gu, gl = O.grad(s, lam, x)
+
+    def L(diag, upper, lower, b):
+        Ad = np.zeros((N * n, N * n))
+        for i in range(N):
+            Ad[i * n:(i + 1) * n, i * n:(i + 1) * n] = diag[i]
+        for f in range(F):
+            l, u = s["lower_addr"][f], s["upper_addr"][f]
+            Ad[l * n:(l + 1) * n, u * n:(u + 1) * n] = upper[f]
+            Ad[u * n:(u + 1) * n, l * n:(l + 1) * n] = lower[f]
+        return c.ravel() @ np.linalg.solve(Ad, b.ravel())
+
+    h = 1e-6
+    base = dict(diag=s["diag"], upper=s["upper"], lower=s["lower"], b=s["b"])
+    for key, g in (("diag", gd), ("upper", gu), ("lower", gl)):
+        for _ in range(6):
+            idx = tuple(rng.integers(0, d) for d in base[key].shape)
+            p = {k: v.copy() for k, v in base.items()}; m = {k: v.copy() for k, v in base.items()}
+            p[key][idx] += h; m[key][idx] -= h
+            fd = (L(**p) - L(**m)) / (2 * h)
+            assert abs(fd - g[idx]) <= 1e-6 * max(1.0, abs(g[idx]))
+    idx = (3, 2)
+    p = {k: v.copy() for k, v in base.items()}; m = {k: v.copy() for k, v in base.items()}
+    p["b"][idx] += h; m["b"][idx] -= h
+    assert abs((L(**p) - L(**m)) / (2 * h) - lam[idx]) <= 1e-6
+
+
+def test_dilu_amg_reaches_tolerance_on_pressure_velocity():
+    s = pressure_velocity(10, 10, 10, seed=0)
+    A = O.from_system(s)
+    amg = O.AMG(A, coarse_max=32, smoother=O.SMOOTH_DILU)
+    x, st = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=amg, tol=1e-8)
+    assert st["status"] == O.OK and O.relres(A, s["b"], x) <= 1e-8

@@ -1,0 +1,165 @@
+"""Pins for the oracle's block SpMV, transpose, block inversion, dense solve
+and smoothers: closed forms, invariants and textbook special cases."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from workloads import jacobian_box, jacobian_stretched, pressure_velocity
+
+
+def test_spmv_bcsr_equals_ldu_face_loop_and_dense():
+    s = pressure_velocity(5, 4, 3, seed=1)
+    A = O.from_system(s)
+    x = np.random.default_rng(0).standard_normal((s["N"], 4))
+    y1 = O.spmv(A, x)
+    y2 = O.spmv_ldu(s, x)
+    y3 = (A.dense() @ x.ravel()).reshape(y1.shape)
+    scale = np.abs(y3).max()
+    assert np.abs(y1 - y2).max() <= 1e-14 * scale
+    assert np.abs(y1 - y3).max() <= 1e-14 * scale
+
+
+def test_spmv_constant_vector_row_sum_invariant():
+    # Variant-A Jacobian: every block row sums to (V/dtau) I, so A (v,...,v) = (V/dtau) v.
+    s = jacobian_box(6, 5, 4, seed=0, vdt=1.0)
+    A = O.from_system(s)
+    v = np.array([0.3, -1.2, 2.0, 0.7, -0.1])
+    y = O.spmv(A, np.tile(v, (s["N"], 1)))
+    assert np.abs(y - v).max() <= 64 * np.finfo(float).eps * np.abs(A.vals).max()
+    # stretched mesh: block rows sum to V_i I
+    t = jacobian_stretched(4, 3, 6, seed=0)
+    At = O.from_system(t)
+    yt = O.spmv(At, np.tile(v, (t["N"], 1)))
+    vol = np.repeat(np.array([1e-3 * 1.2 ** k for k in range(6)]), 12)
+    assert np.allclose(yt, vol[:, None] * v, rtol=1e-12, atol=1e-15)
+
+
+def test_spmv_scalar_blocks_is_textbook_csr():
+    s = jacobian_box(7, 3, 2, n=1, seed=4)
+    A = O.from_system(s)
+    S = sp.csr_matrix((A.vals.ravel(), A.col, A.row_ptr), shape=(A.N, A.N))
+    x = np.random.default_rng(2).standard_normal(A.N)
+    assert np.allclose(O.spmv(A, x[:, None]).ravel(), S @ x, rtol=1e-14, atol=1e-14)
+
+
+def test_transpose_dot_product_identity_and_dense():
+    s = pressure_velocity(4, 4, 3, seed=3)
+    A = O.from_system(s)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((A.N, 4)); y = rng.standard_normal((A.N, 4))
+    lhs = np.dot(y.ravel(), O.spmv(A, x).ravel())
+    rhs = np.dot(O.spmv_t(A, y).ravel(), x.ravel())
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    AT = O.transpose(A)
+    assert np.array_equal(AT.dense(), A.dense().T)
+    assert np.allclose(O.spmv(AT, y), O.spmv_t(A, y), rtol=1e-13, atol=1e-13)
+
+
+def test_blockinv_against_identity_and_library():
+    rng = np.random.default_rng(1)
+    D = rng.standard_normal((50, 5, 5)) + 3 * np.eye(5)
+    Di = O.blockinv(D)
+    eye = np.einsum("kij,kjl->kil", D, Di)
+    cond = np.linalg.cond(D)
+    err = np.abs(eye - np.eye(5)).max(axis=(1, 2))
+    assert np.all(err <= 50 * cond * np.finfo(float).eps)
+    assert np.allclose(Di, np.linalg.inv(D), rtol=1e-10, atol=1e-12)
+    # a zero pivot column needs partial pivoting
+    P = np.array([[[0.0, 1.0], [1.0, 0.0]]])
+    assert np.array_equal(O.blockinv(P), P)
+
+
+def test_blockinv_singular_reports_block():
+    D = np.stack([np.eye(3), np.zeros((3, 3)), np.eye(3)])
+    with pytest.raises(O.OracleError) as e:
+        O.blockinv(D)
+    assert e.value.code == O.ERR_SINGULAR and "block 1" in str(e.value)
+
+
+def test_dense_solve_against_library():
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((40, 40)) + 10 * np.eye(40)
+    b = rng.standard_normal(40)
+    assert np.allclose(O.dense_solve(A, b), np.linalg.solve(A, b), rtol=1e-12, atol=1e-13)
+    A[:, 3] = 0.0
+    with pytest.raises(O.OracleError):
+        O.dense_solve(A, b)
+
+
+def test_bjacobi_block_diagonal_exact_in_one_sweep():
+    rng = np.random.default_rng(0)
+    D = rng.standard_normal((10, 4, 4)) + 4 * np.eye(4)
+    A = O.ldu_to_bcsr(10, 4, [], [], D, np.zeros((0, 4, 4)), np.zeros((0, 4, 4)))[0]
+    b = rng.standard_normal((10, 4))
+    x = O.bjacobi_sweep(A, O.blockinv(D), b, np.zeros((10, 4)), 1.0)
+    assert np.allclose(x, np.linalg.solve(D, b[..., None])[..., 0], rtol=1e-13, atol=1e-14)
+
+
+def test_bjacobi_sweep_matches_dense_splitting():
+    s = jacobian_box(4, 3, 3, seed=2)
+    A = O.from_system(s)
+    Dinv = O.blockinv(O.diag_blocks(A))
+    rng = np.random.default_rng(3)
+    x0 = rng.standard_normal((A.N, 5))
+    x1 = O.bjacobi_sweep(A, Dinv, s["b"], x0, 0.8)
+    # dense splitting A = D + R: x1 = x0 + w D^{-1}(b - A x0)
+    Ad = A.dense()
+    Dd = np.zeros_like(Ad)
+    for i in range(A.N):
+        Dd[i * 5:(i + 1) * 5, i * 5:(i + 1) * 5] = Ad[i * 5:(i + 1) * 5, i * 5:(i + 1) * 5]
+    ref = x0.ravel() + 0.8 * np.linalg.solve(Dd, s["b"].ravel() - Ad @ x0.ravel())
+    assert np.allclose(x1.ravel(), ref, rtol=1e-12, atol=1e-13)
+
+
+def _chain(N, n, seed):
+    """Block-tridiagonal 1D chain: cells 0-1-2-..., natural order."""
+    rng = np.random.default_rng(seed)
+    la = np.arange(N - 1, dtype=np.int32); ua = la + 1
+    return {"N": N, "n": n, "F": N - 1, "lower_addr": la, "upper_addr": ua.astype(np.int32),
+            "diag": rng.standard_normal((N, n, n)) + 6 * np.eye(n),
+            "upper": rng.standard_normal((N - 1, n, n)), "lower": rng.standard_normal((N - 1, n, n))}
+
+
+def test_dilu_exact_on_block_tridiagonal_chain():
+    # On a chain in natural order there is no fill-in, so DILU = exact block LU.
+    s = _chain(12, 3, 0)
+    A = O.from_system(s)
+    rank = np.arange(12, dtype=np.int32)
+    Einv = O.dilu_setup(A, rank)
+    r = np.random.default_rng(1).standard_normal((12, 3))
+    z = O.dilu_apply(A, rank, Einv, r)
+    assert np.allclose(z.ravel(), np.linalg.solve(A.dense(), r.ravel()), rtol=1e-11, atol=1e-12)
+
+
+def test_dilu_defining_property_diag_of_M_equals_diag_of_A():
+    # M = (E + L) E^{-1} (E + U) with the given ordering has diag(M) = diag(A),
+    # and dilu_apply solves M z = r.
+    s = jacobian_box(3, 3, 2, n=2, seed=5)
+    A = O.from_system(s)
+    N, n = A.N, 2
+    rank = np.random.default_rng(4).permutation(N).astype(np.int32)
+    Einv = O.dilu_setup(A, rank)
+    Ad = A.dense()
+    L = np.zeros_like(Ad); U = np.zeros_like(Ad); E = np.zeros_like(Ad)
+    for i in range(N):
+        for j in range(N):
+            blk = Ad[i * n:(i + 1) * n, j * n:(j + 1) * n]
+            if i == j:
+                E[i * n:(i + 1) * n, i * n:(i + 1) * n] = np.linalg.inv(Einv[i])
+            elif rank[j] < rank[i]:
+                L[i * n:(i + 1) * n, j * n:(j + 1) * n] = blk
+            else:
+                U[i * n:(i + 1) * n, j * n:(j + 1) * n] = blk
+    M = (E + L) @ np.linalg.inv(E) @ (E + U)
+    for i in range(N):
+        sl = slice(i * n, (i + 1) * n)
+        assert np.allclose(M[sl, sl], Ad[sl, sl], rtol=1e-11, atol=1e-12)
+    # a hex-mesh graph has no triangles, so no fill lands on A's own pattern
+    offdiag_mask = np.ones_like(Ad, bool)
+    for i in range(N):
+        offdiag_mask[i * n:(i + 1) * n, i * n:(i + 1) * n] = False
+    assert np.allclose(M[offdiag_mask & (Ad != 0)], Ad[offdiag_mask & (Ad != 0)], rtol=1e-11, atol=1e-12)
+    r = np.random.default_rng(2).standard_normal((N, n))
+    z = O.dilu_apply(A, rank, Einv, r)
+    assert np.allclose(M @ z.ravel(), r.ravel(), rtol=1e-10, atol=1e-11)
