@@ -1,0 +1,201 @@
+/*
+ * cbs.h -- C ABI of the MI355X coupled block-sparse solver (libcbs.so).
+ *
+ * The library solves the assembled coupled system of arXiv 2403.07882,
+ * Eq. (coupl_system):  A_ii U_i + sum_N A_ij U_j = b_i,  with dense n x n
+ * blocks (n = 4 for the pressure-based p-U system of Sec. 2.2, n = 5 for the
+ * density-based system of Sec. 2.1) on a face-neighbour stencil, by an
+ * aggregation-AMG-preconditioned Krylov method (BiCGStab or flexible GMRES,
+ * the solver families of Sec. 2.3).  The call sequence follows the lifecycle
+ * of Algorithm amgxFoam: create from the face-addressed LDU form (pattern set
+ * up once per topology), replace values when only coefficients change,
+ * set up the preconditioner, solve (with the caller's x as initial guess),
+ * read statistics, destroy.
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is a DEVICE pointer (e.g. a torch tensor's
+ *    data_ptr()) unless the comment says "host".  The library never takes
+ *    ownership of caller arrays: they are borrowed for the duration of the
+ *    call (and of the work it enqueues on the handle's stream).
+ *  - Blocks are n x n, row-major, packed one after another (Sec. 2.3, Fig.
+ *    block_amgx).  Vectors are block AoS: x[i*n + v] is variable v of cell i.
+ *  - LDU reading (the paper names only "OpenFOAM native LDU storage"):
+ *    upper[f] is the block at (row lower_addr[f], column upper_addr[f]) and
+ *    lower[f] the block at (row upper_addr[f], column lower_addr[f]).  Faces
+ *    may come in any order and with either orientation.
+ *  - All work is enqueued on the stream given at creation (a hipStream_t
+ *    passed as void*; NULL = the default stream).  Entry points that return
+ *    results to the host (statistics, error flags) synchronise that stream.
+ *  - Return value: 0 = CBS_OK; > 0 = warning (outputs written); < 0 = error.
+ *    cbs_last_error() gives a thread-local message with detail (e.g. the
+ *    index of a singular block).  No C++ exception crosses this boundary.
+ *  - A handle is not thread-safe: use one host thread per handle.
+ */
+#ifndef CBS_H
+#define CBS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cbs_system *cbs_handle;
+
+enum cbs_status {
+    CBS_OK = 0,
+    CBS_NOT_CONVERGED = 1,   /* iteration cap reached; x and stats still written */
+    CBS_ERR_ARG = -1,        /* bad argument (size, NULL pointer, bdim out of 1..5) */
+    CBS_ERR_PATTERN = -2,    /* face index out of range, self face, duplicate face */
+    CBS_ERR_SINGULAR = -3,   /* a diagonal block (any level) or coarse matrix is singular */
+    CBS_ERR_BREAKDOWN = -4,  /* Krylov breakdown persisted after one restart */
+    CBS_ERR_NONFINITE = -5,  /* NaN/Inf in matrix values or right-hand side */
+    CBS_ERR_STATE = -6,      /* call out of order (e.g. solve before setup) */
+    CBS_ERR_OOM = -7,        /* device allocation failed */
+    CBS_ERR_HIP = -8         /* HIP runtime error */
+};
+
+enum { CBS_SOLVER_BICGSTAB = 0, CBS_SOLVER_FGMRES = 1 };
+enum { CBS_PREC_NONE = 0, CBS_PREC_BJACOBI = 1, CBS_PREC_AMG = 2 };
+enum { CBS_SMOOTH_BJACOBI = 0, CBS_SMOOTH_DILU = 1 };
+enum { CBS_PRECISION_FP64 = 0, CBS_PRECISION_MIXED = 1 };
+
+/* Solver options (the "linear solver options" of Algorithm amgxFoam).
+ * cbs_default_options() fills the defaults given in brackets. */
+typedef struct cbs_options {
+    int32_t solver;          /* CBS_SOLVER_*                         [BICGSTAB] */
+    int32_t restart;         /* FGMRES restart length m              [30] */
+    int32_t precond;         /* CBS_PREC_*                           [AMG] */
+    int32_t smoother;        /* CBS_SMOOTH_* (AMG levels)            [BJACOBI] */
+    int32_t pre_sweeps;      /* smoothing sweeps before coarse corr. [1] */
+    int32_t post_sweeps;     /* smoothing sweeps after coarse corr.  [1] */
+    double omega;            /* block-Jacobi damping                 [0.8] */
+    double tol;              /* stop at ||b - A x||_2 / ||b||_2 <= tol [1e-8] */
+    int32_t max_iter;        /* outer Krylov iteration cap           [500] */
+    int32_t precision;       /* CBS_PRECISION_*: MIXED = FP32 hierarchy and
+                                smoothers inside the FP64 Krylov loop [FP64] */
+    int32_t coarse_max;      /* coarsest level: <= this many block rows per
+                                system, solved by a dense FP64 inverse [16] */
+    int32_t match_passes;    /* pairwise-matching passes per level   [2] */
+    int32_t max_levels;      /* hierarchy depth cap                  [24] */
+    int32_t reuse_aggregates;/* cbs_setup again after cbs_update_values: keep
+                                the aggregates, redo only the numeric part [0] */
+    int32_t check_every;     /* read the convergence flag back every k
+                                iterations (device-side early exit)  [1] */
+} cbs_options;
+
+/* Per-solve statistics (Algorithm amgxFoam: iterations and residuals). */
+typedef struct cbs_stats {
+    int32_t iterations;
+    int32_t status;              /* the cbs_status of this system's solve */
+    int32_t levels;              /* AMG levels (1 = no coarsening) */
+    int32_t precision_fallback;  /* 1 if a mixed solve escalated to FP64 */
+    double rel_res_true;         /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
+    double rel_res_recursive;    /* the Krylov recurrence's estimate at exit */
+    double rel_res_initial;      /* ||b - A x0|| / ||b|| */
+    double t_convert_ms;         /* last LDU -> block-CSR value conversion */
+    double t_setup_ms;           /* last cbs_setup */
+    double t_solve_ms;           /* this solve */
+    double op_complexity;        /* sum_l nnzb_l / nnzb_0 */
+} cbs_stats;
+
+void cbs_default_options(cbs_options *opt /* host */);
+
+/* Create a system from the face-addressed LDU form and convert it to block
+ * CSR on the device (the permutation step of Algorithm amgxFoam, Sec. 2.3):
+ * pattern (row_ptr, ascending columns, diagonal inline) and values, bit-exact.
+ *   n_cells  N >= 1 block rows; n_faces F >= 0 internal faces; bdim n in 1..5
+ *   lower_addr[F], upper_addr[F]  int32 cell indices, 0 <= . < N, l != u,
+ *                                 each unordered pair at most once
+ *   diag[N*n*n], upper[F*n*n], lower[F*n*n]   FP64 blocks
+ *   stream   hipStream_t as void*; all later work of the handle runs on it
+ * Errors: CBS_ERR_ARG, CBS_ERR_PATTERN, CBS_ERR_NONFINITE, CBS_ERR_OOM,
+ * CBS_ERR_HIP.  On error *out is NULL and nothing leaks. */
+int cbs_create_from_ldu(cbs_handle *out /* host */, int32_t n_cells, int32_t n_faces,
+                        int32_t bdim, const int32_t *lower_addr, const int32_t *upper_addr,
+                        const double *diag, const double *upper, const double *lower,
+                        void *stream);
+
+/* Batched create: n_sys independent systems concatenated (the offset layout
+ * of the partition consolidation in Sec. 2.3).  cell_off[n_sys+1] and
+ * face_off[n_sys+1] are HOST int64 prefix offsets; the face address arrays
+ * hold per-system LOCAL cell indices; the value arrays are concatenated.
+ * Every system converges on its own (per-system scalars and masks). */
+int cbs_create_batch_from_ldu(cbs_handle *out /* host */, int32_t n_sys,
+                              const int64_t *cell_off /* host */, const int64_t *face_off /* host */,
+                              int32_t bdim, const int32_t *lower_addr, const int32_t *upper_addr,
+                              const double *diag, const double *upper, const double *lower,
+                              void *stream);
+
+/* Replace the coefficients, same pattern (Algorithm amgxFoam: "replace the
+ * old matrix coefficients").  Invalidates the preconditioner: call
+ * cbs_setup again (reuse_aggregates = 1 keeps the coarsening). */
+int cbs_update_values(cbs_handle h, const double *diag, const double *upper, const double *lower);
+
+/* Build the preconditioner: block-diagonal inverses (FP64), and for AMG the
+ * pairwise-matching aggregation, Galerkin coarse operators P^T A P with
+ * piecewise-constant P, FP32 level copies (mixed precision) and the dense
+ * FP64 inverse of each coarsest system.  opt may be NULL (defaults).
+ * Errors: CBS_ERR_SINGULAR (cbs_last_error names level and block). */
+int cbs_setup(cbs_handle h, const cbs_options *opt /* host */);
+
+/* Solve A x = b.  b[N*n] in; x[N*n] is the initial guess on entry (warm
+ * start, as Algorithm amgxFoam uploads the current solution) and the
+ * solution on exit.  st: host, may be NULL; for a batch, an array of n_sys.
+ * b = 0 returns x = 0 with 0 iterations.  Returns CBS_NOT_CONVERGED (x
+ * written) at the iteration cap. */
+int cbs_solve(cbs_handle h, const double *b, double *x, cbs_stats *st /* host */);
+
+/* Solve the transposed system A^T lambda = g with the same options and
+ * aggregates (the adjoint solve of L(x(A,b))).  Same argument rules as
+ * cbs_solve (lambda in = initial guess). */
+int cbs_solve_transpose(cbs_handle h, const double *g, double *lambda, cbs_stats *st /* host */);
+
+/* Gradient of a scalar L(x) w.r.t. the LDU values given lambda = A^{-T} dL/dx
+ * and the solution x:  grad_diag[i] = -lambda_i x_i^T,
+ * grad_upper[f] = -lambda_{l(f)} x_{u(f)}^T, grad_lower[f] = -lambda_{u(f)} x_{l(f)}^T
+ * (dL/db = lambda itself).  Outputs are N*n*n and F*n*n FP64 blocks. */
+int cbs_gradient(cbs_handle h, const double *lambda, const double *x,
+                 double *grad_diag, double *grad_upper, double *grad_lower);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1), FP64, block AoS. */
+int cbs_spmv(cbs_handle h, const double *x, double *y, int32_t transpose);
+
+/* One application z = M^{-1} r of the preconditioner built by cbs_setup
+ * (zero initial guess), in the configured precision. */
+int cbs_apply_precond(cbs_handle h, const double *r, double *z);
+
+/* Field packing around the solve (Algorithm amgxFoam, first and last steps):
+ * soa[v*N + i] (one array per variable) <-> aos[i*n + v].  Bit-exact. */
+int cbs_pack_fields(int32_t n_cells, int32_t bdim, const double *soa, double *aos, void *stream);
+int cbs_unpack_fields(int32_t n_cells, int32_t bdim, const double *aos, double *soa, void *stream);
+
+/* Introspection for verification.  Sizes: cbs_get_info fills any non-NULL
+ * host scalar.  cbs_get_bcsr copies the level-0 block CSR and the slot maps
+ * (diag_slot[N], upper_slot[F], lower_slot[F]) into device arrays of the
+ * caller (any pointer may be NULL to skip it). */
+int cbs_get_info(cbs_handle h, int32_t *n_cells /* host */, int32_t *n_faces /* host */,
+                 int32_t *bdim /* host */, int64_t *nnzb /* host */, int32_t *levels /* host */,
+                 int32_t *n_sys /* host */);
+int cbs_get_bcsr(cbs_handle h, int32_t *row_ptr, int32_t *col, double *vals,
+                 int32_t *diag_slot, int32_t *upper_slot, int32_t *lower_slot);
+
+/* Level l of the AMG hierarchy (after cbs_setup): n_rows, nnzb (host) and,
+ * into caller device arrays when non-NULL, its block CSR (FP64 values), the
+ * aggregate map agg[n_rows] to level l+1 (coarsest level: not written) and
+ * the DILU colour of each row (colour[n_rows], DILU smoother only). */
+int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows /* host */, int64_t *nnzb /* host */,
+                  int32_t *row_ptr, int32_t *col, double *vals, int32_t *agg, int32_t *colour);
+
+/* Free every device buffer of the handle (Algorithm amgxFoam, final step).
+ * NULL is allowed. */
+int cbs_destroy(cbs_handle h);
+
+const char *cbs_error_string(int code);
+const char *cbs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBS_H */

@@ -1,0 +1,783 @@
+// amg.hip -- aggregation-AMG setup on the device.
+//
+// The paper's GPU solver is aggregation AMG for block-coupled systems whose
+// parallel setup rests on graph matching (Sec. 2.3).  Here, per level:
+//   1. FP64 block-diagonal inverses D_i^{-1} (Gauss-Jordan, partial pivoting),
+//   2. strength weights w_ij = 1/2 (|A_ij|_F + |A_ji|_F) / max(|A_ii|_F, |A_jj|_F),
+//   3. handshake matching: every unmatched node proposes to its strongest
+//      unmatched neighbour (ties -> smaller index); mutual proposals pair up;
+//      a few rounds, then leftovers join their strongest matched neighbour;
+//      `match_passes` passes are composed (pass 2 matches the pair graph
+//      whose weights are the scalar Galerkin sums of pass 1),
+//   4. Galerkin coarse operator A_c(I,J) = sum_{i in I, j in J} A(i,j)
+//      (P^T A P with piecewise-constant P), one wavefront per coarse row,
+//      duplicates merged in LDS, sums in a fixed order (deterministic),
+//   5. coarsest level: dense FP64 inverse of each system's matrix.
+// Integer atomics appear only in counting; every order they could perturb is
+// re-sorted, so the hierarchy is reproducible run to run.
+#include "cbs_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+void build_row_sys(cbs_system *h, Level &L0);
+
+namespace {
+
+constexpr int kRapWaves = 4;
+constexpr int kRapCap = 1024;     // candidate blocks gathered per coarse row
+constexpr int kMatchRounds = 4;
+
+// ------------------------------------------------------------------ block inverse
+template <int n>
+__device__ inline bool gj_inverse(double (&a)[n][2 * n]) {
+#pragma unroll
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double pv = fabs(a[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < n; ++r)
+            if (fabs(a[r][k]) > pv) { pv = fabs(a[r][k]); p = r; }
+        if (!(pv > 0.0) || !isfinite(pv)) return false;
+        if (p != k) {
+#pragma unroll
+            for (int c = 0; c < 2 * n; ++c) { double t = a[k][c]; a[k][c] = a[p][c]; a[p][c] = t; }
+        }
+        const double piv = a[k][k];
+#pragma unroll
+        for (int c = 0; c < 2 * n; ++c) a[k][c] /= piv;
+#pragma unroll
+        for (int r = 0; r < n; ++r) {
+            if (r == k) continue;
+            const double m = a[r][k];
+#pragma unroll
+            for (int c = 0; c < 2 * n; ++c) a[r][c] -= m * a[k][c];
+        }
+    }
+    return true;
+}
+
+template <int n>
+__global__ void k_blockinv(int32_t N, const int32_t *__restrict__ dslot, const double *__restrict__ val,
+                           double *__restrict__ Dinv, int32_t *bad) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double *D = val + (int64_t)dslot[i] * (n * n);
+    double a[n][2 * n];
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+#pragma unroll
+        for (int c = 0; c < 2 * n; ++c) a[r][c] = c < n ? D[r * n + c] : (c - n == r ? 1.0 : 0.0);
+    const bool ok = gj_inverse<n>(a);
+    if (!ok) atomicMin(bad, i);
+    double *out = Dinv + (int64_t)i * (n * n);
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+#pragma unroll
+        for (int c = 0; c < n; ++c) out[r * n + c] = ok ? a[r][n + c] : 0.0;
+}
+
+// per-block transpose: out[k] = in[src_k]^T, src_k = mirror[k] (or k)
+template <int n>
+__global__ void k_block_transpose(int64_t nb, const int32_t *__restrict__ mirror, const double *__restrict__ in,
+                                  double *__restrict__ out) {
+    constexpr int nn = n * n;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nb * nn) return;
+    const int64_t k = g / nn;
+    const int e = (int)(g - k * nn), r = e / n, c = e - r * n;
+    const int64_t s = mirror ? (int64_t)mirror[k] : k;
+    out[g] = in[s * nn + c * n + r];
+}
+
+// ------------------------------------------------------------------ strength
+template <int n>
+__global__ void k_diag_frob(int32_t N, const int32_t *dslot, const double *val, double *df) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double *D = val + (int64_t)dslot[i] * (n * n);
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < n * n; ++e) s += D[e] * D[e];
+    df[i] = sqrt(s);
+}
+
+template <int n>
+__global__ void k_strength(int32_t N, const int32_t *rp, const int32_t *col, const int32_t *mirror,
+                           const double *val, const double *df, double *w) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int32_t j = col[k];
+        if (j == i) { w[k] = 0.0; continue; }
+        const double *A = val + (int64_t)k * (n * n), *B = val + (int64_t)mirror[k] * (n * n);
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int e = 0; e < n * n; ++e) { sa += A[e] * A[e]; sb += B[e] * B[e]; }
+        const double den = fmax(df[i], df[j]);
+        w[k] = den > 0.0 ? 0.5 * (sqrt(sa) + sqrt(sb)) / den : 0.0;
+    }
+}
+
+__global__ void k_zero_diag_w(int32_t N, const int32_t *rp, const int32_t *col, double *w) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+        if (col[k] == i) w[k] = 0.0;
+}
+
+// ------------------------------------------------------------------ matching
+// partner: -1 unmatched, -2 excluded (frozen system), >= 0 matched partner
+__global__ void k_match_init(int32_t N, const int32_t *row_sys, const int32_t *sys_frozen, int32_t *partner) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    partner[i] = sys_frozen[row_sys[i]] ? -2 : -1;
+}
+
+__global__ void k_match_pick(int32_t N, const int32_t *rp, const int32_t *col, const double *w,
+                             const int32_t *partner, int32_t *cand) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int32_t best = -1;
+    double bw = 0.0;
+    if (partner[i] == -1) {
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t j = col[k];
+            const double wk = w[k];
+            if (j == i || partner[j] != -1 || !(wk > 0.0)) continue;
+            if (wk > bw || (wk == bw && j < best)) { bw = wk; best = j; }
+        }
+    }
+    cand[i] = best;
+}
+
+__global__ void k_match_confirm(int32_t N, const int32_t *cand, int32_t *partner) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t j = cand[i];
+    if (j >= 0 && cand[j] == i) partner[i] = j;
+}
+
+__global__ void k_match_rep(int32_t N, const int32_t *rp, const int32_t *col, const double *w,
+                            const int32_t *partner, int32_t *rep, int32_t *root) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t p = partner[i];
+    int32_t r = i;
+    if (p >= 0) {
+        r = min(i, p);
+    } else if (p == -1) {
+        int32_t best = -1;
+        double bw = 0.0;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t j = col[k];
+            const double wk = w[k];
+            if (j == i || partner[j] < 0 || !(wk > 0.0)) continue;
+            if (wk > bw || (wk == bw && j < best)) { bw = wk; best = j; }
+        }
+        if (best >= 0) r = min(best, partner[best]);
+    }
+    rep[i] = r;
+    root[i] = (r == i) ? 1 : 0;
+}
+
+__global__ void k_match_assign(int32_t N, const int32_t *rep, const int32_t *newid, int32_t *agg) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    agg[i] = newid[rep[i]];
+}
+
+__global__ void k_compose(int32_t N, const int32_t *a2, int32_t *agg) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    agg[i] = a2[agg[i]];
+}
+
+__global__ void k_inherit_sys(int32_t N, const int32_t *agg, const int32_t *row_sys, int32_t *rs_c) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    rs_c[agg[i]] = row_sys[i];          // every member writes the same value
+}
+
+// ------------------------------------------------------------------ members
+__global__ void k_fill_int(int32_t *a, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void k_count_members(int32_t N, const int32_t *agg, int32_t *cnt) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) atomicAdd(&cnt[agg[i]], 1);
+}
+
+__global__ void k_fill_members(int32_t N, const int32_t *agg, int32_t *fill, int32_t *mem) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    mem[atomicAdd(&fill[agg[i]], 1)] = i;
+}
+
+__global__ void k_sort_members(int32_t nc, const int32_t *aptr, int32_t *mem) {
+    const int32_t I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    const int32_t b = aptr[I], e = aptr[I + 1];
+    for (int32_t a = b + 1; a < e; ++a) {
+        const int32_t v = mem[a];
+        int32_t q = a - 1;
+        while (q >= b && mem[q] > v) { mem[q + 1] = mem[q]; --q; }
+        mem[q + 1] = v;
+    }
+}
+
+// ------------------------------------------------------------------ Galerkin RAP
+// pass 0: cnt[I] = number of distinct coarse columns of coarse row I
+// pass 1: colc / valc of coarse row I at rpc[I] (columns ascending)
+template <int n, int PASS>
+__global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, const int32_t *__restrict__ aptr,
+                                                        const int32_t *__restrict__ amem,
+                                                        const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ col,
+                                                        const double *__restrict__ val,
+                                                        const int32_t *__restrict__ agg, int32_t *cnt,
+                                                        const int32_t *__restrict__ rpc, int32_t *colc,
+                                                        double *valc, int32_t *flag) {
+    constexpr int nn = n * n;
+    __shared__ int32_t sJ[kRapWaves][kRapCap];
+    __shared__ int32_t sK[kRapWaves][kRapCap];
+    __shared__ int32_t sF[kRapWaves][kRapCap];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t I = blockIdx.x * kRapWaves + w;
+    const bool active = I < nc;
+    int32_t c = 0;
+    if (active) {
+        for (int32_t m = aptr[I]; m < aptr[I + 1]; ++m) {
+            const int32_t i = amem[m];
+            const int32_t kb = rp[i], len = rp[i + 1] - kb;
+            for (int32_t e = lane; e < len; e += 64) {
+                const int32_t q = c + e;
+                if (q < kRapCap) { sJ[w][q] = agg[col[kb + e]]; sK[w][q] = kb + e; }
+            }
+            c += len;
+        }
+        if (c > kRapCap && lane == 0) atomicOr(flag, 8);
+    }
+    __syncthreads();
+    const int32_t cc = active ? min(c, kRapCap) : 0;
+    for (int32_t q = lane; q < cc; q += 64) {
+        const int32_t J = sJ[w][q];
+        int f = 1;
+        for (int32_t p = 0; p < q; ++p)
+            if (sJ[w][p] == J) { f = 0; break; }
+        sF[w][q] = f;
+    }
+    __syncthreads();
+    if (PASS == 0) {
+        int32_t d = 0;
+        for (int32_t q = lane; q < cc; q += 64) d += sF[w][q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+        if (active && lane == 0) cnt[I] = d;
+        return;
+    }
+    if (!active) return;
+    const int32_t base = rpc[I];
+    for (int32_t q = lane; q < cc; q += 64) {
+        if (!sF[w][q]) continue;
+        const int32_t J = sJ[w][q];
+        int32_t rank = 0;
+        for (int32_t p = 0; p < cc; ++p) rank += (sF[w][p] && sJ[w][p] < J) ? 1 : 0;
+        double acc[nn];
+#pragma unroll
+        for (int e = 0; e < nn; ++e) acc[e] = 0.0;
+        for (int32_t p = q; p < cc; ++p) {
+            if (sJ[w][p] != J) continue;
+            const double *B = val + (int64_t)sK[w][p] * nn;
+#pragma unroll
+            for (int e = 0; e < nn; ++e) acc[e] += B[e];
+        }
+        colc[base + rank] = J;
+        double *out = valc + (int64_t)(base + rank) * nn;
+#pragma unroll
+        for (int e = 0; e < nn; ++e) out[e] = acc[e];
+    }
+}
+
+__device__ inline int32_t bsearch_col(const int32_t *col, int32_t lo, int32_t hi, int32_t j) {
+    hi -= 1;
+    while (lo <= hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        const int32_t v = col[mid];
+        if (v == j) return mid;
+        if (v < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+__global__ void k_mirror_search(int32_t N, const int32_t *rp, const int32_t *col, int32_t *mirror,
+                                int32_t *dslot, int32_t *flag) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int32_t j = col[k];
+        const int32_t m = bsearch_col(col, rp[j], rp[j + 1], i);
+        if (m < 0) atomicOr(flag, 16);
+        mirror[k] = m < 0 ? k : m;
+        if (j == i) dslot[i] = k;
+    }
+}
+
+__global__ void k_sys_first(int32_t N, const int32_t *row_sys, int64_t *first) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    if (i == 0 || row_sys[i] != row_sys[i - 1]) first[row_sys[i]] = i;
+}
+
+// ------------------------------------------------------------------ coarsest
+// One workgroup per system: dense matrix of the system's rows, then
+// Gauss-Jordan with partial pivoting in global memory (m = rows * n, small).
+template <int n>
+__global__ __launch_bounds__(256) void k_coarse_inverse(const int32_t *rp, const int32_t *col, const double *val,
+                                                        const int64_t *roff_blk, const int64_t *off,
+                                                        const int32_t *msz, double *work, double *inv,
+                                                        double *invT, int32_t *flag) {
+    const int s = blockIdx.x;
+    const int m = msz[s];
+    const int64_t r0 = roff_blk[s];               // first block row of the system
+    double *a = work + off[s];
+    double *x = inv + off[s];
+    __shared__ int piv_row;
+    __shared__ double piv_val;
+    for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
+        a[e] = 0.0;
+        x[e] = ((e / m) == (e % m)) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int nb = m / n;
+    for (int bi = threadIdx.x; bi < nb; bi += blockDim.x) {
+        const int64_t i = r0 + bi;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int64_t bj = col[k] - r0;
+            for (int r = 0; r < n; ++r)
+                for (int c = 0; c < n; ++c)
+                    a[((int64_t)bi * n + r) * m + bj * n + c] = val[(int64_t)k * n * n + r * n + c];
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+        if (threadIdx.x == 0) {
+            int p = k;
+            double pv = fabs(a[(int64_t)k * m + k]);
+            for (int r = k + 1; r < m; ++r) {
+                const double v = fabs(a[(int64_t)r * m + k]);
+                if (v > pv) { pv = v; p = r; }
+            }
+            piv_row = p;
+            piv_val = pv;
+        }
+        __syncthreads();
+        if (!(piv_val > 0.0) || !isfinite(piv_val)) {
+            if (threadIdx.x == 0) atomicOr(flag, 32);
+            return;
+        }
+        const int p = piv_row;
+        if (p != k) {
+            for (int c = threadIdx.x; c < m; c += blockDim.x) {
+                double t = a[(int64_t)k * m + c]; a[(int64_t)k * m + c] = a[(int64_t)p * m + c]; a[(int64_t)p * m + c] = t;
+                t = x[(int64_t)k * m + c]; x[(int64_t)k * m + c] = x[(int64_t)p * m + c]; x[(int64_t)p * m + c] = t;
+            }
+        }
+        __syncthreads();
+        const double d = a[(int64_t)k * m + k];
+        __syncthreads();
+        for (int c = threadIdx.x; c < m; c += blockDim.x) {
+            a[(int64_t)k * m + c] /= d;
+            x[(int64_t)k * m + c] /= d;
+        }
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
+            const int r = (int)(e / m), c = (int)(e % m);
+            if (r == k) continue;
+            const double f = a[(int64_t)r * m + k];
+            if (c != k) a[e] -= f * a[(int64_t)k * m + c];
+            x[e] -= f * x[(int64_t)k * m + c];
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < m; r += blockDim.x)
+            if (r != k) a[(int64_t)r * m + k] = 0.0;
+        __syncthreads();
+    }
+    for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
+        const int r = (int)(e / m), c = (int)(e % m);
+        invT[off[s] + (int64_t)c * m + r] = x[e];
+    }
+}
+
+}  // namespace
+
+// ====================================================================== host
+#define NSWITCH(n, F, ...)                                                \
+    switch (n) {                                                          \
+        case 1: F<1>(__VA_ARGS__); break;                                 \
+        case 2: F<2>(__VA_ARGS__); break;                                 \
+        case 3: F<3>(__VA_ARGS__); break;                                 \
+        case 4: F<4>(__VA_ARGS__); break;                                 \
+        case 5: F<5>(__VA_ARGS__); break;                                 \
+        default: cbs_throw(CBS_ERR_ARG, "bdim must be 1..5");             \
+    }
+
+namespace {
+
+template <int n>
+void blockinv_n(int32_t N, const int32_t *dslot, const double *val, double *Dinv, int32_t *bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_blockinv<n>, dim3(cdiv(N, 128)), dim3(128), 0, st, N, dslot, val, Dinv, bad);
+}
+template <int n>
+void transpose_n(int64_t nb, const int32_t *mirror, const double *in, double *out, hipStream_t st) {
+    const int64_t tot = nb * n * n;
+    if (tot > 0) hipLaunchKernelGGL(k_block_transpose<n>, dim3(cdiv(tot, 256)), dim3(256), 0, st, nb, mirror, in, out);
+}
+template <int n>
+void strength_n(int32_t N, const int32_t *rp, const int32_t *col, const int32_t *mirror, const int32_t *dslot,
+                const double *val, double *df, double *w, hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_frob<n>, dim3(cdiv(N, 256)), dim3(256), 0, st, N, dslot, val, df);
+    hipLaunchKernelGGL(k_strength<n>, dim3(cdiv(N, 256)), dim3(256), 0, st, N, rp, col, mirror, val, df, w);
+}
+template <int n>
+void rap_n(int pass, int32_t nc, const int32_t *aptr, const int32_t *amem, const int32_t *rp, const int32_t *col,
+           const double *val, const int32_t *agg, int32_t *cnt, const int32_t *rpc, int32_t *colc, double *valc,
+           int32_t *flag, hipStream_t st) {
+    const dim3 g(cdiv(nc, kRapWaves)), b(64 * kRapWaves);
+    if (pass == 0)
+        hipLaunchKernelGGL((k_rap<n, 0>), g, b, 0, st, nc, aptr, amem, rp, col, val, agg, cnt, rpc, colc, valc, flag);
+    else
+        hipLaunchKernelGGL((k_rap<n, 1>), g, b, 0, st, nc, aptr, amem, rp, col, val, agg, cnt, rpc, colc, valc, flag);
+}
+template <int n>
+void coarse_inverse_n(int32_t n_sys, const int32_t *rp, const int32_t *col, const double *val, const int64_t *roffb,
+                      const int64_t *off, const int32_t *msz, double *work, double *inv, double *invT, int32_t *flag,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_coarse_inverse<n>, dim3(n_sys), dim3(256), 0, st, rp, col, val, roffb, off, msz, work, inv,
+                       invT, flag);
+}
+
+struct Graph {
+    int32_t N;
+    const int32_t *rp, *col;
+    const double *w;
+};
+
+// one pass of handshake matching -> agg (size N), returns the aggregate count
+int32_t match_pass(cbs_system *h, const Graph &g, const int32_t *row_sys, const int32_t *sys_frozen, int32_t *agg) {
+    hipStream_t st = h->stream;
+    const int32_t N = g.N;
+    DArr<int32_t> partner(N), cand(N), rep(N), root(N + 1);
+    const dim3 G(cdiv(N, 256)), B(256);
+    hipLaunchKernelGGL(k_match_init, G, B, 0, st, N, row_sys, sys_frozen, partner.get());
+    for (int r = 0; r < kMatchRounds; ++r) {
+        hipLaunchKernelGGL(k_match_pick, G, B, 0, st, N, g.rp, g.col, g.w, partner.get(), cand.get());
+        hipLaunchKernelGGL(k_match_confirm, G, B, 0, st, N, cand.get(), partner.get());
+    }
+    hipLaunchKernelGGL(k_match_rep, G, B, 0, st, N, g.rp, g.col, g.w, partner.get(), rep.get(), root.get());
+    LAUNCHCHK();
+    scan_exclusive(root.get(), root.get(), N, st);
+    hipLaunchKernelGGL(k_match_assign, G, B, 0, st, N, rep.get(), root.get(), agg);
+    LAUNCHCHK();
+    return read_int(root.get() + N, st);
+}
+
+// member lists of each aggregate (ascending)
+void build_members(cbs_system *h, int32_t N, const int32_t *agg, int32_t nc, DArr<int32_t> &aptr,
+                   DArr<int32_t> &amem) {
+    hipStream_t st = h->stream;
+    aptr.alloc(nc + 1);
+    amem.alloc(N > 0 ? N : 1);
+    DArr<int32_t> fill(nc + 1);
+    hipLaunchKernelGGL(k_fill_int, dim3(cdiv(nc + 1, 256)), dim3(256), 0, st, aptr.get(), (int64_t)nc + 1, 0);
+    hipLaunchKernelGGL(k_count_members, dim3(cdiv(N, 256)), dim3(256), 0, st, N, agg, aptr.get());
+    LAUNCHCHK();
+    scan_exclusive(aptr.get(), aptr.get(), nc, st);
+    HIPCHK(hipMemcpyAsync(fill.get(), aptr.get(), sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_fill_members, dim3(cdiv(N, 256)), dim3(256), 0, st, N, agg, fill.get(), amem.get());
+    hipLaunchKernelGGL(k_sort_members, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, aptr.get(), amem.get());
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+// Galerkin pattern + values of the next level.  n_blk = block size of `val`.
+void rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, const int32_t *amem, const int32_t *rp,
+               const int32_t *col, const double *val, const int32_t *agg, DArr<int32_t> &rpc, DArr<int32_t> &colc,
+               DArr<double> &valc, bool pattern) {
+    hipStream_t st = h->stream;
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+    if (pattern) {
+        rpc.alloc(nc + 1);
+        NSWITCH(n_blk, rap_n, 0, nc, aptr, amem, rp, col, val, agg, rpc.get(), nullptr, nullptr, nullptr,
+                h->dflag.get(), st);
+        LAUNCHCHK();
+        if (read_int(h->dflag.get(), st) & 8)
+            cbs_throw(CBS_ERR_ARG, "coarse row gathers more than 1024 blocks (aggregates too large)");
+        scan_exclusive(rpc.get(), rpc.get(), nc, st);
+        const int32_t nz = read_int(rpc.get() + nc, st);
+        colc.alloc(nz > 0 ? nz : 1);
+        valc.alloc((size_t)(nz > 0 ? nz : 1) * n_blk * n_blk);
+    }
+    NSWITCH(n_blk, rap_n, 1, nc, aptr, amem, rp, col, val, agg, nullptr, rpc.get(), colc.get(), valc.get(),
+            h->dflag.get(), st);
+    LAUNCHCHK();
+    if (read_int(h->dflag.get(), st) & 8)
+        cbs_throw(CBS_ERR_ARG, "coarse row gathers more than 1024 blocks (aggregates too large)");
+}
+
+// Aggregation of level L into L.agg / L.nc (composed matching passes).
+void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen) {
+    hipStream_t st = h->stream;
+    const int32_t N = L.N;
+    const int n = h->n;
+    DArr<double> df(N), w(L.nnzb > 0 ? L.nnzb : 1);
+    NSWITCH(n, strength_n, N, L.rp, L.col, L.mirror, L.dslot, L.v64, df.get(), w.get(), st);
+    LAUNCHCHK();
+    L.agg.alloc(N);
+    Graph g{N, L.rp, L.col, w.get()};
+    int32_t nc = match_pass(h, g, L.row_sys.get(), sys_frozen, L.agg.get());
+    // further passes on the aggregate graph with summed weights
+    DArr<int32_t> grp, gcol, rs, a2, gaptr, gamem;
+    DArr<double> gw;
+    DArr<int32_t> cur_rs;                          // row_sys of the current graph
+    const int32_t *cur_rp = L.rp, *cur_col = L.col, *cur_rowsys = L.row_sys.get();
+    const double *cur_w = w.get();
+    int32_t cur_N = N;
+    DArr<int32_t> agg1;                            // last pass's map on the current graph
+    agg1.alloc(N);
+    HIPCHK(hipMemcpyAsync(agg1.get(), L.agg.get(), sizeof(int32_t) * N, hipMemcpyDeviceToDevice, st));
+    for (int p = 1; p < h->opt.match_passes && nc > 1; ++p) {
+        DArr<int32_t> aptr, amem, nrp, ncol, nrs;
+        DArr<double> nw;
+        build_members(h, cur_N, agg1.get(), nc, aptr, amem);
+        rap_build(h, 1, nc, aptr.get(), amem.get(), cur_rp, cur_col, cur_w, agg1.get(), nrp, ncol, nw, true);
+        hipLaunchKernelGGL(k_zero_diag_w, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, nrp.get(), ncol.get(), nw.get());
+        nrs.alloc(nc);
+        hipLaunchKernelGGL(k_inherit_sys, dim3(cdiv(cur_N, 256)), dim3(256), 0, st, cur_N, agg1.get(), cur_rowsys,
+                           nrs.get());
+        LAUNCHCHK();
+        DArr<int32_t> a(nc);
+        Graph g2{nc, nrp.get(), ncol.get(), nw.get()};
+        const int32_t nc2 = match_pass(h, g2, nrs.get(), sys_frozen, a.get());
+        hipLaunchKernelGGL(k_compose, dim3(cdiv(N, 256)), dim3(256), 0, st, N, a.get(), L.agg.get());
+        LAUNCHCHK();
+        // the new graph becomes current
+        grp = std::move(nrp); gcol = std::move(ncol); gw = std::move(nw); cur_rs = std::move(nrs);
+        cur_rp = grp.get(); cur_col = gcol.get(); cur_w = gw.get(); cur_rowsys = cur_rs.get();
+        cur_N = nc;
+        agg1 = std::move(a);
+        nc = nc2;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    L.nc = nc;
+}
+
+std::vector<int64_t> level_sys_off(cbs_system *h, Level &L) {
+    std::vector<int64_t> off(h->n_sys + 1, 0);
+    if (h->n_sys == 1) {
+        off[1] = L.N;
+        return off;
+    }
+    DArr<int64_t> first(h->n_sys);
+    hipLaunchKernelGGL(k_sys_first, dim3(cdiv(L.N, 256)), dim3(256), 0, h->stream, L.N, L.row_sys.get(), first.get());
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(off.data(), first.get(), sizeof(int64_t) * h->n_sys, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    off[h->n_sys] = L.N;
+    return off;
+}
+
+void alloc_level_vectors(cbs_system *h, Level &L, bool mixed) {
+    const size_t bytes = (size_t)L.N * h->n * (mixed ? sizeof(float) : sizeof(double));
+    L.vb.ensure(bytes); L.vx.ensure(bytes); L.vr.ensure(bytes); L.vt.ensure(bytes);
+}
+
+}  // namespace
+
+void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv) {
+    Level &L = h->lev[l];
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0x7f, sizeof(int32_t), h->stream));
+    NSWITCH(h->n, blockinv_n, L.N, L.dslot, vals, Dinv, h->dflag.get(), h->stream);
+    LAUNCHCHK();
+    const int32_t bad = read_int(h->dflag.get(), h->stream);
+    if (bad != 0x7f7f7f7f)
+        cbs_throw(CBS_ERR_SINGULAR, "singular diagonal block at level " + std::to_string(l) + ", block row " +
+                                        std::to_string(bad));
+}
+
+// Build (or, with reuse, refresh) the hierarchy.
+void amg_setup(cbs_system *h) {
+    hipStream_t st = h->stream;
+    const cbs_options &o = h->opt;
+    const int n = h->n;
+    const bool mixed = o.precision == CBS_PRECISION_MIXED;
+    const bool amg = o.precond == CBS_PREC_AMG;
+    const bool reuse = o.reuse_aggregates && h->setup_done && amg && h->lev.size() > 1 && h->lev[0].agg.get() != nullptr;
+    h->transposed_ready = false;
+
+    if (!reuse) h->lev.clear();
+    if (h->lev.empty()) h->lev.emplace_back();
+    Level &L0 = h->lev[0];
+    L0.N = h->N; L0.nnzb = h->nnzb;
+    L0.rp = h->rp.get(); L0.col = h->col.get(); L0.mirror = h->mirror.get(); L0.dslot = h->dslot.get();
+    L0.v64 = h->vals.get();
+    if (!L0.row_sys.get()) build_row_sys(h, L0);
+    L0.sys_off = h->cell_off;
+
+    // level 0 block inverses (block-Jacobi preconditioner or smoother)
+    if (o.precond != CBS_PREC_NONE) {
+        L0.Dinv.ensure((size_t)h->N * n * n);
+        blockinv_level(h, 0, L0.v64, L0.Dinv.get());
+    }
+    if (!amg) {
+        h->lev.resize(1);
+        h->op_complexity = 1.0;
+        return;
+    }
+
+    DArr<int32_t> frozen(h->n_sys);
+    std::vector<int32_t> hfrozen(h->n_sys);
+    int l = 0;
+    for (;; ++l) {
+        Level &L = h->lev[l];
+        if (L.sys_off.size() != (size_t)h->n_sys + 1) L.sys_off = level_sys_off(h, L);
+        bool all_small = true;
+        for (int s = 0; s < h->n_sys; ++s) {
+            const int64_t Ns = L.sys_off[s + 1] - L.sys_off[s];
+            hfrozen[s] = Ns <= o.coarse_max ? 1 : 0;
+            all_small = all_small && hfrozen[s];
+        }
+        bool last = all_small || l + 1 >= o.max_levels;
+        if (!last && !(reuse && L.agg.get() && (int)h->lev.size() > l + 1)) {
+            HIPCHK(hipMemcpyAsync(frozen.get(), hfrozen.data(), sizeof(int32_t) * h->n_sys, hipMemcpyHostToDevice, st));
+            aggregate_level(h, L, frozen.get());
+            // stall test over the systems still coarsening (frozen rows map 1:1)
+            int64_t n_frozen = 0;
+            for (int s = 0; s < h->n_sys; ++s)
+                if (hfrozen[s]) n_frozen += L.sys_off[s + 1] - L.sys_off[s];
+            const double active = (double)(L.N - n_frozen), active_c = (double)(L.nc - n_frozen);
+            if (active_c > 0.97 * active) {                  // coarsening stalled
+                L.agg.release(); L.nc = 0;
+                last = true;
+            } else {
+                build_members(h, L.N, L.agg.get(), L.nc, L.agg_ptr, L.agg_mem);
+                if ((int)h->lev.size() > l + 1) h->lev.resize(l + 1);
+                h->lev.emplace_back();
+                Level &C = h->lev[l + 1];
+                Level &F = h->lev[l];
+                C.N = F.nc;
+                rap_build(h, n, C.N, F.agg_ptr.get(), F.agg_mem.get(), F.rp, F.col, F.v64, F.agg.get(), C.o_rp,
+                          C.o_col, C.o_v64, true);
+                C.rp = C.o_rp.get(); C.col = C.o_col.get(); C.v64 = C.o_v64.get();
+                C.nnzb = read_int(C.rp + C.N, st);
+                C.o_mirror.alloc(C.nnzb); C.o_dslot.alloc(C.N);
+                C.mirror = C.o_mirror.get(); C.dslot = C.o_dslot.get();
+                HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+                hipLaunchKernelGGL(k_mirror_search, dim3(cdiv(C.N, 256)), dim3(256), 0, st, C.N, C.rp, C.col, C.mirror,
+                                   C.dslot, h->dflag.get());
+                C.row_sys.alloc(C.N);
+                hipLaunchKernelGGL(k_inherit_sys, dim3(cdiv(F.N, 256)), dim3(256), 0, st, F.N, F.agg.get(),
+                                   F.row_sys.get(), C.row_sys.get());
+                LAUNCHCHK();
+                if (read_int(h->dflag.get(), st) & 16) cbs_throw(CBS_ERR_PATTERN, "coarse pattern is not symmetric");
+                C.sys_off = level_sys_off(h, C);
+                continue;
+            }
+        } else if (!last) {
+            // reuse: refresh the values of level l+1 with the kept pattern
+            Level &C = h->lev[l + 1];
+            Level &F = h->lev[l];
+            rap_build(h, n, C.N, F.agg_ptr.get(), F.agg_mem.get(), F.rp, F.col, F.v64, F.agg.get(), C.o_rp, C.o_col,
+                      C.o_v64, false);
+            continue;
+        }
+        // level l is the coarsest
+        h->lev.resize(l + 1);
+        h->lev[l].agg.release();
+        h->lev[l].nc = 0;
+        break;
+    }
+    const int nlev = (int)h->lev.size();
+
+    // smoothers (FP64 inverses), FP32 copies, vectors
+    int64_t nz_sum = 0;
+    for (int q = 0; q < nlev; ++q) {
+        Level &L = h->lev[q];
+        nz_sum += L.nnzb;
+        if (q > 0 && q + 1 < nlev) {
+            L.Dinv.ensure((size_t)L.N * n * n);
+            blockinv_level(h, q, L.v64, L.Dinv.get());
+        }
+        if (mixed) {
+            L.o_v32.ensure((size_t)L.nnzb * n * n);
+            L.v32 = L.o_v32.get();
+            launch_cast<double, float>(L.nnzb * n * n, L.v64, L.v32, st);
+        }
+        alloc_level_vectors(h, L, mixed);
+    }
+    h->op_complexity = (double)nz_sum / (double)h->nnzb;
+
+    // coarsest: dense inverse of each system
+    Level &Lc = h->lev[nlev - 1];
+    std::vector<int64_t> off(h->n_sys + 1, 0), roffb(h->n_sys), roff(h->n_sys);
+    std::vector<int32_t> msz(h->n_sys);
+    int32_t maxm = 0;
+    for (int s = 0; s < h->n_sys; ++s) {
+        const int64_t rows = Lc.sys_off[s + 1] - Lc.sys_off[s];
+        const int64_t m = rows * n;
+        if (m > 4096)
+            cbs_throw(CBS_ERR_ARG, "coarsest system too large for the dense solve (" + std::to_string(m) +
+                                       " unknowns); raise max_levels or lower coarse_max");
+        msz[s] = (int32_t)m;
+        roffb[s] = Lc.sys_off[s];
+        roff[s] = Lc.sys_off[s] * n;
+        off[s + 1] = off[s] + m * m;
+        maxm = std::max<int32_t>(maxm, (int32_t)m);
+    }
+    Coarse &C = h->coarse;
+    C.max_m = maxm;
+    C.inv.ensure(off[h->n_sys] > 0 ? off[h->n_sys] : 1);
+    C.invT.ensure(off[h->n_sys] > 0 ? off[h->n_sys] : 1);
+    C.off.ensure(h->n_sys + 1); C.m.ensure(h->n_sys); C.roff.ensure(h->n_sys);
+    DArr<int64_t> droffb(h->n_sys);
+    DArr<double> work(off[h->n_sys] > 0 ? off[h->n_sys] : 1);
+    HIPCHK(hipMemcpyAsync(C.off.get(), off.data(), sizeof(int64_t) * (h->n_sys + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(C.m.get(), msz.data(), sizeof(int32_t) * h->n_sys, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(C.roff.get(), roff.data(), sizeof(int64_t) * h->n_sys, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(droffb.get(), roffb.data(), sizeof(int64_t) * h->n_sys, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+    NSWITCH(n, coarse_inverse_n, h->n_sys, Lc.rp, Lc.col, Lc.v64, droffb.get(), C.off.get(), C.m.get(), work.get(),
+            C.inv.get(), C.invT.get(), h->dflag.get(), st);
+    LAUNCHCHK();
+    if (read_int(h->dflag.get(), st) & 32) cbs_throw(CBS_ERR_SINGULAR, "coarsest-level matrix is singular");
+}
+
+// Transposed level values for the adjoint solve: A^T(i,j) = A(j,i)^T through
+// the mirror map (a bit-exact permuted copy), D^{-T} = (D^{-1})^T.
+void amg_build_transposed(cbs_system *h) {
+    if (h->transposed_ready) return;
+    hipStream_t st = h->stream;
+    const int n = h->n;
+    const bool mixed = h->opt.precision == CBS_PRECISION_MIXED;
+    const int nlev = (int)h->lev.size();
+    for (int q = 0; q < nlev; ++q) {
+        Level &L = h->lev[q];
+        L.o_v64T.ensure((size_t)L.nnzb * n * n);
+        L.v64T = L.o_v64T.get();
+        NSWITCH(n, transpose_n, L.nnzb, L.mirror, L.v64, L.v64T, st);
+        if (mixed && q < nlev) {
+            L.o_v32T.ensure((size_t)L.nnzb * n * n);
+            L.v32T = L.o_v32T.get();
+            launch_cast<double, float>(L.nnzb * n * n, L.v64T, L.v32T, st);
+        }
+        if (L.Dinv.get()) {
+            L.DinvT.ensure((size_t)L.N * n * n);
+            NSWITCH(n, transpose_n, (int64_t)L.N, nullptr, L.Dinv.get(), L.DinvT.get(), st);
+        }
+        LAUNCHCHK();
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    h->transposed_ready = true;
+}

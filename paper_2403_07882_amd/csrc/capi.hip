@@ -1,0 +1,356 @@
+// capi.hip -- the extern "C" entry points of libcbs.so (declared in cbs.h).
+//
+// Lifecycle of Algorithm amgxFoam (Sec. 2.3): create from LDU (pattern +
+// values), replace values, set up, solve (warm start), statistics, destroy.
+// Every entry point catches internal errors and returns a cbs_status; the
+// message goes to a thread-local buffer read by cbs_last_error().
+#include "cbs_internal.h"
+
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <new>
+
+void globalize_faces(cbs_system *h, const int32_t *la_in, const int32_t *ua_in);
+void alloc_krylov(cbs_system *h);
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename F>
+int guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const CbsError &e) {
+        g_last_error = e.msg;
+        (void)hipGetLastError();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return CBS_ERR_OOM;
+    } catch (...) {
+        g_last_error = "unexpected internal error";
+        return CBS_ERR_HIP;
+    }
+}
+
+void require(bool cond, int code, const char *msg) {
+    if (!cond) cbs_throw(code, msg);
+}
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    HIPCHK(hipEventSynchronize(b));
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    return ms;
+}
+
+void build_items(cbs_system *h) {
+    std::vector<Item> items;
+    h->items_per_sys_off.assign(h->n_sys + 1, 0);
+    for (int s = 0; s < h->n_sys; ++s) {
+        const int64_t b = h->cell_off[s] * h->n, e = h->cell_off[s + 1] * h->n;
+        for (int64_t q = b; q < e; q += kItemElems) items.push_back(Item{s, 0, q, std::min<int64_t>(e, q + kItemElems)});
+        h->items_per_sys_off[s + 1] = (int32_t)items.size();
+    }
+    h->n_items = (int32_t)items.size();
+    h->items.alloc(items.size());
+    HIPCHK(hipMemcpy(h->items.get(), items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+    h->item_off.alloc(h->n_sys + 1);
+    HIPCHK(hipMemcpy(h->item_off.get(), h->items_per_sys_off.data(), sizeof(int32_t) * (h->n_sys + 1),
+                     hipMemcpyHostToDevice));
+}
+
+void ensure_level0(cbs_system *h) {
+    if (h->lev.empty()) h->lev.emplace_back();
+    Level &L0 = h->lev[0];
+    L0.N = h->N; L0.nnzb = h->nnzb;
+    L0.rp = h->rp.get(); L0.col = h->col.get(); L0.mirror = h->mirror.get(); L0.dslot = h->dslot.get();
+    L0.v64 = h->vals.get();
+}
+
+int create_common(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const int64_t *face_off, int32_t bdim,
+                  const int32_t *la, const int32_t *ua, const double *diag, const double *upper, const double *lower,
+                  void *stream) {
+    require(out != nullptr, CBS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    require(bdim >= 1 && bdim <= 5, CBS_ERR_ARG, "bdim must be in 1..5");
+    require(n_sys >= 1, CBS_ERR_ARG, "n_sys must be >= 1");
+    require(cell_off[0] == 0 && face_off[0] == 0, CBS_ERR_ARG, "offsets must start at 0");
+    for (int s = 0; s < n_sys; ++s) {
+        require(cell_off[s + 1] > cell_off[s], CBS_ERR_ARG, "every system needs at least one cell");
+        require(face_off[s + 1] >= face_off[s], CBS_ERR_ARG, "face offsets must not decrease");
+    }
+    const int64_t N = cell_off[n_sys], F = face_off[n_sys];
+    require(N + 2 * F < (int64_t)INT32_MAX, CBS_ERR_ARG, "too many blocks for 32-bit block indices");
+    require(diag != nullptr, CBS_ERR_ARG, "diag is NULL");
+    require(F == 0 || (la && ua && upper && lower), CBS_ERR_ARG, "face arrays are NULL");
+    std::unique_ptr<cbs_system> h(new cbs_system());
+    h->N = (int32_t)N; h->F = (int32_t)F; h->n = bdim; h->n_sys = n_sys;
+    h->stream = (hipStream_t)stream;
+    h->cell_off.assign(cell_off, cell_off + n_sys + 1);
+    h->face_off.assign(face_off, face_off + n_sys + 1);
+    HIPCHK(hipEventCreate(&h->ev0));
+    HIPCHK(hipEventCreate(&h->ev1));
+    h->dflag.alloc(4);
+    h->scal.alloc((size_t)S_NSCAL * n_sys);
+    h->done.alloc((size_t)3 * n_sys);
+    h->flags.alloc((size_t)5 * n_sys);
+    HIPCHK(hipMemsetAsync(h->flags.get(), 0, sizeof(int32_t) * 5 * n_sys, h->stream));
+    build_items(h.get());
+    const auto t0 = std::chrono::steady_clock::now();
+    HIPCHK(hipEventRecord(h->ev0, h->stream));
+    globalize_faces(h.get(), la, ua);
+    convert_pattern(h.get());
+    convert_values(h.get(), diag, upper, lower);
+    HIPCHK(hipEventRecord(h->ev1, h->stream));
+    h->t_convert_ms = elapsed_ms(h->ev0, h->ev1);
+    (void)t0;
+    ensure_level0(h.get());
+    *out = h.release();
+    return CBS_OK;
+}
+}  // namespace
+
+[[noreturn]] void cbs_throw(int code, const std::string &msg) { throw CbsError{code, msg}; }
+
+cbs_system::~cbs_system() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    else (void)hipDeviceSynchronize();
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+}
+
+extern "C" {
+
+void cbs_default_options(cbs_options *o) {
+    if (!o) return;
+    o->solver = CBS_SOLVER_BICGSTAB;
+    o->restart = 30;
+    o->precond = CBS_PREC_AMG;
+    o->smoother = CBS_SMOOTH_BJACOBI;
+    o->pre_sweeps = 1;
+    o->post_sweeps = 1;
+    o->omega = 0.8;
+    o->tol = 1e-8;
+    o->max_iter = 500;
+    o->precision = CBS_PRECISION_FP64;
+    o->coarse_max = 16;
+    o->match_passes = 2;
+    o->max_levels = 24;
+    o->reuse_aggregates = 0;
+    o->check_every = 1;
+}
+
+int cbs_create_from_ldu(cbs_handle *out, int32_t n_cells, int32_t n_faces, int32_t bdim, const int32_t *lower_addr,
+                        const int32_t *upper_addr, const double *diag, const double *upper, const double *lower,
+                        void *stream) {
+    return guarded([&] {
+        require(n_cells >= 1 && n_faces >= 0, CBS_ERR_ARG, "need n_cells >= 1 and n_faces >= 0");
+        const int64_t co[2] = {0, n_cells}, fo[2] = {0, n_faces};
+        return create_common(out, 1, co, fo, bdim, lower_addr, upper_addr, diag, upper, lower, stream);
+    });
+}
+
+int cbs_create_batch_from_ldu(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const int64_t *face_off,
+                              int32_t bdim, const int32_t *lower_addr, const int32_t *upper_addr, const double *diag,
+                              const double *upper, const double *lower, void *stream) {
+    return guarded([&] {
+        require(cell_off != nullptr && face_off != nullptr, CBS_ERR_ARG, "offset arrays are NULL");
+        return create_common(out, n_sys, cell_off, face_off, bdim, lower_addr, upper_addr, diag, upper, lower, stream);
+    });
+}
+
+int cbs_update_values(cbs_handle h, const double *diag, const double *upper, const double *lower) {
+    return guarded([&] {
+        require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        require(diag != nullptr && (h->F == 0 || (upper && lower)), CBS_ERR_ARG, "value arrays are NULL");
+        HIPCHK(hipEventRecord(h->ev0, h->stream));
+        convert_values(h, diag, upper, lower);
+        HIPCHK(hipEventRecord(h->ev1, h->stream));
+        h->t_convert_ms = elapsed_ms(h->ev0, h->ev1);
+        h->values_changed = true;
+        h->transposed_ready = false;
+        return CBS_OK;
+    });
+}
+
+int cbs_setup(cbs_handle h, const cbs_options *opt) {
+    return guarded([&] {
+        require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        cbs_options o;
+        if (opt) o = *opt; else cbs_default_options(&o);
+        require(o.solver == CBS_SOLVER_BICGSTAB || o.solver == CBS_SOLVER_FGMRES, CBS_ERR_ARG, "unknown solver");
+        require(o.precond >= CBS_PREC_NONE && o.precond <= CBS_PREC_AMG, CBS_ERR_ARG, "unknown preconditioner");
+        require(o.smoother == CBS_SMOOTH_BJACOBI || o.smoother == CBS_SMOOTH_DILU, CBS_ERR_ARG, "unknown smoother");
+        require(o.precision == CBS_PRECISION_FP64 || o.precision == CBS_PRECISION_MIXED, CBS_ERR_ARG,
+                "unknown precision");
+        require(o.restart >= 1 && o.restart <= 200, CBS_ERR_ARG, "restart must be in 1..200");
+        require(o.tol > 0.0 && o.max_iter >= 0, CBS_ERR_ARG, "need tol > 0 and max_iter >= 0");
+        require(o.coarse_max >= 1 && o.max_levels >= 1 && o.match_passes >= 1, CBS_ERR_ARG,
+                "coarse_max, max_levels and match_passes must be >= 1");
+        require(o.pre_sweeps >= 0 && o.post_sweeps >= 0, CBS_ERR_ARG, "sweeps must be >= 0");
+        if (o.smoother == CBS_SMOOTH_DILU) cbs_throw(CBS_ERR_ARG, "DILU smoother is not available in this build");
+        const bool keep = o.reuse_aggregates && h->setup_done && h->opt.precision == o.precision &&
+                          h->opt.precond == o.precond && h->opt.smoother == o.smoother &&
+                          h->opt.coarse_max == o.coarse_max && h->opt.match_passes == o.match_passes &&
+                          h->opt.max_levels == o.max_levels;
+        if (!keep) o.reuse_aggregates = 0;
+        h->opt = o;
+        ensure_level0(h);
+        HIPCHK(hipEventRecord(h->ev0, h->stream));
+        h->setup_done = false;
+        amg_setup(h);
+        alloc_krylov(h);
+        HIPCHK(hipEventRecord(h->ev1, h->stream));
+        h->t_setup_ms = elapsed_ms(h->ev0, h->ev1);
+        h->setup_done = true;
+        h->values_changed = false;
+        return CBS_OK;
+    });
+}
+
+int cbs_solve(cbs_handle h, const double *b, double *x, cbs_stats *st) {
+    return guarded([&] {
+        require(h != nullptr && b != nullptr && x != nullptr, CBS_ERR_ARG, "NULL argument");
+        require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
+        check_finite(x, (int64_t)h->N * h->n, h->dflag.get(), h->stream);
+        return krylov_solve(h, b, x, st, false);
+    });
+}
+
+int cbs_solve_transpose(cbs_handle h, const double *g, double *lambda, cbs_stats *st) {
+    return guarded([&] {
+        require(h != nullptr && g != nullptr && lambda != nullptr, CBS_ERR_ARG, "NULL argument");
+        require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
+        check_finite(lambda, (int64_t)h->N * h->n, h->dflag.get(), h->stream);
+        return krylov_solve(h, g, lambda, st, true);
+    });
+}
+
+int cbs_gradient(cbs_handle h, const double *lambda, const double *x, double *gd, double *gu, double *gl) {
+    return guarded([&] {
+        require(h != nullptr && lambda && x && gd && (h->F == 0 || (gu && gl)), CBS_ERR_ARG, "NULL argument");
+        gradient(h, lambda, x, gd, gu, gl);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return CBS_OK;
+    });
+}
+
+int cbs_spmv(cbs_handle h, const double *x, double *y, int32_t transpose) {
+    return guarded([&] {
+        require(h != nullptr && x && y, CBS_ERR_ARG, "NULL argument");
+        ensure_level0(h);
+        if (transpose) amg_build_transposed(h);
+        spmv64(h, x, y, transpose != 0);
+        return CBS_OK;
+    });
+}
+
+int cbs_apply_precond(cbs_handle h, const double *r, double *z) {
+    return guarded([&] {
+        require(h != nullptr && r && z, CBS_ERR_ARG, "NULL argument");
+        require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
+        precond_apply(h, r, z, false);
+        return CBS_OK;
+    });
+}
+
+int cbs_pack_fields(int32_t n_cells, int32_t bdim, const double *soa, double *aos, void *stream) {
+    return guarded([&] {
+        require(n_cells >= 0 && bdim >= 1 && soa && aos, CBS_ERR_ARG, "bad argument");
+        pack_fields(n_cells, bdim, soa, aos, (hipStream_t)stream);
+        return CBS_OK;
+    });
+}
+
+int cbs_unpack_fields(int32_t n_cells, int32_t bdim, const double *aos, double *soa, void *stream) {
+    return guarded([&] {
+        require(n_cells >= 0 && bdim >= 1 && soa && aos, CBS_ERR_ARG, "bad argument");
+        unpack_fields(n_cells, bdim, aos, soa, (hipStream_t)stream);
+        return CBS_OK;
+    });
+}
+
+int cbs_get_info(cbs_handle h, int32_t *n_cells, int32_t *n_faces, int32_t *bdim, int64_t *nnzb, int32_t *levels,
+                 int32_t *n_sys) {
+    return guarded([&] {
+        require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        if (n_cells) *n_cells = h->N;
+        if (n_faces) *n_faces = h->F;
+        if (bdim) *bdim = h->n;
+        if (nnzb) *nnzb = h->nnzb;
+        if (levels) *levels = h->setup_done ? (int32_t)h->lev.size() : 0;
+        if (n_sys) *n_sys = h->n_sys;
+        return CBS_OK;
+    });
+}
+
+int cbs_get_bcsr(cbs_handle h, int32_t *row_ptr, int32_t *col, double *vals, int32_t *diag_slot, int32_t *upper_slot,
+                 int32_t *lower_slot) {
+    return guarded([&] {
+        require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        hipStream_t st = h->stream;
+        const size_t bs = (size_t)h->n * h->n;
+        if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, h->rp.get(), sizeof(int32_t) * (h->N + 1), hipMemcpyDeviceToDevice, st));
+        if (col) HIPCHK(hipMemcpyAsync(col, h->col.get(), sizeof(int32_t) * h->nnzb, hipMemcpyDeviceToDevice, st));
+        if (vals) HIPCHK(hipMemcpyAsync(vals, h->vals.get(), sizeof(double) * h->nnzb * bs, hipMemcpyDeviceToDevice, st));
+        if (diag_slot) HIPCHK(hipMemcpyAsync(diag_slot, h->dslot.get(), sizeof(int32_t) * h->N, hipMemcpyDeviceToDevice, st));
+        if (upper_slot && h->F)
+            HIPCHK(hipMemcpyAsync(upper_slot, h->uslot.get(), sizeof(int32_t) * h->F, hipMemcpyDeviceToDevice, st));
+        if (lower_slot && h->F)
+            HIPCHK(hipMemcpyAsync(lower_slot, h->lslot.get(), sizeof(int32_t) * h->F, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return CBS_OK;
+    });
+}
+
+int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows, int64_t *nnzb, int32_t *row_ptr, int32_t *col,
+                  double *vals, int32_t *agg, int32_t *colour) {
+    return guarded([&] {
+        require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        require(h->setup_done, CBS_ERR_STATE, "no hierarchy before cbs_setup");
+        require(level >= 0 && level < (int32_t)h->lev.size(), CBS_ERR_ARG, "level out of range");
+        Level &L = h->lev[level];
+        hipStream_t st = h->stream;
+        if (n_rows) *n_rows = L.N;
+        if (nnzb) *nnzb = L.nnzb;
+        const size_t bs = (size_t)h->n * h->n;
+        if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, L.rp, sizeof(int32_t) * (L.N + 1), hipMemcpyDeviceToDevice, st));
+        if (col) HIPCHK(hipMemcpyAsync(col, L.col, sizeof(int32_t) * L.nnzb, hipMemcpyDeviceToDevice, st));
+        if (vals) HIPCHK(hipMemcpyAsync(vals, L.v64, sizeof(double) * L.nnzb * bs, hipMemcpyDeviceToDevice, st));
+        if (agg && L.agg.get()) HIPCHK(hipMemcpyAsync(agg, L.agg.get(), sizeof(int32_t) * L.N, hipMemcpyDeviceToDevice, st));
+        if (colour && L.colour.get())
+            HIPCHK(hipMemcpyAsync(colour, L.colour.get(), sizeof(int32_t) * L.N, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return CBS_OK;
+    });
+}
+
+int cbs_destroy(cbs_handle h) {
+    return guarded([&] {
+        delete h;
+        return CBS_OK;
+    });
+}
+
+const char *cbs_error_string(int code) {
+    switch (code) {
+        case CBS_OK: return "CBS_OK";
+        case CBS_NOT_CONVERGED: return "CBS_NOT_CONVERGED";
+        case CBS_ERR_ARG: return "CBS_ERR_ARG";
+        case CBS_ERR_PATTERN: return "CBS_ERR_PATTERN";
+        case CBS_ERR_SINGULAR: return "CBS_ERR_SINGULAR";
+        case CBS_ERR_BREAKDOWN: return "CBS_ERR_BREAKDOWN";
+        case CBS_ERR_NONFINITE: return "CBS_ERR_NONFINITE";
+        case CBS_ERR_STATE: return "CBS_ERR_STATE";
+        case CBS_ERR_OOM: return "CBS_ERR_OOM";
+        case CBS_ERR_HIP: return "CBS_ERR_HIP";
+        default: return "CBS_UNKNOWN";
+    }
+}
+
+const char *cbs_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

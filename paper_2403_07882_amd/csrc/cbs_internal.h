@@ -1,0 +1,198 @@
+// cbs_internal.h -- device runtime shared by the HIP translation units of
+// libcbs.so (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "cbs.h"
+
+// ---------------------------------------------------------------- errors
+struct CbsError {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void cbs_throw(int code, const std::string &msg);
+
+#define HIPCHK(x)                                                                    \
+    do {                                                                             \
+        hipError_t e_ = (x);                                                         \
+        if (e_ != hipSuccess)                                                        \
+            cbs_throw(CBS_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+#define LAUNCHCHK() HIPCHK(hipGetLastError())
+
+// ---------------------------------------------------------------- memory
+// Owning device array (hipMalloc / hipFree).  Move-only.
+template <typename T>
+struct DArr {
+    T *p = nullptr;
+    size_t n = 0;
+    DArr() = default;
+    explicit DArr(size_t count) { alloc(count); }
+    DArr(const DArr &) = delete;
+    DArr &operator=(const DArr &) = delete;
+    DArr(DArr &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DArr &operator=(DArr &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DArr() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count) {
+            void *q = nullptr;
+            if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+                (void)hipGetLastError();
+                cbs_throw(CBS_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+            }
+            p = static_cast<T *>(q);
+        }
+        n = count;
+    }
+    // allocate only when the current buffer is too small
+    void ensure(size_t count) { if (n < count) alloc(count); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr; n = 0;
+    }
+    T *get() const { return p; }
+};
+
+// ---------------------------------------------------------------- vectors
+// A contiguous range of scalar vector elements belonging to one system.
+// Element-wise kernels and reductions run one workgroup per item, so the
+// per-system Krylov scalars are loaded once per workgroup.
+struct Item {
+    int32_t sys;
+    int32_t pad;
+    int64_t beg, end;
+};
+
+constexpr int kItemElems = 4096;      // scalar elements per work item
+constexpr int kVecThreads = 256;      // threads per element-wise workgroup
+
+// per-system scalar slots of the Krylov loops: scal[slot * n_sys + s]
+enum {
+    S_RHO = 0, S_RHO0, S_ALPHA, S_OMEGA, S_RV, S_TS, S_TT, S_RR, S_BB, S_RES0, S_SS,
+    S_NSCAL
+};
+
+// ---------------------------------------------------------------- levels
+struct Level {
+    int32_t N = 0;          // block rows
+    int64_t nnzb = 0;
+    // pattern (level 0 points at the handle's arrays)
+    int32_t *rp = nullptr, *col = nullptr, *mirror = nullptr, *dslot = nullptr;
+    double *v64 = nullptr;  // FP64 values
+    float *v32 = nullptr;   // FP32 copy (mixed precision)
+    double *v64T = nullptr; // transposed values (adjoint solve)
+    float *v32T = nullptr;
+    // owned storage (coarse levels own their pattern and values)
+    DArr<int32_t> o_rp, o_col, o_mirror, o_dslot;
+    DArr<double> o_v64, o_v64T;
+    DArr<float> o_v32, o_v32T;
+    // per-row system id and per-system row offsets (host copy)
+    DArr<int32_t> row_sys;
+    std::vector<int64_t> sys_off;
+    // smoother data (FP64 per the block-inversion rule)
+    DArr<double> Dinv, DinvT;
+    // DILU: colour classes
+    DArr<int32_t> colour, rows_by_colour;
+    std::vector<int32_t> colour_off;     // host, ncolours + 1
+    DArr<double> Einv, EinvT;
+    // transfer to the next level
+    DArr<int32_t> agg, agg_ptr, agg_mem;
+    int32_t nc = 0;
+    // level vectors in the hierarchy precision (bytes)
+    DArr<char> vb, vx, vr, vt;
+};
+
+struct Coarse {
+    DArr<double> inv;                    // per-system dense inverses, concatenated
+    DArr<double> invT;
+    DArr<int64_t> off;                   // element offset of each system's inverse
+    DArr<int32_t> m;                     // order of each system's matrix (rows * n)
+    DArr<int64_t> roff;                  // scalar-row offset of each system
+    int32_t max_m = 0;
+};
+
+// ---------------------------------------------------------------- handle
+struct cbs_system {
+    int32_t N = 0, F = 0, n = 0, n_sys = 1;
+    hipStream_t stream = nullptr;
+    std::vector<int64_t> cell_off, face_off;     // host
+    // level-0 pattern and conversion maps
+    DArr<int32_t> la, ua;                        // face addresses, global cell ids
+    DArr<int32_t> rp, col, src, mirror, dslot, uslot, lslot;
+    DArr<double> vals;                           // FP64 block CSR values
+    int64_t nnzb = 0;
+    // preconditioner
+    bool setup_done = false, values_changed = false, transposed_ready = false;
+    cbs_options opt{};
+    std::vector<Level> lev;
+    Coarse coarse;
+    double op_complexity = 1.0;
+    // Krylov workspace (FP64, N*n each)
+    DArr<double> r, rh, p, v, ph, s, sh, t, w;
+    DArr<double> V, Z, H, gvec, cs, sn, yv;      // FGMRES
+    DArr<double> scal, partial;                  // per-system scalars, reduction partials
+    DArr<int32_t> done, flags;                   // per-system converged / breakdown flags
+    DArr<Item> items;                            // element ranges for level-0 vectors
+    int32_t n_items = 0;
+    std::vector<int32_t> items_per_sys_off;      // host: first item of each system
+    DArr<int32_t> item_off;                      // device copy of the above
+    DArr<int32_t> dflag;                         // error flag scratch for checks
+    // pinned host mirrors for read-back
+    double *h_scal = nullptr;
+    int32_t *h_done = nullptr;
+    // statistics
+    double t_convert_ms = 0.0, t_setup_ms = 0.0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    ~cbs_system();
+};
+
+// ---------------------------------------------------------------- helpers
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// exclusive scan of n int32 counts into out[0..n] (out[n] = total); in may alias out
+void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, hipStream_t st);
+int32_t read_int(const int32_t *dptr, hipStream_t st);
+
+// conversion (convert.hip)
+void convert_pattern(cbs_system *h);
+void convert_values(cbs_system *h, const double *diag, const double *upper, const double *lower);
+void check_finite(const double *a, int64_t count, int32_t *dflag, hipStream_t st);
+void pack_fields(int32_t N, int32_t n, const double *soa, double *aos, hipStream_t st);
+void unpack_fields(int32_t N, int32_t n, const double *aos, double *soa, hipStream_t st);
+void gradient(cbs_system *h, const double *lam, const double *x, double *gd, double *gu, double *gl);
+
+// block-row kernels (spmv.hip).  T = FP64 or FP32 level precision.
+//   mode 0: y = A x;  mode 1: y = b - A x;  mode 2: y = x + omega Dinv (b - A x)
+//   mode 3: y = omega Dinv b (block-Jacobi sweep from a zero guess)
+template <typename TV, typename TX>
+void launch_rows(int mode, int n, int32_t N, const int32_t *rp, const int32_t *col, const TV *val,
+                 const TX *x, const TX *b, TX *y, const double *Dinv, double omega, hipStream_t st);
+template <typename TX>
+void launch_restrict(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem,
+                     const TX *r, TX *bc, hipStream_t st);
+template <typename TX>
+void launch_prolong(int n, int32_t N, const int32_t *agg, const TX *e, TX *x, hipStream_t st);
+template <typename TA, typename TB>
+void launch_cast(int64_t m, const TA *a, TB *b, hipStream_t st);
+void launch_coarse_solve(cbs_system *h, bool transposed, const void *b, void *x, bool fp32);
+void launch_block_apply(int n, int32_t N, const double *Dinv, const double *r, double *z, hipStream_t st);
+
+// AMG setup (amg.hip)
+void amg_setup(cbs_system *h);
+void amg_build_transposed(cbs_system *h);
+void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv);
+
+// Krylov (krylov.hip)
+int krylov_solve(cbs_system *h, const double *b, double *x, cbs_stats *st, bool transposed);
+void precond_apply(cbs_system *h, const double *r, double *z, bool transposed);
+void spmv64(cbs_system *h, const double *x, double *y, bool transposed);

@@ -1,0 +1,396 @@
+// convert.hip -- face-addressed LDU -> block CSR on the device, field
+// packing, and the LDU-layout gradient.
+//
+// Sec. 2.3 (Alg. amgxFoam, Fig. block_amgx): the coupled matrix keeps the
+// sparsity of the scalar problem; only the indices now address n x n blocks.
+// The conversion is a permutation of whole blocks, so it is done as
+//   pattern (once per topology): degree count -> scan -> placement -> per-row
+//     sort by column (diagonal inline) -> slot maps for diag/upper/lower;
+//   values (every coefficient update): vals[slot] = source block, copied
+//     element for element (bit-exact), writes fully coalesced.
+#include "cbs_internal.h"
+
+#include <algorithm>
+
+// ------------------------------------------------------------------ scan
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t *total) {
+    __shared__ int32_t wsum[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int32_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int32_t woff = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        if (w < wid) woff += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return woff + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int32_t *in, int32_t *out, int64_t n,
+                                                            int32_t *bsum) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int32_t v[kScanPer];
+    int32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        v[q] = (base + q < n) ? in[base + q] : 0;
+        s += v[q];
+    }
+    int32_t tot;
+    int32_t run = block_exclusive_scan(s, &tot);
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        if (base + q < n) out[base + q] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_add(int32_t *out, int64_t n, const int32_t *boff, int32_t nb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += boff[i / kScanTile];
+    if (i == 0) out[n] = boff[nb];
+}
+
+}  // namespace
+
+void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, hipStream_t st) {
+    if (n <= 0) {
+        HIPCHK(hipMemsetAsync(out, 0, sizeof(int32_t), st));
+        return;
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 1) {
+        // one tile: its total is the grand total, written straight to out[n]
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kScanThreads), 0, st, in, out, n, out + n);
+        LAUNCHCHK();
+        return;
+    }
+    DArr<int32_t> bsum(nb + 1);
+    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, out, n, bsum.get());
+    LAUNCHCHK();
+    scan_exclusive(bsum.get(), bsum.get(), nb, st);   // bsum[0..nb], bsum[nb] = total
+    hipLaunchKernelGGL(k_scan_add, dim3(cdiv(n, 256)), dim3(256), 0, st, out, n, bsum.get(), (int32_t)nb);
+    LAUNCHCHK();
+    // keep bsum alive until the kernels consuming it have run
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+int32_t read_int(const int32_t *dptr, hipStream_t st) {
+    int32_t v = 0;
+    HIPCHK(hipMemcpyAsync(&v, dptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return v;
+}
+
+// ------------------------------------------------------------------ pattern
+namespace {
+
+// Local face addresses -> global cell ids; flag bad faces.
+__global__ void k_globalize(int32_t F, int32_t n_sys, const int64_t *cell_off, const int64_t *face_off,
+                            const int32_t *la_in, const int32_t *ua_in, int32_t *la, int32_t *ua,
+                            int32_t *flag) {
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    int lo = 0, hi = n_sys - 1;            // system s with face_off[s] <= f < face_off[s+1]
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (face_off[mid] <= f) lo = mid; else hi = mid - 1;
+    }
+    const int64_t c0 = cell_off[lo], nc = cell_off[lo + 1] - c0;
+    const int32_t l = la_in[f], u = ua_in[f];
+    if (l < 0 || l >= nc || u < 0 || u >= nc || l == u) {
+        atomicOr(flag, 1);
+        la[f] = 0; ua[f] = 0;
+        return;
+    }
+    la[f] = (int32_t)(c0 + l);
+    ua[f] = (int32_t)(c0 + u);
+}
+
+__global__ void k_fill_int(int32_t *a, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void k_count(int32_t F, const int32_t *la, const int32_t *ua, int32_t *deg) {
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    atomicAdd(&deg[la[f]], 1);
+    atomicAdd(&deg[ua[f]], 1);
+}
+
+__global__ void k_place_diag(int32_t N, const int32_t *rp, int32_t *col, int32_t *src, int32_t *fill) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    col[rp[i]] = i;
+    src[rp[i]] = i;
+    fill[i] = rp[i] + 1;
+}
+
+// source code: i < N diag; N + f upper face f; N + F + f lower face f
+__global__ void k_place_faces(int32_t N, int32_t F, const int32_t *la, const int32_t *ua, int32_t *col,
+                              int32_t *src, int32_t *fill) {
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const int32_t l = la[f], u = ua[f];
+    int32_t p = atomicAdd(&fill[l], 1);
+    col[p] = u;
+    src[p] = N + f;
+    p = atomicAdd(&fill[u], 1);
+    col[p] = l;
+    src[p] = N + F + f;
+}
+
+// Insertion-sort each row by column (makes the atomic placement order
+// irrelevant: columns are unique, so the result is deterministic) and flag
+// duplicate columns.
+__global__ void k_sort_rows(int32_t N, const int32_t *rp, int32_t *col, int32_t *src, int32_t *flag) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t b = rp[i], e = rp[i + 1];
+    for (int32_t a = b + 1; a < e; ++a) {
+        const int32_t c = col[a], s = src[a];
+        int32_t q = a - 1;
+        while (q >= b && col[q] > c) {
+            col[q + 1] = col[q];
+            src[q + 1] = src[q];
+            --q;
+        }
+        col[q + 1] = c;
+        src[q + 1] = s;
+    }
+    for (int32_t a = b + 1; a < e; ++a)
+        if (col[a] == col[a - 1]) atomicOr(flag, 2);
+}
+
+__global__ void k_slots(int64_t nnzb, int32_t N, int32_t F, const int32_t *src, int32_t *dslot,
+                        int32_t *uslot, int32_t *lslot) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnzb) return;
+    const int32_t s = src[k];
+    if (s < N) dslot[s] = (int32_t)k;
+    else if (s < N + F) uslot[s - N] = (int32_t)k;
+    else lslot[s - N - F] = (int32_t)k;
+}
+
+__global__ void k_mirror(int64_t nnzb, int32_t N, int32_t F, const int32_t *src, const int32_t *uslot,
+                         const int32_t *lslot, int32_t *mirror) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnzb) return;
+    const int32_t s = src[k];
+    if (s < N) mirror[k] = (int32_t)k;
+    else if (s < N + F) mirror[k] = lslot[s - N];
+    else mirror[k] = uslot[s - N - F];
+}
+
+// row id of every system's rows
+__global__ void k_row_sys(int32_t N, int32_t n_sys, const int64_t *cell_off, int32_t *row_sys) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int lo = 0, hi = n_sys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cell_off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    row_sys[i] = lo;
+}
+
+// ------------------------------------------------------------------ values
+// One thread per scalar of the block-CSR value array: contiguous writes,
+// block-contiguous reads.  Non-finite inputs raise flag bit 4.
+template <int n>
+__global__ void k_values(int64_t total, int32_t N, int32_t F, const int32_t *src, const double *diag,
+                         const double *upper, const double *lower, double *vals, int32_t *flag) {
+    constexpr int nn = n * n;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int64_t k = g / nn;
+    const int e = (int)(g - k * nn);
+    const int32_t s = src[k];
+    const double *from = s < N ? diag + (int64_t)s * nn
+                       : (s < N + F ? upper + (int64_t)(s - N) * nn : lower + (int64_t)(s - N - F) * nn);
+    const double v = from[e];
+    if (!isfinite(v)) atomicOr(flag, 4);
+    vals[g] = v;
+}
+
+__global__ void k_check_finite(const double *a, int64_t count, int32_t *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count && !isfinite(a[i])) atomicOr(flag, 4);
+}
+
+}  // namespace
+
+void convert_pattern(cbs_system *h) {
+    hipStream_t st = h->stream;
+    const int32_t N = h->N, F = h->F;
+    DArr<int32_t> deg(N + 1);
+    hipLaunchKernelGGL(k_fill_int, dim3(cdiv(N, 256)), dim3(256), 0, st, deg.get(), (int64_t)N, 1);
+    if (F > 0)
+        hipLaunchKernelGGL(k_count, dim3(cdiv(F, 256)), dim3(256), 0, st, F, h->la.get(), h->ua.get(), deg.get());
+    LAUNCHCHK();
+    h->rp.alloc(N + 1);
+    scan_exclusive(deg.get(), h->rp.get(), N, st);
+    h->nnzb = (int64_t)N + 2 * (int64_t)F;
+    const int64_t nnzb = h->nnzb;
+    h->col.alloc(nnzb);
+    h->src.alloc(nnzb);
+    hipLaunchKernelGGL(k_place_diag, dim3(cdiv(N, 256)), dim3(256), 0, st, N, h->rp.get(), h->col.get(),
+                       h->src.get(), deg.get());
+    if (F > 0)
+        hipLaunchKernelGGL(k_place_faces, dim3(cdiv(F, 256)), dim3(256), 0, st, N, F, h->la.get(), h->ua.get(),
+                           h->col.get(), h->src.get(), deg.get());
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_sort_rows, dim3(cdiv(N, 256)), dim3(256), 0, st, N, h->rp.get(), h->col.get(),
+                       h->src.get(), h->dflag.get());
+    LAUNCHCHK();
+    if (read_int(h->dflag.get(), st) != 0) cbs_throw(CBS_ERR_PATTERN, "duplicate face (same cell pair twice)");
+    h->dslot.alloc(N);
+    h->uslot.alloc(F > 0 ? F : 1);
+    h->lslot.alloc(F > 0 ? F : 1);
+    h->mirror.alloc(nnzb);
+    hipLaunchKernelGGL(k_slots, dim3(cdiv(nnzb, 256)), dim3(256), 0, st, nnzb, N, F, h->src.get(),
+                       h->dslot.get(), h->uslot.get(), h->lslot.get());
+    hipLaunchKernelGGL(k_mirror, dim3(cdiv(nnzb, 256)), dim3(256), 0, st, nnzb, N, F, h->src.get(),
+                       h->uslot.get(), h->lslot.get(), h->mirror.get());
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+// exposed for the batched create
+void globalize_faces(cbs_system *h, const int32_t *la_in, const int32_t *ua_in) {
+    hipStream_t st = h->stream;
+    const int32_t F = h->F;
+    DArr<int64_t> coff(h->n_sys + 1), foff(h->n_sys + 1);
+    HIPCHK(hipMemcpyAsync(coff.get(), h->cell_off.data(), sizeof(int64_t) * (h->n_sys + 1),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(foff.get(), h->face_off.data(), sizeof(int64_t) * (h->n_sys + 1),
+                          hipMemcpyHostToDevice, st));
+    h->la.alloc(F > 0 ? F : 1);
+    h->ua.alloc(F > 0 ? F : 1);
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+    if (F > 0)
+        hipLaunchKernelGGL(k_globalize, dim3(cdiv(F, 256)), dim3(256), 0, st, F, h->n_sys, coff.get(), foff.get(),
+                           la_in, ua_in, h->la.get(), h->ua.get(), h->dflag.get());
+    LAUNCHCHK();
+    if (read_int(h->dflag.get(), st) != 0)
+        cbs_throw(CBS_ERR_PATTERN, "face index out of range or self face (lower_addr == upper_addr)");
+    // per-row system ids of level 0 are built in amg setup from cell_off
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+void build_row_sys(cbs_system *h, Level &L0) {
+    DArr<int64_t> coff(h->n_sys + 1);
+    HIPCHK(hipMemcpyAsync(coff.get(), h->cell_off.data(), sizeof(int64_t) * (h->n_sys + 1),
+                          hipMemcpyHostToDevice, h->stream));
+    L0.row_sys.alloc(h->N);
+    hipLaunchKernelGGL(k_row_sys, dim3(cdiv(h->N, 256)), dim3(256), 0, h->stream, h->N, h->n_sys, coff.get(),
+                       L0.row_sys.get());
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(h->stream));
+}
+
+void convert_values(cbs_system *h, const double *diag, const double *upper, const double *lower) {
+    hipStream_t st = h->stream;
+    const int n = h->n;
+    const int64_t total = h->nnzb * n * n;
+    h->vals.ensure(total);
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+    const dim3 g(cdiv(total, 256)), b(256);
+    switch (n) {
+        case 1: hipLaunchKernelGGL(k_values<1>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
+        case 2: hipLaunchKernelGGL(k_values<2>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
+        case 3: hipLaunchKernelGGL(k_values<3>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
+        case 4: hipLaunchKernelGGL(k_values<4>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
+        case 5: hipLaunchKernelGGL(k_values<5>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
+        default: cbs_throw(CBS_ERR_ARG, "bdim must be 1..5");
+    }
+    LAUNCHCHK();
+    if (read_int(h->dflag.get(), st) & 4) cbs_throw(CBS_ERR_NONFINITE, "non-finite matrix coefficient");
+}
+
+void check_finite(const double *a, int64_t count, int32_t *dflag, hipStream_t st) {
+    HIPCHK(hipMemsetAsync(dflag, 0, sizeof(int32_t), st));
+    if (count > 0) hipLaunchKernelGGL(k_check_finite, dim3(cdiv(count, 256)), dim3(256), 0, st, a, count, dflag);
+    LAUNCHCHK();
+    if (read_int(dflag, st) & 4) cbs_throw(CBS_ERR_NONFINITE, "non-finite entry in right-hand side or guess");
+}
+
+// ------------------------------------------------------------------ packing
+namespace {
+__global__ void k_pack(int32_t N, int32_t n, const double *soa, double *aos) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)N * n) return;
+    const int64_t i = g / n;
+    const int v = (int)(g - i * n);
+    aos[g] = soa[(int64_t)v * N + i];
+}
+__global__ void k_unpack(int32_t N, int32_t n, const double *aos, double *soa) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)N * n) return;
+    const int v = (int)(g / N);
+    const int64_t i = g - (int64_t)v * N;
+    soa[g] = aos[i * n + v];
+}
+
+template <int n>
+__global__ void k_grad(int32_t N, int32_t F, const int32_t *la, const int32_t *ua, const double *lam,
+                       const double *x, double *gd, double *gu, double *gl) {
+    constexpr int nn = n * n;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nd = (int64_t)N * nn, nf = (int64_t)F * nn;
+    if (g < nd) {
+        const int64_t i = g / nn;
+        const int e = (int)(g - i * nn), r = e / n, c = e - r * n;
+        gd[g] = -lam[i * n + r] * x[i * n + c];
+    } else if (g < nd + nf) {
+        const int64_t q = g - nd, f = q / nn;
+        const int e = (int)(q - f * nn), r = e / n, c = e - r * n;
+        const int64_t l = la[f], u = ua[f];
+        gu[q] = -lam[l * n + r] * x[u * n + c];
+        gl[q] = -lam[u * n + r] * x[l * n + c];
+    }
+}
+}  // namespace
+
+void pack_fields(int32_t N, int32_t n, const double *soa, double *aos, hipStream_t st) {
+    const int64_t m = (int64_t)N * n;
+    if (m > 0) hipLaunchKernelGGL(k_pack, dim3(cdiv(m, 256)), dim3(256), 0, st, N, n, soa, aos);
+    LAUNCHCHK();
+}
+
+void unpack_fields(int32_t N, int32_t n, const double *aos, double *soa, hipStream_t st) {
+    const int64_t m = (int64_t)N * n;
+    if (m > 0) hipLaunchKernelGGL(k_unpack, dim3(cdiv(m, 256)), dim3(256), 0, st, N, n, aos, soa);
+    LAUNCHCHK();
+}
+
+void gradient(cbs_system *h, const double *lam, const double *x, double *gd, double *gu, double *gl) {
+    const int64_t tot = ((int64_t)h->N + h->F) * h->n * h->n;
+    const dim3 g(cdiv(tot, 256)), b(256);
+    hipStream_t st = h->stream;
+    switch (h->n) {
+        case 1: hipLaunchKernelGGL(k_grad<1>, g, b, 0, st, h->N, h->F, h->la.get(), h->ua.get(), lam, x, gd, gu, gl); break;
+        case 2: hipLaunchKernelGGL(k_grad<2>, g, b, 0, st, h->N, h->F, h->la.get(), h->ua.get(), lam, x, gd, gu, gl); break;
+        case 3: hipLaunchKernelGGL(k_grad<3>, g, b, 0, st, h->N, h->F, h->la.get(), h->ua.get(), lam, x, gd, gu, gl); break;
+        case 4: hipLaunchKernelGGL(k_grad<4>, g, b, 0, st, h->N, h->F, h->la.get(), h->ua.get(), lam, x, gd, gu, gl); break;
+        case 5: hipLaunchKernelGGL(k_grad<5>, g, b, 0, st, h->N, h->F, h->la.get(), h->ua.get(), lam, x, gd, gu, gl); break;
+    }
+    LAUNCHCHK();
+}

@@ -1,0 +1,726 @@
+// krylov.hip -- preconditioned BiCGStab and flexible GMRES(m) on the device,
+// the AMG V-cycle, and the mixed-precision wrapper.
+//
+// Solver families of Sec. 2.3 (GMRES, bi-conjugate gradient) with the AMG
+// preconditioner.  All Krylov scalars (rho, alpha, omega, Hessenberg, Givens)
+// live in device memory, one set per system, so a batch of independent
+// systems runs through the same launches; the host only reads the
+// per-system "converged" flags every `check_every` iterations.  Reductions
+// are two-stage and deterministic: one partial per (system, work item),
+// then a per-system sum over its items in a fixed order.
+//
+// Mixed precision: the hierarchy (level matrices, smoother sweeps, level
+// vectors) runs in FP32, while residuals, inner products, D^{-1} and the
+// coarsest dense inverse stay FP64 (FP64 -> FP32 casts round to nearest even).
+#include "cbs_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+namespace {
+
+enum { PH_INIT = 0, PH_ALPHA, PH_OMEGA, PH_END, PH_RESTART, PH_TRUE };
+
+__device__ inline double block_sum(double v, double *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    __syncthreads();
+    return t;   // valid in thread 0
+}
+
+// up to three dot products of one work item -> partial[q * n_items + item]
+__global__ __launch_bounds__(kVecThreads) void k_dots(const Item *__restrict__ items, int32_t n_items,
+                                                      const int32_t *__restrict__ done, int K,
+                                                      const double *a0, const double *b0, const double *a1,
+                                                      const double *b1, const double *a2, const double *b2,
+                                                      double *partial) {
+    __shared__ double sh[kVecThreads / 64];
+    const Item it = items[blockIdx.x];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (!done[it.sys]) {
+        for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) {
+            s0 += a0[e] * b0[e];
+            if (K > 1) s1 += a1[e] * b1[e];
+            if (K > 2) s2 += a2[e] * b2[e];
+        }
+    }
+    s0 = block_sum(s0, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s0;
+    if (K > 1) { s1 = block_sum(s1, sh); if (threadIdx.x == 0) partial[n_items + blockIdx.x] = s1; }
+    if (K > 2) { s2 = block_sum(s2, sh); if (threadIdx.x == 0) partial[2 * n_items + blockIdx.x] = s2; }
+}
+
+__device__ inline double sum_items(const double *partial, int32_t n_items, int q, int32_t i0, int32_t i1) {
+    double t = 0.0;
+    for (int32_t k = i0; k < i1; ++k) t += partial[q * n_items + k];
+    return t;
+}
+
+#define SC(slot) scal[(slot) * nsys + s]
+
+// Per-system scalar updates after a reduction.  flags: bit0 breakdown.
+__global__ void k_fin(int phase, int32_t nsys, const int32_t *__restrict__ item_off, int32_t n_items,
+                      const double *__restrict__ partial, double *scal, int32_t *done, int32_t *flags,
+                      int32_t *iters, double tol2, const int32_t *restart_mask) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys) return;
+    const int32_t i0 = item_off[s], i1 = item_off[s + 1];
+    if (phase == PH_INIT) {
+        const double rr = sum_items(partial, n_items, 0, i0, i1), bb = sum_items(partial, n_items, 1, i0, i1);
+        SC(S_RR) = rr; SC(S_BB) = bb; SC(S_RES0) = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+        SC(S_RHO) = rr; SC(S_RHO0) = 1.0; SC(S_ALPHA) = 1.0; SC(S_OMEGA) = 1.0;
+        done[s] = (bb == 0.0 || rr <= tol2 * bb) ? 1 : 0;
+        flags[s] = 0;
+        iters[s] = 0;
+        return;
+    }
+    if (phase == PH_TRUE) {                          // true residual of every system
+        SC(S_RR) = sum_items(partial, n_items, 0, i0, i1);
+        return;
+    }
+    if (phase == PH_RESTART) {                       // rhat = r; p = v = 0 done by the caller
+        if (!restart_mask[s]) return;
+        const double rr = sum_items(partial, n_items, 0, i0, i1);
+        SC(S_RR) = rr; SC(S_RHO) = rr; SC(S_RHO0) = 1.0; SC(S_ALPHA) = 1.0; SC(S_OMEGA) = 1.0;
+        done[s] = (SC(S_BB) == 0.0 || rr <= tol2 * SC(S_BB)) ? 1 : 0;
+        flags[s] = 0;
+        return;
+    }
+    if (done[s] || (flags[s] & 1)) return;
+    if (phase == PH_ALPHA) {
+        const double rv = sum_items(partial, n_items, 0, i0, i1);
+        SC(S_RV) = rv;
+        const double rho = SC(S_RHO);
+        if (rv == 0.0 || !isfinite(rv) || fabs(rv) < 1e-300 * fmax(SC(S_RR), 1e-300)) {
+            flags[s] |= 1;
+            SC(S_ALPHA) = 0.0;
+        } else {
+            SC(S_ALPHA) = rho / rv;
+        }
+        iters[s] += 1;
+    } else if (phase == PH_OMEGA) {
+        const double ts = sum_items(partial, n_items, 0, i0, i1), tt = sum_items(partial, n_items, 1, i0, i1);
+        SC(S_TS) = ts; SC(S_TT) = tt;
+        SC(S_OMEGA) = tt > 0.0 ? ts / tt : 0.0;
+    } else if (phase == PH_END) {
+        const double rr = sum_items(partial, n_items, 0, i0, i1), rhn = sum_items(partial, n_items, 1, i0, i1);
+        SC(S_RR) = rr;
+        SC(S_RHO0) = SC(S_RHO);
+        SC(S_RHO) = rhn;
+        if (rr <= tol2 * SC(S_BB)) done[s] = 1;
+        else if (SC(S_OMEGA) == 0.0 || rhn == 0.0 || !isfinite(rhn) || (flags[s] & 1)) flags[s] |= 1;
+    }
+}
+
+// p = r + beta (p - omega v),  beta = (rho / rho0) (alpha / omega)
+__global__ __launch_bounds__(kVecThreads) void k_p_update(const Item *__restrict__ items, int32_t nsys,
+                                                          const int32_t *__restrict__ done,
+                                                          const double *__restrict__ scal,
+                                                          const int32_t *__restrict__ flags, const double *r,
+                                                          double *p, const double *v) {
+    const Item it = items[blockIdx.x];
+    const int s = it.sys;
+    if (done[s] || flags[s]) return;
+    const double omega = SC(S_OMEGA);
+    const double beta = (SC(S_RHO) / SC(S_RHO0)) * (SC(S_ALPHA) / omega);
+    for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) p[e] = r[e] + beta * (p[e] - omega * v[e]);
+}
+
+// s = r - alpha v
+__global__ __launch_bounds__(kVecThreads) void k_s_update(const Item *__restrict__ items, int32_t nsys,
+                                                          const int32_t *__restrict__ done,
+                                                          const double *__restrict__ scal,
+                                                          const int32_t *__restrict__ flags, const double *r,
+                                                          const double *v, double *sv) {
+    const Item it = items[blockIdx.x];
+    const int s = it.sys;
+    if (done[s] || flags[s]) return;
+    const double alpha = SC(S_ALPHA);
+    for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) sv[e] = r[e] - alpha * v[e];
+}
+
+// x += alpha ph + omega sh;  r = s - omega t;  partials (r,r), (rhat,r)
+__global__ __launch_bounds__(kVecThreads) void k_xr_update(const Item *__restrict__ items, int32_t n_items,
+                                                           int32_t nsys, const int32_t *__restrict__ done,
+                                                           const double *__restrict__ scal,
+                                                           const int32_t *__restrict__ flags, double *x,
+                                                           const double *ph, const double *sh, double *r,
+                                                           const double *sv, const double *t, const double *rh,
+                                                           double *partial) {
+    __shared__ double red[kVecThreads / 64];
+    const Item it = items[blockIdx.x];
+    const int s = it.sys;
+    double s0 = 0.0, s1 = 0.0;
+    if (!done[s] && !flags[s]) {
+        const double alpha = SC(S_ALPHA), omega = SC(S_OMEGA);
+        for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) {
+            x[e] += alpha * ph[e] + omega * sh[e];
+            const double re = sv[e] - omega * t[e];
+            r[e] = re;
+            s0 += re * re;
+            s1 += rh[e] * re;
+        }
+    }
+    s0 = block_sum(s0, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s0;
+    s1 = block_sum(s1, red);
+    if (threadIdx.x == 0) partial[n_items + blockIdx.x] = s1;
+}
+
+// masked vector ops: y = a (copy), y = 0, x = 0 where b = 0 systems
+__global__ void k_mask_copy(const Item *__restrict__ items, const int32_t *__restrict__ mask, int want,
+                            const double *a, double *y) {
+    const Item it = items[blockIdx.x];
+    if ((mask[it.sys] != 0) != (want != 0)) return;
+    for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) y[e] = a ? a[e] : 0.0;
+}
+
+__global__ void k_zero_if_bzero(const Item *__restrict__ items, int32_t nsys, const double *__restrict__ scal,
+                                double *x) {
+    const Item it = items[blockIdx.x];
+    const int s = it.sys;
+    if (SC(S_BB) != 0.0) return;
+    for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) x[e] = 0.0;
+}
+
+// ------------------------------------------------------------------ FGMRES
+// multi-dot: partial[i * n_items + item] = (w, V_i), i = 0..j
+__global__ __launch_bounds__(kVecThreads) void k_mdot(const Item *__restrict__ items, int32_t n_items,
+                                                      const int32_t *__restrict__ done, int j, int64_t ld,
+                                                      const double *__restrict__ V, const double *__restrict__ w,
+                                                      double *partial) {
+    __shared__ double red[kVecThreads / 64];
+    const Item it = items[blockIdx.x];
+    const bool act = !done[it.sys];
+    for (int i = 0; i <= j; ++i) {
+        double acc = 0.0;
+        if (act)
+            for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) acc += w[e] * V[i * ld + e];
+        acc = block_sum(acc, red);
+        if (threadIdx.x == 0) partial[(int64_t)i * n_items + blockIdx.x] = acc;
+    }
+}
+
+// h_i (per system) = sum of partials; accumulate into H(:, j); store in coef
+__global__ void k_mdot_fin(int32_t nsys, int j, int m, const int32_t *__restrict__ item_off, int32_t n_items,
+                           const double *__restrict__ partial, const int32_t *__restrict__ done, double *H,
+                           double *coef, int accumulate) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys || done[s]) return;
+    for (int i = 0; i <= j; ++i) {
+        const double hv = sum_items(partial, n_items, i, item_off[s], item_off[s + 1]);
+        double *Hs = H + (int64_t)s * (m + 1) * m;
+        Hs[i * m + j] = accumulate ? Hs[i * m + j] + hv : hv;
+        coef[(int64_t)s * (m + 1) + i] = hv;
+    }
+}
+
+// w -= sum_i coef_i V_i
+__global__ __launch_bounds__(kVecThreads) void k_maxpy(const Item *__restrict__ items, const int32_t *__restrict__ done,
+                                                       int j, int m, int64_t ld, const double *__restrict__ V,
+                                                       const double *__restrict__ coef, double *w) {
+    const Item it = items[blockIdx.x];
+    if (done[it.sys]) return;
+    const double *c = coef + (int64_t)it.sys * (m + 1);
+    for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) {
+        double acc = w[e];
+        for (int i = 0; i <= j; ++i) acc -= c[i] * V[i * ld + e];
+        w[e] = acc;
+    }
+}
+
+// y = a * inv(scal) per system: V_{j+1} = w / hn ; V_0 = r / beta
+__global__ __launch_bounds__(kVecThreads) void k_scale(const Item *__restrict__ items, const int32_t *__restrict__ done,
+                                                       const double *__restrict__ nrm, int stride, const double *a,
+                                                       double *y) {
+    const Item it = items[blockIdx.x];
+    if (done[it.sys]) return;
+    const double d = nrm[(int64_t)it.sys * stride];
+    const double f = d > 0.0 ? 1.0 / d : 0.0;
+    for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) y[e] = a[e] * f;
+}
+
+// Restart start: beta = ||r||, g = (beta, 0, ...), converged check.
+__global__ void k_gm_start(int32_t nsys, int m, const int32_t *__restrict__ item_off, int32_t n_items,
+                           const double *__restrict__ partial, double *scal, double *g, int32_t *done,
+                           int32_t *jlen, double tol2, int first) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys) return;
+    const double rr = sum_items(partial, n_items, 0, item_off[s], item_off[s + 1]);
+    SC(S_RR) = rr;
+    if (first) {
+        const double bb = sum_items(partial, n_items, 1, item_off[s], item_off[s + 1]);
+        SC(S_BB) = bb;
+        SC(S_RES0) = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    }
+    const double beta = sqrt(rr);
+    SC(S_RHO) = beta;            // ||r|| of this cycle
+    double *gs = g + (int64_t)s * (m + 1);
+    for (int i = 0; i <= m; ++i) gs[i] = 0.0;
+    gs[0] = beta;
+    jlen[s] = 0;
+    done[s] = (SC(S_BB) == 0.0 || rr <= tol2 * SC(S_BB)) ? 1 : 0;
+}
+
+// After the orthogonalisation of column j: H(j+1,j) = ||w||, apply the
+// previous rotations, make rotation j, update g, and test |g(j+1)|.
+__global__ void k_gm_givens(int32_t nsys, int j, int m, const int32_t *__restrict__ item_off, int32_t n_items,
+                            const double *__restrict__ partial, double *scal, double *H, double *cs, double *sn,
+                            double *g, int32_t *done, int32_t *jlen, int32_t *iters, double tol2, double *hn_out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys || done[s]) return;
+    const double hn = sqrt(sum_items(partial, n_items, 0, item_off[s], item_off[s + 1]));
+    double *Hs = H + (int64_t)s * (m + 1) * m;
+    double *c = cs + (int64_t)s * (m + 1), *sv = sn + (int64_t)s * (m + 1), *gs = g + (int64_t)s * (m + 1);
+    Hs[(j + 1) * m + j] = hn;
+    hn_out[(int64_t)s * (m + 1)] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = Hs[i * m + j], b = Hs[(i + 1) * m + j];
+        Hs[i * m + j] = c[i] * a + sv[i] * b;
+        Hs[(i + 1) * m + j] = -sv[i] * a + c[i] * b;
+    }
+    const double a = Hs[j * m + j], b = Hs[(j + 1) * m + j];
+    const double den = sqrt(a * a + b * b);
+    c[j] = den > 0.0 ? a / den : 1.0;
+    sv[j] = den > 0.0 ? b / den : 0.0;
+    Hs[j * m + j] = den;
+    Hs[(j + 1) * m + j] = 0.0;
+    gs[j + 1] = -sv[j] * gs[j];
+    gs[j] = c[j] * gs[j];
+    jlen[s] = j + 1;
+    iters[s] += 1;
+    const double est = gs[j + 1] * gs[j + 1];
+    SC(S_RR) = est;
+    if (est <= tol2 * SC(S_BB) || hn == 0.0) done[s] = 1;
+}
+
+// y = H^{-1} g on the jlen x jlen upper triangle, per system
+__global__ void k_gm_solve(int32_t nsys, int m, const double *H, const double *g, const int32_t *jlen, double *y) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys) return;
+    const int j = jlen[s];
+    const double *Hs = H + (int64_t)s * (m + 1) * m;
+    const double *gs = g + (int64_t)s * (m + 1);
+    double *ys = y + (int64_t)s * (m + 1);
+    for (int i = m; i >= 0; --i) ys[i] = 0.0;
+    for (int i = j - 1; i >= 0; --i) {
+        double acc = gs[i];
+        for (int k = i + 1; k < j; ++k) acc -= Hs[i * m + k] * ys[k];
+        const double d = Hs[i * m + i];
+        ys[i] = d != 0.0 ? acc / d : 0.0;
+    }
+}
+
+// x += sum_i y_i Z_i (all systems; y = 0 beyond jlen)
+__global__ __launch_bounds__(kVecThreads) void k_gm_update(const Item *__restrict__ items, int m, int jmax, int64_t ld,
+                                                           const double *__restrict__ Z, const double *__restrict__ y,
+                                                           const int32_t *__restrict__ jlen, double *x) {
+    const Item it = items[blockIdx.x];
+    const double *ys = y + (int64_t)it.sys * (m + 1);
+    const int js = min(jmax, jlen[it.sys]);      // columns this system built in the cycle
+    for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) {
+        double acc = x[e];
+        for (int i = 0; i < js; ++i) acc += ys[i] * Z[i * ld + e];
+        x[e] = acc;
+    }
+}
+
+#undef SC
+
+// ------------------------------------------------------------------ helpers
+inline const int32_t *done_none(cbs_system *h) { return h->flags.get() + h->n_sys; }   // all-zero mask
+
+void dots(cbs_system *h, int K, const double *a0, const double *b0, const double *a1 = nullptr,
+          const double *b1 = nullptr, const double *a2 = nullptr, const double *b2 = nullptr,
+          const int32_t *mask = nullptr) {
+    hipLaunchKernelGGL(k_dots, dim3(h->n_items), dim3(kVecThreads), 0, h->stream, h->items.get(), h->n_items,
+                       mask ? mask : h->done.get(), K, a0, b0, a1, b1, a2, b2, h->partial.get());
+    LAUNCHCHK();
+}
+
+void fin(cbs_system *h, int phase, double tol2, const int32_t *restart_mask = nullptr) {
+    hipLaunchKernelGGL(k_fin, dim3(cdiv(h->n_sys, 64)), dim3(64), 0, h->stream, phase, h->n_sys, h->item_off.get(),
+                       h->n_items, h->partial.get(), h->scal.get(), h->done.get(), h->flags.get(),
+                       h->done.get() + 2 * h->n_sys, tol2, restart_mask);
+    LAUNCHCHK();
+}
+
+int32_t *iters_ptr(cbs_system *h) { return h->done.get() + 2 * h->n_sys; }
+
+// ------------------------------------------------------------------ V-cycle
+template <typename T> T *vptr(DArr<char> &a) { return reinterpret_cast<T *>(a.get()); }
+
+template <typename T>
+const T *level_vals(Level &L, bool tr);
+template <>
+const double *level_vals<double>(Level &L, bool tr) { return tr ? L.v64T : L.v64; }
+template <>
+const float *level_vals<float>(Level &L, bool tr) { return tr ? L.v32T : L.v32; }
+
+// x = V(b) with zero initial guess on level l; the result lands in x.
+template <typename T>
+void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
+    hipStream_t st = h->stream;
+    const cbs_options &o = h->opt;
+    const int n = h->n;
+    const int nlev = (int)h->lev.size();
+    Level &L = h->lev[l];
+    if (l == nlev - 1) {
+        launch_coarse_solve(h, tr, b, x, sizeof(T) == sizeof(float));
+        return;
+    }
+    const T *val = level_vals<T>(L, tr);
+    const double *Dinv = tr ? L.DinvT.get() : L.Dinv.get();
+    T *tmp = vptr<T>(L.vt);
+    T *r = vptr<T>(L.vr);
+    const int nu1 = std::max(0, o.pre_sweeps), nu2 = std::max(0, o.post_sweeps);
+    const int switches = (nu1 >= 1 ? nu1 - 1 : 0) + nu2;
+    T *cur = (switches % 2 == 0) ? x : tmp;
+    T *oth = (cur == x) ? tmp : x;
+    if (nu1 >= 1) {
+        launch_rows<T, T>(3, n, L.N, L.rp, L.col, val, cur, b, cur, Dinv, o.omega, st);
+        for (int s = 1; s < nu1; ++s) {
+            launch_rows<T, T>(2, n, L.N, L.rp, L.col, val, cur, b, oth, Dinv, o.omega, st);
+            std::swap(cur, oth);
+        }
+    } else {
+        HIPCHK(hipMemsetAsync(cur, 0, sizeof(T) * (size_t)L.N * n, st));
+    }
+    launch_rows<T, T>(1, n, L.N, L.rp, L.col, val, cur, b, r, Dinv, o.omega, st);
+    Level &C = h->lev[l + 1];
+    T *bc = vptr<T>(C.vb), *xc = vptr<T>(C.vx);
+    launch_restrict<T>(n, C.N, L.agg_ptr.get(), L.agg_mem.get(), r, bc, st);
+    vcycle<T>(h, tr, l + 1, bc, xc);
+    launch_prolong<T>(n, L.N, L.agg.get(), xc, cur, st);
+    for (int s = 0; s < nu2; ++s) {
+        launch_rows<T, T>(2, n, L.N, L.rp, L.col, val, cur, b, oth, Dinv, o.omega, st);
+        std::swap(cur, oth);
+    }
+}
+
+}  // namespace
+
+void spmv64(cbs_system *h, const double *x, double *y, bool transposed) {
+    const double *val = transposed ? h->lev[0].v64T : h->vals.get();
+    launch_rows<double, double>(0, h->n, h->N, h->rp.get(), h->col.get(), val, x, nullptr, y, nullptr, 0.0, h->stream);
+}
+
+static void residual64(cbs_system *h, const double *b, const double *x, double *r, bool transposed) {
+    const double *val = transposed ? h->lev[0].v64T : h->vals.get();
+    launch_rows<double, double>(1, h->n, h->N, h->rp.get(), h->col.get(), val, x, b, r, nullptr, 0.0, h->stream);
+}
+
+void precond_apply(cbs_system *h, const double *r, double *z, bool tr) {
+    const int n = h->n;
+    const int64_t m = (int64_t)h->N * n;
+    hipStream_t st = h->stream;
+    switch (h->opt.precond) {
+        case CBS_PREC_NONE:
+            HIPCHK(hipMemcpyAsync(z, r, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+            return;
+        case CBS_PREC_BJACOBI:
+            launch_block_apply(n, h->N, tr ? h->lev[0].DinvT.get() : h->lev[0].Dinv.get(), r, z, st);
+            return;
+        default:
+            break;
+    }
+    if (h->opt.precision == CBS_PRECISION_MIXED) {
+        Level &L0 = h->lev[0];
+        float *b32 = vptr<float>(L0.vb), *x32 = vptr<float>(L0.vx);
+        launch_cast<double, float>(m, r, b32, st);
+        vcycle<float>(h, tr, 0, b32, x32);
+        launch_cast<float, double>(m, x32, z, st);
+    } else {
+        vcycle<double>(h, tr, 0, r, z);
+    }
+}
+
+// ------------------------------------------------------------------ drivers
+namespace {
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct HostView {
+    std::vector<double> scal;
+    std::vector<int32_t> state;     // done | flags | iters
+};
+
+void read_state(cbs_system *h, HostView &hv, bool with_scal) {
+    hipStream_t st = h->stream;
+    hv.state.resize(3 * h->n_sys);
+    HIPCHK(hipMemcpyAsync(hv.state.data(), h->done.get(), sizeof(int32_t) * 3 * h->n_sys, hipMemcpyDeviceToHost, st));
+    if (with_scal) {
+        hv.scal.resize(S_NSCAL * h->n_sys);
+        HIPCHK(hipMemcpyAsync(hv.scal.data(), h->scal.get(), sizeof(double) * S_NSCAL * h->n_sys,
+                              hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+}
+
+// true residual r = b - A x of every system -> S_RR
+void true_residual(cbs_system *h, const double *b, const double *x, bool tr) {
+    residual64(h, b, x, h->r.get(), tr);
+    dots(h, 1, h->r.get(), h->r.get(), nullptr, nullptr, nullptr, nullptr, done_none(h));
+    fin(h, PH_TRUE, 0.0);
+}
+
+int bicgstab(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> &status) {
+    hipStream_t st = h->stream;
+    const cbs_options &o = h->opt;
+    const double tol2 = o.tol * o.tol;
+    const int nsys = h->n_sys;
+    double *r = h->r.get(), *rh = h->rh.get(), *p = h->p.get(), *v = h->v.get();
+    double *ph = h->ph.get(), *sv = h->s.get(), *sh = h->sh.get(), *t = h->t.get();
+    const Item *items = h->items.get();
+    const dim3 G(h->n_items), B(kVecThreads);
+    int32_t *rmask = h->flags.get() + 2 * nsys;     // restart mask scratch
+
+    residual64(h, b, x, r, tr);
+    dots(h, 2, r, r, b, b, nullptr, nullptr, done_none(h));
+    fin(h, PH_INIT, tol2);
+    hipLaunchKernelGGL(k_zero_if_bzero, G, B, 0, st, items, nsys, h->scal.get(), x);
+    HIPCHK(hipMemcpyAsync(rh, r, sizeof(double) * (size_t)h->N * h->n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(p, 0, sizeof(double) * (size_t)h->N * h->n, st));
+    HIPCHK(hipMemsetAsync(v, 0, sizeof(double) * (size_t)h->N * h->n, st));
+
+    std::vector<int> bd_restarts(nsys, 0), tr_restarts(nsys, 0);
+    status.assign(nsys, CBS_NOT_CONVERGED);
+    HostView hv;
+    int it = 0;
+    const int every = std::max(1, o.check_every);
+    for (;;) {
+        bool check = (it % every == 0) || it >= o.max_iter;
+        if (check) {
+            read_state(h, hv, false);
+            const int32_t *dn = hv.state.data(), *fl = dn + nsys;
+            bool all_done = true, any_bd = false;
+            for (int s = 0; s < nsys; ++s) {
+                if (status[s] == CBS_ERR_BREAKDOWN) continue;
+                if (!dn[s]) all_done = false;
+                if (fl[s] & 1) any_bd = true;
+            }
+            if (any_bd) {
+                // restart broken systems once from the true residual
+                std::vector<int32_t> mask(nsys, 0);
+                for (int s = 0; s < nsys; ++s) {
+                    if (status[s] == CBS_ERR_BREAKDOWN || !(fl[s] & 1)) continue;
+                    if (bd_restarts[s]++ >= 1) { status[s] = CBS_ERR_BREAKDOWN; mask[s] = 0; }
+                    else mask[s] = 1;
+                }
+                HIPCHK(hipMemcpyAsync(rmask, mask.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
+                residual64(h, b, x, h->w.get(), tr);
+                hipLaunchKernelGGL(k_mask_copy, G, B, 0, st, items, rmask, 1, h->w.get(), r);
+                hipLaunchKernelGGL(k_mask_copy, G, B, 0, st, items, rmask, 1, h->w.get(), rh);
+                hipLaunchKernelGGL(k_mask_copy, G, B, 0, st, items, rmask, 1, nullptr, p);
+                hipLaunchKernelGGL(k_mask_copy, G, B, 0, st, items, rmask, 1, nullptr, v);
+                dots(h, 1, r, r, nullptr, nullptr, nullptr, nullptr, done_none(h));
+                fin(h, PH_RESTART, tol2, rmask);
+                // systems out of restarts stay frozen: mark them done
+                for (int s = 0; s < nsys; ++s)
+                    if (status[s] == CBS_ERR_BREAKDOWN) {
+                        int32_t one = 1;
+                        HIPCHK(hipMemcpyAsync(h->done.get() + s, &one, sizeof(int32_t), hipMemcpyHostToDevice, st));
+                        HIPCHK(hipStreamSynchronize(st));
+                    }
+                continue;
+            }
+            if (all_done) {
+                // verify with the true residual; restart systems that fall short
+                true_residual(h, b, x, tr);
+                read_state(h, hv, true);
+                std::vector<int32_t> mask(nsys, 0);
+                bool any = false;
+                for (int s = 0; s < nsys; ++s) {
+                    if (status[s] == CBS_ERR_BREAKDOWN) continue;
+                    const double bb = hv.scal[S_BB * nsys + s], rr = hv.scal[S_RR * nsys + s];
+                    if (bb == 0.0 || rr <= tol2 * bb) status[s] = CBS_OK;
+                    else if (it < o.max_iter && tr_restarts[s]++ < 50) { mask[s] = 1; any = true; }
+                }
+                if (!any) break;
+                HIPCHK(hipMemcpyAsync(rmask, mask.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_mask_copy, G, B, 0, st, items, rmask, 1, r, rh);
+                hipLaunchKernelGGL(k_mask_copy, G, B, 0, st, items, rmask, 1, nullptr, p);
+                hipLaunchKernelGGL(k_mask_copy, G, B, 0, st, items, rmask, 1, nullptr, v);
+                dots(h, 1, r, r, nullptr, nullptr, nullptr, nullptr, done_none(h));
+                fin(h, PH_RESTART, tol2, rmask);
+                continue;
+            }
+        }
+        if (it >= o.max_iter) break;
+        // one BiCGStab iteration (right preconditioning)
+        hipLaunchKernelGGL(k_p_update, G, B, 0, st, items, nsys, h->done.get(), h->scal.get(), h->flags.get(), r, p, v);
+        precond_apply(h, p, ph, tr);
+        spmv64(h, ph, v, tr);
+        dots(h, 1, rh, v);
+        fin(h, PH_ALPHA, tol2);
+        hipLaunchKernelGGL(k_s_update, G, B, 0, st, items, nsys, h->done.get(), h->scal.get(), h->flags.get(), r, v, sv);
+        precond_apply(h, sv, sh, tr);
+        spmv64(h, sh, t, tr);
+        dots(h, 2, t, sv, t, t);
+        fin(h, PH_OMEGA, tol2);
+        hipLaunchKernelGGL(k_xr_update, G, B, 0, st, items, h->n_items, nsys, h->done.get(), h->scal.get(),
+                           h->flags.get(), x, ph, sh, r, sv, t, rh, h->partial.get());
+        fin(h, PH_END, tol2);
+        LAUNCHCHK();
+        ++it;
+    }
+    return it;
+}
+
+int fgmres(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> &status) {
+    hipStream_t st = h->stream;
+    const cbs_options &o = h->opt;
+    const double tol2 = o.tol * o.tol;
+    const int nsys = h->n_sys;
+    const int m = std::max(1, o.restart);
+    const int64_t ld = (int64_t)h->N * h->n;
+    double *r = h->r.get(), *w = h->w.get();
+    double *V = h->V.get(), *Z = h->Z.get();
+    const Item *items = h->items.get();
+    const dim3 G(h->n_items), B(kVecThreads), GS(cdiv(nsys, 64)), BS(64);
+    double *coef = h->yv.get() + (int64_t)nsys * (m + 1);       // (m+1) per system
+    double *hn = coef + (int64_t)nsys * (m + 1);                // 1 per system (stride m+1)
+    status.assign(nsys, CBS_NOT_CONVERGED);
+    HostView hv;
+    int it = 0;
+    bool first = true;
+    const int every = std::max(1, o.check_every);
+    int32_t *iters = iters_ptr(h);
+    HIPCHK(hipMemsetAsync(iters, 0, sizeof(int32_t) * nsys, st));
+    for (int cycle = 0;; ++cycle) {
+        residual64(h, b, x, r, tr);
+        dots(h, 2, r, r, b, b, nullptr, nullptr, done_none(h));
+        hipLaunchKernelGGL(k_gm_start, GS, BS, 0, st, nsys, m, h->item_off.get(), h->n_items, h->partial.get(),
+                           h->scal.get(), h->gvec.get(), h->done.get(), h->flags.get() + 3 * nsys, tol2, first ? 1 : 0);
+        if (first) hipLaunchKernelGGL(k_zero_if_bzero, G, B, 0, st, items, nsys, h->scal.get(), x);
+        first = false;
+        read_state(h, hv, false);
+        bool all_done = true;
+        for (int s = 0; s < nsys; ++s) {
+            if (hv.state[s]) status[s] = CBS_OK; else all_done = false;
+        }
+        if (all_done || it >= o.max_iter) break;
+        hipLaunchKernelGGL(k_scale, G, B, 0, st, items, h->done.get(), h->scal.get() + S_RHO * nsys, 1, r, V);
+        int j = 0;
+        for (; j < m && it < o.max_iter; ++j) {
+            double *vj = V + j * ld, *zj = Z + j * ld;
+            precond_apply(h, vj, zj, tr);
+            spmv64(h, zj, w, tr);
+            for (int pass = 0; pass < 2; ++pass) {        // classical Gram-Schmidt, twice
+                hipLaunchKernelGGL(k_mdot, G, B, 0, st, items, h->n_items, h->done.get(), j, ld, V, w, h->partial.get());
+                hipLaunchKernelGGL(k_mdot_fin, GS, BS, 0, st, nsys, j, m, h->item_off.get(), h->n_items,
+                                   h->partial.get(), h->done.get(), h->H.get(), coef, pass);
+                hipLaunchKernelGGL(k_maxpy, G, B, 0, st, items, h->done.get(), j, m, ld, V, coef, w);
+            }
+            dots(h, 1, w, w);
+            hipLaunchKernelGGL(k_gm_givens, GS, BS, 0, st, nsys, j, m, h->item_off.get(), h->n_items,
+                               h->partial.get(), h->scal.get(), h->H.get(), h->cs.get(), h->sn.get(), h->gvec.get(),
+                               h->done.get(), h->flags.get() + 3 * nsys, iters, tol2, hn);
+            hipLaunchKernelGGL(k_scale, G, B, 0, st, items, h->done.get(), hn, m + 1, w, V + (j + 1) * ld);
+            LAUNCHCHK();
+            ++it;
+            if ((it % every) == 0) {
+                read_state(h, hv, false);
+                bool ad = true;
+                for (int s = 0; s < nsys; ++s) ad = ad && hv.state[s];
+                if (ad) { ++j; break; }
+            }
+        }
+        const int jmax = std::min(j, m);
+        hipLaunchKernelGGL(k_gm_solve, GS, BS, 0, st, nsys, m, h->H.get(), h->gvec.get(), h->flags.get() + 3 * nsys,
+                           h->yv.get());
+        hipLaunchKernelGGL(k_gm_update, G, B, 0, st, items, m, jmax, ld, Z, h->yv.get(), h->flags.get() + 3 * nsys, x);
+        LAUNCHCHK();
+        // next cycle re-evaluates every system from its true residual
+        HIPCHK(hipMemsetAsync(h->done.get(), 0, sizeof(int32_t) * nsys, st));
+    }
+    // final true residual for the statistics
+    true_residual(h, b, x, tr);
+    return it;
+}
+
+}  // namespace
+
+void alloc_krylov(cbs_system *h) {
+    const int64_t m = (int64_t)h->N * h->n;
+    const int nsys = h->n_sys;
+    for (DArr<double> *a : {&h->r, &h->rh, &h->p, &h->v, &h->ph, &h->s, &h->sh, &h->t, &h->w}) a->ensure(m);
+    if (h->opt.solver == CBS_SOLVER_FGMRES) {
+        const int mr = std::max(1, h->opt.restart);
+        h->V.ensure((size_t)(mr + 1) * m);
+        h->Z.ensure((size_t)mr * m);
+        h->H.ensure((size_t)nsys * (mr + 1) * mr);
+        h->gvec.ensure((size_t)nsys * (mr + 1));
+        h->cs.ensure((size_t)nsys * (mr + 1));
+        h->sn.ensure((size_t)nsys * (mr + 1));
+        h->yv.ensure((size_t)nsys * (mr + 1) * 3);
+    }
+    const int K = std::max(3, h->opt.solver == CBS_SOLVER_FGMRES ? h->opt.restart + 2 : 3);
+    h->partial.ensure((size_t)K * h->n_items);
+}
+
+int krylov_solve(cbs_system *h, const double *b, double *x, cbs_stats *stv, bool tr) {
+    hipStream_t st = h->stream;
+    const int nsys = h->n_sys;
+    if (tr) amg_build_transposed(h);
+    check_finite(b, (int64_t)h->N * h->n, h->dflag.get(), st);
+    alloc_krylov(h);
+    HIPCHK(hipMemsetAsync(h->flags.get(), 0, sizeof(int32_t) * 5 * nsys, st));
+    HIPCHK(hipMemsetAsync(h->done.get(), 0, sizeof(int32_t) * 3 * nsys, st));
+    HIPCHK(hipEventRecord(h->ev0, st));
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<int> status;
+    if (h->opt.solver == CBS_SOLVER_FGMRES) fgmres(h, b, x, tr, status);
+    else bicgstab(h, b, x, tr, status);
+    HIPCHK(hipEventRecord(h->ev1, st));
+    // statistics: true residual per system (BiCGStab's last step may not have computed it)
+    std::vector<double> rr_rec(nsys), res0(nsys), bbv(nsys);
+    {
+        HostView hv;
+        read_state(h, hv, true);
+        for (int s = 0; s < nsys; ++s) {
+            rr_rec[s] = hv.scal[S_RR * nsys + s];
+            res0[s] = hv.scal[S_RES0 * nsys + s];
+            bbv[s] = hv.scal[S_BB * nsys + s];
+        }
+    }
+    true_residual(h, b, x, tr);
+    HostView hv;
+    read_state(h, hv, true);
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    (void)t0;
+    int worst = CBS_OK;
+    const double tol2 = h->opt.tol * h->opt.tol;
+    for (int s = 0; s < nsys; ++s) {
+        const double bb = bbv[s], rr = hv.scal[S_RR * nsys + s];
+        int stt = status[s];
+        if (stt != CBS_ERR_BREAKDOWN) stt = (bb == 0.0 || rr <= tol2 * bb) ? CBS_OK : CBS_NOT_CONVERGED;
+        if (stt < 0) worst = std::min(worst, stt);
+        else if (worst >= 0) worst = std::max(worst, stt);
+        if (stv) {
+            cbs_stats &S = stv[s];
+            S.iterations = hv.state[2 * nsys + s];
+            S.status = stt;
+            S.levels = (int32_t)h->lev.size();
+            S.precision_fallback = 0;
+            S.rel_res_true = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+            S.rel_res_recursive = bb > 0.0 ? std::sqrt(std::max(rr_rec[s], 0.0) / bb) : 0.0;
+            S.rel_res_initial = res0[s];
+            S.t_convert_ms = h->t_convert_ms;
+            S.t_setup_ms = h->t_setup_ms;
+            S.t_solve_ms = ms;
+            S.op_complexity = h->op_complexity;
+        }
+    }
+    return worst;
+}

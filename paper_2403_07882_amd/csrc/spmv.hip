@@ -1,0 +1,213 @@
+// spmv.hip -- block-row kernels: block SpMV, residual, block-Jacobi sweeps,
+// restriction / prolongation, precision casts and the coarsest-level solve.
+//
+// Block SpMV of the coupled system (Eq. coupl_system): y_i = sum_j A_ij x_j
+// over block CSR with dense n x n row-major blocks (Sec. 2.3).  Mapping for
+// gfx950: one workgroup = 64 block rows x n threads; thread (row i, r) owns
+// scalar row i*n + r and streams the r-th row of each block of block row i
+// (n contiguous values).  The n threads of a block row read the whole block
+// (n*n contiguous values) together, so every fetched cache line is used in
+// full; x_j is gathered once per block and shared through L1.  Smoother
+// modes finish with D_i^{-1} (FP64) applied to the n residual components of
+// the block row, exchanged through LDS.
+#include "cbs_internal.h"
+
+namespace {
+
+template <typename T> struct Acc { using type = double; };
+template <> struct Acc<float> { using type = float; };
+
+// mode 0: y = A x; 1: y = b - A x; 2: y = x + w Dinv (b - A x); 3: y = w Dinv b
+template <int n, typename TV, typename TX, int MODE>
+__global__ __launch_bounds__(64 * n) void k_rows(int32_t N, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ col, const TV *__restrict__ val,
+                                                 const TX *__restrict__ x, const TX *__restrict__ b,
+                                                 TX *__restrict__ y, const double *__restrict__ Dinv,
+                                                 double omega) {
+    using A = typename Acc<TX>::type;
+    const int t = threadIdx.x;
+    const int lr = t / n, r = t - lr * n;
+    const int32_t i = blockIdx.x * 64 + lr;
+    A acc = 0;
+    if (MODE != 3 && i < N) {
+        const int32_t kb = rp[i], ke = rp[i + 1];
+        for (int32_t k = kb; k < ke; ++k) {
+            const int32_t j = col[k];
+            const TV *B = val + (int64_t)k * (n * n) + r * n;
+            const TX *xj = x + (int64_t)j * n;
+#pragma unroll
+            for (int c = 0; c < n; ++c) acc += (A)B[c] * (A)xj[c];
+        }
+    }
+    const int64_t o = (int64_t)i * n + r;
+    if (MODE == 0) {
+        if (i < N) y[o] = (TX)acc;
+        return;
+    }
+    A res = 0;
+    if (i < N) res = (A)b[o] - acc;
+    if (MODE == 1) {
+        if (i < N) y[o] = (TX)res;
+        return;
+    }
+    __shared__ A sres[64 * n];
+    sres[t] = res;
+    __syncthreads();
+    if (i < N) {
+        const double *Di = Dinv + (int64_t)i * (n * n) + r * n;
+        double z = 0.0;
+#pragma unroll
+        for (int c = 0; c < n; ++c) z += Di[c] * (double)sres[lr * n + c];
+        const A xi = (MODE == 2) ? (A)x[o] : (A)0;
+        y[o] = (TX)(xi + (A)(omega * z));
+    }
+}
+
+template <int n, typename TV, typename TX>
+void rows_n(int mode, int32_t N, const int32_t *rp, const int32_t *col, const TV *val, const TX *x,
+            const TX *b, TX *y, const double *Dinv, double omega, hipStream_t st) {
+    const dim3 g(cdiv(N, 64)), bl(64 * n);
+    switch (mode) {
+        case 0: hipLaunchKernelGGL((k_rows<n, TV, TX, 0>), g, bl, 0, st, N, rp, col, val, x, b, y, Dinv, omega); break;
+        case 1: hipLaunchKernelGGL((k_rows<n, TV, TX, 1>), g, bl, 0, st, N, rp, col, val, x, b, y, Dinv, omega); break;
+        case 2: hipLaunchKernelGGL((k_rows<n, TV, TX, 2>), g, bl, 0, st, N, rp, col, val, x, b, y, Dinv, omega); break;
+        case 3: hipLaunchKernelGGL((k_rows<n, TV, TX, 3>), g, bl, 0, st, N, rp, col, val, x, b, y, Dinv, omega); break;
+    }
+}
+
+template <typename TX>
+__global__ void k_restrict(int32_t nc, int n, const int32_t *__restrict__ aptr, const int32_t *__restrict__ amem,
+                           const TX *__restrict__ r, TX *__restrict__ bc) {
+    using A = typename Acc<TX>::type;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)nc * n) return;
+    const int64_t I = g / n;
+    const int q = (int)(g - I * n);
+    A s = 0;
+    for (int32_t m = aptr[I]; m < aptr[I + 1]; ++m) s += (A)r[(int64_t)amem[m] * n + q];
+    bc[g] = (TX)s;
+}
+
+template <typename TX>
+__global__ void k_prolong(int32_t N, int n, const int32_t *__restrict__ agg, const TX *__restrict__ e,
+                          TX *__restrict__ x) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)N * n) return;
+    const int64_t i = g / n;
+    const int q = (int)(g - i * n);
+    x[g] += e[(int64_t)agg[i] * n + q];
+}
+
+template <typename TA, typename TB>
+__global__ void k_cast(int64_t m, const TA *__restrict__ a, TB *__restrict__ b) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < m) b[g] = (TB)a[g];
+}
+
+// Coarsest level: x_s = inv_s b_s for every system s (one workgroup each), FP64.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_coarse(const double *__restrict__ inv, const int64_t *__restrict__ off,
+                                                const int32_t *__restrict__ msz, const int64_t *__restrict__ roff,
+                                                const TX *__restrict__ b, TX *__restrict__ x) {
+    extern __shared__ double sb[];
+    const int s = blockIdx.x;
+    const int m = msz[s];
+    const int64_t r0 = roff[s];
+    for (int c = threadIdx.x; c < m; c += blockDim.x) sb[c] = (double)b[r0 + c];
+    __syncthreads();
+    const double *M = inv + off[s];
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+        double acc = 0.0;
+        for (int c = 0; c < m; ++c) acc += M[(int64_t)r * m + c] * sb[c];
+        x[r0 + r] = (TX)acc;
+    }
+}
+
+template <int n>
+__global__ void k_block_apply(int32_t N, const double *__restrict__ Dinv, const double *__restrict__ r,
+                              double *__restrict__ z) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)N * n) return;
+    const int64_t i = g / n;
+    const int q = (int)(g - i * n);
+    const double *Di = Dinv + i * (n * n) + q * n;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < n; ++c) s += Di[c] * r[i * n + c];
+    z[g] = s;
+}
+
+}  // namespace
+
+template <typename TV, typename TX>
+void launch_rows(int mode, int n, int32_t N, const int32_t *rp, const int32_t *col, const TV *val,
+                 const TX *x, const TX *b, TX *y, const double *Dinv, double omega, hipStream_t st) {
+    if (N <= 0) return;
+    switch (n) {
+        case 1: rows_n<1>(mode, N, rp, col, val, x, b, y, Dinv, omega, st); break;
+        case 2: rows_n<2>(mode, N, rp, col, val, x, b, y, Dinv, omega, st); break;
+        case 3: rows_n<3>(mode, N, rp, col, val, x, b, y, Dinv, omega, st); break;
+        case 4: rows_n<4>(mode, N, rp, col, val, x, b, y, Dinv, omega, st); break;
+        case 5: rows_n<5>(mode, N, rp, col, val, x, b, y, Dinv, omega, st); break;
+    }
+    LAUNCHCHK();
+}
+template void launch_rows<double, double>(int, int, int32_t, const int32_t *, const int32_t *, const double *,
+                                          const double *, const double *, double *, const double *, double, hipStream_t);
+template void launch_rows<float, float>(int, int, int32_t, const int32_t *, const int32_t *, const float *,
+                                        const float *, const float *, float *, const double *, double, hipStream_t);
+
+template <typename TX>
+void launch_restrict(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem, const TX *r, TX *bc,
+                     hipStream_t st) {
+    const int64_t m = (int64_t)nc * n;
+    if (m > 0) hipLaunchKernelGGL(k_restrict<TX>, dim3(cdiv(m, 256)), dim3(256), 0, st, nc, n, agg_ptr, agg_mem, r, bc);
+    LAUNCHCHK();
+}
+template void launch_restrict<double>(int, int32_t, const int32_t *, const int32_t *, const double *, double *, hipStream_t);
+template void launch_restrict<float>(int, int32_t, const int32_t *, const int32_t *, const float *, float *, hipStream_t);
+
+template <typename TX>
+void launch_prolong(int n, int32_t N, const int32_t *agg, const TX *e, TX *x, hipStream_t st) {
+    const int64_t m = (int64_t)N * n;
+    if (m > 0) hipLaunchKernelGGL(k_prolong<TX>, dim3(cdiv(m, 256)), dim3(256), 0, st, N, n, agg, e, x);
+    LAUNCHCHK();
+}
+template void launch_prolong<double>(int, int32_t, const int32_t *, const double *, double *, hipStream_t);
+template void launch_prolong<float>(int, int32_t, const int32_t *, const float *, float *, hipStream_t);
+
+template <typename TA, typename TB>
+void launch_cast(int64_t m, const TA *a, TB *b, hipStream_t st) {
+    if (m > 0) hipLaunchKernelGGL((k_cast<TA, TB>), dim3(cdiv(m, 256)), dim3(256), 0, st, m, a, b);
+    LAUNCHCHK();
+}
+template void launch_cast<double, float>(int64_t, const double *, float *, hipStream_t);
+template void launch_cast<float, double>(int64_t, const float *, double *, hipStream_t);
+template void launch_cast<double, double>(int64_t, const double *, double *, hipStream_t);
+
+void launch_coarse_solve(cbs_system *h, bool transposed, const void *b, void *x, bool fp32) {
+    Coarse &C = h->coarse;
+    const double *inv = transposed ? C.invT.get() : C.inv.get();
+    const size_t shm = sizeof(double) * (size_t)C.max_m;
+    if (fp32)
+        hipLaunchKernelGGL(k_coarse<float>, dim3(h->n_sys), dim3(256), shm, h->stream, inv, C.off.get(), C.m.get(),
+                           C.roff.get(), (const float *)b, (float *)x);
+    else
+        hipLaunchKernelGGL(k_coarse<double>, dim3(h->n_sys), dim3(256), shm, h->stream, inv, C.off.get(), C.m.get(),
+                           C.roff.get(), (const double *)b, (double *)x);
+    LAUNCHCHK();
+}
+
+void launch_block_apply(int n, int32_t N, const double *Dinv, const double *r, double *z, hipStream_t st) {
+    const int64_t m = (int64_t)N * n;
+    if (m <= 0) return;
+    const dim3 g(cdiv(m, 256)), b(256);
+    switch (n) {
+        case 1: hipLaunchKernelGGL(k_block_apply<1>, g, b, 0, st, N, Dinv, r, z); break;
+        case 2: hipLaunchKernelGGL(k_block_apply<2>, g, b, 0, st, N, Dinv, r, z); break;
+        case 3: hipLaunchKernelGGL(k_block_apply<3>, g, b, 0, st, N, Dinv, r, z); break;
+        case 4: hipLaunchKernelGGL(k_block_apply<4>, g, b, 0, st, N, Dinv, r, z); break;
+        case 5: hipLaunchKernelGGL(k_block_apply<5>, g, b, 0, st, N, Dinv, r, z); break;
+    }
+    LAUNCHCHK();
+}

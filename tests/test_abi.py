@@ -1,0 +1,48 @@
+"""CPU checks of the C ABI: the built library loads and exports every
+function include/cbs.h declares, and the binding declares each of them."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cbs.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cbs_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_lifecycle():
+    names = _declared()
+    for fn in ("cbs_create_from_ldu", "cbs_update_values", "cbs_setup", "cbs_solve",
+               "cbs_solve_transpose", "cbs_destroy", "cbs_create_batch_from_ldu", "cbs_gradient"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2403_07882_amd as P
+    L = P.lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+    bound = {name for name, _, _ in P.binding.SIGNATURES}
+    assert set(_declared()) == bound
+
+
+def test_error_strings_without_gpu():
+    import paper_2403_07882_amd as P
+    L = P.lib()
+    assert L.cbs_error_string(-3) == b"CBS_ERR_SINGULAR"
+    assert L.cbs_error_string(1) == b"CBS_NOT_CONVERGED"
+    o = P.default_options()
+    assert o.tol == 1e-8 and o.restart == 30 and o.precond == P.PREC_AMG
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import paper_2403_07882_amd.binding as B
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(ImportError):
+        B.lib()

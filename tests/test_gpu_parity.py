@@ -1,0 +1,362 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Bars: conversion and packing bit-exact; FP64 kernels to a few ulps of the
+oracle's arithmetic; solves to the relative residual 1e-8 (recomputed by the
+oracle's own SpMV on the GPU's x) and a solution error <= 1e-6 relative to
+an oracle solve at 1e-12.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import concat_systems, jacobian_box, jacobian_stretched, pressure_velocity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2403_07882_amd as P  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _ref_solution(A, b):
+    x, st = O.fgmres(A, b, prec=O.PREC_BJACOBI, tol=1e-12, maxit=20000, restart=60)
+    assert st["status"] == O.OK, st
+    return x
+
+
+def _check_solution(A, b, x, xref, tol=1e-8, err=1e-6):
+    rr = O.relres(A, b, x)
+    assert rr <= tol * 1.0001, rr
+    e = np.linalg.norm((x - xref).ravel()) / np.linalg.norm(xref.ravel())
+    assert e <= err, e
+    return rr, e
+
+
+# ------------------------------------------------------------------ conversion
+@pytest.mark.parametrize("case", ["c0_20", "pv_perm", "stretched", "tiny"])
+def test_conversion_bitexact(case):
+    _say("conversion", case)
+    s = {"c0_20": lambda: jacobian_box(20, 20, 20, seed=0),
+         "pv_perm": lambda: pressure_velocity(12, 9, 7, seed=3),
+         "stretched": lambda: jacobian_stretched(9, 8, 30, seed=1),
+         "tiny": lambda: jacobian_box(2, 1, 1, n=3, seed=2)}[case]()
+    A, ds, us, ls = O.ldu_to_bcsr(s["N"], s["n"], s["lower_addr"], s["upper_addr"], s["diag"], s["upper"], s["lower"])
+    with P.System.from_dict(s) as sysm:
+        g = sysm.get_bcsr()
+        assert np.array_equal(_np(g["row_ptr"]), A.row_ptr)
+        assert np.array_equal(_np(g["col"]), A.col)
+        assert np.array_equal(_np(g["vals"]).view(np.uint64), A.vals.view(np.uint64))
+        assert np.array_equal(_np(g["diag_slot"]), ds)
+        assert np.array_equal(_np(g["upper_slot"]), us)
+        assert np.array_equal(_np(g["lower_slot"]), ls)
+
+
+def test_conversion_values_update_bitexact():
+    s = pressure_velocity(8, 6, 5, seed=1)
+    t = pressure_velocity(8, 6, 5, seed=1, nu=0.05)
+    with P.System.from_dict(s) as sysm:
+        sysm.update_values(t["diag"], t["upper"], t["lower"])
+        A = O.from_system(t)
+        assert np.array_equal(_np(sysm.get_bcsr()["vals"]), A.vals)
+
+
+def test_pack_unpack_bitexact():
+    rng = np.random.default_rng(0)
+    soa = rng.standard_normal((4, 1001))
+    aos = P.pack_fields(soa)
+    assert np.array_equal(_np(aos), O.pack(soa))
+    assert np.array_equal(_np(P.unpack_fields(aos)), soa)
+
+
+@pytest.mark.parametrize("la,ua,code", [([0], [5], P.ERR_PATTERN), ([1], [1], P.ERR_PATTERN),
+                                        ([0, 1], [1, 0], P.ERR_PATTERN), ([-1], [2], P.ERR_PATTERN)])
+def test_bad_pattern_codes(la, ua, code):
+    F = len(la)
+    with pytest.raises(P.CbsError) as e:
+        P.System(3, 2, la, ua, np.ones((3, 2, 2)), np.ones((F, 2, 2)), np.ones((F, 2, 2)))
+    assert e.value.code == code
+
+
+def test_nonfinite_and_state_codes():
+    s = jacobian_box(4, 3, 2, seed=0)
+    d = s["diag"].copy(); d[3, 1, 1] = np.nan
+    with pytest.raises(P.CbsError) as e:
+        P.System(s["N"], 5, s["lower_addr"], s["upper_addr"], d, s["upper"], s["lower"])
+    assert e.value.code == P.ERR_NONFINITE
+    with P.System.from_dict(s) as sysm:
+        with pytest.raises(P.CbsError) as e:
+            sysm.solve(s["b"])
+        assert e.value.code == P.ERR_STATE
+        sysm.setup(precond=P.PREC_BJACOBI)
+        bad = s["b"].copy(); bad[0, 0] = np.inf
+        with pytest.raises(P.CbsError) as e:
+            sysm.solve(bad)
+        assert e.value.code == P.ERR_NONFINITE
+        sysm.update_values(s["diag"], s["upper"], s["lower"])
+        with pytest.raises(P.CbsError) as e:
+            sysm.solve(s["b"])
+        assert e.value.code == P.ERR_STATE
+
+
+def test_singular_block_code():
+    s = jacobian_box(3, 3, 2, seed=0)
+    d = s["diag"].copy(); d[7] = 0.0
+    with P.System(s["N"], 5, s["lower_addr"], s["upper_addr"], d, s["upper"], s["lower"]) as sysm:
+        with pytest.raises(P.CbsError) as e:
+            sysm.setup(precond=P.PREC_BJACOBI)
+        assert e.value.code == P.ERR_SINGULAR and "block row 7" in str(e.value)
+
+
+# ------------------------------------------------------------------ SpMV
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_spmv_and_transpose(n):
+    _say("spmv n", n)
+    s = jacobian_box(11, 7, 5, n=n, seed=n) if n != 4 else pressure_velocity(11, 7, 5, seed=2)
+    A = O.from_system(s)
+    x = np.random.default_rng(1).standard_normal((s["N"], n))
+    with P.System.from_dict(s) as sysm:
+        y = _np(sysm.spmv(x))
+        yt = _np(sysm.spmv(x, transpose=True))
+    ref, reft = O.spmv(A, x), O.spmv_t(A, x)
+    scale = np.abs(A.vals).max() * np.abs(x).max() * 8
+    assert np.abs(y - ref).max() <= 1e-14 * scale
+    assert np.abs(yt - reft).max() <= 1e-14 * scale
+
+
+def test_spmv_empty_rows_and_no_faces():
+    rng = np.random.default_rng(3)
+    D = rng.standard_normal((70, 4, 4))
+    with P.System(70, 4, np.zeros(0, np.int32), np.zeros(0, np.int32), D, np.zeros((0, 4, 4)),
+                  np.zeros((0, 4, 4))) as sysm:
+        x = rng.standard_normal((70, 4))
+        assert np.allclose(_np(sysm.spmv(x)), np.einsum("kij,kj->ki", D, x), rtol=1e-14, atol=1e-14)
+
+
+# ------------------------------------------------------------------ solves
+def test_c0_bicgstab_block_jacobi_full_size():
+    """20^3 density-based 5x5 Jacobian, BiCGStab + block Jacobi to 1e-8."""
+    _say("c0 full size")
+    s = jacobian_box(20, 20, 20, seed=0)
+    A = O.from_system(s)
+    xref = _ref_solution(A, s["b"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_BJACOBI, tol=1e-8, max_iter=1000)
+        x, st = sysm.solve(s["b"])
+    assert st["status"] == P.OK, st
+    _check_solution(A, s["b"], _np(x), xref)
+    assert abs(st["rel_res_true"] - O.relres(A, s["b"], _np(x))) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
+@pytest.mark.parametrize("solver", [P.SOLVER_BICGSTAB, P.SOLVER_FGMRES])
+def test_amg_solve_pressure_velocity(precision, solver):
+    _say("amg pv", precision, solver)
+    s = pressure_velocity(16, 16, 16, seed=0)
+    A = O.from_system(s)
+    xref = _ref_solution(A, s["b"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, precision=precision, solver=solver, tol=1e-8)
+        x, st = sysm.solve(s["b"])
+        assert st["status"] == P.OK and st["levels"] > 1, st
+        rr, _ = _check_solution(A, s["b"], _np(x), xref, err=1e-5)
+        # tighter verification solve for the 1e-6 solution-error bar
+        sysm.setup(precond=P.PREC_AMG, precision=precision, solver=solver, tol=1e-11)
+        x2, st2 = sysm.solve(s["b"])
+        _check_solution(A, s["b"], _np(x2), xref, tol=1e-11, err=1e-6)
+
+
+def test_amg_solve_density_stretched():
+    _say("amg stretched")
+    s = jacobian_stretched(14, 14, 40, seed=0)
+    A = O.from_system(s)
+    xref = _ref_solution(A, s["b"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, precision=P.PRECISION_MIXED, solver=P.SOLVER_FGMRES, tol=1e-8)
+        x, st = sysm.solve(s["b"])
+    assert st["status"] == P.OK, st
+    _check_solution(A, s["b"], _np(x), xref, err=1e-5)
+
+
+def test_zero_rhs_and_warm_start():
+    s = jacobian_box(6, 6, 6, seed=1)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup()
+        x, st = sysm.solve(np.zeros_like(s["b"]), x0=np.ones_like(s["b"]))
+        assert st["iterations"] == 0 and float(torch.abs(x).max()) == 0.0
+        x, st = sysm.solve(s["b"])
+        x2, st2 = sysm.solve(s["b"], x0=x)
+        assert st2["iterations"] == 0 and st2["status"] == P.OK
+
+
+def test_iteration_cap_not_converged():
+    s = pressure_velocity(8, 8, 8, seed=0)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_NONE, max_iter=2, tol=1e-14)
+        x, st = sysm.solve(s["b"])
+    assert st["status"] == P.NOT_CONVERGED and st["iterations"] == 2
+    assert abs(st["rel_res_true"] - O.relres(O.from_system(s), s["b"], _np(x))) <= 1e-12
+
+
+def test_solve_is_deterministic():
+    s = pressure_velocity(12, 10, 8, seed=2)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precision=P.PRECISION_MIXED)
+        x1, s1 = sysm.solve(s["b"])
+        x2, s2 = sysm.solve(s["b"])
+    assert s1["iterations"] == s2["iterations"]
+    assert np.array_equal(_np(x1), _np(x2))
+
+
+# ------------------------------------------------------------------ AMG pieces
+def test_rap_and_vcycle_match_oracle_given_gpu_aggregates():
+    _say("rap/vcycle parity")
+    s = pressure_velocity(10, 9, 8, seed=4)
+    A = O.from_system(s)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, coarse_max=8, pre_sweeps=1, post_sweeps=1, omega=0.8)
+        nlev = sysm.info()["levels"]
+        assert nlev >= 3
+        aggs, Al = [], A
+        for l in range(nlev):
+            lv = sysm.get_level(l)
+            assert np.array_equal(_np(lv["row_ptr"]), Al.row_ptr)
+            assert np.array_equal(_np(lv["col"]), Al.col)
+            assert np.array_equal(_np(lv["vals"]), Al.vals)          # same sums in the same order
+            if l + 1 < nlev:
+                agg = _np(lv["agg"])
+                nc = int(agg.max()) + 1
+                assert np.array_equal(np.unique(agg), np.arange(nc))
+                aggs.append(agg)
+                Al = O.rap(Al, agg, nc)
+        amg = O.AMG(A, nu1=1, nu2=1, omega=0.8, aggs=aggs)
+        r = np.random.default_rng(0).standard_normal((A.N, 4))
+        z = _np(sysm.apply_precond(r))
+    zr = amg.apply(r)
+    assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+
+
+def test_aggregation_properties():
+    s = jacobian_box(16, 16, 16, seed=0)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, match_passes=2)
+        lv = sysm.get_level(0)
+        agg = _np(lv["agg"])
+    nc = agg.max() + 1
+    sizes = np.bincount(agg)
+    assert sizes.min() >= 1 and nc < s["N"] / 2.5
+    # every aggregate is connected in the matrix graph (checked on a sample)
+    A = O.from_system(s)
+    rows = np.repeat(np.arange(A.N), np.diff(A.row_ptr))
+    nbr = {}
+    for i, j in zip(rows, A.col):
+        nbr.setdefault(i, set()).add(j)
+    mem = {}
+    for i, I in enumerate(agg):
+        mem.setdefault(I, []).append(i)
+    for I in list(mem)[:500]:
+        ms = set(mem[I]); seen, st_ = set(), [mem[I][0]]
+        while st_:
+            u = st_.pop()
+            if u in seen:
+                continue
+            seen.add(u); st_.extend(v for v in nbr[u] if v in ms)
+        assert seen == ms
+
+
+# ------------------------------------------------------------------ adjoint
+def test_transpose_solve_and_gradient():
+    _say("adjoint")
+    s = pressure_velocity(10, 8, 6, seed=5)
+    A = O.from_system(s)
+    rng = np.random.default_rng(4)
+    c = rng.standard_normal((s["N"], 4))
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, tol=1e-12)
+        x, st = sysm.solve(s["b"])
+        lam, stt = sysm.solve_transpose(c)
+        assert stt["status"] == P.OK
+        gd, gu, gl = sysm.gradient(lam, x)
+    xn, ln = _np(x), _np(lam)
+    assert np.linalg.norm(O.spmv_t(A, ln) - c) <= 1e-11 * np.linalg.norm(c)
+    rd, ru, rl = O.grad(s, ln, xn)
+    assert np.array_equal(_np(gd), rd) and np.array_equal(_np(gu), ru) and np.array_equal(_np(gl), rl)
+
+
+def test_autograd_matches_finite_differences():
+    _say("autograd FD")
+    s = pressure_velocity(5, 4, 4, seed=6)
+    N, n = s["N"], 4
+    dev = "cuda"
+    diag = torch.tensor(s["diag"], device=dev, requires_grad=True)
+    upper = torch.tensor(s["upper"], device=dev, requires_grad=True)
+    lower = torch.tensor(s["lower"], device=dev, requires_grad=True)
+    b = torch.tensor(s["b"], device=dev, requires_grad=True)
+    c = torch.tensor(np.random.default_rng(4).standard_normal((N, n)), device=dev)
+    sysm = P.System.from_dict(s)
+    sysm.setup(precond=P.PREC_AMG, tol=1e-13, max_iter=2000)
+    x = P.coupled_solve(sysm, diag, upper, lower, b)
+    L = (c * x).sum()
+    L.backward()
+
+    def Lval(d, u, l, bb):
+        A = O.ldu_to_bcsr(N, n, s["lower_addr"], s["upper_addr"], d, u, l)[0]
+        return float((c.cpu().numpy() * O.dense_solve(A.dense(), bb.ravel()).reshape(N, n)).sum())
+
+    base = [s["diag"], s["upper"], s["lower"], s["b"]]
+    grads = [_np(diag.grad), _np(upper.grad), _np(lower.grad), _np(b.grad)]
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    for which in range(4):
+        for _ in range(8):
+            idx = tuple(rng.integers(0, d) for d in base[which].shape)
+            p = [a.copy() for a in base]; m = [a.copy() for a in base]
+            p[which][idx] += h; m[which][idx] -= h
+            fd = (Lval(*p) - Lval(*m)) / (2 * h)
+            g = grads[which][idx]
+            assert abs(fd - g) <= 1e-4 * abs(g) + 1e-6 * np.abs(grads[which]).max(), (which, idx, fd, g)
+    sysm.close()
+
+
+# ------------------------------------------------------------------ batching
+def test_batched_solve_matches_solo_solves():
+    _say("batched")
+    shapes = [(5, 4, 3), (9, 8, 7), (3, 3, 3), (12, 10, 6), (4, 4, 1)]
+    systems = [jacobian_box(*sh, seed=10 + i) for i, sh in enumerate(shapes)]
+    cat = concat_systems(systems)
+    for precision in (P.PRECISION_FP64, P.PRECISION_MIXED):
+        with P.System.from_dict(cat) as bs:
+            bs.setup(precond=P.PREC_AMG, precision=precision, tol=1e-8)
+            x, stats = bs.solve(cat["b"])
+        xn = _np(x)
+        assert len(stats) == len(systems)
+        for k, s in enumerate(systems):
+            A = O.from_system(s)
+            xk = xn[cat["cell_off"][k]:cat["cell_off"][k + 1]]
+            assert stats[k]["status"] == P.OK, (k, stats[k])
+            assert O.relres(A, s["b"], xk) <= 1e-8 * 1.0001
+            xref = _ref_solution(A, s["b"])
+            kappa_tol = 1e-8 * 50
+            assert np.linalg.norm(xk - xref) <= kappa_tol * np.linalg.norm(xref)
+
+
+def test_batched_fgmres_and_zero_system():
+    systems = [jacobian_box(6, 5, 4, seed=1), jacobian_box(7, 3, 3, seed=2)]
+    systems[1]["b"] = np.zeros_like(systems[1]["b"])
+    cat = concat_systems(systems)
+    with P.System.from_dict(cat) as bs:
+        bs.setup(precond=P.PREC_AMG, solver=P.SOLVER_FGMRES, tol=1e-9)
+        x, stats = bs.solve(cat["b"])
+    xn = _np(x)
+    assert stats[1]["iterations"] == 0 and np.all(xn[cat["cell_off"][1]:] == 0)
+    assert O.relres(O.from_system(systems[0]), systems[0]["b"], xn[:cat["cell_off"][1]]) <= 1e-9
