@@ -118,6 +118,8 @@ int create_common(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const
 cbs_system::~cbs_system() {
     if (stream) (void)hipStreamSynchronize(stream);
     else (void)hipDeviceSynchronize();
+    invalidate_graphs(this);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
 }
@@ -172,6 +174,7 @@ int cbs_update_values(cbs_handle h, const double *diag, const double *upper, con
         h->t_convert_ms = elapsed_ms(h->ev0, h->ev1);
         h->values_changed = true;
         h->transposed_ready = false;
+        invalidate_graphs(h);
         return CBS_OK;
     });
 }
@@ -201,6 +204,7 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
         ensure_level0(h);
         HIPCHK(hipEventRecord(h->ev0, h->stream));
         h->setup_done = false;
+        invalidate_graphs(h);
         amg_setup(h);
         alloc_krylov(h);
         HIPCHK(hipEventRecord(h->ev1, h->stream));

@@ -150,6 +150,10 @@ struct cbs_system {
     // pinned host mirrors for read-back
     double *h_scal = nullptr;
     int32_t *h_done = nullptr;
+    // captured iteration graphs (index: transposed solve), replayed on `stream`
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t g_iter[2] = {nullptr, nullptr};
+    DArr<double> xw;                             // solution work copy the graphs point at
     // statistics
     double t_convert_ms = 0.0, t_setup_ms = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -194,5 +198,9 @@ void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv);
 
 // Krylov (krylov.hip)
 int krylov_solve(cbs_system *h, const double *b, double *x, cbs_stats *st, bool transposed);
+void invalidate_graphs(cbs_system *h);
+void launch_copy(int64_t m, const double *a, double *b, hipStream_t st);
+template <typename T>
+void launch_fill(int64_t m, T *a, hipStream_t st);
 void precond_apply(cbs_system *h, const double *r, double *z, bool transposed);
 void spmv64(cbs_system *h, const double *x, double *y, bool transposed);

@@ -57,23 +57,51 @@ __global__ __launch_bounds__(kVecThreads) void k_dots(const Item *__restrict__ i
     if (K > 2) { s2 = block_sum(s2, sh); if (threadIdx.x == 0) partial[2 * n_items + blockIdx.x] = s2; }
 }
 
+// Sum of one system's partials, by the whole workgroup: thread t adds items
+// i0+t, i0+t+256, ... in order, then a fixed tree combines the threads, so
+// the result does not depend on timing.  Every thread gets the value.
+constexpr int kFinThreads = 256;
+
 __device__ inline double sum_items(const double *partial, int32_t n_items, int q, int32_t i0, int32_t i1) {
+    __shared__ double sh[kFinThreads / 64];
+    __shared__ double res;
     double t = 0.0;
-    for (int32_t k = i0; k < i1; ++k) t += partial[q * n_items + k];
-    return t;
+    for (int32_t k = i0 + (int32_t)threadIdx.x; k < i1; k += kFinThreads) t += partial[(int64_t)q * n_items + k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+        for (int w = 0; w < kFinThreads / 64; ++w) a += sh[w];
+        res = a;
+    }
+    __syncthreads();
+    const double v = res;
+    __syncthreads();
+    return v;
 }
 
 #define SC(slot) scal[(slot) * nsys + s]
 
 // Per-system scalar updates after a reduction.  flags: bit0 breakdown.
-__global__ void k_fin(int phase, int32_t nsys, const int32_t *__restrict__ item_off, int32_t n_items,
-                      const double *__restrict__ partial, double *scal, int32_t *done, int32_t *flags,
-                      int32_t *iters, double tol2, const int32_t *restart_mask) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsys) return;
+__global__ __launch_bounds__(kFinThreads) void k_fin(int phase, int32_t nsys, const int32_t *__restrict__ item_off,
+                                                      int32_t n_items, const double *__restrict__ partial, double *scal,
+                                                      int32_t *done, int32_t *flags, int32_t *iters, double tol2,
+                                                      const int32_t *restart_mask) {
+    const int s = blockIdx.x;
     const int32_t i0 = item_off[s], i1 = item_off[s + 1];
+    // every phase needs at most two sums; compute them with the whole group
+    const bool skip = (phase == PH_RESTART && !restart_mask[s]) ||
+                      ((phase == PH_ALPHA || phase == PH_OMEGA || phase == PH_END) && (done[s] || (flags[s] & 1)));
+    if (skip) return;
+    const double q0 = sum_items(partial, n_items, 0, i0, i1);
+    const double q1 = (phase == PH_INIT || phase == PH_OMEGA || phase == PH_END) ? sum_items(partial, n_items, 1, i0, i1)
+                                                                                 : 0.0;
+    if (threadIdx.x != 0) return;
     if (phase == PH_INIT) {
-        const double rr = sum_items(partial, n_items, 0, i0, i1), bb = sum_items(partial, n_items, 1, i0, i1);
+        const double rr = q0, bb = q1;
         SC(S_RR) = rr; SC(S_BB) = bb; SC(S_RES0) = bb > 0.0 ? sqrt(rr / bb) : 0.0;
         SC(S_RHO) = rr; SC(S_RHO0) = 1.0; SC(S_ALPHA) = 1.0; SC(S_OMEGA) = 1.0;
         done[s] = (bb == 0.0 || rr <= tol2 * bb) ? 1 : 0;
@@ -82,20 +110,18 @@ __global__ void k_fin(int phase, int32_t nsys, const int32_t *__restrict__ item_
         return;
     }
     if (phase == PH_TRUE) {                          // true residual of every system
-        SC(S_RR) = sum_items(partial, n_items, 0, i0, i1);
+        SC(S_RR) = q0;
         return;
     }
     if (phase == PH_RESTART) {                       // rhat = r; p = v = 0 done by the caller
-        if (!restart_mask[s]) return;
-        const double rr = sum_items(partial, n_items, 0, i0, i1);
+        const double rr = q0;
         SC(S_RR) = rr; SC(S_RHO) = rr; SC(S_RHO0) = 1.0; SC(S_ALPHA) = 1.0; SC(S_OMEGA) = 1.0;
         done[s] = (SC(S_BB) == 0.0 || rr <= tol2 * SC(S_BB)) ? 1 : 0;
         flags[s] = 0;
         return;
     }
-    if (done[s] || (flags[s] & 1)) return;
     if (phase == PH_ALPHA) {
-        const double rv = sum_items(partial, n_items, 0, i0, i1);
+        const double rv = q0;
         SC(S_RV) = rv;
         const double rho = SC(S_RHO);
         if (rv == 0.0 || !isfinite(rv) || fabs(rv) < 1e-300 * fmax(SC(S_RR), 1e-300)) {
@@ -106,11 +132,11 @@ __global__ void k_fin(int phase, int32_t nsys, const int32_t *__restrict__ item_
         }
         iters[s] += 1;
     } else if (phase == PH_OMEGA) {
-        const double ts = sum_items(partial, n_items, 0, i0, i1), tt = sum_items(partial, n_items, 1, i0, i1);
+        const double ts = q0, tt = q1;
         SC(S_TS) = ts; SC(S_TT) = tt;
         SC(S_OMEGA) = tt > 0.0 ? ts / tt : 0.0;
     } else if (phase == PH_END) {
-        const double rr = sum_items(partial, n_items, 0, i0, i1), rhn = sum_items(partial, n_items, 1, i0, i1);
+        const double rr = q0, rhn = q1;
         SC(S_RR) = rr;
         SC(S_RHO0) = SC(S_RHO);
         SC(S_RHO) = rhn;
@@ -209,16 +235,20 @@ __global__ __launch_bounds__(kVecThreads) void k_mdot(const Item *__restrict__ i
 }
 
 // h_i (per system) = sum of partials; accumulate into H(:, j); store in coef
-__global__ void k_mdot_fin(int32_t nsys, int j, int m, const int32_t *__restrict__ item_off, int32_t n_items,
-                           const double *__restrict__ partial, const int32_t *__restrict__ done, double *H,
-                           double *coef, int accumulate) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsys || done[s]) return;
+__global__ __launch_bounds__(kFinThreads) void k_mdot_fin(int32_t nsys, int j, int m,
+                                                           const int32_t *__restrict__ item_off, int32_t n_items,
+                                                           const double *__restrict__ partial,
+                                                           const int32_t *__restrict__ done, double *H, double *coef,
+                                                           int accumulate) {
+    const int s = blockIdx.x;
+    if (done[s]) return;
     for (int i = 0; i <= j; ++i) {
         const double hv = sum_items(partial, n_items, i, item_off[s], item_off[s + 1]);
-        double *Hs = H + (int64_t)s * (m + 1) * m;
-        Hs[i * m + j] = accumulate ? Hs[i * m + j] + hv : hv;
-        coef[(int64_t)s * (m + 1) + i] = hv;
+        if (threadIdx.x == 0) {
+            double *Hs = H + (int64_t)s * (m + 1) * m;
+            Hs[i * m + j] = accumulate ? Hs[i * m + j] + hv : hv;
+            coef[(int64_t)s * (m + 1) + i] = hv;
+        }
     }
 }
 
@@ -248,15 +278,17 @@ __global__ __launch_bounds__(kVecThreads) void k_scale(const Item *__restrict__ 
 }
 
 // Restart start: beta = ||r||, g = (beta, 0, ...), converged check.
-__global__ void k_gm_start(int32_t nsys, int m, const int32_t *__restrict__ item_off, int32_t n_items,
-                           const double *__restrict__ partial, double *scal, double *g, int32_t *done,
-                           int32_t *jlen, double tol2, int first) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsys) return;
+__global__ __launch_bounds__(kFinThreads) void k_gm_start(int32_t nsys, int m, const int32_t *__restrict__ item_off,
+                                                           int32_t n_items, const double *__restrict__ partial,
+                                                           double *scal, double *g, int32_t *done, int32_t *jlen,
+                                                           double tol2, int first) {
+    const int s = blockIdx.x;
     const double rr = sum_items(partial, n_items, 0, item_off[s], item_off[s + 1]);
+    const double bbs = first ? sum_items(partial, n_items, 1, item_off[s], item_off[s + 1]) : 0.0;
+    if (threadIdx.x != 0) return;
     SC(S_RR) = rr;
     if (first) {
-        const double bb = sum_items(partial, n_items, 1, item_off[s], item_off[s + 1]);
+        const double bb = bbs;
         SC(S_BB) = bb;
         SC(S_RES0) = bb > 0.0 ? sqrt(rr / bb) : 0.0;
     }
@@ -271,12 +303,15 @@ __global__ void k_gm_start(int32_t nsys, int m, const int32_t *__restrict__ item
 
 // After the orthogonalisation of column j: H(j+1,j) = ||w||, apply the
 // previous rotations, make rotation j, update g, and test |g(j+1)|.
-__global__ void k_gm_givens(int32_t nsys, int j, int m, const int32_t *__restrict__ item_off, int32_t n_items,
-                            const double *__restrict__ partial, double *scal, double *H, double *cs, double *sn,
-                            double *g, int32_t *done, int32_t *jlen, int32_t *iters, double tol2, double *hn_out) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsys || done[s]) return;
+__global__ __launch_bounds__(kFinThreads) void k_gm_givens(int32_t nsys, int j, int m,
+                                                            const int32_t *__restrict__ item_off, int32_t n_items,
+                                                            const double *__restrict__ partial, double *scal, double *H,
+                                                            double *cs, double *sn, double *g, int32_t *done,
+                                                            int32_t *jlen, int32_t *iters, double tol2, double *hn_out) {
+    const int s = blockIdx.x;
+    if (done[s]) return;
     const double hn = sqrt(sum_items(partial, n_items, 0, item_off[s], item_off[s + 1]));
+    if (threadIdx.x != 0) return;
     double *Hs = H + (int64_t)s * (m + 1) * m;
     double *c = cs + (int64_t)s * (m + 1), *sv = sn + (int64_t)s * (m + 1), *gs = g + (int64_t)s * (m + 1);
     Hs[(j + 1) * m + j] = hn;
@@ -346,7 +381,7 @@ void dots(cbs_system *h, int K, const double *a0, const double *b0, const double
 }
 
 void fin(cbs_system *h, int phase, double tol2, const int32_t *restart_mask = nullptr) {
-    hipLaunchKernelGGL(k_fin, dim3(cdiv(h->n_sys, 64)), dim3(64), 0, h->stream, phase, h->n_sys, h->item_off.get(),
+    hipLaunchKernelGGL(k_fin, dim3(h->n_sys), dim3(kFinThreads), 0, h->stream, phase, h->n_sys, h->item_off.get(),
                        h->n_items, h->partial.get(), h->scal.get(), h->done.get(), h->flags.get(),
                        h->done.get() + 2 * h->n_sys, tol2, restart_mask);
     LAUNCHCHK();
@@ -391,7 +426,7 @@ void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
             std::swap(cur, oth);
         }
     } else {
-        HIPCHK(hipMemsetAsync(cur, 0, sizeof(T) * (size_t)L.N * n, st));
+        launch_fill<T>((int64_t)L.N * n, cur, st);
     }
     launch_rows<T, T>(1, n, L.N, L.rp, L.col, val, cur, b, r, Dinv, o.omega, st);
     Level &C = h->lev[l + 1];
@@ -423,7 +458,7 @@ void precond_apply(cbs_system *h, const double *r, double *z, bool tr) {
     hipStream_t st = h->stream;
     switch (h->opt.precond) {
         case CBS_PREC_NONE:
-            HIPCHK(hipMemcpyAsync(z, r, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+            launch_copy(m, r, z, st);
             return;
         case CBS_PREC_BJACOBI:
             launch_block_apply(n, h->N, tr ? h->lev[0].DinvT.get() : h->lev[0].Dinv.get(), r, z, st);
@@ -473,6 +508,60 @@ void true_residual(cbs_system *h, const double *b, const double *x, bool tr) {
     fin(h, PH_TRUE, 0.0);
 }
 
+// One right-preconditioned BiCGStab iteration for every unfinished system.
+// Only kernel launches on h->stream (no memset/memcpy, no host sync), so it
+// can be captured once and replayed as a graph.
+void bicg_iteration(cbs_system *h, double *x, bool tr) {
+    hipStream_t st = h->stream;
+    const double tol2 = h->opt.tol * h->opt.tol;
+    const int nsys = h->n_sys;
+    double *r = h->r.get(), *rh = h->rh.get(), *p = h->p.get(), *v = h->v.get();
+    double *ph = h->ph.get(), *sv = h->s.get(), *sh = h->sh.get(), *t = h->t.get();
+    const Item *items = h->items.get();
+    const dim3 G(h->n_items), B(kVecThreads);
+    hipLaunchKernelGGL(k_p_update, G, B, 0, st, items, nsys, h->done.get(), h->scal.get(), h->flags.get(), r, p, v);
+    precond_apply(h, p, ph, tr);
+    spmv64(h, ph, v, tr);
+    dots(h, 1, rh, v);
+    fin(h, PH_ALPHA, tol2);
+    hipLaunchKernelGGL(k_s_update, G, B, 0, st, items, nsys, h->done.get(), h->scal.get(), h->flags.get(), r, v, sv);
+    precond_apply(h, sv, sh, tr);
+    spmv64(h, sh, t, tr);
+    dots(h, 2, t, sv, t, t);
+    fin(h, PH_OMEGA, tol2);
+    hipLaunchKernelGGL(k_xr_update, G, B, 0, st, items, h->n_items, nsys, h->done.get(), h->scal.get(),
+                       h->flags.get(), x, ph, sh, r, sv, t, rh, h->partial.get());
+    fin(h, PH_END, tol2);
+    LAUNCHCHK();
+}
+
+// Replay the captured iteration (capture on first use).
+void bicg_iteration_graph(cbs_system *h, double *xw, bool tr) {
+    hipGraphExec_t &ex = h->g_iter[tr ? 1 : 0];
+    if (!ex) {
+        if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        hipStream_t saved = h->stream;
+        h->stream = h->cap_stream;
+        hipGraph_t g = nullptr;
+        try {
+            HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+            bicg_iteration(h, xw, tr);
+            HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(h->cap_stream, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            h->stream = saved;
+            throw;
+        }
+        h->stream = saved;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) { ex = nullptr; cbs_throw(CBS_ERR_HIP, "hipGraphInstantiate failed"); }
+    }
+    HIPCHK(hipGraphLaunch(ex, h->stream));
+}
+
 int bicgstab(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> &status) {
     hipStream_t st = h->stream;
     const cbs_options &o = h->opt;
@@ -483,6 +572,7 @@ int bicgstab(cbs_system *h, const double *b, double *x, bool tr, std::vector<int
     const Item *items = h->items.get();
     const dim3 G(h->n_items), B(kVecThreads);
     int32_t *rmask = h->flags.get() + 2 * nsys;     // restart mask scratch
+    (void)sv; (void)sh; (void)t; (void)ph;
 
     residual64(h, b, x, r, tr);
     dots(h, 2, r, r, b, b, nullptr, nullptr, done_none(h));
@@ -556,21 +646,8 @@ int bicgstab(cbs_system *h, const double *b, double *x, bool tr, std::vector<int
             }
         }
         if (it >= o.max_iter) break;
-        // one BiCGStab iteration (right preconditioning)
-        hipLaunchKernelGGL(k_p_update, G, B, 0, st, items, nsys, h->done.get(), h->scal.get(), h->flags.get(), r, p, v);
-        precond_apply(h, p, ph, tr);
-        spmv64(h, ph, v, tr);
-        dots(h, 1, rh, v);
-        fin(h, PH_ALPHA, tol2);
-        hipLaunchKernelGGL(k_s_update, G, B, 0, st, items, nsys, h->done.get(), h->scal.get(), h->flags.get(), r, v, sv);
-        precond_apply(h, sv, sh, tr);
-        spmv64(h, sh, t, tr);
-        dots(h, 2, t, sv, t, t);
-        fin(h, PH_OMEGA, tol2);
-        hipLaunchKernelGGL(k_xr_update, G, B, 0, st, items, h->n_items, nsys, h->done.get(), h->scal.get(),
-                           h->flags.get(), x, ph, sh, r, sv, t, rh, h->partial.get());
-        fin(h, PH_END, tol2);
-        LAUNCHCHK();
+        if (x == h->xw.get()) bicg_iteration_graph(h, x, tr);
+        else bicg_iteration(h, x, tr);
         ++it;
     }
     return it;
@@ -586,7 +663,7 @@ int fgmres(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> 
     double *r = h->r.get(), *w = h->w.get();
     double *V = h->V.get(), *Z = h->Z.get();
     const Item *items = h->items.get();
-    const dim3 G(h->n_items), B(kVecThreads), GS(cdiv(nsys, 64)), BS(64);
+    const dim3 G(h->n_items), B(kVecThreads), GS(nsys), BS(kFinThreads), GS1(cdiv(nsys, 64)), BS1(64);
     double *coef = h->yv.get() + (int64_t)nsys * (m + 1);       // (m+1) per system
     double *hn = coef + (int64_t)nsys * (m + 1);                // 1 per system (stride m+1)
     status.assign(nsys, CBS_NOT_CONVERGED);
@@ -636,7 +713,7 @@ int fgmres(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> 
             }
         }
         const int jmax = std::min(j, m);
-        hipLaunchKernelGGL(k_gm_solve, GS, BS, 0, st, nsys, m, h->H.get(), h->gvec.get(), h->flags.get() + 3 * nsys,
+        hipLaunchKernelGGL(k_gm_solve, GS1, BS1, 0, st, nsys, m, h->H.get(), h->gvec.get(), h->flags.get() + 3 * nsys,
                            h->yv.get());
         hipLaunchKernelGGL(k_gm_update, G, B, 0, st, items, m, jmax, ld, Z, h->yv.get(), h->flags.get() + 3 * nsys, x);
         LAUNCHCHK();
@@ -650,7 +727,23 @@ int fgmres(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> 
 
 }  // namespace
 
+void invalidate_graphs(cbs_system *h) {
+    for (auto &g : h->g_iter)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
 void alloc_krylov(cbs_system *h) {
+    // any reallocation below would leave the captured graphs pointing at freed buffers
+    const void *before[4] = {h->r.get(), h->partial.get(), h->V.get(), h->yv.get()};
+    struct Check {
+        cbs_system *h;
+        const void *const *b;
+        ~Check() {
+            const void *after[4] = {h->r.get(), h->partial.get(), h->V.get(), h->yv.get()};
+            for (int i = 0; i < 4; ++i)
+                if (after[i] != b[i]) { invalidate_graphs(h); break; }
+        }
+    } check{h, before};
     const int64_t m = (int64_t)h->N * h->n;
     const int nsys = h->n_sys;
     for (DArr<double> *a : {&h->r, &h->rh, &h->p, &h->v, &h->ph, &h->s, &h->sh, &h->t, &h->w}) a->ensure(m);
@@ -679,8 +772,16 @@ int krylov_solve(cbs_system *h, const double *b, double *x, cbs_stats *stv, bool
     HIPCHK(hipEventRecord(h->ev0, st));
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<int> status;
-    if (h->opt.solver == CBS_SOLVER_FGMRES) fgmres(h, b, x, tr, status);
-    else bicgstab(h, b, x, tr, status);
+    if (h->opt.solver == CBS_SOLVER_FGMRES) {
+        fgmres(h, b, x, tr, status);
+    } else {
+        // the captured iteration points at the work copy xw
+        const int64_t m = (int64_t)h->N * h->n;
+        h->xw.ensure(m);
+        launch_copy(m, x, h->xw.get(), st);
+        bicgstab(h, b, h->xw.get(), tr, status);
+        launch_copy(m, h->xw.get(), x, st);
+    }
     HIPCHK(hipEventRecord(h->ev1, st));
     // statistics: true residual per system (BiCGStab's last step may not have computed it)
     std::vector<double> rr_rec(nsys), res0(nsys), bbv(nsys);

@@ -17,6 +17,45 @@ namespace {
 template <typename T> struct Acc { using type = double; };
 template <> struct Acc<float> { using type = float; };
 
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Row r of one block: n contiguous values, streamed once per SpMV, so they
+// are loaded non-temporally (keeps x resident in the caches).  16-byte
+// vector loads where the alignment allows it (n = 4).
+template <int n, typename T>
+__device__ inline void load_block_row(const T *__restrict__ p, T (&v)[n]) {
+#pragma unroll
+    for (int c = 0; c < n; ++c) v[c] = __builtin_nontemporal_load(p + c);
+}
+template <>
+__device__ inline void load_block_row<4, double>(const double *__restrict__ p, double (&v)[4]) {
+    const dbl2 a = __builtin_nontemporal_load(reinterpret_cast<const dbl2 *>(p));
+    const dbl2 b = __builtin_nontemporal_load(reinterpret_cast<const dbl2 *>(p) + 1);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+template <>
+__device__ inline void load_block_row<4, float>(const float *__restrict__ p, float (&v)[4]) {
+    const flt4 a = __builtin_nontemporal_load(reinterpret_cast<const flt4 *>(p));
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
+template <int n, typename T>
+__device__ inline void load_x(const T *__restrict__ p, T (&v)[n]) {
+#pragma unroll
+    for (int c = 0; c < n; ++c) v[c] = p[c];
+}
+template <>
+__device__ inline void load_x<4, double>(const double *__restrict__ p, double (&v)[4]) {
+    const dbl2 a = *reinterpret_cast<const dbl2 *>(p), b = *(reinterpret_cast<const dbl2 *>(p) + 1);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+template <>
+__device__ inline void load_x<4, float>(const float *__restrict__ p, float (&v)[4]) {
+    const flt4 a = *reinterpret_cast<const flt4 *>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
 // mode 0: y = A x; 1: y = b - A x; 2: y = x + w Dinv (b - A x); 3: y = w Dinv b
 template <int n, typename TV, typename TX, int MODE>
 __global__ __launch_bounds__(64 * n) void k_rows(int32_t N, const int32_t *__restrict__ rp,
@@ -31,12 +70,30 @@ __global__ __launch_bounds__(64 * n) void k_rows(int32_t N, const int32_t *__res
     A acc = 0;
     if (MODE != 3 && i < N) {
         const int32_t kb = rp[i], ke = rp[i + 1];
-        for (int32_t k = kb; k < ke; ++k) {
-            const int32_t j = col[k];
-            const TV *B = val + (int64_t)k * (n * n) + r * n;
-            const TX *xj = x + (int64_t)j * n;
+        int32_t k = kb;
+        // two blocks per step: both blocks' loads are in flight together;
+        // the sums still run block after block in column order
+        for (; k + 1 < ke; k += 2) {
+            const int32_t j0 = col[k], j1 = col[k + 1];
+            TV b0[n], b1[n];
+            TX x0[n], x1[n];
+            load_block_row<n, TV>(val + (int64_t)k * (n * n) + r * n, b0);
+            load_block_row<n, TV>(val + (int64_t)(k + 1) * (n * n) + r * n, b1);
+            load_x<n, TX>(x + (int64_t)j0 * n, x0);
+            load_x<n, TX>(x + (int64_t)j1 * n, x1);
 #pragma unroll
-            for (int c = 0; c < n; ++c) acc += (A)B[c] * (A)xj[c];
+            for (int c = 0; c < n; ++c) acc += (A)b0[c] * (A)x0[c];
+#pragma unroll
+            for (int c = 0; c < n; ++c) acc += (A)b1[c] * (A)x1[c];
+        }
+        if (k < ke) {
+            const int32_t j0 = col[k];
+            TV b0[n];
+            TX x0[n];
+            load_block_row<n, TV>(val + (int64_t)k * (n * n) + r * n, b0);
+            load_x<n, TX>(x + (int64_t)j0 * n, x0);
+#pragma unroll
+            for (int c = 0; c < n; ++c) acc += (A)b0[c] * (A)x0[c];
         }
     }
     const int64_t o = (int64_t)i * n + r;
@@ -175,6 +232,27 @@ void launch_prolong(int n, int32_t N, const int32_t *agg, const TX *e, TX *x, hi
 }
 template void launch_prolong<double>(int, int32_t, const int32_t *, const double *, double *, hipStream_t);
 template void launch_prolong<float>(int, int32_t, const int32_t *, const float *, float *, hipStream_t);
+
+namespace {
+template <typename T>
+__global__ void k_fill0(int64_t m, T *a) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < m) a[g] = (T)0;
+}
+}  // namespace
+
+void launch_copy(int64_t m, const double *a, double *b, hipStream_t st) {
+    if (m > 0) hipLaunchKernelGGL((k_cast<double, double>), dim3(cdiv(m, 256)), dim3(256), 0, st, m, a, b);
+    LAUNCHCHK();
+}
+
+template <typename T>
+void launch_fill(int64_t m, T *a, hipStream_t st) {
+    if (m > 0) hipLaunchKernelGGL(k_fill0<T>, dim3(cdiv(m, 256)), dim3(256), 0, st, m, a);
+    LAUNCHCHK();
+}
+template void launch_fill<double>(int64_t, double *, hipStream_t);
+template void launch_fill<float>(int64_t, float *, hipStream_t);
 
 template <typename TA, typename TB>
 void launch_cast(int64_t m, const TA *a, TB *b, hipStream_t st) {
