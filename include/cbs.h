@@ -82,6 +82,12 @@ typedef struct cbs_options {
                                 the aggregates, redo only the numeric part [0] */
     int32_t check_every;     /* read the convergence flag back every k
                                 iterations (device-side early exit)  [1] */
+    int32_t renumber;        /* AMG only: renumber rows internally so that
+                                every aggregate (at every level) is a
+                                contiguous row range, which keeps vector
+                                gathers cache-local on irregularly numbered
+                                meshes; inputs and outputs keep the caller's
+                                numbering                            [1] */
 } cbs_options;
 
 /* Per-solve statistics (Algorithm amgxFoam: iterations and residuals). */
@@ -181,11 +187,15 @@ int cbs_get_bcsr(cbs_handle h, int32_t *row_ptr, int32_t *col, double *vals,
                  int32_t *diag_slot, int32_t *upper_slot, int32_t *lower_slot);
 
 /* Level l of the AMG hierarchy (after cbs_setup): n_rows, nnzb (host) and,
- * into caller device arrays when non-NULL, its block CSR (FP64 values), the
- * aggregate map agg[n_rows] to level l+1 (coarsest level: not written) and
- * the DILU colour of each row (colour[n_rows], DILU smoother only). */
+ * into caller device arrays when non-NULL, its block CSR (FP64 values) in
+ * the internal row numbering, the aggregate map agg[n_rows] to level l+1
+ * (coarsest level: not written), the DILU colour of each row (colour[n_rows],
+ * DILU smoother only) and order[n_rows]: the row of the previous numbering
+ * that internal row i' holds (level 0: the caller's cell index; identity
+ * when renumbering is off). */
 int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows /* host */, int64_t *nnzb /* host */,
-                  int32_t *row_ptr, int32_t *col, double *vals, int32_t *agg, int32_t *colour);
+                  int32_t *row_ptr, int32_t *col, double *vals, int32_t *agg, int32_t *colour,
+                  int32_t *order);
 
 /* Free every device buffer of the handle (Algorithm amgxFoam, final step).
  * NULL is allowed. */

@@ -33,6 +33,7 @@ class Options(C.Structure):
         ("omega", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
         ("precision", C.c_int32), ("coarse_max", C.c_int32), ("match_passes", C.c_int32),
         ("max_levels", C.c_int32), ("reuse_aggregates", C.c_int32), ("check_every", C.c_int32),
+        ("renumber", C.c_int32),
     ]
 
 
@@ -68,7 +69,7 @@ SIGNATURES = [
     ("cbs_get_info", C.c_int, [_VP, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I64),
                                C.POINTER(_I32), C.POINTER(_I32)]),
     ("cbs_get_bcsr", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
-    ("cbs_get_level", C.c_int, [_VP, _I32, C.POINTER(_I32), C.POINTER(_I64), _VP, _VP, _VP, _VP, _VP]),
+    ("cbs_get_level", C.c_int, [_VP, _I32, C.POINTER(_I32), C.POINTER(_I64), _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cbs_destroy", C.c_int, [_VP]),
     ("cbs_error_string", C.c_char_p, [C.c_int]),
     ("cbs_last_error", C.c_char_p, []),
@@ -300,7 +301,7 @@ class System:
     def get_level(self, level):
         torch = _torch()
         nr, nz = C.c_int32(), C.c_int64()
-        _check(lib().cbs_get_level(self.h, level, C.byref(nr), C.byref(nz), None, None, None, None, None),
+        _check(lib().cbs_get_level(self.h, level, C.byref(nr), C.byref(nz), None, None, None, None, None, None),
                "cbs_get_level")
         N, nnzb, n = nr.value, nz.value, self.n
         dev = "cuda"
@@ -309,10 +310,11 @@ class System:
         vals = torch.empty((max(nnzb, 1), n, n), dtype=torch.float64, device=dev)
         agg = torch.full((N,), -1, dtype=torch.int32, device=dev)
         colour = torch.full((N,), -1, dtype=torch.int32, device=dev)
+        order = torch.empty((N,), dtype=torch.int32, device=dev)
         _check(lib().cbs_get_level(self.h, level, C.byref(nr), C.byref(nz), _ptr(rp), _ptr(col), _ptr(vals),
-                                   _ptr(agg), _ptr(colour)), "cbs_get_level")
+                                   _ptr(agg), _ptr(colour), _ptr(order)), "cbs_get_level")
         return {"N": N, "nnzb": nnzb, "row_ptr": rp, "col": col[:nnzb], "vals": vals[:nnzb],
-                "agg": agg, "colour": colour}
+                "agg": agg, "colour": colour, "order": order}
 
 
 # ---------------------------------------------------------------- autograd

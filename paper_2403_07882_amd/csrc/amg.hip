@@ -411,6 +411,83 @@ __global__ __launch_bounds__(256) void k_coarse_inverse(const int32_t *rp, const
     }
 }
 
+// ------------------------------------------------------------------ renumbering
+// Positions come top-down from the aggregation tree: the rows of coarse row
+// I' (new numbering) take the contiguous range start[I'] .. start[I'+1),
+// in their previous relative order.  Rows that share an aggregate at any
+// level therefore sit next to each other, so the x gathers of the block
+// kernels stay within a few cache lines.
+__global__ void k_pos_counts(int32_t nc, const int32_t *aptr, const int32_t *pos_c, int32_t *cnt) {
+    const int32_t I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < nc) cnt[pos_c[I]] = aptr[I + 1] - aptr[I];
+}
+
+__global__ void k_pos_assign(int32_t nc, const int32_t *aptr, const int32_t *amem, const int32_t *pos_c,
+                             const int32_t *start, int32_t *pos_f) {
+    const int32_t I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    const int32_t s0 = start[pos_c[I]];
+    for (int32_t q = aptr[I]; q < aptr[I + 1]; ++q) pos_f[amem[q]] = s0 + (q - aptr[I]);
+}
+
+__global__ void k_invert(int32_t N, const int32_t *pos, int32_t *ip) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) ip[pos[i]] = i;
+}
+
+__global__ void k_perm_len(int32_t N, const int32_t *ip, const int32_t *rp, int32_t *len) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) len[i] = rp[ip[i] + 1] - rp[ip[i]];
+}
+
+// new row i' = old row ip[i'], columns renamed by pos and sorted; sk = old slot
+__global__ void k_perm_rows(int32_t N, const int32_t *ip, const int32_t *pos, const int32_t *rp, const int32_t *col,
+                            const int32_t *rpn, int32_t *coln, int32_t *sk) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t o = ip[i], b = rpn[i], len = rp[o + 1] - rp[o];
+    for (int32_t e = 0; e < len; ++e) {
+        const int32_t c = pos[col[rp[o] + e]], k = rp[o] + e;
+        int32_t q = b + e - 1;
+        while (q >= b && coln[q] > c) { coln[q + 1] = coln[q]; sk[q + 1] = sk[q]; --q; }
+        coln[q + 1] = c;
+        sk[q + 1] = k;
+    }
+}
+
+template <int n>
+__global__ void k_gather_blocks(int64_t nb, const int32_t *__restrict__ sk, const double *__restrict__ in,
+                                double *__restrict__ out) {
+    constexpr int nn = n * n;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nb * nn) return;
+    const int64_t k = g / nn;
+    out[g] = in[(int64_t)sk[k] * nn + (g - k * nn)];
+}
+
+// out[i'] = map[ip[i']], renamed through pos_c when given
+__global__ void k_perm_map(int32_t N, const int32_t *ip, const int32_t *map, const int32_t *pos_c, int32_t *out) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t v = map[ip[i]];
+    out[i] = pos_c ? pos_c[v] : v;
+}
+
+__global__ void k_iota(int32_t N, int32_t *a) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) a[i] = i;
+}
+
+__global__ void k_perm_vec(int32_t N, int n, const int32_t *__restrict__ ip, const double *__restrict__ in,
+                           double *__restrict__ out, int to_internal) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)N * n) return;
+    const int64_t i = g / n;
+    const int q = (int)(g - i * n);
+    if (to_internal) out[g] = in[(int64_t)ip[i] * n + q];
+    else out[(int64_t)ip[i] * n + q] = in[g];
+}
+
 }  // namespace
 
 // ====================================================================== host
@@ -450,6 +527,11 @@ void rap_n(int pass, int32_t nc, const int32_t *aptr, const int32_t *amem, const
         hipLaunchKernelGGL((k_rap<n, 0>), g, b, 0, st, nc, aptr, amem, rp, col, val, agg, cnt, rpc, colc, valc, flag);
     else
         hipLaunchKernelGGL((k_rap<n, 1>), g, b, 0, st, nc, aptr, amem, rp, col, val, agg, cnt, rpc, colc, valc, flag);
+}
+template <int n>
+void gather_blocks_n(int64_t nb, const int32_t *sk, const double *in, double *out, hipStream_t st) {
+    const int64_t tot = nb * n * n;
+    if (tot > 0) hipLaunchKernelGGL(k_gather_blocks<n>, dim3(cdiv(tot, 256)), dim3(256), 0, st, nb, sk, in, out);
 }
 template <int n>
 void coarse_inverse_n(int32_t n_sys, const int32_t *rp, const int32_t *col, const double *val, const int64_t *roffb,
@@ -574,6 +656,20 @@ void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen) {
     L.nc = nc;
 }
 
+// Sliced-ELL copy of a level for the solve phase (pattern kept on reuse).
+void level_sell(cbs_system *h, Level &L, bool mixed, bool reuse) {
+    hipStream_t st = h->stream;
+    const int n = h->n;
+    if (!reuse || L.sell.N != L.N || !L.sell.soff.get()) sell_build(L.N, L.rp, L.col, L.sell, st);
+    const size_t tot = (size_t)L.sell.nent * n * n;
+    L.sell.v64.ensure(tot > 0 ? tot : 1);
+    sell_fill(n, L.sell, L.v64, L.sell.v64.get(), st);
+    if (mixed) {
+        L.sell.v32.ensure(tot > 0 ? tot : 1);
+        launch_cast<double, float>((int64_t)tot, L.sell.v64.get(), L.sell.v32.get(), st);
+    }
+}
+
 std::vector<int64_t> level_sys_off(cbs_system *h, Level &L) {
     std::vector<int64_t> off(h->n_sys + 1, 0);
     if (h->n_sys == 1) {
@@ -617,22 +713,31 @@ void amg_setup(cbs_system *h) {
     const bool reuse = o.reuse_aggregates && h->setup_done && amg && h->lev.size() > 1 && h->lev[0].agg.get() != nullptr;
     h->transposed_ready = false;
 
-    if (!reuse) h->lev.clear();
+    if (!reuse) {
+        h->lev.clear();
+        h->renumbered = false;
+        h->perm_sk.release();
+    }
     if (h->lev.empty()) h->lev.emplace_back();
     Level &L0 = h->lev[0];
-    L0.N = h->N; L0.nnzb = h->nnzb;
-    L0.rp = h->rp.get(); L0.col = h->col.get(); L0.mirror = h->mirror.get(); L0.dslot = h->dslot.get();
-    L0.v64 = h->vals.get();
-    if (!L0.row_sys.get()) build_row_sys(h, L0);
+    if (!h->renumbered) {
+        L0.N = h->N; L0.nnzb = h->nnzb;
+        L0.rp = h->rp.get(); L0.col = h->col.get(); L0.mirror = h->mirror.get(); L0.dslot = h->dslot.get();
+        L0.v64 = h->vals.get();
+        if (!L0.row_sys.get()) build_row_sys(h, L0);
+    } else {
+        refresh_level0_values(h);
+    }
     L0.sys_off = h->cell_off;
 
-    // level 0 block inverses (block-Jacobi preconditioner or smoother)
-    if (o.precond != CBS_PREC_NONE) {
-        L0.Dinv.ensure((size_t)h->N * n * n);
-        blockinv_level(h, 0, L0.v64, L0.Dinv.get());
-    }
     if (!amg) {
+        // block-Jacobi preconditioner: level-0 block inverses only
+        if (o.precond != CBS_PREC_NONE) {
+            L0.Dinv.ensure((size_t)h->N * n * n);
+            blockinv_level(h, 0, L0.v64, L0.Dinv.get());
+        }
         h->lev.resize(1);
+        level_sell(h, L0, false, false);
         h->op_complexity = 1.0;
         return;
     }
@@ -700,21 +805,18 @@ void amg_setup(cbs_system *h) {
         break;
     }
     const int nlev = (int)h->lev.size();
+    if (!reuse && o.renumber && nlev > 1) renumber_hierarchy(h);
 
     // smoothers (FP64 inverses), FP32 copies, vectors
     int64_t nz_sum = 0;
     for (int q = 0; q < nlev; ++q) {
         Level &L = h->lev[q];
         nz_sum += L.nnzb;
-        if (q > 0 && q + 1 < nlev) {
+        if (q + 1 < nlev) {
             L.Dinv.ensure((size_t)L.N * n * n);
             blockinv_level(h, q, L.v64, L.Dinv.get());
         }
-        if (mixed) {
-            L.o_v32.ensure((size_t)L.nnzb * n * n);
-            L.v32 = L.o_v32.get();
-            launch_cast<double, float>(L.nnzb * n * n, L.v64, L.v32, st);
-        }
+        if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, reuse);
         alloc_level_vectors(h, L, mixed);
     }
     h->op_complexity = (double)nz_sum / (double)h->nnzb;
@@ -767,10 +869,14 @@ void amg_build_transposed(cbs_system *h) {
         L.o_v64T.ensure((size_t)L.nnzb * n * n);
         L.v64T = L.o_v64T.get();
         NSWITCH(n, transpose_n, L.nnzb, L.mirror, L.v64, L.v64T, st);
-        if (mixed && q < nlev) {
-            L.o_v32T.ensure((size_t)L.nnzb * n * n);
-            L.v32T = L.o_v32T.get();
-            launch_cast<double, float>(L.nnzb * n * n, L.v64T, L.v32T, st);
+        if (L.sell.soff.get()) {
+            const size_t tot = (size_t)L.sell.nent * n * n;
+            L.sell.v64T.ensure(tot > 0 ? tot : 1);
+            sell_fill(n, L.sell, L.v64T, L.sell.v64T.get(), st);
+            if (mixed) {
+                L.sell.v32T.ensure(tot > 0 ? tot : 1);
+                launch_cast<double, float>((int64_t)tot, L.sell.v64T.get(), L.sell.v32T.get(), st);
+            }
         }
         if (L.Dinv.get()) {
             L.DinvT.ensure((size_t)L.N * n * n);
@@ -780,4 +886,107 @@ void amg_build_transposed(cbs_system *h) {
     }
     HIPCHK(hipStreamSynchronize(st));
     h->transposed_ready = true;
+}
+
+// Permute every level but the coarsest into the aggregation-tree order.
+void renumber_hierarchy(cbs_system *h) {
+    hipStream_t st = h->stream;
+    const int n = h->n;
+    const int nlev = (int)h->lev.size();
+    if (nlev < 2) return;
+    std::vector<DArr<int32_t>> pos(nlev);
+    {
+        Level &C = h->lev[nlev - 1];
+        pos[nlev - 1].alloc(C.N);
+        hipLaunchKernelGGL(k_iota, dim3(cdiv(C.N, 256)), dim3(256), 0, st, C.N, pos[nlev - 1].get());
+    }
+    std::vector<DArr<int32_t>> new_aptr(nlev);
+    for (int l = nlev - 2; l >= 0; --l) {
+        Level &F = h->lev[l];
+        const int32_t nc = F.nc;
+        new_aptr[l].alloc(nc + 1);
+        hipLaunchKernelGGL(k_pos_counts, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, F.agg_ptr.get(), pos[l + 1].get(),
+                           new_aptr[l].get());
+        LAUNCHCHK();
+        scan_exclusive(new_aptr[l].get(), new_aptr[l].get(), nc, st);
+        pos[l].alloc(F.N);
+        hipLaunchKernelGGL(k_pos_assign, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, F.agg_ptr.get(), F.agg_mem.get(),
+                           pos[l + 1].get(), new_aptr[l].get(), pos[l].get());
+        LAUNCHCHK();
+    }
+    for (int l = 0; l + 1 < nlev; ++l) {
+        Level &L = h->lev[l];
+        const int32_t N = L.N;
+        const int64_t nnz = L.nnzb;
+        const dim3 G(cdiv(N, 256)), B(256);
+        DArr<int32_t> ip(N), rpn(N + 1), coln(nnz), sk(nnz), aggn(N), memn(N), rsn(N), mir(nnz), dsl(N);
+        DArr<double> vn((size_t)nnz * n * n);
+        hipLaunchKernelGGL(k_invert, G, B, 0, st, N, pos[l].get(), ip.get());
+        hipLaunchKernelGGL(k_perm_len, G, B, 0, st, N, ip.get(), L.rp, rpn.get());
+        LAUNCHCHK();
+        scan_exclusive(rpn.get(), rpn.get(), N, st);
+        hipLaunchKernelGGL(k_perm_rows, G, B, 0, st, N, ip.get(), pos[l].get(), L.rp, L.col, rpn.get(), coln.get(),
+                           sk.get());
+        NSWITCH(n, gather_blocks_n, nnz, sk.get(), L.v64, vn.get(), st);
+        hipLaunchKernelGGL(k_perm_map, G, B, 0, st, N, ip.get(), L.agg.get(), pos[l + 1].get(), aggn.get());
+        hipLaunchKernelGGL(k_iota, G, B, 0, st, N, memn.get());
+        hipLaunchKernelGGL(k_perm_map, G, B, 0, st, N, ip.get(), L.row_sys.get(), nullptr, rsn.get());
+        HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_mirror_search, G, B, 0, st, N, rpn.get(), coln.get(), mir.get(), dsl.get(), h->dflag.get());
+        LAUNCHCHK();
+        if (read_int(h->dflag.get(), st) & 16) cbs_throw(CBS_ERR_PATTERN, "renumbered pattern is not symmetric");
+        if (l == 0) h->perm_sk = std::move(sk);
+        L.o_rp = std::move(rpn); L.o_col = std::move(coln); L.o_v64 = std::move(vn);
+        L.o_mirror = std::move(mir); L.o_dslot = std::move(dsl);
+        L.rp = L.o_rp.get(); L.col = L.o_col.get(); L.v64 = L.o_v64.get();
+        L.mirror = L.o_mirror.get(); L.dslot = L.o_dslot.get();
+        L.agg = std::move(aggn); L.agg_ptr = std::move(new_aptr[l]); L.agg_mem = std::move(memn);
+        L.row_sys = std::move(rsn);
+        L.order = std::move(ip);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    h->renumbered = true;
+}
+
+// Level-0 values in the internal numbering after a coefficient update.
+void refresh_level0_values(cbs_system *h) {
+    Level &L0 = h->lev[0];
+    NSWITCH(h->n, gather_blocks_n, h->nnzb, h->perm_sk.get(), h->vals.get(), L0.o_v64.get(), h->stream);
+    LAUNCHCHK();
+}
+
+// Caller numbering <-> internal numbering of a level-0 vector.
+void permute_vec(cbs_system *h, const double *in, double *out, bool to_internal) {
+    const int64_t m = (int64_t)h->N * h->n;
+    if (m > 0)
+        hipLaunchKernelGGL(k_perm_vec, dim3(cdiv(m, 256)), dim3(256), 0, h->stream, h->N, h->n, h->lev[0].order.get(),
+                           in, out, to_internal ? 1 : 0);
+    LAUNCHCHK();
+}
+
+// cbs_spmv: caller-numbered A or A^T (sliced copy built on first use)
+void spmv_user(cbs_system *h, const double *x, double *y, bool transposed) {
+    Sell &U = h->usell;
+    const int n = h->n;
+    const size_t tot = 0;
+    (void)tot;
+    if (!U.soff.get()) sell_build(h->N, h->rp.get(), h->col.get(), U, h->stream);
+    const size_t nv = (size_t)U.nent * n * n;
+    if (!transposed) {
+        if (!U.v64.get()) {
+            U.v64.alloc(nv > 0 ? nv : 1);
+            sell_fill(n, U, h->vals.get(), U.v64.get(), h->stream);
+        }
+        launch_rows<double, double>(0, n, U.view(), U.v64.get(), x, nullptr, y, nullptr, 0.0, h->stream);
+        return;
+    }
+    if (!U.v64T.get()) {
+        h->valsT.alloc((size_t)h->nnzb * n * n);
+        NSWITCH(n, transpose_n, h->nnzb, h->mirror.get(), h->vals.get(), h->valsT.get(), h->stream);
+        LAUNCHCHK();
+        U.v64T.alloc(nv > 0 ? nv : 1);
+        sell_fill(n, U, h->valsT.get(), U.v64T.get(), h->stream);
+        h->valsT.release();
+    }
+    launch_rows<double, double>(0, n, U.view(), U.v64T.get(), x, nullptr, y, nullptr, 0.0, h->stream);
 }

@@ -62,13 +62,6 @@ void build_items(cbs_system *h) {
                      hipMemcpyHostToDevice));
 }
 
-void ensure_level0(cbs_system *h) {
-    if (h->lev.empty()) h->lev.emplace_back();
-    Level &L0 = h->lev[0];
-    L0.N = h->N; L0.nnzb = h->nnzb;
-    L0.rp = h->rp.get(); L0.col = h->col.get(); L0.mirror = h->mirror.get(); L0.dslot = h->dslot.get();
-    L0.v64 = h->vals.get();
-}
 
 int create_common(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const int64_t *face_off, int32_t bdim,
                   const int32_t *la, const int32_t *ua, const double *diag, const double *upper, const double *lower,
@@ -107,7 +100,6 @@ int create_common(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const
     HIPCHK(hipEventRecord(h->ev1, h->stream));
     h->t_convert_ms = elapsed_ms(h->ev0, h->ev1);
     (void)t0;
-    ensure_level0(h.get());
     *out = h.release();
     return CBS_OK;
 }
@@ -143,6 +135,7 @@ void cbs_default_options(cbs_options *o) {
     o->max_levels = 24;
     o->reuse_aggregates = 0;
     o->check_every = 1;
+    o->renumber = 1;
 }
 
 int cbs_create_from_ldu(cbs_handle *out, int32_t n_cells, int32_t n_faces, int32_t bdim, const int32_t *lower_addr,
@@ -174,6 +167,9 @@ int cbs_update_values(cbs_handle h, const double *diag, const double *upper, con
         h->t_convert_ms = elapsed_ms(h->ev0, h->ev1);
         h->values_changed = true;
         h->transposed_ready = false;
+        h->valsT.release();
+        h->usell.v64.release();
+        h->usell.v64T.release();
         invalidate_graphs(h);
         return CBS_OK;
     });
@@ -201,7 +197,6 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
                           h->opt.max_levels == o.max_levels;
         if (!keep) o.reuse_aggregates = 0;
         h->opt = o;
-        ensure_level0(h);
         HIPCHK(hipEventRecord(h->ev0, h->stream));
         h->setup_done = false;
         invalidate_graphs(h);
@@ -245,9 +240,7 @@ int cbs_gradient(cbs_handle h, const double *lambda, const double *x, double *gd
 int cbs_spmv(cbs_handle h, const double *x, double *y, int32_t transpose) {
     return guarded([&] {
         require(h != nullptr && x && y, CBS_ERR_ARG, "NULL argument");
-        ensure_level0(h);
-        if (transpose) amg_build_transposed(h);
-        spmv64(h, x, y, transpose != 0);
+        spmv_user(h, x, y, transpose != 0);
         return CBS_OK;
     });
 }
@@ -256,7 +249,16 @@ int cbs_apply_precond(cbs_handle h, const double *r, double *z) {
     return guarded([&] {
         require(h != nullptr && r && z, CBS_ERR_ARG, "NULL argument");
         require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
-        precond_apply(h, r, z, false);
+        if (h->renumbered) {
+            const int64_t m = (int64_t)h->N * h->n;
+            h->bw.ensure(m);
+            h->xw.ensure(m);
+            permute_vec(h, r, h->bw.get(), true);
+            precond_apply(h, h->bw.get(), h->xw.get(), false);
+            permute_vec(h, h->xw.get(), z, false);
+        } else {
+            precond_apply(h, r, z, false);
+        }
         return CBS_OK;
     });
 }
@@ -311,7 +313,7 @@ int cbs_get_bcsr(cbs_handle h, int32_t *row_ptr, int32_t *col, double *vals, int
 }
 
 int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows, int64_t *nnzb, int32_t *row_ptr, int32_t *col,
-                  double *vals, int32_t *agg, int32_t *colour) {
+                  double *vals, int32_t *agg, int32_t *colour, int32_t *order) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
         require(h->setup_done, CBS_ERR_STATE, "no hierarchy before cbs_setup");
@@ -327,6 +329,16 @@ int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows, int64_t *nnzb, i
         if (agg && L.agg.get()) HIPCHK(hipMemcpyAsync(agg, L.agg.get(), sizeof(int32_t) * L.N, hipMemcpyDeviceToDevice, st));
         if (colour && L.colour.get())
             HIPCHK(hipMemcpyAsync(colour, L.colour.get(), sizeof(int32_t) * L.N, hipMemcpyDeviceToDevice, st));
+        if (order) {
+            if (L.order.get())
+                HIPCHK(hipMemcpyAsync(order, L.order.get(), sizeof(int32_t) * L.N, hipMemcpyDeviceToDevice, st));
+            else {
+                std::vector<int32_t> id(L.N);
+                for (int32_t i = 0; i < L.N; ++i) id[i] = i;
+                HIPCHK(hipMemcpyAsync(order, id.data(), sizeof(int32_t) * L.N, hipMemcpyHostToDevice, st));
+                HIPCHK(hipStreamSynchronize(st));
+            }
+        }
         HIPCHK(hipStreamSynchronize(st));
         return CBS_OK;
     });

@@ -82,6 +82,28 @@ enum {
     S_NSCAL
 };
 
+// ---------------------------------------------------------------- sliced ELL
+// Solve-phase storage of a level matrix: slices of kSlice block rows; in
+// slice s, entry k of row 16s+ii sits at soff[s] + k*kSlice + ii (rows keep
+// their column order; short rows are padded with col = -1 up to the slice
+// width sw[s]).  One wavefront of a block-row kernel then reads kSlice
+// consecutive blocks per step.  BCSR stays the setup-time format.
+constexpr int kSlice = 16;
+
+struct SellView {
+    int32_t N;
+    const int32_t *soff, *sw, *scol;
+};
+
+struct Sell {
+    int32_t N = 0, nslices = 0;
+    int64_t nent = 0;
+    DArr<int32_t> soff, sw, scol, ssrc;   // ssrc: BCSR slot of each entry, -1 = padding
+    DArr<double> v64, v64T;
+    DArr<float> v32, v32T;
+    SellView view() const { return SellView{N, soff.get(), sw.get(), scol.get()}; }
+};
+
 // ---------------------------------------------------------------- levels
 struct Level {
     int32_t N = 0;          // block rows
@@ -105,11 +127,15 @@ struct Level {
     DArr<int32_t> colour, rows_by_colour;
     std::vector<int32_t> colour_off;     // host, ncolours + 1
     DArr<double> Einv, EinvT;
+    // internal renumbering: order[i'] = row of the original numbering
+    DArr<int32_t> order;
     // transfer to the next level
     DArr<int32_t> agg, agg_ptr, agg_mem;
     int32_t nc = 0;
     // level vectors in the hierarchy precision (bytes)
     DArr<char> vb, vx, vr, vt;
+    // solve-phase matrix copy
+    Sell sell;
 };
 
 struct Coarse {
@@ -153,7 +179,12 @@ struct cbs_system {
     // captured iteration graphs (index: transposed solve), replayed on `stream`
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t g_iter[2] = {nullptr, nullptr};
-    DArr<double> xw;                             // solution work copy the graphs point at
+    DArr<double> xw, bw;                         // solution / rhs work copies the graphs point at
+    // internal renumbering of level 0 (AMG setup)
+    bool renumbered = false;
+    DArr<int32_t> perm_sk;                       // permuted level-0 slot -> caller-order slot
+    DArr<double> valsT;                          // caller-order A^T values (cbs_spmv transpose)
+    Sell usell;                                  // caller-order sliced copy (cbs_spmv)
     // statistics
     double t_convert_ms = 0.0, t_setup_ms = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -179,8 +210,11 @@ void gradient(cbs_system *h, const double *lam, const double *x, double *gd, dou
 //   mode 0: y = A x;  mode 1: y = b - A x;  mode 2: y = x + omega Dinv (b - A x)
 //   mode 3: y = omega Dinv b (block-Jacobi sweep from a zero guess)
 template <typename TV, typename TX>
-void launch_rows(int mode, int n, int32_t N, const int32_t *rp, const int32_t *col, const TV *val,
-                 const TX *x, const TX *b, TX *y, const double *Dinv, double omega, hipStream_t st);
+void launch_rows(int mode, int n, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y,
+                 const double *Dinv, double omega, hipStream_t st);
+// sliced-ELL pattern from BCSR, and values gathered from BCSR values
+void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st);
+void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st);
 template <typename TX>
 void launch_restrict(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem,
                      const TX *r, TX *bc, hipStream_t st);
@@ -194,6 +228,10 @@ void launch_block_apply(int n, int32_t N, const double *Dinv, const double *r, d
 // AMG setup (amg.hip)
 void amg_setup(cbs_system *h);
 void amg_build_transposed(cbs_system *h);
+void renumber_hierarchy(cbs_system *h);
+void refresh_level0_values(cbs_system *h);
+void permute_vec(cbs_system *h, const double *in, double *out, bool to_internal);
+void spmv_user(cbs_system *h, const double *x, double *y, bool transposed);
 void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv);
 
 // Krylov (krylov.hip)

@@ -395,9 +395,9 @@ template <typename T> T *vptr(DArr<char> &a) { return reinterpret_cast<T *>(a.ge
 template <typename T>
 const T *level_vals(Level &L, bool tr);
 template <>
-const double *level_vals<double>(Level &L, bool tr) { return tr ? L.v64T : L.v64; }
+const double *level_vals<double>(Level &L, bool tr) { return tr ? L.sell.v64T.get() : L.sell.v64.get(); }
 template <>
-const float *level_vals<float>(Level &L, bool tr) { return tr ? L.v32T : L.v32; }
+const float *level_vals<float>(Level &L, bool tr) { return tr ? L.sell.v32T.get() : L.sell.v32.get(); }
 
 // x = V(b) with zero initial guess on level l; the result lands in x.
 template <typename T>
@@ -420,36 +420,39 @@ void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
     T *cur = (switches % 2 == 0) ? x : tmp;
     T *oth = (cur == x) ? tmp : x;
     if (nu1 >= 1) {
-        launch_rows<T, T>(3, n, L.N, L.rp, L.col, val, cur, b, cur, Dinv, o.omega, st);
+        launch_rows<T, T>(3, n, L.sell.view(), val, cur, b, cur, Dinv, o.omega, st);
         for (int s = 1; s < nu1; ++s) {
-            launch_rows<T, T>(2, n, L.N, L.rp, L.col, val, cur, b, oth, Dinv, o.omega, st);
+            launch_rows<T, T>(2, n, L.sell.view(), val, cur, b, oth, Dinv, o.omega, st);
             std::swap(cur, oth);
         }
     } else {
         launch_fill<T>((int64_t)L.N * n, cur, st);
     }
-    launch_rows<T, T>(1, n, L.N, L.rp, L.col, val, cur, b, r, Dinv, o.omega, st);
+    launch_rows<T, T>(1, n, L.sell.view(), val, cur, b, r, Dinv, o.omega, st);
     Level &C = h->lev[l + 1];
     T *bc = vptr<T>(C.vb), *xc = vptr<T>(C.vx);
     launch_restrict<T>(n, C.N, L.agg_ptr.get(), L.agg_mem.get(), r, bc, st);
     vcycle<T>(h, tr, l + 1, bc, xc);
     launch_prolong<T>(n, L.N, L.agg.get(), xc, cur, st);
     for (int s = 0; s < nu2; ++s) {
-        launch_rows<T, T>(2, n, L.N, L.rp, L.col, val, cur, b, oth, Dinv, o.omega, st);
+        launch_rows<T, T>(2, n, L.sell.view(), val, cur, b, oth, Dinv, o.omega, st);
         std::swap(cur, oth);
     }
 }
 
 }  // namespace
 
+// FP64 operator of the Krylov loop: level 0 in the internal numbering
 void spmv64(cbs_system *h, const double *x, double *y, bool transposed) {
-    const double *val = transposed ? h->lev[0].v64T : h->vals.get();
-    launch_rows<double, double>(0, h->n, h->N, h->rp.get(), h->col.get(), val, x, nullptr, y, nullptr, 0.0, h->stream);
+    Level &L0 = h->lev[0];
+    const double *val = transposed ? L0.sell.v64T.get() : L0.sell.v64.get();
+    launch_rows<double, double>(0, h->n, L0.sell.view(), val, x, nullptr, y, nullptr, 0.0, h->stream);
 }
 
 static void residual64(cbs_system *h, const double *b, const double *x, double *r, bool transposed) {
-    const double *val = transposed ? h->lev[0].v64T : h->vals.get();
-    launch_rows<double, double>(1, h->n, h->N, h->rp.get(), h->col.get(), val, x, b, r, nullptr, 0.0, h->stream);
+    Level &L0 = h->lev[0];
+    const double *val = transposed ? L0.sell.v64T.get() : L0.sell.v64.get();
+    launch_rows<double, double>(1, h->n, L0.sell.view(), val, x, b, r, nullptr, 0.0, h->stream);
 }
 
 void precond_apply(cbs_system *h, const double *r, double *z, bool tr) {
@@ -772,16 +775,23 @@ int krylov_solve(cbs_system *h, const double *b, double *x, cbs_stats *stv, bool
     HIPCHK(hipEventRecord(h->ev0, st));
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<int> status;
-    if (h->opt.solver == CBS_SOLVER_FGMRES) {
-        fgmres(h, b, x, tr, status);
+    // the solvers run on work copies in the internal numbering (the captured
+    // iteration graph points at xw)
+    const int64_t m = (int64_t)h->N * h->n;
+    h->xw.ensure(m);
+    h->bw.ensure(m);
+    const double *bi = b;
+    if (h->renumbered) {
+        permute_vec(h, b, h->bw.get(), true);
+        permute_vec(h, x, h->xw.get(), true);
+        bi = h->bw.get();
     } else {
-        // the captured iteration points at the work copy xw
-        const int64_t m = (int64_t)h->N * h->n;
-        h->xw.ensure(m);
         launch_copy(m, x, h->xw.get(), st);
-        bicgstab(h, b, h->xw.get(), tr, status);
-        launch_copy(m, h->xw.get(), x, st);
     }
+    if (h->opt.solver == CBS_SOLVER_FGMRES) fgmres(h, bi, h->xw.get(), tr, status);
+    else bicgstab(h, bi, h->xw.get(), tr, status);
+    if (h->renumbered) permute_vec(h, h->xw.get(), x, false);
+    else launch_copy(m, h->xw.get(), x, st);
     HIPCHK(hipEventRecord(h->ev1, st));
     // statistics: true residual per system (BiCGStab's last step may not have computed it)
     std::vector<double> rr_rec(nsys), res0(nsys), bbv(nsys);
@@ -794,7 +804,7 @@ int krylov_solve(cbs_system *h, const double *b, double *x, cbs_stats *stv, bool
             bbv[s] = hv.scal[S_BB * nsys + s];
         }
     }
-    true_residual(h, b, x, tr);
+    true_residual(h, bi, h->xw.get(), tr);
     HostView hv;
     read_state(h, hv, true);
     float ms = 0.f;

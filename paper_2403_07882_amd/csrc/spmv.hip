@@ -23,15 +23,17 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 // Row r of one block: n contiguous values, streamed once per SpMV, so they
 // are loaded non-temporally (keeps x resident in the caches).  16-byte
 // vector loads where the alignment allows it (n = 4).
+// FP32 values are streamed with non-temporal loads (measured faster on
+// gfx950 for the 64-byte blocks); FP64 values use ordinary loads.
 template <int n, typename T>
 __device__ inline void load_block_row(const T *__restrict__ p, T (&v)[n]) {
 #pragma unroll
-    for (int c = 0; c < n; ++c) v[c] = __builtin_nontemporal_load(p + c);
+    for (int c = 0; c < n; ++c) v[c] = sizeof(T) == 4 ? __builtin_nontemporal_load(p + c) : p[c];
 }
 template <>
 __device__ inline void load_block_row<4, double>(const double *__restrict__ p, double (&v)[4]) {
-    const dbl2 a = __builtin_nontemporal_load(reinterpret_cast<const dbl2 *>(p));
-    const dbl2 b = __builtin_nontemporal_load(reinterpret_cast<const dbl2 *>(p) + 1);
+    const dbl2 a = *reinterpret_cast<const dbl2 *>(p);
+    const dbl2 b = *(reinterpret_cast<const dbl2 *>(p) + 1);
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 template <>
@@ -57,43 +59,54 @@ __device__ inline void load_x<4, float>(const float *__restrict__ p, float (&v)[
 }
 
 // mode 0: y = A x; 1: y = b - A x; 2: y = x + w Dinv (b - A x); 3: y = w Dinv b
+// Rows are read from the sliced-ELL copy: at step k the 16 rows of a slice
+// read 16 consecutive blocks; four steps are loaded before they are summed,
+// and the sums run in the row's column order.
 template <int n, typename TV, typename TX, int MODE>
-__global__ __launch_bounds__(64 * n) void k_rows(int32_t N, const int32_t *__restrict__ rp,
-                                                 const int32_t *__restrict__ col, const TV *__restrict__ val,
-                                                 const TX *__restrict__ x, const TX *__restrict__ b,
-                                                 TX *__restrict__ y, const double *__restrict__ Dinv,
-                                                 double omega) {
+__global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restrict__ val, const TX *__restrict__ x,
+                                                 const TX *__restrict__ b, TX *__restrict__ y,
+                                                 const double *__restrict__ Dinv, double omega) {
     using A = typename Acc<TX>::type;
+    constexpr int nn = n * n;
+    constexpr int U = 4;
     const int t = threadIdx.x;
     const int lr = t / n, r = t - lr * n;
     const int32_t i = blockIdx.x * 64 + lr;
+    const int32_t N = S.N;
     A acc = 0;
     if (MODE != 3 && i < N) {
-        const int32_t kb = rp[i], ke = rp[i + 1];
-        int32_t k = kb;
-        // two blocks per step: both blocks' loads are in flight together;
-        // the sums still run block after block in column order
-        for (; k + 1 < ke; k += 2) {
-            const int32_t j0 = col[k], j1 = col[k + 1];
-            TV b0[n], b1[n];
-            TX x0[n], x1[n];
-            load_block_row<n, TV>(val + (int64_t)k * (n * n) + r * n, b0);
-            load_block_row<n, TV>(val + (int64_t)(k + 1) * (n * n) + r * n, b1);
-            load_x<n, TX>(x + (int64_t)j0 * n, x0);
-            load_x<n, TX>(x + (int64_t)j1 * n, x1);
+        const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+        const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
+        int32_t k = 0;
+        for (; k + U <= w; k += U) {
+            int32_t j[U];
+            TV bv[U][n];
+            TX xv[U][n];
 #pragma unroll
-            for (int c = 0; c < n; ++c) acc += (A)b0[c] * (A)x0[c];
+            for (int u = 0; u < U; ++u) j[u] = S.scol[base + (k + u) * kSlice];
 #pragma unroll
-            for (int c = 0; c < n; ++c) acc += (A)b1[c] * (A)x1[c];
+            for (int u = 0; u < U; ++u) {
+                const int64_t e = base + (int64_t)(k + u) * kSlice;
+                load_block_row<n, TV>(val + e * nn + r * n, bv[u]);
+                load_x<n, TX>(x + (int64_t)(j[u] < 0 ? i : j[u]) * n, xv[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (j[u] >= 0) {
+#pragma unroll
+                    for (int c = 0; c < n; ++c) acc += (A)bv[u][c] * (A)xv[u][c];
+                }
         }
-        if (k < ke) {
-            const int32_t j0 = col[k];
-            TV b0[n];
-            TX x0[n];
-            load_block_row<n, TV>(val + (int64_t)k * (n * n) + r * n, b0);
-            load_x<n, TX>(x + (int64_t)j0 * n, x0);
+        for (; k < w; ++k) {
+            const int64_t e = base + (int64_t)k * kSlice;
+            const int32_t j = S.scol[e];
+            if (j < 0) continue;
+            TV bv[n];
+            TX xv[n];
+            load_block_row<n, TV>(val + e * nn + r * n, bv);
+            load_x<n, TX>(x + (int64_t)j * n, xv);
 #pragma unroll
-            for (int c = 0; c < n; ++c) acc += (A)b0[c] * (A)x0[c];
+            for (int c = 0; c < n; ++c) acc += (A)bv[c] * (A)xv[c];
         }
     }
     const int64_t o = (int64_t)i * n + r;
@@ -111,7 +124,7 @@ __global__ __launch_bounds__(64 * n) void k_rows(int32_t N, const int32_t *__res
     sres[t] = res;
     __syncthreads();
     if (i < N) {
-        const double *Di = Dinv + (int64_t)i * (n * n) + r * n;
+        const double *Di = Dinv + (int64_t)i * nn + r * n;
         double z = 0.0;
 #pragma unroll
         for (int c = 0; c < n; ++c) z += Di[c] * (double)sres[lr * n + c];
@@ -121,15 +134,53 @@ __global__ __launch_bounds__(64 * n) void k_rows(int32_t N, const int32_t *__res
 }
 
 template <int n, typename TV, typename TX>
-void rows_n(int mode, int32_t N, const int32_t *rp, const int32_t *col, const TV *val, const TX *x,
-            const TX *b, TX *y, const double *Dinv, double omega, hipStream_t st) {
-    const dim3 g(cdiv(N, 64)), bl(64 * n);
+void rows_n(int mode, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, const double *Dinv,
+            double omega, hipStream_t st) {
+    const dim3 g(cdiv(S.N, 64)), bl(64 * n);
     switch (mode) {
-        case 0: hipLaunchKernelGGL((k_rows<n, TV, TX, 0>), g, bl, 0, st, N, rp, col, val, x, b, y, Dinv, omega); break;
-        case 1: hipLaunchKernelGGL((k_rows<n, TV, TX, 1>), g, bl, 0, st, N, rp, col, val, x, b, y, Dinv, omega); break;
-        case 2: hipLaunchKernelGGL((k_rows<n, TV, TX, 2>), g, bl, 0, st, N, rp, col, val, x, b, y, Dinv, omega); break;
-        case 3: hipLaunchKernelGGL((k_rows<n, TV, TX, 3>), g, bl, 0, st, N, rp, col, val, x, b, y, Dinv, omega); break;
+        case 0: hipLaunchKernelGGL((k_rows<n, TV, TX, 0>), g, bl, 0, st, S, val, x, b, y, Dinv, omega); break;
+        case 1: hipLaunchKernelGGL((k_rows<n, TV, TX, 1>), g, bl, 0, st, S, val, x, b, y, Dinv, omega); break;
+        case 2: hipLaunchKernelGGL((k_rows<n, TV, TX, 2>), g, bl, 0, st, S, val, x, b, y, Dinv, omega); break;
+        case 3: hipLaunchKernelGGL((k_rows<n, TV, TX, 3>), g, bl, 0, st, S, val, x, b, y, Dinv, omega); break;
     }
+}
+
+// ------------------------------------------------------------------ sliced ELL build
+__global__ void k_sell_width(int32_t N, int32_t ns, const int32_t *rp, int32_t *sw, int32_t *cnt) {
+    const int32_t sl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= ns) return;
+    int32_t w = 0;
+    for (int32_t i = sl * kSlice; i < min(N, (sl + 1) * kSlice); ++i) w = max(w, rp[i + 1] - rp[i]);
+    sw[sl] = w;
+    cnt[sl] = w * kSlice;
+}
+
+__global__ void k_sell_fill_idx(int32_t N, const int32_t *rp, const int32_t *col, const int32_t *soff, int32_t *scol,
+                                int32_t *ssrc) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int64_t e = soff[sl] + (int64_t)(k - rp[i]) * kSlice + ii;
+        scol[e] = col[k];
+        ssrc[e] = k;
+    }
+}
+
+__global__ void k_fill_i32(int64_t m, int32_t *a, int32_t v) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < m) a[g] = v;
+}
+
+template <int n>
+__global__ void k_sell_vals(int64_t nent, const int32_t *__restrict__ ssrc, const double *__restrict__ in,
+                            double *__restrict__ out) {
+    constexpr int nn = n * n;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nent * nn) return;
+    const int64_t e = g / nn;
+    const int32_t k = ssrc[e];
+    out[g] = k >= 0 ? in[(int64_t)k * nn + (g - e * nn)] : 0.0;
 }
 
 template <typename TX>
@@ -197,22 +248,59 @@ __global__ void k_block_apply(int32_t N, const double *__restrict__ Dinv, const 
 }  // namespace
 
 template <typename TV, typename TX>
-void launch_rows(int mode, int n, int32_t N, const int32_t *rp, const int32_t *col, const TV *val,
-                 const TX *x, const TX *b, TX *y, const double *Dinv, double omega, hipStream_t st) {
-    if (N <= 0) return;
+void launch_rows(int mode, int n, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y,
+                 const double *Dinv, double omega, hipStream_t st) {
+    if (S.N <= 0) return;
     switch (n) {
-        case 1: rows_n<1>(mode, N, rp, col, val, x, b, y, Dinv, omega, st); break;
-        case 2: rows_n<2>(mode, N, rp, col, val, x, b, y, Dinv, omega, st); break;
-        case 3: rows_n<3>(mode, N, rp, col, val, x, b, y, Dinv, omega, st); break;
-        case 4: rows_n<4>(mode, N, rp, col, val, x, b, y, Dinv, omega, st); break;
-        case 5: rows_n<5>(mode, N, rp, col, val, x, b, y, Dinv, omega, st); break;
+        case 1: rows_n<1>(mode, S, val, x, b, y, Dinv, omega, st); break;
+        case 2: rows_n<2>(mode, S, val, x, b, y, Dinv, omega, st); break;
+        case 3: rows_n<3>(mode, S, val, x, b, y, Dinv, omega, st); break;
+        case 4: rows_n<4>(mode, S, val, x, b, y, Dinv, omega, st); break;
+        case 5: rows_n<5>(mode, S, val, x, b, y, Dinv, omega, st); break;
     }
     LAUNCHCHK();
 }
-template void launch_rows<double, double>(int, int, int32_t, const int32_t *, const int32_t *, const double *,
-                                          const double *, const double *, double *, const double *, double, hipStream_t);
-template void launch_rows<float, float>(int, int, int32_t, const int32_t *, const int32_t *, const float *,
-                                        const float *, const float *, float *, const double *, double, hipStream_t);
+template void launch_rows<double, double>(int, int, const SellView &, const double *, const double *, const double *,
+                                          double *, const double *, double, hipStream_t);
+template void launch_rows<float, float>(int, int, const SellView &, const float *, const float *, const float *,
+                                        float *, const double *, double, hipStream_t);
+
+void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st) {
+    S.N = N;
+    S.nslices = (N + kSlice - 1) / kSlice;
+    const int32_t ns = S.nslices;
+    S.sw.alloc(ns > 0 ? ns : 1);
+    S.soff.alloc(ns + 1);
+    if (ns > 0)
+        hipLaunchKernelGGL(k_sell_width, dim3(cdiv(ns, 256)), dim3(256), 0, st, N, ns, rp, S.sw.get(), S.soff.get());
+    LAUNCHCHK();
+    scan_exclusive(S.soff.get(), S.soff.get(), ns, st);
+    S.nent = read_int(S.soff.get() + ns, st);
+    S.scol.alloc(S.nent > 0 ? S.nent : 1);
+    S.ssrc.alloc(S.nent > 0 ? S.nent : 1);
+    if (S.nent > 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(cdiv(S.nent, 256)), dim3(256), 0, st, S.nent, S.scol.get(), -1);
+        hipLaunchKernelGGL(k_fill_i32, dim3(cdiv(S.nent, 256)), dim3(256), 0, st, S.nent, S.ssrc.get(), -1);
+    }
+    if (N > 0)
+        hipLaunchKernelGGL(k_sell_fill_idx, dim3(cdiv(N, 256)), dim3(256), 0, st, N, rp, col, S.soff.get(),
+                           S.scol.get(), S.ssrc.get());
+    LAUNCHCHK();
+}
+
+void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st) {
+    const int64_t tot = S.nent * n * n;
+    if (tot <= 0) return;
+    const dim3 g(cdiv(tot, 256)), b(256);
+    switch (n) {
+        case 1: hipLaunchKernelGGL(k_sell_vals<1>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
+        case 2: hipLaunchKernelGGL(k_sell_vals<2>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
+        case 3: hipLaunchKernelGGL(k_sell_vals<3>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
+        case 4: hipLaunchKernelGGL(k_sell_vals<4>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
+        case 5: hipLaunchKernelGGL(k_sell_vals<5>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
+    }
+    LAUNCHCHK();
+}
 
 template <typename TX>
 void launch_restrict(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem, const TX *r, TX *bc,

@@ -219,31 +219,65 @@ def test_solve_is_deterministic():
 
 
 # ------------------------------------------------------------------ AMG pieces
-def test_rap_and_vcycle_match_oracle_given_gpu_aggregates():
-    _say("rap/vcycle parity")
+@pytest.mark.parametrize("renumber", [0, 1])
+def test_rap_and_vcycle_match_oracle_given_gpu_aggregates(renumber):
+    _say("rap/vcycle parity renumber", renumber)
     s = pressure_velocity(10, 9, 8, seed=4)
     A = O.from_system(s)
     with P.System.from_dict(s) as sysm:
-        sysm.setup(precond=P.PREC_AMG, coarse_max=8, pre_sweeps=1, post_sweeps=1, omega=0.8)
+        sysm.setup(precond=P.PREC_AMG, coarse_max=8, pre_sweeps=1, post_sweeps=1, omega=0.8, renumber=renumber)
         nlev = sysm.info()["levels"]
         assert nlev >= 3
-        aggs, Al = [], A
+        lv0 = sysm.get_level(0)
+        order = _np(lv0["order"])
+        assert np.array_equal(np.sort(order), np.arange(A.N))
+        if not renumber:
+            assert np.array_equal(order, np.arange(A.N))
+        # level 0 in the internal numbering is exactly P A P^T (a permuted copy)
+        pos = np.empty_like(order); pos[order] = np.arange(A.N)
+        A0 = O.BCSR(A.N, 4, _np(lv0["row_ptr"]), _np(lv0["col"]), _np(lv0["vals"]))
+        assert np.array_equal(A0.dense(), A.dense()[np.repeat(order * 4, 4) + np.tile(np.arange(4), A.N)][:, np.repeat(order * 4, 4) + np.tile(np.arange(4), A.N)])
+        aggs, Al = [], A0
         for l in range(nlev):
             lv = sysm.get_level(l)
             assert np.array_equal(_np(lv["row_ptr"]), Al.row_ptr)
             assert np.array_equal(_np(lv["col"]), Al.col)
-            assert np.array_equal(_np(lv["vals"]), Al.vals)          # same sums in the same order
+            if renumber:
+                # same Galerkin sums, taken in another order
+                assert np.allclose(_np(lv["vals"]), Al.vals, rtol=1e-13, atol=1e-13 * np.abs(Al.vals).max())
+            else:
+                assert np.array_equal(_np(lv["vals"]), Al.vals)          # same sums in the same order
+            Al = O.BCSR(Al.N, 4, Al.row_ptr, Al.col, _np(lv["vals"]))
             if l + 1 < nlev:
                 agg = _np(lv["agg"])
                 nc = int(agg.max()) + 1
                 assert np.array_equal(np.unique(agg), np.arange(nc))
+                if renumber:          # aggregates are contiguous row ranges
+                    assert np.all(np.diff(agg) >= 0)
                 aggs.append(agg)
                 Al = O.rap(Al, agg, nc)
-        amg = O.AMG(A, nu1=1, nu2=1, omega=0.8, aggs=aggs)
+        amg = O.AMG(A0, nu1=1, nu2=1, omega=0.8, aggs=aggs)
         r = np.random.default_rng(0).standard_normal((A.N, 4))
         z = _np(sysm.apply_precond(r))
-    zr = amg.apply(r)
+    zr_int = amg.apply(r[order])
+    zr = np.empty_like(zr_int); zr[order] = zr_int
     assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+
+
+def test_renumbering_keeps_the_solution():
+    s = pressure_velocity(14, 12, 10, seed=7)
+    A = O.from_system(s)
+    xref = _ref_solution(A, s["b"])
+    out = {}
+    for rn in (0, 1):
+        with P.System.from_dict(s) as sysm:
+            sysm.setup(precond=P.PREC_AMG, precision=P.PRECISION_MIXED, renumber=rn, tol=1e-10)
+            x, st = sysm.solve(s["b"])
+            assert st["status"] == P.OK
+            out[rn] = _np(x)
+            _check_solution(A, s["b"], out[rn], xref, tol=1e-10, err=1e-7)
+            lam, stt = sysm.solve_transpose(s["b"])
+            assert O.relres(O.transpose(A), s["b"], _np(lam)) <= 1e-10 * 1.0001
 
 
 def test_aggregation_properties():
@@ -251,7 +285,10 @@ def test_aggregation_properties():
     with P.System.from_dict(s) as sysm:
         sysm.setup(precond=P.PREC_AMG, match_passes=2)
         lv = sysm.get_level(0)
-        agg = _np(lv["agg"])
+        agg_int = _np(lv["agg"])
+        order = _np(lv["order"])
+    agg = np.empty_like(agg_int)
+    agg[order] = agg_int                       # back to the caller's cell numbering
     nc = agg.max() + 1
     sizes = np.bincount(agg)
     assert sizes.min() >= 1 and nc < s["N"] / 2.5
