@@ -88,6 +88,9 @@ typedef struct cbs_options {
                                 gathers cache-local on irregularly numbered
                                 meshes; inputs and outputs keep the caller's
                                 numbering                            [1] */
+    int32_t dilu_levels;     /* smoother DILU: the dilu_levels finest levels use
+                                multicolour DILU, coarser ones damped block
+                                Jacobi; < 0 = every level            [2] */
 } cbs_options;
 
 /* Per-solve statistics (Algorithm amgxFoam: iterations and residuals). */

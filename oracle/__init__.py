@@ -74,7 +74,7 @@ def _declare(L):
         "orc_restrict": (None, [ci, ci, _i32p, _f64p, ci, _f64p]),
         "orc_prolong_add": (None, [ci, ci, _i32p, _f64p, _f64p]),
         "orc_amg_create": (vp, [ci, ci, _i32p, _i32p, _f64p, ci, ci, ci, ci, ci, cd,
-                                vp, ci, vp]),
+                                vp, ci, vp, ci, ci]),
         "orc_amg_free": (None, [vp]),
         "orc_amg_levels": (ci, [vp]),
         "orc_amg_level_info": (None, [vp, ci, C.POINTER(ci), C.POINTER(cl)]),
@@ -302,7 +302,7 @@ class AMG:
     """
 
     def __init__(self, A: BCSR, coarse_max=32, passes=2, smoother=SMOOTH_BJACOBI,
-                 nu1=1, nu2=1, omega=0.8, aggs=None, ranks=None):
+                 nu1=1, nu2=1, omega=0.8, aggs=None, ranks=None, dilu_levels=-1):
         self._keep = []
         aggp, nag = None, 0
         if aggs is not None:
@@ -312,15 +312,15 @@ class AMG:
             aggp, nag = cat.ctypes.data, len(aggs)
             if nag == 0:
                 aggp = cat.ctypes.data
-        rk = None
-        if ranks is not None:
+        rk, nrk = None, 0
+        if ranks is not None and len(ranks):
             catr = np.ascontiguousarray(np.concatenate([np.asarray(a, np.int32) for a in ranks]), np.int32)
             self._keep.append(catr)
-            rk = catr.ctypes.data
+            rk, nrk = catr.ctypes.data, len(ranks)
         self.A = A
         self.h = lib().orc_amg_create(A.N, A.n, A.row_ptr, A.col, A.vals.ravel(),
                                       coarse_max, passes, smoother, nu1, nu2, float(omega),
-                                      aggp, nag, rk)
+                                      aggp, nag, rk, nrk, int(dilu_levels))
         if not self.h:
             raise OracleError(ERR_SINGULAR, "amg_create")
 

@@ -625,7 +625,7 @@ typedef struct {
 } olevel;
 
 typedef struct {
-    int n, nlev, smoother, nu1, nu2;
+    int n, nlev, smoother, nu1, nu2, dilu_levels;
     double omega;
     olevel L[MAXLEV];
     double *LU; int *piv; int m;   /* coarsest level, dense LU */
@@ -645,20 +645,24 @@ void orc_amg_free(void *h)
     free(A->LU); free(A->piv); free(A);
 }
 
-/* Build the hierarchy.  smoother: 0 = damped block Jacobi, 1 = DILU.
+/* Build the hierarchy.  smoother: 0 = damped block Jacobi, 1 = DILU on the
+ * dilu_levels finest levels (all levels when dilu_levels < 0) and damped
+ * block Jacobi below them.
  * If aggs != NULL, level l uses the aggregate map aggs[off_l .. off_l+N_l)
  * (concatenated in level order, n_agg_levels maps in total) instead of its
- * own matching; ranks (same layout, one per row of every smoothed level)
- * give the DILU ordering, else the natural order is used.
+ * own matching; ranks (same layout, one per row, for the n_rank_levels
+ * finest DILU levels) give the DILU ordering, else the natural order.
  * Coarsening stops when N_l <= coarse_max, when matching stalls, or when
  * the given maps run out.  Returns NULL on failure (singular blocks). */
 void *orc_amg_create(int N, int n, const int *rp, const int *col, const double *val,
                      int coarse_max, int passes, int smoother, int nu1, int nu2,
-                     double omega, const int *aggs, int n_agg_levels, const int *ranks)
+                     double omega, const int *aggs, int n_agg_levels, const int *ranks,
+                     int n_rank_levels, int dilu_levels)
 {
     oamg *A = (oamg *)calloc(1, sizeof(oamg));
     long bs = (long)n * n;
     A->n = n; A->smoother = smoother; A->nu1 = nu1; A->nu2 = nu2; A->omega = omega;
+    A->dilu_levels = (smoother == 1) ? (dilu_levels < 0 ? MAXLEV : dilu_levels) : 0;
     /* level 0: own copy */
     olevel *L0 = &A->L[0];
     L0->N = N;
@@ -729,12 +733,12 @@ void *orc_amg_create(int N, int n, const int *rp, const int *col, const double *
     /* smoothers on every level but the coarsest */
     for (int q = 0; q + 1 < A->nlev; q++) {
         olevel *c = &A->L[q];
-        if (smoother == 0) {
+        if (q >= A->dilu_levels) {
             c->Dinv = (double *)malloc(sizeof(double) * ((long)c->N * bs + 1));
             if (diag_inverse(c->N, n, c->rp, c->col, c->val, c->Dinv)) { orc_amg_free(A); return NULL; }
         } else {
             c->rank = (int *)malloc(sizeof(int) * (c->N + 1));
-            if (ranks) { for (int i = 0; i < c->N; i++) c->rank[i] = ranks[roff + i]; roff += c->N; }
+            if (ranks && q < n_rank_levels) { for (int i = 0; i < c->N; i++) c->rank[i] = ranks[roff + i]; roff += c->N; }
             else for (int i = 0; i < c->N; i++) c->rank[i] = i;
             c->Einv = (double *)malloc(sizeof(double) * ((long)c->N * bs + 1));
             if (orc_dilu_setup(c->N, n, c->rp, c->col, c->val, c->rank, c->Einv)) { orc_amg_free(A); return NULL; }
@@ -762,7 +766,7 @@ static void smooth(oamg *A, olevel *c, const double *b, double *x)
 {
     int n = A->n;
     long m = (long)c->N * n;
-    if (A->smoother == 0) {
+    if (c->Dinv) {
         orc_bjacobi_sweep(c->N, n, c->rp, c->col, c->val, c->Dinv, b, x, c->r, A->omega);
         memcpy(x, c->r, sizeof(double) * m);
     } else {

@@ -488,6 +488,139 @@ __global__ void k_perm_vec(int32_t N, int n, const int32_t *__restrict__ ip, con
     else out[(int64_t)ip[i] * n + q] = in[g];
 }
 
+// ------------------------------------------------------------------ DILU setup
+// Colouring: Jones-Plassmann rounds with a fixed hash priority; a node whose
+// uncoloured neighbours all rank lower takes the smallest colour unused by
+// its coloured neighbours (first fit).  Nodes selected in one round are
+// never adjacent, so the result does not depend on scheduling.
+__device__ inline uint32_t mix32(uint32_t x) {
+    x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
+    return x;
+}
+__device__ inline bool outranks(int32_t j, int32_t i) {
+    const uint32_t hj = mix32((uint32_t)j), hi = mix32((uint32_t)i);
+    return hj > hi || (hj == hi && j > i);
+}
+
+__global__ void k_jp_select(int32_t N, const int32_t *rp, const int32_t *col, const int32_t *colour, int32_t *sel) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int32_t s = colour[i] < 0 ? 1 : 0;
+    for (int32_t k = rp[i]; s && k < rp[i + 1]; ++k) {
+        const int32_t j = col[k];
+        if (j != i && colour[j] < 0 && outranks(j, i)) s = 0;
+    }
+    sel[i] = s;
+}
+
+// counters[0]: nodes coloured, [1]: largest colour, [2]: colour overflow
+__global__ void k_jp_assign(int32_t N, const int32_t *rp, const int32_t *col, const int32_t *sel, int32_t *colour,
+                            int32_t *counters) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N || !sel[i]) return;
+    uint64_t m0 = 0, m1 = 0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int32_t j = col[k];
+        const int32_t cj = j == i ? -1 : colour[j];
+        if (cj >= 0 && cj < 64) m0 |= 1ull << cj;
+        else if (cj >= 64 && cj < 128) m1 |= 1ull << (cj - 64);
+    }
+    int32_t c;
+    if (~m0) c = __ffsll((long long)~m0) - 1;
+    else if (~m1) c = 64 + __ffsll((long long)~m1) - 1;
+    else { atomicOr(&counters[2], 1); c = 127; }
+    colour[i] = c;
+    atomicAdd(&counters[0], 1);
+    atomicMax(&counters[1], c);
+}
+
+// rows ordered by (colour, index): per-block colour histograms, a scan in
+// colour-major order, then in-block ranks
+constexpr int kColourBlock = 256;
+constexpr int kMaxColours = 128;
+
+__global__ __launch_bounds__(kColourBlock) void k_colour_hist(int32_t N, int32_t ncol, int32_t nblk,
+                                                              const int32_t *colour, int32_t *hist) {
+    __shared__ int32_t hsh[kMaxColours];
+    for (int c = threadIdx.x; c < kMaxColours; c += kColourBlock) hsh[c] = 0;
+    __syncthreads();
+    const int32_t i = blockIdx.x * kColourBlock + threadIdx.x;
+    if (i < N) atomicAdd(&hsh[colour[i]], 1);
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncol; c += kColourBlock) hist[(int64_t)c * nblk + blockIdx.x] = hsh[c];
+}
+
+__global__ __launch_bounds__(kColourBlock) void k_colour_place(int32_t N, int32_t nblk, const int32_t *colour,
+                                                               const int32_t *off, int32_t *rows) {
+    __shared__ int32_t sc[kColourBlock];
+    const int32_t i = blockIdx.x * kColourBlock + threadIdx.x;
+    sc[threadIdx.x] = i < N ? colour[i] : -1;
+    __syncthreads();
+    if (i >= N) return;
+    const int32_t c = sc[threadIdx.x];
+    int32_t rank = 0;
+    for (int t = 0; t < (int)threadIdx.x; ++t) rank += sc[t] == c ? 1 : 0;
+    rows[off[(int64_t)c * nblk + blockIdx.x] + rank] = i;
+}
+
+__global__ void k_colour_starts(int32_t ncol, int32_t nblk, const int32_t *off, int32_t *starts) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncol) starts[c] = off[(int64_t)c * nblk];
+}
+
+// E_i = A_ii - sum_{colour(j) < c} A_ij E_j^{-1} A_ji for the rows of colour c
+template <int n>
+__global__ void k_dilu_setup(const int32_t *rows, int32_t cnt, int c, const int32_t *rp, const int32_t *col,
+                             const int32_t *mirror, const int32_t *dslot, const double *val,
+                             const int32_t *colour, double *Einv, int32_t *bad) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= cnt) return;
+    constexpr int nn = n * n;
+    const int32_t i = rows[q];
+    double E[n][2 * n];
+    const double *Aii = val + (int64_t)dslot[i] * nn;
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+#pragma unroll
+        for (int cc = 0; cc < n; ++cc) E[r][cc] = Aii[r * n + cc];
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int32_t j = col[k];
+        if (j == i || colour[j] >= c) continue;
+        const double *Aij = val + (int64_t)k * nn, *Aji = val + (int64_t)mirror[k] * nn;
+        const double *Ej = Einv + (int64_t)j * nn;
+        double T[n][n];
+#pragma unroll
+        for (int r = 0; r < n; ++r)
+#pragma unroll
+            for (int cc = 0; cc < n; ++cc) {
+                double a = 0.0;
+#pragma unroll
+                for (int m = 0; m < n; ++m) a += Aij[r * n + m] * Ej[m * n + cc];
+                T[r][cc] = a;
+            }
+#pragma unroll
+        for (int r = 0; r < n; ++r)
+#pragma unroll
+            for (int cc = 0; cc < n; ++cc) {
+                double a = 0.0;
+#pragma unroll
+                for (int m = 0; m < n; ++m) a += T[r][m] * Aji[m * n + cc];
+                E[r][cc] -= a;
+            }
+    }
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+#pragma unroll
+        for (int cc = 0; cc < n; ++cc) E[r][n + cc] = (r == cc) ? 1.0 : 0.0;
+    const bool ok = gj_inverse<n>(E);
+    if (!ok) atomicMin(bad, i);
+    double *out = Einv + (int64_t)i * nn;
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+#pragma unroll
+        for (int cc = 0; cc < n; ++cc) out[r * n + cc] = ok ? E[r][n + cc] : 0.0;
+}
+
 }  // namespace
 
 // ====================================================================== host
@@ -527,6 +660,14 @@ void rap_n(int pass, int32_t nc, const int32_t *aptr, const int32_t *amem, const
         hipLaunchKernelGGL((k_rap<n, 0>), g, b, 0, st, nc, aptr, amem, rp, col, val, agg, cnt, rpc, colc, valc, flag);
     else
         hipLaunchKernelGGL((k_rap<n, 1>), g, b, 0, st, nc, aptr, amem, rp, col, val, agg, cnt, rpc, colc, valc, flag);
+}
+template <int n>
+void dilu_setup_n(const int32_t *rows, int32_t cnt, int c, const int32_t *rp, const int32_t *col, const int32_t *mirror,
+                  const int32_t *dslot, const double *val, const int32_t *colour, double *Einv, int32_t *bad,
+                  hipStream_t st) {
+    if (cnt > 0)
+        hipLaunchKernelGGL(k_dilu_setup<n>, dim3(cdiv(cnt, 128)), dim3(128), 0, st, rows, cnt, c, rp, col, mirror, dslot,
+                           val, colour, Einv, bad);
 }
 template <int n>
 void gather_blocks_n(int64_t nb, const int32_t *sk, const double *in, double *out, hipStream_t st) {
@@ -654,6 +795,66 @@ void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen) {
     }
     HIPCHK(hipStreamSynchronize(st));
     L.nc = nc;
+}
+
+// Multicolour ordering of level l (pattern only).
+void colour_level(cbs_system *h, int l) {
+    hipStream_t st = h->stream;
+    Level &L = h->lev[l];
+    const int32_t N = L.N;
+    const dim3 G(cdiv(N, 256)), B(256);
+    L.colour.alloc(N > 0 ? N : 1);
+    DArr<int32_t> sel(N > 0 ? N : 1), cnt(4);
+    hipLaunchKernelGGL(k_fill_int, G, B, 0, st, L.colour.get(), (int64_t)N, -1);
+    HIPCHK(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * 4, st));
+    int32_t done = 0;
+    for (int round = 0; done < N; ++round) {
+        if (round >= 4096) cbs_throw(CBS_ERR_HIP, "colouring did not finish");
+        hipLaunchKernelGGL(k_jp_select, G, B, 0, st, N, L.rp, L.col, L.colour.get(), sel.get());
+        hipLaunchKernelGGL(k_jp_assign, G, B, 0, st, N, L.rp, L.col, sel.get(), L.colour.get(), cnt.get());
+        LAUNCHCHK();
+        if (round % 4 == 3) done = read_int(cnt.get(), st);
+    }
+    int32_t hc[3];
+    HIPCHK(hipMemcpyAsync(hc, cnt.get(), sizeof(int32_t) * 3, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hc[2]) cbs_throw(CBS_ERR_ARG, "level " + std::to_string(l) + " needs more than 128 DILU colours; "
+                                      "lower dilu_levels");
+    const int32_t ncol = hc[1] + 1;
+    const int32_t nblk = (int32_t)cdiv(N, kColourBlock);
+    DArr<int32_t> hist((size_t)ncol * nblk + 1), starts(ncol + 1);
+    hipLaunchKernelGGL(k_colour_hist, dim3(nblk), dim3(kColourBlock), 0, st, N, ncol, nblk, L.colour.get(), hist.get());
+    LAUNCHCHK();
+    scan_exclusive(hist.get(), hist.get(), (int64_t)ncol * nblk, st);
+    L.rows_by_colour.alloc(N > 0 ? N : 1);
+    hipLaunchKernelGGL(k_colour_place, dim3(nblk), dim3(kColourBlock), 0, st, N, nblk, L.colour.get(), hist.get(),
+                       L.rows_by_colour.get());
+    hipLaunchKernelGGL(k_colour_starts, dim3(cdiv(ncol, 64)), dim3(64), 0, st, ncol, nblk, hist.get(), starts.get());
+    LAUNCHCHK();
+    L.colour_off.assign(ncol + 1, 0);
+    HIPCHK(hipMemcpyAsync(L.colour_off.data(), starts.get(), sizeof(int32_t) * ncol, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    L.colour_off[ncol] = N;
+}
+
+// E^{-1} of the DILU factorisation of level l, colour after colour (FP64).
+void dilu_factor_level(cbs_system *h, int l) {
+    hipStream_t st = h->stream;
+    Level &L = h->lev[l];
+    const int n = h->n;
+    L.Einv.ensure((size_t)L.N * n * n);
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0x7f, sizeof(int32_t), st));
+    const int ncol = (int)L.colour_off.size() - 1;
+    for (int c = 0; c < ncol; ++c) {
+        const int32_t b0 = L.colour_off[c], cnt = L.colour_off[c + 1] - b0;
+        NSWITCH(n, dilu_setup_n, L.rows_by_colour.get() + b0, cnt, c, L.rp, L.col, L.mirror, L.dslot, L.v64,
+                L.colour.get(), L.Einv.get(), h->dflag.get(), st);
+    }
+    LAUNCHCHK();
+    const int32_t bad = read_int(h->dflag.get(), st);
+    if (bad != 0x7f7f7f7f)
+        cbs_throw(CBS_ERR_SINGULAR, "singular DILU pivot at level " + std::to_string(l) + ", block row " +
+                                        std::to_string(bad));
 }
 
 // Sliced-ELL copy of a level for the solve phase (pattern kept on reuse).
@@ -812,7 +1013,13 @@ void amg_setup(cbs_system *h) {
     for (int q = 0; q < nlev; ++q) {
         Level &L = h->lev[q];
         nz_sum += L.nnzb;
-        if (q + 1 < nlev) {
+        const bool use_dilu = o.smoother == CBS_SMOOTH_DILU && (o.dilu_levels < 0 || q < o.dilu_levels);
+        if (q + 1 < nlev && use_dilu) {
+            L.dilu = true;
+            if (!reuse || !L.colour.get()) colour_level(h, q);
+            dilu_factor_level(h, q);
+        } else if (q + 1 < nlev) {
+            L.dilu = false;
             L.Dinv.ensure((size_t)L.N * n * n);
             blockinv_level(h, q, L.v64, L.Dinv.get());
         }
@@ -881,6 +1088,11 @@ void amg_build_transposed(cbs_system *h) {
         if (L.Dinv.get()) {
             L.DinvT.ensure((size_t)L.N * n * n);
             NSWITCH(n, transpose_n, (int64_t)L.N, nullptr, L.Dinv.get(), L.DinvT.get(), st);
+        }
+        if (L.dilu) {
+            // DILU of A^T in the same ordering has E' = E^T
+            L.EinvT.ensure((size_t)L.N * n * n);
+            NSWITCH(n, transpose_n, (int64_t)L.N, nullptr, L.Einv.get(), L.EinvT.get(), st);
         }
         LAUNCHCHK();
     }

@@ -136,6 +136,7 @@ void cbs_default_options(cbs_options *o) {
     o->reuse_aggregates = 0;
     o->check_every = 1;
     o->renumber = 1;
+    o->dilu_levels = 2;
 }
 
 int cbs_create_from_ldu(cbs_handle *out, int32_t n_cells, int32_t n_faces, int32_t bdim, const int32_t *lower_addr,
@@ -190,11 +191,11 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
         require(o.coarse_max >= 1 && o.max_levels >= 1 && o.match_passes >= 1, CBS_ERR_ARG,
                 "coarse_max, max_levels and match_passes must be >= 1");
         require(o.pre_sweeps >= 0 && o.post_sweeps >= 0, CBS_ERR_ARG, "sweeps must be >= 0");
-        if (o.smoother == CBS_SMOOTH_DILU) cbs_throw(CBS_ERR_ARG, "DILU smoother is not available in this build");
         const bool keep = o.reuse_aggregates && h->setup_done && h->opt.precision == o.precision &&
                           h->opt.precond == o.precond && h->opt.smoother == o.smoother &&
                           h->opt.coarse_max == o.coarse_max && h->opt.match_passes == o.match_passes &&
-                          h->opt.max_levels == o.max_levels;
+                          h->opt.max_levels == o.max_levels && h->opt.dilu_levels == o.dilu_levels &&
+                          h->opt.renumber == o.renumber;
         if (!keep) o.reuse_aggregates = 0;
         h->opt = o;
         HIPCHK(hipEventRecord(h->ev0, h->stream));

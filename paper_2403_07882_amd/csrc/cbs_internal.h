@@ -123,7 +123,9 @@ struct Level {
     std::vector<int64_t> sys_off;
     // smoother data (FP64 per the block-inversion rule)
     DArr<double> Dinv, DinvT;
-    // DILU: colour classes
+    // DILU: colour classes (rows of colour c: rows_by_colour[colour_off[c] ..
+    // colour_off[c+1])) and the FP64 inverses of the DILU diagonal E
+    bool dilu = false;
     DArr<int32_t> colour, rows_by_colour;
     std::vector<int32_t> colour_off;     // host, ncolours + 1
     DArr<double> Einv, EinvT;
@@ -224,6 +226,14 @@ template <typename TA, typename TB>
 void launch_cast(int64_t m, const TA *a, TB *b, hipStream_t st);
 void launch_coarse_solve(cbs_system *h, bool transposed, const void *b, void *x, bool fp32);
 void launch_block_apply(int n, int32_t N, const double *Dinv, const double *r, double *z, hipStream_t st);
+// DILU colour sweeps on the rows rows[0..cnt): forward y = E^{-1}(b - A x - L y)
+// (zero_guess: A x omitted), backward z = y - E^{-1} U z, x = x + z
+template <typename T>
+void launch_dilu_fwd(int n, const SellView &S, const T *val, const int32_t *colour, int c, const int32_t *rows,
+                     int32_t cnt, const double *Einv, const T *b, const T *x, T *y, bool zero_guess, hipStream_t st);
+template <typename T>
+void launch_dilu_bwd(int n, const SellView &S, const T *val, const int32_t *colour, int c, const int32_t *rows,
+                     int32_t cnt, const double *Einv, T *yz, T *x, bool zero_guess, hipStream_t st);
 
 // AMG setup (amg.hip)
 void amg_setup(cbs_system *h);

@@ -399,6 +399,22 @@ const double *level_vals<double>(Level &L, bool tr) { return tr ? L.sell.v64T.ge
 template <>
 const float *level_vals<float>(Level &L, bool tr) { return tr ? L.sell.v32T.get() : L.sell.v32.get(); }
 
+// One DILU smoothing step x <- x + M^{-1}(b - A x) (zero_guess: x <- M^{-1} b).
+template <typename T>
+void dilu_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x, bool zero_guess) {
+    const T *val = level_vals<T>(L, tr);
+    const double *Einv = tr ? L.EinvT.get() : L.Einv.get();
+    T *y = vptr<T>(L.vt);
+    const int ncol = (int)L.colour_off.size() - 1;
+    const SellView S = L.sell.view();
+    for (int c = 0; c < ncol; ++c)
+        launch_dilu_fwd<T>(h->n, S, val, L.colour.get(), c, L.rows_by_colour.get() + L.colour_off[c],
+                           L.colour_off[c + 1] - L.colour_off[c], Einv, b, x, y, zero_guess, h->stream);
+    for (int c = ncol - 1; c >= 0; --c)
+        launch_dilu_bwd<T>(h->n, S, val, L.colour.get(), c, L.rows_by_colour.get() + L.colour_off[c],
+                           L.colour_off[c + 1] - L.colour_off[c], Einv, y, x, zero_guess, h->stream);
+}
+
 // x = V(b) with zero initial guess on level l; the result lands in x.
 template <typename T>
 void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
@@ -416,6 +432,18 @@ void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
     T *tmp = vptr<T>(L.vt);
     T *r = vptr<T>(L.vr);
     const int nu1 = std::max(0, o.pre_sweeps), nu2 = std::max(0, o.post_sweeps);
+    if (L.dilu) {
+        for (int s = 0; s < nu1; ++s) dilu_smooth<T>(h, L, tr, b, x, s == 0);
+        if (nu1 == 0) launch_fill<T>((int64_t)L.N * n, x, st);
+        launch_rows<T, T>(1, n, L.sell.view(), val, x, b, r, nullptr, 0.0, st);
+        Level &C = h->lev[l + 1];
+        T *bc = vptr<T>(C.vb), *xc = vptr<T>(C.vx);
+        launch_restrict<T>(n, C.N, L.agg_ptr.get(), L.agg_mem.get(), r, bc, st);
+        vcycle<T>(h, tr, l + 1, bc, xc);
+        launch_prolong<T>(n, L.N, L.agg.get(), xc, x, st);
+        for (int s = 0; s < nu2; ++s) dilu_smooth<T>(h, L, tr, b, x, false);
+        return;
+    }
     const int switches = (nu1 >= 1 ? nu1 - 1 : 0) + nu2;
     T *cur = (switches % 2 == 0) ? x : tmp;
     T *oth = (cur == x) ? tmp : x;

@@ -397,3 +397,69 @@ def test_batched_fgmres_and_zero_system():
     xn = _np(x)
     assert stats[1]["iterations"] == 0 and np.all(xn[cat["cell_off"][1]:] == 0)
     assert O.relres(O.from_system(systems[0]), systems[0]["b"], xn[:cat["cell_off"][1]]) <= 1e-9
+
+
+# ------------------------------------------------------------------ DILU
+def _ranks_from_colour(colour):
+    """DILU order of a multicolour sweep: colour first, then row index."""
+    N = colour.size
+    key = colour.astype(np.int64) * N + np.arange(N)
+    rank = np.empty(N, np.int32)
+    rank[np.argsort(key, kind="stable")] = np.arange(N)
+    return rank
+
+
+@pytest.mark.parametrize("dilu_levels", [1, 2, -1])
+def test_dilu_vcycle_matches_oracle_given_gpu_hierarchy(dilu_levels):
+    _say("dilu vcycle", dilu_levels)
+    s = pressure_velocity(10, 9, 8, seed=4)
+    A = O.from_system(s)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, smoother=P.SMOOTH_DILU, dilu_levels=dilu_levels, coarse_max=8,
+                   pre_sweeps=1, post_sweeps=1, omega=0.8)
+        nlev = sysm.info()["levels"]
+        lv0 = sysm.get_level(0)
+        order = _np(lv0["order"])
+        A0 = O.BCSR(A.N, 4, _np(lv0["row_ptr"]), _np(lv0["col"]), _np(lv0["vals"]))
+        aggs, ranks = [], []
+        ndilu = nlev - 1 if dilu_levels < 0 else min(dilu_levels, nlev - 1)
+        for l in range(nlev - 1):
+            lv = sysm.get_level(l)
+            aggs.append(_np(lv["agg"]))
+            colour = _np(lv["colour"])
+            if l < ndilu:
+                assert colour.min() >= 0
+                # a proper colouring: no two neighbours share a colour
+                rp, col = _np(lv["row_ptr"]), _np(lv["col"])
+                rows = np.repeat(np.arange(lv["N"]), np.diff(rp))
+                off = rows != col
+                assert np.all(colour[rows[off]] != colour[col[off]])
+                ranks.append(_ranks_from_colour(colour))
+        amg = O.AMG(A0, nu1=1, nu2=1, omega=0.8, aggs=aggs, smoother=O.SMOOTH_DILU, ranks=ranks,
+                    dilu_levels=ndilu)
+        r = np.random.default_rng(0).standard_normal((A.N, 4))
+        z = _np(sysm.apply_precond(r))
+    zr_int = amg.apply(r[order])
+    zr = np.empty_like(zr_int); zr[order] = zr_int
+    assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+
+
+@pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
+def test_dilu_amg_solve_and_transpose(precision):
+    _say("dilu solve", precision)
+    s = pressure_velocity(16, 16, 16, seed=0)
+    A = O.from_system(s)
+    xref = _ref_solution(A, s["b"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, smoother=P.SMOOTH_DILU, precision=precision, tol=1e-10)
+        x, st = sysm.solve(s["b"])
+        assert st["status"] == P.OK, st
+        _check_solution(A, s["b"], _np(x), xref, tol=1e-10, err=1e-7)
+        with P.System.from_dict(s) as bj:
+            bj.setup(precond=P.PREC_AMG, smoother=P.SMOOTH_BJACOBI, precision=precision, tol=1e-10)
+            _, stb = bj.solve(s["b"])
+        assert st["iterations"] < stb["iterations"]          # DILU smooths better than block Jacobi
+        c = np.random.default_rng(1).standard_normal((A.N, 4))
+        lam, stt = sysm.solve_transpose(c)
+        assert stt["status"] == P.OK
+        assert O.relres(O.transpose(A), c, _np(lam)) <= 1e-10 * 1.0001
