@@ -34,6 +34,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, nargs=3, default=[48, 48, 48])
     ap.add_argument("--spmv-reps", type=int, default=50)
+    ap.add_argument("--smoother", choices=["dilu", "bjacobi"], default="bjacobi")
+    ap.add_argument("--dilu-levels", type=int, default=2)
+    ap.add_argument("--sweeps", type=int, default=2)
+    ap.add_argument("--omega", type=float, default=0.9)
+    ap.add_argument("--coarse-max", type=int, default=16)
+    ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--solver", choices=["bicgstab", "fgmres"], default="bicgstab")
+    ap.add_argument("--skip-fp64", action="store_true")
     return ap.parse_args()
 
 
@@ -99,10 +107,13 @@ def main():
     del s
     sysm = P.System(N, n, la, ua, diag, upper, lower)
     nnzb = sysm.info()["nnzb"]
-    opt_mixed = P.default_options(precision=P.PRECISION_MIXED, solver=P.SOLVER_BICGSTAB,
-                                  precond=P.PREC_AMG, tol=1e-8, max_iter=500)
-    opt_fp64 = P.default_options(precision=P.PRECISION_FP64, solver=P.SOLVER_BICGSTAB,
-                                 precond=P.PREC_AMG, tol=1e-8, max_iter=500)
+    common = dict(solver=P.SOLVER_BICGSTAB if args.solver == "bicgstab" else P.SOLVER_FGMRES,
+                  precond=P.PREC_AMG, tol=1e-8, max_iter=500,
+                  smoother=P.SMOOTH_DILU if args.smoother == "dilu" else P.SMOOTH_BJACOBI,
+                  dilu_levels=args.dilu_levels, pre_sweeps=args.sweeps, post_sweeps=args.sweeps,
+                  omega=args.omega, coarse_max=args.coarse_max, match_passes=args.passes)
+    opt_mixed = P.default_options(precision=P.PRECISION_MIXED, **common)
+    opt_fp64 = P.default_options(precision=P.PRECISION_FP64, **common)
 
     def step(opt):
         sysm.update_values(diag, upper, lower)
@@ -122,19 +133,22 @@ def main():
         stats.append(st)
     torch.cuda.synchronize()
     t_mixed = (time.perf_counter() - t0) / args.steps * 1e3
-    log("mixed: %.2f ms/step, iterations %d, relres %.3e" % (t_mixed, st["iterations"], st["rel_res_true"]))
+    log("mixed: %.2f ms/step, iterations %d, relres %.3e, setup %.2f ms, solve %.2f ms"
+        % (t_mixed, st["iterations"], st["rel_res_true"], st["t_setup_ms"], st["t_solve_ms"]))
 
     # plain FP64 GPU path on the same system
-    for _ in range(max(1, args.warmup // 2)):
-        step(opt_fp64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    k64 = max(1, args.steps // 2)
-    for _ in range(k64):
-        _, st64, _ = step(opt_fp64)
-    torch.cuda.synchronize()
-    t_fp64 = (time.perf_counter() - t0) / k64 * 1e3
-    log("fp64: %.2f ms/step, iterations %d" % (t_fp64, st64["iterations"]))
+    t_fp64, st64 = float("nan"), {"iterations": -1}
+    if not args.skip_fp64:
+        for _ in range(max(1, args.warmup // 2)):
+            step(opt_fp64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k64 = max(1, args.steps // 2)
+        for _ in range(k64):
+            _, st64, _ = step(opt_fp64)
+        torch.cuda.synchronize()
+        t_fp64 = (time.perf_counter() - t0) / k64 * 1e3
+        log("fp64: %.2f ms/step, iterations %d" % (t_fp64, st64["iterations"]))
 
     # dominant bandwidth kernel: FP64 block SpMV, timed with events on its
     # stream (torch's current stream, which the library was given).
@@ -189,7 +203,10 @@ def main():
         "config": {"workload": "pressure-based coupled p-U 4x4, %dx%dx%d jittered hex mesh, cells "
                                "randomly renumbered (N=%d, F=%d, nnzb=%d); mixed AMG-BiCGStab to 1e-8"
                                % (nx, ny, nz, N, F, nnzb),
-                   "step": "update_values + setup + solve"},
+                   "step": "update_values + setup + solve",
+                   "solver": args.solver, "smoother": args.smoother, "dilu_levels": args.dilu_levels,
+                   "sweeps": args.sweeps, "omega": args.omega, "coarse_max": args.coarse_max,
+                   "match_passes": args.passes},
         "iterations": st["iterations"],
         "rel_res_true": st["rel_res_true"],
         "levels": st["levels"],
@@ -199,7 +216,7 @@ def main():
         "convert_ms": round(st["t_convert_ms"], 3),
         "fp64_ms_per_step": round(t_fp64, 3),
         "fp64_iterations": st64["iterations"],
-        "mixed_vs_fp64_speedup": round(t_fp64 / t_mixed, 3),
+        "mixed_vs_fp64_speedup": round(t_fp64 / t_mixed, 3) if t_fp64 == t_fp64 else None,
         "roofline": {"bound": "hbm", "kernel": "block SpMV FP64 (k_rows mode 0, n=4), internal numbering",
                      "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,

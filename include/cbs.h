@@ -67,9 +67,9 @@ typedef struct cbs_options {
     int32_t restart;         /* FGMRES restart length m              [30] */
     int32_t precond;         /* CBS_PREC_*                           [AMG] */
     int32_t smoother;        /* CBS_SMOOTH_* (AMG levels)            [BJACOBI] */
-    int32_t pre_sweeps;      /* smoothing sweeps before coarse corr. [1] */
-    int32_t post_sweeps;     /* smoothing sweeps after coarse corr.  [1] */
-    double omega;            /* block-Jacobi damping                 [0.8] */
+    int32_t pre_sweeps;      /* smoothing sweeps before coarse corr. [2] */
+    int32_t post_sweeps;     /* smoothing sweeps after coarse corr.  [2] */
+    double omega;            /* block-Jacobi damping                 [0.9] */
     double tol;              /* stop at ||b - A x||_2 / ||b||_2 <= tol [1e-8] */
     int32_t max_iter;        /* outer Krylov iteration cap           [500] */
     int32_t precision;       /* CBS_PRECISION_*: MIXED = FP32 hierarchy and

@@ -722,7 +722,6 @@ void build_members(cbs_system *h, int32_t N, const int32_t *agg, int32_t nc, DAr
     hipLaunchKernelGGL(k_fill_members, dim3(cdiv(N, 256)), dim3(256), 0, st, N, agg, fill.get(), amem.get());
     hipLaunchKernelGGL(k_sort_members, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, aptr.get(), amem.get());
     LAUNCHCHK();
-    HIPCHK(hipStreamSynchronize(st));
 }
 
 // Galerkin pattern + values of the next level.  n_blk = block size of `val`.
@@ -793,7 +792,6 @@ void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen) {
         agg1 = std::move(a);
         nc = nc2;
     }
-    HIPCHK(hipStreamSynchronize(st));
     L.nc = nc;
 }
 
@@ -907,6 +905,7 @@ void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv) {
 // Build (or, with reuse, refresh) the hierarchy.
 void amg_setup(cbs_system *h) {
     hipStream_t st = h->stream;
+    PhaseTimer pt(st, "setup");
     const cbs_options &o = h->opt;
     const int n = h->n;
     const bool mixed = o.precision == CBS_PRECISION_MIXED;
@@ -930,6 +929,7 @@ void amg_setup(cbs_system *h) {
         refresh_level0_values(h);
     }
     L0.sys_off = h->cell_off;
+    pt.mark("level0");
 
     if (!amg) {
         // block-Jacobi preconditioner: level-0 block inverses only
@@ -959,6 +959,7 @@ void amg_setup(cbs_system *h) {
         if (!last && !(reuse && L.agg.get() && (int)h->lev.size() > l + 1)) {
             HIPCHK(hipMemcpyAsync(frozen.get(), hfrozen.data(), sizeof(int32_t) * h->n_sys, hipMemcpyHostToDevice, st));
             aggregate_level(h, L, frozen.get());
+            pt.mark("agg" + std::to_string(l));
             // stall test over the systems still coarsening (frozen rows map 1:1)
             int64_t n_frozen = 0;
             for (int s = 0; s < h->n_sys; ++s)
@@ -989,6 +990,7 @@ void amg_setup(cbs_system *h) {
                 LAUNCHCHK();
                 if (read_int(h->dflag.get(), st) & 16) cbs_throw(CBS_ERR_PATTERN, "coarse pattern is not symmetric");
                 C.sys_off = level_sys_off(h, C);
+                pt.mark("rap" + std::to_string(l));
                 continue;
             }
         } else if (!last) {
@@ -1007,6 +1009,7 @@ void amg_setup(cbs_system *h) {
     }
     const int nlev = (int)h->lev.size();
     if (!reuse && o.renumber && nlev > 1) renumber_hierarchy(h);
+    pt.mark("renumber");
 
     // smoothers (FP64 inverses), FP32 copies, vectors
     int64_t nz_sum = 0;
@@ -1023,8 +1026,10 @@ void amg_setup(cbs_system *h) {
             L.Dinv.ensure((size_t)L.N * n * n);
             blockinv_level(h, q, L.v64, L.Dinv.get());
         }
+        pt.mark("smoother" + std::to_string(q));
         if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, reuse);
         alloc_level_vectors(h, L, mixed);
+        pt.mark("sell" + std::to_string(q));
     }
     h->op_complexity = (double)nz_sum / (double)h->nnzb;
 
@@ -1061,6 +1066,7 @@ void amg_setup(cbs_system *h) {
             C.inv.get(), C.invT.get(), h->dflag.get(), st);
     LAUNCHCHK();
     if (read_int(h->dflag.get(), st) & 32) cbs_throw(CBS_ERR_SINGULAR, "coarsest-level matrix is singular");
+    pt.mark("coarse");
 }
 
 // Transposed level values for the adjoint solve: A^T(i,j) = A(j,i)^T through
@@ -1156,7 +1162,6 @@ void renumber_hierarchy(cbs_system *h) {
         L.row_sys = std::move(rsn);
         L.order = std::move(ip);
     }
-    HIPCHK(hipStreamSynchronize(st));
     h->renumbered = true;
 }
 

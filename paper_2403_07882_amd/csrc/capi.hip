@@ -7,6 +7,8 @@
 #include "cbs_internal.h"
 
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -79,6 +81,7 @@ int create_common(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const
     require(N + 2 * F < (int64_t)INT32_MAX, CBS_ERR_ARG, "too many blocks for 32-bit block indices");
     require(diag != nullptr, CBS_ERR_ARG, "diag is NULL");
     require(F == 0 || (la && ua && upper && lower), CBS_ERR_ARG, "face arrays are NULL");
+    set_alloc_stream((hipStream_t)stream);
     std::unique_ptr<cbs_system> h(new cbs_system());
     h->N = (int32_t)N; h->F = (int32_t)F; h->n = bdim; h->n_sys = n_sys;
     h->stream = (hipStream_t)stream;
@@ -107,6 +110,67 @@ int create_common(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const
 
 [[noreturn]] void cbs_throw(int code, const std::string &msg) { throw CbsError{code, msg}; }
 
+// ------------------------------------------------------------------ memory
+namespace {
+thread_local hipStream_t g_alloc_stream = nullptr;
+thread_local int g_pool_device = -1;
+
+void ensure_pool() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    if (g_pool_device == dev) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;     // keep freed memory in the pool
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+    g_pool_device = dev;
+}
+}  // namespace
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+PhaseTimer::PhaseTimer(hipStream_t s, const char *w) : st(s), what(w) {
+    const char *e = getenv("CBS_PROFILE");
+    on = e && e[0] == '1';
+    t0 = last = on ? now_ms() : 0.0;
+}
+
+void PhaseTimer::mark(const std::string &name) {
+    if (!on) return;
+    (void)hipStreamSynchronize(st);
+    const double t = now_ms();
+    marks.emplace_back(name, t - last);
+    last = t;
+}
+
+PhaseTimer::~PhaseTimer() {
+    if (!on) return;
+    std::string line = "[cbs] " + what + " total " + std::to_string(last - t0) + " ms:";
+    for (auto &m : marks) line += " " + m.first + "=" + std::to_string(m.second).substr(0, 6);
+    fprintf(stderr, "%s\n", line.c_str());
+}
+
+hipStream_t alloc_stream() { return g_alloc_stream; }
+void set_alloc_stream(hipStream_t st) { g_alloc_stream = st; }
+
+void *dev_alloc(size_t bytes) {
+    ensure_pool();
+    void *q = nullptr;
+    if (hipMallocAsync(&q, bytes, g_alloc_stream) != hipSuccess || !q) {
+        (void)hipGetLastError();
+        cbs_throw(CBS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return q;
+}
+
+void dev_free(void *p) {
+    if (p) (void)hipFreeAsync(p, g_alloc_stream);
+}
+
 cbs_system::~cbs_system() {
     if (stream) (void)hipStreamSynchronize(stream);
     else (void)hipDeviceSynchronize();
@@ -124,9 +188,9 @@ void cbs_default_options(cbs_options *o) {
     o->restart = 30;
     o->precond = CBS_PREC_AMG;
     o->smoother = CBS_SMOOTH_BJACOBI;
-    o->pre_sweeps = 1;
-    o->post_sweeps = 1;
-    o->omega = 0.8;
+    o->pre_sweeps = 2;
+    o->post_sweeps = 2;
+    o->omega = 0.9;
     o->tol = 1e-8;
     o->max_iter = 500;
     o->precision = CBS_PRECISION_FP64;
@@ -161,6 +225,7 @@ int cbs_create_batch_from_ldu(cbs_handle *out, int32_t n_sys, const int64_t *cel
 int cbs_update_values(cbs_handle h, const double *diag, const double *upper, const double *lower) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        set_alloc_stream(h->stream);
         require(diag != nullptr && (h->F == 0 || (upper && lower)), CBS_ERR_ARG, "value arrays are NULL");
         HIPCHK(hipEventRecord(h->ev0, h->stream));
         convert_values(h, diag, upper, lower);
@@ -179,6 +244,7 @@ int cbs_update_values(cbs_handle h, const double *diag, const double *upper, con
 int cbs_setup(cbs_handle h, const cbs_options *opt) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        set_alloc_stream(h->stream);
         cbs_options o;
         if (opt) o = *opt; else cbs_default_options(&o);
         require(o.solver == CBS_SOLVER_BICGSTAB || o.solver == CBS_SOLVER_FGMRES, CBS_ERR_ARG, "unknown solver");
@@ -214,6 +280,7 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
 int cbs_solve(cbs_handle h, const double *b, double *x, cbs_stats *st) {
     return guarded([&] {
         require(h != nullptr && b != nullptr && x != nullptr, CBS_ERR_ARG, "NULL argument");
+        set_alloc_stream(h->stream);
         require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
         check_finite(x, (int64_t)h->N * h->n, h->dflag.get(), h->stream);
         return krylov_solve(h, b, x, st, false);
@@ -223,6 +290,7 @@ int cbs_solve(cbs_handle h, const double *b, double *x, cbs_stats *st) {
 int cbs_solve_transpose(cbs_handle h, const double *g, double *lambda, cbs_stats *st) {
     return guarded([&] {
         require(h != nullptr && g != nullptr && lambda != nullptr, CBS_ERR_ARG, "NULL argument");
+        set_alloc_stream(h->stream);
         require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
         check_finite(lambda, (int64_t)h->N * h->n, h->dflag.get(), h->stream);
         return krylov_solve(h, g, lambda, st, true);
@@ -232,6 +300,7 @@ int cbs_solve_transpose(cbs_handle h, const double *g, double *lambda, cbs_stats
 int cbs_gradient(cbs_handle h, const double *lambda, const double *x, double *gd, double *gu, double *gl) {
     return guarded([&] {
         require(h != nullptr && lambda && x && gd && (h->F == 0 || (gu && gl)), CBS_ERR_ARG, "NULL argument");
+        set_alloc_stream(h->stream);
         gradient(h, lambda, x, gd, gu, gl);
         HIPCHK(hipStreamSynchronize(h->stream));
         return CBS_OK;
@@ -241,6 +310,7 @@ int cbs_gradient(cbs_handle h, const double *lambda, const double *x, double *gd
 int cbs_spmv(cbs_handle h, const double *x, double *y, int32_t transpose) {
     return guarded([&] {
         require(h != nullptr && x && y, CBS_ERR_ARG, "NULL argument");
+        set_alloc_stream(h->stream);
         spmv_user(h, x, y, transpose != 0);
         return CBS_OK;
     });
@@ -249,6 +319,7 @@ int cbs_spmv(cbs_handle h, const double *x, double *y, int32_t transpose) {
 int cbs_apply_precond(cbs_handle h, const double *r, double *z) {
     return guarded([&] {
         require(h != nullptr && r && z, CBS_ERR_ARG, "NULL argument");
+        set_alloc_stream(h->stream);
         require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
         if (h->renumbered) {
             const int64_t m = (int64_t)h->N * h->n;
@@ -284,6 +355,7 @@ int cbs_get_info(cbs_handle h, int32_t *n_cells, int32_t *n_faces, int32_t *bdim
                  int32_t *n_sys) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        set_alloc_stream(h->stream);
         if (n_cells) *n_cells = h->N;
         if (n_faces) *n_faces = h->F;
         if (bdim) *bdim = h->n;
@@ -298,6 +370,7 @@ int cbs_get_bcsr(cbs_handle h, int32_t *row_ptr, int32_t *col, double *vals, int
                  int32_t *lower_slot) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        set_alloc_stream(h->stream);
         hipStream_t st = h->stream;
         const size_t bs = (size_t)h->n * h->n;
         if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, h->rp.get(), sizeof(int32_t) * (h->N + 1), hipMemcpyDeviceToDevice, st));
@@ -317,6 +390,7 @@ int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows, int64_t *nnzb, i
                   double *vals, int32_t *agg, int32_t *colour, int32_t *order) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        set_alloc_stream(h->stream);
         require(h->setup_done, CBS_ERR_STATE, "no hierarchy before cbs_setup");
         require(level >= 0 && level < (int32_t)h->lev.size(), CBS_ERR_ARG, "level out of range");
         Level &L = h->lev[level];
@@ -347,6 +421,7 @@ int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows, int64_t *nnzb, i
 
 int cbs_destroy(cbs_handle h) {
     return guarded([&] {
+        if (h) set_alloc_stream(h->stream);
         delete h;
         return CBS_OK;
     });

@@ -27,7 +27,16 @@ struct CbsError {
 #define LAUNCHCHK() HIPCHK(hipGetLastError())
 
 // ---------------------------------------------------------------- memory
-// Owning device array (hipMalloc / hipFree).  Move-only.
+// Device memory comes from the device's stream-ordered pool (hipMallocAsync /
+// hipFreeAsync on the stream of the handle being worked on), with a release
+// threshold that keeps freed blocks in the pool: setup can allocate and
+// free its temporaries without synchronising the device.
+hipStream_t alloc_stream();
+void set_alloc_stream(hipStream_t st);
+void *dev_alloc(size_t bytes);
+void dev_free(void *p);
+
+// Owning device array.  Move-only.
 template <typename T>
 struct DArr {
     T *p = nullptr;
@@ -44,20 +53,13 @@ struct DArr {
     ~DArr() { release(); }
     void alloc(size_t count) {
         release();
-        if (count) {
-            void *q = nullptr;
-            if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
-                (void)hipGetLastError();
-                cbs_throw(CBS_ERR_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-            }
-            p = static_cast<T *>(q);
-        }
+        if (count) p = static_cast<T *>(dev_alloc(count * sizeof(T)));
         n = count;
     }
     // allocate only when the current buffer is too small
     void ensure(size_t count) { if (n < count) alloc(count); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p);
         p = nullptr; n = 0;
     }
     T *get() const { return p; }
@@ -195,6 +197,19 @@ struct cbs_system {
 
 // ---------------------------------------------------------------- helpers
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Phase timers for setup and solve, printed to stderr when the environment
+// sets CBS_PROFILE=1 (each mark synchronises the stream, so only then).
+struct PhaseTimer {
+    bool on;
+    hipStream_t st;
+    double t0, last;
+    std::vector<std::pair<std::string, double>> marks;
+    PhaseTimer(hipStream_t s, const char *what);
+    void mark(const std::string &name);
+    ~PhaseTimer();
+    std::string what;
+};
 
 // exclusive scan of n int32 counts into out[0..n] (out[n] = total); in may alias out
 void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, hipStream_t st);

@@ -87,8 +87,6 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, hipStream_t st) 
     scan_exclusive(bsum.get(), bsum.get(), nb, st);   // bsum[0..nb], bsum[nb] = total
     hipLaunchKernelGGL(k_scan_add, dim3(cdiv(n, 256)), dim3(256), 0, st, out, n, bsum.get(), (int32_t)nb);
     LAUNCHCHK();
-    // keep bsum alive until the kernels consuming it have run
-    HIPCHK(hipStreamSynchronize(st));
 }
 
 int32_t read_int(const int32_t *dptr, hipStream_t st) {
