@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mesh", type=int, nargs=3, default=[100, 100, 100])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, nargs=3, default=[48, 48, 48])
+    ap.add_argument("--cpu-sample", type=int, nargs=3, default=[80, 80, 80])
     ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--smoother", choices=["dilu", "bjacobi"], default="bjacobi")
     ap.add_argument("--dilu-levels", type=int, default=2)
@@ -61,7 +61,7 @@ def cpu_baseline(shape):
     s = pressure_velocity(*shape, seed=0)
     A = O.from_system(s)
     t0 = time.perf_counter()
-    amg = O.AMG(A, coarse_max=16, passes=2, smoother=O.SMOOTH_BJACOBI, nu1=1, nu2=1, omega=0.8)
+    amg = O.AMG(A, coarse_max=16, passes=2, smoother=O.SMOOTH_BJACOBI, nu1=2, nu2=2, omega=0.9)
     x, st = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=amg, tol=1e-8, maxit=500)
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -70,7 +70,7 @@ def cpu_baseline(shape):
         "unit": "ms per 1M-cell solve (scaled)",
         "cores": threads,
         "kind": "oracle",
-        "sample": "oracle AMG(block-Jacobi V(1,1))-BiCGStab FP64 setup+solve to 1e-8 on the same "
+        "sample": "oracle AMG(block-Jacobi V(2,2), omega 0.9)-BiCGStab FP64 setup+solve to 1e-8 on the same "
                   "pressure-velocity construction at %dx%dx%d (%d cells, %d iterations, %.2f s), "
                   "scaled linearly to 1M cells" % (*shape, s["N"], st["iterations"], dt),
         "measured_s": dt,

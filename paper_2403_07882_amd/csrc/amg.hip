@@ -25,7 +25,7 @@ void build_row_sys(cbs_system *h, Level &L0);
 namespace {
 
 constexpr int kRapWaves = 4;
-constexpr int kRapCap = 1024;     // candidate blocks gathered per coarse row
+constexpr int kRapCap = 4096;     // largest candidate list a coarse row may gather
 constexpr int kMatchRounds = 4;
 
 // ------------------------------------------------------------------ block inverse
@@ -231,8 +231,27 @@ __global__ void k_sort_members(int32_t nc, const int32_t *aptr, int32_t *mem) {
 // ------------------------------------------------------------------ Galerkin RAP
 // pass 0: cnt[I] = number of distinct coarse columns of coarse row I
 // pass 1: colc / valc of coarse row I at rpc[I] (columns ascending)
+// One wavefront per coarse row: the candidate blocks (coarse column J of
+// every block of every member row) are gathered into LDS, duplicates are
+// marked (top bit of the slot), every candidate learns the rank d of its
+// column among the distinct ones, and the n*n sums of each distinct column
+// are spread over the lanes (coalesced block reads).  Each sum runs over
+// the candidates in gather order: members ascending, then row slots, the
+// order of the CPU reference.
+// Candidate count of a coarse row: the blocks of all its member rows.
+__global__ void k_rap_maxc(int32_t nc, const int32_t *aptr, const int32_t *amem, const int32_t *rp, int32_t *maxc) {
+    const int32_t I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nc) return;
+    int32_t c = 0;
+    for (int32_t m = aptr[I]; m < aptr[I + 1]; ++m) c += rp[amem[m] + 1] - rp[amem[m]];
+    atomicMax(maxc, c);
+}
+
+// LDS per wavefront: cap entries of column, slot and rank (cap = the
+// level's largest candidate count, rounded up), so light levels keep many
+// wavefronts resident.
 template <int n, int PASS>
-__global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, const int32_t *__restrict__ aptr,
+__global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, int32_t cap, const int32_t *__restrict__ aptr,
                                                         const int32_t *__restrict__ amem,
                                                         const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col,
@@ -241,11 +260,13 @@ __global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, const int32_
                                                         const int32_t *__restrict__ rpc, int32_t *colc,
                                                         double *valc, int32_t *flag) {
     constexpr int nn = n * n;
-    __shared__ int32_t sJ[kRapWaves][kRapCap];
-    __shared__ int32_t sK[kRapWaves][kRapCap];
-    __shared__ int32_t sF[kRapWaves][kRapCap];
+    constexpr uint32_t kFirst = 0x80000000u;
+    extern __shared__ int32_t rap_lds[];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t I = blockIdx.x * kRapWaves + w;
+    int32_t *sJw = rap_lds + (size_t)w * 3 * cap;
+    uint32_t *sKw = reinterpret_cast<uint32_t *>(sJw + cap);
+    int32_t *sDw = sJw + 2 * cap;
+    const int32_t I = blockIdx.x * (int32_t)(blockDim.x >> 6) + w;
     const bool active = I < nc;
     int32_t c = 0;
     if (active) {
@@ -254,50 +275,47 @@ __global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, const int32_
             const int32_t kb = rp[i], len = rp[i + 1] - kb;
             for (int32_t e = lane; e < len; e += 64) {
                 const int32_t q = c + e;
-                if (q < kRapCap) { sJ[w][q] = agg[col[kb + e]]; sK[w][q] = kb + e; }
+                if (q < cap) { sJw[q] = agg[col[kb + e]]; sKw[q] = (uint32_t)(kb + e); }
             }
             c += len;
         }
-        if (c > kRapCap && lane == 0) atomicOr(flag, 8);
+        if (c > cap && lane == 0) atomicOr(flag, 8);
     }
     __syncthreads();
-    const int32_t cc = active ? min(c, kRapCap) : 0;
+    const int32_t cc = active ? min(c, cap) : 0;
     for (int32_t q = lane; q < cc; q += 64) {
-        const int32_t J = sJ[w][q];
-        int f = 1;
+        const int32_t J = sJw[q];
+        bool f = true;
         for (int32_t p = 0; p < q; ++p)
-            if (sJ[w][p] == J) { f = 0; break; }
-        sF[w][q] = f;
+            if (sJw[p] == J) { f = false; break; }
+        if (f) sKw[q] |= kFirst;
     }
     __syncthreads();
     if (PASS == 0) {
         int32_t d = 0;
-        for (int32_t q = lane; q < cc; q += 64) d += sF[w][q];
+        for (int32_t q = lane; q < cc; q += 64) d += (sKw[q] & kFirst) ? 1 : 0;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
         if (active && lane == 0) cnt[I] = d;
         return;
     }
-    if (!active) return;
-    const int32_t base = rpc[I];
+    const int32_t base = active ? rpc[I] : 0;
     for (int32_t q = lane; q < cc; q += 64) {
-        if (!sF[w][q]) continue;
-        const int32_t J = sJ[w][q];
-        int32_t rank = 0;
-        for (int32_t p = 0; p < cc; ++p) rank += (sF[w][p] && sJ[w][p] < J) ? 1 : 0;
-        double acc[nn];
-#pragma unroll
-        for (int e = 0; e < nn; ++e) acc[e] = 0.0;
-        for (int32_t p = q; p < cc; ++p) {
-            if (sJ[w][p] != J) continue;
-            const double *B = val + (int64_t)sK[w][p] * nn;
-#pragma unroll
-            for (int e = 0; e < nn; ++e) acc[e] += B[e];
-        }
-        colc[base + rank] = J;
-        double *out = valc + (int64_t)(base + rank) * nn;
-#pragma unroll
-        for (int e = 0; e < nn; ++e) out[e] = acc[e];
+        const int32_t J = sJw[q];
+        int32_t d = 0;
+        for (int32_t p = 0; p < cc; ++p) d += ((sKw[p] & kFirst) && sJw[p] < J) ? 1 : 0;
+        sDw[q] = d;
+        if (sKw[q] & kFirst) colc[base + d] = J;
+    }
+    __syncthreads();
+    if (!active) return;
+    const int32_t nd = rpc[I + 1] - base;
+    for (int32_t t = lane; t < nd * nn; t += 64) {
+        const int32_t d = t / nn, e = t - d * nn;
+        double acc = 0.0;
+        for (int32_t q = 0; q < cc; ++q)
+            if (sDw[q] == d) acc += val[(int64_t)(sKw[q] & ~kFirst) * nn + e];
+        valc[(int64_t)(base + d) * nn + e] = acc;
     }
 }
 
@@ -652,14 +670,19 @@ void strength_n(int32_t N, const int32_t *rp, const int32_t *col, const int32_t 
     hipLaunchKernelGGL(k_strength<n>, dim3(cdiv(N, 256)), dim3(256), 0, st, N, rp, col, mirror, val, df, w);
 }
 template <int n>
-void rap_n(int pass, int32_t nc, const int32_t *aptr, const int32_t *amem, const int32_t *rp, const int32_t *col,
-           const double *val, const int32_t *agg, int32_t *cnt, const int32_t *rpc, int32_t *colc, double *valc,
-           int32_t *flag, hipStream_t st) {
-    const dim3 g(cdiv(nc, kRapWaves)), b(64 * kRapWaves);
+void rap_n(int pass, int32_t nc, int32_t cap, const int32_t *aptr, const int32_t *amem, const int32_t *rp,
+           const int32_t *col, const double *val, const int32_t *agg, int32_t *cnt, const int32_t *rpc, int32_t *colc,
+           double *valc, int32_t *flag, hipStream_t st) {
+    // at most 48 KB of LDS per workgroup: fewer wavefronts for long lists
+    const int waves = std::max(1, std::min(kRapWaves, (int)(49152 / (12 * (size_t)cap))));
+    const dim3 g(cdiv(nc, waves)), b(64 * waves);
+    const size_t lds = sizeof(int32_t) * 3 * (size_t)cap * waves;
     if (pass == 0)
-        hipLaunchKernelGGL((k_rap<n, 0>), g, b, 0, st, nc, aptr, amem, rp, col, val, agg, cnt, rpc, colc, valc, flag);
+        hipLaunchKernelGGL((k_rap<n, 0>), g, b, lds, st, nc, cap, aptr, amem, rp, col, val, agg, cnt, rpc, colc, valc,
+                           flag);
     else
-        hipLaunchKernelGGL((k_rap<n, 1>), g, b, 0, st, nc, aptr, amem, rp, col, val, agg, cnt, rpc, colc, valc, flag);
+        hipLaunchKernelGGL((k_rap<n, 1>), g, b, lds, st, nc, cap, aptr, amem, rp, col, val, agg, cnt, rpc, colc, valc,
+                           flag);
 }
 template <int n>
 void dilu_setup_n(const int32_t *rows, int32_t cnt, int c, const int32_t *rp, const int32_t *col, const int32_t *mirror,
@@ -729,27 +752,38 @@ void rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, const 
                const int32_t *col, const double *val, const int32_t *agg, DArr<int32_t> &rpc, DArr<int32_t> &colc,
                DArr<double> &valc, bool pattern) {
     hipStream_t st = h->stream;
-    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+    // largest candidate list of the level -> LDS per wavefront
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, 2 * sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_rap_maxc, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, aptr, amem, rp, h->dflag.get() + 1);
+    LAUNCHCHK();
+    const int32_t maxc = read_int(h->dflag.get() + 1, st);
+    if (maxc > kRapCap)
+        cbs_throw(CBS_ERR_ARG, "a coarse row gathers " + std::to_string(maxc) + " blocks (limit " +
+                                   std::to_string(kRapCap) + "); lower match_passes");
+    int32_t cap = 64;
+    while (cap < maxc) cap *= 2;
     if (pattern) {
         rpc.alloc(nc + 1);
-        NSWITCH(n_blk, rap_n, 0, nc, aptr, amem, rp, col, val, agg, rpc.get(), nullptr, nullptr, nullptr,
+        NSWITCH(n_blk, rap_n, 0, nc, cap, aptr, amem, rp, col, val, agg, rpc.get(), nullptr, nullptr, nullptr,
                 h->dflag.get(), st);
         LAUNCHCHK();
         if (read_int(h->dflag.get(), st) & 8)
-            cbs_throw(CBS_ERR_ARG, "coarse row gathers more than 1024 blocks (aggregates too large)");
+            cbs_throw(CBS_ERR_ARG, "coarse row candidate overflow");
         scan_exclusive(rpc.get(), rpc.get(), nc, st);
         const int32_t nz = read_int(rpc.get() + nc, st);
         colc.alloc(nz > 0 ? nz : 1);
         valc.alloc((size_t)(nz > 0 ? nz : 1) * n_blk * n_blk);
     }
-    NSWITCH(n_blk, rap_n, 1, nc, aptr, amem, rp, col, val, agg, nullptr, rpc.get(), colc.get(), valc.get(),
+    NSWITCH(n_blk, rap_n, 1, nc, cap, aptr, amem, rp, col, val, agg, nullptr, rpc.get(), colc.get(), valc.get(),
             h->dflag.get(), st);
     LAUNCHCHK();
-    if (read_int(h->dflag.get(), st) & 8)
-        cbs_throw(CBS_ERR_ARG, "coarse row gathers more than 1024 blocks (aggregates too large)");
+    if (read_int(h->dflag.get(), st) & 8) cbs_throw(CBS_ERR_ARG, "coarse row candidate overflow");
 }
 
 // Aggregation of level L into L.agg / L.nc (composed matching passes).
+PhaseTimer *g_pt = nullptr;
+inline void gmark(const char *w) { if (g_pt) g_pt->mark(w); }
+
 void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen) {
     hipStream_t st = h->stream;
     const int32_t N = L.N;
@@ -757,9 +791,11 @@ void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen) {
     DArr<double> df(N), w(L.nnzb > 0 ? L.nnzb : 1);
     NSWITCH(n, strength_n, N, L.rp, L.col, L.mirror, L.dslot, L.v64, df.get(), w.get(), st);
     LAUNCHCHK();
+    gmark("strength");
     L.agg.alloc(N);
     Graph g{N, L.rp, L.col, w.get()};
     int32_t nc = match_pass(h, g, L.row_sys.get(), sys_frozen, L.agg.get());
+    gmark("match1");
     // further passes on the aggregate graph with summed weights
     DArr<int32_t> grp, gcol, rs, a2, gaptr, gamem;
     DArr<double> gw;
@@ -774,7 +810,9 @@ void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen) {
         DArr<int32_t> aptr, amem, nrp, ncol, nrs;
         DArr<double> nw;
         build_members(h, cur_N, agg1.get(), nc, aptr, amem);
+        gmark("members1");
         rap_build(h, 1, nc, aptr.get(), amem.get(), cur_rp, cur_col, cur_w, agg1.get(), nrp, ncol, nw, true);
+        gmark("wrap");
         hipLaunchKernelGGL(k_zero_diag_w, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, nrp.get(), ncol.get(), nw.get());
         nrs.alloc(nc);
         hipLaunchKernelGGL(k_inherit_sys, dim3(cdiv(cur_N, 256)), dim3(256), 0, st, cur_N, agg1.get(), cur_rowsys,
@@ -783,6 +821,7 @@ void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen) {
         DArr<int32_t> a(nc);
         Graph g2{nc, nrp.get(), ncol.get(), nw.get()};
         const int32_t nc2 = match_pass(h, g2, nrs.get(), sys_frozen, a.get());
+        gmark("match2");
         hipLaunchKernelGGL(k_compose, dim3(cdiv(N, 256)), dim3(256), 0, st, N, a.get(), L.agg.get());
         LAUNCHCHK();
         // the new graph becomes current
@@ -869,6 +908,11 @@ void level_sell(cbs_system *h, Level &L, bool mixed, bool reuse) {
     }
 }
 
+__global__ void k_nonfinite_f32(int64_t m, const float *a, int32_t *flag) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < m && !isfinite(a[g])) atomicOr(flag, 64);
+}
+
 std::vector<int64_t> level_sys_off(cbs_system *h, Level &L) {
     std::vector<int64_t> off(h->n_sys + 1, 0);
     if (h->n_sys == 1) {
@@ -906,6 +950,8 @@ void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv) {
 void amg_setup(cbs_system *h) {
     hipStream_t st = h->stream;
     PhaseTimer pt(st, "setup");
+    g_pt = &pt;
+    struct Unset { ~Unset() { g_pt = nullptr; } } unset_;
     const cbs_options &o = h->opt;
     const int n = h->n;
     const bool mixed = o.precision == CBS_PRECISION_MIXED;
@@ -918,6 +964,7 @@ void amg_setup(cbs_system *h) {
         h->renumbered = false;
         h->perm_sk.release();
     }
+    pt.mark("free");
     if (h->lev.empty()) h->lev.emplace_back();
     Level &L0 = h->lev[0];
     if (!h->renumbered) {
@@ -939,6 +986,7 @@ void amg_setup(cbs_system *h) {
         }
         h->lev.resize(1);
         level_sell(h, L0, false, false);
+        L0.sell.sched64 = autotune_rows(n, L0.sell, false, L0.sell.v64.get(), st);
         h->op_complexity = 1.0;
         return;
     }
@@ -1030,6 +1078,31 @@ void amg_setup(cbs_system *h) {
         if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, reuse);
         alloc_level_vectors(h, L, mixed);
         pt.mark("sell" + std::to_string(q));
+    }
+    {
+        // schedules of the block-row kernels, tuned on level 0, used on every level
+        Level &T0 = h->lev[0];
+        const Sched s64 = autotune_rows(n, T0.sell, false, T0.sell.v64.get(), st);
+        const Sched s32 = mixed ? autotune_rows(n, T0.sell, true, T0.sell.v32.get(), st) : Sched{4, 1};
+        for (auto &L : h->lev) { L.sell.sched64 = s64; L.sell.sched32 = s32; }
+        pt.mark("autotune");
+    }
+    if (mixed) {
+        // FP32 level values that overflow: escalate the hierarchy to FP64
+        HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+        for (int q = 0; q + 1 < nlev; ++q) {
+            const Level &L = h->lev[q];
+            const int64_t tot = L.sell.nent * n * n;
+            if (tot > 0)
+                hipLaunchKernelGGL(k_nonfinite_f32, dim3(cdiv(tot, 256)), dim3(256), 0, st, tot, L.sell.v32.get(),
+                                   h->dflag.get());
+        }
+        LAUNCHCHK();
+        if (read_int(h->dflag.get(), st) & 64) {
+            h->opt.precision = CBS_PRECISION_FP64;
+            h->precision_fallback = true;
+            for (int q = 0; q < nlev; ++q) alloc_level_vectors(h, h->lev[q], false);
+        }
     }
     h->op_complexity = (double)nz_sum / (double)h->nnzb;
 
@@ -1132,12 +1205,14 @@ void renumber_hierarchy(cbs_system *h) {
                            pos[l + 1].get(), new_aptr[l].get(), pos[l].get());
         LAUNCHCHK();
     }
+    gmark("positions");
     for (int l = 0; l + 1 < nlev; ++l) {
         Level &L = h->lev[l];
         const int32_t N = L.N;
         const int64_t nnz = L.nnzb;
         const dim3 G(cdiv(N, 256)), B(256);
         DArr<int32_t> ip(N), rpn(N + 1), coln(nnz), sk(nnz), aggn(N), memn(N), rsn(N), mir(nnz), dsl(N);
+        if (l == 0) gmark("alloc0");
         DArr<double> vn((size_t)nnz * n * n);
         hipLaunchKernelGGL(k_invert, G, B, 0, st, N, pos[l].get(), ip.get());
         hipLaunchKernelGGL(k_perm_len, G, B, 0, st, N, ip.get(), L.rp, rpn.get());
@@ -1161,6 +1236,7 @@ void renumber_hierarchy(cbs_system *h) {
         L.agg = std::move(aggn); L.agg_ptr = std::move(new_aptr[l]); L.agg_mem = std::move(memn);
         L.row_sys = std::move(rsn);
         L.order = std::move(ip);
+        if (l == 0) gmark("perm0");
     }
     h->renumbered = true;
 }
@@ -1188,12 +1264,14 @@ void spmv_user(cbs_system *h, const double *x, double *y, bool transposed) {
     const size_t tot = 0;
     (void)tot;
     if (!U.soff.get()) sell_build(h->N, h->rp.get(), h->col.get(), U, h->stream);
+    const bool tune = !U.v64.get() && !U.v64T.get();
     const size_t nv = (size_t)U.nent * n * n;
     if (!transposed) {
         if (!U.v64.get()) {
             U.v64.alloc(nv > 0 ? nv : 1);
             sell_fill(n, U, h->vals.get(), U.v64.get(), h->stream);
         }
+        if (tune) U.sched64 = autotune_rows(n, U, false, U.v64.get(), h->stream);
         launch_rows<double, double>(0, n, U.view(), U.v64.get(), x, nullptr, y, nullptr, 0.0, h->stream);
         return;
     }

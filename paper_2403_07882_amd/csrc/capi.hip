@@ -10,8 +10,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 
 void globalize_faces(cbs_system *h, const int32_t *la_in, const int32_t *ua_in);
 void alloc_krylov(cbs_system *h);
@@ -111,23 +114,71 @@ int create_common(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const
 [[noreturn]] void cbs_throw(int code, const std::string &msg) { throw CbsError{code, msg}; }
 
 // ------------------------------------------------------------------ memory
+// Caching device allocator: a freed block is kept, tagged with the stream
+// it was last used on, and handed out again for a request on the same
+// stream that fits (up to 2x its size).  Work on one stream runs in order,
+// so a block reused on that stream cannot overlap its previous use.  Setup
+// re-runs therefore do not free and re-map device memory; cbs_destroy
+// returns the handle's cached blocks to HIP.
 namespace {
 thread_local hipStream_t g_alloc_stream = nullptr;
-thread_local int g_pool_device = -1;
 
-void ensure_pool() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return;
-    if (g_pool_device == dev) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t keep = UINT64_MAX;     // keep freed memory in the pool
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
-    (void)hipGetLastError();
-    g_pool_device = dev;
-}
+struct CachedBlock {
+    void *p;
+    size_t bytes;
+    hipStream_t st;
+};
+std::mutex g_mem_mu;
+std::multimap<size_t, CachedBlock> g_free_blocks;
+std::unordered_map<void *, size_t> g_live_blocks;
 }  // namespace
+
+hipStream_t alloc_stream() { return g_alloc_stream; }
+void set_alloc_stream(hipStream_t st) { g_alloc_stream = st; }
+
+void *dev_alloc(size_t bytes) {
+    bytes = (bytes + 511) & ~(size_t)511;
+    {
+        std::lock_guard<std::mutex> lk(g_mem_mu);
+        for (auto it = g_free_blocks.lower_bound(bytes); it != g_free_blocks.end() && it->first <= 2 * bytes; ++it) {
+            if (it->second.st != g_alloc_stream) continue;
+            void *p = it->second.p;
+            g_live_blocks[p] = it->first;
+            g_free_blocks.erase(it);
+            return p;
+        }
+    }
+    void *q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess || !q) {
+        (void)hipGetLastError();
+        cbs_throw(CBS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_live_blocks[q] = bytes;
+    return q;
+}
+
+void dev_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    auto it = g_live_blocks.find(p);
+    if (it == g_live_blocks.end()) return;
+    g_free_blocks.emplace(it->second, CachedBlock{p, it->second, g_alloc_stream});
+    g_live_blocks.erase(it);
+}
+
+// return the cached blocks of one stream to HIP (the stream must be idle)
+static void dev_cache_trim(hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    for (auto it = g_free_blocks.begin(); it != g_free_blocks.end();) {
+        if (it->second.st == st) {
+            (void)hipFree(it->second.p);
+            it = g_free_blocks.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
 
 static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -152,23 +203,6 @@ PhaseTimer::~PhaseTimer() {
     std::string line = "[cbs] " + what + " total " + std::to_string(last - t0) + " ms:";
     for (auto &m : marks) line += " " + m.first + "=" + std::to_string(m.second).substr(0, 6);
     fprintf(stderr, "%s\n", line.c_str());
-}
-
-hipStream_t alloc_stream() { return g_alloc_stream; }
-void set_alloc_stream(hipStream_t st) { g_alloc_stream = st; }
-
-void *dev_alloc(size_t bytes) {
-    ensure_pool();
-    void *q = nullptr;
-    if (hipMallocAsync(&q, bytes, g_alloc_stream) != hipSuccess || !q) {
-        (void)hipGetLastError();
-        cbs_throw(CBS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-    }
-    return q;
-}
-
-void dev_free(void *p) {
-    if (p) (void)hipFreeAsync(p, g_alloc_stream);
 }
 
 cbs_system::~cbs_system() {
@@ -266,6 +300,7 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
         h->opt = o;
         HIPCHK(hipEventRecord(h->ev0, h->stream));
         h->setup_done = false;
+        h->precision_fallback = false;
         invalidate_graphs(h);
         amg_setup(h);
         alloc_krylov(h);
@@ -277,13 +312,41 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
     });
 }
 
+// Solve; a mixed-precision solve that breaks down or does not converge is
+// repeated from the caller's initial guess with the hierarchy in FP64 (same
+// aggregates), and the statistics report the escalation.
+static int solve_common(cbs_handle h, const double *b, double *x, cbs_stats *st, bool tr) {
+    require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
+    const int64_t m = (int64_t)h->N * h->n;
+    check_finite(x, m, h->dflag.get(), h->stream);
+    const bool mixed = h->opt.precision == CBS_PRECISION_MIXED && h->opt.precond == CBS_PREC_AMG;
+    if (mixed) {
+        h->x0.ensure(m);
+        launch_copy(m, x, h->x0.get(), h->stream);
+    }
+    int rc = krylov_solve(h, b, x, st, tr);
+    if (mixed && rc != CBS_OK) {
+        cbs_options o = h->opt;
+        o.precision = CBS_PRECISION_FP64;
+        o.reuse_aggregates = 1;
+        h->opt = o;
+        invalidate_graphs(h);
+        amg_setup(h);
+        alloc_krylov(h);
+        h->precision_fallback = true;
+        launch_copy(m, h->x0.get(), x, h->stream);
+        rc = krylov_solve(h, b, x, st, tr);
+    }
+    if (st)
+        for (int s = 0; s < h->n_sys; ++s) st[s].precision_fallback = h->precision_fallback ? 1 : 0;
+    return rc;
+}
+
 int cbs_solve(cbs_handle h, const double *b, double *x, cbs_stats *st) {
     return guarded([&] {
         require(h != nullptr && b != nullptr && x != nullptr, CBS_ERR_ARG, "NULL argument");
         set_alloc_stream(h->stream);
-        require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
-        check_finite(x, (int64_t)h->N * h->n, h->dflag.get(), h->stream);
-        return krylov_solve(h, b, x, st, false);
+        return solve_common(h, b, x, st, false);
     });
 }
 
@@ -291,9 +354,7 @@ int cbs_solve_transpose(cbs_handle h, const double *g, double *lambda, cbs_stats
     return guarded([&] {
         require(h != nullptr && g != nullptr && lambda != nullptr, CBS_ERR_ARG, "NULL argument");
         set_alloc_stream(h->stream);
-        require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
-        check_finite(lambda, (int64_t)h->N * h->n, h->dflag.get(), h->stream);
-        return krylov_solve(h, g, lambda, st, true);
+        return solve_common(h, g, lambda, st, true);
     });
 }
 
@@ -421,8 +482,11 @@ int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows, int64_t *nnzb, i
 
 int cbs_destroy(cbs_handle h) {
     return guarded([&] {
-        if (h) set_alloc_stream(h->stream);
+        if (!h) return CBS_OK;
+        set_alloc_stream(h->stream);
+        hipStream_t st = h->stream;
         delete h;
+        dev_cache_trim(st);
         return CBS_OK;
     });
 }

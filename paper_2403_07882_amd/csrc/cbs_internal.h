@@ -92,9 +92,17 @@ enum {
 // consecutive blocks per step.  BCSR stays the setup-time format.
 constexpr int kSlice = 16;
 
+// Schedule of the block-row kernels: blocks loaded per step (1, 2, 4) and
+// whether matrix values are loaded non-temporally; picked by autotuning.
+struct Sched {
+    int8_t unroll = 4;
+    int8_t nontemporal = 0;
+};
+
 struct SellView {
     int32_t N;
     const int32_t *soff, *sw, *scol;
+    Sched sched;
 };
 
 struct Sell {
@@ -103,7 +111,10 @@ struct Sell {
     DArr<int32_t> soff, sw, scol, ssrc;   // ssrc: BCSR slot of each entry, -1 = padding
     DArr<double> v64, v64T;
     DArr<float> v32, v32T;
-    SellView view() const { return SellView{N, soff.get(), sw.get(), scol.get()}; }
+    Sched sched64{4, 0}, sched32{4, 1};
+    SellView view(bool fp32 = false) const {
+        return SellView{N, soff.get(), sw.get(), scol.get(), fp32 ? sched32 : sched64};
+    }
 };
 
 // ---------------------------------------------------------------- levels
@@ -189,6 +200,9 @@ struct cbs_system {
     DArr<int32_t> perm_sk;                       // permuted level-0 slot -> caller-order slot
     DArr<double> valsT;                          // caller-order A^T values (cbs_spmv transpose)
     Sell usell;                                  // caller-order sliced copy (cbs_spmv)
+    // mixed precision escalated to FP64 (sticky until the next cbs_setup)
+    bool precision_fallback = false;
+    DArr<double> x0;                             // caller's initial guess, kept for a re-solve
     // statistics
     double t_convert_ms = 0.0, t_setup_ms = 0.0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -229,6 +243,8 @@ void gradient(cbs_system *h, const double *lam, const double *x, double *gd, dou
 template <typename TV, typename TX>
 void launch_rows(int mode, int n, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y,
                  const double *Dinv, double omega, hipStream_t st);
+// time the schedules of the residual kernel on S (cached per shape)
+Sched autotune_rows(int n, const Sell &S, bool fp32, const void *val, hipStream_t st);
 // sliced-ELL pattern from BCSR, and values gathered from BCSR values
 void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st);
 void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st);

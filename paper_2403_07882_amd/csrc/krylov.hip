@@ -406,7 +406,7 @@ void dilu_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x, bool zero_g
     const double *Einv = tr ? L.EinvT.get() : L.Einv.get();
     T *y = vptr<T>(L.vt);
     const int ncol = (int)L.colour_off.size() - 1;
-    const SellView S = L.sell.view();
+    const SellView S = L.sell.view(sizeof(T) == 4);
     for (int c = 0; c < ncol; ++c)
         launch_dilu_fwd<T>(h->n, S, val, L.colour.get(), c, L.rows_by_colour.get() + L.colour_off[c],
                            L.colour_off[c + 1] - L.colour_off[c], Einv, b, x, y, zero_guess, h->stream);
@@ -435,7 +435,7 @@ void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
     if (L.dilu) {
         for (int s = 0; s < nu1; ++s) dilu_smooth<T>(h, L, tr, b, x, s == 0);
         if (nu1 == 0) launch_fill<T>((int64_t)L.N * n, x, st);
-        launch_rows<T, T>(1, n, L.sell.view(), val, x, b, r, nullptr, 0.0, st);
+        launch_rows<T, T>(1, n, L.sell.view(sizeof(T) == 4), val, x, b, r, nullptr, 0.0, st);
         Level &C = h->lev[l + 1];
         T *bc = vptr<T>(C.vb), *xc = vptr<T>(C.vx);
         launch_restrict<T>(n, C.N, L.agg_ptr.get(), L.agg_mem.get(), r, bc, st);
@@ -448,22 +448,22 @@ void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
     T *cur = (switches % 2 == 0) ? x : tmp;
     T *oth = (cur == x) ? tmp : x;
     if (nu1 >= 1) {
-        launch_rows<T, T>(3, n, L.sell.view(), val, cur, b, cur, Dinv, o.omega, st);
+        launch_rows<T, T>(3, n, L.sell.view(sizeof(T) == 4), val, cur, b, cur, Dinv, o.omega, st);
         for (int s = 1; s < nu1; ++s) {
-            launch_rows<T, T>(2, n, L.sell.view(), val, cur, b, oth, Dinv, o.omega, st);
+            launch_rows<T, T>(2, n, L.sell.view(sizeof(T) == 4), val, cur, b, oth, Dinv, o.omega, st);
             std::swap(cur, oth);
         }
     } else {
         launch_fill<T>((int64_t)L.N * n, cur, st);
     }
-    launch_rows<T, T>(1, n, L.sell.view(), val, cur, b, r, Dinv, o.omega, st);
+    launch_rows<T, T>(1, n, L.sell.view(sizeof(T) == 4), val, cur, b, r, Dinv, o.omega, st);
     Level &C = h->lev[l + 1];
     T *bc = vptr<T>(C.vb), *xc = vptr<T>(C.vx);
     launch_restrict<T>(n, C.N, L.agg_ptr.get(), L.agg_mem.get(), r, bc, st);
     vcycle<T>(h, tr, l + 1, bc, xc);
     launch_prolong<T>(n, L.N, L.agg.get(), xc, cur, st);
     for (int s = 0; s < nu2; ++s) {
-        launch_rows<T, T>(2, n, L.sell.view(), val, cur, b, oth, Dinv, o.omega, st);
+        launch_rows<T, T>(2, n, L.sell.view(sizeof(T) == 4), val, cur, b, oth, Dinv, o.omega, st);
         std::swap(cur, oth);
     }
 }

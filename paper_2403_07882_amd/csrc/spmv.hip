@@ -12,6 +12,10 @@
 // the block row, exchanged through LDS.
 #include "cbs_internal.h"
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace {
 
 template <typename T> struct Acc { using type = double; };
@@ -23,23 +27,30 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 // Row r of one block: n contiguous values, streamed once per SpMV, so they
 // are loaded non-temporally (keeps x resident in the caches).  16-byte
 // vector loads where the alignment allows it (n = 4).
-// FP32 values are streamed with non-temporal loads (measured faster on
-// gfx950 for the 64-byte blocks); FP64 values use ordinary loads.
+// Row r of one block (n contiguous values), loaded non-temporally when NT
+// (values are streamed once per sweep); 16-byte vector loads for n = 4.
+template <int n, typename T, bool NT>
+__device__ inline void load_row_nt(const T *__restrict__ p, T (&v)[n]) {
+    if constexpr (n == 4 && sizeof(T) == 8) {
+        const dbl2 a = NT ? __builtin_nontemporal_load(reinterpret_cast<const dbl2 *>(p))
+                          : *reinterpret_cast<const dbl2 *>(p);
+        const dbl2 b = NT ? __builtin_nontemporal_load(reinterpret_cast<const dbl2 *>(p) + 1)
+                          : *(reinterpret_cast<const dbl2 *>(p) + 1);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    } else if constexpr (n == 4 && sizeof(T) == 4) {
+        const flt4 a = NT ? __builtin_nontemporal_load(reinterpret_cast<const flt4 *>(p))
+                          : *reinterpret_cast<const flt4 *>(p);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    } else {
+#pragma unroll
+        for (int c = 0; c < n; ++c) v[c] = NT ? __builtin_nontemporal_load(p + c) : p[c];
+    }
+}
+
+// default schedule of the DILU sweeps: streamed FP32, cached FP64
 template <int n, typename T>
 __device__ inline void load_block_row(const T *__restrict__ p, T (&v)[n]) {
-#pragma unroll
-    for (int c = 0; c < n; ++c) v[c] = sizeof(T) == 4 ? __builtin_nontemporal_load(p + c) : p[c];
-}
-template <>
-__device__ inline void load_block_row<4, double>(const double *__restrict__ p, double (&v)[4]) {
-    const dbl2 a = *reinterpret_cast<const dbl2 *>(p);
-    const dbl2 b = *(reinterpret_cast<const dbl2 *>(p) + 1);
-    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-}
-template <>
-__device__ inline void load_block_row<4, float>(const float *__restrict__ p, float (&v)[4]) {
-    const flt4 a = __builtin_nontemporal_load(reinterpret_cast<const flt4 *>(p));
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    load_row_nt<n, T, sizeof(T) == 4>(p, v);
 }
 
 template <int n, typename T>
@@ -62,13 +73,12 @@ __device__ inline void load_x<4, float>(const float *__restrict__ p, float (&v)[
 // Rows are read from the sliced-ELL copy: at step k the 16 rows of a slice
 // read 16 consecutive blocks; four steps are loaded before they are summed,
 // and the sums run in the row's column order.
-template <int n, typename TV, typename TX, int MODE>
+template <int n, typename TV, typename TX, int MODE, int U, bool NT>
 __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restrict__ val, const TX *__restrict__ x,
                                                  const TX *__restrict__ b, TX *__restrict__ y,
                                                  const double *__restrict__ Dinv, double omega) {
     using A = typename Acc<TX>::type;
     constexpr int nn = n * n;
-    constexpr int U = 4;
     const int t = threadIdx.x;
     const int lr = t / n, r = t - lr * n;
     const int32_t i = blockIdx.x * 64 + lr;
@@ -87,7 +97,7 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t e = base + (int64_t)(k + u) * kSlice;
-                load_block_row<n, TV>(val + e * nn + r * n, bv[u]);
+                load_row_nt<n, TV, NT>(val + e * nn + r * n, bv[u]);
                 load_x<n, TX>(x + (int64_t)(j[u] < 0 ? i : j[u]) * n, xv[u]);
             }
 #pragma unroll
@@ -103,7 +113,7 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
             if (j < 0) continue;
             TV bv[n];
             TX xv[n];
-            load_block_row<n, TV>(val + e * nn + r * n, bv);
+            load_row_nt<n, TV, NT>(val + e * nn + r * n, bv);
             load_x<n, TX>(x + (int64_t)j * n, xv);
 #pragma unroll
             for (int c = 0; c < n; ++c) acc += (A)bv[c] * (A)xv[c];
@@ -133,15 +143,28 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
     }
 }
 
+template <int n, typename TV, typename TX, int MODE>
+void rows_nm(const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, const double *Dinv, double omega,
+             hipStream_t st) {
+    const dim3 g(cdiv(S.N, 64)), bl(64 * n);
+    const int u = S.sched.unroll;
+    const bool nt = S.sched.nontemporal != 0;
+#define ROWS_V(UU, NTT) hipLaunchKernelGGL((k_rows<n, TV, TX, MODE, UU, NTT>), g, bl, 0, st, S, val, x, b, y, Dinv, omega)
+    if (MODE == 3) { ROWS_V(1, false); return; }       // no matrix read
+    if (u <= 1) { if (nt) ROWS_V(1, true); else ROWS_V(1, false); }
+    else if (u == 2) { if (nt) ROWS_V(2, true); else ROWS_V(2, false); }
+    else { if (nt) ROWS_V(4, true); else ROWS_V(4, false); }
+#undef ROWS_V
+}
+
 template <int n, typename TV, typename TX>
 void rows_n(int mode, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, const double *Dinv,
             double omega, hipStream_t st) {
-    const dim3 g(cdiv(S.N, 64)), bl(64 * n);
     switch (mode) {
-        case 0: hipLaunchKernelGGL((k_rows<n, TV, TX, 0>), g, bl, 0, st, S, val, x, b, y, Dinv, omega); break;
-        case 1: hipLaunchKernelGGL((k_rows<n, TV, TX, 1>), g, bl, 0, st, S, val, x, b, y, Dinv, omega); break;
-        case 2: hipLaunchKernelGGL((k_rows<n, TV, TX, 2>), g, bl, 0, st, S, val, x, b, y, Dinv, omega); break;
-        case 3: hipLaunchKernelGGL((k_rows<n, TV, TX, 3>), g, bl, 0, st, S, val, x, b, y, Dinv, omega); break;
+        case 0: rows_nm<n, TV, TX, 0>(S, val, x, b, y, Dinv, omega, st); break;
+        case 1: rows_nm<n, TV, TX, 1>(S, val, x, b, y, Dinv, omega, st); break;
+        case 2: rows_nm<n, TV, TX, 2>(S, val, x, b, y, Dinv, omega, st); break;
+        case 3: rows_nm<n, TV, TX, 3>(S, val, x, b, y, Dinv, omega, st); break;
     }
 }
 
@@ -529,3 +552,58 @@ template void launch_dilu_bwd<double>(int, const SellView &, const double *, con
                                       int32_t, const double *, double *, double *, bool, hipStream_t);
 template void launch_dilu_bwd<float>(int, const SellView &, const float *, const int32_t *, int, const int32_t *,
                                      int32_t, const double *, float *, float *, bool, hipStream_t);
+
+// ------------------------------------------------------------------ autotuning
+// The residual kernel (the shape shared by SpMV and the smoother sweeps) is
+// timed with HIP events for each schedule on the matrix itself; the fastest
+// is kept per (rows, entries, block size, precision) for the process.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int32_t, int64_t, int, bool>, Sched> g_tune_cache;
+}  // namespace
+
+Sched autotune_rows(int n, const Sell &S, bool fp32, const void *val, hipStream_t st) {
+    const auto key = std::make_tuple(S.N, S.nent, n, fp32);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return it->second;
+    }
+    Sched best = fp32 ? Sched{4, 1} : Sched{4, 0};
+    if (S.N < 65536) return best;                        // small levels: launch-bound, keep the default
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    const int64_t m = (int64_t)S.N * n;
+    DArr<double> scratch((size_t)3 * m);
+    void *x = scratch.get(), *b = scratch.get() + m, *y = scratch.get() + 2 * m;
+    if (fp32) { launch_fill<float>(m, (float *)x, st); launch_fill<float>(m, (float *)b, st); }
+    else { launch_fill<double>(m, (double *)x, st); launch_fill<double>(m, (double *)b, st); }
+    for (int u : {1, 2, 4})
+        for (int nt : {0, 1}) {
+            SellView v = S.view(fp32);
+            v.sched = Sched{(int8_t)u, (int8_t)nt};
+            auto run = [&] {
+                if (fp32)
+                    launch_rows<float, float>(1, n, v, (const float *)val, (const float *)x, (const float *)b, (float *)y,
+                                              nullptr, 0.0, st);
+                else
+                    launch_rows<double, double>(1, n, v, (const double *)val, (const double *)x, (const double *)b,
+                                                (double *)y, nullptr, 0.0, st);
+            };
+            run();
+            HIPCHK(hipEventRecord(e0, st));
+            for (int rep = 0; rep < 3; ++rep) run();
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) { best_ms = ms; best = v.sched; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+    return best;
+}

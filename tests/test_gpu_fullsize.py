@@ -1,0 +1,154 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark uses, checked through properties that hold at any size: the
+relative residual of the GPU's x recomputed by the oracle's own SpMV (face
+loop on the LDU arrays), per-system residuals of a batch with a few systems
+against oracle solo solves, the transposed-solve residual, and the adjoint
+gradient against central finite differences."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import concat_systems, jacobian_batch, jacobian_box, jacobian_stretched, pressure_velocity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2403_07882_amd as P  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _relres_ldu(s, x):
+    """||b - A x|| / ||b|| with the oracle's LDU face-loop SpMV."""
+    r = s["b"] - O.spmv_ldu(s, x)
+    return float(np.linalg.norm(r) / np.linalg.norm(s["b"]))
+
+
+def test_stretched_density_8M_mixed_fgmres():
+    """200^3 boundary-layer mesh (aspect ratio up to 1e3), 5x5 blocks, 8M cells:
+    mixed-precision AMG-FGMRES(30) to 1e-8."""
+    t0 = time.time()
+    s = jacobian_stretched(200, 200, 200, seed=0)
+    _say("generated 8M stretched system in %.1f s" % (time.time() - t0))
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precision=P.PRECISION_MIXED, solver=P.SOLVER_FGMRES, restart=30, tol=1e-8)
+        x, st = sysm.solve(s["b"])
+        _say("gpu:", st)
+    assert st["status"] == P.OK, st
+    rr = _relres_ldu(s, _np(x))
+    _say("oracle relres %.3e" % rr)
+    assert rr <= 1e-8 * 1.0001
+    assert abs(rr - st["rel_res_true"]) <= 1e-10
+
+
+def test_batch_64_uneven_systems():
+    """64 density-based systems of 10k-500k cells in one batched mixed solve."""
+    t0 = time.time()
+    cat = jacobian_batch(64, seed=0)
+    _say("generated batch of 64 (%d cells) in %.1f s" % (cat["N"], time.time() - t0))
+    with P.System.from_dict(cat) as bs:
+        bs.setup(precision=P.PRECISION_MIXED, tol=1e-8)
+        x, stats = bs.solve(cat["b"])
+    xn = _np(x)
+    assert len(stats) == 64
+    co, fo = cat["cell_off"], cat["face_off"]
+    sizes = np.diff(co)
+    for k in range(64):
+        assert stats[k]["status"] == P.OK, (k, stats[k])
+        sk = {"N": int(sizes[k]), "n": 5, "lower_addr": cat["lower_addr"][fo[k]:fo[k + 1]],
+              "upper_addr": cat["upper_addr"][fo[k]:fo[k + 1]], "diag": cat["diag"][co[k]:co[k + 1]],
+              "upper": cat["upper"][fo[k]:fo[k + 1]], "lower": cat["lower"][fo[k]:fo[k + 1]],
+              "b": cat["b"][co[k]:co[k + 1]]}
+        assert _relres_ldu(sk, xn[co[k]:co[k + 1]]) <= 1e-8 * 1.0001
+    # the three smallest systems against oracle solo solves
+    for k in np.argsort(sizes)[:3]:
+        sh = cat["shapes"][k]
+        sk = jacobian_box(*sh, seed=1 + int(k))
+        A = O.from_system(sk)
+        xr, st = O.fgmres(A, sk["b"], prec=O.PREC_BJACOBI, tol=1e-12, maxit=20000, restart=60)
+        xk = xn[co[k]:co[k + 1]]
+        assert np.linalg.norm(xk - xr) <= 1e-6 * np.linalg.norm(xr)
+
+
+def test_adjoint_2M_pressure_velocity_fd_check():
+    """200x100x100 p-U system: forward and transposed solves, gradient of
+    L = c^T x w.r.t. 16 b entries and 16 nonzero A entries against central
+    finite differences with step 1e-6.  Each difference is taken through
+    correction solves (x(A + hE) = x + d with (A + hE) d = -h E x), which is
+    the same central difference without cancellation in L."""
+    t0 = time.time()
+    s = pressure_velocity(200, 100, 100, seed=0)
+    N, n, F = s["N"], 4, s["F"]
+    rng = np.random.default_rng(4)
+    c = rng.standard_normal((N, n))
+    _say("generated 2M p-U system in %.1f s" % (time.time() - t0))
+    opt = dict(precision=P.PRECISION_FP64, tol=1e-11, max_iter=2000)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(**opt)
+        x, st = sysm.solve(s["b"])
+        lam, stt = sysm.solve_transpose(c)
+        assert st["status"] == P.OK and stt["status"] == P.OK
+        gd, gu, gl = sysm.gradient(lam, x)
+        xn, ln = _np(x), _np(lam)
+        gd, gu, gl = _np(gd), _np(gu), _np(gl)
+        _say("forward %d it, transpose %d it" % (st["iterations"], stt["iterations"]))
+        # transposed residual with the oracle's transposed LDU product
+        # A^T in LDU form: diag^T, upper' = lower^T, lower' = upper^T
+        tr = lambda a: np.ascontiguousarray(np.transpose(a, (0, 2, 1)))
+        sT = dict(s, diag=tr(s["diag"]), upper=tr(s["lower"]), lower=tr(s["upper"]), b=c)
+        assert _relres_ldu(sT, ln) <= 1e-11 * 1.0001
+        h = 1e-6
+        gmax = max(np.abs(gd).max(), np.abs(gu).max(), np.abs(gl).max(), np.abs(ln).max())
+        # b entries: L(b + h e) - L(b - h e) = 2 h c^T A^{-1} e
+        for _ in range(16):
+            i, r = int(rng.integers(N)), int(rng.integers(n))
+            e = np.zeros((N, n)); e[i, r] = h
+            d, std = sysm.solve(e)
+            fd = float((c * _np(d)).sum()) / h
+            assert abs(fd - ln[i, r]) <= 1e-4 * abs(ln[i, r]) + 1e-6 * gmax, (i, r, fd, ln[i, r])
+        # A entries: diag, upper and lower blocks
+        picks = [("diag", int(rng.integers(N))) for _ in range(6)] + \
+                [("upper", int(rng.integers(F))) for _ in range(5)] + \
+                [("lower", int(rng.integers(F))) for _ in range(5)]
+        la, ua = s["lower_addr"], s["upper_addr"]
+        for kind, idx in picks:
+            rr, cc = int(rng.integers(n)), int(rng.integers(n))
+            row = idx if kind == "diag" else (la[idx] if kind == "upper" else ua[idx])
+            colc = idx if kind == "diag" else (ua[idx] if kind == "upper" else la[idx])
+            ad = {"diag": gd, "upper": gu, "lower": gl}[kind][idx, rr, cc]
+            diffs = []
+            for sign in (1.0, -1.0):
+                vals = {k: s[k].copy() for k in ("diag", "upper", "lower")}
+                vals[kind][idx, rr, cc] += sign * h
+                sysm.update_values(vals["diag"], vals["upper"], vals["lower"])
+                sysm.setup(reuse_aggregates=1, **opt)
+                rhs = np.zeros((N, n)); rhs[row, rr] = -sign * h * xn[colc, cc]
+                d, _ = sysm.solve(rhs)
+                diffs.append(_np(d))
+            fd = float((c * (diffs[0] - diffs[1])).sum()) / (2 * h)
+            assert abs(fd - ad) <= 1e-4 * abs(ad) + 1e-6 * gmax, (kind, idx, rr, cc, fd, ad)
+        _say("fd check done")
+
+
+def test_mixed_overflow_escalates_to_fp64():
+    """FP32 cannot hold blocks scaled by 1e39: the hierarchy escalates to FP64."""
+    s = jacobian_box(8, 8, 8, seed=0)
+    A = O.from_system(s)
+    xr, _ = O.fgmres(A, s["b"], prec=O.PREC_BJACOBI, tol=1e-12, maxit=5000)
+    k = 1e39
+    with P.System(s["N"], 5, s["lower_addr"], s["upper_addr"], s["diag"] * k, s["upper"] * k,
+                  s["lower"] * k) as sysm:
+        sysm.setup(precision=P.PRECISION_MIXED, tol=1e-9)
+        x, st = sysm.solve(s["b"] * k)
+    assert st["status"] == P.OK and st["precision_fallback"] == 1, st
+    assert np.linalg.norm(_np(x) - xr) <= 1e-7 * np.linalg.norm(xr)

@@ -62,3 +62,12 @@ def test_batch_sizes_in_range_and_concat_offsets():
     cat = concat_systems(sys_)
     assert cat["cell_off"].tolist() == [0, 12, 20]
     assert cat["face_off"].tolist() == [0, sys_[0]["F"], sys_[0]["F"] + sys_[1]["F"]]
+
+
+def test_spectral_norm_helper_matches_library_svd():
+    from workloads.gen import _spectral_norms
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 4, 5):
+        J = rng.normal(0.0, 0.2, size=(500, n, n))
+        ref = np.linalg.norm(J, ord=2, axis=(1, 2))
+        assert np.allclose(_spectral_norms(J), ref, rtol=1e-12, atol=1e-15)

@@ -62,13 +62,38 @@ def box_faces(nx: int, ny: int, nz: int):
             np.concatenate(dr))
 
 
-def _spectral_norms(J: np.ndarray, chunk: int = 1 << 20) -> np.ndarray:
-    """Largest singular value of each square block (via eigvalsh of J^T J)."""
+_SPEC_LIB = None
+
+
+def _spec_lib():
+    """specnorm.c built with gcc on first use (input generation helper)."""
+    global _SPEC_LIB
+    if _SPEC_LIB is None:
+        import ctypes
+        import os
+        import subprocess
+        here = os.path.dirname(os.path.abspath(__file__))
+        src, so = os.path.join(here, "specnorm.c"), os.path.join(here, "libspecnorm.so")
+        if not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+            tmp = so + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+            os.replace(tmp, so)
+        lib = ctypes.CDLL(so)
+        lib.spectral_norms.restype = None
+        lib.spectral_norms.argtypes = [ctypes.c_long, ctypes.c_int,
+                                       np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS"),
+                                       np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")]
+        _SPEC_LIB = lib
+    return _SPEC_LIB
+
+
+def _spectral_norms(J: np.ndarray) -> np.ndarray:
+    """Largest singular value of each square block: sqrt(lambda_max(J^T J)),
+    eigenvalues by cyclic Jacobi rotations (specnorm.c)."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
     out = np.empty(J.shape[0])
-    for s in range(0, J.shape[0], chunk):
-        Jc = J[s:s + chunk]
-        G = np.einsum("fki,fkj->fij", Jc, Jc)
-        out[s:s + chunk] = np.sqrt(np.maximum(np.linalg.eigvalsh(G)[:, -1], 0.0))
+    if J.shape[0]:
+        _spec_lib().spectral_norms(J.shape[0], J.shape[1], J.reshape(-1), out)
     return out
 
 
@@ -91,12 +116,18 @@ def _jacobian_blocks(N, lower_addr, upper_addr, J, face_w, cell_w, n, variant="A
         Wn = 0.5 * (-J + s[:, None, None] * eye) * face_w[:, None, None]
     else:
         raise ValueError("variant must be 'A' or 'B'")
-    diag = np.zeros((N, n, n))
+    # Per-cell sums of the face contributions; bincount accumulates in face
+    # order, so the result is reproducible.
+    nn = n * n
+    lanes = np.arange(nn, dtype=np.int64)
+
+    def cell_sums(addr, W):
+        idx = (addr.astype(np.int64)[:, None] * nn + lanes).reshape(-1)
+        return np.bincount(idx, weights=W.reshape(-1), minlength=N * nn).reshape(N, n, n)
+
+    diag = cell_sums(lower_addr, Wp)
+    diag += cell_sums(upper_addr, Wn)
     diag += cell_w[:, None, None] * eye
-    # Sum face contributions cell by cell in face order (np.add.at is
-    # sequential in index order, so the result is reproducible).
-    np.add.at(diag, lower_addr, Wp)
-    np.add.at(diag, upper_addr, Wn)
     upper = -Wp          # row owner, column neighbour
     lower = -Wn          # row neighbour, column owner
     return diag, np.ascontiguousarray(upper), np.ascontiguousarray(lower)
