@@ -23,6 +23,11 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the FP64 SpMV on the internal numbering of the
+# 100x100x100 p-U system, from FETCH_SIZE and WRITE_SIZE counter runs scaled
+# by the readings of a 1 GiB copy kernel (factors 2.0 and 1.0):
+# profiles/block_spmv_fp64_pu1M_hbm_counters.md
+SPMV_TRAFFIC_PU1M = 1133719389
 
 
 def parse():
@@ -42,6 +47,8 @@ def parse():
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--solver", choices=["bicgstab", "fgmres"], default="bicgstab")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--spmv-only", action="store_true",
+                    help="only the FP64 block SpMV (both numberings) and a 1 GiB copy, for counter runs")
     return ap.parse_args()
 
 
@@ -77,6 +84,36 @@ def cpu_baseline(shape):
     }
 
 
+def spmv_only(args, P, torch, dev, sysm, N, n, nnzb, la, ua, diag, upper, lower):
+    """FP64 block SpMV launches on both numberings plus a plain 1 GiB copy
+    (the calibration kernel of the HBM byte counters)."""
+    import ctypes as C
+    L = P.lib()
+    xv = torch.randn(N * n, dtype=torch.float64, device=dev)
+    yv = torch.empty_like(xv)
+    sysm.setup(P.default_options(precision=P.PRECISION_MIXED))
+    order = sysm.get_level(0)["order"].long()
+    pos = torch.empty_like(order)
+    pos[order] = torch.arange(N, device=dev)
+    sys2 = P.System(N, n, pos[la.long()].int(), pos[ua.long()].int(), diag[order], upper, lower)
+    res = {}
+    for name, system in (("caller", sysm), ("internal", sys2)):
+        for _ in range(args.spmv_reps):
+            L.cbs_spmv(system.h, C.c_void_p(xv.data_ptr()), C.c_void_p(yv.data_ptr()), 0)
+        torch.cuda.synchronize()
+        res[name] = args.spmv_reps
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB
+    a.fill_(1.0)
+    bcopy = torch.empty_like(a)
+    for _ in range(3):
+        bcopy.copy_(a)
+    torch.cuda.synchronize()
+    sys2.close()
+    print(json.dumps({"spmv_launches_per_numbering": args.spmv_reps,
+                      "algorithmic_bytes_per_spmv": int(spmv_bytes(N, nnzb, n)),
+                      "copy_bytes_read": int(a.numel() * 8), "copy_bytes_written": int(a.numel() * 8)}))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -102,11 +139,17 @@ def main():
     diag = torch.tensor(s["diag"], device=dev)
     upper = torch.tensor(s["upper"], device=dev)
     lower = torch.tensor(s["lower"], device=dev)
-    b = torch.tensor(s["b"], device=dev).reshape(-1)
+    # right-hand side as per-variable fields (p, Ux, Uy, Uz), as a CFD code holds them
+    b_fields = torch.tensor(np.ascontiguousarray(s["b"].T), device=dev)
+    x_fields = torch.empty_like(b_fields)
+    b = P.pack_fields(b_fields).reshape(-1)
     x = torch.zeros_like(b)
     del s
     sysm = P.System(N, n, la, ua, diag, upper, lower)
     nnzb = sysm.info()["nnzb"]
+    if args.spmv_only:
+        spmv_only(args, P, torch, dev, sysm, N, n, nnzb, la, ua, diag, upper, lower)
+        return
     common = dict(solver=P.SOLVER_BICGSTAB if args.solver == "bicgstab" else P.SOLVER_FGMRES,
                   precond=P.PREC_AMG, tol=1e-8, max_iter=500,
                   smoother=P.SMOOTH_DILU if args.smoother == "dilu" else P.SMOOTH_BJACOBI,
@@ -115,11 +158,22 @@ def main():
     opt_mixed = P.default_options(precision=P.PRECISION_MIXED, **common)
     opt_fp64 = P.default_options(precision=P.PRECISION_FP64, **common)
 
+    L = P.lib()
+    import ctypes as C
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
     def step(opt):
+        # a1 pack -> a3 values -> setup -> solve -> a1 unpack
+        L.cbs_pack_fields(N, n, C.c_void_p(b_fields.data_ptr()), C.c_void_p(b.data_ptr()), stream)
         sysm.update_values(diag, upper, lower)
         sysm.setup(opt)
         x.zero_()
-        return sysm._solve(P.lib().cbs_solve, "cbs_solve", b, None)
+        st = P.Stats()
+        rc = L.cbs_solve(sysm.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), C.byref(st))
+        if rc < 0:
+            raise P.CbsError(rc, "cbs_solve")
+        L.cbs_unpack_fields(N, n, C.c_void_p(x.data_ptr()), C.c_void_p(x_fields.data_ptr()), stream)
+        return x, st.as_dict(), rc
 
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
@@ -152,8 +206,6 @@ def main():
 
     # dominant bandwidth kernel: FP64 block SpMV, timed with events on its
     # stream (torch's current stream, which the library was given).
-    L = P.lib()
-    import ctypes as C
 
     def time_spmv(system):
         xv = torch.randn(N * n, dtype=torch.float64, device=dev)
@@ -203,7 +255,7 @@ def main():
         "config": {"workload": "pressure-based coupled p-U 4x4, %dx%dx%d jittered hex mesh, cells "
                                "randomly renumbered (N=%d, F=%d, nnzb=%d); mixed AMG-BiCGStab to 1e-8"
                                % (nx, ny, nz, N, F, nnzb),
-                   "step": "update_values + setup + solve",
+                   "step": "pack fields + update_values + setup + solve + unpack fields",
                    "solver": args.solver, "smoother": args.smoother, "dilu_levels": args.dilu_levels,
                    "sweeps": args.sweeps, "omega": args.omega, "coarse_max": args.coarse_max,
                    "match_passes": args.passes},
@@ -219,7 +271,8 @@ def main():
         "mixed_vs_fp64_speedup": round(t_fp64 / t_mixed, 3) if t_fp64 == t_fp64 else None,
         "roofline": {"bound": "hbm", "kernel": "block SpMV FP64 (k_rows mode 0, n=4), internal numbering",
                      "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": SPMV_TRAFFIC_PU1M if (nx, ny, nz) == (100, 100, 100) else None,
                      "avg_launch_us": round(spmv_ms * 1e3, 2), "algorithmic_bytes": int(byts)},
         "spmv_caller_numbering": {"achieved_gbs": round(gbs_user, 1), "avg_launch_us": round(spmv_user_ms * 1e3, 2),
                                   "frac": round(gbs_user / HBM_PEAK_GBS, 4)},
