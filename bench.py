@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--solver", choices=["bicgstab", "fgmres"], default="bicgstab")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--row-split", type=int, default=0,
+                    help="threads per scalar row on levels under 65,536 block rows (0 = automatic)")
     ap.add_argument("--spmv-only", action="store_true",
                     help="only the FP64 block SpMV (both numberings) and a 1 GiB copy, for counter runs")
     return ap.parse_args()
@@ -154,7 +156,8 @@ def main():
                   precond=P.PREC_AMG, tol=1e-8, max_iter=500,
                   smoother=P.SMOOTH_DILU if args.smoother == "dilu" else P.SMOOTH_BJACOBI,
                   dilu_levels=args.dilu_levels, pre_sweeps=args.sweeps, post_sweeps=args.sweeps,
-                  omega=args.omega, coarse_max=args.coarse_max, match_passes=args.passes)
+                  omega=args.omega, coarse_max=args.coarse_max, match_passes=args.passes,
+                  row_split=args.row_split)
     opt_mixed = P.default_options(precision=P.PRECISION_MIXED, **common)
     opt_fp64 = P.default_options(precision=P.PRECISION_FP64, **common)
 
@@ -187,6 +190,8 @@ def main():
         stats.append(st)
     torch.cuda.synchronize()
     t_mixed = (time.perf_counter() - t0) / args.steps * 1e3
+    if st["precision_fallback"]:
+        log("WARNING: the mixed-precision hierarchy escalated to FP64")
     log("mixed: %.2f ms/step, iterations %d, relres %.3e, setup %.2f ms, solve %.2f ms"
         % (t_mixed, st["iterations"], st["rel_res_true"], st["t_setup_ms"], st["t_solve_ms"]))
 
@@ -258,8 +263,9 @@ def main():
                    "step": "pack fields + update_values + setup + solve + unpack fields",
                    "solver": args.solver, "smoother": args.smoother, "dilu_levels": args.dilu_levels,
                    "sweeps": args.sweeps, "omega": args.omega, "coarse_max": args.coarse_max,
-                   "match_passes": args.passes},
+                   "match_passes": args.passes, "row_split": args.row_split},
         "iterations": st["iterations"],
+        "precision_fallback": st["precision_fallback"],
         "rel_res_true": st["rel_res_true"],
         "levels": st["levels"],
         "op_complexity": round(st["op_complexity"], 3),

@@ -91,6 +91,11 @@ typedef struct cbs_options {
     int32_t dilu_levels;     /* smoother DILU: the dilu_levels finest levels use
                                 multicolour DILU, coarser ones damped block
                                 Jacobi; < 0 = every level            [2] */
+    int32_t row_split;       /* block-row kernels on levels of fewer than
+                                65,536 block rows: threads that share one
+                                scalar row (1, 2, 4, 8 or 16); 0 = chosen from
+                                the level's mean row length. Changes only the
+                                order of the row sums                [0] */
 } cbs_options;
 
 /* Per-solve statistics (Algorithm amgxFoam: iterations and residuals). */

@@ -33,7 +33,7 @@ class Options(C.Structure):
         ("omega", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
         ("precision", C.c_int32), ("coarse_max", C.c_int32), ("match_passes", C.c_int32),
         ("max_levels", C.c_int32), ("reuse_aggregates", C.c_int32), ("check_every", C.c_int32),
-        ("renumber", C.c_int32), ("dilu_levels", C.c_int32),
+        ("renumber", C.c_int32), ("dilu_levels", C.c_int32), ("row_split", C.c_int32),
     ]
 
 

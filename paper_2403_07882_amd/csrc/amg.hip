@@ -931,6 +931,7 @@ std::vector<int64_t> level_sys_off(cbs_system *h, Level &L) {
 void alloc_level_vectors(cbs_system *h, Level &L, bool mixed) {
     const size_t bytes = (size_t)L.N * h->n * (mixed ? sizeof(float) : sizeof(double));
     L.vb.ensure(bytes); L.vx.ensure(bytes); L.vr.ensure(bytes); L.vt.ensure(bytes);
+    if (L.scaled) L.vc.ensure(bytes);
 }
 
 }  // namespace
@@ -987,6 +988,7 @@ void amg_setup(cbs_system *h) {
         h->lev.resize(1);
         level_sell(h, L0, false, false);
         L0.sell.sched64 = autotune_rows(n, L0.sell, false, L0.sell.v64.get(), st);
+        L0.sell.sched64.split = row_split_for(L0.sell, o.row_split);
         h->op_complexity = 1.0;
         return;
     }
@@ -1076,6 +1078,13 @@ void amg_setup(cbs_system *h) {
         }
         pt.mark("smoother" + std::to_string(q));
         if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, reuse);
+        L.scaled = mixed && q + 1 < nlev && !L.dilu;
+        if (L.scaled) {
+            L.sell.v32s.ensure(L.sell.nent > 0 ? (size_t)L.sell.nent * n * n : 1);
+            sell_scale(n, L.sell, L.Dinv.get(), L.sell.v32s.get(), st);
+        } else {
+            L.sell.v32s.release();
+        }
         alloc_level_vectors(h, L, mixed);
         pt.mark("sell" + std::to_string(q));
     }
@@ -1084,7 +1093,11 @@ void amg_setup(cbs_system *h) {
         Level &T0 = h->lev[0];
         const Sched s64 = autotune_rows(n, T0.sell, false, T0.sell.v64.get(), st);
         const Sched s32 = mixed ? autotune_rows(n, T0.sell, true, T0.sell.v32.get(), st) : Sched{4, 1};
-        for (auto &L : h->lev) { L.sell.sched64 = s64; L.sell.sched32 = s32; }
+        for (auto &L : h->lev) {
+            L.sell.sched64 = s64;
+            L.sell.sched32 = s32;
+            L.sell.sched64.split = L.sell.sched32.split = row_split_for(L.sell, o.row_split);
+        }
         pt.mark("autotune");
     }
     if (mixed) {
@@ -1095,6 +1108,9 @@ void amg_setup(cbs_system *h) {
             const int64_t tot = L.sell.nent * n * n;
             if (tot > 0)
                 hipLaunchKernelGGL(k_nonfinite_f32, dim3(cdiv(tot, 256)), dim3(256), 0, st, tot, L.sell.v32.get(),
+                                   h->dflag.get());
+            if (tot > 0 && L.scaled)
+                hipLaunchKernelGGL(k_nonfinite_f32, dim3(cdiv(tot, 256)), dim3(256), 0, st, tot, L.sell.v32s.get(),
                                    h->dflag.get());
         }
         LAUNCHCHK();
@@ -1271,7 +1287,10 @@ void spmv_user(cbs_system *h, const double *x, double *y, bool transposed) {
             U.v64.alloc(nv > 0 ? nv : 1);
             sell_fill(n, U, h->vals.get(), U.v64.get(), h->stream);
         }
-        if (tune) U.sched64 = autotune_rows(n, U, false, U.v64.get(), h->stream);
+        if (tune) {
+            U.sched64 = autotune_rows(n, U, false, U.v64.get(), h->stream);
+            U.sched64.split = row_split_for(U, h->opt.row_split);
+        }
         launch_rows<double, double>(0, n, U.view(), U.v64.get(), x, nullptr, y, nullptr, 0.0, h->stream);
         return;
     }

@@ -97,6 +97,7 @@ constexpr int kSlice = 16;
 struct Sched {
     int8_t unroll = 4;
     int8_t nontemporal = 0;
+    int8_t split = 1;       // threads sharing one scalar row (1, 2, 4, 8, 16)
 };
 
 struct SellView {
@@ -111,6 +112,7 @@ struct Sell {
     DArr<int32_t> soff, sw, scol, ssrc;   // ssrc: BCSR slot of each entry, -1 = padding
     DArr<double> v64, v64T;
     DArr<float> v32, v32T;
+    DArr<float> v32s;                     // FP32 Dinv_i A_ij: values of the scaled sweep
     Sched sched64{4, 0}, sched32{4, 1};
     SellView view(bool fp32 = false) const {
         return SellView{N, soff.get(), sw.get(), scol.get(), fp32 ? sched32 : sched64};
@@ -136,6 +138,9 @@ struct Level {
     std::vector<int64_t> sys_off;
     // smoother data (FP64 per the block-inversion rule)
     DArr<double> Dinv, DinvT;
+    // mixed precision, block Jacobi: the FP32 sweeps run on row-scaled values
+    // (sell.v32s) with the level's Dinv b kept in vc
+    bool scaled = false;
     // DILU: colour classes (rows of colour c: rows_by_colour[colour_off[c] ..
     // colour_off[c+1])) and the FP64 inverses of the DILU diagonal E
     bool dilu = false;
@@ -148,7 +153,7 @@ struct Level {
     DArr<int32_t> agg, agg_ptr, agg_mem;
     int32_t nc = 0;
     // level vectors in the hierarchy precision (bytes)
-    DArr<char> vb, vx, vr, vt;
+    DArr<char> vb, vx, vr, vt, vc;
     // solve-phase matrix copy
     Sell sell;
 };
@@ -239,15 +244,21 @@ void gradient(cbs_system *h, const double *lam, const double *x, double *gd, dou
 
 // block-row kernels (spmv.hip).  T = FP64 or FP32 level precision.
 //   mode 0: y = A x;  mode 1: y = b - A x;  mode 2: y = x + omega Dinv (b - A x)
-//   mode 3: y = omega Dinv b (block-Jacobi sweep from a zero guess)
+//   mode 3: y = omega Dinv b (block-Jacobi sweep from a zero guess), and
+//           aux = Dinv b when aux is not null
+//   mode 4: y = x + omega (b - A x) on row-scaled values Dinv A with b = Dinv b
 template <typename TV, typename TX>
 void launch_rows(int mode, int n, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y,
-                 const double *Dinv, double omega, hipStream_t st);
+                 const double *Dinv, double omega, hipStream_t st, TX *aux = nullptr);
 // time the schedules of the residual kernel on S (cached per shape)
 Sched autotune_rows(int n, const Sell &S, bool fp32, const void *val, hipStream_t st);
+// threads per scalar row of the block-row kernels on a level (row_split option)
+int8_t row_split_for(const Sell &S, int32_t opt_split);
 // sliced-ELL pattern from BCSR, and values gathered from BCSR values
 void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st);
 void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st);
+// out = FP32(Dinv_i A_ij) for every entry of the FP64 sliced values S.v64
+void sell_scale(int n, const Sell &S, const double *Dinv, float *out, hipStream_t st);
 template <typename TX>
 void launch_restrict(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem,
                      const TX *r, TX *bc, hipStream_t st);

@@ -447,13 +447,26 @@ void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
     const int switches = (nu1 >= 1 ? nu1 - 1 : 0) + nu2;
     T *cur = (switches % 2 == 0) ? x : tmp;
     T *oth = (cur == x) ? tmp : x;
+    // FP32 forward sweeps run on the row-scaled values Dinv A against
+    // c = Dinv b, which the zero-guess sweep leaves behind
+    const bool scaled = sizeof(T) == sizeof(float) && !tr && L.scaled;
+    const T *sval = scaled ? reinterpret_cast<const T *>(L.sell.v32s.get()) : nullptr;
+    T *c = scaled ? vptr<T>(L.vc) : nullptr;
+    auto sweep = [&](T *from, T *to) {
+        if (scaled)
+            launch_rows<T, T>(4, n, L.sell.view(true), sval, from, c, to, nullptr, o.omega, st);
+        else
+            launch_rows<T, T>(2, n, L.sell.view(sizeof(T) == 4), val, from, b, to, Dinv, o.omega, st);
+    };
     if (nu1 >= 1) {
-        launch_rows<T, T>(3, n, L.sell.view(sizeof(T) == 4), val, cur, b, cur, Dinv, o.omega, st);
+        launch_rows<T, T>(3, n, L.sell.view(sizeof(T) == 4), val, cur, b, cur, Dinv, o.omega, st, c);
         for (int s = 1; s < nu1; ++s) {
-            launch_rows<T, T>(2, n, L.sell.view(sizeof(T) == 4), val, cur, b, oth, Dinv, o.omega, st);
+            sweep(cur, oth);
             std::swap(cur, oth);
         }
     } else {
+        if (scaled && nu2 > 0)   // c only; oth is scratch here
+            launch_rows<T, T>(3, n, L.sell.view(true), val, oth, b, oth, Dinv, o.omega, st, c);
         launch_fill<T>((int64_t)L.N * n, cur, st);
     }
     launch_rows<T, T>(1, n, L.sell.view(sizeof(T) == 4), val, cur, b, r, Dinv, o.omega, st);
@@ -463,7 +476,7 @@ void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
     vcycle<T>(h, tr, l + 1, bc, xc);
     launch_prolong<T>(n, L.N, L.agg.get(), xc, cur, st);
     for (int s = 0; s < nu2; ++s) {
-        launch_rows<T, T>(2, n, L.sell.view(sizeof(T) == 4), val, cur, b, oth, Dinv, o.omega, st);
+        sweep(cur, oth);
         std::swap(cur, oth);
     }
 }

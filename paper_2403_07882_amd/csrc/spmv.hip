@@ -70,13 +70,16 @@ __device__ inline void load_x<4, float>(const float *__restrict__ p, float (&v)[
 }
 
 // mode 0: y = A x; 1: y = b - A x; 2: y = x + w Dinv (b - A x); 3: y = w Dinv b
+// (and aux = Dinv b when aux is given); 4: y = x + w (b - A x), the sweep of
+// mode 2 on row-scaled values Dinv A with b = Dinv b.
 // Rows are read from the sliced-ELL copy: at step k the 16 rows of a slice
 // read 16 consecutive blocks; four steps are loaded before they are summed,
 // and the sums run in the row's column order.
 template <int n, typename TV, typename TX, int MODE, int U, bool NT>
 __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restrict__ val, const TX *__restrict__ x,
                                                  const TX *__restrict__ b, TX *__restrict__ y,
-                                                 const double *__restrict__ Dinv, double omega) {
+                                                 const double *__restrict__ Dinv, double omega,
+                                                 TX *__restrict__ aux) {
     using A = typename Acc<TX>::type;
     constexpr int nn = n * n;
     const int t = threadIdx.x;
@@ -130,6 +133,10 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
         if (i < N) y[o] = (TX)res;
         return;
     }
+    if (MODE == 4) {
+        if (i < N) y[o] = (TX)((A)x[o] + (A)omega * res);
+        return;
+    }
     __shared__ A sres[64 * n];
     sres[t] = res;
     __syncthreads();
@@ -140,17 +147,97 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
         for (int c = 0; c < n; ++c) z += Di[c] * (double)sres[lr * n + c];
         const A xi = (MODE == 2) ? (A)x[o] : (A)0;
         y[o] = (TX)(xi + (A)(omega * z));
+        if (MODE == 3 && aux) aux[o] = (TX)z;
+    }
+}
+
+// Coarse levels have few block rows with many blocks each, so the chain of
+// dependent loads (column, then x) along a row, not bandwidth, sets the time.
+// Here SP threads share each scalar row: thread kk takes blocks kk, kk + SP,
+// ...; the SP partial sums meet in LDS and are added in kk order.  A
+// workgroup covers 64 / SP block rows.
+template <int n, typename TV, typename TX, int MODE, int SP>
+__global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__restrict__ val,
+                                                       const TX *__restrict__ x, const TX *__restrict__ b,
+                                                       TX *__restrict__ y, const double *__restrict__ Dinv,
+                                                       double omega, TX *__restrict__ aux) {
+    using A = typename Acc<TX>::type;
+    constexpr int nn = n * n, R = 64 / SP;
+    const int t = threadIdx.x;
+    const int lr = t / (n * SP), kr = t - lr * (n * SP);
+    const int kk = kr / n, r = kr - kk * n;
+    const int32_t i = blockIdx.x * R + lr;
+    const int32_t N = S.N;
+    A acc = 0;
+    if (i < N) {
+        const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+        const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
+        for (int32_t k = kk; k < w; k += SP) {
+            const int64_t e = base + (int64_t)k * kSlice;
+            const int32_t j = S.scol[e];
+            if (j < 0) continue;
+            TV bv[n];
+            TX xv[n];
+            load_row_nt<n, TV, false>(val + e * nn + r * n, bv);
+            load_x<n, TX>(x + (int64_t)j * n, xv);
+#pragma unroll
+            for (int c = 0; c < n; ++c) acc += (A)bv[c] * (A)xv[c];
+        }
+    }
+    __shared__ A spart[64 * n];
+    __shared__ A sres[R * n];
+    spart[t] = acc;
+    __syncthreads();
+    const int64_t o = (int64_t)i * n + r;
+    if (kk == 0) {
+        A sum = 0;
+#pragma unroll
+        for (int q = 0; q < SP; ++q) sum += spart[lr * n * SP + q * n + r];
+        if (MODE == 0) {
+            if (i < N) y[o] = (TX)sum;
+        } else {
+            const A res = (i < N) ? (A)b[o] - sum : (A)0;
+            if (MODE == 1) {
+                if (i < N) y[o] = (TX)res;
+            } else if (MODE == 4) {
+                if (i < N) y[o] = (TX)((A)x[o] + (A)omega * res);
+            } else {
+                sres[lr * n + r] = res;
+            }
+        }
+    }
+    if (MODE != 2) return;
+    __syncthreads();
+    if (kk == 0 && i < N) {
+        const double *Di = Dinv + (int64_t)i * nn + r * n;
+        double z = 0.0;
+#pragma unroll
+        for (int c = 0; c < n; ++c) z += Di[c] * (double)sres[lr * n + c];
+        y[o] = (TX)((A)x[o] + (A)(omega * z));
     }
 }
 
 template <int n, typename TV, typename TX, int MODE>
 void rows_nm(const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, const double *Dinv, double omega,
-             hipStream_t st) {
+             TX *aux, hipStream_t st) {
     const dim3 g(cdiv(S.N, 64)), bl(64 * n);
     const int u = S.sched.unroll;
     const bool nt = S.sched.nontemporal != 0;
-#define ROWS_V(UU, NTT) hipLaunchKernelGGL((k_rows<n, TV, TX, MODE, UU, NTT>), g, bl, 0, st, S, val, x, b, y, Dinv, omega)
+#define ROWS_V(UU, NTT) \
+    hipLaunchKernelGGL((k_rows<n, TV, TX, MODE, UU, NTT>), g, bl, 0, st, S, val, x, b, y, Dinv, omega, aux)
     if (MODE == 3) { ROWS_V(1, false); return; }       // no matrix read
+    const int sp = S.sched.split;
+    if (sp > 1) {
+        const dim3 gs(cdiv((int64_t)S.N * sp, 64));
+#define ROWS_S(SS) \
+    hipLaunchKernelGGL((k_rows_split<n, TV, TX, MODE, SS>), gs, bl, 0, st, S, val, x, b, y, Dinv, omega, aux)
+        if (sp == 2) ROWS_S(2);
+        else if (sp == 4) ROWS_S(4);
+        else if (sp == 8) ROWS_S(8);
+        else ROWS_S(16);
+#undef ROWS_S
+        return;
+    }
     if (u <= 1) { if (nt) ROWS_V(1, true); else ROWS_V(1, false); }
     else if (u == 2) { if (nt) ROWS_V(2, true); else ROWS_V(2, false); }
     else { if (nt) ROWS_V(4, true); else ROWS_V(4, false); }
@@ -159,12 +246,13 @@ void rows_nm(const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, 
 
 template <int n, typename TV, typename TX>
 void rows_n(int mode, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, const double *Dinv,
-            double omega, hipStream_t st) {
+            double omega, TX *aux, hipStream_t st) {
     switch (mode) {
-        case 0: rows_nm<n, TV, TX, 0>(S, val, x, b, y, Dinv, omega, st); break;
-        case 1: rows_nm<n, TV, TX, 1>(S, val, x, b, y, Dinv, omega, st); break;
-        case 2: rows_nm<n, TV, TX, 2>(S, val, x, b, y, Dinv, omega, st); break;
-        case 3: rows_nm<n, TV, TX, 3>(S, val, x, b, y, Dinv, omega, st); break;
+        case 0: rows_nm<n, TV, TX, 0>(S, val, x, b, y, Dinv, omega, aux, st); break;
+        case 1: rows_nm<n, TV, TX, 1>(S, val, x, b, y, Dinv, omega, aux, st); break;
+        case 2: rows_nm<n, TV, TX, 2>(S, val, x, b, y, Dinv, omega, aux, st); break;
+        case 3: rows_nm<n, TV, TX, 3>(S, val, x, b, y, Dinv, omega, aux, st); break;
+        case 4: rows_nm<n, TV, TX, 4>(S, val, x, b, y, Dinv, omega, aux, st); break;
     }
 }
 
@@ -306,6 +394,38 @@ __global__ void k_sell_vals(int64_t nent, const int32_t *__restrict__ ssrc, cons
     out[g] = k >= 0 ? in[(int64_t)k * nn + (g - e * nn)] : 0.0;
 }
 
+// Row-scaled FP32 values for the block-Jacobi sweep: entry (i, j) becomes
+// Dinv_i A_ij, formed in FP64 and rounded once.  One thread per (slice row,
+// r); the rows that pad the last slice past N get zeros like every other
+// padding entry.
+template <int n>
+__global__ void k_sell_scaled(int32_t N, int32_t nslices, const int32_t *__restrict__ soff,
+                              const int32_t *__restrict__ sw, const double *__restrict__ v64,
+                              const double *__restrict__ Dinv, float *__restrict__ out) {
+    constexpr int nn = n * n;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)nslices * kSlice * n) return;
+    const int32_t i = (int32_t)(g / n);
+    const int r = (int)(g - (int64_t)i * n);
+    const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+    const int64_t base = (int64_t)soff[sl] + ii;
+    const int32_t w = sw[sl];
+    double d[n];
+#pragma unroll
+    for (int q = 0; q < n; ++q) d[q] = i < N ? Dinv[(int64_t)i * nn + r * n + q] : 0.0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t e = base + (int64_t)k * kSlice;
+        const double *a = v64 + e * nn;
+#pragma unroll
+        for (int c = 0; c < n; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < n; ++q) acc += d[q] * a[q * n + c];
+            out[e * nn + r * n + c] = (float)acc;
+        }
+    }
+}
+
 template <typename TX>
 __global__ void k_restrict(int32_t nc, int n, const int32_t *__restrict__ aptr, const int32_t *__restrict__ amem,
                            const TX *__restrict__ r, TX *__restrict__ bc) {
@@ -372,21 +492,21 @@ __global__ void k_block_apply(int32_t N, const double *__restrict__ Dinv, const 
 
 template <typename TV, typename TX>
 void launch_rows(int mode, int n, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y,
-                 const double *Dinv, double omega, hipStream_t st) {
+                 const double *Dinv, double omega, hipStream_t st, TX *aux) {
     if (S.N <= 0) return;
     switch (n) {
-        case 1: rows_n<1>(mode, S, val, x, b, y, Dinv, omega, st); break;
-        case 2: rows_n<2>(mode, S, val, x, b, y, Dinv, omega, st); break;
-        case 3: rows_n<3>(mode, S, val, x, b, y, Dinv, omega, st); break;
-        case 4: rows_n<4>(mode, S, val, x, b, y, Dinv, omega, st); break;
-        case 5: rows_n<5>(mode, S, val, x, b, y, Dinv, omega, st); break;
+        case 1: rows_n<1>(mode, S, val, x, b, y, Dinv, omega, aux, st); break;
+        case 2: rows_n<2>(mode, S, val, x, b, y, Dinv, omega, aux, st); break;
+        case 3: rows_n<3>(mode, S, val, x, b, y, Dinv, omega, aux, st); break;
+        case 4: rows_n<4>(mode, S, val, x, b, y, Dinv, omega, aux, st); break;
+        case 5: rows_n<5>(mode, S, val, x, b, y, Dinv, omega, aux, st); break;
     }
     LAUNCHCHK();
 }
 template void launch_rows<double, double>(int, int, const SellView &, const double *, const double *, const double *,
-                                          double *, const double *, double, hipStream_t);
+                                          double *, const double *, double, hipStream_t, double *);
 template void launch_rows<float, float>(int, int, const SellView &, const float *, const float *, const float *,
-                                        float *, const double *, double, hipStream_t);
+                                        float *, const double *, double, hipStream_t, float *);
 
 void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st) {
     S.N = N;
@@ -422,6 +542,24 @@ void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipSt
         case 4: hipLaunchKernelGGL(k_sell_vals<4>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
         case 5: hipLaunchKernelGGL(k_sell_vals<5>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
     }
+    LAUNCHCHK();
+}
+
+void sell_scale(int n, const Sell &S, const double *Dinv, float *out, hipStream_t st) {
+    const int64_t m = (int64_t)S.nslices * kSlice * n;
+    if (S.N <= 0) return;
+    const dim3 g(cdiv(m, 256)), b(256);
+#define SCALE_N(NN)                                                                                           \
+    hipLaunchKernelGGL(k_sell_scaled<NN>, g, b, 0, st, S.N, S.nslices, S.soff.get(), S.sw.get(), S.v64.get(), \
+                       Dinv, out)
+    switch (n) {
+        case 1: SCALE_N(1); break;
+        case 2: SCALE_N(2); break;
+        case 3: SCALE_N(3); break;
+        case 4: SCALE_N(4); break;
+        case 5: SCALE_N(5); break;
+    }
+#undef SCALE_N
     LAUNCHCHK();
 }
 
@@ -561,6 +699,19 @@ namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int32_t, int64_t, int, bool>, Sched> g_tune_cache;
 }  // namespace
+
+// Levels of fewer than kSplitRows block rows split each row over several
+// threads; automatic choice: the largest power of two (at most 16) that still
+// leaves every thread about four blocks of a mean-length row.
+constexpr int32_t kSplitRows = 65536;
+int8_t row_split_for(const Sell &S, int32_t opt_split) {
+    if (S.N <= 0 || S.N >= kSplitRows) return 1;
+    if (opt_split > 0) return (int8_t)opt_split;
+    const double w = (double)S.nent / S.N;
+    int s = 1;
+    while (s < 16 && 4.0 * (2 * s) <= w) s *= 2;
+    return (int8_t)s;
+}
 
 Sched autotune_rows(int n, const Sell &S, bool fp32, const void *val, hipStream_t st) {
     const auto key = std::make_tuple(S.N, S.nent, n, fp32);

@@ -46,3 +46,16 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         B.lib()
+
+
+def test_options_and_stats_layout_match_the_header():
+    """The ctypes structures list the header's fields in the header's order."""
+    import paper_2403_07882_amd as P
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for cname, cls in (("cbs_options", P.Options), ("cbs_stats", P.Stats)):
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (cname, cname), src, re.S).group(1)
+        fields = re.findall(r"\b(int32_t|double)\s+([a-z_0-9]+)\s*;", body)
+        assert [f for _, f in fields] == [f for f, _ in cls._fields_], cname
+        kinds = {"int32_t": "c_int", "double": "c_double"}
+        for (ct, _), (_, pt) in zip(fields, cls._fields_):
+            assert pt.__name__.startswith(kinds[ct]), (cname, ct, pt)

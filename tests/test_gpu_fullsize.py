@@ -44,7 +44,7 @@ def test_stretched_density_8M_mixed_fgmres():
         sysm.setup(precision=P.PRECISION_MIXED, solver=P.SOLVER_FGMRES, restart=30, tol=1e-8)
         x, st = sysm.solve(s["b"])
         _say("gpu:", st)
-    assert st["status"] == P.OK, st
+    assert st["status"] == P.OK and st["precision_fallback"] == 0, st
     rr = _relres_ldu(s, _np(x))
     _say("oracle relres %.3e" % rr)
     assert rr <= 1e-8 * 1.0001
@@ -64,7 +64,7 @@ def test_batch_64_uneven_systems():
     co, fo = cat["cell_off"], cat["face_off"]
     sizes = np.diff(co)
     for k in range(64):
-        assert stats[k]["status"] == P.OK, (k, stats[k])
+        assert stats[k]["status"] == P.OK and stats[k]["precision_fallback"] == 0, (k, stats[k])
         sk = {"N": int(sizes[k]), "n": 5, "lower_addr": cat["lower_addr"][fo[k]:fo[k + 1]],
               "upper_addr": cat["upper_addr"][fo[k]:fo[k + 1]], "diag": cat["diag"][co[k]:co[k + 1]],
               "upper": cat["upper"][fo[k]:fo[k + 1]], "lower": cat["lower"][fo[k]:fo[k + 1]],

@@ -134,6 +134,23 @@ def test_spmv_and_transpose(n):
     assert np.abs(yt - reft).max() <= 1e-14 * scale
 
 
+@pytest.mark.parametrize("n,split", [(4, 2), (4, 16), (5, 4), (5, 8), (1, 16)])
+def test_spmv_row_split(n, split):
+    """Rows shared by several threads (the coarse-level kernel): same product,
+    including rows shorter than the split and the transposed product."""
+    _say("spmv row split", n, split)
+    s = jacobian_box(13, 6, 5, n=n, seed=n) if n != 4 else pressure_velocity(13, 6, 5, seed=3)
+    A = O.from_system(s)
+    x = np.random.default_rng(2).standard_normal((s["N"], n))
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_NONE, row_split=split)
+        y = _np(sysm.spmv(x))
+        yt = _np(sysm.spmv(x, transpose=True))
+    scale = np.abs(A.vals).max() * np.abs(x).max() * 8
+    assert np.abs(y - O.spmv(A, x)).max() <= 1e-14 * scale
+    assert np.abs(yt - O.spmv_t(A, x)).max() <= 1e-14 * scale
+
+
 def test_spmv_empty_rows_and_no_faces():
     rng = np.random.default_rng(3)
     D = rng.standard_normal((70, 4, 4))
@@ -169,6 +186,7 @@ def test_amg_solve_pressure_velocity(precision, solver):
         sysm.setup(precond=P.PREC_AMG, precision=precision, solver=solver, tol=1e-8)
         x, st = sysm.solve(s["b"])
         assert st["status"] == P.OK and st["levels"] > 1, st
+        assert st["precision_fallback"] == 0, st          # the FP32 hierarchy really ran
         rr, _ = _check_solution(A, s["b"], _np(x), xref, err=1e-5)
         # tighter verification solve for the 1e-6 solution-error bar
         sysm.setup(precond=P.PREC_AMG, precision=precision, solver=solver, tol=1e-11)
@@ -219,13 +237,14 @@ def test_solve_is_deterministic():
 
 
 # ------------------------------------------------------------------ AMG pieces
-@pytest.mark.parametrize("renumber", [0, 1])
-def test_rap_and_vcycle_match_oracle_given_gpu_aggregates(renumber):
-    _say("rap/vcycle parity renumber", renumber)
+@pytest.mark.parametrize("renumber,split", [(0, 0), (1, 0), (1, 1), (1, 16)])
+def test_rap_and_vcycle_match_oracle_given_gpu_aggregates(renumber, split):
+    _say("rap/vcycle parity renumber", renumber, "row split", split)
     s = pressure_velocity(10, 9, 8, seed=4)
     A = O.from_system(s)
     with P.System.from_dict(s) as sysm:
-        sysm.setup(precond=P.PREC_AMG, coarse_max=8, pre_sweeps=1, post_sweeps=1, omega=0.8, renumber=renumber)
+        sysm.setup(precond=P.PREC_AMG, coarse_max=8, pre_sweeps=1, post_sweeps=1, omega=0.8, renumber=renumber,
+                   row_split=split)
         nlev = sysm.info()["levels"]
         assert nlev >= 3
         lv0 = sysm.get_level(0)
@@ -262,6 +281,32 @@ def test_rap_and_vcycle_match_oracle_given_gpu_aggregates(renumber):
     zr_int = amg.apply(r[order])
     zr = np.empty_like(zr_int); zr[order] = zr_int
     assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+
+
+@pytest.mark.parametrize("split,pre,post", [(0, 2, 2), (16, 2, 2), (0, 1, 3), (0, 0, 2)])
+def test_mixed_vcycle_matches_fp64_oracle_vcycle(split, pre, post):
+    """The mixed-precision V-cycle (FP32 levels, block-Jacobi sweeps on row-scaled
+    values) is the oracle's FP64 V-cycle on the same hierarchy up to FP32 rounding."""
+    _say("mixed vcycle split", split, "sweeps", pre, post)
+    s = pressure_velocity(12, 10, 9, seed=5)
+    A = O.from_system(s)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, precision=P.PRECISION_MIXED, coarse_max=8, pre_sweeps=pre,
+                   post_sweeps=post, omega=0.9, row_split=split)
+        nlev = sysm.info()["levels"]
+        assert nlev >= 3
+        lv0 = sysm.get_level(0)
+        order = _np(lv0["order"])
+        A0 = O.BCSR(A.N, 4, _np(lv0["row_ptr"]), _np(lv0["col"]), _np(lv0["vals"]))
+        aggs = [_np(sysm.get_level(l)["agg"]) for l in range(nlev - 1)]
+        r = np.random.default_rng(1).standard_normal((A.N, 4))
+        z = _np(sysm.apply_precond(r))
+        _, st = sysm.solve(s["b"])
+        assert st["status"] == P.OK and st["precision_fallback"] == 0, st
+    amg = O.AMG(A0, nu1=pre, nu2=post, omega=0.9, aggs=aggs)
+    zr_int = amg.apply(r[order])
+    zr = np.empty_like(zr_int); zr[order] = zr_int
+    assert np.linalg.norm(z - zr) <= 1e-5 * np.linalg.norm(zr)
 
 
 def test_renumbering_keeps_the_solution():
@@ -381,6 +426,7 @@ def test_batched_solve_matches_solo_solves():
             A = O.from_system(s)
             xk = xn[cat["cell_off"][k]:cat["cell_off"][k + 1]]
             assert stats[k]["status"] == P.OK, (k, stats[k])
+            assert stats[k]["precision_fallback"] == 0, (k, stats[k])
             assert O.relres(A, s["b"], xk) <= 1e-8 * 1.0001
             xref = _ref_solution(A, s["b"])
             kappa_tol = 1e-8 * 50
