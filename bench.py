@@ -9,8 +9,10 @@ hierarchy, FP64 block inverses and coarse solve) and the mixed-precision
 AMG-BiCGStab solve to ||b - A x|| / ||b|| <= 1e-8 from x0 = 0.
 
 Also reported: the plain FP64 GPU path on the same system (mixed vs FP64),
-the FP64 block-SpMV kernel against the HBM roofline, and the CPU oracle
-timed on a bounded sample of the same workload.
+the values-only re-setup + solve variant, the level-0 smoothing sweep (the
+kernel with the largest share of the step) and the FP64 block SpMV against
+the HBM roofline next to a measured copy peak, and the CPU oracle timed on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -23,11 +25,11 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the FP64 SpMV on the internal numbering of the
-# 100x100x100 p-U system, from FETCH_SIZE and WRITE_SIZE counter runs scaled
-# by the readings of a 1 GiB copy kernel (factors 2.0 and 1.0):
-# profiles/block_spmv_fp64_pu1M_hbm_counters.md
-SPMV_TRAFFIC_PU1M = 1133719389
+# HBM bytes per launch on the 100x100x100 p-U system, from FETCH_SIZE and
+# WRITE_SIZE counter runs of `bench.py --kernels-only`, each scaled by what the
+# counter reads for a 1 GiB copy (see profiles/); None where not measured for
+# the current kernel code.
+TRAFFIC_PU1M = {"sweep": 620371076, "spmv_internal": 1133360751, "spmv_caller": 1718727495}
 
 
 def parse():
@@ -38,7 +40,6 @@ def parse():
     ap.add_argument("--mesh", type=int, nargs=3, default=[100, 100, 100])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, nargs=3, default=[80, 80, 80])
-    ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--smoother", choices=["dilu", "bjacobi"], default="bjacobi")
     ap.add_argument("--dilu-levels", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=2)
@@ -49,8 +50,10 @@ def parse():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--row-split", type=int, default=0,
                     help="threads per scalar row on levels under 65,536 block rows (0 = automatic)")
-    ap.add_argument("--spmv-only", action="store_true",
-                    help="only the FP64 block SpMV (both numberings) and a 1 GiB copy, for counter runs")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the level-0 sweep, the FP64 block SpMV (both numberings) and a 1 GiB copy, "
+                         "5 launches each, for counter runs")
     return ap.parse_args()
 
 
@@ -62,6 +65,14 @@ def spmv_bytes(N, nnzb, n, s=8):
     """Algorithmic bytes of one block SpMV: values + column indices + row
     pointers + x read once + y written once."""
     return nnzb * (n * n * s + 4) + (N + 1) * 4 + 2 * N * n * s
+
+
+def sweep_bytes(N, nnzb, n, s=4, dinv=False):
+    """Algorithmic bytes of one block-Jacobi sweep y = x + w Dinv (b - A x):
+    values + column indices + row pointers + x, b read once + y written once
+    (+ the FP64 block inverses when the sweep applies them; the row-scaled
+    FP32 sweep has them folded into its values)."""
+    return nnzb * (n * n * s + 4) + (N + 1) * 4 + 3 * N * n * s + (N * n * n * 8 if dinv else 0)
 
 
 def cpu_baseline(shape):
@@ -86,24 +97,75 @@ def cpu_baseline(shape):
     }
 
 
-def spmv_only(args, P, torch, dev, sysm, N, n, nnzb, la, ua, diag, upper, lower):
-    """FP64 block SpMV launches on both numberings plus a plain 1 GiB copy
-    (the calibration kernel of the HBM byte counters)."""
+def internal_system(P, torch, dev, sysm, N, n, la, ua, diag, upper, lower):
+    """A second handle holding the same matrix in the solver's internal
+    (aggregation-tree) row numbering, for the FP64 SpMV on that numbering."""
+    order = sysm.get_level(0)["order"].long()
+    pos = torch.empty_like(order)
+    pos[order] = torch.arange(N, device=dev)
+    return P.System(N, n, pos[la.long()].int(), pos[ua.long()].int(), diag[order], upper, lower)
+
+
+class KernelTimer:
+    """Average launch time of one library call over `reps` launches, with HIP
+    events on the stream the library launches on (torch's current stream)."""
+
+    def __init__(self, torch, reps):
+        self.torch, self.reps = torch, reps
+
+    def __call__(self, fn, warm=5):
+        for _ in range(warm):
+            fn()
+        e0 = self.torch.cuda.Event(enable_timing=True)
+        e1 = self.torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(self.reps):
+            fn()
+        e1.record()
+        self.torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / self.reps       # ms
+
+
+def level_sweep_call(P, torch, dev, sysm, n):
+    """Closure running the level-0 smoothing sweep of the current hierarchy on
+    random vectors, and whether it runs in FP32."""
+    import ctypes as C
+    L = P.lib()
+    f = C.c_int32(0)
+    L.cbs_level_apply(sysm.h, 0, P.LEVEL_SWEEP, None, None, None, C.byref(f))
+    n0 = sysm.get_level(0)["N"]
+    dt = torch.float32 if f.value else torch.float64
+    bv = torch.randn(n0 * n, dtype=dt, device=dev)
+    xv = torch.randn(n0 * n, dtype=dt, device=dev)
+    yv = torch.empty_like(xv)
+
+    def run():
+        rc = L.cbs_level_apply(sysm.h, 0, P.LEVEL_SWEEP, C.c_void_p(bv.data_ptr()), C.c_void_p(xv.data_ptr()),
+                               C.c_void_p(yv.data_ptr()), None)
+        if rc < 0:
+            raise P.CbsError(rc, "cbs_level_apply")
+    return run, bool(f.value)
+
+
+def spmv_call(P, torch, dev, system, N, n):
     import ctypes as C
     L = P.lib()
     xv = torch.randn(N * n, dtype=torch.float64, device=dev)
     yv = torch.empty_like(xv)
-    sysm.setup(P.default_options(precision=P.PRECISION_MIXED))
-    order = sysm.get_level(0)["order"].long()
-    pos = torch.empty_like(order)
-    pos[order] = torch.arange(N, device=dev)
-    sys2 = P.System(N, n, pos[la.long()].int(), pos[ua.long()].int(), diag[order], upper, lower)
-    res = {}
-    for name, system in (("caller", sysm), ("internal", sys2)):
-        for _ in range(args.spmv_reps):
-            L.cbs_spmv(system.h, C.c_void_p(xv.data_ptr()), C.c_void_p(yv.data_ptr()), 0)
+    return lambda: L.cbs_spmv(system.h, C.c_void_p(xv.data_ptr()), C.c_void_p(yv.data_ptr()), 0)
+
+
+def kernels_only(args, P, torch, dev, sysm, opt_mixed, N, n, nnzb, la, ua, diag, upper, lower):
+    """Five launches each of the level-0 mixed-precision sweep and the FP64
+    block SpMV on both numberings, then a plain 1 GiB copy (the calibration
+    kernel of the HBM byte counters)."""
+    sysm.setup(opt_mixed)
+    sweep, _ = level_sweep_call(P, torch, dev, sysm, n)
+    sys2 = internal_system(P, torch, dev, sysm, N, n, la, ua, diag, upper, lower)
+    for fn in (sweep, spmv_call(P, torch, dev, sysm, N, n), spmv_call(P, torch, dev, sys2, N, n)):
+        for _ in range(5):
+            fn()
         torch.cuda.synchronize()
-        res[name] = args.spmv_reps
     a = torch.empty(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB
     a.fill_(1.0)
     bcopy = torch.empty_like(a)
@@ -111,8 +173,10 @@ def spmv_only(args, P, torch, dev, sysm, N, n, nnzb, la, ua, diag, upper, lower)
         bcopy.copy_(a)
     torch.cuda.synchronize()
     sys2.close()
-    print(json.dumps({"spmv_launches_per_numbering": args.spmv_reps,
-                      "algorithmic_bytes_per_spmv": int(spmv_bytes(N, nnzb, n)),
+    lv = sysm.get_level(0)
+    print(json.dumps({"launches_per_kernel": 5, "order": ["sweep", "spmv caller", "spmv internal", "copy"],
+                      "algorithmic_bytes_sweep": int(sweep_bytes(lv["N"], lv["nnzb"], n)),
+                      "algorithmic_bytes_spmv": int(spmv_bytes(N, nnzb, n)),
                       "copy_bytes_read": int(a.numel() * 8), "copy_bytes_written": int(a.numel() * 8)}))
 
 
@@ -149,9 +213,6 @@ def main():
     del s
     sysm = P.System(N, n, la, ua, diag, upper, lower)
     nnzb = sysm.info()["nnzb"]
-    if args.spmv_only:
-        spmv_only(args, P, torch, dev, sysm, N, n, nnzb, la, ua, diag, upper, lower)
-        return
     common = dict(solver=P.SOLVER_BICGSTAB if args.solver == "bicgstab" else P.SOLVER_FGMRES,
                   precond=P.PREC_AMG, tol=1e-8, max_iter=500,
                   smoother=P.SMOOTH_DILU if args.smoother == "dilu" else P.SMOOTH_BJACOBI,
@@ -159,14 +220,18 @@ def main():
                   omega=args.omega, coarse_max=args.coarse_max, match_passes=args.passes,
                   row_split=args.row_split)
     opt_mixed = P.default_options(precision=P.PRECISION_MIXED, **common)
+    opt_reuse = P.default_options(precision=P.PRECISION_MIXED, reuse_aggregates=1, **common)
     opt_fp64 = P.default_options(precision=P.PRECISION_FP64, **common)
+    if args.kernels_only:
+        kernels_only(args, P, torch, dev, sysm, opt_mixed, N, n, nnzb, la, ua, diag, upper, lower)
+        return
 
     L = P.lib()
     import ctypes as C
     stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
     def step(opt):
-        # a1 pack -> a3 values -> setup -> solve -> a1 unpack
+        # pack fields -> LDU values to block CSR -> setup -> solve -> unpack fields
         L.cbs_pack_fields(N, n, C.c_void_p(b_fields.data_ptr()), C.c_void_p(b.data_ptr()), stream)
         sysm.update_values(diag, upper, lower)
         sysm.setup(opt)
@@ -176,73 +241,83 @@ def main():
         if rc < 0:
             raise P.CbsError(rc, "cbs_solve")
         L.cbs_unpack_fields(N, n, C.c_void_p(x.data_ptr()), C.c_void_p(x_fields.data_ptr()), stream)
-        return x, st.as_dict(), rc
+        return st.as_dict()
+
+    def run_steps(opt, k):
+        """Time k steps: total over the bracketed region, and each step."""
+        per = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            t1 = time.perf_counter()
+            st = step(opt)
+            torch.cuda.synchronize()
+            per.append((time.perf_counter() - t1) * 1e3)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k * 1e3, per, st
 
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
-        _, st, _ = step(opt_mixed)
+        step(opt_mixed)
     torch.cuda.synchronize()
     log("timing %d steps (mixed)" % args.steps)
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        xs, st, _ = step(opt_mixed)
-        stats.append(st)
-    torch.cuda.synchronize()
-    t_mixed = (time.perf_counter() - t0) / args.steps * 1e3
+    t_mixed, per_step, st = run_steps(opt_mixed, args.steps)
     if st["precision_fallback"]:
         log("WARNING: the mixed-precision hierarchy escalated to FP64")
-    log("mixed: %.2f ms/step, iterations %d, relres %.3e, setup %.2f ms, solve %.2f ms"
-        % (t_mixed, st["iterations"], st["rel_res_true"], st["t_setup_ms"], st["t_solve_ms"]))
+    log("mixed: %.2f ms/step (median %.2f), iterations %d, relres %.3e, setup %.2f ms, solve %.2f ms"
+        % (t_mixed, float(np.median(per_step)), st["iterations"], st["rel_res_true"], st["t_setup_ms"],
+           st["t_solve_ms"]))
+    # values-only re-setup (aggregates kept) + solve: the branch of the
+    # nonlinear loop where only the coefficients change
+    t_reuse, per_reuse, st_reuse = run_steps(opt_reuse, max(1, args.steps))
+    log("values-only re-setup + solve: %.2f ms/step (setup %.2f ms)" % (t_reuse, st_reuse["t_setup_ms"]))
 
     # plain FP64 GPU path on the same system
     t_fp64, st64 = float("nan"), {"iterations": -1}
     if not args.skip_fp64:
         for _ in range(max(1, args.warmup // 2)):
             step(opt_fp64)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        k64 = max(1, args.steps // 2)
-        for _ in range(k64):
-            _, st64, _ = step(opt_fp64)
-        torch.cuda.synchronize()
-        t_fp64 = (time.perf_counter() - t0) / k64 * 1e3
+        t_fp64, _, st64 = run_steps(opt_fp64, max(1, args.steps // 2))
         log("fp64: %.2f ms/step, iterations %d" % (t_fp64, st64["iterations"]))
 
-    # dominant bandwidth kernel: FP64 block SpMV, timed with events on its
-    # stream (torch's current stream, which the library was given).
-
-    def time_spmv(system):
-        xv = torch.randn(N * n, dtype=torch.float64, device=dev)
-        yv = torch.empty_like(xv)
-        for _ in range(5):
-            L.cbs_spmv(system.h, C.c_void_p(xv.data_ptr()), C.c_void_p(yv.data_ptr()), 0)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.spmv_reps):
-            L.cbs_spmv(system.h, C.c_void_p(xv.data_ptr()), C.c_void_p(yv.data_ptr()), 0)
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / args.spmv_reps
-
+    # kernels, each timed alone with HIP events on the library's stream
+    timer = KernelTimer(torch, args.kernel_reps)
+    sysm.setup(opt_mixed)
+    lv0 = sysm.get_level(0)
+    sweep, sweep_fp32 = level_sweep_call(P, torch, dev, sysm, n)
+    sweep_ms = timer(sweep)
+    sbytes = sweep_bytes(lv0["N"], lv0["nnzb"], n, 4 if sweep_fp32 else 8, dinv=not sweep_fp32)
+    sweep_gbs = sbytes / (sweep_ms * 1e-3) / 1e9
+    log("level-0 sweep (%s): %.1f us, %.0f GB/s" % ("fp32" if sweep_fp32 else "fp64", sweep_ms * 1e3, sweep_gbs))
+    r64 = torch.randn(N * n, dtype=torch.float64, device=dev)
+    z64 = torch.empty_like(r64)
+    vcyc_ms = timer(lambda: L.cbs_apply_precond(sysm.h, C.c_void_p(r64.data_ptr()), C.c_void_p(z64.data_ptr())),
+                    warm=2)
+    log("V-cycle (cbs_apply_precond, mixed): %.3f ms" % vcyc_ms)
     byts = spmv_bytes(N, nnzb, n)
-    spmv_user_ms = time_spmv(sysm)
+    spmv_user_ms = timer(spmv_call(P, torch, dev, sysm, N, n))
     gbs_user = byts / (spmv_user_ms * 1e-3) / 1e9
     log("spmv fp64 (caller numbering): %.1f us, %.0f GB/s" % (spmv_user_ms * 1e3, gbs_user))
-    # the same kernel on the solver's internal (aggregation-tree) numbering:
-    # a system built from the renumbered LDU arrays
-    sysm.setup(opt_mixed)
-    order = sysm.get_level(0)["order"].long()
-    pos = torch.empty_like(order)
-    pos[order] = torch.arange(N, device=dev)
-    la2 = pos[la.long()].int()
-    ua2 = pos[ua.long()].int()
-    sys2 = P.System(N, n, la2, ua2, diag[order], upper, lower)
-    spmv_ms = time_spmv(sys2)
+    sys2 = internal_system(P, torch, dev, sysm, N, n, la, ua, diag, upper, lower)
+    spmv_ms = timer(spmv_call(P, torch, dev, sys2, N, n))
     sys2.close()
-    del la2, ua2, order, pos
     gbs = byts / (spmv_ms * 1e-3) / 1e9
     log("spmv fp64 (internal numbering): %.1f us, %.0f GB/s" % (spmv_ms * 1e3, gbs))
+    # measured copy peak: 1 GiB device-to-device copy (read + write bytes)
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    a.fill_(1.0)
+    bcopy = torch.empty_like(a)
+    copy_ms = KernelTimer(torch, 10)(lambda: bcopy.copy_(a), warm=2)
+    copy_gbs = 2 * a.numel() * 8 / (copy_ms * 1e-3) / 1e9
+    del a, bcopy
+    log("1 GiB copy: %.1f us, %.0f GB/s" % (copy_ms * 1e3, copy_gbs))
+    full = (nx, ny, nz) == (100, 100, 100)
+
+    def kobj(name, ms, nbytes, traffic):
+        gb = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "kernel": name, "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gb / HBM_PEAK_GBS, 4), "traffic": traffic if full else None,
+                "avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes": int(nbytes)}
 
     out = {
         "metric": "coupled solve time to 1e-8 rel. residual; block-SpMV GB/s; mixed vs FP64",
@@ -264,6 +339,8 @@ def main():
                    "solver": args.solver, "smoother": args.smoother, "dilu_levels": args.dilu_levels,
                    "sweeps": args.sweeps, "omega": args.omega, "coarse_max": args.coarse_max,
                    "match_passes": args.passes, "row_split": args.row_split},
+        "step_ms_median": round(float(np.median(per_step)), 3),
+        "step_ms_all": [round(t, 3) for t in per_step],
         "iterations": st["iterations"],
         "precision_fallback": st["precision_fallback"],
         "rel_res_true": st["rel_res_true"],
@@ -272,16 +349,20 @@ def main():
         "setup_ms": round(st["t_setup_ms"], 3),
         "solve_ms": round(st["t_solve_ms"], 3),
         "convert_ms": round(st["t_convert_ms"], 3),
+        "values_only_resetup_ms_per_step": round(t_reuse, 3),
+        "values_only_setup_ms": round(st_reuse["t_setup_ms"], 3),
         "fp64_ms_per_step": round(t_fp64, 3),
         "fp64_iterations": st64["iterations"],
         "mixed_vs_fp64_speedup": round(t_fp64 / t_mixed, 3) if t_fp64 == t_fp64 else None,
-        "roofline": {"bound": "hbm", "kernel": "block SpMV FP64 (k_rows mode 0, n=4), internal numbering",
-                     "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "traffic": SPMV_TRAFFIC_PU1M if (nx, ny, nz) == (100, 100, 100) else None,
-                     "avg_launch_us": round(spmv_ms * 1e3, 2), "algorithmic_bytes": int(byts)},
-        "spmv_caller_numbering": {"achieved_gbs": round(gbs_user, 1), "avg_launch_us": round(spmv_user_ms * 1e3, 2),
-                                  "frac": round(gbs_user / HBM_PEAK_GBS, 4)},
+        "vcycle_ms": round(vcyc_ms, 4),
+        "roofline": kobj("level-0 block-Jacobi sweep, %s (k_rows, internal numbering); the kernel with the "
+                         "largest share of the step" % ("FP32 row-scaled" if sweep_fp32 else "FP64"),
+                         sweep_ms, sbytes, TRAFFIC_PU1M["sweep"]),
+        "spmv_fp64": kobj("block SpMV FP64 (k_rows mode 0), internal numbering", spmv_ms, byts,
+                          TRAFFIC_PU1M["spmv_internal"]),
+        "spmv_fp64_caller_numbering": kobj("block SpMV FP64 (k_rows mode 0), caller's random numbering",
+                                           spmv_user_ms, byts, TRAFFIC_PU1M["spmv_caller"]),
+        "copy_peak": {"achieved": round(copy_gbs, 1), "unit": "GB/s", "kernel": "1 GiB device copy (torch copy_)"},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline on %s" % (args.cpu_sample,))

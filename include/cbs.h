@@ -179,6 +179,26 @@ int cbs_spmv(cbs_handle h, const double *x, double *y, int32_t transpose);
  * (zero initial guess), in the configured precision. */
 int cbs_apply_precond(cbs_handle h, const double *r, double *z);
 
+/* Kernel-level access to the smoother of one AMG level, for verification and
+ * for timing the kernels the V-cycle runs (Sec. 2.3, smoothers).  Works on
+ * level `level` (0 .. levels-2; the coarsest level has no smoother) of the
+ * hierarchy from the last cbs_setup, in its internal row numbering, on device
+ * vectors b, x, y of n_rows(level)*bdim values in the precision the hierarchy
+ * runs in, reported in *fp32 when fp32 is not NULL (1: float, mixed precision
+ * without escalation; 0: double).  All three vectors NULL: only *fp32 is
+ * written.
+ *   op CBS_LEVEL_SWEEP:    one damped block-Jacobi sweep from x,
+ *                          y = x + omega Dinv (b - A x); in mixed precision the
+ *                          sweep runs on the row-scaled values Dinv A, so b
+ *                          must already be the scaled right side Dinv b.
+ *   op CBS_LEVEL_RESIDUAL: y = b - A x.
+ * y must not alias x.  Errors: CBS_ERR_STATE before cbs_setup, without the
+ * AMG preconditioner, or for a sweep on a DILU level; CBS_ERR_ARG for a bad
+ * level or op or a partial set of NULL vectors. */
+enum { CBS_LEVEL_SWEEP = 0, CBS_LEVEL_RESIDUAL = 1 };
+int cbs_level_apply(cbs_handle h, int32_t level, int32_t op, const void *b, const void *x, void *y,
+                    int32_t *fp32 /* host, may be NULL */);
+
 /* Field packing around the solve (Algorithm amgxFoam, first and last steps):
  * soa[v*N + i] (one array per variable) <-> aos[i*n + v].  Bit-exact. */
 int cbs_pack_fields(int32_t n_cells, int32_t bdim, const double *soa, double *aos, void *stream);

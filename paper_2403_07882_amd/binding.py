@@ -24,6 +24,7 @@ SOLVER_BICGSTAB, SOLVER_FGMRES = 0, 1
 PREC_NONE, PREC_BJACOBI, PREC_AMG = 0, 1, 2
 SMOOTH_BJACOBI, SMOOTH_DILU = 0, 1
 PRECISION_FP64, PRECISION_MIXED = 0, 1
+LEVEL_SWEEP, LEVEL_RESIDUAL = 0, 1
 
 
 class Options(C.Structure):
@@ -63,6 +64,7 @@ SIGNATURES = [
     ("cbs_solve_transpose", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
     ("cbs_gradient", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     ("cbs_spmv", C.c_int, [_VP, _VP, _VP, _I32]),
+    ("cbs_level_apply", C.c_int, [_VP, _I32, _I32, _VP, _VP, _VP, C.POINTER(_I32)]),
     ("cbs_apply_precond", C.c_int, [_VP, _VP, _VP]),
     ("cbs_pack_fields", C.c_int, [_I32, _I32, _VP, _VP, _VP]),
     ("cbs_unpack_fields", C.c_int, [_I32, _I32, _VP, _VP, _VP]),
@@ -264,6 +266,19 @@ class System:
         z = torch.empty_like(rr)
         _check(lib().cbs_apply_precond(self.h, _ptr(rr), _ptr(z)), "cbs_apply_precond")
         return z.reshape(-1, self.n)
+
+    def level_apply(self, level, op, b, x):
+        """One level kernel of the smoother (LEVEL_SWEEP or LEVEL_RESIDUAL) in
+        the hierarchy's internal numbering and precision; returns y."""
+        torch = _torch()
+        f = C.c_int32(0)
+        _check(lib().cbs_level_apply(self.h, level, op, None, None, None, C.byref(f)), "cbs_level_apply")
+        dt = torch.float32 if f.value else torch.float64
+        bb = _dev(b, dt).reshape(-1)
+        xx = _dev(x, dt).reshape(-1)
+        y = torch.empty_like(xx)
+        _check(lib().cbs_level_apply(self.h, level, op, _ptr(bb), _ptr(xx), _ptr(y), None), "cbs_level_apply")
+        return y.reshape(-1, self.n)
 
     def gradient(self, lam, x):
         torch = _torch()

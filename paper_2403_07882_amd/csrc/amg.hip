@@ -957,7 +957,9 @@ void amg_setup(cbs_system *h) {
     const int n = h->n;
     const bool mixed = o.precision == CBS_PRECISION_MIXED;
     const bool amg = o.precond == CBS_PREC_AMG;
-    const bool reuse = o.reuse_aggregates && h->setup_done && amg && h->lev.size() > 1 && h->lev[0].agg.get() != nullptr;
+    // cbs_setup keeps reuse_aggregates only when a complete hierarchy with the
+    // same structural options exists
+    const bool reuse = o.reuse_aggregates && amg && h->lev.size() > 1 && h->lev[0].agg.get() != nullptr;
     h->transposed_ready = false;
 
     if (!reuse) {

@@ -400,6 +400,48 @@ int cbs_apply_precond(cbs_handle h, const double *r, double *z) {
     });
 }
 
+int cbs_level_apply(cbs_handle h, int32_t level, int32_t op, const void *b, const void *x, void *y, int32_t *fp32) {
+    return guarded([&] {
+        require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        set_alloc_stream(h->stream);
+        require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
+        require(h->opt.precond == CBS_PREC_AMG, CBS_ERR_STATE, "level kernels need the AMG preconditioner");
+        require(level >= 0 && level + 1 < (int32_t)h->lev.size(), CBS_ERR_ARG,
+                "level out of range (the coarsest level has no smoother)");
+        require(op == CBS_LEVEL_SWEEP || op == CBS_LEVEL_RESIDUAL, CBS_ERR_ARG, "unknown op");
+        const bool mixed = h->opt.precision == CBS_PRECISION_MIXED;
+        if (fp32) *fp32 = mixed ? 1 : 0;
+        if (!b && !x && !y) return CBS_OK;
+        require(b && x && y, CBS_ERR_ARG, "NULL vector");
+        require(x != y, CBS_ERR_ARG, "y must not alias x");
+        Level &L = h->lev[level];
+        require(op == CBS_LEVEL_RESIDUAL || !L.dilu, CBS_ERR_STATE, "a DILU level has no block-Jacobi sweep");
+        const int n = h->n;
+        const double w = h->opt.omega;
+        hipStream_t st = h->stream;
+        if (mixed) {
+            const float *bb = static_cast<const float *>(b), *xx = static_cast<const float *>(x);
+            float *yy = static_cast<float *>(y);
+            const SellView S = L.sell.view(true);
+            if (op == CBS_LEVEL_RESIDUAL)
+                launch_rows<float, float>(1, n, S, L.sell.v32.get(), xx, bb, yy, nullptr, 0.0, st);
+            else if (L.scaled)
+                launch_rows<float, float>(4, n, S, L.sell.v32s.get(), xx, bb, yy, nullptr, w, st);
+            else
+                launch_rows<float, float>(2, n, S, L.sell.v32.get(), xx, bb, yy, L.Dinv.get(), w, st);
+        } else {
+            const double *bb = static_cast<const double *>(b), *xx = static_cast<const double *>(x);
+            double *yy = static_cast<double *>(y);
+            const SellView S = L.sell.view(false);
+            if (op == CBS_LEVEL_RESIDUAL)
+                launch_rows<double, double>(1, n, S, L.sell.v64.get(), xx, bb, yy, nullptr, 0.0, st);
+            else
+                launch_rows<double, double>(2, n, S, L.sell.v64.get(), xx, bb, yy, L.Dinv.get(), w, st);
+        }
+        return CBS_OK;
+    });
+}
+
 int cbs_pack_fields(int32_t n_cells, int32_t bdim, const double *soa, double *aos, void *stream) {
     return guarded([&] {
         require(n_cells >= 0 && bdim >= 1 && soa && aos, CBS_ERR_ARG, "bad argument");

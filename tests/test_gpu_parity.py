@@ -309,6 +309,115 @@ def test_mixed_vcycle_matches_fp64_oracle_vcycle(split, pre, post):
     assert np.linalg.norm(z - zr) <= 1e-5 * np.linalg.norm(zr)
 
 
+@pytest.mark.parametrize("renumber", [0, 1])
+def test_values_only_resetup_keeps_the_hierarchy(renumber):
+    """cbs_update_values + cbs_setup(reuse_aggregates=1): same pattern, aggregates
+    and numbering; level 0 holds the new values, every coarser level is the
+    Galerkin product of the new values on the kept aggregates, and the solve
+    meets the tolerance on the new system."""
+    _say("values-only re-setup renumber", renumber)
+    s = pressure_velocity(10, 9, 8, seed=4)
+    rng = np.random.default_rng(11)
+    pert = lambda a: a * (1.0 + 0.05 * rng.uniform(-1.0, 1.0, a.shape))
+    s2 = dict(s, diag=pert(s["diag"]), upper=pert(s["upper"]), lower=pert(s["lower"]))
+    A2 = O.from_system(s2)
+    opt = dict(precond=P.PREC_AMG, coarse_max=8, pre_sweeps=1, post_sweeps=1, omega=0.8, renumber=renumber)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(**opt)
+        nlev = sysm.info()["levels"]
+        before = [sysm.get_level(l) for l in range(nlev)]
+        before = [{k: _np(v) for k, v in lv.items() if k in ("row_ptr", "col", "agg", "order")} for lv in before]
+        sysm.update_values(s2["diag"], s2["upper"], s2["lower"])
+        sysm.setup(reuse_aggregates=1, **opt)
+        assert sysm.info()["levels"] == nlev
+        lv0 = sysm.get_level(0)
+        order = _np(lv0["order"])
+        A0 = O.BCSR(A2.N, 4, _np(lv0["row_ptr"]), _np(lv0["col"]), _np(lv0["vals"]))
+        idx = np.repeat(order * 4, 4) + np.tile(np.arange(4), A2.N)
+        assert np.array_equal(A0.dense(), A2.dense()[idx][:, idx])
+        Al, aggs = A0, []
+        for l in range(nlev):
+            lv = sysm.get_level(l)
+            for k in ("row_ptr", "col", "order"):
+                assert np.array_equal(_np(lv[k]), before[l][k]), (l, k)
+            if l > 0:
+                assert np.array_equal(_np(lv["row_ptr"]), Al.row_ptr) and np.array_equal(_np(lv["col"]), Al.col)
+                assert np.allclose(_np(lv["vals"]), Al.vals, rtol=1e-13, atol=1e-13 * np.abs(Al.vals).max())
+            Al = O.BCSR(lv["N"], 4, _np(lv["row_ptr"]), _np(lv["col"]), _np(lv["vals"]))
+            if l + 1 < nlev:
+                agg = _np(lv["agg"])
+                assert np.array_equal(agg, before[l]["agg"])
+                aggs.append(agg)
+                Al = O.rap(Al, agg, int(agg.max()) + 1)
+        r = np.random.default_rng(0).standard_normal((A2.N, 4))
+        z = _np(sysm.apply_precond(r))
+        amg = O.AMG(A0, nu1=1, nu2=1, omega=0.8, aggs=aggs)
+        zr_int = amg.apply(r[order])
+        zr = np.empty_like(zr_int); zr[order] = zr_int
+        assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+        x, st = sysm.solve(s2["b"])
+        assert st["status"] == P.OK, st
+        assert O.relres(A2, s2["b"], _np(x)) <= 1e-8 * 1.0001
+
+
+def _diag_blocks(A):
+    D = np.empty((A.N, A.n, A.n))
+    for i in range(A.N):
+        ks = np.arange(A.row_ptr[i], A.row_ptr[i + 1])
+        D[i] = A.vals[ks[A.col[ks] == i][0]]
+    return D
+
+
+@pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
+def test_level_kernels_match_oracle(precision):
+    """cbs_level_apply: the residual and block-Jacobi sweep kernels of every
+    smoothed level against the oracle on that level's matrix; in mixed
+    precision the sweep takes the scaled right side Dinv b."""
+    _say("level kernels", precision)
+    s = pressure_velocity(12, 10, 9, seed=6)
+    rng = np.random.default_rng(7)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, precision=precision, coarse_max=8, omega=0.9)
+        nlev = sysm.info()["levels"]
+        assert nlev >= 3
+        for l in range(nlev - 1):
+            lv = sysm.get_level(l)
+            Al = O.BCSR(lv["N"], 4, _np(lv["row_ptr"]), _np(lv["col"]), _np(lv["vals"]))
+            b = rng.standard_normal((Al.N, 4))
+            x = rng.standard_normal((Al.N, 4))
+            if precision == P.PRECISION_MIXED:      # the kernels see FP32 inputs
+                b, x = b.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64)
+            scale = np.abs(Al.vals).max() * np.abs(x).max() * 64 + np.abs(b).max()
+            tol = 1e-14 if precision == P.PRECISION_FP64 else 1e-6
+            r = _np(sysm.level_apply(l, P.LEVEL_RESIDUAL, b, x)).astype(np.float64)
+            assert np.abs(r - (b - O.spmv(Al, x))).max() <= tol * scale
+            Dinv = O.blockinv(_diag_blocks(Al))
+            y = _np(sysm.level_apply(l, P.LEVEL_SWEEP, b, x)).astype(np.float64)
+            if precision == P.PRECISION_FP64:
+                ref = O.bjacobi_sweep(Al, Dinv, b, x, 0.9)
+            else:
+                ref = x + 0.9 * (b - np.einsum("kij,kj->ki", Dinv, O.spmv(Al, x)))
+            ysc = np.abs(ref).max() + 1.0
+            assert np.abs(y - ref).max() <= (1e-13 if precision == P.PRECISION_FP64 else 1e-5) * ysc
+        with pytest.raises(P.CbsError) as e:
+            sysm.level_apply(nlev - 1, P.LEVEL_RESIDUAL, b, x)
+        assert e.value.code == P.ERR_ARG
+        with pytest.raises(P.CbsError) as e:
+            sysm.level_apply(0, 7, b, x)
+        assert e.value.code == P.ERR_ARG
+        sysm.setup(precond=P.PREC_AMG, precision=precision, smoother=P.SMOOTH_DILU, dilu_levels=1, coarse_max=8)
+        n0 = sysm.get_level(0)["N"]
+        z0 = np.zeros((n0, 4))
+        with pytest.raises(P.CbsError) as e:
+            sysm.level_apply(0, P.LEVEL_SWEEP, z0, z0)
+        assert e.value.code == P.ERR_STATE
+        sysm.level_apply(0, P.LEVEL_RESIDUAL, z0, z0)
+        sysm.setup(precond=P.PREC_BJACOBI)
+        with pytest.raises(P.CbsError) as e:
+            sysm.level_apply(0, P.LEVEL_RESIDUAL, z0, z0)
+        assert e.value.code == P.ERR_STATE
+
+
 def test_renumbering_keeps_the_solution():
     s = pressure_velocity(14, 12, 10, seed=7)
     A = O.from_system(s)
