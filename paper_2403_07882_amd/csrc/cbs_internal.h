@@ -92,6 +92,11 @@ enum {
 // consecutive blocks per step.  BCSR stays the setup-time format.
 constexpr int kSlice = 16;
 
+// Levels with fewer block rows than this are launch- and latency-bound: their
+// block-row kernels split rows over several threads, and their first
+// post-smoothing sweep absorbs the prolongation.
+constexpr int32_t kSmallLevelRows = 65536;
+
 // Schedule of the block-row kernels: blocks loaded per step (1, 2, 4) and
 // whether matrix values are loaded non-temporally; picked by autotuning.
 struct Sched {
@@ -247,9 +252,26 @@ void gradient(cbs_system *h, const double *lam, const double *x, double *gd, dou
 //   mode 3: y = omega Dinv b (block-Jacobi sweep from a zero guess), and
 //           aux = Dinv b when aux is not null
 //   mode 4: y = x + omega (b - A x) on row-scaled values Dinv A with b = Dinv b
+// Modes 2 and 4 with pagg != nullptr sweep from x + P e (pagg: aggregate map
+// of the level, pe: coarse-level correction): the prolongation fused into
+// the first post-smoothing sweep.
+// Modes 2 and 4 with y64 != nullptr write the result widened to FP64 into y64
+// instead of y.
 template <typename TV, typename TX>
 void launch_rows(int mode, int n, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y,
-                 const double *Dinv, double omega, hipStream_t st, TX *aux = nullptr);
+                 const double *Dinv, double omega, hipStream_t st, TX *aux = nullptr,
+                 const int32_t *pagg = nullptr, const TX *pe = nullptr, double *y64 = nullptr);
+// Mixed precision, level 0: b = FP32(b64) fused with the zero-guess sweep
+// x = omega Dinv b (and c = Dinv b when c is not null).
+void launch_cast_sweep0(int n, int32_t N, const double *b64, float *b, const double *Dinv, double omega, float *x,
+                        float *c, hipStream_t st);
+// Restriction fused into the zero-guess block-Jacobi sweep of the coarse
+// level: b[I] = sum of r over the members of aggregate I (agg_ptr/agg_mem of
+// the fine level, summed in member order like launch_restrict), then
+// x = omega Dinv b and, when c is not null, c = Dinv b.
+template <typename TX>
+void launch_restrict_sweep0(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem, const TX *r, TX *b,
+                            const double *Dinv, double omega, TX *x, TX *c, hipStream_t st);
 // time the schedules of the residual kernel on S (cached per shape)
 Sched autotune_rows(int n, const Sell &S, bool fp32, const void *val, hipStream_t st);
 // threads per scalar row of the block-row kernels on a level (row_split option)

@@ -415,33 +415,55 @@ void dilu_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x, bool zero_g
                            L.colour_off[c + 1] - L.colour_off[c], Einv, y, x, zero_guess, h->stream);
 }
 
-// x = V(b) with zero initial guess on level l; the result lands in x.
+// x = V(b) with zero initial guess on level l; the result lands in x.  When
+// rfine is given, b is not yet formed: it is the restriction of the finer
+// level's residual rfine, which the first kernel of this level computes and
+// stores into b (fused into the zero-guess sweep when there is one).  On
+// level 0 of a mixed-precision cycle, b64 is the FP64 right side (rounded
+// into b by the first kernel) and the result goes widened to x64 instead.
 template <typename T>
-void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
+void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const double *b64 = nullptr,
+            double *x64 = nullptr) {
     hipStream_t st = h->stream;
     const cbs_options &o = h->opt;
     const int n = h->n;
     const int nlev = (int)h->lev.size();
     Level &L = h->lev[l];
+    const int64_t m = (int64_t)L.N * n;
+    const int nu1 = std::max(0, o.pre_sweeps), nu2 = std::max(0, o.post_sweeps);
+    constexpr bool fp32 = sizeof(T) == sizeof(float);
+    const bool bj = l < nlev - 1 && !L.dilu;
+    const bool fuse_in = fp32 && b64 && bj && nu1 >= 1;
+    const bool fuse_out = fp32 && x64 && bj && nu2 >= 1;
+    if (b64 && !fuse_in) launch_cast<double, T>(m, b64, b, st);
+    auto finish = [&] {
+        if (x64 && !fuse_out) launch_cast<T, double>(m, x, x64, st);
+    };
+    auto restrict_into_b = [&] {
+        const Level &F = h->lev[l - 1];
+        launch_restrict<T>(n, L.N, F.agg_ptr.get(), F.agg_mem.get(), rfine, b, st);
+    };
     if (l == nlev - 1) {
-        launch_coarse_solve(h, tr, b, x, sizeof(T) == sizeof(float));
+        if (rfine) restrict_into_b();
+        launch_coarse_solve(h, tr, b, x, fp32);
+        finish();
         return;
     }
     const T *val = level_vals<T>(L, tr);
     const double *Dinv = tr ? L.DinvT.get() : L.Dinv.get();
     T *tmp = vptr<T>(L.vt);
     T *r = vptr<T>(L.vr);
-    const int nu1 = std::max(0, o.pre_sweeps), nu2 = std::max(0, o.post_sweeps);
+    Level &C = h->lev[l + 1];
+    T *bc = vptr<T>(C.vb), *xc = vptr<T>(C.vx);
     if (L.dilu) {
+        if (rfine) restrict_into_b();
         for (int s = 0; s < nu1; ++s) dilu_smooth<T>(h, L, tr, b, x, s == 0);
-        if (nu1 == 0) launch_fill<T>((int64_t)L.N * n, x, st);
-        launch_rows<T, T>(1, n, L.sell.view(sizeof(T) == 4), val, x, b, r, nullptr, 0.0, st);
-        Level &C = h->lev[l + 1];
-        T *bc = vptr<T>(C.vb), *xc = vptr<T>(C.vx);
-        launch_restrict<T>(n, C.N, L.agg_ptr.get(), L.agg_mem.get(), r, bc, st);
-        vcycle<T>(h, tr, l + 1, bc, xc);
+        if (nu1 == 0) launch_fill<T>(m, x, st);
+        launch_rows<T, T>(1, n, L.sell.view(fp32), val, x, b, r, nullptr, 0.0, st);
+        vcycle<T>(h, tr, l + 1, bc, xc, r);
         launch_prolong<T>(n, L.N, L.agg.get(), xc, x, st);
         for (int s = 0; s < nu2; ++s) dilu_smooth<T>(h, L, tr, b, x, false);
+        finish();
         return;
     }
     const int switches = (nu1 >= 1 ? nu1 - 1 : 0) + nu2;
@@ -449,36 +471,50 @@ void vcycle(cbs_system *h, bool tr, int l, const T *b, T *x) {
     T *oth = (cur == x) ? tmp : x;
     // FP32 forward sweeps run on the row-scaled values Dinv A against
     // c = Dinv b, which the zero-guess sweep leaves behind
-    const bool scaled = sizeof(T) == sizeof(float) && !tr && L.scaled;
+    const bool scaled = fp32 && !tr && L.scaled;
     const T *sval = scaled ? reinterpret_cast<const T *>(L.sell.v32s.get()) : nullptr;
     T *c = scaled ? vptr<T>(L.vc) : nullptr;
-    auto sweep = [&](T *from, T *to) {
+    // pagg/pe: sweep from x + P e (the prolongation fused into the sweep);
+    // y64: write the result widened to FP64 there instead of into `to`
+    auto sweep = [&](T *from, T *to, const int32_t *pagg, const T *pe, double *y64) {
         if (scaled)
-            launch_rows<T, T>(4, n, L.sell.view(true), sval, from, c, to, nullptr, o.omega, st);
+            launch_rows<T, T>(4, n, L.sell.view(true), sval, from, c, to, nullptr, o.omega, st, nullptr, pagg, pe,
+                              y64);
         else
-            launch_rows<T, T>(2, n, L.sell.view(sizeof(T) == 4), val, from, b, to, Dinv, o.omega, st);
+            launch_rows<T, T>(2, n, L.sell.view(fp32), val, from, b, to, Dinv, o.omega, st, nullptr, pagg, pe, y64);
     };
     if (nu1 >= 1) {
-        launch_rows<T, T>(3, n, L.sell.view(sizeof(T) == 4), val, cur, b, cur, Dinv, o.omega, st, c);
+        if (fuse_in) {
+            if constexpr (fp32)
+                launch_cast_sweep0(n, L.N, b64, b, Dinv, o.omega, cur, c, st);
+        } else if (rfine) {
+            launch_restrict_sweep0<T>(n, L.N, h->lev[l - 1].agg_ptr.get(), h->lev[l - 1].agg_mem.get(), rfine, b,
+                                      Dinv, o.omega, cur, c, st);
+        } else {
+            launch_rows<T, T>(3, n, L.sell.view(fp32), val, cur, b, cur, Dinv, o.omega, st, c);
+        }
         for (int s = 1; s < nu1; ++s) {
-            sweep(cur, oth);
+            sweep(cur, oth, nullptr, nullptr, nullptr);
             std::swap(cur, oth);
         }
     } else {
+        if (rfine) restrict_into_b();
         if (scaled && nu2 > 0)   // c only; oth is scratch here
             launch_rows<T, T>(3, n, L.sell.view(true), val, oth, b, oth, Dinv, o.omega, st, c);
-        launch_fill<T>((int64_t)L.N * n, cur, st);
+        launch_fill<T>(m, cur, st);
     }
-    launch_rows<T, T>(1, n, L.sell.view(sizeof(T) == 4), val, cur, b, r, Dinv, o.omega, st);
-    Level &C = h->lev[l + 1];
-    T *bc = vptr<T>(C.vb), *xc = vptr<T>(C.vx);
-    launch_restrict<T>(n, C.N, L.agg_ptr.get(), L.agg_mem.get(), r, bc, st);
-    vcycle<T>(h, tr, l + 1, bc, xc);
-    launch_prolong<T>(n, L.N, L.agg.get(), xc, cur, st);
+    launch_rows<T, T>(1, n, L.sell.view(fp32), val, cur, b, r, Dinv, o.omega, st);
+    vcycle<T>(h, tr, l + 1, bc, xc, r);
+    // On large levels the extra aggregate-map gathers cost more than the
+    // separate prolongation pass; on small ones the saved launch wins.
+    const bool fuse_pro = nu2 > 0 && L.N < kSmallLevelRows;
+    if (!fuse_pro) launch_prolong<T>(n, L.N, L.agg.get(), xc, cur, st);
     for (int s = 0; s < nu2; ++s) {
-        sweep(cur, oth);
+        const bool first = s == 0 && fuse_pro, last = s == nu2 - 1 && fuse_out;
+        sweep(cur, oth, first ? L.agg.get() : nullptr, first ? xc : nullptr, last ? x64 : nullptr);
         std::swap(cur, oth);
     }
+    finish();
 }
 
 }  // namespace
@@ -513,11 +549,9 @@ void precond_apply(cbs_system *h, const double *r, double *z, bool tr) {
     if (h->opt.precision == CBS_PRECISION_MIXED) {
         Level &L0 = h->lev[0];
         float *b32 = vptr<float>(L0.vb), *x32 = vptr<float>(L0.vx);
-        launch_cast<double, float>(m, r, b32, st);
-        vcycle<float>(h, tr, 0, b32, x32);
-        launch_cast<float, double>(m, x32, z, st);
+        vcycle<float>(h, tr, 0, b32, x32, nullptr, r, z);
     } else {
-        vcycle<double>(h, tr, 0, r, z);
+        vcycle<double>(h, tr, 0, const_cast<double *>(r), z, nullptr);
     }
 }
 

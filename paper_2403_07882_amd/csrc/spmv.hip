@@ -69,22 +69,46 @@ __device__ inline void load_x<4, float>(const float *__restrict__ p, float (&v)[
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 
+// x_j as a sweep sees it: with PRO the coarse-grid correction of j's
+// aggregate, e[agg[j]], is added first -- the same floating-point addition the
+// prolongation kernel makes, so fusing prolongation into the first
+// post-smoothing sweep changes no result.
+template <int n, typename TX, bool PRO>
+__device__ inline void load_xc(const TX *__restrict__ x, int64_t j, const int32_t *__restrict__ pagg,
+                               const TX *__restrict__ pe, TX (&v)[n]) {
+    load_x<n, TX>(x + j * n, v);
+    if constexpr (PRO) {
+        const TX *ej = pe + (int64_t)pagg[j] * n;
+#pragma unroll
+        for (int c = 0; c < n; ++c) v[c] = v[c] + ej[c];
+    }
+}
+
 // mode 0: y = A x; 1: y = b - A x; 2: y = x + w Dinv (b - A x); 3: y = w Dinv b
 // (and aux = Dinv b when aux is given); 4: y = x + w (b - A x), the sweep of
 // mode 2 on row-scaled values Dinv A with b = Dinv b.
 // Rows are read from the sliced-ELL copy: at step k the 16 rows of a slice
 // read 16 consecutive blocks; four steps are loaded before they are summed,
 // and the sums run in the row's column order.
-template <int n, typename TV, typename TX, int MODE, int U, bool NT>
+// Modes 2 and 4 with PRO: x is first corrected by the prolongated coarse
+// solution (x + P e, pagg = aggregate map, pe = e), see load_xc.
+template <int n, typename TV, typename TX, int MODE, int U, bool NT, bool PRO>
 __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restrict__ val, const TX *__restrict__ x,
                                                  const TX *__restrict__ b, TX *__restrict__ y,
                                                  const double *__restrict__ Dinv, double omega,
-                                                 TX *__restrict__ aux) {
+                                                 TX *__restrict__ aux, const int32_t *__restrict__ pagg,
+                                                 const TX *__restrict__ pe, double *__restrict__ y64) {
     using A = typename Acc<TX>::type;
     constexpr int nn = n * n;
     const int t = threadIdx.x;
     const int lr = t / n, r = t - lr * n;
     const int32_t i = blockIdx.x * 64 + lr;
+    // sweep result: to y, or widened to FP64 into y64 (the last sweep of a
+    // mixed-precision V-cycle hands its result straight to the FP64 loop)
+    auto put = [&](int64_t o, TX v) {
+        if (y64) y64[o] = (double)v;
+        else y[o] = v;
+    };
     const int32_t N = S.N;
     A acc = 0;
     if (MODE != 3 && i < N) {
@@ -101,7 +125,7 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
             for (int u = 0; u < U; ++u) {
                 const int64_t e = base + (int64_t)(k + u) * kSlice;
                 load_row_nt<n, TV, NT>(val + e * nn + r * n, bv[u]);
-                load_x<n, TX>(x + (int64_t)(j[u] < 0 ? i : j[u]) * n, xv[u]);
+                load_xc<n, TX, PRO>(x, j[u] < 0 ? i : j[u], pagg, pe, xv[u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -117,12 +141,17 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
             TV bv[n];
             TX xv[n];
             load_row_nt<n, TV, NT>(val + e * nn + r * n, bv);
-            load_x<n, TX>(x + (int64_t)j * n, xv);
+            load_xc<n, TX, PRO>(x, j, pagg, pe, xv);
 #pragma unroll
             for (int c = 0; c < n; ++c) acc += (A)bv[c] * (A)xv[c];
         }
     }
     const int64_t o = (int64_t)i * n + r;
+    auto x_own = [&]() -> A {
+        TX v = x[o];
+        if constexpr (PRO) v = v + pe[(int64_t)pagg[i] * n + r];
+        return (A)v;
+    };
     if (MODE == 0) {
         if (i < N) y[o] = (TX)acc;
         return;
@@ -134,7 +163,7 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
         return;
     }
     if (MODE == 4) {
-        if (i < N) y[o] = (TX)((A)x[o] + (A)omega * res);
+        if (i < N) put(o, (TX)(x_own() + (A)omega * res));
         return;
     }
     __shared__ A sres[64 * n];
@@ -145,8 +174,8 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
         double z = 0.0;
 #pragma unroll
         for (int c = 0; c < n; ++c) z += Di[c] * (double)sres[lr * n + c];
-        const A xi = (MODE == 2) ? (A)x[o] : (A)0;
-        y[o] = (TX)(xi + (A)(omega * z));
+        const A xi = (MODE == 2) ? x_own() : (A)0;
+        put(o, (TX)(xi + (A)(omega * z)));
         if (MODE == 3 && aux) aux[o] = (TX)z;
     }
 }
@@ -156,13 +185,19 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
 // Here SP threads share each scalar row: thread kk takes blocks kk, kk + SP,
 // ...; the SP partial sums meet in LDS and are added in kk order.  A
 // workgroup covers 64 / SP block rows.
-template <int n, typename TV, typename TX, int MODE, int SP>
+template <int n, typename TV, typename TX, int MODE, int SP, bool PRO>
 __global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__restrict__ val,
                                                        const TX *__restrict__ x, const TX *__restrict__ b,
                                                        TX *__restrict__ y, const double *__restrict__ Dinv,
-                                                       double omega, TX *__restrict__ aux) {
+                                                       double omega, TX *__restrict__ aux,
+                                                       const int32_t *__restrict__ pagg,
+                                                       const TX *__restrict__ pe, double *__restrict__ y64) {
     using A = typename Acc<TX>::type;
     constexpr int nn = n * n, R = 64 / SP;
+    auto put = [&](int64_t o, TX v) {
+        if (y64) y64[o] = (double)v;
+        else y[o] = v;
+    };
     const int t = threadIdx.x;
     const int lr = t / (n * SP), kr = t - lr * (n * SP);
     const int kk = kr / n, r = kr - kk * n;
@@ -179,11 +214,16 @@ __global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__r
             TV bv[n];
             TX xv[n];
             load_row_nt<n, TV, false>(val + e * nn + r * n, bv);
-            load_x<n, TX>(x + (int64_t)j * n, xv);
+            load_xc<n, TX, PRO>(x, j, pagg, pe, xv);
 #pragma unroll
             for (int c = 0; c < n; ++c) acc += (A)bv[c] * (A)xv[c];
         }
     }
+    auto x_own = [&](int64_t o) -> A {
+        TX v = x[o];
+        if constexpr (PRO) v = v + pe[(int64_t)pagg[i] * n + r];
+        return (A)v;
+    };
     __shared__ A spart[64 * n];
     __shared__ A sres[R * n];
     spart[t] = acc;
@@ -200,7 +240,7 @@ __global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__r
             if (MODE == 1) {
                 if (i < N) y[o] = (TX)res;
             } else if (MODE == 4) {
-                if (i < N) y[o] = (TX)((A)x[o] + (A)omega * res);
+                if (i < N) put(o, (TX)(x_own(o) + (A)omega * res));
             } else {
                 sres[lr * n + r] = res;
             }
@@ -213,24 +253,26 @@ __global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__r
         double z = 0.0;
 #pragma unroll
         for (int c = 0; c < n; ++c) z += Di[c] * (double)sres[lr * n + c];
-        y[o] = (TX)((A)x[o] + (A)(omega * z));
+        put(o, (TX)(x_own(o) + (A)(omega * z)));
     }
 }
 
-template <int n, typename TV, typename TX, int MODE>
-void rows_nm(const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, const double *Dinv, double omega,
-             TX *aux, hipStream_t st) {
+template <int n, typename TV, typename TX, int MODE, bool PRO>
+void rows_launch(const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, const double *Dinv,
+                 double omega, TX *aux, const int32_t *pagg, const TX *pe, double *y64, hipStream_t st) {
     const dim3 g(cdiv(S.N, 64)), bl(64 * n);
     const int u = S.sched.unroll;
     const bool nt = S.sched.nontemporal != 0;
-#define ROWS_V(UU, NTT) \
-    hipLaunchKernelGGL((k_rows<n, TV, TX, MODE, UU, NTT>), g, bl, 0, st, S, val, x, b, y, Dinv, omega, aux)
+#define ROWS_V(UU, NTT)                                                                                  \
+    hipLaunchKernelGGL((k_rows<n, TV, TX, MODE, UU, NTT, PRO>), g, bl, 0, st, S, val, x, b, y, Dinv, omega, \
+                       aux, pagg, pe, y64)
     if (MODE == 3) { ROWS_V(1, false); return; }       // no matrix read
     const int sp = S.sched.split;
     if (sp > 1) {
         const dim3 gs(cdiv((int64_t)S.N * sp, 64));
-#define ROWS_S(SS) \
-    hipLaunchKernelGGL((k_rows_split<n, TV, TX, MODE, SS>), gs, bl, 0, st, S, val, x, b, y, Dinv, omega, aux)
+#define ROWS_S(SS)                                                                                           \
+    hipLaunchKernelGGL((k_rows_split<n, TV, TX, MODE, SS, PRO>), gs, bl, 0, st, S, val, x, b, y, Dinv, omega, \
+                       aux, pagg, pe, y64)
         if (sp == 2) ROWS_S(2);
         else if (sp == 4) ROWS_S(4);
         else if (sp == 8) ROWS_S(8);
@@ -244,15 +286,27 @@ void rows_nm(const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, 
 #undef ROWS_V
 }
 
+template <int n, typename TV, typename TX, int MODE>
+void rows_nm(const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, const double *Dinv, double omega,
+             TX *aux, const int32_t *pagg, const TX *pe, double *y64, hipStream_t st) {
+    if constexpr (MODE == 2 || MODE == 4) {
+        if (pagg) {
+            rows_launch<n, TV, TX, MODE, true>(S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st);
+            return;
+        }
+    }
+    rows_launch<n, TV, TX, MODE, false>(S, val, x, b, y, Dinv, omega, aux, nullptr, nullptr, y64, st);
+}
+
 template <int n, typename TV, typename TX>
 void rows_n(int mode, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y, const double *Dinv,
-            double omega, TX *aux, hipStream_t st) {
+            double omega, TX *aux, const int32_t *pagg, const TX *pe, double *y64, hipStream_t st) {
     switch (mode) {
-        case 0: rows_nm<n, TV, TX, 0>(S, val, x, b, y, Dinv, omega, aux, st); break;
-        case 1: rows_nm<n, TV, TX, 1>(S, val, x, b, y, Dinv, omega, aux, st); break;
-        case 2: rows_nm<n, TV, TX, 2>(S, val, x, b, y, Dinv, omega, aux, st); break;
-        case 3: rows_nm<n, TV, TX, 3>(S, val, x, b, y, Dinv, omega, aux, st); break;
-        case 4: rows_nm<n, TV, TX, 4>(S, val, x, b, y, Dinv, omega, aux, st); break;
+        case 0: rows_nm<n, TV, TX, 0>(S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st); break;
+        case 1: rows_nm<n, TV, TX, 1>(S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st); break;
+        case 2: rows_nm<n, TV, TX, 2>(S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st); break;
+        case 3: rows_nm<n, TV, TX, 3>(S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st); break;
+        case 4: rows_nm<n, TV, TX, 4>(S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st); break;
     }
 }
 
@@ -492,21 +546,24 @@ __global__ void k_block_apply(int32_t N, const double *__restrict__ Dinv, const 
 
 template <typename TV, typename TX>
 void launch_rows(int mode, int n, const SellView &S, const TV *val, const TX *x, const TX *b, TX *y,
-                 const double *Dinv, double omega, hipStream_t st, TX *aux) {
+                 const double *Dinv, double omega, hipStream_t st, TX *aux, const int32_t *pagg, const TX *pe,
+                 double *y64) {
     if (S.N <= 0) return;
     switch (n) {
-        case 1: rows_n<1>(mode, S, val, x, b, y, Dinv, omega, aux, st); break;
-        case 2: rows_n<2>(mode, S, val, x, b, y, Dinv, omega, aux, st); break;
-        case 3: rows_n<3>(mode, S, val, x, b, y, Dinv, omega, aux, st); break;
-        case 4: rows_n<4>(mode, S, val, x, b, y, Dinv, omega, aux, st); break;
-        case 5: rows_n<5>(mode, S, val, x, b, y, Dinv, omega, aux, st); break;
+        case 1: rows_n<1>(mode, S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st); break;
+        case 2: rows_n<2>(mode, S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st); break;
+        case 3: rows_n<3>(mode, S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st); break;
+        case 4: rows_n<4>(mode, S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st); break;
+        case 5: rows_n<5>(mode, S, val, x, b, y, Dinv, omega, aux, pagg, pe, y64, st); break;
     }
     LAUNCHCHK();
 }
 template void launch_rows<double, double>(int, int, const SellView &, const double *, const double *, const double *,
-                                          double *, const double *, double, hipStream_t, double *);
+                                          double *, const double *, double, hipStream_t, double *,
+                                          const int32_t *, const double *, double *);
 template void launch_rows<float, float>(int, int, const SellView &, const float *, const float *, const float *,
-                                        float *, const double *, double, hipStream_t, float *);
+                                        float *, const double *, double, hipStream_t, float *, const int32_t *,
+                                        const float *, double *);
 
 void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st) {
     S.N = N;
@@ -562,6 +619,100 @@ void sell_scale(int n, const Sell &S, const double *Dinv, float *out, hipStream_
 #undef SCALE_N
     LAUNCHCHK();
 }
+
+template <int n, typename TX>
+__global__ __launch_bounds__(64 * n) void k_restrict_sweep0(int32_t nc, const int32_t *__restrict__ aptr,
+                                                            const int32_t *__restrict__ amem,
+                                                            const TX *__restrict__ r, TX *__restrict__ b,
+                                                            const double *__restrict__ Dinv, double omega,
+                                                            TX *__restrict__ x, TX *__restrict__ c) {
+    using A = typename Acc<TX>::type;
+    constexpr int nn = n * n;
+    const int t = threadIdx.x;
+    const int lr = t / n, q = t - lr * n;
+    const int32_t I = blockIdx.x * 64 + lr;
+    A s = 0;
+    if (I < nc)
+        for (int32_t m = aptr[I]; m < aptr[I + 1]; ++m) s += (A)r[(int64_t)amem[m] * n + q];
+    const TX bv = (TX)s;
+    const int64_t o = (int64_t)I * n + q;
+    if (I < nc) b[o] = bv;
+    __shared__ A sb[64 * n];
+    sb[t] = (A)bv;
+    __syncthreads();
+    if (I < nc) {
+        const double *Di = Dinv + (int64_t)I * nn + q * n;
+        double z = 0.0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) z += Di[k] * (double)sb[lr * n + k];
+        x[o] = (TX)((A)0 + (A)(omega * z));
+        if (c) c[o] = (TX)z;
+    }
+}
+
+// Mixed precision, level 0: the FP64 right side rounded to FP32 (kept in b
+// for the residual) fused with the zero-guess sweep x = omega Dinv b,
+// c = Dinv b.  Same roundings as a cast kernel followed by mode 3.
+template <int n>
+__global__ __launch_bounds__(64 * n) void k_cast_sweep0(int32_t N, const double *__restrict__ b64,
+                                                        float *__restrict__ b, const double *__restrict__ Dinv,
+                                                        double omega, float *__restrict__ x, float *__restrict__ c) {
+    constexpr int nn = n * n;
+    const int t = threadIdx.x;
+    const int lr = t / n, q = t - lr * n;
+    const int32_t i = blockIdx.x * 64 + lr;
+    const int64_t o = (int64_t)i * n + q;
+    const float bv = i < N ? (float)b64[o] : 0.0f;
+    if (i < N) b[o] = bv;
+    __shared__ float sb[64 * n];
+    sb[t] = bv;
+    __syncthreads();
+    if (i < N) {
+        const double *Di = Dinv + (int64_t)i * nn + q * n;
+        double z = 0.0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) z += Di[k] * (double)sb[lr * n + k];
+        x[o] = (float)(0.0f + (float)(omega * z));
+        if (c) c[o] = (float)z;
+    }
+}
+
+void launch_cast_sweep0(int n, int32_t N, const double *b64, float *b, const double *Dinv, double omega, float *x,
+                        float *c, hipStream_t st) {
+    if (N <= 0) return;
+    const dim3 g(cdiv(N, 64)), bl(64 * n);
+#define CS0(NN) hipLaunchKernelGGL((k_cast_sweep0<NN>), g, bl, 0, st, N, b64, b, Dinv, omega, x, c)
+    switch (n) {
+        case 1: CS0(1); break;
+        case 2: CS0(2); break;
+        case 3: CS0(3); break;
+        case 4: CS0(4); break;
+        case 5: CS0(5); break;
+    }
+#undef CS0
+    LAUNCHCHK();
+}
+
+template <typename TX>
+void launch_restrict_sweep0(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem, const TX *r, TX *b,
+                            const double *Dinv, double omega, TX *x, TX *c, hipStream_t st) {
+    if (nc <= 0) return;
+    const dim3 g(cdiv(nc, 64)), bl(64 * n);
+#define RS0(NN) hipLaunchKernelGGL((k_restrict_sweep0<NN, TX>), g, bl, 0, st, nc, agg_ptr, agg_mem, r, b, Dinv, omega, x, c)
+    switch (n) {
+        case 1: RS0(1); break;
+        case 2: RS0(2); break;
+        case 3: RS0(3); break;
+        case 4: RS0(4); break;
+        case 5: RS0(5); break;
+    }
+#undef RS0
+    LAUNCHCHK();
+}
+template void launch_restrict_sweep0<double>(int, int32_t, const int32_t *, const int32_t *, const double *, double *,
+                                             const double *, double, double *, double *, hipStream_t);
+template void launch_restrict_sweep0<float>(int, int32_t, const int32_t *, const int32_t *, const float *, float *,
+                                            const double *, double, float *, float *, hipStream_t);
 
 template <typename TX>
 void launch_restrict(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem, const TX *r, TX *bc,
@@ -700,12 +851,11 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int32_t, int64_t, int, bool>, Sched> g_tune_cache;
 }  // namespace
 
-// Levels of fewer than kSplitRows block rows split each row over several
+// Levels of fewer than kSmallLevelRows block rows split each row over several
 // threads; automatic choice: the largest power of two (at most 16) that still
 // leaves every thread about four blocks of a mean-length row.
-constexpr int32_t kSplitRows = 65536;
 int8_t row_split_for(const Sell &S, int32_t opt_split) {
-    if (S.N <= 0 || S.N >= kSplitRows) return 1;
+    if (S.N <= 0 || S.N >= kSmallLevelRows) return 1;
     if (opt_split > 0) return (int8_t)opt_split;
     const double w = (double)S.nent / S.N;
     int s = 1;
