@@ -748,9 +748,10 @@ void build_members(cbs_system *h, int32_t N, const int32_t *agg, int32_t nc, DAr
 }
 
 // Galerkin pattern + values of the next level.  n_blk = block size of `val`.
-void rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, const int32_t *amem, const int32_t *rp,
-               const int32_t *col, const double *val, const int32_t *agg, DArr<int32_t> &rpc, DArr<int32_t> &colc,
-               DArr<double> &valc, bool pattern) {
+// Returns the coarse block count when it builds the pattern, else -1.
+int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, const int32_t *amem, const int32_t *rp,
+                  const int32_t *col, const double *val, const int32_t *agg, DArr<int32_t> &rpc, DArr<int32_t> &colc,
+                  DArr<double> &valc, bool pattern) {
     hipStream_t st = h->stream;
     // largest candidate list of the level -> LDS per wavefront
     HIPCHK(hipMemsetAsync(h->dflag.get(), 0, 2 * sizeof(int32_t), st));
@@ -762,22 +763,26 @@ void rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, const 
                                    std::to_string(kRapCap) + "); lower match_passes");
     int32_t cap = 64;
     while (cap < maxc) cap *= 2;
+    int32_t nz = -1;
     if (pattern) {
         rpc.alloc(nc + 1);
         NSWITCH(n_blk, rap_n, 0, nc, cap, aptr, amem, rp, col, val, agg, rpc.get(), nullptr, nullptr, nullptr,
                 h->dflag.get(), st);
         LAUNCHCHK();
-        if (read_int(h->dflag.get(), st) & 8)
-            cbs_throw(CBS_ERR_ARG, "coarse row candidate overflow");
         scan_exclusive(rpc.get(), rpc.get(), nc, st);
-        const int32_t nz = read_int(rpc.get() + nc, st);
+        int32_t v[2];
+        read_ints({h->dflag.get(), rpc.get() + nc}, v, st);
+        if (v[0] & 8) cbs_throw(CBS_ERR_ARG, "coarse row candidate overflow");
+        nz = v[1];
         colc.alloc(nz > 0 ? nz : 1);
         valc.alloc((size_t)(nz > 0 ? nz : 1) * n_blk * n_blk);
     }
+    // the fill pass visits the candidates the counting pass (or the first
+    // build of this pattern) already fitted into cap, so it cannot overflow
     NSWITCH(n_blk, rap_n, 1, nc, cap, aptr, amem, rp, col, val, agg, nullptr, rpc.get(), colc.get(), valc.get(),
             h->dflag.get(), st);
     LAUNCHCHK();
-    if (read_int(h->dflag.get(), st) & 8) cbs_throw(CBS_ERR_ARG, "coarse row candidate overflow");
+    return nz;
 }
 
 // Aggregation of level L into L.agg / L.nc (composed matching passes).
@@ -895,7 +900,18 @@ void dilu_factor_level(cbs_system *h, int l) {
 }
 
 // Sliced-ELL copy of a level for the solve phase (pattern kept on reuse).
-void level_sell(cbs_system *h, Level &L, bool mixed, bool reuse) {
+// FP32 copy of FP64 level values; an entry that does not fit FP32 sets bit
+// 64 of *flag (the hierarchy then escalates to FP64).
+__global__ void k_cast_f32_flag(int64_t m, const double *__restrict__ in, float *__restrict__ out, int32_t *flag) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= m) return;
+    const float v = (float)in[g];
+    out[g] = v;
+    if (!isfinite(v)) atomicOr(flag, 64);
+}
+
+// f32flag: where the FP32 copy reports values it cannot hold (mixed only)
+void level_sell(cbs_system *h, Level &L, bool mixed, bool reuse, int32_t *f32flag) {
     hipStream_t st = h->stream;
     const int n = h->n;
     if (!reuse || L.sell.N != L.N || !L.sell.soff.get()) sell_build(L.N, L.rp, L.col, L.sell, st);
@@ -904,13 +920,11 @@ void level_sell(cbs_system *h, Level &L, bool mixed, bool reuse) {
     sell_fill(n, L.sell, L.v64, L.sell.v64.get(), st);
     if (mixed) {
         L.sell.v32.ensure(tot > 0 ? tot : 1);
-        launch_cast<double, float>((int64_t)tot, L.sell.v64.get(), L.sell.v32.get(), st);
+        if (tot > 0)
+            hipLaunchKernelGGL(k_cast_f32_flag, dim3(cdiv((int64_t)tot, 256)), dim3(256), 0, st, (int64_t)tot,
+                               L.sell.v64.get(), L.sell.v32.get(), f32flag);
+        LAUNCHCHK();
     }
-}
-
-__global__ void k_nonfinite_f32(int64_t m, const float *a, int32_t *flag) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < m && !isfinite(a[g])) atomicOr(flag, 64);
 }
 
 std::vector<int64_t> level_sys_off(cbs_system *h, Level &L) {
@@ -936,11 +950,13 @@ void alloc_level_vectors(cbs_system *h, Level &L, bool mixed) {
 
 }  // namespace
 
-void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv) {
+void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv, int32_t *bad_slot) {
     Level &L = h->lev[l];
-    HIPCHK(hipMemsetAsync(h->dflag.get(), 0x7f, sizeof(int32_t), h->stream));
-    NSWITCH(h->n, blockinv_n, L.N, L.dslot, vals, Dinv, h->dflag.get(), h->stream);
+    int32_t *slot = bad_slot ? bad_slot : h->dflag.get();
+    HIPCHK(hipMemsetAsync(slot, 0x7f, sizeof(int32_t), h->stream));
+    NSWITCH(h->n, blockinv_n, L.N, L.dslot, vals, Dinv, slot, h->stream);
     LAUNCHCHK();
+    if (bad_slot) return;                        // the caller checks later
     const int32_t bad = read_int(h->dflag.get(), h->stream);
     if (bad != 0x7f7f7f7f)
         cbs_throw(CBS_ERR_SINGULAR, "singular diagonal block at level " + std::to_string(l) + ", block row " +
@@ -961,6 +977,13 @@ void amg_setup(cbs_system *h) {
     // same structural options exists
     const bool reuse = o.reuse_aggregates && amg && h->lev.size() > 1 && h->lev[0].agg.get() != nullptr;
     h->transposed_ready = false;
+    // errors found by kernels are collected here and read back once at the
+    // end: word 0 holds flag bits (16 asymmetric coarse pattern, 32 singular
+    // coarsest matrix), word 1 + l the first singular block row of level l
+    DArr<int32_t> errs((size_t)std::max(1, o.max_levels) + 1);
+    int32_t *deferred = errs.get();
+    HIPCHK(hipMemsetAsync(errs.get(), 0x7f, sizeof(int32_t) * ((size_t)std::max(1, o.max_levels) + 1), st));
+    HIPCHK(hipMemsetAsync(deferred, 0, sizeof(int32_t), st));
 
     if (!reuse) {
         h->lev.clear();
@@ -988,7 +1011,7 @@ void amg_setup(cbs_system *h) {
             blockinv_level(h, 0, L0.v64, L0.Dinv.get());
         }
         h->lev.resize(1);
-        level_sell(h, L0, false, false);
+        level_sell(h, L0, false, false, nullptr);
         L0.sell.sched64 = autotune_rows(n, L0.sell, false, L0.sell.v64.get(), st);
         L0.sell.sched64.split = row_split_for(L0.sell, o.row_split);
         h->op_complexity = 1.0;
@@ -1027,20 +1050,17 @@ void amg_setup(cbs_system *h) {
                 Level &C = h->lev[l + 1];
                 Level &F = h->lev[l];
                 C.N = F.nc;
-                rap_build(h, n, C.N, F.agg_ptr.get(), F.agg_mem.get(), F.rp, F.col, F.v64, F.agg.get(), C.o_rp,
-                          C.o_col, C.o_v64, true);
+                C.nnzb = rap_build(h, n, C.N, F.agg_ptr.get(), F.agg_mem.get(), F.rp, F.col, F.v64, F.agg.get(),
+                                   C.o_rp, C.o_col, C.o_v64, true);
                 C.rp = C.o_rp.get(); C.col = C.o_col.get(); C.v64 = C.o_v64.get();
-                C.nnzb = read_int(C.rp + C.N, st);
                 C.o_mirror.alloc(C.nnzb); C.o_dslot.alloc(C.N);
                 C.mirror = C.o_mirror.get(); C.dslot = C.o_dslot.get();
-                HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
                 hipLaunchKernelGGL(k_mirror_search, dim3(cdiv(C.N, 256)), dim3(256), 0, st, C.N, C.rp, C.col, C.mirror,
-                                   C.dslot, h->dflag.get());
+                                   C.dslot, deferred);
                 C.row_sys.alloc(C.N);
                 hipLaunchKernelGGL(k_inherit_sys, dim3(cdiv(F.N, 256)), dim3(256), 0, st, F.N, F.agg.get(),
                                    F.row_sys.get(), C.row_sys.get());
                 LAUNCHCHK();
-                if (read_int(h->dflag.get(), st) & 16) cbs_throw(CBS_ERR_PATTERN, "coarse pattern is not symmetric");
                 C.sys_off = level_sys_off(h, C);
                 pt.mark("rap" + std::to_string(l));
                 continue;
@@ -1060,7 +1080,7 @@ void amg_setup(cbs_system *h) {
         break;
     }
     const int nlev = (int)h->lev.size();
-    if (!reuse && o.renumber && nlev > 1) renumber_hierarchy(h);
+    if (!reuse && o.renumber && nlev > 1) renumber_hierarchy(h, deferred);
     pt.mark("renumber");
 
     // smoothers (FP64 inverses), FP32 copies, vectors
@@ -1076,14 +1096,14 @@ void amg_setup(cbs_system *h) {
         } else if (q + 1 < nlev) {
             L.dilu = false;
             L.Dinv.ensure((size_t)L.N * n * n);
-            blockinv_level(h, q, L.v64, L.Dinv.get());
+            blockinv_level(h, q, L.v64, L.Dinv.get(), errs.get() + 1 + q);
         }
         pt.mark("smoother" + std::to_string(q));
-        if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, reuse);
+        if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, reuse, deferred);
         L.scaled = mixed && q + 1 < nlev && !L.dilu;
         if (L.scaled) {
             L.sell.v32s.ensure(L.sell.nent > 0 ? (size_t)L.sell.nent * n * n : 1);
-            sell_scale(n, L.sell, L.Dinv.get(), L.sell.v32s.get(), st);
+            sell_scale(n, L.sell, L.Dinv.get(), L.sell.v32s.get(), deferred, st);
         } else {
             L.sell.v32s.release();
         }
@@ -1103,20 +1123,9 @@ void amg_setup(cbs_system *h) {
         pt.mark("autotune");
     }
     if (mixed) {
-        // FP32 level values that overflow: escalate the hierarchy to FP64
-        HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
-        for (int q = 0; q + 1 < nlev; ++q) {
-            const Level &L = h->lev[q];
-            const int64_t tot = L.sell.nent * n * n;
-            if (tot > 0)
-                hipLaunchKernelGGL(k_nonfinite_f32, dim3(cdiv(tot, 256)), dim3(256), 0, st, tot, L.sell.v32.get(),
-                                   h->dflag.get());
-            if (tot > 0 && L.scaled)
-                hipLaunchKernelGGL(k_nonfinite_f32, dim3(cdiv(tot, 256)), dim3(256), 0, st, tot, L.sell.v32s.get(),
-                                   h->dflag.get());
-        }
-        LAUNCHCHK();
-        if (read_int(h->dflag.get(), st) & 64) {
+        // FP32 level values that overflow (flagged while the FP32 copies and
+        // the row-scaled values were written): escalate the hierarchy to FP64
+        if (read_int(deferred, st) & 64) {
             h->opt.precision = CBS_PRECISION_FP64;
             h->precision_fallback = true;
             for (int q = 0; q < nlev; ++q) alloc_level_vectors(h, h->lev[q], false);
@@ -1152,11 +1161,19 @@ void amg_setup(cbs_system *h) {
     HIPCHK(hipMemcpyAsync(C.m.get(), msz.data(), sizeof(int32_t) * h->n_sys, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(C.roff.get(), roff.data(), sizeof(int64_t) * h->n_sys, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(droffb.get(), roffb.data(), sizeof(int64_t) * h->n_sys, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
     NSWITCH(n, coarse_inverse_n, h->n_sys, Lc.rp, Lc.col, Lc.v64, droffb.get(), C.off.get(), C.m.get(), work.get(),
-            C.inv.get(), C.invT.get(), h->dflag.get(), st);
+            C.inv.get(), C.invT.get(), deferred, st);
     LAUNCHCHK();
-    if (read_int(h->dflag.get(), st) & 32) cbs_throw(CBS_ERR_SINGULAR, "coarsest-level matrix is singular");
+    // one read-back of every error the setup kernels recorded
+    std::vector<int32_t> ev((size_t)nlev + 1);
+    for (int32_t k0 = 0; k0 < nlev + 1; k0 += kPinnedWords)
+        read_array(errs.get() + k0, std::min<int32_t>(kPinnedWords, nlev + 1 - k0), ev.data() + k0, st);
+    if (ev[0] & 16) cbs_throw(CBS_ERR_PATTERN, "coarse pattern is not symmetric");
+    for (int q = 0; q + 1 < nlev; ++q)
+        if (!h->lev[q].dilu && ev[1 + q] != 0x7f7f7f7f)
+            cbs_throw(CBS_ERR_SINGULAR, "singular diagonal block at level " + std::to_string(q) + ", block row " +
+                                            std::to_string(ev[1 + q]));
+    if (ev[0] & 32) cbs_throw(CBS_ERR_SINGULAR, "coarsest-level matrix is singular");
     pt.mark("coarse");
 }
 
@@ -1197,8 +1214,9 @@ void amg_build_transposed(cbs_system *h) {
     h->transposed_ready = true;
 }
 
-// Permute every level but the coarsest into the aggregation-tree order.
-void renumber_hierarchy(cbs_system *h) {
+// Permute every level but the coarsest into the aggregation-tree order;
+// pattern errors go to the flag word `deferred`.
+void renumber_hierarchy(cbs_system *h, int32_t *deferred) {
     hipStream_t st = h->stream;
     const int n = h->n;
     const int nlev = (int)h->lev.size();
@@ -1242,10 +1260,8 @@ void renumber_hierarchy(cbs_system *h) {
         hipLaunchKernelGGL(k_perm_map, G, B, 0, st, N, ip.get(), L.agg.get(), pos[l + 1].get(), aggn.get());
         hipLaunchKernelGGL(k_iota, G, B, 0, st, N, memn.get());
         hipLaunchKernelGGL(k_perm_map, G, B, 0, st, N, ip.get(), L.row_sys.get(), nullptr, rsn.get());
-        HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
-        hipLaunchKernelGGL(k_mirror_search, G, B, 0, st, N, rpn.get(), coln.get(), mir.get(), dsl.get(), h->dflag.get());
+        hipLaunchKernelGGL(k_mirror_search, G, B, 0, st, N, rpn.get(), coln.get(), mir.get(), dsl.get(), deferred);
         LAUNCHCHK();
-        if (read_int(h->dflag.get(), st) & 16) cbs_throw(CBS_ERR_PATTERN, "renumbered pattern is not symmetric");
         if (l == 0) h->perm_sk = std::move(sk);
         L.o_rp = std::move(rpn); L.o_col = std::move(coln); L.o_v64 = std::move(vn);
         L.o_mirror = std::move(mir); L.o_dslot = std::move(dsl);

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <initializer_list>
 #include <vector>
 
 #include "cbs.h"
@@ -238,6 +239,10 @@ struct PhaseTimer {
 // exclusive scan of n int32 counts into out[0..n] (out[n] = total); in may alias out
 void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, hipStream_t st);
 int32_t read_int(const int32_t *dptr, hipStream_t st);
+// several device int32 scalars / a short device array, one synchronisation
+constexpr int kPinnedWords = 64;
+void read_ints(std::initializer_list<const int32_t *> src, int32_t *out, hipStream_t st);
+void read_array(const int32_t *dptr, int32_t count, int32_t *out, hipStream_t st);
 
 // conversion (convert.hip)
 void convert_pattern(cbs_system *h);
@@ -279,8 +284,9 @@ int8_t row_split_for(const Sell &S, int32_t opt_split);
 // sliced-ELL pattern from BCSR, and values gathered from BCSR values
 void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st);
 void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st);
-// out = FP32(Dinv_i A_ij) for every entry of the FP64 sliced values S.v64
-void sell_scale(int n, const Sell &S, const double *Dinv, float *out, hipStream_t st);
+// out = FP32(Dinv_i A_ij) for every entry of the FP64 sliced values S.v64;
+// an entry FP32 cannot hold sets bit 64 of *flag
+void sell_scale(int n, const Sell &S, const double *Dinv, float *out, int32_t *flag, hipStream_t st);
 template <typename TX>
 void launch_restrict(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem,
                      const TX *r, TX *bc, hipStream_t st);
@@ -302,11 +308,13 @@ void launch_dilu_bwd(int n, const SellView &S, const T *val, const int32_t *colo
 // AMG setup (amg.hip)
 void amg_setup(cbs_system *h);
 void amg_build_transposed(cbs_system *h);
-void renumber_hierarchy(cbs_system *h);
+void renumber_hierarchy(cbs_system *h, int32_t *deferred);
 void refresh_level0_values(cbs_system *h);
 void permute_vec(cbs_system *h, const double *in, double *out, bool to_internal);
 void spmv_user(cbs_system *h, const double *x, double *y, bool transposed);
-void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv);
+// block-diagonal inverses of level l; with bad_slot the first singular block
+// row is left there for the caller to check, else it is checked here
+void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv, int32_t *bad_slot = nullptr);
 
 // Krylov (krylov.hip)
 int krylov_solve(cbs_system *h, const double *b, double *x, cbs_stats *st, bool transposed);

@@ -89,10 +89,35 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, hipStream_t st) 
     LAUNCHCHK();
 }
 
+// Device scalars come back through a few pinned host words (one set per host
+// thread, kept for the life of the process), so several reads share one
+// stream synchronisation.
+static int32_t *pinned_words() {
+    thread_local int32_t *p = nullptr;
+    if (!p) HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&p), kPinnedWords * sizeof(int32_t), hipHostMallocDefault));
+    return p;
+}
+
+void read_ints(std::initializer_list<const int32_t *> src, int32_t *out, hipStream_t st) {
+    if (src.size() > (size_t)kPinnedWords) cbs_throw(CBS_ERR_ARG, "too many device scalars in one read");
+    int32_t *w = pinned_words();
+    int k = 0;
+    for (const int32_t *p : src) HIPCHK(hipMemcpyAsync(w + k++, p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < k; ++i) out[i] = w[i];
+}
+
+void read_array(const int32_t *dptr, int32_t count, int32_t *out, hipStream_t st) {
+    if (count > kPinnedWords) cbs_throw(CBS_ERR_ARG, "too many device scalars in one read");
+    int32_t *w = pinned_words();
+    if (count > 0) HIPCHK(hipMemcpyAsync(w, dptr, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < count; ++i) out[i] = w[i];
+}
+
 int32_t read_int(const int32_t *dptr, hipStream_t st) {
     int32_t v = 0;
-    HIPCHK(hipMemcpyAsync(&v, dptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    read_ints({dptr}, &v, st);
     return v;
 }
 

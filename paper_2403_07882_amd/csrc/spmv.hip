@@ -455,7 +455,7 @@ __global__ void k_sell_vals(int64_t nent, const int32_t *__restrict__ ssrc, cons
 template <int n>
 __global__ void k_sell_scaled(int32_t N, int32_t nslices, const int32_t *__restrict__ soff,
                               const int32_t *__restrict__ sw, const double *__restrict__ v64,
-                              const double *__restrict__ Dinv, float *__restrict__ out) {
+                              const double *__restrict__ Dinv, float *__restrict__ out, int32_t *flag) {
     constexpr int nn = n * n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (int64_t)nslices * kSlice * n) return;
@@ -475,7 +475,9 @@ __global__ void k_sell_scaled(int32_t N, int32_t nslices, const int32_t *__restr
             double acc = 0.0;
 #pragma unroll
             for (int q = 0; q < n; ++q) acc += d[q] * a[q * n + c];
-            out[e * nn + r * n + c] = (float)acc;
+            const float v = (float)acc;
+            out[e * nn + r * n + c] = v;
+            if (!isfinite(v)) atomicOr(flag, 64);
         }
     }
 }
@@ -602,13 +604,13 @@ void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipSt
     LAUNCHCHK();
 }
 
-void sell_scale(int n, const Sell &S, const double *Dinv, float *out, hipStream_t st) {
+void sell_scale(int n, const Sell &S, const double *Dinv, float *out, int32_t *flag, hipStream_t st) {
     const int64_t m = (int64_t)S.nslices * kSlice * n;
     if (S.N <= 0) return;
     const dim3 g(cdiv(m, 256)), b(256);
 #define SCALE_N(NN)                                                                                           \
     hipLaunchKernelGGL(k_sell_scaled<NN>, g, b, 0, st, S.N, S.nslices, S.soff.get(), S.sw.get(), S.v64.get(), \
-                       Dinv, out)
+                       Dinv, out, flag)
     switch (n) {
         case 1: SCALE_N(1); break;
         case 2: SCALE_N(2); break;
