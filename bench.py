@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE counter runs of `bench.py --kernels-only`, each scaled by what the
 # counter reads for a 1 GiB copy (see profiles/); None where not measured for
 # the current kernel code.
-TRAFFIC_PU1M = {"sweep": 620371076, "spmv_internal": 1133360751, "spmv_caller": 1718727495}
+TRAFFIC_PU1M = {"sweep": 542220394, "spmv_internal": 1133360751, "spmv_caller": 1718727495}
 
 
 def parse():
@@ -69,10 +69,13 @@ def spmv_bytes(N, nnzb, n, s=8):
 
 def sweep_bytes(N, nnzb, n, s=4, dinv=False):
     """Algorithmic bytes of one block-Jacobi sweep y = x + w Dinv (b - A x):
-    values + column indices + row pointers + x, b read once + y written once
-    (+ the FP64 block inverses when the sweep applies them; the row-scaled
-    FP32 sweep has them folded into its values)."""
-    return nnzb * (n * n * s + 4) + (N + 1) * 4 + 3 * N * n * s + (N * n * n * 8 if dinv else 0)
+    values + column indices + row pointers + x, b read once + y written once.
+    The FP64 sweep also reads the block inverses; the row-scaled FP32 sweep
+    has them folded into its values and stores no diagonal blocks (the
+    scaled diagonal block is the identity), so it reads nnzb - N blocks."""
+    if dinv:
+        return nnzb * (n * n * s + 4) + (N + 1) * 4 + 3 * N * n * s + N * n * n * 8
+    return (nnzb - N) * (n * n * s + 4) + (N + 1) * 4 + 3 * N * n * s
 
 
 def cpu_baseline(shape):
@@ -356,7 +359,7 @@ def main():
         "mixed_vs_fp64_speedup": round(t_fp64 / t_mixed, 3) if t_fp64 == t_fp64 else None,
         "vcycle_ms": round(vcyc_ms, 4),
         "roofline": kobj("level-0 block-Jacobi sweep, %s (k_rows, internal numbering); the kernel with the "
-                         "largest share of the step" % ("FP32 row-scaled" if sweep_fp32 else "FP64"),
+                         "largest share of the step" % ("FP32 row-scaled off-diagonal" if sweep_fp32 else "FP64"),
                          sweep_ms, sbytes, TRAFFIC_PU1M["sweep"]),
         "spmv_fp64": kobj("block SpMV FP64 (k_rows mode 0), internal numbering", spmv_ms, byts,
                           TRAFFIC_PU1M["spmv_internal"]),

@@ -910,11 +910,11 @@ __global__ void k_cast_f32_flag(int64_t m, const double *__restrict__ in, float 
     if (!isfinite(v)) atomicOr(flag, 64);
 }
 
+// Values of the level's sliced copy (its pattern is built beforehand).
 // f32flag: where the FP32 copy reports values it cannot hold (mixed only)
-void level_sell(cbs_system *h, Level &L, bool mixed, bool reuse, int32_t *f32flag) {
+void level_sell(cbs_system *h, Level &L, bool mixed, int32_t *f32flag) {
     hipStream_t st = h->stream;
     const int n = h->n;
-    if (!reuse || L.sell.N != L.N || !L.sell.soff.get()) sell_build(L.N, L.rp, L.col, L.sell, st);
     const size_t tot = (size_t)L.sell.nent * n * n;
     L.sell.v64.ensure(tot > 0 ? tot : 1);
     sell_fill(n, L.sell, L.v64, L.sell.v64.get(), st);
@@ -1011,7 +1011,8 @@ void amg_setup(cbs_system *h) {
             blockinv_level(h, 0, L0.v64, L0.Dinv.get());
         }
         h->lev.resize(1);
-        level_sell(h, L0, false, false, nullptr);
+        sell_build(L0.N, L0.rp, L0.col, L0.sell, st);
+        level_sell(h, L0, false, nullptr);
         L0.sell.sched64 = autotune_rows(n, L0.sell, false, L0.sell.v64.get(), st);
         L0.sell.sched64.split = row_split_for(L0.sell, o.row_split);
         h->op_complexity = 1.0;
@@ -1083,12 +1084,46 @@ void amg_setup(cbs_system *h) {
     if (!reuse && o.renumber && nlev > 1) renumber_hierarchy(h, deferred);
     pt.mark("renumber");
 
+    // sliced patterns of the solve phase: the full one of every smoothed level
+    // (and level 0), the off-diagonal one of the mixed block-Jacobi levels;
+    // new patterns share one read-back of their entry counts
+    auto level_uses_dilu = [&](int q) {
+        return o.smoother == CBS_SMOOTH_DILU && (o.dilu_levels < 0 || q < o.dilu_levels) && q + 1 < nlev;
+    };
+    {
+        struct Pending { Level *L; Sell *S; bool od; };
+        std::vector<Pending> todo;
+        for (int q = 0; q < nlev; ++q) {
+            Level &L = h->lev[q];
+            const bool keep_sell = reuse && L.sell.N == L.N && L.sell.soff.get();
+            const bool keep_sod = reuse && L.sod.N == L.N && L.sod.soff.get();
+            if ((q == 0 || q + 1 < nlev) && !keep_sell) todo.push_back({&L, &L.sell, false});
+            if (mixed && q + 1 < nlev && !level_uses_dilu(q) && !keep_sod) todo.push_back({&L, &L.sod, true});
+        }
+        for (auto &t : todo) sell_pattern_begin(t.L->N, t.L->rp, t.L->col, *t.S, st, t.od);
+        for (size_t k0 = 0; k0 < todo.size(); k0 += kPinnedWords) {
+            const size_t k1 = std::min(todo.size(), k0 + kPinnedWords);
+            int32_t cnt[kPinnedWords];
+            int32_t *w = pinned_words();
+            for (size_t k = k0; k < k1; ++k) {   // one synchronisation per 64 patterns
+                const Sell &S = *todo[k].S;
+                HIPCHK(hipMemcpyAsync(w + (k - k0), S.soff.get() + S.nslices, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      st));
+            }
+            HIPCHK(hipStreamSynchronize(st));
+            for (size_t k = k0; k < k1; ++k) cnt[k - k0] = w[k - k0];
+            for (size_t k = k0; k < k1; ++k)
+                sell_pattern_finish(todo[k].L->rp, todo[k].L->col, *todo[k].S, cnt[k - k0], st, todo[k].od);
+        }
+        pt.mark("patterns");
+    }
+
     // smoothers (FP64 inverses), FP32 copies, vectors
     int64_t nz_sum = 0;
     for (int q = 0; q < nlev; ++q) {
         Level &L = h->lev[q];
         nz_sum += L.nnzb;
-        const bool use_dilu = o.smoother == CBS_SMOOTH_DILU && (o.dilu_levels < 0 || q < o.dilu_levels);
+        const bool use_dilu = level_uses_dilu(q);
         if (q + 1 < nlev && use_dilu) {
             L.dilu = true;
             if (!reuse || !L.colour.get()) colour_level(h, q);
@@ -1099,13 +1134,13 @@ void amg_setup(cbs_system *h) {
             blockinv_level(h, q, L.v64, L.Dinv.get(), errs.get() + 1 + q);
         }
         pt.mark("smoother" + std::to_string(q));
-        if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, reuse, deferred);
+        if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, deferred);
         L.scaled = mixed && q + 1 < nlev && !L.dilu;
         if (L.scaled) {
-            L.sell.v32s.ensure(L.sell.nent > 0 ? (size_t)L.sell.nent * n * n : 1);
-            sell_scale(n, L.sell, L.Dinv.get(), L.sell.v32s.get(), deferred, st);
+            L.sod.v32.ensure(L.sod.nent > 0 ? (size_t)L.sod.nent * n * n : 1);
+            sell_scale(n, L.sod, L.v64, L.Dinv.get(), L.sod.v32.get(), deferred, st);
         } else {
-            L.sell.v32s.release();
+            L.sod = Sell();
         }
         alloc_level_vectors(h, L, mixed);
         pt.mark("sell" + std::to_string(q));
@@ -1116,9 +1151,10 @@ void amg_setup(cbs_system *h) {
         const Sched s64 = autotune_rows(n, T0.sell, false, T0.sell.v64.get(), st);
         const Sched s32 = mixed ? autotune_rows(n, T0.sell, true, T0.sell.v32.get(), st) : Sched{4, 1};
         for (auto &L : h->lev) {
-            L.sell.sched64 = s64;
-            L.sell.sched32 = s32;
+            L.sell.sched64 = L.sod.sched64 = s64;
+            L.sell.sched32 = L.sod.sched32 = s32;
             L.sell.sched64.split = L.sell.sched32.split = row_split_for(L.sell, o.row_split);
+            L.sod.sched32.split = row_split_for(L.sod, o.row_split);
         }
         pt.mark("autotune");
     }

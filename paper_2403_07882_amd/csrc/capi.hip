@@ -426,7 +426,7 @@ int cbs_level_apply(cbs_handle h, int32_t level, int32_t op, const void *b, cons
             if (op == CBS_LEVEL_RESIDUAL)
                 launch_rows<float, float>(1, n, S, L.sell.v32.get(), xx, bb, yy, nullptr, 0.0, st);
             else if (L.scaled)
-                launch_rows<float, float>(4, n, S, L.sell.v32s.get(), xx, bb, yy, nullptr, w, st);
+                launch_rows<float, float>(4, n, L.sod.view(true), L.sod.v32.get(), xx, bb, yy, nullptr, w, st);
             else
                 launch_rows<float, float>(2, n, S, L.sell.v32.get(), xx, bb, yy, L.Dinv.get(), w, st);
         } else {

@@ -118,7 +118,6 @@ struct Sell {
     DArr<int32_t> soff, sw, scol, ssrc;   // ssrc: BCSR slot of each entry, -1 = padding
     DArr<double> v64, v64T;
     DArr<float> v32, v32T;
-    DArr<float> v32s;                     // FP32 Dinv_i A_ij: values of the scaled sweep
     Sched sched64{4, 0}, sched32{4, 1};
     SellView view(bool fp32 = false) const {
         return SellView{N, soff.get(), sw.get(), scol.get(), fp32 ? sched32 : sched64};
@@ -144,9 +143,11 @@ struct Level {
     std::vector<int64_t> sys_off;
     // smoother data (FP64 per the block-inversion rule)
     DArr<double> Dinv, DinvT;
-    // mixed precision, block Jacobi: the FP32 sweeps run on row-scaled values
-    // (sell.v32s) with the level's Dinv b kept in vc
+    // mixed precision, block Jacobi: the FP32 sweeps run on the row-scaled
+    // off-diagonal values Dinv_i A_ij, j != i (sod: its own sliced pattern,
+    // values in sod.v32), with the level's Dinv b kept in vc
     bool scaled = false;
+    Sell sod;
     // DILU: colour classes (rows of colour c: rows_by_colour[colour_off[c] ..
     // colour_off[c+1])) and the FP64 inverses of the DILU diagonal E
     bool dilu = false;
@@ -241,6 +242,7 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, hipStream_t st);
 int32_t read_int(const int32_t *dptr, hipStream_t st);
 // several device int32 scalars / a short device array, one synchronisation
 constexpr int kPinnedWords = 64;
+int32_t *pinned_words();                 // kPinnedWords pinned host words of this thread
 void read_ints(std::initializer_list<const int32_t *> src, int32_t *out, hipStream_t st);
 void read_array(const int32_t *dptr, int32_t count, int32_t *out, hipStream_t st);
 
@@ -256,7 +258,8 @@ void gradient(cbs_system *h, const double *lam, const double *x, double *gd, dou
 //   mode 0: y = A x;  mode 1: y = b - A x;  mode 2: y = x + omega Dinv (b - A x)
 //   mode 3: y = omega Dinv b (block-Jacobi sweep from a zero guess), and
 //           aux = Dinv b when aux is not null
-//   mode 4: y = x + omega (b - A x) on row-scaled values Dinv A with b = Dinv b
+//   mode 4: y = x + omega (b - x - A x) on the row-scaled off-diagonal values
+//           Dinv_i A_ij (j != i) with b = Dinv b: the sweep of mode 2
 // Modes 2 and 4 with pagg != nullptr sweep from x + P e (pagg: aggregate map
 // of the level, pe: coarse-level correction): the prolongation fused into
 // the first post-smoothing sweep.
@@ -281,12 +284,19 @@ void launch_restrict_sweep0(int n, int32_t nc, const int32_t *agg_ptr, const int
 Sched autotune_rows(int n, const Sell &S, bool fp32, const void *val, hipStream_t st);
 // threads per scalar row of the block-row kernels on a level (row_split option)
 int8_t row_split_for(const Sell &S, int32_t opt_split);
-// sliced-ELL pattern from BCSR, and values gathered from BCSR values
-void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st);
+// sliced-ELL pattern from BCSR (offdiag: without the diagonal blocks), and
+// values gathered from BCSR values
+void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag = false);
+// the same in two halves, so that several patterns share one read-back of
+// their entry counts (S.soff[S.nslices] after begin)
+void sell_pattern_begin(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag);
+void sell_pattern_finish(const int32_t *rp, const int32_t *col, Sell &S, int64_t nent, hipStream_t st,
+                         bool offdiag);
 void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st);
-// out = FP32(Dinv_i A_ij) for every entry of the FP64 sliced values S.v64;
-// an entry FP32 cannot hold sets bit 64 of *flag
-void sell_scale(int n, const Sell &S, const double *Dinv, float *out, int32_t *flag, hipStream_t st);
+// out = FP32(Dinv_i A_ij) for every entry of the sliced pattern S, A_ij read
+// from the block-CSR values; an entry FP32 cannot hold sets bit 64 of *flag
+void sell_scale(int n, const Sell &S, const double *bcsr_vals, const double *Dinv, float *out, int32_t *flag,
+                hipStream_t st);
 template <typename TX>
 void launch_restrict(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem,
                      const TX *r, TX *bc, hipStream_t st);

@@ -92,7 +92,7 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, hipStream_t st) 
 // Device scalars come back through a few pinned host words (one set per host
 // thread, kept for the life of the process), so several reads share one
 // stream synchronisation.
-static int32_t *pinned_words() {
+int32_t *pinned_words() {
     thread_local int32_t *p = nullptr;
     if (!p) HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&p), kPinnedWords * sizeof(int32_t), hipHostMallocDefault));
     return p;

@@ -472,13 +472,13 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
     // FP32 forward sweeps run on the row-scaled values Dinv A against
     // c = Dinv b, which the zero-guess sweep leaves behind
     const bool scaled = fp32 && !tr && L.scaled;
-    const T *sval = scaled ? reinterpret_cast<const T *>(L.sell.v32s.get()) : nullptr;
+    const T *sval = scaled ? reinterpret_cast<const T *>(L.sod.v32.get()) : nullptr;
     T *c = scaled ? vptr<T>(L.vc) : nullptr;
     // pagg/pe: sweep from x + P e (the prolongation fused into the sweep);
     // y64: write the result widened to FP64 there instead of into `to`
     auto sweep = [&](T *from, T *to, const int32_t *pagg, const T *pe, double *y64) {
         if (scaled)
-            launch_rows<T, T>(4, n, L.sell.view(true), sval, from, c, to, nullptr, o.omega, st, nullptr, pagg, pe,
+            launch_rows<T, T>(4, n, L.sod.view(true), sval, from, c, to, nullptr, o.omega, st, nullptr, pagg, pe,
                               y64);
         else
             launch_rows<T, T>(2, n, L.sell.view(fp32), val, from, b, to, Dinv, o.omega, st, nullptr, pagg, pe, y64);

@@ -85,8 +85,9 @@ __device__ inline void load_xc(const TX *__restrict__ x, int64_t j, const int32_
 }
 
 // mode 0: y = A x; 1: y = b - A x; 2: y = x + w Dinv (b - A x); 3: y = w Dinv b
-// (and aux = Dinv b when aux is given); 4: y = x + w (b - A x), the sweep of
-// mode 2 on row-scaled values Dinv A with b = Dinv b.
+// (and aux = Dinv b when aux is given); 4: y = x + w (b - x - A x), the sweep
+// of mode 2 on the row-scaled off-diagonal values Dinv_i A_ij (j != i; the
+// scaled diagonal block is the identity and is not stored) with b = Dinv b.
 // Rows are read from the sliced-ELL copy: at step k the 16 rows of a slice
 // read 16 consecutive blocks; four steps are loaded before they are summed,
 // and the sums run in the row's column order.
@@ -163,7 +164,10 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
         return;
     }
     if (MODE == 4) {
-        if (i < N) put(o, (TX)(x_own() + (A)omega * res));
+        if (i < N) {
+            const A xo = x_own();
+            put(o, (TX)(xo + (A)omega * (res - xo)));
+        }
         return;
     }
     __shared__ A sres[64 * n];
@@ -240,7 +244,10 @@ __global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__r
             if (MODE == 1) {
                 if (i < N) y[o] = (TX)res;
             } else if (MODE == 4) {
-                if (i < N) put(o, (TX)(x_own(o) + (A)omega * res));
+                if (i < N) {
+                    const A xo = x_own(o);
+                    put(o, (TX)(xo + (A)omega * (res - xo)));
+                }
             } else {
                 sres[lr * n + r] = res;
             }
@@ -411,24 +418,34 @@ __global__ __launch_bounds__(64 * n) void k_dilu_bwd(SellView S, const T *__rest
 }
 
 // ------------------------------------------------------------------ sliced ELL build
-__global__ void k_sell_width(int32_t N, int32_t ns, const int32_t *rp, int32_t *sw, int32_t *cnt) {
+// offdiag: leave out the diagonal block of each row (counted, not assumed)
+__global__ void k_sell_width(int32_t N, int32_t ns, const int32_t *rp, const int32_t *col, int32_t *sw, int32_t *cnt,
+                             int offdiag) {
     const int32_t sl = blockIdx.x * blockDim.x + threadIdx.x;
     if (sl >= ns) return;
     int32_t w = 0;
-    for (int32_t i = sl * kSlice; i < min(N, (sl + 1) * kSlice); ++i) w = max(w, rp[i + 1] - rp[i]);
+    for (int32_t i = sl * kSlice; i < min(N, (sl + 1) * kSlice); ++i) {
+        int32_t len = rp[i + 1] - rp[i];
+        if (offdiag)
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) len -= col[k] == i ? 1 : 0;
+        w = max(w, len);
+    }
     sw[sl] = w;
     cnt[sl] = w * kSlice;
 }
 
 __global__ void k_sell_fill_idx(int32_t N, const int32_t *rp, const int32_t *col, const int32_t *soff, int32_t *scol,
-                                int32_t *ssrc) {
+                                int32_t *ssrc, int offdiag) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+    int32_t q = 0;
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int64_t e = soff[sl] + (int64_t)(k - rp[i]) * kSlice + ii;
+        if (offdiag && col[k] == i) continue;
+        const int64_t e = soff[sl] + (int64_t)q * kSlice + ii;
         scol[e] = col[k];
         ssrc[e] = k;
+        ++q;
     }
 }
 
@@ -448,14 +465,16 @@ __global__ void k_sell_vals(int64_t nent, const int32_t *__restrict__ ssrc, cons
     out[g] = k >= 0 ? in[(int64_t)k * nn + (g - e * nn)] : 0.0;
 }
 
-// Row-scaled FP32 values for the block-Jacobi sweep: entry (i, j) becomes
-// Dinv_i A_ij, formed in FP64 and rounded once.  One thread per (slice row,
-// r); the rows that pad the last slice past N get zeros like every other
-// padding entry.
+// Row-scaled FP32 values for the block-Jacobi sweep: entry (i, j) of the
+// sliced copy S becomes Dinv_i A_ij (A_ij read from the block-CSR values
+// through S.ssrc), formed in FP64 and rounded once.  One thread per (slice
+// row, r); padding entries, including the rows that pad the last slice past
+// N, get zeros.
 template <int n>
 __global__ void k_sell_scaled(int32_t N, int32_t nslices, const int32_t *__restrict__ soff,
-                              const int32_t *__restrict__ sw, const double *__restrict__ v64,
-                              const double *__restrict__ Dinv, float *__restrict__ out, int32_t *flag) {
+                              const int32_t *__restrict__ sw, const int32_t *__restrict__ ssrc,
+                              const double *__restrict__ bvals, const double *__restrict__ Dinv,
+                              float *__restrict__ out, int32_t *flag) {
     constexpr int nn = n * n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (int64_t)nslices * kSlice * n) return;
@@ -469,12 +488,13 @@ __global__ void k_sell_scaled(int32_t N, int32_t nslices, const int32_t *__restr
     for (int q = 0; q < n; ++q) d[q] = i < N ? Dinv[(int64_t)i * nn + r * n + q] : 0.0;
     for (int32_t k = 0; k < w; ++k) {
         const int64_t e = base + (int64_t)k * kSlice;
-        const double *a = v64 + e * nn;
+        const int32_t src = i < N ? ssrc[e] : -1;
+        const double *a = bvals + (int64_t)(src < 0 ? 0 : src) * nn;
 #pragma unroll
         for (int c = 0; c < n; ++c) {
             double acc = 0.0;
 #pragma unroll
-            for (int q = 0; q < n; ++q) acc += d[q] * a[q * n + c];
+            for (int q = 0; q < n; ++q) acc += d[q] * (src < 0 ? 0.0 : a[q * n + c]);
             const float v = (float)acc;
             out[e * nn + r * n + c] = v;
             if (!isfinite(v)) atomicOr(flag, 64);
@@ -567,17 +587,23 @@ template void launch_rows<float, float>(int, int, const SellView &, const float 
                                         float *, const double *, double, hipStream_t, float *, const int32_t *,
                                         const float *, double *);
 
-void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st) {
+void sell_pattern_begin(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag) {
     S.N = N;
     S.nslices = (N + kSlice - 1) / kSlice;
     const int32_t ns = S.nslices;
     S.sw.alloc(ns > 0 ? ns : 1);
     S.soff.alloc(ns + 1);
     if (ns > 0)
-        hipLaunchKernelGGL(k_sell_width, dim3(cdiv(ns, 256)), dim3(256), 0, st, N, ns, rp, S.sw.get(), S.soff.get());
+        hipLaunchKernelGGL(k_sell_width, dim3(cdiv(ns, 256)), dim3(256), 0, st, N, ns, rp, col, S.sw.get(),
+                           S.soff.get(), offdiag ? 1 : 0);
     LAUNCHCHK();
     scan_exclusive(S.soff.get(), S.soff.get(), ns, st);
-    S.nent = read_int(S.soff.get() + ns, st);
+}
+
+void sell_pattern_finish(const int32_t *rp, const int32_t *col, Sell &S, int64_t nent, hipStream_t st,
+                         bool offdiag) {
+    const int32_t N = S.N;
+    S.nent = nent;
     S.scol.alloc(S.nent > 0 ? S.nent : 1);
     S.ssrc.alloc(S.nent > 0 ? S.nent : 1);
     if (S.nent > 0) {
@@ -586,8 +612,13 @@ void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipSt
     }
     if (N > 0)
         hipLaunchKernelGGL(k_sell_fill_idx, dim3(cdiv(N, 256)), dim3(256), 0, st, N, rp, col, S.soff.get(),
-                           S.scol.get(), S.ssrc.get());
+                           S.scol.get(), S.ssrc.get(), offdiag ? 1 : 0);
     LAUNCHCHK();
+}
+
+void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag) {
+    sell_pattern_begin(N, rp, col, S, st, offdiag);
+    sell_pattern_finish(rp, col, S, read_int(S.soff.get() + S.nslices, st), st, offdiag);
 }
 
 void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st) {
@@ -604,13 +635,14 @@ void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipSt
     LAUNCHCHK();
 }
 
-void sell_scale(int n, const Sell &S, const double *Dinv, float *out, int32_t *flag, hipStream_t st) {
+void sell_scale(int n, const Sell &S, const double *bcsr_vals, const double *Dinv, float *out, int32_t *flag,
+                hipStream_t st) {
     const int64_t m = (int64_t)S.nslices * kSlice * n;
     if (S.N <= 0) return;
     const dim3 g(cdiv(m, 256)), b(256);
 #define SCALE_N(NN)                                                                                           \
-    hipLaunchKernelGGL(k_sell_scaled<NN>, g, b, 0, st, S.N, S.nslices, S.soff.get(), S.sw.get(), S.v64.get(), \
-                       Dinv, out, flag)
+    hipLaunchKernelGGL(k_sell_scaled<NN>, g, b, 0, st, S.N, S.nslices, S.soff.get(), S.sw.get(), S.ssrc.get(), \
+                       bcsr_vals, Dinv, out, flag)
     switch (n) {
         case 1: SCALE_N(1); break;
         case 2: SCALE_N(2); break;
