@@ -283,8 +283,38 @@ def main():
         t_fp64, _, st64 = run_steps(opt_fp64, max(1, args.steps // 2))
         log("fp64: %.2f ms/step, iterations %d" % (t_fp64, st64["iterations"]))
 
-    # kernels, each timed alone with HIP events on the library's stream
+    # the remaining rows of the path on the same system: field packing, the
+    # adjoint (transposed solve + LDU gradient), each timed with HIP events
     timer = KernelTimer(torch, args.kernel_reps)
+    pack_ms = timer(lambda: L.cbs_pack_fields(N, n, C.c_void_p(b_fields.data_ptr()), C.c_void_p(b.data_ptr()), stream))
+    unpack_ms = timer(lambda: L.cbs_unpack_fields(N, n, C.c_void_p(x.data_ptr()), C.c_void_p(x_fields.data_ptr()),
+                                                  stream))
+    sysm.setup(opt_mixed)
+    gvec = torch.randn(N * n, dtype=torch.float64, device=dev)
+    lam = torch.zeros_like(gvec)
+    xsol = torch.zeros_like(gvec)
+    st_f = P.Stats()
+    L.cbs_solve(sysm.h, C.c_void_p(b.data_ptr()), C.c_void_p(xsol.data_ptr()), C.byref(st_f))
+    st_t = P.Stats()
+
+    def adjoint_solve():
+        lam.zero_()
+        rc = L.cbs_solve_transpose(sysm.h, C.c_void_p(gvec.data_ptr()), C.c_void_p(lam.data_ptr()), C.byref(st_t))
+        if rc < 0:
+            raise P.CbsError(rc, "cbs_solve_transpose")
+    adjoint_solve()                                     # builds the transposed hierarchy once
+    adj_ms = KernelTimer(torch, 3)(adjoint_solve, warm=1)
+    gd = torch.empty((N, n, n), dtype=torch.float64, device=dev)
+    gu = torch.empty((F, n, n), dtype=torch.float64, device=dev)
+    gl = torch.empty((F, n, n), dtype=torch.float64, device=dev)
+    grad_ms = timer(lambda: L.cbs_gradient(sysm.h, C.c_void_p(lam.data_ptr()), C.c_void_p(xsol.data_ptr()),
+                                           C.c_void_p(gd.data_ptr()), C.c_void_p(gu.data_ptr()),
+                                           C.c_void_p(gl.data_ptr())))
+    del gd, gu, gl
+    log("pack %.1f us, unpack %.1f us; transposed solve %.2f ms (%d iterations), gradient %.1f us"
+        % (pack_ms * 1e3, unpack_ms * 1e3, adj_ms, st_t.iterations, grad_ms * 1e3))
+
+    # kernels, each timed alone with HIP events on the library's stream
     sysm.setup(opt_mixed)
     lv0 = sysm.get_level(0)
     sweep, sweep_fp32 = level_sweep_call(P, torch, dev, sysm, n)
@@ -358,6 +388,11 @@ def main():
         "fp64_iterations": st64["iterations"],
         "mixed_vs_fp64_speedup": round(t_fp64 / t_mixed, 3) if t_fp64 == t_fp64 else None,
         "vcycle_ms": round(vcyc_ms, 4),
+        "pack_fields_us": round(pack_ms * 1e3, 2),
+        "unpack_fields_us": round(unpack_ms * 1e3, 2),
+        "transposed_solve_ms": round(adj_ms, 3),
+        "transposed_iterations": st_t.iterations,
+        "gradient_us": round(grad_ms * 1e3, 2),
         "roofline": kobj("level-0 block-Jacobi sweep, %s (k_rows, internal numbering); the kernel with the "
                          "largest share of the step" % ("FP32 row-scaled off-diagonal" if sweep_fp32 else "FP64"),
                          sweep_ms, sbytes, TRAFFIC_PU1M["sweep"]),
