@@ -194,6 +194,25 @@ def test_amg_solve_pressure_velocity(precision, solver):
         _check_solution(A, s["b"], _np(x2), xref, tol=1e-11, err=1e-6)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_amg_solve_every_block_size(n):
+    """Mixed AMG-BiCGStab and the transposed solve for each block size the
+    kernels are built for (n = 4 is covered by the pressure-velocity tests)."""
+    _say("amg block size", n)
+    s = jacobian_box(14, 12, 10, n=n, seed=20 + n)
+    A = O.from_system(s)
+    xref = _ref_solution(A, s["b"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, precision=P.PRECISION_MIXED, tol=1e-10, coarse_max=8)
+        assert sysm.info()["levels"] >= 3
+        x, st = sysm.solve(s["b"])
+        assert st["status"] == P.OK and st["precision_fallback"] == 0, st
+        _check_solution(A, s["b"], _np(x), xref, tol=1e-10, err=1e-7)
+        lam, stt = sysm.solve_transpose(s["b"])
+        assert stt["status"] == P.OK, stt
+        assert O.relres(O.transpose(A), s["b"], _np(lam)) <= 1e-10 * 1.0001
+
+
 def test_amg_solve_density_stretched():
     _say("amg stretched")
     s = jacobian_stretched(14, 14, 40, seed=0)
@@ -552,6 +571,28 @@ def test_batched_fgmres_and_zero_system():
     xn = _np(x)
     assert stats[1]["iterations"] == 0 and np.all(xn[cat["cell_off"][1]:] == 0)
     assert O.relres(O.from_system(systems[0]), systems[0]["b"], xn[:cat["cell_off"][1]]) <= 1e-9
+
+
+@pytest.mark.parametrize("smoother", [P.SMOOTH_BJACOBI, P.SMOOTH_DILU])
+def test_batched_mixed_uneven_pressure_velocity(smoother):
+    """A batch of p-U systems of uneven sizes, mixed precision, both smoothers:
+    every system meets its tolerance; the transposed batch solve too."""
+    _say("batched pv", smoother)
+    shapes = [(9, 7, 5), (4, 4, 3), (12, 6, 6), (5, 5, 5)]
+    systems = [pressure_velocity(*sh, seed=30 + k) for k, sh in enumerate(shapes)]
+    cat = concat_systems(systems)
+    with P.System.from_dict(cat) as bs:
+        bs.setup(precond=P.PREC_AMG, precision=P.PRECISION_MIXED, smoother=smoother, tol=1e-9)
+        x, stats = bs.solve(cat["b"])
+        lam, statt = bs.solve_transpose(cat["b"])
+    xn, ln = _np(x), _np(lam)
+    co = cat["cell_off"]
+    for k, sk in enumerate(systems):
+        assert stats[k]["status"] == P.OK and statt[k]["status"] == P.OK, (k, stats[k], statt[k])
+        assert stats[k]["precision_fallback"] == 0
+        Ak = O.from_system(sk)
+        assert O.relres(Ak, sk["b"], xn[co[k]:co[k + 1]]) <= 1e-9 * 1.0001
+        assert O.relres(O.transpose(Ak), sk["b"], ln[co[k]:co[k + 1]]) <= 1e-9 * 1.0001
 
 
 # ------------------------------------------------------------------ DILU
