@@ -26,6 +26,11 @@ namespace {
 
 constexpr int kRapWaves = 4;
 constexpr int kRapCap = 4096;     // largest candidate list a coarse row may gather
+// Coarse rows with at most kRapSmall candidates (pairwise aggregates of short
+// rows) take a thread each instead of a wavefront: kRapSmallTpb threads per
+// workgroup, each with a sorted list of kRapSmall slots in LDS.
+constexpr int kRapSmall = 48;
+constexpr int kRapSmallTpb = 64;
 constexpr int kMatchRounds = 4;
 
 // ------------------------------------------------------------------ block inverse
@@ -316,6 +321,55 @@ __global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, int32_t cap,
         for (int32_t q = 0; q < cc; ++q)
             if (sDw[q] == d) acc += val[(int64_t)(sKw[q] & ~kFirst) * nn + e];
         valc[(int64_t)(base + d) * nn + e] = acc;
+    }
+}
+
+// Thread-per-coarse-row Galerkin product for short candidate lists.  The
+// distinct coarse columns are kept sorted (slot layout [slot][thread] in
+// LDS); PASS 0 counts them, PASS 1 (scalar values only, n = 1) writes the
+// columns and the sums, added in candidate order like k_rap.
+template <int PASS>
+__global__ __launch_bounds__(kRapSmallTpb) void k_rap_small(int32_t nc, const int32_t *__restrict__ aptr,
+                                                            const int32_t *__restrict__ amem,
+                                                            const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ col,
+                                                            const double *__restrict__ w,
+                                                            const int32_t *__restrict__ agg, int32_t *cnt,
+                                                            const int32_t *__restrict__ rpc, int32_t *colc,
+                                                            double *wc) {
+    __shared__ int32_t sJ[kRapSmall * kRapSmallTpb];
+    __shared__ double sS[PASS ? kRapSmall * kRapSmallTpb : 1];
+    const int t = threadIdx.x;
+    const int32_t I = blockIdx.x * kRapSmallTpb + t;
+    if (I >= nc) return;
+    int nd = 0;
+    for (int32_t m = aptr[I]; m < aptr[I + 1]; ++m) {
+        const int32_t i = amem[m];
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t J = agg[col[k]];
+            int p = 0;
+            while (p < nd && sJ[p * kRapSmallTpb + t] < J) ++p;
+            if (p < nd && sJ[p * kRapSmallTpb + t] == J) {
+                if (PASS) sS[p * kRapSmallTpb + t] += w[k];
+                continue;
+            }
+            for (int q = nd; q > p; --q) {
+                sJ[q * kRapSmallTpb + t] = sJ[(q - 1) * kRapSmallTpb + t];
+                if (PASS) sS[q * kRapSmallTpb + t] = sS[(q - 1) * kRapSmallTpb + t];
+            }
+            sJ[p * kRapSmallTpb + t] = J;
+            if (PASS) sS[p * kRapSmallTpb + t] = w[k];
+            ++nd;
+        }
+    }
+    if (PASS == 0) {
+        cnt[I] = nd;
+        return;
+    }
+    const int32_t base = rpc[I];
+    for (int d = 0; d < nd; ++d) {
+        colc[base + d] = sJ[d * kRapSmallTpb + t];
+        wc[base + d] = sS[d * kRapSmallTpb + t];
     }
 }
 
@@ -763,11 +817,18 @@ int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, con
                                    std::to_string(kRapCap) + "); lower match_passes");
     int32_t cap = 64;
     while (cap < maxc) cap *= 2;
+    // maxc bounds the distinct columns too, so short lists fit kRapSmall slots
+    const bool small = maxc <= kRapSmall;
+    const dim3 gs(cdiv(nc, kRapSmallTpb)), bs(kRapSmallTpb);
     int32_t nz = -1;
     if (pattern) {
         rpc.alloc(nc + 1);
-        NSWITCH(n_blk, rap_n, 0, nc, cap, aptr, amem, rp, col, val, agg, rpc.get(), nullptr, nullptr, nullptr,
-                h->dflag.get(), st);
+        if (small && nc > 0)
+            hipLaunchKernelGGL(k_rap_small<0>, gs, bs, 0, st, nc, aptr, amem, rp, col, nullptr, agg, rpc.get(),
+                               nullptr, nullptr, nullptr);
+        else
+            NSWITCH(n_blk, rap_n, 0, nc, cap, aptr, amem, rp, col, val, agg, rpc.get(), nullptr, nullptr, nullptr,
+                    h->dflag.get(), st);
         LAUNCHCHK();
         scan_exclusive(rpc.get(), rpc.get(), nc, st);
         int32_t v[2];
@@ -779,8 +840,12 @@ int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, con
     }
     // the fill pass visits the candidates the counting pass (or the first
     // build of this pattern) already fitted into cap, so it cannot overflow
-    NSWITCH(n_blk, rap_n, 1, nc, cap, aptr, amem, rp, col, val, agg, nullptr, rpc.get(), colc.get(), valc.get(),
-            h->dflag.get(), st);
+    if (small && n_blk == 1 && nc > 0)
+        hipLaunchKernelGGL(k_rap_small<1>, gs, bs, 0, st, nc, aptr, amem, rp, col, val, agg, nullptr, rpc.get(),
+                           colc.get(), valc.get());
+    else
+        NSWITCH(n_blk, rap_n, 1, nc, cap, aptr, amem, rp, col, val, agg, nullptr, rpc.get(), colc.get(), valc.get(),
+                h->dflag.get(), st);
     LAUNCHCHK();
     return nz;
 }
