@@ -193,7 +193,7 @@ template <int n, typename TV, typename TX, int MODE, int SP, bool PRO>
 __global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__restrict__ val,
                                                        const TX *__restrict__ x, const TX *__restrict__ b,
                                                        TX *__restrict__ y, const double *__restrict__ Dinv,
-                                                       double omega, TX *__restrict__ aux,
+                                                       double omega, [[maybe_unused]] TX *__restrict__ aux,
                                                        const int32_t *__restrict__ pagg,
                                                        const TX *__restrict__ pe, double *__restrict__ y64) {
     using A = typename Acc<TX>::type;
