@@ -1079,7 +1079,7 @@ void amg_setup(cbs_system *h) {
         sell_build(L0.N, L0.rp, L0.col, L0.sell, st);
         level_sell(h, L0, false, nullptr);
         L0.sell.sched64 = autotune_rows(n, L0.sell, false, L0.sell.v64.get(), st);
-        L0.sell.sched64.split = row_split_for(L0.sell, o.row_split);
+        L0.sell.sched64.split = row_split_for(L0.sell, L0.nnzb, o.row_split);
         h->op_complexity = 1.0;
         return;
     }
@@ -1165,7 +1165,8 @@ void amg_setup(cbs_system *h) {
             if ((q == 0 || q + 1 < nlev) && !keep_sell) todo.push_back({&L, &L.sell, false});
             if (mixed && q + 1 < nlev && !level_uses_dilu(q) && !keep_sod) todo.push_back({&L, &L.sod, true});
         }
-        for (auto &t : todo) sell_pattern_begin(t.L->N, t.L->rp, t.L->col, *t.S, st, t.od);
+        for (auto &t : todo)
+            sell_pattern_begin(t.L->N, t.L->rp, t.L->col, *t.S, st, t.od, t.L == &h->lev[0] ? kSlice : kCoarseSlice);
         for (size_t k0 = 0; k0 < todo.size(); k0 += kPinnedWords) {
             const size_t k1 = std::min(todo.size(), k0 + kPinnedWords);
             int32_t cnt[kPinnedWords];
@@ -1218,8 +1219,8 @@ void amg_setup(cbs_system *h) {
         for (auto &L : h->lev) {
             L.sell.sched64 = L.sod.sched64 = s64;
             L.sell.sched32 = L.sod.sched32 = s32;
-            L.sell.sched64.split = L.sell.sched32.split = row_split_for(L.sell, o.row_split);
-            L.sod.sched32.split = row_split_for(L.sod, o.row_split);
+            L.sell.sched64.split = L.sell.sched32.split = row_split_for(L.sell, L.nnzb, o.row_split);
+            L.sod.sched32.split = row_split_for(L.sod, L.nnzb - L.N, o.row_split);
         }
         pt.mark("autotune");
     }
@@ -1408,7 +1409,7 @@ void spmv_user(cbs_system *h, const double *x, double *y, bool transposed) {
         }
         if (tune) {
             U.sched64 = autotune_rows(n, U, false, U.v64.get(), h->stream);
-            U.sched64.split = row_split_for(U, h->opt.row_split);
+            U.sched64.split = row_split_for(U, h->nnzb, h->opt.row_split);
         }
         launch_rows<double, double>(0, n, U.view(), U.v64.get(), x, nullptr, y, nullptr, 0.0, h->stream);
         return;

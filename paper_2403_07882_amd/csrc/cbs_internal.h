@@ -86,12 +86,15 @@ enum {
 };
 
 // ---------------------------------------------------------------- sliced ELL
-// Solve-phase storage of a level matrix: slices of kSlice block rows; in
-// slice s, entry k of row 16s+ii sits at soff[s] + k*kSlice + ii (rows keep
+// Solve-phase storage of a level matrix: slices of C = 2^lc block rows (C =
+// kSlice on level 0, kCoarseSlice on coarser levels, where row lengths vary
+// more and a shorter slice pads less); in slice s, entry k of row C s + ii
+// sits at soff[s] + k C + ii (rows keep
 // their column order; short rows are padded with col = -1 up to the slice
 // width sw[s]).  One wavefront of a block-row kernel then reads kSlice
 // consecutive blocks per step.  BCSR stays the setup-time format.
 constexpr int kSlice = 16;
+constexpr int kCoarseSlice = 8;
 
 // Levels with fewer block rows than this are launch- and latency-bound: their
 // block-row kernels split rows over several threads, and their first
@@ -110,17 +113,18 @@ struct SellView {
     int32_t N;
     const int32_t *soff, *sw, *scol;
     Sched sched;
+    int32_t lc;             // log2 of the slice height
 };
 
 struct Sell {
-    int32_t N = 0, nslices = 0;
+    int32_t N = 0, nslices = 0, lc = 4;
     int64_t nent = 0;
     DArr<int32_t> soff, sw, scol, ssrc;   // ssrc: BCSR slot of each entry, -1 = padding
     DArr<double> v64, v64T;
     DArr<float> v32, v32T;
     Sched sched64{4, 0}, sched32{4, 1};
     SellView view(bool fp32 = false) const {
-        return SellView{N, soff.get(), sw.get(), scol.get(), fp32 ? sched32 : sched64};
+        return SellView{N, soff.get(), sw.get(), scol.get(), fp32 ? sched32 : sched64, lc};
     }
 };
 
@@ -283,13 +287,16 @@ void launch_restrict_sweep0(int n, int32_t nc, const int32_t *agg_ptr, const int
 // time the schedules of the residual kernel on S (cached per shape)
 Sched autotune_rows(int n, const Sell &S, bool fp32, const void *val, hipStream_t st);
 // threads per scalar row of the block-row kernels on a level (row_split option)
-int8_t row_split_for(const Sell &S, int32_t opt_split);
+int8_t row_split_for(const Sell &S, int64_t nblocks, int32_t opt_split);
 // sliced-ELL pattern from BCSR (offdiag: without the diagonal blocks), and
 // values gathered from BCSR values
-void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag = false);
+void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag = false,
+                int slice = kSlice);
 // the same in two halves, so that several patterns share one read-back of
 // their entry counts (S.soff[S.nslices] after begin)
-void sell_pattern_begin(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag);
+// slice: slice height, a power of two up to 64
+void sell_pattern_begin(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag,
+                        int slice = kSlice);
 void sell_pattern_finish(const int32_t *rp, const int32_t *col, Sell &S, int64_t nent, hipStream_t st,
                          bool offdiag);
 void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st);

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
     const int32_t N = S.N;
     A acc = 0;
     if (MODE != 3 && i < N) {
-        const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+        const int32_t sl = i >> S.lc, ii = i - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
         int32_t k = 0;
         for (; k + U <= w; k += U) {
@@ -121,10 +121,10 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
             TV bv[U][n];
             TX xv[U][n];
 #pragma unroll
-            for (int u = 0; u < U; ++u) j[u] = S.scol[base + (k + u) * kSlice];
+            for (int u = 0; u < U; ++u) j[u] = S.scol[base + ((k + u) << S.lc)];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t e = base + (int64_t)(k + u) * kSlice;
+                const int64_t e = base + ((int64_t)(k + u) << S.lc);
                 load_row_nt<n, TV, NT>(val + e * nn + r * n, bv[u]);
                 load_xc<n, TX, PRO>(x, j[u] < 0 ? i : j[u], pagg, pe, xv[u]);
             }
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
                 }
         }
         for (; k < w; ++k) {
-            const int64_t e = base + (int64_t)k * kSlice;
+            const int64_t e = base + ((int64_t)k << S.lc);
             const int32_t j = S.scol[e];
             if (j < 0) continue;
             TV bv[n];
@@ -209,10 +209,10 @@ __global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__r
     const int32_t N = S.N;
     A acc = 0;
     if (i < N) {
-        const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+        const int32_t sl = i >> S.lc, ii = i - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
         for (int32_t k = kk; k < w; k += SP) {
-            const int64_t e = base + (int64_t)k * kSlice;
+            const int64_t e = base + ((int64_t)k << S.lc);
             const int32_t j = S.scol[e];
             if (j < 0) continue;
             TV bv[n];
@@ -339,10 +339,10 @@ __global__ __launch_bounds__(64 * n) void k_dilu_fwd(SellView S, const T *__rest
     const int32_t i = act ? rows[q] : 0;
     A ax = 0, ay = 0;
     if (act) {
-        const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+        const int32_t sl = i >> S.lc, ii = i - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
         for (int32_t k = 0; k < w; ++k) {
-            const int64_t e = base + (int64_t)k * kSlice;
+            const int64_t e = base + ((int64_t)k << S.lc);
             const int32_t j = S.scol[e];
             if (j < 0) break;                      // padding sits at the end of a row
             T bv[n];
@@ -388,10 +388,10 @@ __global__ __launch_bounds__(64 * n) void k_dilu_bwd(SellView S, const T *__rest
     const int32_t i = act ? rows[q] : 0;
     A au = 0;
     if (act) {
-        const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+        const int32_t sl = i >> S.lc, ii = i - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
         for (int32_t k = 0; k < w; ++k) {
-            const int64_t e = base + (int64_t)k * kSlice;
+            const int64_t e = base + ((int64_t)k << S.lc);
             const int32_t j = S.scol[e];
             if (j < 0) break;
             if (colour[j] <= c) continue;
@@ -419,30 +419,30 @@ __global__ __launch_bounds__(64 * n) void k_dilu_bwd(SellView S, const T *__rest
 
 // ------------------------------------------------------------------ sliced ELL build
 // offdiag: leave out the diagonal block of each row (counted, not assumed)
-__global__ void k_sell_width(int32_t N, int32_t ns, const int32_t *rp, const int32_t *col, int32_t *sw, int32_t *cnt,
-                             int offdiag) {
+__global__ void k_sell_width(int32_t N, int32_t ns, int32_t C, const int32_t *rp, const int32_t *col, int32_t *sw,
+                             int32_t *cnt, int offdiag) {
     const int32_t sl = blockIdx.x * blockDim.x + threadIdx.x;
     if (sl >= ns) return;
     int32_t w = 0;
-    for (int32_t i = sl * kSlice; i < min(N, (sl + 1) * kSlice); ++i) {
+    for (int32_t i = sl * C; i < min(N, (sl + 1) * C); ++i) {
         int32_t len = rp[i + 1] - rp[i];
         if (offdiag)
             for (int32_t k = rp[i]; k < rp[i + 1]; ++k) len -= col[k] == i ? 1 : 0;
         w = max(w, len);
     }
     sw[sl] = w;
-    cnt[sl] = w * kSlice;
+    cnt[sl] = w * C;
 }
 
-__global__ void k_sell_fill_idx(int32_t N, const int32_t *rp, const int32_t *col, const int32_t *soff, int32_t *scol,
-                                int32_t *ssrc, int offdiag) {
+__global__ void k_sell_fill_idx(int32_t N, int32_t C, const int32_t *rp, const int32_t *col, const int32_t *soff,
+                                int32_t *scol, int32_t *ssrc, int offdiag) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+    const int32_t sl = i / C, ii = i - sl * C;
     int32_t q = 0;
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
         if (offdiag && col[k] == i) continue;
-        const int64_t e = soff[sl] + (int64_t)q * kSlice + ii;
+        const int64_t e = soff[sl] + (int64_t)q * C + ii;
         scol[e] = col[k];
         ssrc[e] = k;
         ++q;
@@ -471,23 +471,23 @@ __global__ void k_sell_vals(int64_t nent, const int32_t *__restrict__ ssrc, cons
 // row, r); padding entries, including the rows that pad the last slice past
 // N, get zeros.
 template <int n>
-__global__ void k_sell_scaled(int32_t N, int32_t nslices, const int32_t *__restrict__ soff,
+__global__ void k_sell_scaled(int32_t N, int32_t nslices, int32_t C, const int32_t *__restrict__ soff,
                               const int32_t *__restrict__ sw, const int32_t *__restrict__ ssrc,
                               const double *__restrict__ bvals, const double *__restrict__ Dinv,
                               float *__restrict__ out, int32_t *flag) {
     constexpr int nn = n * n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (int64_t)nslices * kSlice * n) return;
+    if (g >= (int64_t)nslices * C * n) return;
     const int32_t i = (int32_t)(g / n);
     const int r = (int)(g - (int64_t)i * n);
-    const int32_t sl = i / kSlice, ii = i - sl * kSlice;
+    const int32_t sl = i / C, ii = i - sl * C;
     const int64_t base = (int64_t)soff[sl] + ii;
     const int32_t w = sw[sl];
     double d[n];
 #pragma unroll
     for (int q = 0; q < n; ++q) d[q] = i < N ? Dinv[(int64_t)i * nn + r * n + q] : 0.0;
     for (int32_t k = 0; k < w; ++k) {
-        const int64_t e = base + (int64_t)k * kSlice;
+        const int64_t e = base + (int64_t)k * C;
         const int32_t src = i < N ? ssrc[e] : -1;
         const double *a = bvals + (int64_t)(src < 0 ? 0 : src) * nn;
 #pragma unroll
@@ -587,14 +587,20 @@ template void launch_rows<float, float>(int, int, const SellView &, const float 
                                         float *, const double *, double, hipStream_t, float *, const int32_t *,
                                         const float *, double *);
 
-void sell_pattern_begin(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag) {
+void sell_pattern_begin(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag,
+                        int slice) {
+    int lc = 0;
+    while ((1 << lc) < slice) ++lc;
+    if ((1 << lc) != slice || lc > 6) cbs_throw(CBS_ERR_ARG, "slice height must be a power of two up to 64");
+    const int32_t C = 1 << lc;
     S.N = N;
-    S.nslices = (N + kSlice - 1) / kSlice;
+    S.lc = lc;
+    S.nslices = (N + C - 1) / C;
     const int32_t ns = S.nslices;
     S.sw.alloc(ns > 0 ? ns : 1);
     S.soff.alloc(ns + 1);
     if (ns > 0)
-        hipLaunchKernelGGL(k_sell_width, dim3(cdiv(ns, 256)), dim3(256), 0, st, N, ns, rp, col, S.sw.get(),
+        hipLaunchKernelGGL(k_sell_width, dim3(cdiv(ns, 256)), dim3(256), 0, st, N, ns, C, rp, col, S.sw.get(),
                            S.soff.get(), offdiag ? 1 : 0);
     LAUNCHCHK();
     scan_exclusive(S.soff.get(), S.soff.get(), ns, st);
@@ -611,13 +617,13 @@ void sell_pattern_finish(const int32_t *rp, const int32_t *col, Sell &S, int64_t
         hipLaunchKernelGGL(k_fill_i32, dim3(cdiv(S.nent, 256)), dim3(256), 0, st, S.nent, S.ssrc.get(), -1);
     }
     if (N > 0)
-        hipLaunchKernelGGL(k_sell_fill_idx, dim3(cdiv(N, 256)), dim3(256), 0, st, N, rp, col, S.soff.get(),
-                           S.scol.get(), S.ssrc.get(), offdiag ? 1 : 0);
+        hipLaunchKernelGGL(k_sell_fill_idx, dim3(cdiv(N, 256)), dim3(256), 0, st, N, 1 << S.lc, rp, col,
+                           S.soff.get(), S.scol.get(), S.ssrc.get(), offdiag ? 1 : 0);
     LAUNCHCHK();
 }
 
-void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag) {
-    sell_pattern_begin(N, rp, col, S, st, offdiag);
+void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag, int slice) {
+    sell_pattern_begin(N, rp, col, S, st, offdiag, slice);
     sell_pattern_finish(rp, col, S, read_int(S.soff.get() + S.nslices, st), st, offdiag);
 }
 
@@ -637,11 +643,11 @@ void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipSt
 
 void sell_scale(int n, const Sell &S, const double *bcsr_vals, const double *Dinv, float *out, int32_t *flag,
                 hipStream_t st) {
-    const int64_t m = (int64_t)S.nslices * kSlice * n;
+    const int64_t m = (int64_t)S.nslices * (1 << S.lc) * n;
     if (S.N <= 0) return;
     const dim3 g(cdiv(m, 256)), b(256);
 #define SCALE_N(NN)                                                                                           \
-    hipLaunchKernelGGL(k_sell_scaled<NN>, g, b, 0, st, S.N, S.nslices, S.soff.get(), S.sw.get(), S.ssrc.get(), \
+    hipLaunchKernelGGL(k_sell_scaled<NN>, g, b, 0, st, S.N, S.nslices, 1 << S.lc, S.soff.get(), S.sw.get(), S.ssrc.get(), \
                        bcsr_vals, Dinv, out, flag)
     switch (n) {
         case 1: SCALE_N(1); break;
@@ -886,14 +892,15 @@ std::map<std::tuple<int32_t, int64_t, int, bool>, Sched> g_tune_cache;
 }  // namespace
 
 // Levels of fewer than kSmallLevelRows block rows split each row over several
-// threads; automatic choice: the largest power of two (at most 16) that still
-// leaves every thread about four blocks of a mean-length row.
-int8_t row_split_for(const Sell &S, int32_t opt_split) {
+// threads; automatic choice from the mean row length (nblocks / N, stored
+// blocks only): the largest power of two (at most 16) that still leaves every
+// thread about three blocks.
+int8_t row_split_for(const Sell &S, int64_t nblocks, int32_t opt_split) {
     if (S.N <= 0 || S.N >= kSmallLevelRows) return 1;
     if (opt_split > 0) return (int8_t)opt_split;
-    const double w = (double)S.nent / S.N;
+    const double w = (double)nblocks / S.N;
     int s = 1;
-    while (s < 16 && 4.0 * (2 * s) <= w) s *= 2;
+    while (s < 16 && 3.0 * (2 * s) <= w) s *= 2;
     return (int8_t)s;
 }
 
