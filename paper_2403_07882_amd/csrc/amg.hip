@@ -30,6 +30,8 @@ constexpr int kRapCap = 4096;     // largest candidate list a coarse row may gat
 // rows) take a thread each instead of a wavefront: kRapSmallTpb threads per
 // workgroup, each with a sorted list of kRapSmall slots in LDS.
 constexpr int kRapSmall = 48;
+constexpr int kRapSmallCount = 64;   // the counting pass keeps no values: longer lists fit
+constexpr int32_t kRapSmallRows = 16384;
 constexpr int kRapSmallTpb = 64;
 constexpr int kMatchRounds = 4;
 
@@ -313,22 +315,43 @@ __global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, int32_t cap,
         if (sKw[q] & kFirst) colc[base + d] = J;
     }
     __syncthreads();
+    // Candidates regrouped by output block, candidate order kept within a
+    // group: slot of q = (candidates of lower blocks) + (earlier candidates
+    // of its own block).  sJw (columns, no longer needed) takes the list.
+    for (int32_t q = lane; q < cc; q += 64) {
+        const int32_t d = sDw[q];
+        int32_t pos = 0;
+        for (int32_t p = 0; p < cc; ++p) {
+            const int32_t dp = sDw[p];
+            pos += (dp < d || (dp == d && p < q)) ? 1 : 0;
+        }
+        sJw[pos] = q;
+    }
+    __syncthreads();
     if (!active) return;
     const int32_t nd = rpc[I + 1] - base;
     for (int32_t t = lane; t < nd * nn; t += 64) {
         const int32_t d = t / nn, e = t - d * nn;
+        // the group of block d starts where the candidates of blocks < d end
+        // (the list is ordered by block: binary search)
+        int32_t lo = 0, hi = cc;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (sDw[sJw[mid]] < d) lo = mid + 1;
+            else hi = mid;
+        }
         double acc = 0.0;
-        for (int32_t q = 0; q < cc; ++q)
-            if (sDw[q] == d) acc += val[(int64_t)(sKw[q] & ~kFirst) * nn + e];
+        for (int32_t g = lo; g < cc && sDw[sJw[g]] == d; ++g)
+            acc += val[(int64_t)(sKw[sJw[g]] & ~kFirst) * nn + e];
         valc[(int64_t)(base + d) * nn + e] = acc;
     }
 }
 
-// Thread-per-coarse-row Galerkin product for short candidate lists.  The
-// distinct coarse columns are kept sorted (slot layout [slot][thread] in
-// LDS); PASS 0 counts them, PASS 1 (scalar values only, n = 1) writes the
-// columns and the sums, added in candidate order like k_rap.
-template <int PASS>
+// Thread-per-coarse-row Galerkin product for short candidate lists (at most
+// CAP).  The distinct coarse columns are kept sorted (slot layout
+// [slot][thread] in LDS); PASS 0 counts them, PASS 1 (scalar values only,
+// n = 1) writes the columns and the sums, added in candidate order like k_rap.
+template <int PASS, int CAP>
 __global__ __launch_bounds__(kRapSmallTpb) void k_rap_small(int32_t nc, const int32_t *__restrict__ aptr,
                                                             const int32_t *__restrict__ amem,
                                                             const int32_t *__restrict__ rp,
@@ -337,8 +360,8 @@ __global__ __launch_bounds__(kRapSmallTpb) void k_rap_small(int32_t nc, const in
                                                             const int32_t *__restrict__ agg, int32_t *cnt,
                                                             const int32_t *__restrict__ rpc, int32_t *colc,
                                                             double *wc) {
-    __shared__ int32_t sJ[kRapSmall * kRapSmallTpb];
-    __shared__ double sS[PASS ? kRapSmall * kRapSmallTpb : 1];
+    __shared__ int32_t sJ[CAP * kRapSmallTpb];
+    __shared__ double sS[PASS ? CAP * kRapSmallTpb : 1];
     const int t = threadIdx.x;
     const int32_t I = blockIdx.x * kRapSmallTpb + t;
     if (I >= nc) return;
@@ -817,15 +840,18 @@ int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, con
                                    std::to_string(kRapCap) + "); lower match_passes");
     int32_t cap = 64;
     while (cap < maxc) cap *= 2;
-    // maxc bounds the distinct columns too, so short lists fit kRapSmall slots
-    const bool small = maxc <= kRapSmall;
+    // maxc bounds the distinct columns too, so short lists fit the slots; a
+    // thread per row only pays when there are many rows (few rows with long
+    // lists are faster a wavefront each)
+    const bool many = nc >= kRapSmallRows;
+    const bool small = many && maxc <= kRapSmall, small_count = many && maxc <= kRapSmallCount;
     const dim3 gs(cdiv(nc, kRapSmallTpb)), bs(kRapSmallTpb);
     int32_t nz = -1;
     if (pattern) {
         rpc.alloc(nc + 1);
-        if (small && nc > 0)
-            hipLaunchKernelGGL(k_rap_small<0>, gs, bs, 0, st, nc, aptr, amem, rp, col, nullptr, agg, rpc.get(),
-                               nullptr, nullptr, nullptr);
+        if (small_count && nc > 0)
+            hipLaunchKernelGGL((k_rap_small<0, kRapSmallCount>), gs, bs, 0, st, nc, aptr, amem, rp, col, nullptr, agg,
+                               rpc.get(), nullptr, nullptr, nullptr);
         else
             NSWITCH(n_blk, rap_n, 0, nc, cap, aptr, amem, rp, col, val, agg, rpc.get(), nullptr, nullptr, nullptr,
                     h->dflag.get(), st);
@@ -841,8 +867,8 @@ int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, con
     // the fill pass visits the candidates the counting pass (or the first
     // build of this pattern) already fitted into cap, so it cannot overflow
     if (small && n_blk == 1 && nc > 0)
-        hipLaunchKernelGGL(k_rap_small<1>, gs, bs, 0, st, nc, aptr, amem, rp, col, val, agg, nullptr, rpc.get(),
-                           colc.get(), valc.get());
+        hipLaunchKernelGGL((k_rap_small<1, kRapSmall>), gs, bs, 0, st, nc, aptr, amem, rp, col, val, agg, nullptr,
+                           rpc.get(), colc.get(), valc.get());
     else
         NSWITCH(n_blk, rap_n, 1, nc, cap, aptr, amem, rp, col, val, agg, nullptr, rpc.get(), colc.get(), valc.get(),
                 h->dflag.get(), st);
