@@ -82,6 +82,7 @@ constexpr int kVecThreads = 256;      // threads per element-wise workgroup
 // per-system scalar slots of the Krylov loops: scal[slot * n_sys + s]
 enum {
     S_RHO = 0, S_RHO0, S_ALPHA, S_OMEGA, S_RV, S_TS, S_TT, S_RR, S_BB, S_RES0, S_SS,
+    S_RRPREV,               // ||r||^2 one iteration earlier (convergence forecast)
     S_NSCAL
 };
 
@@ -209,7 +210,8 @@ struct cbs_system {
     int32_t *h_done = nullptr;
     // captured iteration graphs (index: transposed solve), replayed on `stream`
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t g_iter[2] = {nullptr, nullptr};
+    // captured BiCGStab iteration: [whole, first half, second half][forward, transposed]
+    hipGraphExec_t g_iter[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
     DArr<double> xw, bw;                         // solution / rhs work copies the graphs point at
     // internal renumbering of level 0 (AMG setup)
     bool renumbered = false;

@@ -19,7 +19,15 @@
 
 namespace {
 
-enum { PH_INIT = 0, PH_ALPHA, PH_OMEGA, PH_END, PH_RESTART, PH_TRUE };
+enum { PH_INIT = 0, PH_ALPHA, PH_OMEGA, PH_END, PH_RESTART, PH_TRUE, PH_SNORM };
+
+// flags bits: 1 breakdown; 2 converged at the half step (||s|| met the
+// tolerance: the iteration ends with x += alpha ph, r = s); 4 the residual,
+// shrinking as in the last iteration, would be within 4x of the tolerance
+// after the next one
+constexpr int32_t kFlagBreak = 1, kFlagHalf = 2, kFlagNear = 4;
+// partial sums of (s, s), written with s, read at the half-step test
+constexpr int kSlotSS = 2;
 
 __device__ inline double block_sum(double v, double *sh) {
 #pragma unroll
@@ -84,7 +92,7 @@ __device__ inline double sum_items(const double *partial, int32_t n_items, int q
 
 #define SC(slot) scal[(slot) * nsys + s]
 
-// Per-system scalar updates after a reduction.  flags: bit0 breakdown.
+// Per-system scalar updates after a reduction.
 __global__ __launch_bounds__(kFinThreads) void k_fin(int phase, int32_t nsys, const int32_t *__restrict__ item_off,
                                                       int32_t n_items, const double *__restrict__ partial, double *scal,
                                                       int32_t *done, int32_t *flags, int32_t *iters, double tol2,
@@ -93,16 +101,18 @@ __global__ __launch_bounds__(kFinThreads) void k_fin(int phase, int32_t nsys, co
     const int32_t i0 = item_off[s], i1 = item_off[s + 1];
     // every phase needs at most two sums; compute them with the whole group
     const bool skip = (phase == PH_RESTART && !restart_mask[s]) ||
-                      ((phase == PH_ALPHA || phase == PH_OMEGA || phase == PH_END) && (done[s] || (flags[s] & 1)));
+                      ((phase == PH_ALPHA || phase == PH_OMEGA || phase == PH_END || phase == PH_SNORM) &&
+                       (done[s] || (flags[s] & kFlagBreak)));
     if (skip) return;
-    const double q0 = sum_items(partial, n_items, 0, i0, i1);
+    const double q0 = phase == PH_SNORM ? 0.0 : sum_items(partial, n_items, 0, i0, i1);
     const double q1 = (phase == PH_INIT || phase == PH_OMEGA || phase == PH_END) ? sum_items(partial, n_items, 1, i0, i1)
                                                                                  : 0.0;
+    const double qss = (phase == PH_SNORM || phase == PH_OMEGA) ? sum_items(partial, n_items, kSlotSS, i0, i1) : 0.0;
     if (threadIdx.x != 0) return;
     if (phase == PH_INIT) {
         const double rr = q0, bb = q1;
         SC(S_RR) = rr; SC(S_BB) = bb; SC(S_RES0) = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-        SC(S_RHO) = rr; SC(S_RHO0) = 1.0; SC(S_ALPHA) = 1.0; SC(S_OMEGA) = 1.0;
+        SC(S_RHO) = rr; SC(S_RHO0) = 1.0; SC(S_ALPHA) = 1.0; SC(S_OMEGA) = 1.0; SC(S_RRPREV) = 0.0;
         done[s] = (bb == 0.0 || rr <= tol2 * bb) ? 1 : 0;
         flags[s] = 0;
         iters[s] = 0;
@@ -115,6 +125,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fin(int phase, int32_t nsys, co
     if (phase == PH_RESTART) {                       // rhat = r; p = v = 0 done by the caller
         const double rr = q0;
         SC(S_RR) = rr; SC(S_RHO) = rr; SC(S_RHO0) = 1.0; SC(S_ALPHA) = 1.0; SC(S_OMEGA) = 1.0;
+        SC(S_RRPREV) = 0.0;
         done[s] = (SC(S_BB) == 0.0 || rr <= tol2 * SC(S_BB)) ? 1 : 0;
         flags[s] = 0;
         return;
@@ -130,17 +141,24 @@ __global__ __launch_bounds__(kFinThreads) void k_fin(int phase, int32_t nsys, co
             SC(S_ALPHA) = rho / rv;
         }
         iters[s] += 1;
+    } else if (phase == PH_SNORM) {                  // ||s||^2: converged at the half step?
+        if (qss <= tol2 * SC(S_BB)) flags[s] |= kFlagHalf;
     } else if (phase == PH_OMEGA) {
+        if (qss <= tol2 * SC(S_BB)) flags[s] |= kFlagHalf;
         const double ts = q0, tt = q1;
         SC(S_TS) = ts; SC(S_TT) = tt;
-        SC(S_OMEGA) = tt > 0.0 ? ts / tt : 0.0;
+        SC(S_OMEGA) = (flags[s] & kFlagHalf) ? 0.0 : (tt > 0.0 ? ts / tt : 0.0);
     } else if (phase == PH_END) {
         const double rr = q0, rhn = q1;
         SC(S_RR) = rr;
         SC(S_RHO0) = SC(S_RHO);
         SC(S_RHO) = rhn;
         if (rr <= tol2 * SC(S_BB)) done[s] = 1;
-        else if (SC(S_OMEGA) == 0.0 || rhn == 0.0 || !isfinite(rhn) || (flags[s] & 1)) flags[s] |= 1;
+        else if (SC(S_OMEGA) == 0.0 || rhn == 0.0 || !isfinite(rhn) || (flags[s] & kFlagBreak)) flags[s] |= kFlagBreak;
+        flags[s] &= ~(kFlagHalf | kFlagNear);
+        const double rrp = SC(S_RRPREV);
+        if (rrp > 0.0 && rr * (rr / rrp) <= 16.0 * tol2 * SC(S_BB)) flags[s] |= kFlagNear;
+        SC(S_RRPREV) = rr;
     }
 }
 
@@ -152,26 +170,36 @@ __global__ __launch_bounds__(kVecThreads) void k_p_update(const Item *__restrict
                                                           double *p, const double *v) {
     const Item it = items[blockIdx.x];
     const int s = it.sys;
-    if (done[s] || flags[s]) return;
+    if (done[s] || (flags[s] & kFlagBreak)) return;
     const double omega = SC(S_OMEGA);
     const double beta = (SC(S_RHO) / SC(S_RHO0)) * (SC(S_ALPHA) / omega);
     for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) p[e] = r[e] + beta * (p[e] - omega * v[e]);
 }
 
-// s = r - alpha v
-__global__ __launch_bounds__(kVecThreads) void k_s_update(const Item *__restrict__ items, int32_t nsys,
-                                                          const int32_t *__restrict__ done,
+// s = r - alpha v, and partials of (s, s) for the half-step test
+__global__ __launch_bounds__(kVecThreads) void k_s_update(const Item *__restrict__ items, int32_t n_items,
+                                                          int32_t nsys, const int32_t *__restrict__ done,
                                                           const double *__restrict__ scal,
                                                           const int32_t *__restrict__ flags, const double *r,
-                                                          const double *v, double *sv) {
+                                                          const double *v, double *sv, double *partial) {
+    __shared__ double red[kVecThreads / 64];
     const Item it = items[blockIdx.x];
     const int s = it.sys;
-    if (done[s] || flags[s]) return;
-    const double alpha = SC(S_ALPHA);
-    for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) sv[e] = r[e] - alpha * v[e];
+    double s0 = 0.0;
+    if (!done[s] && !(flags[s] & kFlagBreak)) {
+        const double alpha = SC(S_ALPHA);
+        for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) {
+            const double se = r[e] - alpha * v[e];
+            sv[e] = se;
+            s0 += se * se;
+        }
+    }
+    s0 = block_sum(s0, red);
+    if (threadIdx.x == 0) partial[(int64_t)kSlotSS * n_items + blockIdx.x] = s0;
 }
 
-// x += alpha ph + omega sh;  r = s - omega t;  partials (r,r), (rhat,r)
+// x += alpha ph + omega sh;  r = s - omega t;  partials (r,r), (rhat,r).
+// A system converged at the half step takes x += alpha ph, r = s.
 __global__ __launch_bounds__(kVecThreads) void k_xr_update(const Item *__restrict__ items, int32_t n_items,
                                                            int32_t nsys, const int32_t *__restrict__ done,
                                                            const double *__restrict__ scal,
@@ -183,14 +211,24 @@ __global__ __launch_bounds__(kVecThreads) void k_xr_update(const Item *__restric
     const Item it = items[blockIdx.x];
     const int s = it.sys;
     double s0 = 0.0, s1 = 0.0;
-    if (!done[s] && !flags[s]) {
+    if (!done[s] && !(flags[s] & kFlagBreak)) {
         const double alpha = SC(S_ALPHA), omega = SC(S_OMEGA);
-        for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) {
-            x[e] += alpha * ph[e] + omega * sh[e];
-            const double re = sv[e] - omega * t[e];
-            r[e] = re;
-            s0 += re * re;
-            s1 += rh[e] * re;
+        if (flags[s] & kFlagHalf) {
+            for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) {
+                x[e] += alpha * ph[e];
+                const double re = sv[e];
+                r[e] = re;
+                s0 += re * re;
+                s1 += rh[e] * re;
+            }
+        } else {
+            for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) {
+                x[e] += alpha * ph[e] + omega * sh[e];
+                const double re = sv[e] - omega * t[e];
+                r[e] = re;
+                s0 += re * re;
+                s1 += rh[e] * re;
+            }
         }
     }
     s0 = block_sum(s0, red);
@@ -581,15 +619,17 @@ void true_residual(cbs_system *h, const double *b, const double *x, bool tr) {
     fin(h, PH_TRUE, 0.0);
 }
 
-// One right-preconditioned BiCGStab iteration for every unfinished system.
-// Only kernel launches on h->stream (no memset/memcpy, no host sync), so it
-// can be captured once and replayed as a graph.
-void bicg_iteration(cbs_system *h, double *x, bool tr) {
+// One right-preconditioned BiCGStab iteration for every unfinished system,
+// in two halves: the first ends with s = r - alpha v and the half-step test
+// on ||s||, the second applies the preconditioner to s and finishes.  Only
+// kernel launches on h->stream (no memset/memcpy, no host sync), so each
+// part can be captured once and replayed as a graph.
+void bicg_half1(cbs_system *h, bool tr) {
     hipStream_t st = h->stream;
     const double tol2 = h->opt.tol * h->opt.tol;
     const int nsys = h->n_sys;
     double *r = h->r.get(), *rh = h->rh.get(), *p = h->p.get(), *v = h->v.get();
-    double *ph = h->ph.get(), *sv = h->s.get(), *sh = h->sh.get(), *t = h->t.get();
+    double *ph = h->ph.get(), *sv = h->s.get();
     const Item *items = h->items.get();
     const dim3 G(h->n_items), B(kVecThreads);
     hipLaunchKernelGGL(k_p_update, G, B, 0, st, items, nsys, h->done.get(), h->scal.get(), h->flags.get(), r, p, v);
@@ -597,20 +637,47 @@ void bicg_iteration(cbs_system *h, double *x, bool tr) {
     spmv64(h, ph, v, tr);
     dots(h, 1, rh, v);
     fin(h, PH_ALPHA, tol2);
-    hipLaunchKernelGGL(k_s_update, G, B, 0, st, items, nsys, h->done.get(), h->scal.get(), h->flags.get(), r, v, sv);
-    precond_apply(h, sv, sh, tr);
-    spmv64(h, sh, t, tr);
-    dots(h, 2, t, sv, t, t);
-    fin(h, PH_OMEGA, tol2);
-    hipLaunchKernelGGL(k_xr_update, G, B, 0, st, items, h->n_items, nsys, h->done.get(), h->scal.get(),
-                       h->flags.get(), x, ph, sh, r, sv, t, rh, h->partial.get());
+    hipLaunchKernelGGL(k_s_update, G, B, 0, st, items, h->n_items, nsys, h->done.get(), h->scal.get(), h->flags.get(),
+                       r, v, sv, h->partial.get());
+    LAUNCHCHK();
+}
+
+// x and r updates and the end-of-iteration scalars
+void bicg_finish(cbs_system *h, double *x) {
+    hipStream_t st = h->stream;
+    const double tol2 = h->opt.tol * h->opt.tol;
+    const dim3 G(h->n_items), B(kVecThreads);
+    hipLaunchKernelGGL(k_xr_update, G, B, 0, st, h->items.get(), h->n_items, h->n_sys, h->done.get(), h->scal.get(),
+                       h->flags.get(), x, h->ph.get(), h->sh.get(), h->r.get(), h->s.get(), h->t.get(), h->rh.get(),
+                       h->partial.get());
     fin(h, PH_END, tol2);
     LAUNCHCHK();
 }
 
-// Replay the captured iteration (capture on first use).
-void bicg_iteration_graph(cbs_system *h, double *xw, bool tr) {
-    hipGraphExec_t &ex = h->g_iter[tr ? 1 : 0];
+void bicg_half2(cbs_system *h, double *x, bool tr) {
+    const double tol2 = h->opt.tol * h->opt.tol;
+    double *sv = h->s.get(), *sh = h->sh.get(), *t = h->t.get();
+    precond_apply(h, sv, sh, tr);
+    spmv64(h, sh, t, tr);
+    dots(h, 2, t, sv, t, t);
+    fin(h, PH_OMEGA, tol2);
+    bicg_finish(h, x);
+}
+
+enum { PART_FULL = 0, PART_HALF1, PART_HALF2 };
+
+// The whole iteration tests ||s|| with omega (the result of a half-step
+// convergence is then exact, only nothing is skipped); the first half alone
+// ends with the test so that the host can skip the second.
+void bicg_part(cbs_system *h, double *x, bool tr, int part) {
+    if (part != PART_HALF2) bicg_half1(h, tr);
+    if (part == PART_HALF1) fin(h, PH_SNORM, h->opt.tol * h->opt.tol);
+    if (part != PART_HALF1) bicg_half2(h, x, tr);
+}
+
+// Replay a captured part of the iteration (captured on first use).
+void bicg_part_graph(cbs_system *h, double *xw, bool tr, int part) {
+    hipGraphExec_t &ex = h->g_iter[part][tr ? 1 : 0];
     if (!ex) {
         if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         hipStream_t saved = h->stream;
@@ -618,7 +685,7 @@ void bicg_iteration_graph(cbs_system *h, double *xw, bool tr) {
         hipGraph_t g = nullptr;
         try {
             HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
-            bicg_iteration(h, xw, tr);
+            bicg_part(h, xw, tr, part);
             HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
         } catch (...) {
             hipGraph_t junk = nullptr;
@@ -660,6 +727,8 @@ int bicgstab(cbs_system *h, const double *b, double *x, bool tr, std::vector<int
     HostView hv;
     int it = 0;
     const int every = std::max(1, o.check_every);
+    const bool graphs = x == h->xw.get();
+    bool split = false;          // next iteration in two halves with a check between
     for (;;) {
         bool check = (it % every == 0) || it >= o.max_iter;
         if (check) {
@@ -719,8 +788,31 @@ int bicgstab(cbs_system *h, const double *b, double *x, bool tr, std::vector<int
             }
         }
         if (it >= o.max_iter) break;
-        if (x == h->xw.get()) bicg_iteration_graph(h, x, tr);
-        else bicg_iteration(h, x, tr);
+        if (check) {
+            // Near convergence (every unfinished system flagged by the end of
+            // the last iteration) run the iteration in halves: if every
+            // unfinished system already meets the tolerance with s, the second
+            // preconditioner application and product are skipped.
+            const int32_t *dn = hv.state.data(), *fl = dn + nsys;
+            split = true;
+            for (int s = 0; s < nsys && split; ++s)
+                if (!dn[s] && !(fl[s] & kFlagBreak) && !(fl[s] & kFlagNear)) split = false;
+        }
+        if (!split) {
+            if (graphs) bicg_part_graph(h, x, tr, PART_FULL);
+            else bicg_part(h, x, tr, PART_FULL);
+        } else {
+            if (graphs) bicg_part_graph(h, x, tr, PART_HALF1);
+            else bicg_part(h, x, tr, PART_HALF1);
+            read_state(h, hv, false);
+            const int32_t *dn = hv.state.data(), *fl = dn + nsys;
+            bool all_half = true;
+            for (int s = 0; s < nsys && all_half; ++s)
+                if (!dn[s] && !(fl[s] & kFlagBreak) && !(fl[s] & kFlagHalf)) all_half = false;
+            if (all_half) bicg_finish(h, x);
+            else if (graphs) bicg_part_graph(h, x, tr, PART_HALF2);
+            else bicg_part(h, x, tr, PART_HALF2);
+        }
         ++it;
     }
     return it;
@@ -801,8 +893,9 @@ int fgmres(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> 
 }  // namespace
 
 void invalidate_graphs(cbs_system *h) {
-    for (auto &g : h->g_iter)
-        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    for (auto &part : h->g_iter)
+        for (auto &g : part)
+            if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
 void alloc_krylov(cbs_system *h) {
