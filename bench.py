@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--solver", choices=["bicgstab", "fgmres"], default="bicgstab")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--tail-rows", type=int, default=0,
+                    help="V-cycle tail in one workgroup from levels of at most this many block rows "
+                         "(0 = library default, -1 = off)")
     ap.add_argument("--row-split", type=int, default=0,
                     help="threads per scalar row on levels under 65,536 block rows (0 = automatic)")
     ap.add_argument("--kernel-reps", type=int, default=50)
@@ -229,7 +232,7 @@ def main():
                   smoother=P.SMOOTH_DILU if args.smoother == "dilu" else P.SMOOTH_BJACOBI,
                   dilu_levels=args.dilu_levels, pre_sweeps=args.sweeps, post_sweeps=args.sweeps,
                   omega=args.omega, coarse_max=args.coarse_max, match_passes=args.passes,
-                  row_split=args.row_split)
+                  row_split=args.row_split, tail_rows=args.tail_rows)
     opt_mixed = P.default_options(precision=P.PRECISION_MIXED, **common)
     opt_reuse = P.default_options(precision=P.PRECISION_MIXED, reuse_aggregates=1, **common)
     opt_fp64 = P.default_options(precision=P.PRECISION_FP64, **common)
@@ -379,7 +382,8 @@ def main():
                    "step": "pack fields + update_values + setup + solve + unpack fields",
                    "solver": args.solver, "smoother": args.smoother, "dilu_levels": args.dilu_levels,
                    "sweeps": args.sweeps, "omega": args.omega, "coarse_max": args.coarse_max,
-                   "match_passes": args.passes, "row_split": args.row_split},
+                   "match_passes": args.passes, "row_split": args.row_split,
+                   "tail_rows": args.tail_rows},
         "step_ms_median": round(float(np.median(per_step)), 3),
         "step_ms_all": [round(t, 3) for t in per_step],
         "iterations": st["iterations"],

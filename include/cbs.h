@@ -96,6 +96,12 @@ typedef struct cbs_options {
                                 scalar row (1, 2, 4, 8 or 16); 0 = chosen from
                                 the level's mean row length. Changes only the
                                 order of the row sums                [0] */
+    int32_t tail_rows;       /* AMG V-cycle: from the first level of at most
+                                this many block rows (all systems together)
+                                down to the coarsest and back, the cycle runs
+                                in one workgroup (one kernel instead of about
+                                five per level); 0 = 256, < 0 = never. Changes
+                                only the order of the row sums       [0] */
 } cbs_options;
 
 /* Per-solve statistics (Algorithm amgxFoam: iterations and residuals). */

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcbs.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["convert.hip", "spmv.hip", "amg.hip", "krylov.hip", "capi.hip"]
+SOURCES = ["convert.hip", "spmv.hip", "tail.hip", "amg.hip", "krylov.hip", "capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -236,6 +236,7 @@ void cbs_default_options(cbs_options *o) {
     o->renumber = 1;
     o->dilu_levels = 2;
     o->row_split = 0;
+    o->tail_rows = 0;
 }
 
 int cbs_create_from_ldu(cbs_handle *out, int32_t n_cells, int32_t n_faces, int32_t bdim, const int32_t *lower_addr,

@@ -102,6 +102,11 @@ constexpr int kCoarseSlice = 8;
 // post-smoothing sweep absorbs the prolongation.
 constexpr int32_t kSmallLevelRows = 65536;
 
+// V-cycle tail (tail.hip): default block-row limit of its first level, and the
+// most levels (coarsest included) it takes
+constexpr int32_t kTailRowsDefault = 256;
+constexpr int kTailMax = 8;
+
 // Schedule of the block-row kernels: blocks loaded per step (1, 2, 4) and
 // whether matrix values are loaded non-temporally; picked by autotuning.
 struct Sched {
@@ -315,6 +320,13 @@ template <typename TA, typename TB>
 void launch_cast(int64_t m, const TA *a, TB *b, hipStream_t st);
 void launch_coarse_solve(cbs_system *h, bool transposed, const void *b, void *x, bool fp32);
 void launch_block_apply(int n, int32_t N, const double *Dinv, const double *r, double *z, hipStream_t st);
+// V-cycle tail (tail.hip): the first level (>= 1) from which the rest of the
+// cycle runs in one workgroup for level vectors of tsize bytes per value, or
+// -1; and that launch, given the residual of the level above (the result
+// lands in the first tail level's x)
+int tail_level_for(const cbs_system *h, size_t tsize);
+template <typename T>
+void launch_tail(cbs_system *h, bool tr, int l0, const T *rfine);
 // DILU colour sweeps on the rows rows[0..cnt): forward y = E^{-1}(b - A x - L y)
 // (zero_guess: A x omitted), backward z = y - E^{-1} U z, x = x + z
 template <typename T>

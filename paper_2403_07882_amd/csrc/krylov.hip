@@ -480,6 +480,10 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
         const Level &F = h->lev[l - 1];
         launch_restrict<T>(n, L.N, F.agg_ptr.get(), F.agg_mem.get(), rfine, b, st);
     };
+    if (rfine && l == tail_level_for(h, sizeof(T))) {        // the rest of the cycle in one workgroup
+        launch_tail<T>(h, tr, l, rfine);
+        return;
+    }
     if (l == nlev - 1) {
         if (rfine) restrict_into_b();
         launch_coarse_solve(h, tr, b, x, fp32);
