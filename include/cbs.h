@@ -185,6 +185,13 @@ int cbs_spmv(cbs_handle h, const double *x, double *y, int32_t transpose);
  * (zero initial guess), in the configured precision. */
 int cbs_apply_precond(cbs_handle h, const double *r, double *z);
 
+/* The preconditioner of the transposed solve (reading of Sec. 2.3 for the
+ * adjoint: the same aggregates, Galerkin operators of A^T, block-Jacobi or
+ * DILU factors of A^T): one application z = M_T^{-1} r, zero initial guess,
+ * in the configured precision.  Builds the transposed hierarchy on first use
+ * after cbs_setup, as cbs_solve_transpose does. */
+int cbs_apply_precond_transpose(cbs_handle h, const double *r, double *z);
+
 /* Kernel-level access to the smoother of one AMG level, for verification and
  * for timing the kernels the V-cycle runs (Sec. 2.3, smoothers).  Works on
  * level `level` (0 .. levels-2; the coarsest level has no smoother) of the

@@ -67,6 +67,7 @@ SIGNATURES = [
     ("cbs_spmv", C.c_int, [_VP, _VP, _VP, _I32]),
     ("cbs_level_apply", C.c_int, [_VP, _I32, _I32, _VP, _VP, _VP, C.POINTER(_I32)]),
     ("cbs_apply_precond", C.c_int, [_VP, _VP, _VP]),
+    ("cbs_apply_precond_transpose", C.c_int, [_VP, _VP, _VP]),
     ("cbs_pack_fields", C.c_int, [_I32, _I32, _VP, _VP, _VP]),
     ("cbs_unpack_fields", C.c_int, [_I32, _I32, _VP, _VP, _VP]),
     ("cbs_get_info", C.c_int, [_VP, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I64),
@@ -261,11 +262,13 @@ class System:
         _check(lib().cbs_spmv(self.h, _ptr(xx), _ptr(y), 1 if transpose else 0), "cbs_spmv")
         return y.reshape(-1, self.n)
 
-    def apply_precond(self, r):
+    def apply_precond(self, r, transpose=False):
+        """z = M^{-1} r (transpose: the preconditioner of the transposed solve)."""
         torch = _torch()
         rr = _dev(r, torch.float64).reshape(-1)
         z = torch.empty_like(rr)
-        _check(lib().cbs_apply_precond(self.h, _ptr(rr), _ptr(z)), "cbs_apply_precond")
+        fn = lib().cbs_apply_precond_transpose if transpose else lib().cbs_apply_precond
+        _check(fn(self.h, _ptr(rr), _ptr(z)), "cbs_apply_precond")
         return z.reshape(-1, self.n)
 
     def level_apply(self, level, op, b, x):

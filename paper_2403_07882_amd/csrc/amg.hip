@@ -1228,6 +1228,7 @@ void amg_setup(cbs_system *h) {
         pt.mark("smoother" + std::to_string(q));
         if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, deferred);
         L.scaled = mixed && q + 1 < nlev && !L.dilu;
+        L.scaledT = false;
         if (L.scaled) {
             L.sod.v32.ensure(L.sod.nent > 0 ? (size_t)L.sod.nent * n * n : 1);
             sell_scale(n, L.sod, L.v64, L.Dinv.get(), L.sod.v32.get(), deferred, st);
@@ -1313,6 +1314,7 @@ void amg_build_transposed(cbs_system *h) {
     const int n = h->n;
     const bool mixed = h->opt.precision == CBS_PRECISION_MIXED;
     const int nlev = (int)h->lev.size();
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
     for (int q = 0; q < nlev; ++q) {
         Level &L = h->lev[q];
         L.o_v64T.ensure((size_t)L.nnzb * n * n);
@@ -1336,9 +1338,16 @@ void amg_build_transposed(cbs_system *h) {
             L.EinvT.ensure((size_t)L.N * n * n);
             NSWITCH(n, transpose_n, (int64_t)L.N, nullptr, L.Einv.get(), L.EinvT.get(), st);
         }
+        if (mixed && L.scaled) {
+            // row-scaled off-diagonal values of A^T: D_i^{-T} (A^T)_ij, j != i
+            L.sod.v32T.ensure(L.sod.nent > 0 ? (size_t)L.sod.nent * n * n : 1);
+            sell_scale(n, L.sod, L.v64T, L.DinvT.get(), L.sod.v32T.get(), h->dflag.get(), st);
+        }
         LAUNCHCHK();
     }
-    HIPCHK(hipStreamSynchronize(st));
+    // FP32 cannot hold some scaled value: the transposed sweeps keep D^{-T}
+    const bool overflow = read_int(h->dflag.get(), st) & 64;
+    for (auto &L : h->lev) L.scaledT = mixed && L.scaled && !overflow;
     h->transposed_ready = true;
 }
 

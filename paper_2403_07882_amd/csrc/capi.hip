@@ -401,6 +401,26 @@ int cbs_apply_precond(cbs_handle h, const double *r, double *z) {
     });
 }
 
+int cbs_apply_precond_transpose(cbs_handle h, const double *r, double *z) {
+    return guarded([&] {
+        require(h != nullptr && r && z, CBS_ERR_ARG, "NULL argument");
+        set_alloc_stream(h->stream);
+        require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
+        amg_build_transposed(h);
+        if (h->renumbered) {
+            const int64_t m = (int64_t)h->N * h->n;
+            h->bw.ensure(m);
+            h->xw.ensure(m);
+            permute_vec(h, r, h->bw.get(), true);
+            precond_apply(h, h->bw.get(), h->xw.get(), true);
+            permute_vec(h, h->xw.get(), z, false);
+        } else {
+            precond_apply(h, r, z, true);
+        }
+        return CBS_OK;
+    });
+}
+
 int cbs_level_apply(cbs_handle h, int32_t level, int32_t op, const void *b, const void *x, void *y, int32_t *fp32) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");

@@ -158,6 +158,9 @@ struct Level {
     // values in sod.v32), with the level's Dinv b kept in vc
     bool scaled = false;
     Sell sod;
+    // the same for the transposed solve: D_i^{-T} (A^T)_ij in sod.v32T, set
+    // when the transposed values are built and FP32 holds them all
+    bool scaledT = false;
     // DILU: colour classes (rows of colour c: rows_by_colour[colour_off[c] ..
     // colour_off[c+1])) and the FP64 inverses of the DILU diagonal E
     bool dilu = false;

@@ -510,10 +510,11 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
     const int switches = (nu1 >= 1 ? nu1 - 1 : 0) + nu2;
     T *cur = (switches % 2 == 0) ? x : tmp;
     T *oth = (cur == x) ? tmp : x;
-    // FP32 forward sweeps run on the row-scaled values Dinv A against
-    // c = Dinv b, which the zero-guess sweep leaves behind
-    const bool scaled = fp32 && !tr && L.scaled;
-    const T *sval = scaled ? reinterpret_cast<const T *>(L.sod.v32.get()) : nullptr;
+    // FP32 sweeps run on the row-scaled values Dinv A (D^{-T} A^T in the
+    // transposed solve) against c = Dinv b, which the zero-guess sweep leaves
+    // behind
+    const bool scaled = fp32 && (tr ? L.scaledT : L.scaled);
+    const T *sval = scaled ? reinterpret_cast<const T *>(tr ? L.sod.v32T.get() : L.sod.v32.get()) : nullptr;
     T *c = scaled ? vptr<T>(L.vc) : nullptr;
     // pagg/pe: sweep from x + P e (the prolongation fused into the sweep);
     // y64: write the result widened to FP64 there instead of into `to`

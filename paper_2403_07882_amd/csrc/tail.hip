@@ -355,7 +355,7 @@ int64_t tail_plan(const cbs_system *h, int l0, bool tr, TailArgs<T> *a) {
     const int n = h->n;
     const int nlev = (int)h->lev.size();
     const int nl = nlev - 1 - l0;
-    auto scaled = [&](const Level &L) { return fp32 && !tr && L.scaled; };
+    auto scaled = [&](const Level &L) { return fp32 && (tr ? L.scaledT : L.scaled); };
     int64_t nvec = 0;                                  // elements of T
     for (int k = 0; k <= nl; ++k) {
         const Level &L = h->lev[l0 + k];
@@ -453,9 +453,9 @@ void launch_tail(cbs_system *h, bool tr, int l0, const T *rfine) {
         d.Dinv = tr ? L.DinvT.get() : L.Dinv.get();
         d.lc = L.sell.lc;
         d.sp = tail_split(L.N, n);
-        d.scaled = fp32 && !tr && L.scaled;
+        d.scaled = fp32 && (tr ? L.scaledT : L.scaled);
         if (d.scaled) {
-            d.sval = reinterpret_cast<const T *>(L.sod.v32.get());
+            d.sval = reinterpret_cast<const T *>(tr ? L.sod.v32T.get() : L.sod.v32.get());
             d.lco = L.sod.lc;
             d.spo = d.sp;
         }

@@ -106,3 +106,35 @@ def test_solves_with_and_without_tail(precision):
         assert O.relres(At, s["b"], ls[tail]) <= 1e-10 * 1.0001
     for d in (xs, ls):
         assert np.linalg.norm(d[-1] - d[ALL]) <= 1e-7 * np.linalg.norm(d[-1])
+
+
+@pytest.mark.parametrize("tail", [-1, ALL])
+@pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
+@pytest.mark.parametrize("n", [4, 5])
+def test_transposed_vcycle_matches_oracle_on_transposed_matrix(n, precision, tail):
+    """The preconditioner of the transposed solve is the oracle's V-cycle built
+    on A^T with the same aggregates (Galerkin operators of A^T, block inverses
+    of A^T's diagonal); in mixed precision its sweeps run on the row-scaled
+    values D^{-T} A^T."""
+    _say("transposed vcycle n", n, "precision", precision, "tail", tail)
+    s = pressure_velocity(11, 9, 8, seed=44) if n == 4 else jacobian_box(11, 9, 8, n=5, seed=45)
+    N = int(s["N"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, precision=precision, coarse_max=8, pre_sweeps=2, post_sweeps=2,
+                   omega=0.9, tail_rows=tail)
+        nlev = sysm.info()["levels"]
+        assert nlev >= 3
+        lv0 = sysm.get_level(0)
+        order = _np(lv0["order"])
+        A0 = O.BCSR(N, n, _np(lv0["row_ptr"]), _np(lv0["col"]), _np(lv0["vals"]))
+        aggs = [_np(sysm.get_level(l)["agg"]) for l in range(nlev - 1)]
+        r = np.random.default_rng(3).standard_normal((N, n))
+        z = _np(sysm.apply_precond(r, transpose=True))
+        zf = _np(sysm.apply_precond(r))
+    amg = O.AMG(O.transpose(A0), nu1=2, nu2=2, omega=0.9, aggs=aggs)
+    zr_int = amg.apply(r[order])
+    zr = np.empty_like(zr_int)
+    zr[order] = zr_int
+    tol = 1e-11 if precision == P.PRECISION_FP64 else 1e-5
+    assert np.linalg.norm(z - zr) <= tol * np.linalg.norm(zr)
+    assert np.linalg.norm(zf - zr) > 1e3 * tol * np.linalg.norm(zr)     # not the forward cycle
