@@ -98,32 +98,65 @@ __global__ void k_block_transpose(int64_t nb, const int32_t *__restrict__ mirror
 }
 
 // ------------------------------------------------------------------ strength
+// Frobenius norm of every block, read once (one thread per block; the
+// squares are summed in element order)
 template <int n>
-__global__ void k_diag_frob(int32_t N, const int32_t *dslot, const double *val, double *df) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const double *D = val + (int64_t)dslot[i] * (n * n);
+__global__ void k_block_frob(int64_t nb, const double *__restrict__ val, double *__restrict__ nrm) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nb) return;
+    const double *A = val + k * (n * n);
     double s = 0.0;
 #pragma unroll
-    for (int e = 0; e < n * n; ++e) s += D[e] * D[e];
-    df[i] = sqrt(s);
+    for (int e = 0; e < n * n; ++e) s += A[e] * A[e];
+    nrm[k] = sqrt(s);
 }
 
-template <int n>
+// w_ij = (||A_ij||_F + ||A_ji||_F) / 2 / max(||A_ii||_F, ||A_jj||_F), from
+// the block norms (0 on the diagonal).  Rows of up to 8 blocks (face
+// neighbours of a hexahedral cell and itself) issue all their gathers before
+// using any (a few dependent loads per row instead of a chain per block);
+// longer rows take one block at a time.
 __global__ void k_strength(int32_t N, const int32_t *rp, const int32_t *col, const int32_t *mirror,
-                           const double *val, const double *df, double *w) {
+                           const double *nrm, const double *df, double *w) {
+    constexpr int MAXL = 8;
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    const int32_t r0 = rp[i], len = rp[i + 1] - r0;
+    if (len <= MAXL) {
+        int32_t j[MAXL], m[MAXL];
+#pragma unroll
+        for (int e = 0; e < MAXL; ++e) {
+            j[e] = e < len ? col[r0 + e] : i;
+            m[e] = e < len ? mirror[r0 + e] : r0;
+        }
+        const double di = df[i];
+        double dj[MAXL], a[MAXL], b[MAXL];
+#pragma unroll
+        for (int e = 0; e < MAXL; ++e) {
+            dj[e] = e < len ? df[j[e]] : 0.0;
+            a[e] = e < len ? nrm[r0 + e] : 0.0;
+            b[e] = e < len ? nrm[m[e]] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < MAXL; ++e) {
+            if (e < len) {
+                const double den = fmax(di, dj[e]);
+                w[r0 + e] = j[e] == i ? 0.0 : (den > 0.0 ? 0.5 * (a[e] + b[e]) / den : 0.0);
+            }
+        }
+        return;
+    }
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
         const int32_t j = col[k];
         if (j == i) { w[k] = 0.0; continue; }
-        const double *A = val + (int64_t)k * (n * n), *B = val + (int64_t)mirror[k] * (n * n);
-        double sa = 0.0, sb = 0.0;
-#pragma unroll
-        for (int e = 0; e < n * n; ++e) { sa += A[e] * A[e]; sb += B[e] * B[e]; }
         const double den = fmax(df[i], df[j]);
-        w[k] = den > 0.0 ? 0.5 * (sqrt(sa) + sqrt(sb)) / den : 0.0;
+        w[k] = den > 0.0 ? 0.5 * (nrm[k] + nrm[mirror[k]]) / den : 0.0;
     }
+}
+
+__global__ void k_diag_norm(int32_t N, const int32_t *dslot, const double *nrm, double *df) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) df[i] = nrm[dslot[i]];
 }
 
 __global__ void k_zero_diag_w(int32_t N, const int32_t *rp, const int32_t *col, double *w) {
@@ -332,17 +365,30 @@ __global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, int32_t cap,
     const int32_t nd = rpc[I + 1] - base;
     for (int32_t t = lane; t < nd * nn; t += 64) {
         const int32_t d = t / nn, e = t - d * nn;
-        // the group of block d starts where the candidates of blocks < d end
-        // (the list is ordered by block: binary search)
+        // the group of block d is [lo, hi) of the list (ordered by block:
+        // two binary searches); its values are loaded four at a time and
+        // added in candidate order
         int32_t lo = 0, hi = cc;
         while (lo < hi) {
             const int32_t mid = (lo + hi) >> 1;
             if (sDw[sJw[mid]] < d) lo = mid + 1;
             else hi = mid;
         }
+        int32_t end = lo;
+        hi = cc;
+        while (end < hi) {
+            const int32_t mid = (end + hi) >> 1;
+            if (sDw[sJw[mid]] <= d) end = mid + 1;
+            else hi = mid;
+        }
+        auto src = [&](int32_t g) { return val[(int64_t)(sKw[sJw[g]] & ~kFirst) * nn + e]; };
         double acc = 0.0;
-        for (int32_t g = lo; g < cc && sDw[sJw[g]] == d; ++g)
-            acc += val[(int64_t)(sKw[sJw[g]] & ~kFirst) * nn + e];
+        int32_t g = lo;
+        for (; g + 4 <= end; g += 4) {
+            const double v0 = src(g), v1 = src(g + 1), v2 = src(g + 2), v3 = src(g + 3);
+            acc += v0; acc += v1; acc += v2; acc += v3;
+        }
+        for (; g < end; ++g) acc += src(g);
         valc[(int64_t)(base + d) * nn + e] = acc;
     }
 }
@@ -536,11 +582,34 @@ __global__ void k_perm_len(int32_t N, const int32_t *ip, const int32_t *rp, int3
 }
 
 // new row i' = old row ip[i'], columns renamed by pos and sorted; sk = old slot
+// Row i' of the renumbered pattern is row ip[i'] of the old one with its
+// columns renamed through pos and sorted; sk gives each new slot's old slot.
+// Rows of up to MAXL blocks are ranked in registers (the columns of a row are
+// distinct, so each entry's rank is the number of smaller columns); longer
+// rows fall back to an insertion sort in place.
+template <int MAXL>
 __global__ void k_perm_rows(int32_t N, const int32_t *ip, const int32_t *pos, const int32_t *rp, const int32_t *col,
                             const int32_t *rpn, int32_t *coln, int32_t *sk) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int32_t o = ip[i], b = rpn[i], len = rp[o + 1] - rp[o];
+    if (len <= MAXL) {
+        const int32_t r0 = rp[o];
+        int32_t c[MAXL];
+#pragma unroll
+        for (int e = 0; e < MAXL; ++e) c[e] = e < len ? pos[col[r0 + e]] : INT32_MAX;
+#pragma unroll
+        for (int e = 0; e < MAXL; ++e) {
+            if (e < len) {
+                int32_t q = 0;
+#pragma unroll
+                for (int f = 0; f < MAXL; ++f) q += c[f] < c[e] ? 1 : 0;
+                coln[b + q] = c[e];
+                sk[b + q] = r0 + e;
+            }
+        }
+        return;
+    }
     for (int32_t e = 0; e < len; ++e) {
         const int32_t c = pos[col[rp[o] + e]], k = rp[o] + e;
         int32_t q = b + e - 1;
@@ -742,9 +811,11 @@ void transpose_n(int64_t nb, const int32_t *mirror, const double *in, double *ou
 }
 template <int n>
 void strength_n(int32_t N, const int32_t *rp, const int32_t *col, const int32_t *mirror, const int32_t *dslot,
-                const double *val, double *df, double *w, hipStream_t st) {
-    hipLaunchKernelGGL(k_diag_frob<n>, dim3(cdiv(N, 256)), dim3(256), 0, st, N, dslot, val, df);
-    hipLaunchKernelGGL(k_strength<n>, dim3(cdiv(N, 256)), dim3(256), 0, st, N, rp, col, mirror, val, df, w);
+                const double *val, int64_t nnzb, double *df, double *w, hipStream_t st) {
+    DArr<double> nrm(nnzb > 0 ? nnzb : 1);
+    if (nnzb > 0) hipLaunchKernelGGL(k_block_frob<n>, dim3(cdiv(nnzb, 256)), dim3(256), 0, st, nnzb, val, nrm.get());
+    hipLaunchKernelGGL(k_diag_norm, dim3(cdiv(N, 256)), dim3(256), 0, st, N, dslot, nrm.get(), df);
+    hipLaunchKernelGGL(k_strength, dim3(cdiv(N, 256)), dim3(256), 0, st, N, rp, col, mirror, nrm.get(), df, w);
 }
 template <int n>
 void rap_n(int pass, int32_t nc, int32_t cap, const int32_t *aptr, const int32_t *amem, const int32_t *rp,
@@ -885,7 +956,7 @@ void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen) {
     const int32_t N = L.N;
     const int n = h->n;
     DArr<double> df(N), w(L.nnzb > 0 ? L.nnzb : 1);
-    NSWITCH(n, strength_n, N, L.rp, L.col, L.mirror, L.dslot, L.v64, df.get(), w.get(), st);
+    NSWITCH(n, strength_n, N, L.rp, L.col, L.mirror, L.dslot, L.v64, L.nnzb, df.get(), w.get(), st);
     LAUNCHCHK();
     gmark("strength");
     L.agg.alloc(N);
@@ -990,17 +1061,6 @@ void dilu_factor_level(cbs_system *h, int l) {
                                         std::to_string(bad));
 }
 
-// Sliced-ELL copy of a level for the solve phase (pattern kept on reuse).
-// FP32 copy of FP64 level values; an entry that does not fit FP32 sets bit
-// 64 of *flag (the hierarchy then escalates to FP64).
-__global__ void k_cast_f32_flag(int64_t m, const double *__restrict__ in, float *__restrict__ out, int32_t *flag) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= m) return;
-    const float v = (float)in[g];
-    out[g] = v;
-    if (!isfinite(v)) atomicOr(flag, 64);
-}
-
 // Values of the level's sliced copy (its pattern is built beforehand).
 // f32flag: where the FP32 copy reports values it cannot hold (mixed only)
 void level_sell(cbs_system *h, Level &L, bool mixed, int32_t *f32flag) {
@@ -1008,14 +1068,8 @@ void level_sell(cbs_system *h, Level &L, bool mixed, int32_t *f32flag) {
     const int n = h->n;
     const size_t tot = (size_t)L.sell.nent * n * n;
     L.sell.v64.ensure(tot > 0 ? tot : 1);
-    sell_fill(n, L.sell, L.v64, L.sell.v64.get(), st);
-    if (mixed) {
-        L.sell.v32.ensure(tot > 0 ? tot : 1);
-        if (tot > 0)
-            hipLaunchKernelGGL(k_cast_f32_flag, dim3(cdiv((int64_t)tot, 256)), dim3(256), 0, st, (int64_t)tot,
-                               L.sell.v64.get(), L.sell.v32.get(), f32flag);
-        LAUNCHCHK();
-    }
+    if (mixed) L.sell.v32.ensure(tot > 0 ? tot : 1);
+    sell_fill(n, L.sell, L.v64, L.sell.v64.get(), st, mixed ? L.sell.v32.get() : nullptr, f32flag);
 }
 
 std::vector<int64_t> level_sys_off(cbs_system *h, Level &L) {
@@ -1323,11 +1377,8 @@ void amg_build_transposed(cbs_system *h) {
         if (L.sell.soff.get()) {
             const size_t tot = (size_t)L.sell.nent * n * n;
             L.sell.v64T.ensure(tot > 0 ? tot : 1);
-            sell_fill(n, L.sell, L.v64T, L.sell.v64T.get(), st);
-            if (mixed) {
-                L.sell.v32T.ensure(tot > 0 ? tot : 1);
-                launch_cast<double, float>((int64_t)tot, L.sell.v64T.get(), L.sell.v32T.get(), st);
-            }
+            if (mixed) L.sell.v32T.ensure(tot > 0 ? tot : 1);
+            sell_fill(n, L.sell, L.v64T, L.sell.v64T.get(), st, mixed ? L.sell.v32T.get() : nullptr, h->dflag.get());
         }
         if (L.Dinv.get()) {
             L.DinvT.ensure((size_t)L.N * n * n);
@@ -1391,8 +1442,12 @@ void renumber_hierarchy(cbs_system *h, int32_t *deferred) {
         hipLaunchKernelGGL(k_perm_len, G, B, 0, st, N, ip.get(), L.rp, rpn.get());
         LAUNCHCHK();
         scan_exclusive(rpn.get(), rpn.get(), N, st);
-        hipLaunchKernelGGL(k_perm_rows, G, B, 0, st, N, ip.get(), pos[l].get(), L.rp, L.col, rpn.get(), coln.get(),
-                           sk.get());
+        if (l == 0)        // level 0: short rows (face neighbours)
+            hipLaunchKernelGGL(k_perm_rows<16>, G, B, 0, st, N, ip.get(), pos[l].get(), L.rp, L.col, rpn.get(),
+                               coln.get(), sk.get());
+        else
+            hipLaunchKernelGGL(k_perm_rows<32>, G, B, 0, st, N, ip.get(), pos[l].get(), L.rp, L.col, rpn.get(),
+                               coln.get(), sk.get());
         NSWITCH(n, gather_blocks_n, nnz, sk.get(), L.v64, vn.get(), st);
         hipLaunchKernelGGL(k_perm_map, G, B, 0, st, N, ip.get(), L.agg.get(), pos[l + 1].get(), aggn.get());
         hipLaunchKernelGGL(k_iota, G, B, 0, st, N, memn.get());

@@ -309,7 +309,10 @@ void sell_pattern_begin(int32_t N, const int32_t *rp, const int32_t *col, Sell &
                         int slice = kSlice);
 void sell_pattern_finish(const int32_t *rp, const int32_t *col, Sell &S, int64_t nent, hipStream_t st,
                          bool offdiag);
-void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st);
+// (with out32: also the FP32 rounding of every value, bit 64 of *flag set for
+// values FP32 cannot hold)
+void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st, float *out32 = nullptr,
+               int32_t *flag = nullptr);
 // out = FP32(Dinv_i A_ij) for every entry of the sliced pattern S, A_ij read
 // from the block-CSR values; an entry FP32 cannot hold sets bit 64 of *flag
 void sell_scale(int n, const Sell &S, const double *bcsr_vals, const double *Dinv, float *out, int32_t *flag,

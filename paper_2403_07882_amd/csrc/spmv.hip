@@ -419,19 +419,23 @@ __global__ __launch_bounds__(64 * n) void k_dilu_bwd(SellView S, const T *__rest
 
 // ------------------------------------------------------------------ sliced ELL build
 // offdiag: leave out the diagonal block of each row (counted, not assumed)
+// Slice widths: one thread per (padded) row computes its stored length, the
+// C consecutive lanes of a slice (C divides the wavefront) take the maximum.
 __global__ void k_sell_width(int32_t N, int32_t ns, int32_t C, const int32_t *rp, const int32_t *col, int32_t *sw,
                              int32_t *cnt, int offdiag) {
-    const int32_t sl = blockIdx.x * blockDim.x + threadIdx.x;
-    if (sl >= ns) return;
-    int32_t w = 0;
-    for (int32_t i = sl * C; i < min(N, (sl + 1) * C); ++i) {
-        int32_t len = rp[i + 1] - rp[i];
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t len = 0;
+    if (i < N) {
+        len = rp[i + 1] - rp[i];
         if (offdiag)
             for (int32_t k = rp[i]; k < rp[i + 1]; ++k) len -= col[k] == i ? 1 : 0;
-        w = max(w, len);
     }
-    sw[sl] = w;
-    cnt[sl] = w * C;
+    for (int o = C >> 1; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
+    const int32_t sl = i / C;
+    if (i - sl * C == 0 && sl < ns) {
+        sw[sl] = len;
+        cnt[sl] = len * C;
+    }
 }
 
 __global__ void k_sell_fill_idx(int32_t N, int32_t C, const int32_t *rp, const int32_t *col, const int32_t *soff,
@@ -454,15 +458,23 @@ __global__ void k_fill_i32(int64_t m, int32_t *a, int32_t v) {
     if (g < m) a[g] = v;
 }
 
-template <int n>
+// Values of a sliced copy gathered from block CSR (zeros in padding); with
+// out32, also their FP32 rounding, flagging (bit 64) values FP32 cannot hold.
+template <int n, bool F32>
 __global__ void k_sell_vals(int64_t nent, const int32_t *__restrict__ ssrc, const double *__restrict__ in,
-                            double *__restrict__ out) {
+                            double *__restrict__ out, float *__restrict__ out32, int32_t *flag) {
     constexpr int nn = n * n;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nent * nn) return;
     const int64_t e = g / nn;
     const int32_t k = ssrc[e];
-    out[g] = k >= 0 ? in[(int64_t)k * nn + (g - e * nn)] : 0.0;
+    const double v = k >= 0 ? in[(int64_t)k * nn + (g - e * nn)] : 0.0;
+    out[g] = v;
+    if constexpr (F32) {
+        const float f = (float)v;
+        out32[g] = f;
+        if (!isfinite(f)) atomicOr(flag, 64);
+    }
 }
 
 // Row-scaled FP32 values for the block-Jacobi sweep: entry (i, j) of the
@@ -600,8 +612,8 @@ void sell_pattern_begin(int32_t N, const int32_t *rp, const int32_t *col, Sell &
     S.sw.alloc(ns > 0 ? ns : 1);
     S.soff.alloc(ns + 1);
     if (ns > 0)
-        hipLaunchKernelGGL(k_sell_width, dim3(cdiv(ns, 256)), dim3(256), 0, st, N, ns, C, rp, col, S.sw.get(),
-                           S.soff.get(), offdiag ? 1 : 0);
+        hipLaunchKernelGGL(k_sell_width, dim3(cdiv((int64_t)ns * C, 256)), dim3(256), 0, st, N, ns, C, rp, col,
+                           S.sw.get(), S.soff.get(), offdiag ? 1 : 0);
     LAUNCHCHK();
     scan_exclusive(S.soff.get(), S.soff.get(), ns, st);
 }
@@ -627,17 +639,25 @@ void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipSt
     sell_pattern_finish(rp, col, S, read_int(S.soff.get() + S.nslices, st), st, offdiag);
 }
 
-void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st) {
+void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipStream_t st, float *out32,
+               int32_t *flag) {
     const int64_t tot = S.nent * n * n;
     if (tot <= 0) return;
     const dim3 g(cdiv(tot, 256)), b(256);
+#define SV(NN)                                                                                                  \
+    if (out32)                                                                                                  \
+        hipLaunchKernelGGL((k_sell_vals<NN, true>), g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out, out32, flag); \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_sell_vals<NN, false>), g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out, nullptr,    \
+                           nullptr)
     switch (n) {
-        case 1: hipLaunchKernelGGL(k_sell_vals<1>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
-        case 2: hipLaunchKernelGGL(k_sell_vals<2>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
-        case 3: hipLaunchKernelGGL(k_sell_vals<3>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
-        case 4: hipLaunchKernelGGL(k_sell_vals<4>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
-        case 5: hipLaunchKernelGGL(k_sell_vals<5>, g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out); break;
+        case 1: SV(1); break;
+        case 2: SV(2); break;
+        case 3: SV(3); break;
+        case 4: SV(4); break;
+        case 5: SV(5); break;
     }
+#undef SV
     LAUNCHCHK();
 }
 
