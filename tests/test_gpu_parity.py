@@ -659,3 +659,38 @@ def test_dilu_amg_solve_and_transpose(precision):
         lam, stt = sysm.solve_transpose(c)
         assert stt["status"] == P.OK
         assert O.relres(O.transpose(A), c, _np(lam)) <= 1e-10 * 1.0001
+
+
+@pytest.mark.parametrize("tail", [-1, 0])
+def test_amg_on_graph_with_long_rows(tail):
+    """Rows of up to 66 blocks in random order and orientation (the register
+    paths of the setup and the V-cycle tail fall back to their loops there):
+    the FP64 V-cycle matches the oracle's on the GPU's hierarchy, and mixed
+    AMG-BiCGStab solves A x = b and A^T y = b to the tolerance."""
+    from workloads import jacobian_graph
+    _say("graph long rows tail", tail)
+    s = jacobian_graph(N=3000, n=4, seed=3)
+    A = O.from_system(s)
+    xref = _ref_solution(A, s["b"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, coarse_max=8, pre_sweeps=2, post_sweeps=2, omega=0.9, tail_rows=tail)
+        nlev = sysm.info()["levels"]
+        assert nlev >= 3
+        lv0 = sysm.get_level(0)
+        order = _np(lv0["order"])
+        A0 = O.BCSR(A.N, 4, _np(lv0["row_ptr"]), _np(lv0["col"]), _np(lv0["vals"]))
+        assert np.diff(_np(lv0["row_ptr"])).max() > 32
+        aggs = [_np(sysm.get_level(l)["agg"]) for l in range(nlev - 1)]
+        r = np.random.default_rng(6).standard_normal((A.N, 4))
+        z = _np(sysm.apply_precond(r))
+        sysm.setup(precond=P.PREC_AMG, precision=P.PRECISION_MIXED, tol=1e-9, tail_rows=tail)
+        x, st = sysm.solve(s["b"])
+        lam, stt = sysm.solve_transpose(s["b"])
+    zr_int = O.AMG(A0, nu1=2, nu2=2, omega=0.9, aggs=aggs).apply(r[order])
+    zr = np.empty_like(zr_int)
+    zr[order] = zr_int
+    assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+    assert st["status"] == P.OK and st["precision_fallback"] == 0, st
+    _check_solution(A, s["b"], _np(x), xref, tol=1e-9, err=1e-6)
+    assert stt["status"] == P.OK, stt
+    assert O.relres(O.transpose(A), s["b"], _np(lam)) <= 1e-9 * 1.0001

@@ -1,7 +1,7 @@
 """Invariants of the seeded input generators (no solver arithmetic here)."""
 import numpy as np
 
-from workloads import (batch_sizes, box_faces, concat_systems, jacobian_box,
+from workloads import (batch_sizes, box_faces, concat_systems, jacobian_box, jacobian_graph,
                        jacobian_stretched, pressure_velocity, stretched_spacing)
 
 
@@ -71,3 +71,24 @@ def test_spectral_norm_helper_matches_library_svd():
         J = rng.normal(0.0, 0.2, size=(500, n, n))
         ref = np.linalg.norm(J, ord=2, axis=(1, 2))
         assert np.allclose(_spectral_norms(J), ref, rtol=1e-12, atol=1e-15)
+
+
+def test_graph_workload_faces_and_row_sums():
+    """Random graph: faces unique and valid, both orientations present, a few
+    rows far longer than a hexahedral mesh gives, seeded, and every block row
+    sums to the identity (unit cell weight)."""
+    s = jacobian_graph(N=600, n=3, hubs=4, hub_degree=40, base_degree=3, seed=5)
+    assert np.array_equal(s["upper"], jacobian_graph(N=600, n=3, hubs=4, hub_degree=40, base_degree=3,
+                                                     seed=5)["upper"])
+    N, la, ua = s["N"], s["lower_addr"], s["upper_addr"]
+    assert np.all((la >= 0) & (la < N) & (ua >= 0) & (ua < N)) and np.all(la != ua)
+    key = np.minimum(la, ua).astype(np.int64) * N + np.maximum(la, ua)
+    assert np.unique(key).size == key.size
+    assert 0.3 < np.mean(la > ua) < 0.7
+    deg = np.bincount(np.concatenate([la, ua]), minlength=N)
+    assert deg.max() >= 35 and np.median(deg) <= 8
+    rows = s["diag"].copy()
+    np.add.at(rows, la, s["upper"])
+    np.add.at(rows, ua, s["lower"])
+    assert np.allclose(rows, np.eye(3)[None], atol=1e-12)
+

@@ -23,6 +23,9 @@ workloads.  Four families stand in for the paper's two industrial systems:
 * ``batch_sizes`` / ``jacobian_batch`` -- many independent density-based
   systems of log-uniform sizes concatenated with cell and face offsets
   (the offset layout of the consolidation scheme in Sec. 2.3).
+* ``jacobian_graph`` -- the density-based blocks on a random face graph with
+  a few very high-degree cells: an edge case for row lengths (far beyond a
+  hexahedral mesh's seven blocks), random cell order and face orientation.
 """
 from __future__ import annotations
 
@@ -30,7 +33,7 @@ import numpy as np
 
 __all__ = [
     "box_faces", "jacobian_box", "jacobian_stretched", "pressure_velocity",
-    "batch_sizes", "jacobian_batch", "concat_systems", "stretched_spacing",
+    "batch_sizes", "jacobian_batch", "concat_systems", "stretched_spacing", "jacobian_graph",
 ]
 
 
@@ -415,3 +418,41 @@ def jacobian_batch(k=64, lo=1e4, hi=5e5, seed=0, n=5):
     out = concat_systems(systems)
     out["shapes"] = shapes
     return out
+
+
+def jacobian_graph(N=3000, n=4, hubs=12, hub_degree=48, base_degree=4, seed=0, sigma=0.2):
+    """Density-type blocks (as in ``jacobian_box``, unit face and cell
+    weights) on a random face graph: every cell draws ``base_degree`` random
+    partners and ``hubs`` cells draw ``hub_degree`` more, so a few block rows
+    hold over 50 blocks.  Self pairs are dropped, repeated unordered pairs
+    kept once (first draw), and each face's orientation is random, so the
+    owner may be the higher cell index.
+
+    Draw order from ``numpy.random.default_rng(seed)``: the N*base_degree base
+    pairs (first cells, then second cells), the hub cells, their partners
+    (hub-major), the orientation coin per kept face, J_f (N(0, sigma^2)),
+    then b (U(-1, 1)).
+    """
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, N, size=N * base_degree)
+    c = rng.integers(0, N, size=N * base_degree)
+    hub = rng.choice(N, size=hubs, replace=False)
+    partners = rng.integers(0, N, size=(hubs, hub_degree))
+    a = np.concatenate([a, np.repeat(hub, hub_degree)])
+    c = np.concatenate([c, partners.reshape(-1)])
+    keep = a != c
+    lo, hi = np.minimum(a, c)[keep], np.maximum(a, c)[keep]
+    _, first = np.unique(lo.astype(np.int64) * N + hi, return_index=True)
+    first.sort()
+    lo, hi = lo[first], hi[first]
+    flip = rng.random(lo.size) < 0.5
+    la = np.where(flip, hi, lo)
+    ua = np.where(flip, lo, hi)
+    F = la.size
+    J = rng.normal(0.0, sigma, size=(F, n, n))
+    b = rng.uniform(-1.0, 1.0, size=(N, n))
+    diag, upper, lower = _jacobian_blocks(N, la, ua, J, np.ones(F), np.ones(N), n, "A")
+    return _pack(N, n, la, ua, diag, upper, lower, b,
+                 {"kind": "jacobian_graph", "N": N, "hubs": hubs, "hub_degree": hub_degree,
+                  "base_degree": base_degree, "seed": seed, "sigma": sigma})
+
