@@ -498,18 +498,33 @@ __global__ void k_sell_scaled(int32_t N, int32_t nslices, int32_t C, const int32
     double d[n];
 #pragma unroll
     for (int q = 0; q < n; ++q) d[q] = i < N ? Dinv[(int64_t)i * nn + r * n + q] : 0.0;
-    for (int32_t k = 0; k < w; ++k) {
-        const int64_t e = base + (int64_t)k * C;
-        const int32_t src = i < N ? ssrc[e] : -1;
-        const double *a = bvals + (int64_t)(src < 0 ? 0 : src) * nn;
+    // entries two at a time, the next pair's source slots loaded ahead
+    auto slot = [&](int32_t k) { return (i < N && k < w) ? ssrc[base + (int64_t)k * C] : -1; };
+    int32_t s0 = slot(0), s1 = slot(1);
+    for (int32_t k = 0; k < w; k += 2) {
+        const int32_t src[2] = {s0, s1};
+        s0 = slot(k + 2);
+        s1 = slot(k + 3);
+        double a[2][nn];
 #pragma unroll
-        for (int c = 0; c < n; ++c) {
-            double acc = 0.0;
+        for (int u = 0; u < 2; ++u) {
+            const double *p = bvals + (int64_t)(src[u] < 0 ? 0 : src[u]) * nn;
 #pragma unroll
-            for (int q = 0; q < n; ++q) acc += d[q] * (src < 0 ? 0.0 : a[q * n + c]);
-            const float v = (float)acc;
-            out[e * nn + r * n + c] = v;
-            if (!isfinite(v)) atomicOr(flag, 64);
+            for (int q = 0; q < nn; ++q) a[u][q] = src[u] < 0 ? 0.0 : p[q];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (k + u >= w) break;
+            const int64_t e = base + (int64_t)(k + u) * C;
+#pragma unroll
+            for (int c = 0; c < n; ++c) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < n; ++q) acc += d[q] * a[u][q * n + c];
+                const float v = (float)acc;
+                out[e * nn + r * n + c] = v;
+                if (!isfinite(v)) atomicOr(flag, 64);
+            }
         }
     }
 }
