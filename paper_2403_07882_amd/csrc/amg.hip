@@ -308,9 +308,48 @@ __global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, int32_t cap,
     int32_t *sDw = sJw + 2 * cap;
     const int32_t I = blockIdx.x * (int32_t)(blockDim.x >> 6) + w;
     const bool active = I < nc;
+    // the candidate list: the blocks of the members' rows, member by member.
+    // Up to 64 members: one lane per member reads its row's extent, a scan
+    // over the lanes gives each member's offset in the list, and every lane
+    // then fills list entries of any member (found by binary search over the
+    // offsets), so the dependent loads are not repeated per member.
+    __shared__ int32_t sMo[kRapWaves][65], sMk[kRapWaves][64];
     int32_t c = 0;
-    if (active) {
-        for (int32_t m = aptr[I]; m < aptr[I + 1]; ++m) {
+    const int32_t m0 = active ? aptr[I] : 0, nm = active ? aptr[I + 1] - m0 : 0;
+    const bool by_lane = nm <= 64;                   // the same for the whole wavefront
+    if (by_lane) {
+        int32_t kb = 0, len = 0;
+        if (lane < nm) {
+            const int32_t i = amem[m0 + lane];
+            kb = rp[i];
+            len = rp[i + 1] - kb;
+        }
+        int32_t inc = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+        }
+        c = __shfl(inc, 63, 64);
+        if (lane < nm) { sMo[w][lane] = inc - len; sMk[w][lane] = kb; }
+        if (lane == 0) sMo[w][nm] = c;
+    }
+    __syncthreads();
+    if (by_lane) {
+        const int32_t cl = min(c, cap);
+        for (int32_t q = lane; q < cl; q += 64) {
+            int32_t lo = 0, hi = nm - 1;             // last member whose offset is <= q
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (sMo[w][mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            const int32_t k = sMk[w][lo] + (q - sMo[w][lo]);
+            sJw[q] = agg[col[k]];
+            sKw[q] = (uint32_t)k;
+        }
+    } else {
+        for (int32_t m = m0; m < m0 + nm; ++m) {
             const int32_t i = amem[m];
             const int32_t kb = rp[i], len = rp[i + 1] - kb;
             for (int32_t e = lane; e < len; e += 64) {
@@ -319,8 +358,8 @@ __global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, int32_t cap,
             }
             c += len;
         }
-        if (c > cap && lane == 0) atomicOr(flag, 8);
     }
+    if (active && c > cap && lane == 0) atomicOr(flag, 8);
     __syncthreads();
     const int32_t cc = active ? min(c, cap) : 0;
     for (int32_t q = lane; q < cc; q += 64) {
