@@ -400,25 +400,42 @@ __global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, int32_t cap,
         sJw[pos] = q;
     }
     __syncthreads();
+    // where each output block's group starts in the list (up to 64 blocks;
+    // sMo is free again), else found by binary search per output value
+    const int32_t nd = active ? rpc[I + 1] - base : 0;
+    const bool starts = nd <= 64;                    // the same for the whole wavefront
+    if (starts) {
+        for (int32_t q = lane; q < cc; q += 64) {
+            const int32_t dq = sDw[sJw[q]];
+            if (q == 0 || sDw[sJw[q - 1]] != dq) sMo[w][dq] = q;
+        }
+        if (lane == 0) sMo[w][nd] = cc;
+    }
+    __syncthreads();
     if (!active) return;
-    const int32_t nd = rpc[I + 1] - base;
     for (int32_t t = lane; t < nd * nn; t += 64) {
         const int32_t d = t / nn, e = t - d * nn;
-        // the group of block d is [lo, hi) of the list (ordered by block:
-        // two binary searches); its values are loaded four at a time and
-        // added in candidate order
-        int32_t lo = 0, hi = cc;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (sDw[sJw[mid]] < d) lo = mid + 1;
-            else hi = mid;
-        }
-        int32_t end = lo;
-        hi = cc;
-        while (end < hi) {
-            const int32_t mid = (end + hi) >> 1;
-            if (sDw[sJw[mid]] <= d) end = mid + 1;
-            else hi = mid;
+        // the group of block d is [lo, end) of the list (ordered by block);
+        // its values are loaded four at a time and added in candidate order
+        int32_t lo, end;
+        if (starts) {
+            lo = sMo[w][d];
+            end = sMo[w][d + 1];
+        } else {
+            int32_t hi = cc;
+            lo = 0;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (sDw[sJw[mid]] < d) lo = mid + 1;
+                else hi = mid;
+            }
+            end = lo;
+            hi = cc;
+            while (end < hi) {
+                const int32_t mid = (end + hi) >> 1;
+                if (sDw[sJw[mid]] <= d) end = mid + 1;
+                else hi = mid;
+            }
         }
         auto src = [&](int32_t g) { return val[(int64_t)(sKw[sJw[g]] & ~kFirst) * nn + e]; };
         double acc = 0.0;
