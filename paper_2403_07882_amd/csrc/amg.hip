@@ -675,14 +675,22 @@ __global__ void k_perm_rows(int32_t N, const int32_t *ip, const int32_t *pos, co
     }
 }
 
+// out block k = in block sk[k]; each thread moves V values (V = 4 or 2 when
+// the block size allows: 32- or 16-byte accesses)
 template <int n>
 __global__ void k_gather_blocks(int64_t nb, const int32_t *__restrict__ sk, const double *__restrict__ in,
                                 double *__restrict__ out) {
-    constexpr int nn = n * n;
+    constexpr int nn = n * n, V = nn % 4 == 0 ? 4 : (nn % 2 == 0 ? 2 : 1);
+    typedef double dv __attribute__((ext_vector_type(V)));
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nb * nn) return;
-    const int64_t k = g / nn;
-    out[g] = in[(int64_t)sk[k] * nn + (g - k * nn)];
+    if (g >= nb * (nn / V)) return;
+    const int64_t k = g / (nn / V);
+    const int64_t e = (g - k * (nn / V)) * V;
+    if constexpr (V == 1) {
+        out[k * nn + e] = in[(int64_t)sk[k] * nn + e];
+    } else {
+        *reinterpret_cast<dv *>(out + k * nn + e) = *reinterpret_cast<const dv *>(in + (int64_t)sk[k] * nn + e);
+    }
 }
 
 // out[i'] = map[ip[i']], renamed through pos_c when given
@@ -898,7 +906,8 @@ void dilu_setup_n(const int32_t *rows, int32_t cnt, int c, const int32_t *rp, co
 }
 template <int n>
 void gather_blocks_n(int64_t nb, const int32_t *sk, const double *in, double *out, hipStream_t st) {
-    const int64_t tot = nb * n * n;
+    constexpr int nn = n * n, V = nn % 4 == 0 ? 4 : (nn % 2 == 0 ? 2 : 1);
+    const int64_t tot = nb * (nn / V);
     if (tot > 0) hipLaunchKernelGGL(k_gather_blocks<n>, dim3(cdiv(tot, 256)), dim3(256), 0, st, nb, sk, in, out);
 }
 template <int n>

@@ -240,17 +240,34 @@ __global__ void k_row_sys(int32_t N, int32_t n_sys, const int64_t *cell_off, int
 template <int n>
 __global__ void k_values(int64_t total, int32_t N, int32_t F, const int32_t *src, const double *diag,
                          const double *upper, const double *lower, double *vals, int32_t *flag) {
-    constexpr int nn = n * n;
+    // V values per thread (32- or 16-byte accesses when the block size allows)
+    constexpr int nn = n * n, V = nn % 4 == 0 ? 4 : (nn % 2 == 0 ? 2 : 1);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const int64_t k = g / nn;
-    const int e = (int)(g - k * nn);
+    if (g >= total / V) return;
+    const int64_t k = g / (nn / V);
+    const int e = (int)(g - k * (nn / V)) * V;
     const int32_t s = src[k];
     const double *from = s < N ? diag + (int64_t)s * nn
                        : (s < N + F ? upper + (int64_t)(s - N) * nn : lower + (int64_t)(s - N - F) * nn);
-    const double v = from[e];
-    if (!isfinite(v)) atomicOr(flag, 4);
-    vals[g] = v;
+    double v[V];
+    if constexpr (V == 4) {
+        typedef double d4 __attribute__((ext_vector_type(4)));
+        const d4 a = *reinterpret_cast<const d4 *>(from + e);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    } else if constexpr (V == 2) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 a = *reinterpret_cast<const d2 *>(from + e);
+        v[0] = a.x; v[1] = a.y;
+    } else {
+        v[0] = from[e];
+    }
+    bool bad = false;
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        bad = bad || !isfinite(v[u]);
+        vals[k * nn + e + u] = v[u];
+    }
+    if (bad) atomicOr(flag, 4);
 }
 
 __global__ void k_check_finite(const double *a, int64_t count, int32_t *flag) {
@@ -335,7 +352,8 @@ void convert_values(cbs_system *h, const double *diag, const double *upper, cons
     const int64_t total = h->nnzb * n * n;
     h->vals.ensure(total);
     HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
-    const dim3 g(cdiv(total, 256)), b(256);
+    const int64_t nthr = (n * n) % 4 == 0 ? total / 4 : ((n * n) % 2 == 0 ? total / 2 : total);
+    const dim3 g(cdiv(nthr, 256)), b(256);
     switch (n) {
         case 1: hipLaunchKernelGGL(k_values<1>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
         case 2: hipLaunchKernelGGL(k_values<2>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
