@@ -197,8 +197,8 @@ def kernels_only(args, P, torch, dev, sysm, opt_mixed, N, n, nnzb, la, ua, diag,
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this solver path runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs on a single MI355X; "
+              "a row-partitioned multi-GPU solve is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2403_07882_amd as P
