@@ -28,10 +28,12 @@ struct CbsError {
 #define LAUNCHCHK() HIPCHK(hipGetLastError())
 
 // ---------------------------------------------------------------- memory
-// Device memory comes from the device's stream-ordered pool (hipMallocAsync /
-// hipFreeAsync on the stream of the handle being worked on), with a release
-// threshold that keeps freed blocks in the pool: setup can allocate and
-// free its temporaries without synchronising the device.
+// Device memory comes from a process-wide cache of hipMalloc blocks: a freed
+// block is kept with the stream it was used on (the handle's stream, set by
+// set_alloc_stream) and handed out again only to allocations on that stream,
+// whose order makes the reuse safe.  Setup can thus allocate and free its
+// temporaries without synchronising the device; cbs_destroy returns the
+// handle's cached blocks to HIP.
 hipStream_t alloc_stream();
 void set_alloc_stream(hipStream_t st);
 void *dev_alloc(size_t bytes);
