@@ -88,9 +88,10 @@ __device__ inline void load_xc(const TX *__restrict__ x, int64_t j, const int32_
 // (and aux = Dinv b when aux is given); 4: y = x + w (b - x - A x), the sweep
 // of mode 2 on the row-scaled off-diagonal values Dinv_i A_ij (j != i; the
 // scaled diagonal block is the identity and is not stored) with b = Dinv b.
-// Rows are read from the sliced-ELL copy: at step k the 16 rows of a slice
-// read 16 consecutive blocks; four steps are loaded before they are summed,
-// and the sums run in the row's column order.
+// Rows are read from the sliced-ELL copy: at step k the C rows of a slice
+// (C = 16 on level 0, 8 on coarser levels) read C consecutive blocks; U steps
+// are loaded before they are summed, and the sums run in the row's column
+// order.
 // Modes 2 and 4 with PRO: x is first corrected by the prolongated coarse
 // solution (x + P e, pagg = aggregate map, pe = e), see load_xc.
 template <int n, typename TV, typename TX, int MODE, int U, bool NT, bool PRO>
