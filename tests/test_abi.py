@@ -59,3 +59,30 @@ def test_options_and_stats_layout_match_the_header():
         kinds = {"int32_t": "c_int", "double": "c_double"}
         for (ct, _), (_, pt) in zip(fields, cls._fields_):
             assert pt.__name__.startswith(kinds[ct]), (cname, ct, pt)
+
+
+def test_argument_errors_without_gpu():
+    """Every entry point rejects a NULL handle or bad sizes with CBS_ERR_ARG
+    before touching the device; cbs_destroy(NULL) is allowed."""
+    import ctypes as C
+    import paper_2403_07882_amd as P
+    L = P.lib()
+    o, st = P.default_options(), P.Stats()
+    calls = [
+        lambda: L.cbs_setup(None, C.byref(o)),
+        lambda: L.cbs_solve(None, None, None, C.byref(st)),
+        lambda: L.cbs_solve_transpose(None, None, None, C.byref(st)),
+        lambda: L.cbs_apply_precond(None, None, None),
+        lambda: L.cbs_apply_precond_transpose(None, None, None),
+        lambda: L.cbs_spmv(None, None, None, 0),
+        lambda: L.cbs_level_apply(None, 0, 0, None, None, None, None),
+        lambda: L.cbs_gradient(None, None, None, None, None, None),
+        lambda: L.cbs_update_values(None, None, None, None),
+    ]
+    for call in calls:
+        assert call() == P.ERR_ARG
+    assert L.cbs_destroy(None) == 0
+    h = C.c_void_p()
+    assert L.cbs_create_from_ldu(C.byref(h), 10, 0, 7, None, None, None, None, None, None) == P.ERR_ARG
+    assert b"bdim" in L.cbs_last_error()
+    assert not h.value
