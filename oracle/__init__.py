@@ -16,7 +16,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1 builds and loads a copy instrumented with AddressSanitizer
+# and UBSan (run the Python process with the two runtimes in LD_PRELOAD)
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_BREAKDOWN = -1, -2, -3, -4
@@ -26,10 +29,12 @@ SMOOTH_BJACOBI, SMOOTH_DILU = 0, 1
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP); with
+    ORACLE_SANITIZE=1 into liboracle_san.so with -fsanitize=address,undefined."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+        opt = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer"] if _SANITIZE else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-std=c11", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
