@@ -88,6 +88,8 @@ def _declare(L):
                               C.POINTER(ci), C.POINTER(cd)]),
         "orc_fgmres": (ci, [ci, ci, _i32p, _i32p, _f64p, ci, vp, _f64p, _f64p, cd, ci, ci,
                             C.POINTER(ci), C.POINTER(cd)]),
+        "orc_gmres": (ci, [ci, ci, _i32p, _i32p, _f64p, ci, vp, _f64p, _f64p, cd, ci, ci,
+                           C.POINTER(ci), C.POINTER(cd)]),
         "orc_grad": (None, [ci, ci, ci, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p]),
     }
     for name, (res, args) in sig.items():
@@ -369,6 +371,11 @@ def bicgstab(A: BCSR, b, x0=None, prec=PREC_BJACOBI, amg=None, tol=1e-8, maxit=1
 
 def fgmres(A: BCSR, b, x0=None, prec=PREC_BJACOBI, amg=None, tol=1e-8, maxit=1000, restart=30):
     return _solve(lib().orc_fgmres, A, b, x0, prec, amg, tol, maxit, (int(restart),))
+
+
+def gmres(A: BCSR, b, x0=None, prec=PREC_BJACOBI, amg=None, tol=1e-8, maxit=1000, restart=30):
+    """Right-preconditioned (non-flexible) GMRES(restart)."""
+    return _solve(lib().orc_gmres, A, b, x0, prec, amg, tol, maxit, (int(restart),))
 
 
 def grad(s, lam, x):

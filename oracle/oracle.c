@@ -993,6 +993,88 @@ done:
     return rc;
 }
 
+/* GMRES(mr) with right preconditioning (Saad 2003, Alg. 9.5): Arnoldi on
+ * A M^{-1} keeping only the basis V; at each restart x += M^{-1} (V y), one
+ * more preconditioner application per cycle instead of storing M^{-1} v_j.
+ * For a fixed preconditioner it builds the same iterates as orc_fgmres.  Same
+ * orthogonalisation, rotations and stopping rule as orc_fgmres. */
+int orc_gmres(int N, int n, const int *rp, const int *col, const double *val,
+              int prec_kind, void *amg, const double *b, double *x,
+              double tol, int maxit, int mr, int *iters, double *relres)
+{
+    long m = (long)N * n;
+    oprec P;
+    int rc = prec_init(&P, prec_kind, amg, N, n, rp, col, val);
+    if (rc) return rc;
+    if (mr < 1) mr = 1;
+    double *V = calloc((size_t)(mr + 1) * m + 1, 8), *z = calloc(m + 1, 8), *u = calloc(m + 1, 8);
+    double *H = calloc((size_t)(mr + 1) * mr + 1, 8), *cs = calloc(mr + 1, 8), *sn = calloc(mr + 1, 8);
+    double *g = calloc(mr + 2, 8), *y = calloc(mr + 1, 8), *r = calloc(m + 1, 8);
+    double bn = nrm2(m, b);
+    int it = 0;
+    rc = ORC_NOT_CONVERGED;
+    if (bn == 0.0) { memset(x, 0, sizeof(double) * m); *iters = 0; *relres = 0.0; rc = ORC_OK; goto done; }
+    for (;;) {
+        double res = true_relres(N, n, rp, col, val, b, x, r, bn);
+        *relres = res;
+        if (res <= tol) { rc = ORC_OK; break; }
+        if (it >= maxit) break;
+        double beta = res * bn;
+        for (long k = 0; k < m; k++) V[k] = r[k] / beta;
+        memset(g, 0, sizeof(double) * (mr + 2)); g[0] = beta;
+        int j = 0;
+        for (; j < mr && it < maxit; j++) {
+            double *vj = V + (size_t)j * m, *w = V + (size_t)(j + 1) * m;
+            prec_apply(&P, vj, z);                       /* w = A M^{-1} v_j */
+            orc_spmv_bcsr(N, n, rp, col, val, z, w);
+            double n0 = nrm2(m, w);
+            for (int i = 0; i <= j; i++) {
+                double h = dot(m, w, V + (size_t)i * m);
+                H[(size_t)i * mr + j] = h;
+                for (long k = 0; k < m; k++) w[k] -= h * V[(size_t)i * m + k];
+            }
+            double hn = nrm2(m, w);
+            if (hn < 0.1 * n0) {
+                for (int i = 0; i <= j; i++) {
+                    double h = dot(m, w, V + (size_t)i * m);
+                    H[(size_t)i * mr + j] += h;
+                    for (long k = 0; k < m; k++) w[k] -= h * V[(size_t)i * m + k];
+                }
+                hn = nrm2(m, w);
+            }
+            H[(size_t)(j + 1) * mr + j] = hn;
+            if (hn > 0.0) for (long k = 0; k < m; k++) w[k] /= hn;
+            for (int i = 0; i < j; i++) {
+                double a = H[(size_t)i * mr + j], c = H[(size_t)(i + 1) * mr + j];
+                H[(size_t)i * mr + j] = cs[i] * a + sn[i] * c;
+                H[(size_t)(i + 1) * mr + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = H[(size_t)j * mr + j], c = H[(size_t)(j + 1) * mr + j];
+            double den = sqrt(a * a + c * c);
+            cs[j] = den > 0.0 ? a / den : 1.0; sn[j] = den > 0.0 ? c / den : 0.0;
+            H[(size_t)j * mr + j] = den; H[(size_t)(j + 1) * mr + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j]; g[j] = cs[j] * g[j];
+            it++;
+            if (fabs(g[j + 1]) / bn <= tol || hn == 0.0) { j++; break; }
+        }
+        for (int i = j - 1; i >= 0; i--) {
+            double s = g[i];
+            for (int k = i + 1; k < j; k++) s -= H[(size_t)i * mr + k] * y[k];
+            y[i] = H[(size_t)i * mr + i] != 0.0 ? s / H[(size_t)i * mr + i] : 0.0;
+        }
+        /* x += M^{-1} (V y) */
+        memset(u, 0, sizeof(double) * m);
+        for (int i = 0; i < j; i++)
+            for (long k = 0; k < m; k++) u[k] += y[i] * V[(size_t)i * m + k];
+        prec_apply(&P, u, z);
+        for (long k = 0; k < m; k++) x[k] += z[k];
+    }
+done:
+    *iters = it;
+    free(V); free(z); free(u); free(H); free(cs); free(sn); free(g); free(y); free(r); free(P.Dinv);
+    return rc;
+}
+
 /* ------------------------------------------------------------------ */
 /* a15: gradient of L(x) with x = A^{-1} b, given lambda = A^{-T} dL/dx */
 /* dL/dA_ij = -lambda_i x_j^T on the pattern, written in LDU layout;   */

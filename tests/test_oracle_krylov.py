@@ -6,7 +6,7 @@ import oracle as O
 from workloads import jacobian_box, pressure_velocity
 
 
-@pytest.mark.parametrize("solver", ["bicgstab", "fgmres"])
+@pytest.mark.parametrize("solver", ["bicgstab", "fgmres", "gmres"])
 @pytest.mark.parametrize("prec", [O.PREC_NONE, O.PREC_BJACOBI, O.PREC_AMG])
 def test_tiny_systems_match_dense_lu(solver, prec):
     for s in (jacobian_box(4, 3, 3, seed=1), pressure_velocity(4, 3, 3, seed=1)):
@@ -28,7 +28,7 @@ def test_scaled_identity_converges_in_one_iteration():
     D = np.tile(3.5 * np.eye(n), (N, 1, 1))
     A = O.ldu_to_bcsr(N, n, [], [], D, np.zeros((0, n, n)), np.zeros((0, n, n)))[0]
     b = np.random.default_rng(0).standard_normal((N, n))
-    for fn in (O.bicgstab, O.fgmres):
+    for fn in (O.bicgstab, O.fgmres, O.gmres):
         x, st = fn(A, b, prec=O.PREC_NONE, tol=1e-12)
         assert st["iterations"] == 1
         assert np.allclose(x, b / 3.5, rtol=1e-14)
@@ -38,14 +38,30 @@ def test_fgmres_finite_termination():
     s = jacobian_box(3, 2, 2, n=2, seed=3)     # 24 unknowns
     A = O.from_system(s)
     m = A.N * A.n
-    x, st = O.fgmres(A, s["b"], prec=O.PREC_NONE, tol=1e-13, maxit=m, restart=m)
-    assert st["status"] == O.OK and st["iterations"] <= m
+    for fn in (O.fgmres, O.gmres):
+        x, st = fn(A, s["b"], prec=O.PREC_NONE, tol=1e-13, maxit=m, restart=m)
+        assert st["status"] == O.OK and st["iterations"] <= m
+
+
+@pytest.mark.parametrize("prec", [O.PREC_BJACOBI, O.PREC_AMG])
+def test_gmres_equals_fgmres_for_a_fixed_preconditioner(prec):
+    """With a preconditioner that is one fixed linear operator, right-
+    preconditioned GMRES and flexible GMRES build the same Krylov space and
+    the same iterates; only rounding separates them."""
+    s = pressure_velocity(6, 5, 5, seed=2)
+    A = O.from_system(s)
+    amg = O.AMG(A, coarse_max=8, nu1=1, nu2=1) if prec == O.PREC_AMG else None
+    xf, sf = O.fgmres(A, s["b"], prec=prec, amg=amg, tol=1e-10, maxit=500, restart=12)
+    xg, sg = O.gmres(A, s["b"], prec=prec, amg=amg, tol=1e-10, maxit=500, restart=12)
+    assert sf["status"] == O.OK and sg["status"] == O.OK
+    assert abs(sf["iterations"] - sg["iterations"]) <= 1
+    assert np.linalg.norm(xf - xg) <= 1e-8 * np.linalg.norm(xf)
 
 
 def test_zero_rhs_gives_zero():
     s = jacobian_box(3, 3, 3, seed=0)
     A = O.from_system(s)
-    for fn in (O.bicgstab, O.fgmres):
+    for fn in (O.bicgstab, O.fgmres, O.gmres):
         x, st = fn(A, np.zeros_like(s["b"]), x0=np.ones_like(s["b"]))
         assert st["iterations"] == 0 and np.all(x == 0)
 
