@@ -55,7 +55,12 @@ enum cbs_status {
     CBS_ERR_HIP = -8         /* HIP runtime error */
 };
 
-enum { CBS_SOLVER_BICGSTAB = 0, CBS_SOLVER_FGMRES = 1 };
+/* Krylov methods of Sec. 2.3: BiCGStab; flexible GMRES(m), which stores the
+ * m preconditioned basis vectors; right-preconditioned GMRES(m), which stores
+ * only the basis and applies the preconditioner once more per restart cycle
+ * (the same iterates as FGMRES when the preconditioner is a fixed linear
+ * operator, with m fewer N*n vectors in device memory). */
+enum { CBS_SOLVER_BICGSTAB = 0, CBS_SOLVER_FGMRES = 1, CBS_SOLVER_GMRES = 2 };
 enum { CBS_PREC_NONE = 0, CBS_PREC_BJACOBI = 1, CBS_PREC_AMG = 2 };
 enum { CBS_SMOOTH_BJACOBI = 0, CBS_SMOOTH_DILU = 1 };
 enum { CBS_PRECISION_FP64 = 0, CBS_PRECISION_MIXED = 1 };
@@ -64,7 +69,7 @@ enum { CBS_PRECISION_FP64 = 0, CBS_PRECISION_MIXED = 1 };
  * cbs_default_options() fills the defaults given in brackets. */
 typedef struct cbs_options {
     int32_t solver;          /* CBS_SOLVER_*                         [BICGSTAB] */
-    int32_t restart;         /* FGMRES restart length m              [30] */
+    int32_t restart;         /* (F)GMRES restart length m            [30] */
     int32_t precond;         /* CBS_PREC_*                           [AMG] */
     int32_t smoother;        /* CBS_SMOOTH_* (AMG levels)            [BJACOBI] */
     int32_t pre_sweeps;      /* smoothing sweeps before coarse corr. [2] */

@@ -283,7 +283,8 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
         set_alloc_stream(h->stream);
         cbs_options o;
         if (opt) o = *opt; else cbs_default_options(&o);
-        require(o.solver == CBS_SOLVER_BICGSTAB || o.solver == CBS_SOLVER_FGMRES, CBS_ERR_ARG, "unknown solver");
+        require(o.solver == CBS_SOLVER_BICGSTAB || o.solver == CBS_SOLVER_FGMRES || o.solver == CBS_SOLVER_GMRES,
+                CBS_ERR_ARG, "unknown solver");
         require(o.precond >= CBS_PREC_NONE && o.precond <= CBS_PREC_AMG, CBS_ERR_ARG, "unknown preconditioner");
         require(o.smoother == CBS_SMOOTH_BJACOBI || o.smoother == CBS_SMOOTH_DILU, CBS_ERR_ARG, "unknown smoother");
         require(o.precision == CBS_PRECISION_FP64 || o.precision == CBS_PRECISION_MIXED, CBS_ERR_ARG,

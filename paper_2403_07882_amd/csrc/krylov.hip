@@ -253,6 +253,12 @@ __global__ void k_zero_if_bzero(const Item *__restrict__ items, int32_t nsys, co
     for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) x[e] = 0.0;
 }
 
+// x += z (every element; a system that did not move contributes z = 0)
+__global__ void k_gm_add(const Item *__restrict__ items, const double *__restrict__ z, double *x) {
+    const Item it = items[blockIdx.x];
+    for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) x[e] += z[e];
+}
+
 // ------------------------------------------------------------------ FGMRES
 // multi-dot: partial[i * n_items + item] = (w, V_i), i = 0..j
 __global__ __launch_bounds__(kVecThreads) void k_mdot(const Item *__restrict__ items, int32_t n_items,
@@ -823,9 +829,15 @@ int bicgstab(cbs_system *h, const double *b, double *x, bool tr, std::vector<int
     return it;
 }
 
+// Flexible GMRES(m) (Z_j = M^{-1} V_j kept, x += Z y), or with flexible ==
+// false right-preconditioned GMRES(m): only V is kept, the preconditioned
+// vector is formed for the product and dropped, and each cycle ends with
+// x += M^{-1} (V y) -- one more preconditioner application per cycle and m
+// fewer stored vectors.
 int fgmres(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> &status) {
     hipStream_t st = h->stream;
     const cbs_options &o = h->opt;
+    const bool flexible = o.solver == CBS_SOLVER_FGMRES;
     const double tol2 = o.tol * o.tol;
     const int nsys = h->n_sys;
     const int m = std::max(1, o.restart);
@@ -859,7 +871,7 @@ int fgmres(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> 
         hipLaunchKernelGGL(k_scale, G, B, 0, st, items, h->done.get(), h->scal.get() + S_RHO * nsys, 1, r, V);
         int j = 0;
         for (; j < m && it < o.max_iter; ++j) {
-            double *vj = V + j * ld, *zj = Z + j * ld;
+            double *vj = V + j * ld, *zj = flexible ? Z + j * ld : h->ph.get();
             precond_apply(h, vj, zj, tr);
             spmv64(h, zj, w, tr);
             for (int pass = 0; pass < 2; ++pass) {        // classical Gram-Schmidt, twice
@@ -885,7 +897,17 @@ int fgmres(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> 
         const int jmax = std::min(j, m);
         hipLaunchKernelGGL(k_gm_solve, GS1, BS1, 0, st, nsys, m, h->H.get(), h->gvec.get(), h->flags.get() + 3 * nsys,
                            h->yv.get());
-        hipLaunchKernelGGL(k_gm_update, G, B, 0, st, items, m, jmax, ld, Z, h->yv.get(), h->flags.get() + 3 * nsys, x);
+        if (flexible) {
+            hipLaunchKernelGGL(k_gm_update, G, B, 0, st, items, m, jmax, ld, Z, h->yv.get(), h->flags.get() + 3 * nsys,
+                               x);
+        } else {
+            double *u = h->sh.get(), *z = h->ph.get();
+            launch_fill<double>(ld, u, st);
+            hipLaunchKernelGGL(k_gm_update, G, B, 0, st, items, m, jmax, ld, V, h->yv.get(), h->flags.get() + 3 * nsys,
+                               u);
+            precond_apply(h, u, z, tr);
+            hipLaunchKernelGGL(k_gm_add, G, B, 0, st, items, z, x);
+        }
         LAUNCHCHK();
         // next cycle re-evaluates every system from its true residual
         HIPCHK(hipMemsetAsync(h->done.get(), 0, sizeof(int32_t) * nsys, st));
@@ -918,17 +940,17 @@ void alloc_krylov(cbs_system *h) {
     const int64_t m = (int64_t)h->N * h->n;
     const int nsys = h->n_sys;
     for (DArr<double> *a : {&h->r, &h->rh, &h->p, &h->v, &h->ph, &h->s, &h->sh, &h->t, &h->w}) a->ensure(m);
-    if (h->opt.solver == CBS_SOLVER_FGMRES) {
+    if (h->opt.solver != CBS_SOLVER_BICGSTAB) {
         const int mr = std::max(1, h->opt.restart);
         h->V.ensure((size_t)(mr + 1) * m);
-        h->Z.ensure((size_t)mr * m);
+        if (h->opt.solver == CBS_SOLVER_FGMRES) h->Z.ensure((size_t)mr * m);
         h->H.ensure((size_t)nsys * (mr + 1) * mr);
         h->gvec.ensure((size_t)nsys * (mr + 1));
         h->cs.ensure((size_t)nsys * (mr + 1));
         h->sn.ensure((size_t)nsys * (mr + 1));
         h->yv.ensure((size_t)nsys * (mr + 1) * 3);
     }
-    const int K = std::max(3, h->opt.solver == CBS_SOLVER_FGMRES ? h->opt.restart + 2 : 3);
+    const int K = std::max(3, h->opt.solver != CBS_SOLVER_BICGSTAB ? h->opt.restart + 2 : 3);
     h->partial.ensure((size_t)K * h->n_items);
 }
 
@@ -955,7 +977,7 @@ int krylov_solve(cbs_system *h, const double *b, double *x, cbs_stats *stv, bool
     } else {
         launch_copy(m, x, h->xw.get(), st);
     }
-    if (h->opt.solver == CBS_SOLVER_FGMRES) fgmres(h, bi, h->xw.get(), tr, status);
+    if (h->opt.solver != CBS_SOLVER_BICGSTAB) fgmres(h, bi, h->xw.get(), tr, status);
     else bicgstab(h, bi, h->xw.get(), tr, status);
     if (h->renumbered) permute_vec(h, h->xw.get(), x, false);
     else launch_copy(m, h->xw.get(), x, st);

@@ -176,7 +176,7 @@ def test_c0_bicgstab_block_jacobi_full_size():
 
 
 @pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
-@pytest.mark.parametrize("solver", [P.SOLVER_BICGSTAB, P.SOLVER_FGMRES])
+@pytest.mark.parametrize("solver", [P.SOLVER_BICGSTAB, P.SOLVER_FGMRES, P.SOLVER_GMRES])
 def test_amg_solve_pressure_velocity(precision, solver):
     _say("amg pv", precision, solver)
     s = pressure_velocity(16, 16, 16, seed=0)
@@ -694,3 +694,42 @@ def test_amg_on_graph_with_long_rows(tail):
     _check_solution(A, s["b"], _np(x), xref, tol=1e-9, err=1e-6)
     assert stt["status"] == P.OK, stt
     assert O.relres(O.transpose(A), s["b"], _np(lam)) <= 1e-9 * 1.0001
+
+
+@pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
+def test_gmres_matches_oracle_gmres_and_fgmres(precision):
+    """Right-preconditioned GMRES(m): the solution matches the oracle's
+    GMRES solution (block Jacobi, 1e-12) to the solution bar; with the FP64
+    hierarchy (a fixed linear preconditioner) it takes the iterations flexible
+    GMRES takes, to within one; the transposed solve meets the tolerance; a
+    batch converges system by system, an all-zero system included."""
+    _say("gmres", precision)
+    s = pressure_velocity(12, 10, 9, seed=8)
+    A = O.from_system(s)
+    xref, sref = O.gmres(A, s["b"], prec=O.PREC_BJACOBI, tol=1e-12, maxit=20000, restart=60)
+    assert sref["status"] == O.OK, sref
+    its = {}
+    for solver in (P.SOLVER_FGMRES, P.SOLVER_GMRES):
+        with P.System.from_dict(s) as sysm:
+            sysm.setup(precond=P.PREC_AMG, precision=precision, solver=solver, restart=10, tol=1e-10)
+            x, st = sysm.solve(s["b"])
+            lam, stt = sysm.solve_transpose(s["b"])
+        assert st["status"] == P.OK and stt["status"] == P.OK, (st, stt)
+        _check_solution(A, s["b"], _np(x), xref, tol=1e-10, err=1e-7)
+        assert O.relres(O.transpose(A), s["b"], _np(lam)) <= 1e-10 * 1.0001
+        its[solver] = st["iterations"]
+    if precision == P.PRECISION_FP64:
+        assert abs(its[P.SOLVER_FGMRES] - its[P.SOLVER_GMRES]) <= 1, its
+    systems = [jacobian_box(6, 5, 4, seed=11), jacobian_box(7, 3, 3, seed=12), jacobian_box(5, 5, 5, seed=13)]
+    systems[1]["b"] = np.zeros_like(systems[1]["b"])
+    cat = concat_systems(systems)
+    with P.System.from_dict(cat) as bs:
+        bs.setup(precond=P.PREC_AMG, precision=precision, solver=P.SOLVER_GMRES, restart=8, tol=1e-9)
+        xb, stats = bs.solve(cat["b"])
+    xn = _np(xb)
+    co = cat["cell_off"]
+    for k, sk in enumerate(systems):
+        assert stats[k]["status"] == P.OK, (k, stats[k])
+        assert O.relres(O.from_system(sk), sk["b"], xn[co[k]:co[k + 1]]) <= 1e-9 * 1.0001 or k == 1
+    assert stats[1]["iterations"] == 0 and np.all(xn[co[1]:co[2]] == 0)
+
