@@ -25,7 +25,7 @@ OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_BREAKDOWN = -1, -2, -3, -4
 
 PREC_NONE, PREC_BJACOBI, PREC_AMG = 0, 1, 2
-SMOOTH_BJACOBI, SMOOTH_DILU = 0, 1
+SMOOTH_BJACOBI, SMOOTH_DILU, SMOOTH_SGS = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -70,6 +70,7 @@ def _declare(L):
         "orc_blockinv": (ci, [cl, ci, _f64p, _f64p, C.POINTER(cl)]),
         "orc_dense_solve": (ci, [ci, _f64p, _f64p, _f64p]),
         "orc_bjacobi_sweep": (None, [ci, ci, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p, cd]),
+        "orc_sgs_sweep": (None, [ci, ci, _i32p, _i32p, _f64p, _f64p, _i32p, _f64p, _f64p]),
         "orc_dilu_setup": (ci, [ci, ci, _i32p, _i32p, _f64p, _i32p, _f64p]),
         "orc_dilu_apply": (None, [ci, ci, _i32p, _i32p, _f64p, _i32p, _f64p, _f64p, _f64p]),
         "orc_strength": (None, [ci, ci, _i32p, _i32p, _f64p, _f64p]),
@@ -246,6 +247,14 @@ def bjacobi_sweep(A: BCSR, Dinv, b, x, omega):
     out = np.empty(A.N * A.n)
     lib().orc_bjacobi_sweep(A.N, A.n, A.row_ptr, A.col, A.vals.ravel(), _c64(Dinv).ravel(),
                             _c64(b).ravel(), _c64(x).ravel(), out, float(omega))
+    return out.reshape(A.N, A.n)
+
+
+def sgs_sweep(A: BCSR, Dinv, rank, b, x):
+    """One symmetric block Gauss-Seidel step from x in the order of rank."""
+    out = _c64(x).ravel().copy()
+    lib().orc_sgs_sweep(A.N, A.n, A.row_ptr, A.col, A.vals.ravel(), _c64(Dinv).ravel(), _c32(rank),
+                        _c64(b).ravel(), out)
     return out.reshape(A.N, A.n)
 
 

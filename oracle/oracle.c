@@ -399,6 +399,34 @@ void orc_bjacobi_sweep(int N, int n, const int *rp, const int *col, const double
     }
 }
 
+/* One symmetric block Gauss-Seidel step in place, for the ordering given by
+ * rank[] (j precedes i when rank[j] < rank[i]): rows in increasing rank, then
+ * in decreasing rank, each row taking x_i = D_i^{-1} (b_i - sum_{j != i}
+ * A_ij x_j) with the newest x_j.  (Sec. 2.3 names Gauss-Seidel among the
+ * smoothers; the forward-backward pair makes it symmetric.) */
+void orc_sgs_sweep(int N, int n, const int *rp, const int *col, const double *val,
+                   const double *Dinv, const int *rank, const double *b, double *x)
+{
+    long bs = (long)n * n;
+    int *order = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
+    for (int i = 0; i < N; i++) order[rank[i]] = i;
+    double t[8], u[8];
+    for (int pass = 0; pass < 2; pass++) {
+        for (int q0 = 0; q0 < N; q0++) {
+            int i = order[pass == 0 ? q0 : N - 1 - q0];
+            for (int e = 0; e < n; e++) t[e] = b[(long)i * n + e];
+            for (int k = rp[i]; k < rp[i + 1]; k++) {
+                int j = col[k];
+                if (j == i) continue;
+                blk_mv(n, val + (long)k * bs, x + (long)j * n, u);
+                for (int e = 0; e < n; e++) t[e] -= u[e];
+            }
+            blk_mv(n, Dinv + (long)i * bs, t, x + (long)i * n);
+        }
+    }
+    free(order);
+}
+
 /* DILU (diagonal incomplete LU) for the ordering given by rank[]:
  * j precedes i when rank[j] < rank[i].
  *   E_i = A_ii - sum_{j precedes i, j adjacent} A_ij E_j^{-1} A_ji
@@ -645,9 +673,9 @@ void orc_amg_free(void *h)
     free(A->LU); free(A->piv); free(A);
 }
 
-/* Build the hierarchy.  smoother: 0 = damped block Jacobi, 1 = DILU on the
- * dilu_levels finest levels (all levels when dilu_levels < 0) and damped
- * block Jacobi below them.
+/* Build the hierarchy.  smoother: 0 = damped block Jacobi, 1 = DILU, 2 =
+ * symmetric block Gauss-Seidel on the dilu_levels finest levels (all levels
+ * when dilu_levels < 0) and damped block Jacobi below them.
  * If aggs != NULL, level l uses the aggregate map aggs[off_l .. off_l+N_l)
  * (concatenated in level order, n_agg_levels maps in total) instead of its
  * own matching; ranks (same layout, one per row, for the n_rank_levels
@@ -662,7 +690,7 @@ void *orc_amg_create(int N, int n, const int *rp, const int *col, const double *
     oamg *A = (oamg *)calloc(1, sizeof(oamg));
     long bs = (long)n * n;
     A->n = n; A->smoother = smoother; A->nu1 = nu1; A->nu2 = nu2; A->omega = omega;
-    A->dilu_levels = (smoother == 1) ? (dilu_levels < 0 ? MAXLEV : dilu_levels) : 0;
+    A->dilu_levels = (smoother == 1 || smoother == 2) ? (dilu_levels < 0 ? MAXLEV : dilu_levels) : 0;
     /* level 0: own copy */
     olevel *L0 = &A->L[0];
     L0->N = N;
@@ -740,8 +768,13 @@ void *orc_amg_create(int N, int n, const int *rp, const int *col, const double *
             c->rank = (int *)malloc(sizeof(int) * (c->N + 1));
             if (ranks && q < n_rank_levels) { for (int i = 0; i < c->N; i++) c->rank[i] = ranks[roff + i]; roff += c->N; }
             else for (int i = 0; i < c->N; i++) c->rank[i] = i;
-            c->Einv = (double *)malloc(sizeof(double) * ((long)c->N * bs + 1));
-            if (orc_dilu_setup(c->N, n, c->rp, c->col, c->val, c->rank, c->Einv)) { orc_amg_free(A); return NULL; }
+            if (smoother == 2) {           /* symmetric Gauss-Seidel: D^{-1} and the order */
+                c->Dinv = (double *)malloc(sizeof(double) * ((long)c->N * bs + 1));
+                if (diag_inverse(c->N, n, c->rp, c->col, c->val, c->Dinv)) { orc_amg_free(A); return NULL; }
+            } else {
+                c->Einv = (double *)malloc(sizeof(double) * ((long)c->N * bs + 1));
+                if (orc_dilu_setup(c->N, n, c->rp, c->col, c->val, c->rank, c->Einv)) { orc_amg_free(A); return NULL; }
+            }
         }
     }
     /* coarsest: dense LU */
@@ -766,7 +799,9 @@ static void smooth(oamg *A, olevel *c, const double *b, double *x)
 {
     int n = A->n;
     long m = (long)c->N * n;
-    if (c->Dinv) {
+    if (c->Dinv && c->rank) {
+        orc_sgs_sweep(c->N, n, c->rp, c->col, c->val, c->Dinv, c->rank, b, x);
+    } else if (c->Dinv) {
         orc_bjacobi_sweep(c->N, n, c->rp, c->col, c->val, c->Dinv, b, x, c->r, A->omega);
         memcpy(x, c->r, sizeof(double) * m);
     } else {

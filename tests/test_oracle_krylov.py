@@ -118,3 +118,21 @@ def test_dilu_amg_reaches_tolerance_on_pressure_velocity():
     amg = O.AMG(A, coarse_max=32, smoother=O.SMOOTH_DILU)
     x, st = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=amg, tol=1e-8)
     assert st["status"] == O.OK and O.relres(A, s["b"], x) <= 1e-8
+
+
+def test_sgs_amg_reaches_tolerance_and_is_exact_on_block_diagonal_levels():
+    """AMG with symmetric Gauss-Seidel smoothing on the finest level solves the
+    pressure-velocity system; on a block-diagonal matrix one SGS step is exact,
+    so the V-cycle is the exact inverse there."""
+    s = pressure_velocity(10, 10, 10, seed=0)
+    A = O.from_system(s)
+    amg = O.AMG(A, coarse_max=32, smoother=O.SMOOTH_SGS, dilu_levels=1)
+    x, st = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=amg, tol=1e-8)
+    assert st["status"] == O.OK and O.relres(A, s["b"], x) <= 1e-8
+    rng = np.random.default_rng(2)
+    D = rng.standard_normal((40, 4, 4)) + 5 * np.eye(4)
+    Ab = O.ldu_to_bcsr(40, 4, [], [], D, np.zeros((0, 4, 4)), np.zeros((0, 4, 4)))[0]
+    agg = np.repeat(np.arange(10), 4).astype(np.int32)
+    mg = O.AMG(Ab, nu1=1, nu2=0, smoother=O.SMOOTH_SGS, aggs=[agg], dilu_levels=1)
+    b = rng.standard_normal((40, 4))
+    assert np.allclose(mg.apply(b), np.linalg.solve(D, b[..., None])[..., 0], rtol=1e-12, atol=1e-13)

@@ -112,6 +112,39 @@ def test_bjacobi_sweep_matches_dense_splitting():
     assert np.allclose(x1.ravel(), ref, rtol=1e-12, atol=1e-13)
 
 
+def test_sgs_block_diagonal_exact_in_one_step():
+    rng = np.random.default_rng(1)
+    D = rng.standard_normal((9, 4, 4)) + 4 * np.eye(4)
+    A = O.ldu_to_bcsr(9, 4, [], [], D, np.zeros((0, 4, 4)), np.zeros((0, 4, 4)))[0]
+    b = rng.standard_normal((9, 4))
+    x = O.sgs_sweep(A, O.blockinv(D), rng.permutation(9), b, np.ones((9, 4)))
+    assert np.allclose(x, np.linalg.solve(D, b[..., None])[..., 0], rtol=1e-13, atol=1e-14)
+
+
+def test_sgs_step_matches_dense_triangular_splitting():
+    """For an ordering (rank), A = D + L + U with L the blocks (i, j), j before
+    i, and U those after: the forward half is x' = (D + L)^{-1} (b - U x), the
+    backward half x'' = (D + U)^{-1} (b - L x')."""
+    s = jacobian_box(4, 3, 3, n=3, seed=4)
+    A = O.from_system(s)
+    n = A.n
+    Dinv = O.blockinv(O.diag_blocks(A))
+    rng = np.random.default_rng(5)
+    rank = rng.permutation(A.N)
+    x0 = rng.standard_normal((A.N, n))
+    x2 = O.sgs_sweep(A, Dinv, rank, s["b"], x0)
+    Ad = A.dense()
+    bi = np.repeat(np.arange(A.N), n)
+    before = rank[bi][:, None] > rank[bi][None, :]
+    after = rank[bi][:, None] < rank[bi][None, :]
+    same = bi[:, None] == bi[None, :]
+    Dd, Ld, Ud = Ad * same, Ad * before, Ad * after
+    b = s["b"].ravel()
+    x1 = np.linalg.solve(Dd + Ld, b - Ud @ x0.ravel())
+    ref = np.linalg.solve(Dd + Ud, b - Ld @ x1)
+    assert np.allclose(x2.ravel(), ref, rtol=1e-11, atol=1e-12)
+
+
 def _chain(N, n, seed):
     """Block-tridiagonal 1D chain: cells 0-1-2-..., natural order."""
     rng = np.random.default_rng(seed)
