@@ -62,7 +62,11 @@ enum cbs_status {
  * operator, with m fewer N*n vectors in device memory). */
 enum { CBS_SOLVER_BICGSTAB = 0, CBS_SOLVER_FGMRES = 1, CBS_SOLVER_GMRES = 2 };
 enum { CBS_PREC_NONE = 0, CBS_PREC_BJACOBI = 1, CBS_PREC_AMG = 2 };
-enum { CBS_SMOOTH_BJACOBI = 0, CBS_SMOOTH_DILU = 1 };
+/* AMG smoothers (Sec. 2.3): damped block Jacobi; multicolour block DILU;
+ * multicolour symmetric block Gauss-Seidel (one step = the colours in order,
+ * then in reverse, each row x_i = D_i^{-1} (b_i - sum_{j != i} A_ij x_j)).
+ * DILU and Gauss-Seidel run on the dilu_levels finest levels. */
+enum { CBS_SMOOTH_BJACOBI = 0, CBS_SMOOTH_DILU = 1, CBS_SMOOTH_SGS = 2 };
 enum { CBS_PRECISION_FP64 = 0, CBS_PRECISION_MIXED = 1 };
 
 /* Solver options (the "linear solver options" of Algorithm amgxFoam).
@@ -93,8 +97,8 @@ typedef struct cbs_options {
                                 gathers cache-local on irregularly numbered
                                 meshes; inputs and outputs keep the caller's
                                 numbering                            [1] */
-    int32_t dilu_levels;     /* smoother DILU: the dilu_levels finest levels use
-                                multicolour DILU, coarser ones damped block
+    int32_t dilu_levels;     /* smoother DILU or SGS: the dilu_levels finest
+                                levels use it, coarser ones damped block
                                 Jacobi; < 0 = every level            [2] */
     int32_t row_split;       /* block-row kernels on levels of fewer than
                                 65,536 block rows: threads that share one

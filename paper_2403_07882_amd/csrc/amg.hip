@@ -1298,7 +1298,8 @@ void amg_setup(cbs_system *h) {
     // (and level 0), the off-diagonal one of the mixed block-Jacobi levels;
     // new patterns share one read-back of their entry counts
     auto level_uses_dilu = [&](int q) {
-        return o.smoother == CBS_SMOOTH_DILU && (o.dilu_levels < 0 || q < o.dilu_levels) && q + 1 < nlev;
+        return (o.smoother == CBS_SMOOTH_DILU || o.smoother == CBS_SMOOTH_SGS) &&
+               (o.dilu_levels < 0 || q < o.dilu_levels) && q + 1 < nlev;
     };
     {
         struct Pending { Level *L; Sell *S; bool od; };
@@ -1334,19 +1335,19 @@ void amg_setup(cbs_system *h) {
     for (int q = 0; q < nlev; ++q) {
         Level &L = h->lev[q];
         nz_sum += L.nnzb;
-        const bool use_dilu = level_uses_dilu(q);
-        if (q + 1 < nlev && use_dilu) {
-            L.dilu = true;
-            if (!reuse || !L.colour.get()) colour_level(h, q);
+        const bool coloured = level_uses_dilu(q);   // DILU or symmetric Gauss-Seidel
+        L.dilu = q + 1 < nlev && coloured && o.smoother == CBS_SMOOTH_DILU;
+        L.sgs = q + 1 < nlev && coloured && o.smoother == CBS_SMOOTH_SGS;
+        if (q + 1 < nlev && coloured && (!reuse || !L.colour.get())) colour_level(h, q);
+        if (L.dilu) {
             dilu_factor_level(h, q);
-        } else if (q + 1 < nlev) {
-            L.dilu = false;
+        } else if (q + 1 < nlev) {                  // block Jacobi and Gauss-Seidel: D^{-1}
             L.Dinv.ensure((size_t)L.N * n * n);
             blockinv_level(h, q, L.v64, L.Dinv.get(), errs.get() + 1 + q);
         }
         pt.mark("smoother" + std::to_string(q));
         if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, deferred);
-        L.scaled = mixed && q + 1 < nlev && !L.dilu;
+        L.scaled = mixed && q + 1 < nlev && !L.dilu && !L.sgs;
         L.scaledT = false;
         if (L.scaled) {
             L.sod.v32.ensure(L.sod.nent > 0 ? (size_t)L.sod.nent * n * n : 1);

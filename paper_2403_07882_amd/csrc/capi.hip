@@ -286,7 +286,8 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
         require(o.solver == CBS_SOLVER_BICGSTAB || o.solver == CBS_SOLVER_FGMRES || o.solver == CBS_SOLVER_GMRES,
                 CBS_ERR_ARG, "unknown solver");
         require(o.precond >= CBS_PREC_NONE && o.precond <= CBS_PREC_AMG, CBS_ERR_ARG, "unknown preconditioner");
-        require(o.smoother == CBS_SMOOTH_BJACOBI || o.smoother == CBS_SMOOTH_DILU, CBS_ERR_ARG, "unknown smoother");
+        require(o.smoother == CBS_SMOOTH_BJACOBI || o.smoother == CBS_SMOOTH_DILU || o.smoother == CBS_SMOOTH_SGS,
+                CBS_ERR_ARG, "unknown smoother");
         require(o.precision == CBS_PRECISION_FP64 || o.precision == CBS_PRECISION_MIXED, CBS_ERR_ARG,
                 "unknown precision");
         require(o.restart >= 1 && o.restart <= 200, CBS_ERR_ARG, "restart must be in 1..200");
@@ -437,7 +438,8 @@ int cbs_level_apply(cbs_handle h, int32_t level, int32_t op, const void *b, cons
         require(b && x && y, CBS_ERR_ARG, "NULL vector");
         require(x != y, CBS_ERR_ARG, "y must not alias x");
         Level &L = h->lev[level];
-        require(op == CBS_LEVEL_RESIDUAL || !L.dilu, CBS_ERR_STATE, "a DILU level has no block-Jacobi sweep");
+        require(op == CBS_LEVEL_RESIDUAL || (!L.dilu && !L.sgs), CBS_ERR_STATE,
+                "a DILU or Gauss-Seidel level has no block-Jacobi sweep");
         const int n = h->n;
         const double w = h->opt.omega;
         hipStream_t st = h->stream;

@@ -166,6 +166,8 @@ struct Level {
     // DILU: colour classes (rows of colour c: rows_by_colour[colour_off[c] ..
     // colour_off[c+1])) and the FP64 inverses of the DILU diagonal E
     bool dilu = false;
+    // symmetric block Gauss-Seidel over the same colour classes (with Dinv)
+    bool sgs = false;
     DArr<int32_t> colour, rows_by_colour;
     std::vector<int32_t> colour_off;     // host, ncolours + 1
     DArr<double> Einv, EinvT;
@@ -335,6 +337,11 @@ void launch_block_apply(int n, int32_t N, const double *Dinv, const double *r, d
 int tail_level_for(const cbs_system *h, size_t tsize);
 template <typename T>
 void launch_tail(cbs_system *h, bool tr, int l0, const T *rfine);
+// block Gauss-Seidel on the rows rows[0..cnt) of one colour, in place:
+// x_i = D_i^{-1} (b_i - sum_{j != i} A_ij x_j)
+template <typename T>
+void launch_gs_colour(int n, const SellView &S, const T *val, const int32_t *rows, int32_t cnt, const double *Dinv,
+                      const T *b, T *x, hipStream_t st);
 // DILU colour sweeps on the rows rows[0..cnt): forward y = E^{-1}(b - A x - L y)
 // (zero_guess: A x omitted), backward z = y - E^{-1} U z, x = x + z
 template <typename T>

@@ -458,6 +458,22 @@ void dilu_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x, bool zero_g
                            L.colour_off[c + 1] - L.colour_off[c], Einv, y, x, zero_guess, h->stream);
 }
 
+// One symmetric block Gauss-Seidel step in place: the colour classes in
+// order, then in reverse (the oracle's order: colour first, then row).
+template <typename T>
+void sgs_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x) {
+    const T *val = level_vals<T>(L, tr);
+    const double *Dinv = tr ? L.DinvT.get() : L.Dinv.get();
+    const int ncol = (int)L.colour_off.size() - 1;
+    const SellView S = L.sell.view(sizeof(T) == 4);
+    auto colour = [&](int c) {
+        launch_gs_colour<T>(h->n, S, val, L.rows_by_colour.get() + L.colour_off[c],
+                            L.colour_off[c + 1] - L.colour_off[c], Dinv, b, x, h->stream);
+    };
+    for (int c = 0; c < ncol; ++c) colour(c);
+    for (int c = ncol - 1; c >= 0; --c) colour(c);
+}
+
 // x = V(b) with zero initial guess on level l; the result lands in x.  When
 // rfine is given, b is not yet formed: it is the restriction of the finer
 // level's residual rfine, which the first kernel of this level computes and
@@ -475,7 +491,7 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
     const int64_t m = (int64_t)L.N * n;
     const int nu1 = std::max(0, o.pre_sweeps), nu2 = std::max(0, o.post_sweeps);
     constexpr bool fp32 = sizeof(T) == sizeof(float);
-    const bool bj = l < nlev - 1 && !L.dilu;
+    const bool bj = l < nlev - 1 && !L.dilu && !L.sgs;
     const bool fuse_in = fp32 && b64 && bj && nu1 >= 1;
     const bool fuse_out = fp32 && x64 && bj && nu2 >= 1;
     if (b64 && !fuse_in) launch_cast<double, T>(m, b64, b, st);
@@ -502,14 +518,20 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
     T *r = vptr<T>(L.vr);
     Level &C = h->lev[l + 1];
     T *bc = vptr<T>(C.vb), *xc = vptr<T>(C.vx);
-    if (L.dilu) {
+    if (L.dilu || L.sgs) {
         if (rfine) restrict_into_b();
-        for (int s = 0; s < nu1; ++s) dilu_smooth<T>(h, L, tr, b, x, s == 0);
-        if (nu1 == 0) launch_fill<T>(m, x, st);
+        if (L.sgs || nu1 == 0) launch_fill<T>(m, x, st);    // Gauss-Seidel starts from x = 0
+        for (int s = 0; s < nu1; ++s) {
+            if (L.dilu) dilu_smooth<T>(h, L, tr, b, x, s == 0);
+            else sgs_smooth<T>(h, L, tr, b, x);
+        }
         launch_rows<T, T>(1, n, L.sell.view(fp32), val, x, b, r, nullptr, 0.0, st);
         vcycle<T>(h, tr, l + 1, bc, xc, r);
         launch_prolong<T>(n, L.N, L.agg.get(), xc, x, st);
-        for (int s = 0; s < nu2; ++s) dilu_smooth<T>(h, L, tr, b, x, false);
+        for (int s = 0; s < nu2; ++s) {
+            if (L.dilu) dilu_smooth<T>(h, L, tr, b, x, false);
+            else sgs_smooth<T>(h, L, tr, b, x);
+        }
         finish();
         return;
     }

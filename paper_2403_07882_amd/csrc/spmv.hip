@@ -325,6 +325,50 @@ void rows_n(int mode, const SellView &S, const TV *val, const TX *x, const TX *b
 //   backward z_i = y_i - E_i^{-1} sum_{colour(j) > c} A_ij z_j ;  x_i += z_i
 // so x + z = x + M^{-1}(b - A x) with M = (E + L) E^{-1} (E + U).  One
 // thread per (row, r) as in k_rows; E^{-1} (FP64) is applied through LDS.
+// One colour of a block Gauss-Seidel half-sweep, in place: for the rows of
+// colour c (rows[0..cnt)), x_i = D_i^{-1} (b_i - sum_{j != i} A_ij x_j).  Rows
+// of one colour are not neighbours, so each reads only x of other colours and
+// writes only its own.
+template <int n, typename T>
+__global__ __launch_bounds__(64 * n) void k_gs_colour(SellView S, const T *__restrict__ val,
+                                                      const int32_t *__restrict__ rows, int32_t cnt,
+                                                      const double *__restrict__ Dinv, const T *__restrict__ b,
+                                                      T *x) {
+    using A = typename Acc<T>::type;
+    constexpr int nn = n * n;
+    const int t = threadIdx.x;
+    const int lr = t / n, r = t - lr * n;
+    const int32_t q = blockIdx.x * 64 + lr;
+    const bool act = q < cnt;
+    const int32_t i = act ? rows[q] : 0;
+    A acc = 0;
+    if (act) {
+        const int32_t sl = i >> S.lc, ii = i - (sl << S.lc);
+        const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
+        for (int32_t k = 0; k < w; ++k) {
+            const int64_t e = base + ((int64_t)k << S.lc);
+            const int32_t j = S.scol[e];
+            if (j < 0) break;                      // padding sits at the end of a row
+            if (j == i) continue;
+            T bv[n], xv[n];
+            load_block_row<n, T>(val + e * nn + r * n, bv);
+            load_x<n, T>(x + (int64_t)j * n, xv);
+#pragma unroll
+            for (int cc = 0; cc < n; ++cc) acc += (A)bv[cc] * (A)xv[cc];
+        }
+    }
+    __shared__ A sres[64 * n];
+    sres[t] = act ? (A)b[(int64_t)i * n + r] - acc : (A)0;
+    __syncthreads();
+    if (act) {
+        const double *Di = Dinv + (int64_t)i * nn + r * n;
+        double z = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < n; ++cc) z += Di[cc] * (double)sres[lr * n + cc];
+        x[(int64_t)i * n + r] = (T)z;
+    }
+}
+
 template <int n, typename T, bool ZERO>
 __global__ __launch_bounds__(64 * n) void k_dilu_fwd(SellView S, const T *__restrict__ val,
                                                      const int32_t *__restrict__ colour, int c,
@@ -865,6 +909,27 @@ void launch_block_apply(int n, int32_t N, const double *Dinv, const double *r, d
     }
     LAUNCHCHK();
 }
+
+template <typename T>
+void launch_gs_colour(int n, const SellView &S, const T *val, const int32_t *rows, int32_t cnt, const double *Dinv,
+                      const T *b, T *x, hipStream_t st) {
+    if (cnt <= 0) return;
+    const dim3 g(cdiv(cnt, 64));
+#define GS_C(NN) hipLaunchKernelGGL((k_gs_colour<NN, T>), g, dim3(64 * NN), 0, st, S, val, rows, cnt, Dinv, b, x)
+    switch (n) {
+        case 1: GS_C(1); break;
+        case 2: GS_C(2); break;
+        case 3: GS_C(3); break;
+        case 4: GS_C(4); break;
+        case 5: GS_C(5); break;
+    }
+#undef GS_C
+    LAUNCHCHK();
+}
+template void launch_gs_colour<double>(int, const SellView &, const double *, const int32_t *, int32_t,
+                                       const double *, const double *, double *, hipStream_t);
+template void launch_gs_colour<float>(int, const SellView &, const float *, const int32_t *, int32_t, const double *,
+                                      const float *, float *, hipStream_t);
 
 template <typename T>
 void launch_dilu_fwd(int n, const SellView &S, const T *val, const int32_t *colour, int c, const int32_t *rows,

@@ -422,8 +422,8 @@ int tail_level_for(const cbs_system *h, size_t tsize) {
     if (lim < 0) return -1;
     for (int l = 1; l < nlev; ++l) {
         if (h->lev[l].N > lim || nlev - l > kTailMax) continue;
-        bool dilu = false;                           // DILU levels keep their own kernels
-        for (int q = l; q + 1 < nlev; ++q) dilu = dilu || h->lev[q].dilu;
+        bool dilu = false;                           // DILU and Gauss-Seidel levels keep their own kernels
+        for (int q = l; q + 1 < nlev; ++q) dilu = dilu || h->lev[q].dilu || h->lev[q].sgs;
         if (dilu) continue;
         // the forward layout is the larger one (scaled levels add a pattern and c)
         const int64_t need = tsize == sizeof(float) ? tail_plan<float>(h, l, false, nullptr)

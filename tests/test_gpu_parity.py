@@ -605,13 +605,16 @@ def _ranks_from_colour(colour):
     return rank
 
 
+@pytest.mark.parametrize("smoother", [P.SMOOTH_DILU, P.SMOOTH_SGS])
 @pytest.mark.parametrize("dilu_levels", [1, 2, -1])
-def test_dilu_vcycle_matches_oracle_given_gpu_hierarchy(dilu_levels):
-    _say("dilu vcycle", dilu_levels)
+def test_dilu_vcycle_matches_oracle_given_gpu_hierarchy(dilu_levels, smoother):
+    """DILU and symmetric Gauss-Seidel V-cycles: the oracle's V-cycle with the
+    GPU's aggregates and colour order (colour first, then row index)."""
+    _say("coloured vcycle", dilu_levels, smoother)
     s = pressure_velocity(10, 9, 8, seed=4)
     A = O.from_system(s)
     with P.System.from_dict(s) as sysm:
-        sysm.setup(precond=P.PREC_AMG, smoother=P.SMOOTH_DILU, dilu_levels=dilu_levels, coarse_max=8,
+        sysm.setup(precond=P.PREC_AMG, smoother=smoother, dilu_levels=dilu_levels, coarse_max=8,
                    pre_sweeps=1, post_sweeps=1, omega=0.8)
         nlev = sysm.info()["levels"]
         lv0 = sysm.get_level(0)
@@ -631,7 +634,8 @@ def test_dilu_vcycle_matches_oracle_given_gpu_hierarchy(dilu_levels):
                 off = rows != col
                 assert np.all(colour[rows[off]] != colour[col[off]])
                 ranks.append(_ranks_from_colour(colour))
-        amg = O.AMG(A0, nu1=1, nu2=1, omega=0.8, aggs=aggs, smoother=O.SMOOTH_DILU, ranks=ranks,
+        amg = O.AMG(A0, nu1=1, nu2=1, omega=0.8, aggs=aggs,
+                    smoother=O.SMOOTH_DILU if smoother == P.SMOOTH_DILU else O.SMOOTH_SGS, ranks=ranks,
                     dilu_levels=ndilu)
         r = np.random.default_rng(0).standard_normal((A.N, 4))
         z = _np(sysm.apply_precond(r))
@@ -640,21 +644,22 @@ def test_dilu_vcycle_matches_oracle_given_gpu_hierarchy(dilu_levels):
     assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
 
 
+@pytest.mark.parametrize("smoother", [P.SMOOTH_DILU, P.SMOOTH_SGS])
 @pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
-def test_dilu_amg_solve_and_transpose(precision):
-    _say("dilu solve", precision)
+def test_dilu_amg_solve_and_transpose(precision, smoother):
+    _say("coloured solve", precision, smoother)
     s = pressure_velocity(16, 16, 16, seed=0)
     A = O.from_system(s)
     xref = _ref_solution(A, s["b"])
     with P.System.from_dict(s) as sysm:
-        sysm.setup(precond=P.PREC_AMG, smoother=P.SMOOTH_DILU, precision=precision, tol=1e-10)
+        sysm.setup(precond=P.PREC_AMG, smoother=smoother, precision=precision, tol=1e-10)
         x, st = sysm.solve(s["b"])
         assert st["status"] == P.OK, st
         _check_solution(A, s["b"], _np(x), xref, tol=1e-10, err=1e-7)
         with P.System.from_dict(s) as bj:
             bj.setup(precond=P.PREC_AMG, smoother=P.SMOOTH_BJACOBI, precision=precision, tol=1e-10)
             _, stb = bj.solve(s["b"])
-        assert st["iterations"] < stb["iterations"]          # DILU smooths better than block Jacobi
+        assert st["iterations"] < stb["iterations"]          # both smooth better than block Jacobi
         c = np.random.default_rng(1).standard_normal((A.N, 4))
         lam, stt = sysm.solve_transpose(c)
         assert stt["status"] == P.OK
