@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
 OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_BREAKDOWN = -1, -2, -3, -4
 
-PREC_NONE, PREC_BJACOBI, PREC_AMG = 0, 1, 2
+PREC_NONE, PREC_BJACOBI, PREC_AMG, PREC_SGS = 0, 1, 2, 3
 SMOOTH_BJACOBI, SMOOTH_DILU, SMOOTH_SGS = 0, 1, 2
 
 
@@ -82,6 +82,9 @@ def _declare(L):
         "orc_amg_create": (vp, [ci, ci, _i32p, _i32p, _f64p, ci, ci, ci, ci, ci, cd,
                                 vp, ci, vp, ci, ci]),
         "orc_amg_free": (None, [vp]),
+        "orc_sgs_prec_create": (vp, [ci, ci, _i32p, _i32p, _f64p, _i32p, ci]),
+        "orc_sgs_prec_free": (None, [vp]),
+        "orc_sgs_prec_apply": (None, [vp, _f64p, _f64p]),
         "orc_amg_levels": (ci, [vp]),
         "orc_amg_level_info": (None, [vp, ci, C.POINTER(ci), C.POINTER(cl)]),
         "orc_amg_apply": (None, [vp, _f64p, _f64p]),
@@ -360,6 +363,30 @@ class AMG:
     def apply(self, r):
         z = np.empty(self.A.N * self.A.n)
         lib().orc_amg_apply(self.h, _c64(r).ravel(), z)
+        return z.reshape(self.A.N, self.A.n)
+
+
+class SGSPrec:
+    """Symmetric block Gauss-Seidel preconditioner (the GMRES + SGS runs of
+    Sec. 4.1): ``sweeps`` symmetric steps from zero in the order of ``rank``
+    (row i is visited at position rank[i] forward and in reverse backward).
+    Pass it as ``amg=`` with ``prec=PREC_SGS`` to the solvers."""
+
+    def __init__(self, A: BCSR, rank, sweeps=1):
+        self.A = A
+        self._rank = _c32(rank)
+        self.h = lib().orc_sgs_prec_create(A.N, A.n, A.row_ptr, A.col, A.vals.ravel(), self._rank, int(sweeps))
+        if not self.h:
+            raise OracleError(ERR_SINGULAR if sweeps >= 1 else ERR_ARG, "sgs_prec_create")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_sgs_prec_free(self.h)
+            self.h = None
+
+    def apply(self, r):
+        z = np.empty(self.A.N * self.A.n)
+        lib().orc_sgs_prec_apply(self.h, _c64(r).ravel(), z)
         return z.reshape(self.A.N, self.A.n)
 
 

@@ -13,10 +13,11 @@
  *     block after block) into block CSR, i.e. the permutation step of
  *     Algorithm amgxFoam and Fig. block_amgx (Sec. 2.3): same pattern, indices
  *     referring to blocks instead of scalars;
- *   - preconditioned Krylov solves of that system (BiCGStab, flexible
- *     GMRES) with block-Jacobi, DILU-smoothed or block-Jacobi-smoothed
- *     aggregation AMG (the solver families named in Sec. 2.3 and used in
- *     Sec. 4.1), plus the transposed solve and the LDU gradient of
+ *   - preconditioned Krylov solves of that system (BiCGStab, flexible and
+ *     right-preconditioned GMRES) with block Jacobi, symmetric block
+ *     Gauss-Seidel, or aggregation AMG smoothed by block Jacobi, DILU or
+ *     symmetric Gauss-Seidel (the solver families named in Sec. 2.3 and used
+ *     in Sec. 4.1), plus the transposed solve and the LDU gradient of
  *     L(x(A, b)).
  *
  * Readings where the paper is silent (each also listed in the design notes):
@@ -844,10 +845,55 @@ void orc_amg_apply(void *h, const double *r, double *z)
 }
 
 /* ------------------------------------------------------------------ */
+/* Symmetric block Gauss-Seidel as the whole preconditioner: the        */
+/* GMRES + SGS configuration of the CRM runs (Sec. 4.1, Fig.            */
+/* CRM_speedup).  z = `sweeps` symmetric steps from z = 0 in the order  */
+/* of rank[].  One step from zero is z = (D+U)^{-1} D (D+L)^{-1} r,     */
+/* with L and U the blocks before and after the row in that order.      */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int N, n, sweeps;
+    const int *rp, *col;
+    const double *val;
+    double *Dinv;
+    int *rank;
+} osgs;
+
+void orc_sgs_prec_free(void *h)
+{
+    osgs *S = (osgs *)h;
+    if (!S) return;
+    free(S->Dinv); free(S->rank); free(S);
+}
+
+/* The pattern and values are borrowed and must outlive the handle; rank is
+ * copied.  NULL on a singular diagonal block or sweeps < 1. */
+void *orc_sgs_prec_create(int N, int n, const int *rp, const int *col, const double *val,
+                          const int *rank, int sweeps)
+{
+    if (sweeps < 1) return NULL;
+    osgs *S = (osgs *)calloc(1, sizeof(osgs));
+    S->N = N; S->n = n; S->sweeps = sweeps; S->rp = rp; S->col = col; S->val = val;
+    S->Dinv = (double *)malloc(sizeof(double) * ((long)N * n * n + 1));
+    S->rank = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
+    memcpy(S->rank, rank, sizeof(int) * N);
+    if (diag_inverse(N, n, rp, col, val, S->Dinv)) { orc_sgs_prec_free(S); return NULL; }
+    return S;
+}
+
+void orc_sgs_prec_apply(void *h, const double *r, double *z)
+{
+    osgs *S = (osgs *)h;
+    memset(z, 0, sizeof(double) * (long)S->N * S->n);
+    for (int k = 0; k < S->sweeps; k++) orc_sgs_sweep(S->N, S->n, S->rp, S->col, S->val, S->Dinv, S->rank, r, z);
+}
+
+/* ------------------------------------------------------------------ */
 /* a12: preconditioned Krylov solvers                                  */
 /* ------------------------------------------------------------------ */
 typedef struct {
-    int kind;          /* 0 identity, 1 block-Jacobi, 2 AMG V-cycle */
+    int kind;          /* 0 identity, 1 block-Jacobi, 2 AMG V-cycle,
+                          3 symmetric Gauss-Seidel (handle in `amg`) */
     int N, n;
     double *Dinv;
     void *amg;
@@ -859,17 +905,20 @@ static void prec_apply(const oprec *P, const double *r, double *z)
     if (P->kind == 0) memcpy(z, r, sizeof(double) * m);
     else if (P->kind == 1) {
         for (int i = 0; i < P->N; i++) blk_mv(P->n, P->Dinv + (long)i * bs, r + (long)i * P->n, z + (long)i * P->n);
-    } else orc_amg_apply(P->amg, r, z);
+    } else if (P->kind == 3) orc_sgs_prec_apply(P->amg, r, z);
+    else orc_amg_apply(P->amg, r, z);
 }
 
 static int prec_init(oprec *P, int kind, void *amg, int N, int n, const int *rp, const int *col, const double *val)
 {
     P->kind = kind; P->N = N; P->n = n; P->Dinv = NULL; P->amg = amg;
+    if (kind < 0 || kind > 3) return ORC_ERR_ARG;
     if (kind == 1) {
         P->Dinv = (double *)malloc(sizeof(double) * ((long)N * n * n + 1));
         if (diag_inverse(N, n, rp, col, val, P->Dinv)) { free(P->Dinv); P->Dinv = NULL; return ORC_ERR_SINGULAR; }
     }
-    if (kind == 2 && !amg) return ORC_ERR_ARG;
+    if ((kind == 2 || kind == 3) && !amg) return ORC_ERR_ARG;
+    if (kind == 3 && (((osgs *)amg)->N != N || ((osgs *)amg)->n != n)) return ORC_ERR_ARG;
     return ORC_OK;
 }
 

@@ -136,3 +136,95 @@ def test_sgs_amg_reaches_tolerance_and_is_exact_on_block_diagonal_levels():
     mg = O.AMG(Ab, nu1=1, nu2=0, smoother=O.SMOOTH_SGS, aggs=[agg], dilu_levels=1)
     b = rng.standard_normal((40, 4))
     assert np.allclose(mg.apply(b), np.linalg.solve(D, b[..., None])[..., 0], rtol=1e-12, atol=1e-13)
+
+
+def _dense_triangles(A, rank):
+    """Dense D, L (blocks of rows visited earlier in rank order) and U."""
+    Ad = A.dense()
+    bi = np.repeat(np.arange(A.N), A.n)
+    same = bi[:, None] == bi[None, :]
+    before = rank[bi][:, None] > rank[bi][None, :]
+    after = rank[bi][:, None] < rank[bi][None, :]
+    return Ad, Ad * same, Ad * before, Ad * after
+
+
+def test_sgs_preconditioner_one_step_closed_form():
+    """One symmetric step from zero: forward z1 = (D+L)^{-1} r, backward
+    z = (D+U)^{-1}(r - L z1) = (D+U)^{-1} D (D+L)^{-1} r."""
+    s = jacobian_box(4, 3, 3, n=3, seed=6)
+    A = O.from_system(s)
+    rank = np.random.default_rng(7).permutation(A.N)
+    r = np.random.default_rng(8).standard_normal((A.N, A.n))
+    z = O.SGSPrec(A, rank, sweeps=1).apply(r)
+    _, D, L, U = _dense_triangles(A, rank)
+    ref = np.linalg.solve(D + U, D @ np.linalg.solve(D + L, r.ravel()))
+    assert np.allclose(z.ravel(), ref, rtol=1e-11, atol=1e-12)
+
+
+def test_sgs_preconditioner_k_steps_are_the_stationary_iteration():
+    """k steps from zero: z_{j+1} = z_j + M^{-1}(r - A z_j), M^{-1} the
+    one-step operator of the closed form."""
+    s = pressure_velocity(4, 3, 3, seed=9)
+    A = O.from_system(s)
+    rank = np.random.default_rng(10).permutation(A.N)
+    r = np.random.default_rng(11).standard_normal((A.N, A.n)).ravel()
+    Ad, D, L, U = _dense_triangles(A, rank)
+
+    def minv(v):
+        return np.linalg.solve(D + U, D @ np.linalg.solve(D + L, v))
+    z = np.zeros_like(r)
+    for k in range(1, 4):
+        z = z + minv(r - Ad @ z)
+        zk = O.SGSPrec(A, rank, sweeps=k).apply(r.reshape(A.N, A.n)).ravel()
+        assert np.allclose(zk, z, rtol=1e-10, atol=1e-11), k
+
+
+def test_sgs_preconditioner_is_symmetric_for_a_symmetric_matrix():
+    """For symmetric A the symmetric step is a symmetric operator:
+    <M^{-1} r1, r2> = <r1, M^{-1} r2> (a one-directional sweep is not)."""
+    s = jacobian_box(4, 4, 3, n=3, seed=12)
+    n = s["n"]
+    sym = dict(s)
+    sym["diag"] = s["diag"] + np.transpose(s["diag"], (0, 2, 1)) + 8 * np.eye(n)
+    sym["lower"] = np.ascontiguousarray(np.transpose(s["upper"], (0, 2, 1)))
+    A = O.from_system(sym)
+    assert np.allclose(A.dense(), A.dense().T)
+    rank = np.random.default_rng(13).permutation(A.N)
+    rng = np.random.default_rng(14)
+    r1, r2 = rng.standard_normal((2, A.N, n))
+    P = O.SGSPrec(A, rank, sweeps=1)
+    lhs, rhs = np.vdot(P.apply(r1), r2), np.vdot(r1, P.apply(r2))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # the forward half alone fails the same test
+    _, D, L, U = _dense_triangles(A, rank)
+    F = np.linalg.inv(D + L)
+    assert abs(np.vdot(F @ r1.ravel(), r2.ravel()) - np.vdot(r1.ravel(), F @ r2.ravel())) > 1e-6
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "fgmres", "gmres"])
+def test_sgs_preconditioned_solvers_match_dense_lu(solver):
+    for s in (jacobian_box(4, 3, 3, seed=15), pressure_velocity(5, 4, 3, seed=15)):
+        A = O.from_system(s)
+        rank = np.random.default_rng(16).permutation(A.N)
+        P = O.SGSPrec(A, rank, sweeps=1)
+        x, st = getattr(O, solver)(A, s["b"], prec=O.PREC_SGS, amg=P, tol=1e-10, maxit=2000)
+        assert st["status"] == O.OK and st["relres"] <= 1e-10
+        Ad = A.dense()
+        xd = np.linalg.solve(Ad, s["b"].ravel())
+        assert np.linalg.norm(x.ravel() - xd) <= 10 * np.linalg.cond(Ad) * 1e-10 * np.linalg.norm(xd)
+        assert abs(O.relres(A, s["b"], x) - st["relres"]) <= 1e-12
+
+
+def test_sgs_preconditioner_exact_on_block_diagonal_and_rejects_bad_input():
+    rng = np.random.default_rng(17)
+    D = rng.standard_normal((7, 4, 4)) + 4 * np.eye(4)
+    A = O.ldu_to_bcsr(7, 4, [], [], D, np.zeros((0, 4, 4)), np.zeros((0, 4, 4)))[0]
+    b = rng.standard_normal((7, 4))
+    P = O.SGSPrec(A, rng.permutation(7))
+    for fn in (O.bicgstab, O.fgmres, O.gmres):
+        x, st = fn(A, b, prec=O.PREC_SGS, amg=P, tol=1e-12)
+        assert st["iterations"] == 1
+    with pytest.raises(O.OracleError):
+        O.gmres(A, b, prec=O.PREC_SGS, amg=None)
+    with pytest.raises(O.OracleError):
+        O.SGSPrec(A, np.arange(7), sweeps=0)
