@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--mesh", type=int, nargs=3, default=[100, 100, 100])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, nargs=3, default=[80, 80, 80])
+    ap.add_argument("--precond", choices=["amg", "sgs"], default="amg",
+                    help="sgs: multicolour symmetric block Gauss-Seidel as the whole preconditioner")
+    ap.add_argument("--max-iter", type=int, default=500)
     ap.add_argument("--smoother", choices=["dilu", "sgs", "bjacobi"], default="bjacobi")
     ap.add_argument("--dilu-levels", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=2)
@@ -228,7 +231,7 @@ def main():
     sysm = P.System(N, n, la, ua, diag, upper, lower)
     nnzb = sysm.info()["nnzb"]
     common = dict(solver={"fgmres": P.SOLVER_FGMRES, "gmres": P.SOLVER_GMRES}.get(args.solver, P.SOLVER_BICGSTAB),
-                  precond=P.PREC_AMG, tol=1e-8, max_iter=500,
+                  precond=P.PREC_SGS if args.precond == "sgs" else P.PREC_AMG, tol=1e-8, max_iter=args.max_iter,
                   smoother={"dilu": P.SMOOTH_DILU, "sgs": P.SMOOTH_SGS}.get(args.smoother, P.SMOOTH_BJACOBI),
                   dilu_levels=args.dilu_levels, pre_sweeps=args.sweeps, post_sweeps=args.sweeps,
                   omega=args.omega, coarse_max=args.coarse_max, match_passes=args.passes,
@@ -333,9 +336,11 @@ def main():
 
     # kernels, each timed alone with HIP events on the library's stream; the
     # roofline kernel is the block-Jacobi sweep, so a run with a coloured
-    # smoother times it on a block-Jacobi hierarchy of the same system
-    sysm.setup(opt_mixed if args.smoother == "bjacobi" else
-               P.default_options(precision=P.PRECISION_MIXED, **dict(common, smoother=P.SMOOTH_BJACOBI)))
+    # smoother or preconditioner times it on a block-Jacobi AMG hierarchy of
+    # the same system
+    sysm.setup(opt_mixed if args.smoother == "bjacobi" and args.precond == "amg" else
+               P.default_options(precision=P.PRECISION_MIXED,
+                                 **dict(common, precond=P.PREC_AMG, smoother=P.SMOOTH_BJACOBI)))
     lv0 = sysm.get_level(0)
     sweep, sweep_fp32 = level_sweep_call(P, torch, dev, sysm, n)
     sweep_ms = timer(sweep)
@@ -384,6 +389,7 @@ def main():
                                "randomly renumbered (N=%d, F=%d, nnzb=%d); mixed AMG-BiCGStab to 1e-8"
                                % (nx, ny, nz, N, F, nnzb),
                    "step": "pack fields + update_values + setup + solve + unpack fields",
+                   "precond": args.precond, "max_iter": args.max_iter,
                    "solver": args.solver, "smoother": args.smoother, "dilu_levels": args.dilu_levels,
                    "sweeps": args.sweeps, "omega": args.omega, "coarse_max": args.coarse_max,
                    "match_passes": args.passes, "row_split": args.row_split,

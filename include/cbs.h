@@ -61,7 +61,13 @@ enum cbs_status {
  * (the same iterates as FGMRES when the preconditioner is a fixed linear
  * operator, with m fewer N*n vectors in device memory). */
 enum { CBS_SOLVER_BICGSTAB = 0, CBS_SOLVER_FGMRES = 1, CBS_SOLVER_GMRES = 2 };
-enum { CBS_PREC_NONE = 0, CBS_PREC_BJACOBI = 1, CBS_PREC_AMG = 2 };
+/* Preconditioners: none; block Jacobi (D^{-1}); the aggregation-AMG V-cycle;
+ * multicolour symmetric block Gauss-Seidel on the whole system, the GMRES +
+ * SGS configuration of the CRM runs (Sec. 4.1): max(1, pre_sweeps) symmetric
+ * steps from z = 0, FP64 whatever the precision option, the colour classes
+ * of a graph colouring of the block pattern in ascending then descending
+ * order.  Colours are computed at cbs_setup (CBS_ERR_ARG beyond 128). */
+enum { CBS_PREC_NONE = 0, CBS_PREC_BJACOBI = 1, CBS_PREC_AMG = 2, CBS_PREC_SGS = 3 };
 /* AMG smoothers (Sec. 2.3): damped block Jacobi; multicolour block DILU;
  * multicolour symmetric block Gauss-Seidel (one step = the colours in order,
  * then in reverse, each row x_i = D_i^{-1} (b_i - sum_{j != i} A_ij x_j)).

@@ -1215,11 +1215,13 @@ void amg_setup(cbs_system *h) {
     pt.mark("level0");
 
     if (!amg) {
-        // block-Jacobi preconditioner: level-0 block inverses only
+        // block Jacobi and symmetric Gauss-Seidel: level-0 block inverses;
+        // Gauss-Seidel also colours level 0
         if (o.precond != CBS_PREC_NONE) {
             L0.Dinv.ensure((size_t)h->N * n * n);
             blockinv_level(h, 0, L0.v64, L0.Dinv.get());
         }
+        if (o.precond == CBS_PREC_SGS) colour_level(h, 0);
         h->lev.resize(1);
         sell_build(L0.N, L0.rp, L0.col, L0.sell, st);
         level_sell(h, L0, false, nullptr);

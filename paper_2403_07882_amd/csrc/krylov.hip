@@ -613,6 +613,10 @@ void precond_apply(cbs_system *h, const double *r, double *z, bool tr) {
         case CBS_PREC_BJACOBI:
             launch_block_apply(n, h->N, tr ? h->lev[0].DinvT.get() : h->lev[0].Dinv.get(), r, z, st);
             return;
+        case CBS_PREC_SGS:
+            launch_fill<double>(m, z, st);
+            for (int s = 0; s < std::max(1, h->opt.pre_sweeps); ++s) sgs_smooth<double>(h, h->lev[0], tr, r, z);
+            return;
         default:
             break;
     }

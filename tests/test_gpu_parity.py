@@ -738,3 +738,72 @@ def test_gmres_matches_oracle_gmres_and_fgmres(precision):
         assert O.relres(O.from_system(sk), sk["b"], xn[co[k]:co[k + 1]]) <= 1e-9 * 1.0001 or k == 1
     assert stats[1]["iterations"] == 0 and np.all(xn[co[1]:co[2]] == 0)
 
+
+
+# ------------------------------------------------------- SGS preconditioner
+@pytest.mark.parametrize("sweeps", [1, 2])
+@pytest.mark.parametrize("n", [4, 5])
+def test_sgs_preconditioner_matches_oracle(n, sweeps):
+    """CBS_PREC_SGS: z = M^{-1} r equals the oracle's symmetric Gauss-Seidel
+    preconditioner in the GPU's colour order (colour first, then row), forward
+    and for the transposed solve (the oracle's on A^T)."""
+    _say("sgs precond n", n, "sweeps", sweeps)
+    s = pressure_velocity(11, 9, 8, seed=60) if n == 4 else jacobian_box(11, 9, 8, seed=61)
+    N = int(s["N"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_SGS, pre_sweeps=sweeps)
+        lv0 = sysm.get_level(0)
+        order = _np(lv0["order"])
+        A0 = O.BCSR(N, n, _np(lv0["row_ptr"]), _np(lv0["col"]), _np(lv0["vals"]))
+        colour = _np(lv0["colour"])
+        rows = np.repeat(np.arange(N), np.diff(A0.row_ptr))
+        off = rows != A0.col
+        assert colour.min() >= 0 and np.all(colour[rows[off]] != colour[A0.col[off]])
+        r = np.random.default_rng(62).standard_normal((N, n))
+        z = _np(sysm.apply_precond(r))
+        zt = _np(sysm.apply_precond(r, transpose=True))
+    rank = _ranks_from_colour(colour)
+    for A, got in ((A0, z), (O.transpose(A0), zt)):
+        zr_int = O.SGSPrec(A, rank, sweeps=sweeps).apply(r[order])
+        zr = np.empty_like(zr_int)
+        zr[order] = zr_int
+        assert np.linalg.norm(got - zr) <= 1e-12 * np.linalg.norm(zr)
+    assert np.linalg.norm(z - zt) > 1e-6 * np.linalg.norm(z)
+
+
+@pytest.mark.parametrize("solver", [P.SOLVER_GMRES, P.SOLVER_FGMRES, P.SOLVER_BICGSTAB])
+def test_sgs_preconditioned_solves_match_oracle(solver):
+    """GMRES + SGS (and FGMRES, BiCGStab): the solution matches the oracle's
+    solve with the same preconditioner to the solution bar, in the oracle's
+    iteration count to within one (GMRES and FGMRES); the transposed solve
+    meets the tolerance; a batch converges system by system."""
+    _say("sgs solve", solver)
+    s = pressure_velocity(12, 10, 9, seed=63)
+    A = O.from_system(s)
+    xref = _ref_solution(A, s["b"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_SGS, solver=solver, restart=20, pre_sweeps=1, tol=1e-10, max_iter=2000)
+        colour = _np(sysm.get_level(0)["colour"])
+        x, st = sysm.solve(s["b"])
+        lam, stt = sysm.solve_transpose(s["b"])
+    assert st["status"] == P.OK and stt["status"] == P.OK, (st, stt)
+    _check_solution(A, s["b"], _np(x), xref, tol=1e-10, err=1e-7)
+    assert O.relres(O.transpose(A), s["b"], _np(lam)) <= 1e-10 * 1.0001
+    name = {P.SOLVER_GMRES: "gmres", P.SOLVER_FGMRES: "fgmres", P.SOLVER_BICGSTAB: "bicgstab"}[solver]
+    kw = {} if solver == P.SOLVER_BICGSTAB else {"restart": 20}
+    xo, so = getattr(O, name)(A, s["b"], prec=O.PREC_SGS, amg=O.SGSPrec(A, _ranks_from_colour(colour)),
+                              tol=1e-10, maxit=2000, **kw)
+    assert so["status"] == O.OK, so
+    if solver != P.SOLVER_BICGSTAB:
+        assert abs(so["iterations"] - st["iterations"]) <= 1, (so, st)
+    systems = [pressure_velocity(6, 5, 4, seed=64), pressure_velocity(4, 4, 3, seed=65),
+               pressure_velocity(7, 3, 3, seed=66)]
+    cat = concat_systems(systems)
+    with P.System.from_dict(cat) as bs:
+        bs.setup(precond=P.PREC_SGS, solver=solver, restart=20, tol=1e-9, max_iter=2000)
+        xb, stats = bs.solve(cat["b"])
+    xn = _np(xb)
+    co = cat["cell_off"]
+    for k, sk in enumerate(systems):
+        assert stats[k]["status"] == P.OK, (k, stats[k])
+        assert O.relres(O.from_system(sk), sk["b"], xn[co[k]:co[k + 1]]) <= 1e-9 * 1.0001
