@@ -25,7 +25,7 @@ OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_BREAKDOWN = -1, -2, -3, -4
 
 PREC_NONE, PREC_BJACOBI, PREC_AMG, PREC_SGS = 0, 1, 2, 3
-SMOOTH_BJACOBI, SMOOTH_DILU, SMOOTH_SGS = 0, 1, 2
+SMOOTH_BJACOBI, SMOOTH_DILU, SMOOTH_SGS, SMOOTH_ILU0 = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -73,6 +73,8 @@ def _declare(L):
         "orc_sgs_sweep": (None, [ci, ci, _i32p, _i32p, _f64p, _f64p, _i32p, _f64p, _f64p]),
         "orc_dilu_setup": (ci, [ci, ci, _i32p, _i32p, _f64p, _i32p, _f64p]),
         "orc_dilu_apply": (None, [ci, ci, _i32p, _i32p, _f64p, _i32p, _f64p, _f64p, _f64p]),
+        "orc_ilu0_setup": (ci, [ci, ci, _i32p, _i32p, _f64p, _i32p, _f64p, _f64p]),
+        "orc_ilu0_apply": (None, [ci, ci, _i32p, _i32p, _f64p, _i32p, _f64p, _f64p, _f64p]),
         "orc_strength": (None, [ci, ci, _i32p, _i32p, _f64p, _f64p]),
         "orc_match": (ci, [ci, _i32p, _i32p, _f64p, _i32p]),
         "orc_rap_count": (cl, [ci, _i32p, _i32p, _i32p, ci, _i32p]),
@@ -273,6 +275,23 @@ def dilu_apply(A: BCSR, rank, Einv, r):
     z = np.empty(A.N * A.n)
     lib().orc_dilu_apply(A.N, A.n, A.row_ptr, A.col, A.vals.ravel(), _c32(rank),
                          _c64(Einv).ravel(), _c64(r).ravel(), z)
+    return z.reshape(A.N, A.n)
+
+
+def ilu0_setup(A: BCSR, rank):
+    """Block ILU(0) in the order of rank: (LU factor in A's pattern, U_ii^{-1})."""
+    LU = np.empty_like(A.vals)
+    Uinv = np.empty((A.N, A.n, A.n))
+    rc = lib().orc_ilu0_setup(A.N, A.n, A.row_ptr, A.col, A.vals.ravel(), _c32(rank), LU.ravel(), Uinv.ravel())
+    if rc < 0:
+        raise OracleError(rc, "ilu0_setup")
+    return LU, Uinv
+
+
+def ilu0_apply(A: BCSR, rank, LU, Uinv, r):
+    z = np.empty(A.N * A.n)
+    lib().orc_ilu0_apply(A.N, A.n, A.row_ptr, A.col, _c64(LU).ravel(), _c32(rank), _c64(Uinv).ravel(),
+                         _c64(r).ravel(), z)
     return z.reshape(A.N, A.n)
 
 

@@ -496,6 +496,90 @@ void orc_dilu_apply(int N, int n, const int *rp, const int *col, const double *v
     free(order);
 }
 
+/* Block ILU(0) for the ordering given by rank[] (the incomplete-LU smoother
+ * among the AMG smoothers of Sec. 2.3): A ~ L U with L unit lower and U upper
+ * in that ordering, both kept to A's block pattern (zero fill-in).  Rows are
+ * factored in rank order; in row i the columns k before i are eliminated in
+ * increasing rank (the IKJ form of Gaussian elimination with every update
+ * outside the pattern dropped):
+ *   L_ik = F_ik U_kk^{-1};   F_ij -= L_ik U_kj  for j in row i, j after k,
+ * where F starts as A and U_kj = F_kj of the already factored row k.
+ * LU receives L_ik in the slots before the diagonal (in rank order) and U_ij
+ * in the others; Uinv the inverses U_ii^{-1}. */
+int orc_ilu0_setup(int N, int n, const int *rp, const int *col, const double *val,
+                   const int *rank, double *LU, double *Uinv)
+{
+    long bs = (long)n * n;
+    memcpy(LU, val, sizeof(double) * (size_t)rp[N] * bs);
+    int *order = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
+    for (int i = 0; i < N; i++) order[rank[i]] = i;
+    int maxlen = 1;
+    for (int i = 0; i < N; i++) if (rp[i + 1] - rp[i] > maxlen) maxlen = rp[i + 1] - rp[i];
+    int *low = (int *)malloc(sizeof(int) * maxlen);
+    double Lik[64], T[64];
+    int rc = ORC_OK;
+    for (int q = 0; q < N && rc == ORC_OK; q++) {
+        int i = order[q];
+        int nl = 0;                                   /* slots of row i before i, by rank */
+        for (int s = rp[i]; s < rp[i + 1]; s++) {
+            if (rank[col[s]] >= rank[i]) continue;
+            int p = nl++;
+            while (p > 0 && rank[col[low[p - 1]]] > rank[col[s]]) { low[p] = low[p - 1]; p--; }
+            low[p] = s;
+        }
+        for (int a = 0; a < nl; a++) {
+            int s = low[a], k = col[s];
+            blk_mm(n, LU + (long)s * bs, Uinv + (long)k * bs, Lik);
+            memcpy(LU + (long)s * bs, Lik, sizeof(double) * bs);
+            for (int t = rp[i]; t < rp[i + 1]; t++) {
+                int j = col[t];
+                if (rank[j] <= rank[k]) continue;
+                long kj = find_slot(rp, col, k, j);
+                if (kj < 0) continue;                 /* fill-in: dropped */
+                blk_mm(n, Lik, LU + kj * bs, T);
+                for (long e = 0; e < bs; e++) LU[(long)t * bs + e] -= T[e];
+            }
+        }
+        long d = find_slot(rp, col, i, i);
+        if (d < 0 || inv_block(n, LU + d * bs, Uinv + (long)i * bs)) rc = ORC_ERR_SINGULAR;
+    }
+    free(low);
+    free(order);
+    return rc;
+}
+
+/* z = (L U)^{-1} r: forward y_i = r_i - sum_{k before i} L_ik y_k, then
+ * backward z_i = U_ii^{-1} (y_i - sum_{j after i} U_ij z_j). */
+void orc_ilu0_apply(int N, int n, const int *rp, const int *col, const double *LU,
+                    const int *rank, const double *Uinv, const double *r, double *z)
+{
+    long bs = (long)n * n;
+    int *order = (int *)malloc(sizeof(int) * (N > 0 ? N : 1));
+    for (int i = 0; i < N; i++) order[rank[i]] = i;
+    double t[8], u[8];
+    for (int q = 0; q < N; q++) {
+        int i = order[q];
+        for (int e = 0; e < n; e++) t[e] = r[(long)i * n + e];
+        for (int s = rp[i]; s < rp[i + 1]; s++) {
+            if (rank[col[s]] >= rank[i]) continue;
+            blk_mv(n, LU + (long)s * bs, z + (long)col[s] * n, u);
+            for (int e = 0; e < n; e++) t[e] -= u[e];
+        }
+        for (int e = 0; e < n; e++) z[(long)i * n + e] = t[e];
+    }
+    for (int q = N - 1; q >= 0; q--) {
+        int i = order[q];
+        for (int e = 0; e < n; e++) t[e] = z[(long)i * n + e];
+        for (int s = rp[i]; s < rp[i + 1]; s++) {
+            if (rank[col[s]] <= rank[i]) continue;
+            blk_mv(n, LU + (long)s * bs, z + (long)col[s] * n, u);
+            for (int e = 0; e < n; e++) t[e] -= u[e];
+        }
+        blk_mv(n, Uinv + (long)i * bs, t, z + (long)i * n);
+    }
+    free(order);
+}
+
 /* ------------------------------------------------------------------ */
 /* a5/a6/a10: aggregation, Galerkin coarse operator, transfers         */
 /* ------------------------------------------------------------------ */
@@ -648,7 +732,8 @@ void orc_prolong_add(int N, int n, const int *agg, const double *e, double *x)
 typedef struct {
     int N; int *rp, *col; double *val;
     double *Dinv;            /* block-Jacobi smoother */
-    int *rank; double *Einv; /* DILU smoother */
+    int *rank; double *Einv; /* DILU smoother (ILU(0): Einv = U_ii^{-1}) */
+    double *LU;              /* ILU(0) factor in the level's pattern */
     int *agg; int nc;        /* map to the next level */
     double *b, *x, *r;
 } olevel;
@@ -662,7 +747,7 @@ typedef struct {
 
 static void free_level(olevel *l)
 {
-    free(l->rp); free(l->col); free(l->val); free(l->Dinv); free(l->rank); free(l->Einv);
+    free(l->rp); free(l->col); free(l->val); free(l->Dinv); free(l->rank); free(l->Einv); free(l->LU);
     free(l->agg); free(l->b); free(l->x); free(l->r);
 }
 
@@ -675,8 +760,8 @@ void orc_amg_free(void *h)
 }
 
 /* Build the hierarchy.  smoother: 0 = damped block Jacobi, 1 = DILU, 2 =
- * symmetric block Gauss-Seidel on the dilu_levels finest levels (all levels
- * when dilu_levels < 0) and damped block Jacobi below them.
+ * symmetric block Gauss-Seidel, 3 = block ILU(0) on the dilu_levels finest
+ * levels (all levels when dilu_levels < 0) and damped block Jacobi below them.
  * If aggs != NULL, level l uses the aggregate map aggs[off_l .. off_l+N_l)
  * (concatenated in level order, n_agg_levels maps in total) instead of its
  * own matching; ranks (same layout, one per row, for the n_rank_levels
@@ -691,7 +776,7 @@ void *orc_amg_create(int N, int n, const int *rp, const int *col, const double *
     oamg *A = (oamg *)calloc(1, sizeof(oamg));
     long bs = (long)n * n;
     A->n = n; A->smoother = smoother; A->nu1 = nu1; A->nu2 = nu2; A->omega = omega;
-    A->dilu_levels = (smoother == 1 || smoother == 2) ? (dilu_levels < 0 ? MAXLEV : dilu_levels) : 0;
+    A->dilu_levels = (smoother >= 1 && smoother <= 3) ? (dilu_levels < 0 ? MAXLEV : dilu_levels) : 0;
     /* level 0: own copy */
     olevel *L0 = &A->L[0];
     L0->N = N;
@@ -772,6 +857,13 @@ void *orc_amg_create(int N, int n, const int *rp, const int *col, const double *
             if (smoother == 2) {           /* symmetric Gauss-Seidel: D^{-1} and the order */
                 c->Dinv = (double *)malloc(sizeof(double) * ((long)c->N * bs + 1));
                 if (diag_inverse(c->N, n, c->rp, c->col, c->val, c->Dinv)) { orc_amg_free(A); return NULL; }
+            } else if (smoother == 3) {    /* ILU(0) */
+                c->Einv = (double *)malloc(sizeof(double) * ((long)c->N * bs + 1));
+                c->LU = (double *)malloc(sizeof(double) * ((long)c->rp[c->N] * bs + 1));
+                if (orc_ilu0_setup(c->N, n, c->rp, c->col, c->val, c->rank, c->LU, c->Einv)) {
+                    orc_amg_free(A);
+                    return NULL;
+                }
             } else {
                 c->Einv = (double *)malloc(sizeof(double) * ((long)c->N * bs + 1));
                 if (orc_dilu_setup(c->N, n, c->rp, c->col, c->val, c->rank, c->Einv)) { orc_amg_free(A); return NULL; }
@@ -809,7 +901,8 @@ static void smooth(oamg *A, olevel *c, const double *b, double *x)
         double *d = (double *)malloc(sizeof(double) * (m + 1));
         orc_spmv_bcsr(c->N, n, c->rp, c->col, c->val, x, c->r);
         for (long k = 0; k < m; k++) c->r[k] = b[k] - c->r[k];
-        orc_dilu_apply(c->N, n, c->rp, c->col, c->val, c->rank, c->Einv, c->r, d);
+        if (c->LU) orc_ilu0_apply(c->N, n, c->rp, c->col, c->LU, c->rank, c->Einv, c->r, d);
+        else orc_dilu_apply(c->N, n, c->rp, c->col, c->val, c->rank, c->Einv, c->r, d);
         for (long k = 0; k < m; k++) x[k] += d[k];
         free(d);
     }

@@ -228,3 +228,16 @@ def test_sgs_preconditioner_exact_on_block_diagonal_and_rejects_bad_input():
         O.gmres(A, b, prec=O.PREC_SGS, amg=None)
     with pytest.raises(O.OracleError):
         O.SGSPrec(A, np.arange(7), sweeps=0)
+
+
+def test_ilu0_amg_reaches_tolerance_on_a_graph_with_fill():
+    from workloads import jacobian_graph
+    s = jacobian_graph(N=400, n=4, hubs=4, hub_degree=20, base_degree=3, seed=30)
+    A = O.from_system(s)
+    its = {}
+    for sm in (O.SMOOTH_BJACOBI, O.SMOOTH_DILU, O.SMOOTH_ILU0):
+        amg = O.AMG(A, coarse_max=16, nu1=1, nu2=1, omega=0.8, smoother=sm, dilu_levels=-1)
+        x, st = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=amg, tol=1e-10, maxit=500)
+        assert st["status"] == O.OK and O.relres(A, s["b"], x) <= 1e-10 * 1.0001
+        its[sm] = st["iterations"]
+    assert its[O.SMOOTH_ILU0] <= its[O.SMOOTH_BJACOBI], its

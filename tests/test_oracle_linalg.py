@@ -196,3 +196,87 @@ def test_dilu_defining_property_diag_of_M_equals_diag_of_A():
     r = np.random.default_rng(2).standard_normal((N, n))
     z = O.dilu_apply(A, rank, Einv, r)
     assert np.allclose(M @ z.ravel(), r.ravel(), rtol=1e-10, atol=1e-11)
+
+
+def _ilu_dense_factors(A, rank, LU):
+    """Dense L (unit lower) and U of the ILU(0) factor, in A's numbering."""
+    n = A.n
+    L = np.eye(A.N * n)
+    U = np.zeros((A.N * n, A.N * n))
+    for i in range(A.N):
+        for s in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            j = A.col[s]
+            blk = (slice(i * n, (i + 1) * n), slice(j * n, (j + 1) * n))
+            if rank[j] < rank[i]:
+                L[blk] = LU[s]
+            else:
+                U[blk] = LU[s]
+    return L, U
+
+
+def _triangle_graph(seed):
+    from workloads import jacobian_graph
+    return jacobian_graph(N=60, n=3, hubs=3, hub_degree=10, base_degree=3, seed=seed)
+
+
+def test_ilu0_defining_property_on_a_graph_with_fill():
+    """ILU(0): (L U)_ij = A_ij at every block (i, j) of A's pattern; the fill
+    it drops makes L U differ from A elsewhere; z = (L U)^{-1} r."""
+    s = _triangle_graph(20)
+    A = O.from_system(s)
+    rank = np.random.default_rng(21).permutation(A.N)
+    LU, Uinv = O.ilu0_setup(A, rank)
+    L, U = _ilu_dense_factors(A, rank, LU)
+    M, Ad = L @ U, A.dense()
+    n = A.n
+    inpat = np.zeros((A.N, A.N), bool)
+    inpat[np.repeat(np.arange(A.N), np.diff(A.row_ptr)), A.col] = True
+    mask = np.kron(inpat, np.ones((n, n), bool))
+    assert np.allclose(M[mask], Ad[mask], rtol=1e-11, atol=1e-11)
+    assert np.abs(M[~mask]).max() > 1e-3                  # dropped fill-in is real
+    for i in range(A.N):
+        assert np.allclose(Uinv[i] @ U[i * n:(i + 1) * n, i * n:(i + 1) * n], np.eye(n), atol=1e-11)
+    r = np.random.default_rng(22).standard_normal((A.N, n))
+    z = O.ilu0_apply(A, rank, LU, Uinv, r)
+    assert np.allclose(z.ravel(), np.linalg.solve(M, r.ravel()), rtol=1e-10, atol=1e-11)
+
+
+def test_ilu0_on_a_full_pattern_is_exact_block_lu():
+    """Every block present: no fill is dropped, so L U = A and one apply solves."""
+    N, n = 6, 3
+    rng = np.random.default_rng(23)
+    pairs = np.array([(i, j) for i in range(N) for j in range(i + 1, N)], np.int32)
+    D = rng.standard_normal((N, n, n)) + 8 * np.eye(n)
+    A = O.ldu_to_bcsr(N, n, pairs[:, 0], pairs[:, 1], D, rng.standard_normal((len(pairs), n, n)),
+                      rng.standard_normal((len(pairs), n, n)))[0]
+    rank = rng.permutation(N)
+    LU, Uinv = O.ilu0_setup(A, rank)
+    L, U = _ilu_dense_factors(A, rank, LU)
+    assert np.allclose(L @ U, A.dense(), rtol=1e-12, atol=1e-12)
+    b = rng.standard_normal((N, n))
+    assert np.allclose(O.ilu0_apply(A, rank, LU, Uinv, b).ravel(), np.linalg.solve(A.dense(), b.ravel()),
+                       rtol=1e-11, atol=1e-12)
+
+
+def test_ilu0_equals_dilu_without_triangles_and_differs_with_them():
+    """Without triangles in the block graph (a hex mesh) no update lands off the
+    diagonal, so ILU(0) keeps A's off-diagonal blocks and its diagonal is the
+    DILU one: the two preconditioners coincide.  With triangles they differ."""
+    for s, same in ((jacobian_box(5, 4, 3, n=3, seed=24), True), (_triangle_graph(25), False)):
+        A = O.from_system(s)
+        rank = np.random.default_rng(26).permutation(A.N)
+        LU, Uinv = O.ilu0_setup(A, rank)
+        Einv = O.dilu_setup(A, rank)
+        r = np.random.default_rng(27).standard_normal((A.N, A.n))
+        zi = O.ilu0_apply(A, rank, LU, Uinv, r)
+        zd = O.dilu_apply(A, rank, Einv, r)
+        err = np.linalg.norm(zi - zd) / np.linalg.norm(zd)
+        assert (err <= 1e-12) if same else (err > 1e-4), err
+
+
+def test_ilu0_singular_pivot_is_reported():
+    N, n = 3, 2
+    D = np.stack([np.eye(n), np.zeros((n, n)), np.eye(n)])
+    A = O.ldu_to_bcsr(N, n, [], [], D, np.zeros((0, n, n)), np.zeros((0, n, n)))[0]
+    with pytest.raises(O.OracleError):
+        O.ilu0_setup(A, np.arange(N))
