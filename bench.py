@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--precond", choices=["amg", "sgs"], default="amg",
                     help="sgs: multicolour symmetric block Gauss-Seidel as the whole preconditioner")
     ap.add_argument("--max-iter", type=int, default=500)
-    ap.add_argument("--smoother", choices=["dilu", "sgs", "bjacobi"], default="bjacobi")
+    ap.add_argument("--smoother", choices=["dilu", "sgs", "ilu0", "bjacobi"], default="bjacobi")
     ap.add_argument("--dilu-levels", type=int, default=2)
     ap.add_argument("--sweeps", type=int, default=2)
     ap.add_argument("--omega", type=float, default=0.9)
@@ -232,7 +232,7 @@ def main():
     nnzb = sysm.info()["nnzb"]
     common = dict(solver={"fgmres": P.SOLVER_FGMRES, "gmres": P.SOLVER_GMRES}.get(args.solver, P.SOLVER_BICGSTAB),
                   precond=P.PREC_SGS if args.precond == "sgs" else P.PREC_AMG, tol=1e-8, max_iter=args.max_iter,
-                  smoother={"dilu": P.SMOOTH_DILU, "sgs": P.SMOOTH_SGS}.get(args.smoother, P.SMOOTH_BJACOBI),
+                  smoother={"dilu": P.SMOOTH_DILU, "sgs": P.SMOOTH_SGS, "ilu0": P.SMOOTH_ILU0}.get(args.smoother, P.SMOOTH_BJACOBI),
                   dilu_levels=args.dilu_levels, pre_sweeps=args.sweeps, post_sweeps=args.sweeps,
                   omega=args.omega, coarse_max=args.coarse_max, match_passes=args.passes,
                   row_split=args.row_split, tail_rows=args.tail_rows)

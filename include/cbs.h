@@ -70,9 +70,13 @@ enum { CBS_SOLVER_BICGSTAB = 0, CBS_SOLVER_FGMRES = 1, CBS_SOLVER_GMRES = 2 };
 enum { CBS_PREC_NONE = 0, CBS_PREC_BJACOBI = 1, CBS_PREC_AMG = 2, CBS_PREC_SGS = 3 };
 /* AMG smoothers (Sec. 2.3): damped block Jacobi; multicolour block DILU;
  * multicolour symmetric block Gauss-Seidel (one step = the colours in order,
- * then in reverse, each row x_i = D_i^{-1} (b_i - sum_{j != i} A_ij x_j)).
- * DILU and Gauss-Seidel run on the dilu_levels finest levels. */
-enum { CBS_SMOOTH_BJACOBI = 0, CBS_SMOOTH_DILU = 1, CBS_SMOOTH_SGS = 2 };
+ * then in reverse, each row x_i = D_i^{-1} (b_i - sum_{j != i} A_ij x_j));
+ * multicolour block ILU(0) (the incomplete-LU smoother: A ~ L U in the
+ * colour order, no fill outside A's block pattern; one step
+ * x += (L U)^{-1} (b - A x)).  On a block graph without triangles (a hex
+ * mesh) ILU(0) and DILU are the same preconditioner.  DILU, Gauss-Seidel and
+ * ILU(0) run on the dilu_levels finest levels. */
+enum { CBS_SMOOTH_BJACOBI = 0, CBS_SMOOTH_DILU = 1, CBS_SMOOTH_SGS = 2, CBS_SMOOTH_ILU0 = 3 };
 enum { CBS_PRECISION_FP64 = 0, CBS_PRECISION_MIXED = 1 };
 
 /* Solver options (the "linear solver options" of Algorithm amgxFoam).
@@ -103,7 +107,7 @@ typedef struct cbs_options {
                                 gathers cache-local on irregularly numbered
                                 meshes; inputs and outputs keep the caller's
                                 numbering                            [1] */
-    int32_t dilu_levels;     /* smoother DILU or SGS: the dilu_levels finest
+    int32_t dilu_levels;     /* smoother DILU, SGS or ILU0: the dilu_levels finest
                                 levels use it, coarser ones damped block
                                 Jacobi; < 0 = every level            [2] */
     int32_t row_split;       /* block-row kernels on levels of fewer than

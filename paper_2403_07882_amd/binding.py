@@ -22,7 +22,7 @@ ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_BREAKDOWN = -1, -2, -3, -4
 ERR_NONFINITE, ERR_STATE, ERR_OOM, ERR_HIP = -5, -6, -7, -8
 SOLVER_BICGSTAB, SOLVER_FGMRES, SOLVER_GMRES = 0, 1, 2
 PREC_NONE, PREC_BJACOBI, PREC_AMG, PREC_SGS = 0, 1, 2, 3
-SMOOTH_BJACOBI, SMOOTH_DILU, SMOOTH_SGS = 0, 1, 2
+SMOOTH_BJACOBI, SMOOTH_DILU, SMOOTH_SGS, SMOOTH_ILU0 = 0, 1, 2, 3
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 LEVEL_SWEEP, LEVEL_RESIDUAL = 0, 1
 

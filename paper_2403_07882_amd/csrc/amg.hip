@@ -849,6 +849,82 @@ __global__ void k_dilu_setup(const int32_t *rows, int32_t cnt, int c, const int3
         for (int cc = 0; cc < n; ++cc) out[r * n + cc] = ok ? E[r][n + cc] : 0.0;
 }
 
+// Block ILU(0), rows of colour c (earlier colours are factored): the order is
+// colour first, then row index.  F holds A's pattern; on entry row i holds
+// A_i*, on exit the unscaled factor: F_ik = L_ik U_kk before the diagonal,
+// U_ij from it on, so that M = L U = (E + F_lower) E^{-1} (E + F_upper) with
+// E = diag(U).  The lower neighbours k are eliminated in increasing order:
+// F_ij -= F_ik E_k^{-1} F_kj for every j of row i after k that row k holds
+// (updates outside the pattern are dropped).  Row i is written only by its
+// own thread; rows of earlier colours are final and only read.
+template <int n>
+__global__ void k_ilu_setup(const int32_t *rows, int32_t cnt, int c, const int32_t *rp, const int32_t *col,
+                            const int32_t *dslot, const int32_t *colour, double *F, double *Einv, int32_t *bad) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= cnt) return;
+    constexpr int nn = n * n;
+    const int32_t i = rows[q];
+    const int32_t b = rp[i], e = rp[i + 1];
+    int32_t pc = -1, pj = -1;                      // last eliminated (colour, row)
+    for (;;) {
+        int32_t ks = -1, kc = 0, kk = 0;
+        for (int32_t s = b; s < e; ++s) {          // next lower neighbour in order
+            const int32_t j = col[s], cj = colour[j];
+            if (cj >= c || cj < pc || (cj == pc && j <= pj)) continue;
+            if (ks < 0 || cj < kc || (cj == kc && j < kk)) { ks = s; kc = cj; kk = j; }
+        }
+        if (ks < 0) break;
+        pc = kc; pj = kk;
+        double Lk[n][n];                           // F_ik E_k^{-1}
+        const double *Fik = F + (int64_t)ks * nn, *Ek = Einv + (int64_t)kk * nn;
+#pragma unroll
+        for (int r = 0; r < n; ++r)
+#pragma unroll
+            for (int cc = 0; cc < n; ++cc) {
+                double a = 0.0;
+#pragma unroll
+                for (int m = 0; m < n; ++m) a += Fik[r * n + m] * Ek[m * n + cc];
+                Lk[r][cc] = a;
+            }
+        const int32_t kb = rp[kk], ke = rp[kk + 1];
+        for (int32_t t = b; t < e; ++t) {
+            const int32_t j = col[t], cj = colour[j];
+            if (cj < kc || (cj == kc && j <= kk)) continue;     // j not after k
+            int32_t kj = -1;
+            for (int32_t u = kb; u < ke; ++u)
+                if (col[u] == j) { kj = u; break; }
+            if (kj < 0) continue;
+            const double *Fkj = F + (int64_t)kj * nn;
+            double *Fij = F + (int64_t)t * nn;
+#pragma unroll
+            for (int r = 0; r < n; ++r)
+#pragma unroll
+                for (int cc = 0; cc < n; ++cc) {
+                    double a = 0.0;
+#pragma unroll
+                    for (int m = 0; m < n; ++m) a += Lk[r][m] * Fkj[m * n + cc];
+                    Fij[r * n + cc] -= a;
+                }
+        }
+    }
+    double E[n][2 * n];
+    const double *Fii = F + (int64_t)dslot[i] * nn;
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+#pragma unroll
+        for (int cc = 0; cc < n; ++cc) {
+            E[r][cc] = Fii[r * n + cc];
+            E[r][n + cc] = (r == cc) ? 1.0 : 0.0;
+        }
+    const bool ok = gj_inverse<n>(E);
+    if (!ok) atomicMin(bad, i);
+    double *out = Einv + (int64_t)i * nn;
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+#pragma unroll
+        for (int cc = 0; cc < n; ++cc) out[r * n + cc] = ok ? E[r][n + cc] : 0.0;
+}
+
 }  // namespace
 
 // ====================================================================== host
@@ -903,6 +979,13 @@ void dilu_setup_n(const int32_t *rows, int32_t cnt, int c, const int32_t *rp, co
     if (cnt > 0)
         hipLaunchKernelGGL(k_dilu_setup<n>, dim3(cdiv(cnt, 128)), dim3(128), 0, st, rows, cnt, c, rp, col, mirror, dslot,
                            val, colour, Einv, bad);
+}
+template <int n>
+void ilu_setup_n(const int32_t *rows, int32_t cnt, int c, const int32_t *rp, const int32_t *col, const int32_t *dslot,
+                 const int32_t *colour, double *F, double *Einv, int32_t *bad, hipStream_t st) {
+    if (cnt > 0)
+        hipLaunchKernelGGL(k_ilu_setup<n>, dim3(cdiv(cnt, 64)), dim3(64), 0, st, rows, cnt, c, rp, col, dslot, colour,
+                           F, Einv, bad);
 }
 template <int n>
 void gather_blocks_n(int64_t nb, const int32_t *sk, const double *in, double *out, hipStream_t st) {
@@ -1126,6 +1209,29 @@ void dilu_factor_level(cbs_system *h, int l) {
                                         std::to_string(bad));
 }
 
+// Block ILU(0) of level l, colour after colour (FP64): the factor F in the
+// level's BCSR pattern and E^{-1} in Einv.
+void ilu_factor_level(cbs_system *h, int l) {
+    hipStream_t st = h->stream;
+    Level &L = h->lev[l];
+    const int n = h->n;
+    L.Einv.ensure((size_t)L.N * n * n);
+    L.iluF.ensure((size_t)L.nnzb * n * n > 0 ? (size_t)L.nnzb * n * n : 1);
+    HIPCHK(hipMemcpyAsync(L.iluF.get(), L.v64, sizeof(double) * (size_t)L.nnzb * n * n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0x7f, sizeof(int32_t), st));
+    const int ncol = (int)L.colour_off.size() - 1;
+    for (int c = 0; c < ncol; ++c) {
+        const int32_t b0 = L.colour_off[c], cnt = L.colour_off[c + 1] - b0;
+        NSWITCH(n, ilu_setup_n, L.rows_by_colour.get() + b0, cnt, c, L.rp, L.col, L.dslot, L.colour.get(),
+                L.iluF.get(), L.Einv.get(), h->dflag.get(), st);
+    }
+    LAUNCHCHK();
+    const int32_t bad = read_int(h->dflag.get(), st);
+    if (bad != 0x7f7f7f7f)
+        cbs_throw(CBS_ERR_SINGULAR, "singular ILU(0) pivot at level " + std::to_string(l) + ", block row " +
+                                        std::to_string(bad));
+}
+
 // Values of the level's sliced copy (its pattern is built beforehand).
 // f32flag: where the FP32 copy reports values it cannot hold (mixed only)
 void level_sell(cbs_system *h, Level &L, bool mixed, int32_t *f32flag) {
@@ -1300,7 +1406,7 @@ void amg_setup(cbs_system *h) {
     // (and level 0), the off-diagonal one of the mixed block-Jacobi levels;
     // new patterns share one read-back of their entry counts
     auto level_uses_dilu = [&](int q) {
-        return (o.smoother == CBS_SMOOTH_DILU || o.smoother == CBS_SMOOTH_SGS) &&
+        return (o.smoother == CBS_SMOOTH_DILU || o.smoother == CBS_SMOOTH_SGS || o.smoother == CBS_SMOOTH_ILU0) &&
                (o.dilu_levels < 0 || q < o.dilu_levels) && q + 1 < nlev;
     };
     {
@@ -1337,11 +1443,15 @@ void amg_setup(cbs_system *h) {
     for (int q = 0; q < nlev; ++q) {
         Level &L = h->lev[q];
         nz_sum += L.nnzb;
-        const bool coloured = level_uses_dilu(q);   // DILU or symmetric Gauss-Seidel
-        L.dilu = q + 1 < nlev && coloured && o.smoother == CBS_SMOOTH_DILU;
+        const bool coloured = level_uses_dilu(q);   // DILU, symmetric Gauss-Seidel or ILU(0)
+        // ILU(0) runs the DILU sweeps on its own factor: it carries both flags
+        L.dilu = q + 1 < nlev && coloured && (o.smoother == CBS_SMOOTH_DILU || o.smoother == CBS_SMOOTH_ILU0);
+        L.ilu = L.dilu && o.smoother == CBS_SMOOTH_ILU0;
         L.sgs = q + 1 < nlev && coloured && o.smoother == CBS_SMOOTH_SGS;
         if (q + 1 < nlev && coloured && (!reuse || !L.colour.get())) colour_level(h, q);
-        if (L.dilu) {
+        if (L.ilu) {
+            ilu_factor_level(h, q);
+        } else if (L.dilu) {
             dilu_factor_level(h, q);
         } else if (q + 1 < nlev) {                  // block Jacobi and Gauss-Seidel: D^{-1}
             L.Dinv.ensure((size_t)L.N * n * n);
@@ -1349,6 +1459,14 @@ void amg_setup(cbs_system *h) {
         }
         pt.mark("smoother" + std::to_string(q));
         if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, deferred);
+        if (L.ilu) {
+            const size_t tot = (size_t)L.sell.nent * n * n;
+            L.iluS64.ensure(tot > 0 ? tot : 1);
+            if (mixed) L.iluS32.ensure(tot > 0 ? tot : 1);
+            sell_fill(n, L.sell, L.iluF.get(), L.iluS64.get(), st, mixed ? L.iluS32.get() : nullptr, deferred);
+        } else {
+            L.iluF.release(); L.iluS64.release(); L.iluS32.release(); L.iluS64T.release(); L.iluS32T.release();
+        }
         L.scaled = mixed && q + 1 < nlev && !L.dilu && !L.sgs;
         L.scaledT = false;
         if (L.scaled) {
@@ -1456,6 +1574,16 @@ void amg_build_transposed(cbs_system *h) {
             // DILU of A^T in the same ordering has E' = E^T
             L.EinvT.ensure((size_t)L.N * n * n);
             NSWITCH(n, transpose_n, (int64_t)L.N, nullptr, L.Einv.get(), L.EinvT.get(), st);
+        }
+        if (L.ilu && L.sell.soff.get()) {
+            // ILU(0) of A^T in the same ordering: M^T = (E^T + F_upper^T) E^{-T}
+            // (E^T + F_lower^T) matches A^T on the pattern, so F' = F^T blockwise
+            const size_t nb = (size_t)L.nnzb * n * n, tot = (size_t)L.sell.nent * n * n;
+            DArr<double> FT(nb > 0 ? nb : 1);
+            NSWITCH(n, transpose_n, L.nnzb, L.mirror, L.iluF.get(), FT.get(), st);
+            L.iluS64T.ensure(tot > 0 ? tot : 1);
+            if (mixed) L.iluS32T.ensure(tot > 0 ? tot : 1);
+            sell_fill(n, L.sell, FT.get(), L.iluS64T.get(), st, mixed ? L.iluS32T.get() : nullptr, h->dflag.get());
         }
         if (mixed && L.scaled) {
             // row-scaled off-diagonal values of A^T: D_i^{-T} (A^T)_ij, j != i

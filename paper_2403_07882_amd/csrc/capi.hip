@@ -286,8 +286,7 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
         require(o.solver == CBS_SOLVER_BICGSTAB || o.solver == CBS_SOLVER_FGMRES || o.solver == CBS_SOLVER_GMRES,
                 CBS_ERR_ARG, "unknown solver");
         require(o.precond >= CBS_PREC_NONE && o.precond <= CBS_PREC_SGS, CBS_ERR_ARG, "unknown preconditioner");
-        require(o.smoother == CBS_SMOOTH_BJACOBI || o.smoother == CBS_SMOOTH_DILU || o.smoother == CBS_SMOOTH_SGS,
-                CBS_ERR_ARG, "unknown smoother");
+        require(o.smoother >= CBS_SMOOTH_BJACOBI && o.smoother <= CBS_SMOOTH_ILU0, CBS_ERR_ARG, "unknown smoother");
         require(o.precision == CBS_PRECISION_FP64 || o.precision == CBS_PRECISION_MIXED, CBS_ERR_ARG,
                 "unknown precision");
         require(o.restart >= 1 && o.restart <= 200, CBS_ERR_ARG, "restart must be in 1..200");

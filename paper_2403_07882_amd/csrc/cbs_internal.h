@@ -168,6 +168,12 @@ struct Level {
     bool dilu = false;
     // symmetric block Gauss-Seidel over the same colour classes (with Dinv)
     bool sgs = false;
+    // block ILU(0) (dilu is set too): the unscaled factor F in the BCSR
+    // pattern, its sliced copies (FP64, FP32 when mixed) and those of F^T;
+    // Einv holds diag(U)^{-1}
+    bool ilu = false;
+    DArr<double> iluF, iluS64, iluS64T;
+    DArr<float> iluS32, iluS32T;
     DArr<int32_t> colour, rows_by_colour;
     std::vector<int32_t> colour_off;     // host, ncolours + 1
     DArr<double> Einv, EinvT;
@@ -345,8 +351,9 @@ void launch_gs_colour(int n, const SellView &S, const T *val, const int32_t *row
 // DILU colour sweeps on the rows rows[0..cnt): forward y = E^{-1}(b - A x - L y)
 // (zero_guess: A x omitted), backward z = y - E^{-1} U z, x = x + z
 template <typename T>
-void launch_dilu_fwd(int n, const SellView &S, const T *val, const int32_t *colour, int c, const int32_t *rows,
-                     int32_t cnt, const double *Einv, const T *b, const T *x, T *y, bool zero_guess, hipStream_t st);
+void launch_dilu_fwd(int n, const SellView &S, const T *val, const T *fval, const int32_t *colour, int c,
+                     const int32_t *rows, int32_t cnt, const double *Einv, const T *b, const T *x, T *y,
+                     bool zero_guess, hipStream_t st);
 template <typename T>
 void launch_dilu_bwd(int n, const SellView &S, const T *val, const int32_t *colour, int c, const int32_t *rows,
                      int32_t cnt, const double *Einv, T *yz, T *x, bool zero_guess, hipStream_t st);

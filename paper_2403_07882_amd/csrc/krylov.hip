@@ -442,19 +442,29 @@ const double *level_vals<double>(Level &L, bool tr) { return tr ? L.sell.v64T.ge
 template <>
 const float *level_vals<float>(Level &L, bool tr) { return tr ? L.sell.v32T.get() : L.sell.v32.get(); }
 
-// One DILU smoothing step x <- x + M^{-1}(b - A x) (zero_guess: x <- M^{-1} b).
+template <typename T>
+const T *ilu_vals(Level &L, bool tr);
+template <>
+const double *ilu_vals<double>(Level &L, bool tr) { return tr ? L.iluS64T.get() : L.iluS64.get(); }
+template <>
+const float *ilu_vals<float>(Level &L, bool tr) { return tr ? L.iluS32T.get() : L.iluS32.get(); }
+
+// One DILU or block ILU(0) smoothing step x <- x + M^{-1}(b - A x)
+// (zero_guess: x <- M^{-1} b).  Both have M = (E + L) E^{-1} (E + U): DILU
+// with A's own off-diagonal blocks, ILU(0) with those of its factor.
 template <typename T>
 void dilu_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x, bool zero_guess) {
     const T *val = level_vals<T>(L, tr);
+    const T *fv = L.ilu ? ilu_vals<T>(L, tr) : nullptr;
     const double *Einv = tr ? L.EinvT.get() : L.Einv.get();
     T *y = vptr<T>(L.vt);
     const int ncol = (int)L.colour_off.size() - 1;
     const SellView S = L.sell.view(sizeof(T) == 4);
     for (int c = 0; c < ncol; ++c)
-        launch_dilu_fwd<T>(h->n, S, val, L.colour.get(), c, L.rows_by_colour.get() + L.colour_off[c],
+        launch_dilu_fwd<T>(h->n, S, val, fv, L.colour.get(), c, L.rows_by_colour.get() + L.colour_off[c],
                            L.colour_off[c + 1] - L.colour_off[c], Einv, b, x, y, zero_guess, h->stream);
     for (int c = ncol - 1; c >= 0; --c)
-        launch_dilu_bwd<T>(h->n, S, val, L.colour.get(), c, L.rows_by_colour.get() + L.colour_off[c],
+        launch_dilu_bwd<T>(h->n, S, fv ? fv : val, L.colour.get(), c, L.rows_by_colour.get() + L.colour_off[c],
                            L.colour_off[c + 1] - L.colour_off[c], Einv, y, x, zero_guess, h->stream);
 }
 

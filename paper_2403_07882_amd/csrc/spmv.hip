@@ -369,8 +369,11 @@ __global__ __launch_bounds__(64 * n) void k_gs_colour(SellView S, const T *__res
     }
 }
 
+// fval: the lower-triangle values when they differ from val (block ILU(0):
+// val = A for the residual, fval = its factor), else nullptr
 template <int n, typename T, bool ZERO>
 __global__ __launch_bounds__(64 * n) void k_dilu_fwd(SellView S, const T *__restrict__ val,
+                                                     const T *__restrict__ fval,
                                                      const int32_t *__restrict__ colour, int c,
                                                      const int32_t *__restrict__ rows, int32_t cnt,
                                                      const double *__restrict__ Einv, const T *__restrict__ b,
@@ -401,6 +404,7 @@ __global__ __launch_bounds__(64 * n) void k_dilu_fwd(SellView S, const T *__rest
             if (colour[j] < c) {
                 T yv[n];
                 load_x<n, T>(y + (int64_t)j * n, yv);
+                if (fval) load_block_row<n, T>(fval + e * nn + r * n, bv);
 #pragma unroll
                 for (int cc = 0; cc < n; ++cc) ay += (A)bv[cc] * (A)yv[cc];
             }
@@ -932,15 +936,22 @@ template void launch_gs_colour<float>(int, const SellView &, const float *, cons
                                       const float *, float *, hipStream_t);
 
 template <typename T>
-void launch_dilu_fwd(int n, const SellView &S, const T *val, const int32_t *colour, int c, const int32_t *rows,
-                     int32_t cnt, const double *Einv, const T *b, const T *x, T *y, bool zero_guess, hipStream_t st) {
+void launch_dilu_fwd(int n, const SellView &S, const T *val, const T *fval, const int32_t *colour, int c,
+                     const int32_t *rows, int32_t cnt, const double *Einv, const T *b, const T *x, T *y,
+                     bool zero_guess, hipStream_t st) {
     if (cnt <= 0) return;
     const dim3 g(cdiv(cnt, 64));
+    if (zero_guess && fval) {                  // no residual: only the factor is read
+        val = fval;
+        fval = nullptr;
+    }
 #define DILU_F(NN)                                                                                              \
     if (zero_guess)                                                                                             \
-        hipLaunchKernelGGL((k_dilu_fwd<NN, T, true>), g, dim3(64 * NN), 0, st, S, val, colour, c, rows, cnt, Einv, b, x, y); \
+        hipLaunchKernelGGL((k_dilu_fwd<NN, T, true>), g, dim3(64 * NN), 0, st, S, val, fval, colour, c, rows, cnt, \
+                           Einv, b, x, y);                                                                      \
     else                                                                                                        \
-        hipLaunchKernelGGL((k_dilu_fwd<NN, T, false>), g, dim3(64 * NN), 0, st, S, val, colour, c, rows, cnt, Einv, b, x, y);
+        hipLaunchKernelGGL((k_dilu_fwd<NN, T, false>), g, dim3(64 * NN), 0, st, S, val, fval, colour, c, rows, cnt, \
+                           Einv, b, x, y);
     switch (n) {
         case 1: DILU_F(1) break;
         case 2: DILU_F(2) break;
@@ -973,11 +984,12 @@ void launch_dilu_bwd(int n, const SellView &S, const T *val, const int32_t *colo
     LAUNCHCHK();
 }
 
-template void launch_dilu_fwd<double>(int, const SellView &, const double *, const int32_t *, int, const int32_t *,
-                                      int32_t, const double *, const double *, const double *, double *, bool,
-                                      hipStream_t);
-template void launch_dilu_fwd<float>(int, const SellView &, const float *, const int32_t *, int, const int32_t *,
-                                     int32_t, const double *, const float *, const float *, float *, bool, hipStream_t);
+template void launch_dilu_fwd<double>(int, const SellView &, const double *, const double *, const int32_t *, int,
+                                      const int32_t *, int32_t, const double *, const double *, const double *,
+                                      double *, bool, hipStream_t);
+template void launch_dilu_fwd<float>(int, const SellView &, const float *, const float *, const int32_t *, int,
+                                     const int32_t *, int32_t, const double *, const float *, const float *, float *,
+                                     bool, hipStream_t);
 template void launch_dilu_bwd<double>(int, const SellView &, const double *, const int32_t *, int, const int32_t *,
                                       int32_t, const double *, double *, double *, bool, hipStream_t);
 template void launch_dilu_bwd<float>(int, const SellView &, const float *, const int32_t *, int, const int32_t *,

@@ -573,7 +573,7 @@ def test_batched_fgmres_and_zero_system():
     assert O.relres(O.from_system(systems[0]), systems[0]["b"], xn[:cat["cell_off"][1]]) <= 1e-9
 
 
-@pytest.mark.parametrize("smoother", [P.SMOOTH_BJACOBI, P.SMOOTH_DILU])
+@pytest.mark.parametrize("smoother", [P.SMOOTH_BJACOBI, P.SMOOTH_DILU, P.SMOOTH_ILU0])
 def test_batched_mixed_uneven_pressure_velocity(smoother):
     """A batch of p-U systems of uneven sizes, mixed precision, both smoothers:
     every system meets its tolerance; the transposed batch solve too."""
@@ -605,13 +605,24 @@ def _ranks_from_colour(colour):
     return rank
 
 
-@pytest.mark.parametrize("smoother", [P.SMOOTH_DILU, P.SMOOTH_SGS])
+_ORACLE_SMOOTHER = {P.SMOOTH_DILU: O.SMOOTH_DILU, P.SMOOTH_SGS: O.SMOOTH_SGS, P.SMOOTH_ILU0: O.SMOOTH_ILU0}
+
+
+@pytest.mark.parametrize("smoother", [P.SMOOTH_DILU, P.SMOOTH_SGS, P.SMOOTH_ILU0])
 @pytest.mark.parametrize("dilu_levels", [1, 2, -1])
 def test_dilu_vcycle_matches_oracle_given_gpu_hierarchy(dilu_levels, smoother):
-    """DILU and symmetric Gauss-Seidel V-cycles: the oracle's V-cycle with the
-    GPU's aggregates and colour order (colour first, then row index)."""
+    """DILU, symmetric Gauss-Seidel and ILU(0) V-cycles: the oracle's V-cycle
+    with the GPU's aggregates and colour order (colour first, then row index).
+    On the hex mesh ILU(0) equals DILU on level 0; the coarse levels (and the
+    graph case below) have triangles, where the two differ."""
+    _coloured_vcycle_case(pressure_velocity(10, 9, 8, seed=4), dilu_levels, smoother)
+
+
+def _coloured_vcycle_case(s, dilu_levels, smoother):
+    """Checks the GPU V-cycle against the oracle's; for ILU(0) returns the
+    relative distance of the oracle's ILU(0) cycle from its DILU cycle."""
     _say("coloured vcycle", dilu_levels, smoother)
-    s = pressure_velocity(10, 9, 8, seed=4)
+    n = int(s["n"])
     A = O.from_system(s)
     with P.System.from_dict(s) as sysm:
         sysm.setup(precond=P.PREC_AMG, smoother=smoother, dilu_levels=dilu_levels, coarse_max=8,
@@ -619,7 +630,7 @@ def test_dilu_vcycle_matches_oracle_given_gpu_hierarchy(dilu_levels, smoother):
         nlev = sysm.info()["levels"]
         lv0 = sysm.get_level(0)
         order = _np(lv0["order"])
-        A0 = O.BCSR(A.N, 4, _np(lv0["row_ptr"]), _np(lv0["col"]), _np(lv0["vals"]))
+        A0 = O.BCSR(A.N, n, _np(lv0["row_ptr"]), _np(lv0["col"]), _np(lv0["vals"]))
         aggs, ranks = [], []
         ndilu = nlev - 1 if dilu_levels < 0 else min(dilu_levels, nlev - 1)
         for l in range(nlev - 1):
@@ -634,17 +645,59 @@ def test_dilu_vcycle_matches_oracle_given_gpu_hierarchy(dilu_levels, smoother):
                 off = rows != col
                 assert np.all(colour[rows[off]] != colour[col[off]])
                 ranks.append(_ranks_from_colour(colour))
-        amg = O.AMG(A0, nu1=1, nu2=1, omega=0.8, aggs=aggs,
-                    smoother=O.SMOOTH_DILU if smoother == P.SMOOTH_DILU else O.SMOOTH_SGS, ranks=ranks,
+        amg = O.AMG(A0, nu1=1, nu2=1, omega=0.8, aggs=aggs, smoother=_ORACLE_SMOOTHER[smoother], ranks=ranks,
                     dilu_levels=ndilu)
-        r = np.random.default_rng(0).standard_normal((A.N, 4))
+        r = np.random.default_rng(0).standard_normal((A.N, n))
         z = _np(sysm.apply_precond(r))
     zr_int = amg.apply(r[order])
     zr = np.empty_like(zr_int); zr[order] = zr_int
     assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+    if smoother == P.SMOOTH_ILU0:        # the same cycle with DILU is a different operator
+        zd = O.AMG(A0, nu1=1, nu2=1, omega=0.8, aggs=aggs, smoother=O.SMOOTH_DILU, ranks=ranks,
+                   dilu_levels=ndilu).apply(r[order])
+        return np.linalg.norm(zd - zr_int) / np.linalg.norm(zr_int)
+    return None
 
 
-@pytest.mark.parametrize("smoother", [P.SMOOTH_DILU, P.SMOOTH_SGS])
+def test_ilu0_vcycle_on_a_graph_with_triangles():
+    """Block ILU(0) on every level of a random-graph system (rows of up to
+    50+ blocks, many triangles): the GPU cycle matches the oracle's, which
+    differs from the DILU cycle there."""
+    from workloads import jacobian_graph
+    s = jacobian_graph(N=2000, n=4, hubs=6, hub_degree=40, base_degree=4, seed=70)
+    d = _coloured_vcycle_case(s, -1, P.SMOOTH_ILU0)
+    assert d > 1e-6, d                  # 1e5 times the parity tolerance
+
+
+@pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
+def test_ilu0_transposed_vcycle_is_the_ilu0_of_the_transpose(precision):
+    """The transposed solve's ILU(0) levels use F^T blockwise: the cycle
+    equals the oracle's V-cycle built on A^T with the same aggregates and
+    colour order, where the oracle factors A^T itself."""
+    from workloads import jacobian_graph
+    _say("ilu0 transposed vcycle", precision)
+    s = jacobian_graph(N=1500, n=4, hubs=5, hub_degree=30, base_degree=4, seed=71)
+    N = int(s["N"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, smoother=P.SMOOTH_ILU0, dilu_levels=-1, precision=precision,
+                   coarse_max=8, pre_sweeps=1, post_sweeps=1, omega=0.8)
+        nlev = sysm.info()["levels"]
+        lv0 = sysm.get_level(0)
+        order = _np(lv0["order"])
+        A0 = O.BCSR(N, 4, _np(lv0["row_ptr"]), _np(lv0["col"]), _np(lv0["vals"]))
+        aggs = [_np(sysm.get_level(l)["agg"]) for l in range(nlev - 1)]
+        ranks = [_ranks_from_colour(_np(sysm.get_level(l)["colour"])) for l in range(nlev - 1)]
+        r = np.random.default_rng(72).standard_normal((N, 4))
+        zt = _np(sysm.apply_precond(r, transpose=True))
+    amg = O.AMG(O.transpose(A0), nu1=1, nu2=1, omega=0.8, aggs=aggs, smoother=O.SMOOTH_ILU0, ranks=ranks,
+                dilu_levels=nlev - 1)
+    zr_int = amg.apply(r[order])
+    zr = np.empty_like(zr_int); zr[order] = zr_int
+    tol = 1e-11 if precision == P.PRECISION_FP64 else 1e-5
+    assert np.linalg.norm(zt - zr) <= tol * np.linalg.norm(zr)
+
+
+@pytest.mark.parametrize("smoother", [P.SMOOTH_DILU, P.SMOOTH_SGS, P.SMOOTH_ILU0])
 @pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
 def test_dilu_amg_solve_and_transpose(precision, smoother):
     _say("coloured solve", precision, smoother)
@@ -659,7 +712,7 @@ def test_dilu_amg_solve_and_transpose(precision, smoother):
         with P.System.from_dict(s) as bj:
             bj.setup(precond=P.PREC_AMG, smoother=P.SMOOTH_BJACOBI, precision=precision, tol=1e-10)
             _, stb = bj.solve(s["b"])
-        assert st["iterations"] < stb["iterations"]          # both smooth better than block Jacobi
+        assert st["iterations"] < stb["iterations"]          # each coloured smoother beats block Jacobi
         c = np.random.default_rng(1).standard_normal((A.N, 4))
         lam, stt = sysm.solve_transpose(c)
         assert stt["status"] == P.OK
