@@ -97,6 +97,9 @@ def _declare(L):
         "orc_gmres": (ci, [ci, ci, _i32p, _i32p, _f64p, ci, vp, _f64p, _f64p, cd, ci, ci,
                            C.POINTER(ci), C.POINTER(cd)]),
         "orc_grad": (None, [ci, ci, ci, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p]),
+        "orc_euler_jac": (None, [_f64p, _f64p, cd, _f64p]),
+        "orc_roe_radius": (cd, [_f64p, _f64p, _f64p, cd]),
+        "orc_luo_assemble": (None, [ci, ci, _i32p, _i32p, _f64p, _f64p, vp, vp, cd, _f64p, _f64p, _f64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -431,6 +434,34 @@ def fgmres(A: BCSR, b, x0=None, prec=PREC_BJACOBI, amg=None, tol=1e-8, maxit=100
 def gmres(A: BCSR, b, x0=None, prec=PREC_BJACOBI, amg=None, tol=1e-8, maxit=1000, restart=30):
     """Right-preconditioned (non-flexible) GMRES(restart)."""
     return _solve(lib().orc_gmres, A, b, x0, prec, amg, tol, maxit, (int(restart),))
+
+
+def euler_jac(Q, s, gamma=1.4):
+    J = np.empty(25)
+    lib().orc_euler_jac(_c64(Q).ravel(), _c64(s).ravel(), float(gamma), J)
+    return J.reshape(5, 5)
+
+
+def roe_radius(QL, QR, s, gamma=1.4):
+    return lib().orc_roe_radius(_c64(QL).ravel(), _c64(QR).ravel(), _c64(s).ravel(), float(gamma))
+
+
+def luo_assemble(d, with_visc=True, with_dt=True):
+    """LDU blocks of the density-based coupled matrix from ``luo_inputs``."""
+    N, F = d["N"], d["F"]
+    diag = np.empty((N, 5, 5)); upper = np.empty((max(F, 1), 5, 5)); lower = np.empty((max(F, 1), 5, 5))
+    la, ua = _c32(d["lower_addr"]), _c32(d["upper_addr"])
+    Sf = _c64(d["Sf"]).reshape(-1)
+    if F == 0:
+        la = ua = np.zeros(1, np.int32); Sf = np.zeros(3)
+    lv = _c64(d["lam_visc"]) if with_visc else None
+    vd = _c64(d["v_dt"]) if with_dt else None
+    lib().orc_luo_assemble(N, F, la, ua, _c64(d["Q"]).ravel(), Sf,
+                           lv.ctypes.data if lv is not None else None,
+                           vd.ctypes.data if vd is not None else None,
+                           float(d["gamma"]), diag.ravel(), upper.ravel(), lower.ravel())
+    return {"N": N, "F": F, "n": 5, "lower_addr": d["lower_addr"], "upper_addr": d["upper_addr"],
+            "diag": diag, "upper": upper[:F], "lower": lower[:F]}
 
 
 def grad(s, lam, x):

@@ -13,6 +13,9 @@
  *     block after block) into block CSR, i.e. the permutation step of
  *     Algorithm amgxFoam and Fig. block_amgx (Sec. 2.3): same pattern, indices
  *     referring to blocks instead of scalars;
+ *   - the assembly of the density-based system of Eq. (discretBackward)
+ *     with the approximate Jacobian of Eqs. (approxJac1, approxJac2),
+ *     face by face into LDU form (Sec. 2.1);
  *   - preconditioned Krylov solves of that system (BiCGStab, flexible and
  *     right-preconditioned GMRES) with block Jacobi, symmetric block
  *     Gauss-Seidel, or aggregation AMG smoothed by block Jacobi, DILU or
@@ -1272,4 +1275,89 @@ void orc_grad(int N, int F, int n, const int *la, const int *ua,
                 gupper[(long)f * bs + r * n + c] = -lam[(long)la[f] * n + r] * x[(long)ua[f] * n + c];
                 glower[(long)f * bs + r * n + c] = -lam[(long)ua[f] * n + r] * x[(long)la[f] * n + c];
             }
+}
+
+/* ------------------------------------------------------------------ */
+/* Assembly of the density-based coupled matrix (Sec. 2.1)             */
+/* ------------------------------------------------------------------ */
+/* Convective flux Jacobian J(Q, s) = d(F(Q) . s)/dQ of the Euler equations
+ * for the conservative state Q = (rho, rho u, rho v, rho w, rho E) of an
+ * ideal gas with ratio gamma, s an area vector (J is linear in s).  Row-major
+ * 5 x 5.  Written from F.s = (rho V, rho u V + p s_x, rho v V + p s_y,
+ * rho w V + p s_z, (rho E + p) V), V = u . s, p = (gamma-1)(rho E - rho|u|^2/2). */
+void orc_euler_jac(const double *Q, const double *s, double gamma, double *J)
+{
+    double rho = Q[0], vel[3] = {Q[1] / rho, Q[2] / rho, Q[3] / rho};
+    double q2 = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2];
+    double g1 = gamma - 1.0, p = g1 * (Q[4] - 0.5 * rho * q2), H = (Q[4] + p) / rho;
+    double V = vel[0] * s[0] + vel[1] * s[1] + vel[2] * s[2];
+    /* dp/dQ */
+    double dp[5] = {0.5 * g1 * q2, -g1 * vel[0], -g1 * vel[1], -g1 * vel[2], g1};
+    /* dV/dQ: V = (rho u . s) / rho */
+    double dV[5] = {-V / rho, s[0] / rho, s[1] / rho, s[2] / rho, 0.0};
+    /* mass: d(rho V) */
+    J[0] = 0.0; J[1] = s[0]; J[2] = s[1]; J[3] = s[2]; J[4] = 0.0;
+    /* momentum k: d((rho u_k) V + p s_k) = V e_{k+1} + (rho u_k) dV + s_k dp */
+    for (int k = 0; k < 3; k++)
+        for (int c = 0; c < 5; c++)
+            J[(k + 1) * 5 + c] = (c == k + 1 ? V : 0.0) + Q[k + 1] * dV[c] + s[k] * dp[c];
+    /* energy: d((rho E + p) V) = V (e_4 + dp) + (rho E + p) dV */
+    for (int c = 0; c < 5; c++) J[20 + c] = V * ((c == 4 ? 1.0 : 0.0) + dp[c]) + rho * H * dV[c];
+}
+
+/* Convective spectral radius of the Roe-averaged state on a face with area
+ * vector s: |u~ . s| + c~ |s|, with Roe averages (weights sqrt(rho)) of the
+ * velocity and the total enthalpy and c~^2 = (gamma-1)(H~ - |u~|^2/2). */
+double orc_roe_radius(const double *QL, const double *QR, const double *s, double gamma)
+{
+    double g1 = gamma - 1.0, wl = sqrt(QL[0]), wr = sqrt(QR[0]);
+    double u[3], q2 = 0.0, un = 0.0, HL, HR;
+    for (int k = 0; k < 3; k++) {
+        u[k] = (QL[k + 1] / wl + QR[k + 1] / wr) / (wl + wr);
+        q2 += u[k] * u[k];
+        un += u[k] * s[k];
+    }
+    {
+        double ql = (QL[1] * QL[1] + QL[2] * QL[2] + QL[3] * QL[3]) / QL[0];
+        double qr = (QR[1] * QR[1] + QR[2] * QR[2] + QR[3] * QR[3]) / QR[0];
+        HL = (QL[4] + g1 * (QL[4] - 0.5 * ql)) / QL[0];
+        HR = (QR[4] + g1 * (QR[4] - 0.5 * qr)) / QR[0];
+    }
+    double H = (wl * HL + wr * HR) / (wl + wr);
+    double c = sqrt(g1 * (H - 0.5 * q2));
+    return fabs(un) + c * sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+}
+
+/* The coupled matrix [V/dtau I - dR/dQ] of Eq. (discretBackward) with the
+ * approximate Jacobian of Eqs. (approxJac1, approxJac2), accumulated face by
+ * face into LDU form (5 x 5 row-major blocks).  Face f has owner l =
+ * lower_addr[f], neighbour u = upper_addr[f] and area vector Sf[f] pointing
+ * from l to u; its radius is S lambda = roe_radius(Q_l, Q_u, Sf) + |Sf|
+ * lam_visc[f].  Row l takes the face with normal n, row u with -n (the
+ * residual is antisymmetric in the normal), J being linear in it:
+ *   A_ll += (J(Q_l, s) + S lambda I)/2,   A_lu += (J(Q_u, s) - S lambda I)/2,
+ *   A_uu += (-J(Q_u, s) + S lambda I)/2,  A_ul += (-J(Q_l, s) - S lambda I)/2.
+ * diag starts at v_dt[i] I (NULL: 0); lam_visc NULL: 0. */
+void orc_luo_assemble(int N, int F, const int *la, const int *ua, const double *Q, const double *Sf,
+                      const double *lam_visc, const double *v_dt, double gamma,
+                      double *diag, double *upper, double *lower)
+{
+    for (int i = 0; i < N; i++)
+        for (int e = 0; e < 25; e++) diag[(long)i * 25 + e] = (e % 6 == 0) ? (v_dt ? v_dt[i] : 0.0) : 0.0;
+    double JL[25], JU[25];
+    for (int f = 0; f < F; f++) {
+        int l = la[f], u = ua[f];
+        const double *s = Sf + (long)f * 3;
+        double S = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        double lam = orc_roe_radius(Q + (long)l * 5, Q + (long)u * 5, s, gamma) + (lam_visc ? S * lam_visc[f] : 0.0);
+        orc_euler_jac(Q + (long)l * 5, s, gamma, JL);
+        orc_euler_jac(Q + (long)u * 5, s, gamma, JU);
+        for (int e = 0; e < 25; e++) {
+            double d = (e % 6 == 0) ? lam : 0.0;
+            diag[(long)l * 25 + e] += 0.5 * (JL[e] + d);
+            upper[(long)f * 25 + e] = 0.5 * (JU[e] - d);
+            diag[(long)u * 25 + e] += 0.5 * (-JU[e] + d);
+            lower[(long)f * 25 + e] = 0.5 * (-JL[e] - d);
+        }
+    }
 }

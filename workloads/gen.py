@@ -34,6 +34,7 @@ import numpy as np
 __all__ = [
     "box_faces", "jacobian_box", "jacobian_stretched", "pressure_velocity",
     "batch_sizes", "jacobian_batch", "concat_systems", "stretched_spacing", "jacobian_graph",
+    "luo_inputs",
 ]
 
 
@@ -456,3 +457,60 @@ def jacobian_graph(N=3000, n=4, hubs=12, hub_degree=48, base_degree=4, seed=0, s
                  {"kind": "jacobian_graph", "N": N, "hubs": hubs, "hub_degree": hub_degree,
                   "base_degree": base_degree, "seed": seed, "sigma": sigma})
 
+
+
+def luo_inputs(nx=20, ny=20, nz=20, seed=0, jitter=0.2, gamma=1.4, mach=0.5, cfl=10.0, uniform=False):
+    """Inputs of the GPU assembly of the density-based coupled matrix: a
+    jittered hex box of nx*ny*nz cells (unit spacing h = 1/nz), its internal
+    faces in ``box_faces`` order with area vectors S_f n_f pointing from the
+    owner (lower id) to the neighbour, a conservative state Q = (rho, rho u,
+    rho v, rho w, rho E) per cell, a viscous spectral radius per unit area
+    per face and V/dtau per cell.  Only geometry and states: no Jacobian.
+
+    State: rho ~ U(0.8, 1.2), p ~ U(0.8, 1.2)/gamma, velocity = free stream
+    (mach, 0.2 mach, 0.1 mach) + N(0, (0.1 mach)^2) per component (all
+    cells equal to the first draw when ``uniform``); rho E = p/(gamma-1) +
+    rho |u|^2 / 2.  lam_visc ~ U(0, 0.05); V/dtau = h^2 (|u| + c) / cfl with
+    cfl ~ U(0.5, 2) * cfl per cell.
+
+    Draw order from ``default_rng(seed)``: node jitter U(-jitter h, jitter h)
+    for every node (applied to interior nodes only), rho, p, velocity
+    perturbation, lam_visc, the cfl factors.
+    """
+    N = nx * ny * nz
+    h = 1.0 / nz
+    rng = np.random.default_rng(seed)
+    g = [np.arange(m + 1) * h for m in (nx, ny, nz)]
+    X = np.stack(np.meshgrid(*g, indexing="ij"), axis=-1)          # (nx+1, ny+1, nz+1, 3)
+    jit = rng.uniform(-jitter * h, jitter * h, size=X.shape)
+    interior = np.zeros(X.shape[:3], bool)
+    interior[1:-1, 1:-1, 1:-1] = True
+    X = X + jit * interior[..., None]
+    Xk = np.transpose(X, (2, 1, 0, 3))                               # [k, j, i, 3]
+    la, ua, dr = box_faces(nx, ny, nz)
+    S = []
+    if nx > 1:   # x faces at node plane i+1 between cells i and i+1, order [k, j, i]
+        q = (Xk[:-1, :-1, 1:-1], Xk[:-1, 1:, 1:-1], Xk[1:, 1:, 1:-1], Xk[1:, :-1, 1:-1])
+        S.append(_quad_area(*q)[0].reshape(-1, 3))
+    if ny > 1:
+        q = (Xk[:-1, 1:-1, :-1], Xk[1:, 1:-1, :-1], Xk[1:, 1:-1, 1:], Xk[:-1, 1:-1, 1:])
+        S.append(_quad_area(*q)[0].reshape(-1, 3))
+    if nz > 1:
+        q = (Xk[1:-1, :-1, :-1], Xk[1:-1, :-1, 1:], Xk[1:-1, 1:, 1:], Xk[1:-1, 1:, :-1])
+        S.append(_quad_area(*q)[0].reshape(-1, 3))
+    Sf = np.concatenate(S) if S else np.zeros((0, 3))
+    rho = rng.uniform(0.8, 1.2, N)
+    p = rng.uniform(0.8, 1.2, N) / gamma
+    vel = np.array([1.0, 0.2, 0.1]) * mach + rng.normal(0.0, 0.1 * mach, (N, 3))
+    if uniform:
+        rho[:] = rho[0]; p[:] = p[0]; vel[:] = vel[0]
+    lam_visc = rng.uniform(0.0, 0.05, la.size)
+    cfl_c = cfl * rng.uniform(0.5, 2.0, N)
+    Q = np.empty((N, 5))
+    Q[:, 0] = rho
+    Q[:, 1:4] = rho[:, None] * vel
+    Q[:, 4] = p / (gamma - 1.0) + 0.5 * rho * (vel ** 2).sum(1)
+    c = np.sqrt(gamma * p / rho)
+    v_dt = h * h * (np.linalg.norm(vel, axis=1) + c) / cfl_c
+    return {"N": N, "F": int(la.size), "n": 5, "lower_addr": la, "upper_addr": ua, "Q": Q, "Sf": Sf,
+            "lam_visc": lam_visc, "v_dt": v_dt, "gamma": float(gamma), "h": h}
