@@ -166,10 +166,35 @@ int cbs_create_batch_from_ldu(cbs_handle *out /* host */, int32_t n_sys,
                               const double *diag, const double *upper, const double *lower,
                               void *stream);
 
-/* Replace the coefficients, same pattern (Algorithm amgxFoam: "replace the
- * old matrix coefficients").  Invalidates the preconditioner: call
- * cbs_setup again (reuse_aggregates = 1 keeps the coarsening). */
+/* Replace the coefficients, same pattern (the coefficient-replacement step of
+ * Algorithm amgxFoam).  Invalidates the preconditioner: call cbs_setup again
+ * (reuse_aggregates = 1 keeps the coarsening). */
 int cbs_update_values(cbs_handle h, const double *diag, const double *upper, const double *lower);
+
+/* Assemble the density-based coupled matrix on the device, straight into the
+ * handle's block-CSR values: V/dtau I - dR/dQ of Eq. (discretBackward) with
+ * the approximate Jacobian of Eqs. (approxJac1, approxJac2), Sec. 2.1.  Takes
+ * the place of cbs_update_values (same pattern, same follow-up: cbs_setup).
+ * Block size 5, unknowns (rho, rho u, rho v, rho w, rho E).
+ *   Q[N*5]        conservative state per cell (device)
+ *   Sf[F*3]       face area vectors S_f n_f, pointing from lower_addr[f]
+ *                 (row of the upper block) to upper_addr[f] (device)
+ *   lam_visc[F]   viscous spectral radius per unit area, added to the
+ *                 convective radius of the Roe-averaged face state (device;
+ *                 NULL = 0)
+ *   v_dt[N]       V/dtau per cell, added to the diagonal (device; NULL = 0)
+ *   gamma         ratio of specific heats (> 1)
+ * Face f with owner l, neighbour u, s = Sf[f], S lambda = |u~.s| + c~|s| +
+ * |s| lam_visc[f] (Roe averages, c~^2 = (gamma-1)(H~ - |u~|^2/2)):
+ *   A_ll += (J(Q_l, s) + S lambda I)/2,   A_lu = (J(Q_u, s) - S lambda I)/2,
+ *   A_uu += (-J(Q_u, s) + S lambda I)/2,  A_ul = (-J(Q_l, s) - S lambda I)/2,
+ * J(Q, s) the Euler convective flux Jacobian d(F(Q).s)/dQ of an ideal gas.
+ * Interior faces only: boundary contributions belong in v_dt or come from
+ * cbs_update_values.  Batched handles take the concatenated cells and faces.
+ * Errors: CBS_ERR_ARG (bdim != 5, NULL Q, NULL Sf with faces, gamma <= 1),
+ * CBS_ERR_NONFINITE (a state with non-positive density or pressure). */
+int cbs_assemble_luo(cbs_handle h, const double *Q, const double *Sf, const double *lam_visc, const double *v_dt,
+                     double gamma);
 
 /* Build the preconditioner: block-diagonal inverses (FP64), and for AMG the
  * pairwise-matching aggregation, Galerkin coarse operators P^T A P with

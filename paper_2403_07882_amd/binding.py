@@ -60,6 +60,7 @@ SIGNATURES = [
     ("cbs_create_batch_from_ldu", C.c_int, [C.POINTER(_VP), _I32, C.POINTER(_I64), C.POINTER(_I64), _I32,
                                             _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cbs_update_values", C.c_int, [_VP, _VP, _VP, _VP]),
+    ("cbs_assemble_luo", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_double]),
     ("cbs_setup", C.c_int, [_VP, C.POINTER(Options)]),
     ("cbs_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
     ("cbs_solve_transpose", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
@@ -230,6 +231,16 @@ class System:
         torch = _torch()
         d, u, lo = (_dev(a, torch.float64) for a in (diag, upper, lower))
         _check(lib().cbs_update_values(self.h, _ptr(d), _ptr(u), _ptr(lo)), "cbs_update_values")
+
+    def assemble_luo(self, Q, Sf, lam_visc=None, v_dt=None, gamma=1.4):
+        """Assemble the density-based coupled matrix on the device from cell
+        states and face area vectors (cbs_assemble_luo); then call setup."""
+        torch = _torch()
+        q, s = _dev(Q, torch.float64), _dev(Sf, torch.float64)
+        lv = _dev(lam_visc, torch.float64) if lam_visc is not None else None
+        vd = _dev(v_dt, torch.float64) if v_dt is not None else None
+        _check(lib().cbs_assemble_luo(self.h, _ptr(q), _ptr(s), None if lv is None else _ptr(lv),
+                                      None if vd is None else _ptr(vd), float(gamma)), "cbs_assemble_luo")
 
     def setup(self, options: Optional[Options] = None, **kw):
         o = options if options is not None else default_options(**kw)

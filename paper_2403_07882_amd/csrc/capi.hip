@@ -277,6 +277,28 @@ int cbs_update_values(cbs_handle h, const double *diag, const double *upper, con
     });
 }
 
+int cbs_assemble_luo(cbs_handle h, const double *Q, const double *Sf, const double *lam_visc, const double *v_dt,
+                     double gamma) {
+    return guarded([&] {
+        require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        set_alloc_stream(h->stream);
+        require(h->n == 5, CBS_ERR_ARG, "the density-based assembly needs 5 x 5 blocks");
+        require(Q != nullptr && (h->F == 0 || Sf != nullptr), CBS_ERR_ARG, "state or face arrays are NULL");
+        require(gamma > 1.0, CBS_ERR_ARG, "gamma must exceed 1");
+        HIPCHK(hipEventRecord(h->ev0, h->stream));
+        assemble_luo(h, Q, Sf, lam_visc, v_dt, gamma);
+        HIPCHK(hipEventRecord(h->ev1, h->stream));
+        h->t_convert_ms = elapsed_ms(h->ev0, h->ev1);
+        h->values_changed = true;
+        h->transposed_ready = false;
+        h->valsT.release();
+        h->usell.v64.release();
+        h->usell.v64T.release();
+        invalidate_graphs(h);
+        return CBS_OK;
+    });
+}
+
 int cbs_setup(cbs_handle h, const cbs_options *opt) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");

@@ -273,6 +273,8 @@ void read_array(const int32_t *dptr, int32_t count, int32_t *out, hipStream_t st
 // conversion (convert.hip)
 void convert_pattern(cbs_system *h);
 void convert_values(cbs_system *h, const double *diag, const double *upper, const double *lower);
+void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double *lam_visc, const double *v_dt,
+                  double gamma);
 void check_finite(const double *a, int64_t count, int32_t *dflag, hipStream_t st);
 void pack_fields(int32_t N, int32_t n, const double *soa, double *aos, hipStream_t st);
 void unpack_fields(int32_t N, int32_t n, const double *aos, double *soa, hipStream_t st);

@@ -270,6 +270,105 @@ __global__ void k_values(int64_t total, int32_t N, int32_t F, const int32_t *src
     if (bad) atomicOr(flag, 4);
 }
 
+// ------------------------------------------------------------------ assembly
+// Row r of the Euler convective flux Jacobian d(F(Q) . s)/dQ for the
+// conservative state Q = (rho, rho u, rho v, rho w, rho E) of an ideal gas
+// (ratio g); s is an area vector and the Jacobian is linear in it.
+__device__ inline void euler_jac_row(const double *Q, double sx, double sy, double sz, double g, int r,
+                                     double out[5]) {
+    const double rho = Q[0], u = Q[1] / rho, v = Q[2] / rho, w = Q[3] / rho;
+    const double g1 = g - 1.0, q2 = u * u + v * v + w * w;
+    const double p = g1 * (Q[4] - 0.5 * rho * q2), H = (Q[4] + p) / rho, phi = 0.5 * g1 * q2;
+    const double V = u * sx + v * sy + w * sz;
+    if (r == 0) {
+        out[0] = 0.0; out[1] = sx; out[2] = sy; out[3] = sz; out[4] = 0.0;
+    } else if (r < 4) {
+        const double uk = r == 1 ? u : (r == 2 ? v : w), sk = r == 1 ? sx : (r == 2 ? sy : sz);
+        out[0] = phi * sk - uk * V;
+        out[1] = uk * sx - g1 * u * sk + (r == 1 ? V : 0.0);
+        out[2] = uk * sy - g1 * v * sk + (r == 2 ? V : 0.0);
+        out[3] = uk * sz - g1 * w * sk + (r == 3 ? V : 0.0);
+        out[4] = g1 * sk;
+    } else {
+        out[0] = V * (phi - H);
+        out[1] = H * sx - g1 * u * V;
+        out[2] = H * sy - g1 * v * V;
+        out[3] = H * sz - g1 * w * V;
+        out[4] = g * V;
+    }
+}
+
+// S lambda of a face: the convective spectral radius of the Roe-averaged
+// state, |u~ . s| + c~ |s|, plus |s| times the viscous radius per unit area.
+// Always evaluated with the owner state first, so both rows of a face see
+// the same value.
+__device__ inline double face_radius(const double *QL, const double *QR, const double *s, double lamv, double g) {
+    const double g1 = g - 1.0, al = sqrt(QL[0]), ar = sqrt(QR[0]), wsum = al + ar;
+    const double ul = QL[1] / QL[0], vl = QL[2] / QL[0], wl = QL[3] / QL[0];
+    const double ur = QR[1] / QR[0], vr = QR[2] / QR[0], wr = QR[3] / QR[0];
+    const double Hl = (QL[4] + g1 * (QL[4] - 0.5 * QL[0] * (ul * ul + vl * vl + wl * wl))) / QL[0];
+    const double Hr = (QR[4] + g1 * (QR[4] - 0.5 * QR[0] * (ur * ur + vr * vr + wr * wr))) / QR[0];
+    const double u = (al * ul + ar * ur) / wsum, v = (al * vl + ar * vr) / wsum, w = (al * wl + ar * wr) / wsum;
+    const double H = (al * Hl + ar * Hr) / wsum;
+    const double c = sqrt(g1 * (H - 0.5 * (u * u + v * v + w * w)));
+    const double S = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    return fabs(u * s[0] + v * s[1] + w * s[2]) + c * S + lamv * S;
+}
+
+// The density-based coupled matrix V/dtau I - dR/dQ with the approximate
+// Jacobian, written straight into block CSR: one thread per (slot, block
+// row r), five values each.  An upper slot (row = owner l, column = u) is
+// (J(Q_u, s) - S lambda I)/2, a lower slot (row = u, column = l) is
+// (J(Q_l, -s) - S lambda I)/2, and the diagonal of cell i is
+// v_dt_i I + (J(Q_i, sum of its outward face vectors) + sum of its S lambda I)/2
+// (J is linear in s, so the faces' Jacobians at Q_i add up to one).
+__global__ void k_assemble_luo(int64_t nnzb, int32_t N, int32_t F, const int32_t *rp, const int32_t *src,
+                               const int32_t *la, const int32_t *ua, const double *Q, const double *Sf,
+                               const double *lamv, const double *vdt, double g, double *vals, int32_t *flag) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnzb * 5) return;
+    const int64_t k = t / 5;
+    const int r = (int)(t - k * 5);
+    const int32_t s = src[k];
+    double out[5];
+    if (s >= N) {
+        const bool up = s < N + F;
+        const int32_t f = up ? s - N : s - N - F;
+        const int32_t l = la[f], u = ua[f];
+        const double *sf = Sf + (int64_t)f * 3;
+        const double lam = face_radius(Q + (int64_t)l * 5, Q + (int64_t)u * 5, sf, lamv ? lamv[f] : 0.0, g);
+        const double sg = up ? 1.0 : -1.0;
+        euler_jac_row(Q + (int64_t)(up ? u : l) * 5, sg * sf[0], sg * sf[1], sg * sf[2], g, r, out);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] - (c == r ? lam : 0.0));
+    } else {
+        const int32_t i = s;
+        double nx = 0.0, ny = 0.0, nz = 0.0, lsum = 0.0;
+        for (int32_t k2 = rp[i]; k2 < rp[i + 1]; ++k2) {
+            const int32_t s2 = src[k2];
+            if (s2 < N) continue;
+            const bool up = s2 < N + F;
+            const int32_t f = up ? s2 - N : s2 - N - F;
+            const double *sf = Sf + (int64_t)f * 3;
+            const double sg = up ? 1.0 : -1.0;
+            nx += sg * sf[0]; ny += sg * sf[1]; nz += sg * sf[2];
+            lsum += face_radius(Q + (int64_t)la[f] * 5, Q + (int64_t)ua[f] * 5, sf, lamv ? lamv[f] : 0.0, g);
+        }
+        euler_jac_row(Q + (int64_t)i * 5, nx, ny, nz, g, r, out);
+        const double dt = vdt ? vdt[i] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] + (c == r ? lsum : 0.0)) + (c == r ? dt : 0.0);
+    }
+    bool bad = false;
+    double *o = vals + k * 25 + r * 5;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        bad = bad || !isfinite(out[c]);
+        o[c] = out[c];
+    }
+    if (bad) atomicOr(flag, 4);
+}
+
 __global__ void k_check_finite(const double *a, int64_t count, int32_t *flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count && !isfinite(a[i])) atomicOr(flag, 4);
@@ -364,6 +463,22 @@ void convert_values(cbs_system *h, const double *diag, const double *upper, cons
     }
     LAUNCHCHK();
     if (read_int(h->dflag.get(), st) & 4) cbs_throw(CBS_ERR_NONFINITE, "non-finite matrix coefficient");
+}
+
+void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double *lam_visc, const double *v_dt,
+                  double gamma) {
+    hipStream_t st = h->stream;
+    h->vals.ensure((size_t)h->nnzb * 25);
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+    const int64_t nthr = h->nnzb * 5;
+    if (nthr > 0)
+        hipLaunchKernelGGL(k_assemble_luo, dim3(cdiv(nthr, 256)), dim3(256), 0, st, h->nnzb, h->N, h->F, h->rp.get(),
+                           h->src.get(), h->la.get(), h->ua.get(), Q, Sf, lam_visc, v_dt, gamma, h->vals.get(),
+                           h->dflag.get());
+    LAUNCHCHK();
+    if (read_int(h->dflag.get(), st) & 4)
+        cbs_throw(CBS_ERR_NONFINITE, "non-finite assembled coefficient (check the states: pressure and density "
+                                     "must be positive)");
 }
 
 void check_finite(const double *a, int64_t count, int32_t *dflag, hipStream_t st) {

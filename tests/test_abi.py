@@ -78,6 +78,7 @@ def test_argument_errors_without_gpu():
         lambda: L.cbs_level_apply(None, 0, 0, None, None, None, None),
         lambda: L.cbs_gradient(None, None, None, None, None, None),
         lambda: L.cbs_update_values(None, None, None, None),
+        lambda: L.cbs_assemble_luo(None, None, None, None, None, 1.4),
     ]
     for call in calls:
         assert call() == P.ERR_ARG
