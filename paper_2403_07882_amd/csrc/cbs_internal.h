@@ -206,6 +206,9 @@ struct cbs_system {
     DArr<int32_t> la, ua;                        // face addresses, global cell ids
     DArr<int32_t> rp, col, src, mirror, dslot, uslot, lslot;
     DArr<double> vals;                           // FP64 block CSR values
+    DArr<double> face_lam;                       // S lambda per face (device assembly)
+    DArr<double> cell_prim;                      // u, v, w, H, phi per cell (device assembly)
+    DArr<double> cell_acc;                       // net face vector, sum of S lambda per cell
     int64_t nnzb = 0;
     // preconditioner
     bool setup_done = false, values_changed = false, transposed_ready = false;

@@ -271,14 +271,26 @@ __global__ void k_values(int64_t total, int32_t N, int32_t F, const int32_t *src
 }
 
 // ------------------------------------------------------------------ assembly
-// Row r of the Euler convective flux Jacobian d(F(Q) . s)/dQ for the
-// conservative state Q = (rho, rho u, rho v, rho w, rho E) of an ideal gas
-// (ratio g); s is an area vector and the Jacobian is linear in it.
-__device__ inline void euler_jac_row(const double *Q, double sx, double sy, double sz, double g, int r,
-                                     double out[5]) {
-    const double rho = Q[0], u = Q[1] / rho, v = Q[2] / rho, w = Q[3] / rho;
+// Per cell, once: u, v, w, the total enthalpy H = (rho E + p)/rho and
+// phi = (gamma-1)|u|^2/2, from the conservative state Q = (rho, rho u,
+// rho v, rho w, rho E) of an ideal gas with p = (gamma-1)(rho E - rho|u|^2/2).
+__global__ void k_cell_prims(int32_t N, const double *Q, double g, double *prim) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double *q = Q + (int64_t)i * 5;
+    const double rho = q[0], u = q[1] / rho, v = q[2] / rho, w = q[3] / rho;
     const double g1 = g - 1.0, q2 = u * u + v * v + w * w;
-    const double p = g1 * (Q[4] - 0.5 * rho * q2), H = (Q[4] + p) / rho, phi = 0.5 * g1 * q2;
+    const double p = g1 * (q[4] - 0.5 * rho * q2);
+    double *o = prim + (int64_t)i * 5;
+    o[0] = u; o[1] = v; o[2] = w; o[3] = (q[4] + p) / rho; o[4] = 0.5 * g1 * q2;
+}
+
+// Row r of the Euler convective flux Jacobian d(F(Q) . s)/dQ in the
+// conservative variables, from the cell's (u, v, w, H, phi); s is an area
+// vector and the Jacobian is linear in it.
+__device__ inline void euler_jac_row(const double *pr, double sx, double sy, double sz, double g, int r,
+                                     double out[5]) {
+    const double u = pr[0], v = pr[1], w = pr[2], H = pr[3], phi = pr[4], g1 = g - 1.0;
     const double V = u * sx + v * sy + w * sz;
     if (r == 0) {
         out[0] = 0.0; out[1] = sx; out[2] = sy; out[3] = sz; out[4] = 0.0;
@@ -298,21 +310,22 @@ __device__ inline void euler_jac_row(const double *Q, double sx, double sy, doub
     }
 }
 
-// S lambda of a face: the convective spectral radius of the Roe-averaged
-// state, |u~ . s| + c~ |s|, plus |s| times the viscous radius per unit area.
-// Always evaluated with the owner state first, so both rows of a face see
-// the same value.
-__device__ inline double face_radius(const double *QL, const double *QR, const double *s, double lamv, double g) {
-    const double g1 = g - 1.0, al = sqrt(QL[0]), ar = sqrt(QR[0]), wsum = al + ar;
-    const double ul = QL[1] / QL[0], vl = QL[2] / QL[0], wl = QL[3] / QL[0];
-    const double ur = QR[1] / QR[0], vr = QR[2] / QR[0], wr = QR[3] / QR[0];
-    const double Hl = (QL[4] + g1 * (QL[4] - 0.5 * QL[0] * (ul * ul + vl * vl + wl * wl))) / QL[0];
-    const double Hr = (QR[4] + g1 * (QR[4] - 0.5 * QR[0] * (ur * ur + vr * vr + wr * wr))) / QR[0];
-    const double u = (al * ul + ar * ur) / wsum, v = (al * vl + ar * vr) / wsum, w = (al * wl + ar * wr) / wsum;
-    const double H = (al * Hl + ar * Hr) / wsum;
-    const double c = sqrt(g1 * (H - 0.5 * (u * u + v * v + w * w)));
+// S lambda of every face, once (the slot kernel reads each face up to 20
+// times): the convective spectral radius of the Roe-averaged state,
+// |u~ . s| + c~ |s| (weights sqrt(rho), c~^2 = (gamma-1)(H~ - |u~|^2/2)),
+// plus |s| times the viscous radius per unit area.
+__global__ void k_face_radius(int32_t F, const int32_t *la, const int32_t *ua, const double *Q, const double *prim,
+                              const double *Sf, const double *lamv, double g, double *lam) {
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const int32_t l = la[f], r = ua[f];
+    const double *pl = prim + (int64_t)l * 5, *pr = prim + (int64_t)r * 5, *s = Sf + (int64_t)f * 3;
+    const double al = sqrt(Q[(int64_t)l * 5]), ar = sqrt(Q[(int64_t)r * 5]), wsum = al + ar;
+    const double u = (al * pl[0] + ar * pr[0]) / wsum, v = (al * pl[1] + ar * pr[1]) / wsum;
+    const double w = (al * pl[2] + ar * pr[2]) / wsum, H = (al * pl[3] + ar * pr[3]) / wsum;
+    const double c = sqrt((g - 1.0) * (H - 0.5 * (u * u + v * v + w * w)));
     const double S = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-    return fabs(u * s[0] + v * s[1] + w * s[2]) + c * S + lamv * S;
+    lam[f] = fabs(u * s[0] + v * s[1] + w * s[2]) + c * S + (lamv ? lamv[f] : 0.0) * S;
 }
 
 // The density-based coupled matrix V/dtau I - dR/dQ with the approximate
@@ -322,51 +335,78 @@ __device__ inline double face_radius(const double *QL, const double *QR, const d
 // (J(Q_l, -s) - S lambda I)/2, and the diagonal of cell i is
 // v_dt_i I + (J(Q_i, sum of its outward face vectors) + sum of its S lambda I)/2
 // (J is linear in s, so the faces' Jacobians at Q_i add up to one).
-__global__ void k_assemble_luo(int64_t nnzb, int32_t N, int32_t F, const int32_t *rp, const int32_t *src,
-                               const int32_t *la, const int32_t *ua, const double *Q, const double *Sf,
-                               const double *lamv, const double *vdt, double g, double *vals, int32_t *flag) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nnzb * 5) return;
-    const int64_t k = t / 5;
+// Per cell, once: the sum of its outward face vectors (a face counts +S_f in
+// its owner's row and -S_f in its neighbour's) and the sum of its faces'
+// S lambda, in the row's slot order.
+__global__ void k_cell_faces(int32_t N, int32_t F, const int32_t *rp, const int32_t *src, const double *Sf,
+                             const double *lam, double *acc) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double nx = 0.0, ny = 0.0, nz = 0.0, lsum = 0.0;
+    for (int32_t k2 = rp[i]; k2 < rp[i + 1]; ++k2) {
+        const int32_t s2 = src[k2];
+        if (s2 < N) continue;
+        const bool up = s2 < N + F;
+        const int32_t f = up ? s2 - N : s2 - N - F;
+        const double *sf = Sf + (int64_t)f * 3;
+        const double sg = up ? 1.0 : -1.0;
+        nx += sg * sf[0]; ny += sg * sf[1]; nz += sg * sf[2];
+        lsum += lam[f];
+    }
+    double *o = acc + (int64_t)i * 4;
+    o[0] = nx; o[1] = ny; o[2] = nz; o[3] = lsum;
+}
+
+// Thread t's five values are vals[5t .. 5t+4], so a workgroup's output is one
+// contiguous run: it is staged in LDS and stored with unit stride.
+constexpr int kAsmThreads = 256;
+__global__ __launch_bounds__(kAsmThreads) void k_assemble_luo(int64_t nnzb, int32_t N, int32_t F, const int32_t *rp,
+                                                              const int32_t *src, const int32_t *la,
+                                                              const int32_t *ua, const double *prim,
+                                                              const double *Sf, const double *lam,
+                                                              const double *cacc, const double *vdt, double g,
+                                                              double *vals, int32_t *flag) {
+    __shared__ double stage[kAsmThreads * 5];
+    const int64_t t0 = (int64_t)blockIdx.x * kAsmThreads;
+    const int64_t t = t0 + threadIdx.x;
+    const bool act = t < nnzb * 5;
+    const int64_t k = act ? t / 5 : 0;
     const int r = (int)(t - k * 5);
-    const int32_t s = src[k];
-    double out[5];
-    if (s >= N) {
+    const int32_t s = act ? src[k] : 0;
+    double out[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (act && s >= N) {
         const bool up = s < N + F;
         const int32_t f = up ? s - N : s - N - F;
         const int32_t l = la[f], u = ua[f];
         const double *sf = Sf + (int64_t)f * 3;
-        const double lam = face_radius(Q + (int64_t)l * 5, Q + (int64_t)u * 5, sf, lamv ? lamv[f] : 0.0, g);
+        const double lf = lam[f];
         const double sg = up ? 1.0 : -1.0;
-        euler_jac_row(Q + (int64_t)(up ? u : l) * 5, sg * sf[0], sg * sf[1], sg * sf[2], g, r, out);
+        euler_jac_row(prim + (int64_t)(up ? u : l) * 5, sg * sf[0], sg * sf[1], sg * sf[2], g, r, out);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] - (c == r ? lam : 0.0));
-    } else {
+        for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] - (c == r ? lf : 0.0));
+    } else if (act) {
         const int32_t i = s;
-        double nx = 0.0, ny = 0.0, nz = 0.0, lsum = 0.0;
-        for (int32_t k2 = rp[i]; k2 < rp[i + 1]; ++k2) {
-            const int32_t s2 = src[k2];
-            if (s2 < N) continue;
-            const bool up = s2 < N + F;
-            const int32_t f = up ? s2 - N : s2 - N - F;
-            const double *sf = Sf + (int64_t)f * 3;
-            const double sg = up ? 1.0 : -1.0;
-            nx += sg * sf[0]; ny += sg * sf[1]; nz += sg * sf[2];
-            lsum += face_radius(Q + (int64_t)la[f] * 5, Q + (int64_t)ua[f] * 5, sf, lamv ? lamv[f] : 0.0, g);
-        }
-        euler_jac_row(Q + (int64_t)i * 5, nx, ny, nz, g, r, out);
+        const double *a = cacc + (int64_t)i * 4;
+        const double lsum = a[3];
+        euler_jac_row(prim + (int64_t)i * 5, a[0], a[1], a[2], g, r, out);
         const double dt = vdt ? vdt[i] : 0.0;
 #pragma unroll
         for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] + (c == r ? lsum : 0.0)) + (c == r ? dt : 0.0);
     }
     bool bad = false;
-    double *o = vals + k * 25 + r * 5;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         bad = bad || !isfinite(out[c]);
-        o[c] = out[c];
+        stage[threadIdx.x * 5 + c] = out[c];
     }
     if (bad) atomicOr(flag, 4);
+    __syncthreads();
+    const int64_t total = nnzb * 25, base = t0 * 5;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const int64_t e = base + threadIdx.x + j * kAsmThreads;
+        if (e < total) vals[e] = stage[threadIdx.x + j * kAsmThreads];
+    }
 }
 
 __global__ void k_check_finite(const double *a, int64_t count, int32_t *flag) {
@@ -470,11 +510,20 @@ void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double
     hipStream_t st = h->stream;
     h->vals.ensure((size_t)h->nnzb * 25);
     HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+    h->face_lam.ensure(h->F > 0 ? (size_t)h->F : 1);
+    h->cell_prim.ensure((size_t)h->N * 5);
+    hipLaunchKernelGGL(k_cell_prims, dim3(cdiv(h->N, 256)), dim3(256), 0, st, h->N, Q, gamma, h->cell_prim.get());
+    if (h->F > 0)
+        hipLaunchKernelGGL(k_face_radius, dim3(cdiv(h->F, 256)), dim3(256), 0, st, h->F, h->la.get(), h->ua.get(), Q,
+                           h->cell_prim.get(), Sf, lam_visc, gamma, h->face_lam.get());
+    h->cell_acc.ensure((size_t)h->N * 4);
+    hipLaunchKernelGGL(k_cell_faces, dim3(cdiv(h->N, 256)), dim3(256), 0, st, h->N, h->F, h->rp.get(), h->src.get(),
+                       Sf, h->face_lam.get(), h->cell_acc.get());
     const int64_t nthr = h->nnzb * 5;
     if (nthr > 0)
-        hipLaunchKernelGGL(k_assemble_luo, dim3(cdiv(nthr, 256)), dim3(256), 0, st, h->nnzb, h->N, h->F, h->rp.get(),
-                           h->src.get(), h->la.get(), h->ua.get(), Q, Sf, lam_visc, v_dt, gamma, h->vals.get(),
-                           h->dflag.get());
+        hipLaunchKernelGGL(k_assemble_luo, dim3(cdiv(nthr, kAsmThreads)), dim3(kAsmThreads), 0, st, h->nnzb, h->N, h->F,
+                           h->rp.get(), h->src.get(), h->la.get(), h->ua.get(), h->cell_prim.get(), Sf,
+                           h->face_lam.get(), h->cell_acc.get(), v_dt, gamma, h->vals.get(), h->dflag.get());
     LAUNCHCHK();
     if (read_int(h->dflag.get(), st) & 4)
         cbs_throw(CBS_ERR_NONFINITE, "non-finite assembled coefficient (check the states: pressure and density "
