@@ -360,7 +360,7 @@ __global__ void k_cell_faces(int32_t N, int32_t F, const int32_t *rp, const int3
 // Thread t's five values are vals[5t .. 5t+4], so a workgroup's output is one
 // contiguous run: it is staged in LDS and stored with unit stride.
 constexpr int kAsmThreads = 256;
-__global__ __launch_bounds__(kAsmThreads) void k_assemble_luo(int64_t nnzb, int32_t N, int32_t F, const int32_t *rp,
+__global__ __launch_bounds__(kAsmThreads) void k_assemble_luo(int64_t nnzb, int32_t N, int32_t F,
                                                               const int32_t *src, const int32_t *la,
                                                               const int32_t *ua, const double *prim,
                                                               const double *Sf, const double *lam,
@@ -522,7 +522,7 @@ void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double
     const int64_t nthr = h->nnzb * 5;
     if (nthr > 0)
         hipLaunchKernelGGL(k_assemble_luo, dim3(cdiv(nthr, kAsmThreads)), dim3(kAsmThreads), 0, st, h->nnzb, h->N, h->F,
-                           h->rp.get(), h->src.get(), h->la.get(), h->ua.get(), h->cell_prim.get(), Sf,
+                           h->src.get(), h->la.get(), h->ua.get(), h->cell_prim.get(), Sf,
                            h->face_lam.get(), h->cell_acc.get(), v_dt, gamma, h->vals.get(), h->dflag.get());
     LAUNCHCHK();
     if (read_int(h->dflag.get(), st) & 4)
