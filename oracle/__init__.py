@@ -100,6 +100,8 @@ def _declare(L):
         "orc_euler_jac": (None, [_f64p, _f64p, cd, _f64p]),
         "orc_roe_radius": (cd, [_f64p, _f64p, _f64p, cd]),
         "orc_luo_assemble": (None, [ci, ci, _i32p, _i32p, _f64p, _f64p, vp, vp, cd, _f64p, _f64p, _f64p]),
+        "orc_pu_assemble": (None, [ci, ci, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, vp, vp,
+                                   _f64p, _f64p, _f64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -461,6 +463,23 @@ def luo_assemble(d, with_visc=True, with_dt=True):
                            vd.ctypes.data if vd is not None else None,
                            float(d["gamma"]), diag.ravel(), upper.ravel(), lower.ravel())
     return {"N": N, "F": F, "n": 5, "lower_addr": d["lower_addr"], "upper_addr": d["upper_addr"],
+            "diag": diag, "upper": upper[:F], "lower": lower[:F]}
+
+
+def pu_assemble(d, with_add=True):
+    """LDU blocks of the pressure-based (p, Ux, Uy, Uz) matrix from ``pu_inputs``."""
+    N, F = d["N"], d["F"]
+    diag = np.empty((N, 4, 4)); upper = np.empty((max(F, 1), 4, 4)); lower = np.empty((max(F, 1), 4, 4))
+    la, ua = _c32(d["lower_addr"]), _c32(d["upper_addr"])
+    Sf, fx, dv, fl, nu = (_c64(d[k]).ravel() for k in ("Sf", "fx", "d", "flux", "nu"))
+    if F == 0:
+        la = ua = np.zeros(1, np.int32)
+        Sf = dv = np.zeros(3); fx = fl = nu = np.zeros(1)
+    ua_, pa_ = (_c64(d["uu_add"]), _c64(d["pp_add"])) if with_add else (None, None)
+    lib().orc_pu_assemble(N, F, la, ua, Sf, fx, dv, fl, nu, _c64(d["vol"]),
+                          None if ua_ is None else ua_.ctypes.data, None if pa_ is None else pa_.ctypes.data,
+                          diag.ravel(), upper.ravel(), lower.ravel())
+    return {"N": N, "F": F, "n": 4, "lower_addr": d["lower_addr"], "upper_addr": d["upper_addr"],
             "diag": diag, "upper": upper[:F], "lower": lower[:F]}
 
 

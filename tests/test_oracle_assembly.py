@@ -132,3 +132,92 @@ def test_two_cell_blocks_by_hand():
 
 def _fd_jac(Q, s, h=1e-6):
     return np.stack([(_flux(Q + h * e, s) - _flux(Q - h * e, s)) / (2 * h) for e in np.eye(5)], axis=1)
+
+
+# ------------------------------------------------ pressure-based (p, U) blocks
+from workloads import pu_inputs  # noqa: E402
+
+
+def _pu(d, **kw):
+    return O.from_system(O.pu_assemble(d, **kw))
+
+
+def test_pu_pressure_rows_are_a_laplacian():
+    """Rhie-Chow pp sub-block: each row sums to pp_add (to 0 without it), off-
+    diagonals are negative and the matrix of pp entries is symmetric."""
+    d = pu_inputs(5, 4, 3, seed=20)
+    A = _pu(d)
+    rows = np.repeat(np.arange(A.N), np.diff(A.row_ptr))
+    pp = A.vals[:, 0, 0]
+    assert np.allclose(np.bincount(rows, pp, A.N), d["pp_add"], rtol=1e-12, atol=1e-15)
+    off = rows != A.col
+    assert np.all(pp[off] < 0)
+    P = np.zeros((A.N, A.N)); P[rows, A.col] = pp
+    assert np.allclose(P, P.T, rtol=1e-14, atol=0)
+
+
+def test_pu_coupling_blocks_are_equal_and_vanish_on_closed_cells():
+    """a^up = a^pu in every block; summed over a closed cell's row they give
+    the sum of its outward face vectors, 0 (a constant pressure has no
+    gradient and a constant velocity no divergence)."""
+    d = pu_inputs(5, 5, 4, seed=21)
+    A = _pu(d)
+    assert np.array_equal(A.vals[:, 1:, 0], A.vals[:, 0, 1:])
+    rowsum = np.add.reduceat(A.vals, A.row_ptr[:-1], axis=0)
+    ids = np.arange(A.N).reshape(4, 5, 5)
+    inner = ids[1:-1, 1:-1, 1:-1].ravel()
+    scale = np.abs(A.vals[:, 1:, 0]).max()
+    assert np.abs(rowsum[inner, 1:, 0]).max() <= 1e-13 * scale
+    assert np.abs(rowsum[ids[0, 0, 0], 1:, 0]).max() > 1e-3 * scale
+
+
+def test_pu_momentum_rows_of_a_divergence_free_flux_sum_to_the_additions():
+    """With a uniform velocity the face fluxes of a closed cell sum to zero,
+    so upwind convection plus diffusion leaves each momentum row summing to
+    uu_add: max(F, 0) - max(-F, 0) = F and the diffusion cancels."""
+    d = pu_inputs(5, 4, 4, seed=22)
+    u = np.array([0.7, -0.3, 0.4])
+    d["flux"] = d["Sf"] @ u
+    A = _pu(d)
+    rowsum = np.add.reduceat(A.vals, A.row_ptr[:-1], axis=0)
+    ids = np.arange(A.N).reshape(4, 4, 5)
+    inner = ids[1:-1, 1:-1, 1:-1].ravel()
+    for c in range(1, 4):
+        assert np.allclose(rowsum[inner, c, c], d["uu_add"][inner], rtol=1e-12)
+        assert np.all(rowsum[inner, c, 1:][:, [k for k in range(3) if k != c - 1]] == 0)
+
+
+def test_pu_reversing_a_face_gives_the_same_matrix():
+    """Listing a face from its other side (neighbour first, -S, -d, -flux,
+    weight 1 - f_x) assembles the same operator."""
+    d = pu_inputs(4, 3, 3, seed=23)
+    A = _pu(d)
+    flip = np.random.default_rng(24).random(d["F"]) < 0.5
+    e = dict(d)
+    e["lower_addr"] = np.where(flip, d["upper_addr"], d["lower_addr"]).astype(np.int32)
+    e["upper_addr"] = np.where(flip, d["lower_addr"], d["upper_addr"]).astype(np.int32)
+    for k in ("Sf", "d"):
+        e[k] = np.where(flip[:, None], -d[k], d[k])
+    e["flux"] = np.where(flip, -d["flux"], d["flux"])
+    e["fx"] = np.where(flip, 1.0 - d["fx"], d["fx"])
+    B = _pu(e)
+    assert np.array_equal(A.col, B.col)
+    assert np.allclose(A.vals, B.vals, rtol=1e-13, atol=1e-16)
+
+
+def test_pu_rhie_chow_coefficient_on_a_uniform_cube_mesh():
+    """Unjittered cubes of side h, uniform inputs: D = V / a^uu for every cell
+    with the same a^uu, so a_ij^pp = -D h^2 / h = -D h exactly."""
+    d = pu_inputs(4, 4, 4, seed=25, jitter=0.0)
+    h = d["h"]
+    d["vol"] = np.full(d["N"], h ** 3)
+    d["nu"] = np.full(d["F"], 0.01)
+    d["flux"] = np.zeros(d["F"])
+    d["uu_add"] = np.full(d["N"], 0.5)
+    A = _pu(d)
+    rows = np.repeat(np.arange(A.N), np.diff(A.row_ptr))
+    deg = np.diff(A.row_ptr) - 1
+    auu = 0.5 + deg * 0.01 * h * h / h                # diffusion k = nu |S| / (n.d) = nu h
+    off = np.nonzero(rows != A.col)[0]
+    Dl, Du = h ** 3 / auu[rows[off]], h ** 3 / auu[A.col[off]]
+    assert np.allclose(A.vals[off, 0, 0], -0.5 * (Dl + Du) * h, rtol=1e-12)

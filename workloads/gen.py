@@ -34,7 +34,7 @@ import numpy as np
 __all__ = [
     "box_faces", "jacobian_box", "jacobian_stretched", "pressure_velocity",
     "batch_sizes", "jacobian_batch", "concat_systems", "stretched_spacing", "jacobian_graph",
-    "luo_inputs",
+    "luo_inputs", "pu_inputs",
 ]
 
 
@@ -514,3 +514,64 @@ def luo_inputs(nx=20, ny=20, nz=20, seed=0, jitter=0.2, gamma=1.4, mach=0.5, cfl
     v_dt = h * h * (np.linalg.norm(vel, axis=1) + c) / cfl_c
     return {"N": N, "F": int(la.size), "n": 5, "lower_addr": la, "upper_addr": ua, "Q": Q, "Sf": Sf,
             "lam_visc": lam_visc, "v_dt": v_dt, "gamma": float(gamma), "h": h}
+
+
+def pu_inputs(nx=20, ny=20, nz=20, seed=0, jitter=0.2, nu=(0.005, 0.02)):
+    """Inputs of the GPU assembly of the pressure-based (p, Ux, Uy, Uz)
+    matrix: a jittered hex box (unit spacing h = 1/nz) with its internal faces
+    in ``box_faces`` order, per face the area vector S_f (owner -> neighbour),
+    the owner's linear-interpolation weight f_x, the centroid distance
+    d = c_neighbour - c_owner, the previous-iteration volume flux u_f . S_f
+    and nu_eff; per cell the volume and two diagonal additions standing in for
+    boundary faces and pseudo-time relaxation (uu_add on the momentum
+    diagonal, pp_add on the pressure diagonal).  Only geometry and fields.
+
+    Velocity: u(x) = u0 (1 + 0.3 (sin 2 pi y, sin 2 pi z, sin 2 pi x)) at the
+    face centre, u0 ~ U(0.2, 1)^3.  f_x = |c_u - x_f| / (|c_u - x_f| +
+    |x_f - c_l|).  V = h^3 (1 + U(-0.05, 0.05)); uu_add = V |u0| / h U(0.5, 1.5);
+    pp_add = 1e-3 h U(0.5, 1.5).
+
+    Draw order from ``default_rng(seed)``: node jitter U(-jitter h, jitter h)
+    for every node (applied to interior nodes only), u0, nu_eff per face
+    U(nu), the volume factors, the uu_add factors, the pp_add factors.
+    """
+    N = nx * ny * nz
+    h = 1.0 / nz
+    rng = np.random.default_rng(seed)
+    g = [np.arange(m + 1) * h for m in (nx, ny, nz)]
+    X = np.stack(np.meshgrid(*g, indexing="ij"), axis=-1)
+    jit = rng.uniform(-jitter * h, jitter * h, size=X.shape)
+    interior = np.zeros(X.shape[:3], bool)
+    interior[1:-1, 1:-1, 1:-1] = True
+    X = X + jit * interior[..., None]
+    Xk = np.transpose(X, (2, 1, 0, 3))
+    C = 0.125 * (Xk[:-1, :-1, :-1] + Xk[:-1, :-1, 1:] + Xk[:-1, 1:, :-1] + Xk[:-1, 1:, 1:]
+                 + Xk[1:, :-1, :-1] + Xk[1:, :-1, 1:] + Xk[1:, 1:, :-1] + Xk[1:, 1:, 1:]).reshape(N, 3)
+    la, ua, _ = box_faces(nx, ny, nz)
+    S, XF = [], []
+    quads = []
+    if nx > 1:
+        quads.append((Xk[:-1, :-1, 1:-1], Xk[:-1, 1:, 1:-1], Xk[1:, 1:, 1:-1], Xk[1:, :-1, 1:-1]))
+    if ny > 1:
+        quads.append((Xk[:-1, 1:-1, :-1], Xk[1:, 1:-1, :-1], Xk[1:, 1:-1, 1:], Xk[:-1, 1:-1, 1:]))
+    if nz > 1:
+        quads.append((Xk[1:-1, :-1, :-1], Xk[1:-1, :-1, 1:], Xk[1:-1, 1:, 1:], Xk[1:-1, 1:, :-1]))
+    for q in quads:
+        a, c = _quad_area(*q)
+        S.append(a.reshape(-1, 3)); XF.append(c.reshape(-1, 3))
+    Sf = np.concatenate(S) if S else np.zeros((0, 3))
+    xf = np.concatenate(XF) if XF else np.zeros((0, 3))
+    d = C[ua] - C[la]
+    dl = np.linalg.norm(xf - C[la], axis=1)
+    du = np.linalg.norm(C[ua] - xf, axis=1)
+    fx = du / (du + dl) if la.size else np.zeros(0)
+    u0 = rng.uniform(0.2, 1.0, 3)
+    tp = 2.0 * np.pi
+    uf = u0 * (1.0 + 0.3 * np.stack([np.sin(tp * xf[:, 1]), np.sin(tp * xf[:, 2]), np.sin(tp * xf[:, 0])], axis=1))
+    flux = (uf * Sf).sum(1)
+    nu_f = rng.uniform(nu[0], nu[1], la.size)
+    vol = h ** 3 * (1.0 + rng.uniform(-0.05, 0.05, N))
+    uu_add = vol * np.linalg.norm(u0) / h * rng.uniform(0.5, 1.5, N)
+    pp_add = 1e-3 * h * rng.uniform(0.5, 1.5, N)
+    return {"N": N, "F": int(la.size), "n": 4, "lower_addr": la, "upper_addr": ua, "Sf": Sf, "fx": fx, "d": d,
+            "flux": flux, "nu": nu_f, "vol": vol, "uu_add": uu_add, "pp_add": pp_add, "h": h}
