@@ -196,6 +196,29 @@ int cbs_update_values(cbs_handle h, const double *diag, const double *upper, con
 int cbs_assemble_luo(cbs_handle h, const double *Q, const double *Sf, const double *lam_visc, const double *v_dt,
                      double gamma);
 
+/* Assemble the pressure-based coupled matrix on the device, straight into
+ * the handle's block-CSR values: the face coefficients of Sec. 2.2 (after
+ * Eq. prb_coeff).  Takes the place of cbs_update_values.  Block size 4,
+ * unknowns (p, Ux, Uy, Uz); row 0 is continuity.  All arrays on the device.
+ *   Sf[F*3]     face area vectors, from lower_addr[f] (owner) to upper_addr[f]
+ *   fx[F]       the owner's linear-interpolation weight at the face
+ *   d[F*3]      centroid distance x_upper - x_lower
+ *   flux[F]     previous-iteration volume flux u_f . Sf out of the owner
+ *   nu_eff[F]   laminar + turbulent viscosity at the face
+ *   vol[N]      cell volumes
+ *   uu_add[N], pp_add[N]  added to the momentum (times I) and pressure
+ *               diagonals: boundary faces and relaxation (NULL = 0)
+ * Per face, seen from row i (area vector s out of i, flux F_i = u_f . s, own
+ * weight w, k = nu_eff |S| / (n . d)): a_ii^uu += (max(F_i, 0) + k) I,
+ * a_ij^uu = -(max(-F_i, 0) + k) I; a_ii^up = a_ii^pu += w s,
+ * a_ij^up = a_ij^pu = (1 - w) s; with D_i = V_i / a_ii^uu (every face and
+ * uu_add summed) and D_f the interpolated D, a_ij^pp = -D_f |S| / (n . d) and
+ * a_ii^pp += D_f |S| / (n . d) (the Rhie-Chow Laplacian, positive diagonal).
+ * Errors: CBS_ERR_ARG (bdim != 4, NULL arrays), CBS_ERR_NONFINITE (a zero
+ * momentum diagonal or n . d = 0). */
+int cbs_assemble_pu(cbs_handle h, const double *Sf, const double *fx, const double *d, const double *flux,
+                    const double *nu_eff, const double *vol, const double *uu_add, const double *pp_add);
+
 /* Build the preconditioner: block-diagonal inverses (FP64), and for AMG the
  * pairwise-matching aggregation, Galerkin coarse operators P^T A P with
  * piecewise-constant P, FP32 level copies (mixed precision) and the dense

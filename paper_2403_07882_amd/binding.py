@@ -61,6 +61,7 @@ SIGNATURES = [
                                             _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cbs_update_values", C.c_int, [_VP, _VP, _VP, _VP]),
     ("cbs_assemble_luo", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_double]),
+    ("cbs_assemble_pu", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cbs_setup", C.c_int, [_VP, C.POINTER(Options)]),
     ("cbs_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
     ("cbs_solve_transpose", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
@@ -241,6 +242,15 @@ class System:
         vd = _dev(v_dt, torch.float64) if v_dt is not None else None
         _check(lib().cbs_assemble_luo(self.h, _ptr(q), _ptr(s), None if lv is None else _ptr(lv),
                                       None if vd is None else _ptr(vd), float(gamma)), "cbs_assemble_luo")
+
+    def assemble_pu(self, Sf, fx, d, flux, nu_eff, vol, uu_add=None, pp_add=None):
+        """Assemble the pressure-based (p, U) coupled matrix on the device
+        from face geometry and fields (cbs_assemble_pu); then call setup."""
+        torch = _torch()
+        a = [_dev(x, torch.float64) for x in (Sf, fx, d, flux, nu_eff, vol)]
+        opt = [None if x is None else _dev(x, torch.float64) for x in (uu_add, pp_add)]
+        _check(lib().cbs_assemble_pu(self.h, *[_ptr(x) for x in a], *[None if x is None else _ptr(x) for x in opt]),
+               "cbs_assemble_pu")
 
     def setup(self, options: Optional[Options] = None, **kw):
         o = options if options is not None else default_options(**kw)

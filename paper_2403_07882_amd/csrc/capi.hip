@@ -299,6 +299,28 @@ int cbs_assemble_luo(cbs_handle h, const double *Q, const double *Sf, const doub
     });
 }
 
+int cbs_assemble_pu(cbs_handle h, const double *Sf, const double *fx, const double *d, const double *flux,
+                    const double *nu_eff, const double *vol, const double *uu_add, const double *pp_add) {
+    return guarded([&] {
+        require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        set_alloc_stream(h->stream);
+        require(h->n == 4, CBS_ERR_ARG, "the pressure-based assembly needs 4 x 4 blocks");
+        require(vol != nullptr && (h->F == 0 || (Sf && fx && d && flux && nu_eff)), CBS_ERR_ARG,
+                "face or cell arrays are NULL");
+        HIPCHK(hipEventRecord(h->ev0, h->stream));
+        assemble_pu(h, Sf, fx, d, flux, nu_eff, vol, uu_add, pp_add);
+        HIPCHK(hipEventRecord(h->ev1, h->stream));
+        h->t_convert_ms = elapsed_ms(h->ev0, h->ev1);
+        h->values_changed = true;
+        h->transposed_ready = false;
+        h->valsT.release();
+        h->usell.v64.release();
+        h->usell.v64T.release();
+        invalidate_graphs(h);
+        return CBS_OK;
+    });
+}
+
 int cbs_setup(cbs_handle h, const cbs_options *opt) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");

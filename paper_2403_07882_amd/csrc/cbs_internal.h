@@ -206,9 +206,11 @@ struct cbs_system {
     DArr<int32_t> la, ua;                        // face addresses, global cell ids
     DArr<int32_t> rp, col, src, mirror, dslot, uslot, lslot;
     DArr<double> vals;                           // FP64 block CSR values
-    DArr<double> face_lam;                       // S lambda per face (device assembly)
-    DArr<double> cell_prim;                      // u, v, w, H, phi per cell (device assembly)
-    DArr<double> cell_acc;                       // net face vector, sum of S lambda per cell
+    // device assembly scratch: per-face and per-cell passes (density-based:
+    // S lambda; u, v, w, H, phi; net face vector and sum of S lambda;
+    // pressure-based: Rhie-Chow and diffusion coefficients; pp diagonal;
+    // a_uu, D and the up/pu diagonal vector)
+    DArr<double> face_lam, cell_prim, cell_acc;
     int64_t nnzb = 0;
     // preconditioner
     bool setup_done = false, values_changed = false, transposed_ready = false;
@@ -278,6 +280,8 @@ void convert_pattern(cbs_system *h);
 void convert_values(cbs_system *h, const double *diag, const double *upper, const double *lower);
 void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double *lam_visc, const double *v_dt,
                   double gamma);
+void assemble_pu(cbs_system *h, const double *Sf, const double *fx, const double *d, const double *flux,
+                 const double *nu, const double *vol, const double *uu_add, const double *pp_add);
 void check_finite(const double *a, int64_t count, int32_t *dflag, hipStream_t st);
 void pack_fields(int32_t N, int32_t n, const double *soa, double *aos, hipStream_t st);
 void unpack_fields(int32_t N, int32_t n, const double *aos, double *soa, hipStream_t st);

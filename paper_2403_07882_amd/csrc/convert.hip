@@ -409,6 +409,116 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_luo(int64_t nnzb, int3
     }
 }
 
+// ---------------------------------------------- pressure-based (p, U) blocks
+// Seen from row i, face f (slot code s) has area vector sg S_f, volume flux
+// sg F_f and the row's own interpolation weight w = f_x (owner) or 1 - f_x.
+// Per cell: the momentum diagonal a_ii^uu = uu_add + sum of (max(sg F, 0) + k_f)
+// with the diffusion k_f = nu |S| / (n . d), D_i = V_i / a_ii^uu, and the
+// up/pu diagonal vector sum of w sg S_f.
+__global__ void k_pu_cells(int32_t N, int32_t F, const int32_t *rp, const int32_t *src, const double *Sf,
+                           const double *fx, const double *dv, const double *flux, const double *nu,
+                           const double *vol, const double *uu_add, double *acc) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double auu = uu_add ? uu_add[i] : 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
+    for (int32_t k2 = rp[i]; k2 < rp[i + 1]; ++k2) {
+        const int32_t s2 = src[k2];
+        if (s2 < N) continue;
+        const bool up = s2 < N + F;
+        const int32_t f = up ? s2 - N : s2 - N - F;
+        const double *S = Sf + (int64_t)f * 3, *d = dv + (int64_t)f * 3;
+        const double Sm = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+        const double nd = (S[0] * d[0] + S[1] * d[1] + S[2] * d[2]) / Sm;
+        const double sg = up ? 1.0 : -1.0, w = up ? fx[f] : 1.0 - fx[f];
+        auu += fmax(sg * flux[f], 0.0) + nu[f] * Sm / nd;
+        ux += w * sg * S[0]; uy += w * sg * S[1]; uz += w * sg * S[2];
+    }
+    double *o = acc + (int64_t)i * 5;
+    o[0] = auu; o[1] = vol[i] / auu; o[2] = ux; o[3] = uy; o[4] = uz;
+}
+
+// Per face: the Rhie-Chow coefficient (f_x D_l + (1 - f_x) D_u) |S| / (n . d)
+// and the diffusion coefficient k_f.
+__global__ void k_pu_faces(int32_t F, const int32_t *la, const int32_t *ua, const double *Sf, const double *fx,
+                           const double *dv, const double *nu, const double *acc, double *fc) {
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    const double *S = Sf + (int64_t)f * 3, *d = dv + (int64_t)f * 3;
+    const double Sm = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+    const double nd = (S[0] * d[0] + S[1] * d[1] + S[2] * d[2]) / Sm;
+    const double Df = fx[f] * acc[(int64_t)la[f] * 5 + 1] + (1.0 - fx[f]) * acc[(int64_t)ua[f] * 5 + 1];
+    fc[2 * (int64_t)f] = Df * Sm / nd;
+    fc[2 * (int64_t)f + 1] = nu[f] * Sm / nd;
+}
+
+// Per cell: the pp diagonal, pp_add plus the row's Rhie-Chow coefficients.
+__global__ void k_pu_pp(int32_t N, int32_t F, const int32_t *rp, const int32_t *src, const double *fc,
+                        const double *pp_add, double *pp) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double a = pp_add ? pp_add[i] : 0.0;
+    for (int32_t k2 = rp[i]; k2 < rp[i + 1]; ++k2) {
+        const int32_t s2 = src[k2];
+        if (s2 < N) continue;
+        a += fc[2 * (int64_t)(s2 < N + F ? s2 - N : s2 - N - F)];
+    }
+    pp[i] = a;
+}
+
+// One thread per (slot, block row r), four values each, staged in LDS like
+// the density-based kernel.  Row 0 is continuity (pp, pu), rows 1-3 momentum
+// (up, uu = scalar times I).
+__global__ __launch_bounds__(kAsmThreads) void k_assemble_pu(int64_t nnzb, int32_t N, int32_t F, const int32_t *src,
+                                                             const double *Sf, const double *fx, const double *flux,
+                                                             const double *fc, const double *acc, const double *pp,
+                                                             double *vals, int32_t *flag) {
+    __shared__ double stage[kAsmThreads * 4];
+    const int64_t t0 = (int64_t)blockIdx.x * kAsmThreads;
+    const int64_t t = t0 + threadIdx.x;
+    const bool act = t < nnzb * 4;
+    const int64_t k = act ? t / 4 : 0;
+    const int r = (int)(t - k * 4);
+    const int32_t s = act ? src[k] : 0;
+    double out[4] = {0.0, 0.0, 0.0, 0.0};
+    if (act && s >= N) {
+        const bool up = s < N + F;
+        const int32_t f = up ? s - N : s - N - F;
+        const double sg = up ? 1.0 : -1.0, w = up ? fx[f] : 1.0 - fx[f];
+        const double *S = Sf + (int64_t)f * 3;
+        const double cpl = (1.0 - w) * sg;              // coupling vector (1 - w) sg S
+        if (r == 0) {
+            out[0] = -fc[2 * (int64_t)f];
+            out[1] = cpl * S[0]; out[2] = cpl * S[1]; out[3] = cpl * S[2];
+        } else {
+            out[0] = cpl * S[r - 1];
+            out[r] = -(fmax(-sg * flux[f], 0.0) + fc[2 * (int64_t)f + 1]);
+        }
+    } else if (act) {
+        const double *a = acc + (int64_t)s * 5;
+        if (r == 0) {
+            out[0] = pp[s];
+            out[1] = a[2]; out[2] = a[3]; out[3] = a[4];
+        } else {
+            out[0] = a[1 + r];
+            out[r] = a[0];
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        bad = bad || !isfinite(out[c]);
+        stage[threadIdx.x * 4 + c] = out[c];
+    }
+    if (bad) atomicOr(flag, 4);
+    __syncthreads();
+    const int64_t total = nnzb * 16, base = t0 * 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t e = base + threadIdx.x + j * kAsmThreads;
+        if (e < total) vals[e] = stage[threadIdx.x + j * kAsmThreads];
+    }
+}
+
 __global__ void k_check_finite(const double *a, int64_t count, int32_t *flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count && !isfinite(a[i])) atomicOr(flag, 4);
@@ -528,6 +638,31 @@ void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double
     if (read_int(h->dflag.get(), st) & 4)
         cbs_throw(CBS_ERR_NONFINITE, "non-finite assembled coefficient (check the states: pressure and density "
                                      "must be positive)");
+}
+
+void assemble_pu(cbs_system *h, const double *Sf, const double *fx, const double *d, const double *flux,
+                 const double *nu, const double *vol, const double *uu_add, const double *pp_add) {
+    hipStream_t st = h->stream;
+    h->vals.ensure((size_t)h->nnzb * 16);
+    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
+    h->cell_acc.ensure((size_t)h->N * 5);
+    h->cell_prim.ensure((size_t)h->N);
+    h->face_lam.ensure(h->F > 0 ? 2 * (size_t)h->F : 1);
+    hipLaunchKernelGGL(k_pu_cells, dim3(cdiv(h->N, 256)), dim3(256), 0, st, h->N, h->F, h->rp.get(), h->src.get(), Sf,
+                       fx, d, flux, nu, vol, uu_add, h->cell_acc.get());
+    if (h->F > 0)
+        hipLaunchKernelGGL(k_pu_faces, dim3(cdiv(h->F, 256)), dim3(256), 0, st, h->F, h->la.get(), h->ua.get(), Sf, fx,
+                           d, nu, h->cell_acc.get(), h->face_lam.get());
+    hipLaunchKernelGGL(k_pu_pp, dim3(cdiv(h->N, 256)), dim3(256), 0, st, h->N, h->F, h->rp.get(), h->src.get(),
+                       h->face_lam.get(), pp_add, h->cell_prim.get());
+    const int64_t nthr = h->nnzb * 4;
+    if (nthr > 0)
+        hipLaunchKernelGGL(k_assemble_pu, dim3(cdiv(nthr, kAsmThreads)), dim3(kAsmThreads), 0, st, h->nnzb, h->N, h->F,
+                           h->src.get(), Sf, fx, flux, h->face_lam.get(), h->cell_acc.get(), h->cell_prim.get(),
+                           h->vals.get(), h->dflag.get());
+    LAUNCHCHK();
+    if (read_int(h->dflag.get(), st) & 4)
+        cbs_throw(CBS_ERR_NONFINITE, "non-finite assembled coefficient (zero momentum diagonal or n . d = 0)");
 }
 
 void check_finite(const double *a, int64_t count, int32_t *dflag, hipStream_t st) {

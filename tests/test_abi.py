@@ -79,6 +79,7 @@ def test_argument_errors_without_gpu():
         lambda: L.cbs_gradient(None, None, None, None, None, None),
         lambda: L.cbs_update_values(None, None, None, None),
         lambda: L.cbs_assemble_luo(None, None, None, None, None, 1.4),
+        lambda: L.cbs_assemble_pu(None, None, None, None, None, None, None, None, None),
     ]
     for call in calls:
         assert call() == P.ERR_ARG

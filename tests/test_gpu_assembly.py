@@ -120,3 +120,63 @@ def test_assembly_rejects_unphysical_states_and_other_block_sizes():
         with pytest.raises(P.CbsError) as e:
             sysm.assemble_luo(d["Q"], d["Sf"])
         assert e.value.code == P.ERR_ARG
+
+
+# ------------------------------------------------ pressure-based (p, U) blocks
+from workloads import pu_inputs  # noqa: E402
+
+
+def _blank4(d):
+    N, F = d["N"], d["F"]
+    return {"N": N, "F": F, "n": 4, "lower_addr": d["lower_addr"], "upper_addr": d["upper_addr"],
+            "diag": np.zeros((N, 4, 4)), "upper": np.zeros((F, 4, 4)), "lower": np.zeros((F, 4, 4)),
+            "b": np.zeros((N, 4))}
+
+
+def _pu_args(d, with_add=True):
+    return (d["Sf"], d["fx"], d["d"], d["flux"], d["nu"], d["vol"],
+            d["uu_add"] if with_add else None, d["pp_add"] if with_add else None)
+
+
+@pytest.mark.parametrize("shape", [(12, 10, 9), (7, 1, 1), (1, 1, 1), (33, 17, 5)])
+@pytest.mark.parametrize("with_add", [True, False])
+def test_pu_assembly_matches_oracle(shape, with_add):
+    _say("pu assembly", shape, with_add)
+    d = pu_inputs(*shape, seed=sum(shape) + 1)
+    A = O.from_system(O.pu_assemble(d, with_add=with_add))
+    with P.System.from_dict(_blank4(d)) as sysm:
+        sysm.assemble_pu(*_pu_args(d, with_add))
+        vals = _gpu_vals(sysm)
+        lv0 = sysm.get_level(0)
+        assert np.array_equal(_np(lv0["row_ptr"]), A.row_ptr) and np.array_equal(_np(lv0["col"]), A.col)
+    _close(vals, A.vals)
+
+
+def test_pu_assembly_batch_solve_and_errors():
+    """A batch matches the oracle system by system; an assembled system
+    solves (forward and transposed, mixed AMG) to the tolerance on the
+    oracle's matrix; a 5 x 5 handle is refused."""
+    _say("pu assembly batch and solve")
+    ds = [pu_inputs(6, 5, 4, seed=31), pu_inputs(3, 3, 2, seed=32), pu_inputs(9, 4, 3, seed=33)]
+    cat = concat_systems([_blank4(d) for d in ds])
+    args = [np.concatenate([a[k] for a in ds]) for k in ("Sf", "fx", "d", "flux", "nu", "vol", "uu_add", "pp_add")]
+    with P.System.from_dict(cat) as sysm:
+        sysm.assemble_pu(*args)
+        vals = _gpu_vals(sysm)
+    _close(vals, np.concatenate([O.from_system(O.pu_assemble(d)).vals for d in ds]))
+    d = pu_inputs(16, 14, 12, seed=5)
+    A = O.from_system(O.pu_assemble(d))
+    b = np.random.default_rng(6).uniform(-1, 1, (d["N"], 4))
+    with P.System.from_dict(_blank4(d)) as sysm:
+        sysm.assemble_pu(*_pu_args(d))
+        sysm.setup(precond=P.PREC_AMG, precision=P.PRECISION_MIXED, tol=1e-10)
+        x, st = sysm.solve(b)
+        lam, stt = sysm.solve_transpose(b)
+    assert st["status"] == P.OK and stt["status"] == P.OK, (st, stt)
+    assert O.relres(A, b, _np(x)) <= 1e-10 * 1.0001
+    assert O.relres(O.transpose(A), b, _np(lam)) <= 1e-10 * 1.0001
+    e = luo_inputs(3, 3, 2, seed=1)
+    with P.System.from_dict(_blank(e)) as s5:
+        with pytest.raises(P.CbsError) as err:
+            s5.assemble_pu(*_pu_args(pu_inputs(3, 3, 2, seed=1)))
+        assert err.value.code == P.ERR_ARG
