@@ -66,8 +66,9 @@ def parse():
                     help="threads per scalar row on levels under 65,536 block rows (0 = automatic)")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--assembly", action="store_true",
-                    help="only the density-based device assembly (cbs_assemble_luo) on an nx*ny*nz hex box "
-                         "against the LDU -> block-CSR conversion of the same pattern (cbs_update_values)")
+                    help="only the device assemblies (cbs_assemble_luo, 5x5; cbs_assemble_pu, 4x4) on an "
+                         "nx*ny*nz hex box, each against the LDU -> block-CSR conversion of the same pattern "
+                         "(cbs_update_values)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the level-0 sweep, the FP64 block SpMV (both numberings) and a 1 GiB copy, "
                          "5 launches each, for counter runs")
@@ -201,12 +202,12 @@ def kernels_only(args, P, torch, dev, sysm, opt_mixed, N, n, nnzb, la, ua, diag,
 
 
 def assembly_only(args, P, torch, dev):
-    """Device assembly of the 5x5 density-based matrix from cell states and
-    face vectors, timed per call (HIP events; each call ends with its
-    non-finite check read-back), next to the LDU -> block-CSR conversion that
-    it replaces.  Algorithmic bytes: the block-CSR values written, the slot
-    map, row pointers, states, face vectors, radii, V/dtau and face addresses
-    read once."""
+    """Device assemblies of the 5x5 density-based matrix (cell states, face
+    vectors) and of the 4x4 pressure-based matrix (face geometry and fluxes),
+    each timed per call (HIP events; each call ends with its non-finite check
+    read-back) next to the LDU -> block-CSR conversion that it replaces.
+    Algorithmic bytes: the block-CSR values written, the slot map, row
+    pointers and every per-face and per-cell input read once."""
     from workloads import luo_inputs
     nx, ny, nz = args.mesh
     t0 = time.time()
@@ -223,16 +224,31 @@ def assembly_only(args, P, torch, dev):
         timer = KernelTimer(torch, args.kernel_reps)
         asm_ms = timer(lambda: sysm.assemble_luo(Q, Sf, lv, vd, d["gamma"]))
         conv_ms = timer(lambda: sysm.update_values(diag, upper, lower))
+        del diag, upper, lower
     nnzb = N + 2 * F
     abytes = nnzb * 25 * 8 + nnzb * 4 + (N + 1) * 4 + N * 5 * 8 + F * (3 * 8 + 8 + 2 * 4) + N * 8
     cbytes = 2 * nnzb * 25 * 8 + nnzb * 4
-    print(json.dumps({"metric": "density-based matrix assembly on the device", "unit": "ms",
-                      "config": {"workload": "jittered hex box %dx%dx%d, 5x5 blocks (N=%d, F=%d, nnzb=%d)"
+    # the pressure-based (p, U) assembly on the same box
+    from workloads import pu_inputs
+    e = pu_inputs(nx, ny, nz, seed=0)
+    d4 = torch.zeros((N, 4, 4), dtype=torch.float64, device=dev)
+    u4 = torch.zeros((F, 4, 4), dtype=torch.float64, device=dev)
+    l4 = torch.zeros((F, 4, 4), dtype=torch.float64, device=dev)
+    pargs = [dv(e[k]) for k in ("Sf", "fx", "d", "flux", "nu", "vol", "uu_add", "pp_add")]
+    with P.System(N, 4, la, ua, d4, u4, l4) as s4:
+        timer = KernelTimer(torch, args.kernel_reps)
+        pu_ms = timer(lambda: s4.assemble_pu(*pargs))
+        pconv_ms = timer(lambda: s4.update_values(d4, u4, l4))
+    pbytes = nnzb * 16 * 8 + nnzb * 4 + (N + 1) * 4 + F * (3 * 8 + 8 + 3 * 8 + 8 + 8 + 2 * 4) + N * 3 * 8
+    print(json.dumps({"metric": "coupled matrix assembly on the device", "unit": "ms",
+                      "config": {"workload": "jittered hex box %dx%dx%d (N=%d, F=%d, nnzb=%d)"
                                              % (nx, ny, nz, N, F, nnzb)},
                       "assemble_ms": round(asm_ms, 4), "assemble_gbs": round(abytes / (asm_ms * 1e-3) / 1e9, 1),
                       "algorithmic_bytes_assemble": int(abytes),
                       "ldu_convert_ms": round(conv_ms, 4), "ldu_convert_gbs": round(cbytes / (conv_ms * 1e-3) / 1e9, 1),
-                      "algorithmic_bytes_convert": int(cbytes)}))
+                      "algorithmic_bytes_convert": int(cbytes),
+                      "pu_assemble_ms": round(pu_ms, 4), "pu_assemble_gbs": round(pbytes / (pu_ms * 1e-3) / 1e9, 1),
+                      "algorithmic_bytes_pu_assemble": int(pbytes), "pu_ldu_convert_ms": round(pconv_ms, 4)}))
 
 
 def main():
