@@ -180,3 +180,22 @@ def test_pu_assembly_batch_solve_and_errors():
         with pytest.raises(P.CbsError) as err:
             s5.assemble_pu(*_pu_args(pu_inputs(3, 3, 2, seed=1)))
         assert err.value.code == P.ERR_ARG
+
+
+def test_both_assemblies_at_full_size_match_the_oracle():
+    """The 100 x 100 x 100 box that bench.py --assembly times (1M cells,
+    6.94M blocks), every element of both matrices against the oracle."""
+    _say("assembly full size")
+    d = luo_inputs(100, 100, 100, seed=0)
+    A = O.from_system(O.luo_assemble(d))
+    with P.System.from_dict(_blank(d)) as sysm:
+        sysm.assemble_luo(d["Q"], d["Sf"], d["lam_visc"], d["v_dt"], d["gamma"])
+        vals = _gpu_vals(sysm)
+    _close(vals, A.vals)
+    del vals, A
+    e = pu_inputs(100, 100, 100, seed=0)
+    B = O.from_system(O.pu_assemble(e))
+    with P.System.from_dict(_blank4(e)) as sysm:
+        sysm.assemble_pu(*_pu_args(e))
+        vals = _gpu_vals(sysm)
+    _close(vals, B.vals)
