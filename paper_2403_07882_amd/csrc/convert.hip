@@ -360,9 +360,12 @@ __global__ void k_cell_faces(int32_t N, int32_t F, const int32_t *rp, const int3
 // Thread t's five values are vals[5t .. 5t+4], so a workgroup's output is one
 // contiguous run: it is staged in LDS and stored with unit stride.
 constexpr int kAsmThreads = 256;
+// The block's column cell (the upper slot's neighbour, the lower slot's owner,
+// the diagonal's own cell) is read from the column array, so its primitives
+// load in parallel with the face data instead of after the face addresses.
 __global__ __launch_bounds__(kAsmThreads) void k_assemble_luo(int64_t nnzb, int32_t N, int32_t F,
-                                                              const int32_t *src, const int32_t *la,
-                                                              const int32_t *ua, const double *prim,
+                                                              const int32_t *src, const int32_t *col,
+                                                              const double *prim,
                                                               const double *Sf, const double *lam,
                                                               const double *cacc, const double *vdt, double g,
                                                               double *vals, int32_t *flag) {
@@ -373,22 +376,22 @@ __global__ __launch_bounds__(kAsmThreads) void k_assemble_luo(int64_t nnzb, int3
     const int64_t k = act ? t / 5 : 0;
     const int r = (int)(t - k * 5);
     const int32_t s = act ? src[k] : 0;
+    const int32_t j = act ? col[k] : 0;
     double out[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (act && s >= N) {
         const bool up = s < N + F;
         const int32_t f = up ? s - N : s - N - F;
-        const int32_t l = la[f], u = ua[f];
         const double *sf = Sf + (int64_t)f * 3;
         const double lf = lam[f];
         const double sg = up ? 1.0 : -1.0;
-        euler_jac_row(prim + (int64_t)(up ? u : l) * 5, sg * sf[0], sg * sf[1], sg * sf[2], g, r, out);
+        euler_jac_row(prim + (int64_t)j * 5, sg * sf[0], sg * sf[1], sg * sf[2], g, r, out);
 #pragma unroll
         for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] - (c == r ? lf : 0.0));
     } else if (act) {
         const int32_t i = s;
         const double *a = cacc + (int64_t)i * 4;
         const double lsum = a[3];
-        euler_jac_row(prim + (int64_t)i * 5, a[0], a[1], a[2], g, r, out);
+        euler_jac_row(prim + (int64_t)j * 5, a[0], a[1], a[2], g, r, out);
         const double dt = vdt ? vdt[i] : 0.0;
 #pragma unroll
         for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] + (c == r ? lsum : 0.0)) + (c == r ? dt : 0.0);
@@ -632,7 +635,7 @@ void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double
     const int64_t nthr = h->nnzb * 5;
     if (nthr > 0)
         hipLaunchKernelGGL(k_assemble_luo, dim3(cdiv(nthr, kAsmThreads)), dim3(kAsmThreads), 0, st, h->nnzb, h->N, h->F,
-                           h->src.get(), h->la.get(), h->ua.get(), h->cell_prim.get(), Sf,
+                           h->src.get(), h->col.get(), h->cell_prim.get(), Sf,
                            h->face_lam.get(), h->cell_acc.get(), v_dt, gamma, h->vals.get(), h->dflag.get());
     LAUNCHCHK();
     if (read_int(h->dflag.get(), st) & 4)
