@@ -192,7 +192,8 @@ int cbs_update_values(cbs_handle h, const double *diag, const double *upper, con
  * Interior faces only: boundary contributions belong in v_dt or come from
  * cbs_update_values.  Batched handles take the concatenated cells and faces.
  * Errors: CBS_ERR_ARG (bdim != 5, NULL Q, NULL Sf with faces, gamma <= 1),
- * CBS_ERR_NONFINITE (a state with non-positive density or pressure). */
+ * CBS_ERR_NONFINITE (a cell state with non-positive density or pressure, or
+ * a non-finite assembled coefficient). */
 int cbs_assemble_luo(cbs_handle h, const double *Q, const double *Sf, const double *lam_visc, const double *v_dt,
                      double gamma);
 

@@ -99,7 +99,7 @@ def _declare(L):
         "orc_grad": (None, [ci, ci, ci, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p]),
         "orc_euler_jac": (None, [_f64p, _f64p, cd, _f64p]),
         "orc_roe_radius": (cd, [_f64p, _f64p, _f64p, cd]),
-        "orc_luo_assemble": (None, [ci, ci, _i32p, _i32p, _f64p, _f64p, vp, vp, cd, _f64p, _f64p, _f64p]),
+        "orc_luo_assemble": (ci, [ci, ci, _i32p, _i32p, _f64p, _f64p, vp, vp, cd, _f64p, _f64p, _f64p]),
         "orc_pu_assemble": (None, [ci, ci, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, vp, vp,
                                    _f64p, _f64p, _f64p]),
     }
@@ -458,10 +458,12 @@ def luo_assemble(d, with_visc=True, with_dt=True):
         la = ua = np.zeros(1, np.int32); Sf = np.zeros(3)
     lv = _c64(d["lam_visc"]) if with_visc else None
     vd = _c64(d["v_dt"]) if with_dt else None
-    lib().orc_luo_assemble(N, F, la, ua, _c64(d["Q"]).ravel(), Sf,
-                           lv.ctypes.data if lv is not None else None,
-                           vd.ctypes.data if vd is not None else None,
-                           float(d["gamma"]), diag.ravel(), upper.ravel(), lower.ravel())
+    rc = lib().orc_luo_assemble(N, F, la, ua, _c64(d["Q"]).ravel(), Sf,
+                                lv.ctypes.data if lv is not None else None,
+                                vd.ctypes.data if vd is not None else None,
+                                float(d["gamma"]), diag.ravel(), upper.ravel(), lower.ravel())
+    if rc != OK:
+        raise OracleError(rc, "luo_assemble: a cell state with non-positive density or pressure")
     return {"N": N, "F": F, "n": 5, "lower_addr": d["lower_addr"], "upper_addr": d["upper_addr"],
             "diag": diag, "upper": upper[:F], "lower": lower[:F]}
 

@@ -1337,11 +1337,19 @@ double orc_roe_radius(const double *QL, const double *QR, const double *s, doubl
  * residual is antisymmetric in the normal), J being linear in it:
  *   A_ll += (J(Q_l, s) + S lambda I)/2,   A_lu += (J(Q_u, s) - S lambda I)/2,
  *   A_uu += (-J(Q_u, s) + S lambda I)/2,  A_ul += (-J(Q_l, s) - S lambda I)/2.
- * diag starts at v_dt[i] I (NULL: 0); lam_visc NULL: 0. */
-void orc_luo_assemble(int N, int F, const int *la, const int *ua, const double *Q, const double *Sf,
-                      const double *lam_visc, const double *v_dt, double gamma,
-                      double *diag, double *upper, double *lower)
+ * diag starts at v_dt[i] I (NULL: 0); lam_visc NULL: 0.
+ * Returns ORC_OK, or ORC_ERR_ARG (nothing written) when a cell's density or
+ * pressure is not positive: the sound speed of the face states, and with it
+ * the spectral radius, is then undefined. */
+int orc_luo_assemble(int N, int F, const int *la, const int *ua, const double *Q, const double *Sf,
+                     const double *lam_visc, const double *v_dt, double gamma,
+                     double *diag, double *upper, double *lower)
 {
+    for (int i = 0; i < N; i++) {
+        const double *q = Q + (long)i * 5;
+        double ke = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+        if (!(q[0] > 0.0) || !((gamma - 1.0) * (q[4] - ke) > 0.0)) return ORC_ERR_ARG;
+    }
     for (int i = 0; i < N; i++)
         for (int e = 0; e < 25; e++) diag[(long)i * 25 + e] = (e % 6 == 0) ? (v_dt ? v_dt[i] : 0.0) : 0.0;
     double JL[25], JU[25];
@@ -1360,6 +1368,7 @@ void orc_luo_assemble(int N, int F, const int *la, const int *ua, const double *
             lower[(long)f * 25 + e] = 0.5 * (-JL[e] - d);
         }
     }
+    return ORC_OK;
 }
 
 /* Assembly of the pressure-based (p, Ux, Uy, Uz) coupled matrix: the face

@@ -274,13 +274,18 @@ __global__ void k_values(int64_t total, int32_t N, int32_t F, const int32_t *src
 // Per cell, once: u, v, w, the total enthalpy H = (rho E + p)/rho and
 // phi = (gamma-1)|u|^2/2, from the conservative state Q = (rho, rho u,
 // rho v, rho w, rho E) of an ideal gas with p = (gamma-1)(rho E - rho|u|^2/2).
-__global__ void k_cell_prims(int32_t N, const double *Q, double g, double *prim) {
+// Per-cell primitives (u, v, w, H, phi).  A state whose density or pressure
+// is not positive (or not a number) sets bit 8 of flag: the Roe average and
+// the speed of sound are undefined there even when every coefficient that
+// comes out happens to be finite.
+__global__ void k_cell_prims(int32_t N, const double *Q, double g, double *prim, int32_t *flag) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double *q = Q + (int64_t)i * 5;
     const double rho = q[0], u = q[1] / rho, v = q[2] / rho, w = q[3] / rho;
     const double g1 = g - 1.0, q2 = u * u + v * v + w * w;
     const double p = g1 * (q[4] - 0.5 * rho * q2);
+    if (!(rho > 0.0) || !(p > 0.0)) atomicOr(flag, 8);
     double *o = prim + (int64_t)i * 5;
     o[0] = u; o[1] = v; o[2] = w; o[3] = (q[4] + p) / rho; o[4] = 0.5 * g1 * q2;
 }
@@ -625,7 +630,8 @@ void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double
     HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
     h->face_lam.ensure(h->F > 0 ? (size_t)h->F : 1);
     h->cell_prim.ensure((size_t)h->N * 5);
-    hipLaunchKernelGGL(k_cell_prims, dim3(cdiv(h->N, 256)), dim3(256), 0, st, h->N, Q, gamma, h->cell_prim.get());
+    hipLaunchKernelGGL(k_cell_prims, dim3(cdiv(h->N, 256)), dim3(256), 0, st, h->N, Q, gamma, h->cell_prim.get(),
+                       h->dflag.get());
     if (h->F > 0)
         hipLaunchKernelGGL(k_face_radius, dim3(cdiv(h->F, 256)), dim3(256), 0, st, h->F, h->la.get(), h->ua.get(), Q,
                            h->cell_prim.get(), Sf, lam_visc, gamma, h->face_lam.get());
@@ -638,9 +644,9 @@ void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double
                            h->src.get(), h->col.get(), h->cell_prim.get(), Sf,
                            h->face_lam.get(), h->cell_acc.get(), v_dt, gamma, h->vals.get(), h->dflag.get());
     LAUNCHCHK();
-    if (read_int(h->dflag.get(), st) & 4)
-        cbs_throw(CBS_ERR_NONFINITE, "non-finite assembled coefficient (check the states: pressure and density "
-                                     "must be positive)");
+    const int32_t fl = read_int(h->dflag.get(), st);
+    if (fl & 8) cbs_throw(CBS_ERR_NONFINITE, "a cell state with non-positive density or pressure");
+    if (fl & 4) cbs_throw(CBS_ERR_NONFINITE, "non-finite assembled coefficient");
 }
 
 void assemble_pu(cbs_system *h, const double *Sf, const double *fx, const double *d, const double *flux,

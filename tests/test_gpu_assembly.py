@@ -114,6 +114,23 @@ def test_assembly_rejects_unphysical_states_and_other_block_sizes():
         with pytest.raises(P.CbsError):
             sysm.assemble_luo(d["Q"], d["Sf"], None, None, 1.0)
         sysm.assemble_luo(d["Q"], d["Sf"], None, None, 1.4)      # the handle is still usable
+        # a mildly negative pressure whose coefficients all stay finite (the
+        # Roe average over each of its faces still has a positive c~^2)
+        rho = d["Q"][5, 0]
+        u = d["Q"][5, 1:4] / rho
+        Q = d["Q"].copy()
+        Q[5, 4] = -1e-2 / (d["gamma"] - 1.0) + 0.5 * rho * u @ u
+        with pytest.raises(O.OracleError):
+            O.luo_assemble(dict(d, Q=Q))
+        with pytest.raises(P.CbsError) as e:
+            sysm.assemble_luo(Q, d["Sf"], d["lam_visc"], d["v_dt"], d["gamma"])
+        assert e.value.code == P.ERR_NONFINITE
+        Q = d["Q"].copy()
+        Q[7, 0] = -Q[7, 0]                        # negative density
+        with pytest.raises(P.CbsError) as e:
+            sysm.assemble_luo(Q, d["Sf"], d["lam_visc"], d["v_dt"], d["gamma"])
+        assert e.value.code == P.ERR_NONFINITE
+        sysm.assemble_luo(d["Q"], d["Sf"], d["lam_visc"], d["v_dt"], d["gamma"])
     s4 = _blank(d)
     s4.update(n=4, diag=np.zeros((d["N"], 4, 4)), upper=np.zeros((d["F"], 4, 4)), lower=np.zeros((d["F"], 4, 4)))
     with P.System.from_dict(s4) as sysm:
