@@ -206,6 +206,9 @@ class System:
         _check(rc, "cbs_create")
         self.h = h
         self.options: Optional[Options] = None
+        # bumped by every call that changes the matrix or its preconditioner;
+        # the autograd backward refuses a System whose generation moved
+        self.generation = 0
 
     @classmethod
     def from_dict(cls, s):
@@ -231,6 +234,7 @@ class System:
     def update_values(self, diag, upper, lower):
         torch = _torch()
         d, u, lo = (_dev(a, torch.float64) for a in (diag, upper, lower))
+        self.generation += 1
         _check(lib().cbs_update_values(self.h, _ptr(d), _ptr(u), _ptr(lo)), "cbs_update_values")
 
     def assemble_luo(self, Q, Sf, lam_visc=None, v_dt=None, gamma=1.4):
@@ -240,6 +244,7 @@ class System:
         q, s = _dev(Q, torch.float64), _dev(Sf, torch.float64)
         lv = _dev(lam_visc, torch.float64) if lam_visc is not None else None
         vd = _dev(v_dt, torch.float64) if v_dt is not None else None
+        self.generation += 1
         _check(lib().cbs_assemble_luo(self.h, _ptr(q), _ptr(s), None if lv is None else _ptr(lv),
                                       None if vd is None else _ptr(vd), float(gamma)), "cbs_assemble_luo")
 
@@ -249,11 +254,13 @@ class System:
         torch = _torch()
         a = [_dev(x, torch.float64) for x in (Sf, fx, d, flux, nu_eff, vol)]
         opt = [None if x is None else _dev(x, torch.float64) for x in (uu_add, pp_add)]
+        self.generation += 1
         _check(lib().cbs_assemble_pu(self.h, *[_ptr(x) for x in a], *[None if x is None else _ptr(x) for x in opt]),
                "cbs_assemble_pu")
 
     def setup(self, options: Optional[Options] = None, **kw):
         o = options if options is not None else default_options(**kw)
+        self.generation += 1
         _check(lib().cbs_setup(self.h, C.byref(o)), "cbs_setup")
         self.options = o
         return self
@@ -368,6 +375,11 @@ def _coupled_solve_cls():
         given System (same pattern), sets it up with its options and solves.
         backward(g): lambda = A^{-T} g (transpose solve on the same
         aggregates); dL/db = lambda, dL/dA_ij = -lambda_i x_j^T on the pattern.
+        Both raise CbsError (code NOT_CONVERGED) when a solve stops at the
+        iteration cap, and backward raises RuntimeError when the System's
+        values or preconditioner changed after forward (another update,
+        assembly, setup or coupled_solve on it), since lambda would then be
+        the adjoint of another matrix.
         """
 
         @staticmethod
@@ -375,7 +387,9 @@ def _coupled_solve_cls():
             system.update_values(diag.detach(), upper.detach(), lower.detach())
             system.setup(system.options if system.options is not None else default_options())
             x, st = system.solve(b.detach())
+            _require_converged(st, "coupled_solve forward")
             ctx.system = system
+            ctx.generation = system.generation
             ctx.save_for_backward(x)
             ctx.stats = st
             return x
@@ -384,11 +398,22 @@ def _coupled_solve_cls():
         def backward(ctx, g):
             (x,) = ctx.saved_tensors
             system = ctx.system
-            lam, _ = system.solve_transpose(g.contiguous())
+            if system.generation != ctx.generation:
+                raise RuntimeError("coupled_solve backward: the System was updated or set up again after "
+                                   "forward; the adjoint would use another matrix")
+            lam, st = system.solve_transpose(g.contiguous())
+            _require_converged(st, "coupled_solve backward (transposed solve)")
             gd, gu, gl = system.gradient(lam, x)
             return None, gd, gu, gl, lam.reshape(g.shape)
 
     return CoupledSolve
+
+
+def _require_converged(st, where):
+    """Raise CbsError(NOT_CONVERGED) unless every system's status is OK."""
+    for s in (st if isinstance(st, list) else [st]):
+        if s["status"] != OK:
+            raise CbsError(int(s["status"]), where)
 
 
 _CS = None

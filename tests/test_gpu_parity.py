@@ -538,6 +538,30 @@ def test_autograd_matches_finite_differences():
     sysm.close()
 
 
+def test_autograd_refuses_stale_system_and_unconverged_solves():
+    """backward on a System updated after forward raises instead of returning
+    the adjoint of another matrix; a forward solve stopped at the iteration
+    cap raises instead of returning an unconverged x."""
+    _say("autograd guards")
+    s = pressure_velocity(5, 4, 4, seed=6)
+    dev = "cuda"
+    leaves = [torch.tensor(s[k], device=dev, requires_grad=True) for k in ("diag", "upper", "lower", "b")]
+    sysm = P.System.from_dict(s)
+    sysm.setup(precond=P.PREC_AMG, tol=1e-10, max_iter=2000)
+    x1 = P.coupled_solve(sysm, *leaves)
+    # a second solve on the same System (scaled matrix) before the first backward
+    x2 = P.coupled_solve(sysm, leaves[0] * 2.0, leaves[1] * 2.0, leaves[2] * 2.0, leaves[3])
+    with pytest.raises(RuntimeError, match="updated or set up again"):
+        x1.sum().backward(retain_graph=True)
+    x2.sum().backward()          # the latest forward is still differentiable
+    assert torch.isfinite(leaves[3].grad).all()
+    sysm.setup(precond=P.PREC_AMG, tol=1e-14, max_iter=1)
+    with pytest.raises(P.CbsError) as ei:
+        P.coupled_solve(sysm, *[t.detach() for t in leaves])
+    assert ei.value.code == P.NOT_CONVERGED
+    sysm.close()
+
+
 # ------------------------------------------------------------------ batching
 def test_batched_solve_matches_solo_solves():
     _say("batched")
