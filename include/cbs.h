@@ -197,6 +197,21 @@ int cbs_update_values(cbs_handle h, const double *diag, const double *upper, con
 int cbs_assemble_luo(cbs_handle h, const double *Q, const double *Sf, const double *lam_visc, const double *v_dt,
                      double gamma);
 
+/* cbs_assemble_luo for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as cbs_assemble_luo; the
+ * per-face and per-cell intermediates live in a fixed 64 MiB array that the
+ * library holds on every device it runs on until the process ends, instead
+ * of buffers of the handle.  No hipMalloc, hipFree or other allocating call
+ * is made.  Limit: 8 * (32 + F' + N5' + N4') bytes <= 64 MiB, where F', N5'
+ * and N4' are F, 5N and 4N rounded up to multiples of 32 (about 699,000 hex
+ * cells); a larger system returns CBS_ERR_ARG before any work.  Every call
+ * on one device shares that array: calls that overlap on one GPU (handles on
+ * different streams) race and must be serialised by the caller.  The handle
+ * must be used with the device current at its creation. */
+int cbs_assemble_luo_noalloc(cbs_handle h, const double *Q, const double *Sf, const double *lam_visc,
+                             const double *v_dt, double gamma);
+
 /* Assemble the pressure-based coupled matrix on the device, straight into
  * the handle's block-CSR values: the face coefficients of Sec. 2.2 (after
  * Eq. prb_coeff).  Takes the place of cbs_update_values.  Block size 4,

@@ -61,6 +61,7 @@ SIGNATURES = [
                                             _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cbs_update_values", C.c_int, [_VP, _VP, _VP, _VP]),
     ("cbs_assemble_luo", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_double]),
+    ("cbs_assemble_luo_noalloc", C.c_int, [_VP, _VP, _VP, _VP, _VP, C.c_double]),
     ("cbs_assemble_pu", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cbs_setup", C.c_int, [_VP, C.POINTER(Options)]),
     ("cbs_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
@@ -247,6 +248,18 @@ class System:
         self.generation += 1
         _check(lib().cbs_assemble_luo(self.h, _ptr(q), _ptr(s), None if lv is None else _ptr(lv),
                                       None if vd is None else _ptr(vd), float(gamma)), "cbs_assemble_luo")
+
+    def assemble_luo_noalloc(self, Q, Sf, lam_visc=None, v_dt=None, gamma=1.4):
+        """assemble_luo through cbs_assemble_luo_noalloc: the library's fixed
+        per-device scratch instead of handle buffers (no device allocation)."""
+        torch = _torch()
+        q, s = _dev(Q, torch.float64), _dev(Sf, torch.float64)
+        lv = _dev(lam_visc, torch.float64) if lam_visc is not None else None
+        vd = _dev(v_dt, torch.float64) if v_dt is not None else None
+        self.generation += 1
+        _check(lib().cbs_assemble_luo_noalloc(self.h, _ptr(q), _ptr(s), None if lv is None else _ptr(lv),
+                                              None if vd is None else _ptr(vd), float(gamma)),
+               "cbs_assemble_luo_noalloc")
 
     def assemble_pu(self, Sf, fx, d, flux, nu_eff, vol, uu_add=None, pp_add=None):
         """Assemble the pressure-based (p, U) coupled matrix on the device

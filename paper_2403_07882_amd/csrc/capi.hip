@@ -88,6 +88,7 @@ int create_common(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const
     std::unique_ptr<cbs_system> h(new cbs_system());
     h->N = (int32_t)N; h->F = (int32_t)F; h->n = bdim; h->n_sys = n_sys;
     h->stream = (hipStream_t)stream;
+    HIPCHK(hipGetDevice(&h->device));
     h->cell_off.assign(cell_off, cell_off + n_sys + 1);
     h->face_off.assign(face_off, face_off + n_sys + 1);
     HIPCHK(hipEventCreate(&h->ev0));
@@ -287,6 +288,28 @@ int cbs_assemble_luo(cbs_handle h, const double *Q, const double *Sf, const doub
         require(gamma > 1.0, CBS_ERR_ARG, "gamma must exceed 1");
         HIPCHK(hipEventRecord(h->ev0, h->stream));
         assemble_luo(h, Q, Sf, lam_visc, v_dt, gamma);
+        HIPCHK(hipEventRecord(h->ev1, h->stream));
+        h->t_convert_ms = elapsed_ms(h->ev0, h->ev1);
+        h->values_changed = true;
+        h->transposed_ready = false;
+        h->valsT.release();
+        h->usell.v64.release();
+        h->usell.v64T.release();
+        invalidate_graphs(h);
+        return CBS_OK;
+    });
+}
+
+int cbs_assemble_luo_noalloc(cbs_handle h, const double *Q, const double *Sf, const double *lam_visc,
+                             const double *v_dt, double gamma) {
+    return guarded([&] {
+        require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        set_alloc_stream(h->stream);
+        require(h->n == 5, CBS_ERR_ARG, "the density-based assembly needs 5 x 5 blocks");
+        require(Q != nullptr && (h->F == 0 || Sf != nullptr), CBS_ERR_ARG, "state or face arrays are NULL");
+        require(gamma > 1.0, CBS_ERR_ARG, "gamma must exceed 1");
+        HIPCHK(hipEventRecord(h->ev0, h->stream));
+        assemble_luo_noalloc(h, Q, Sf, lam_visc, v_dt, gamma);
         HIPCHK(hipEventRecord(h->ev1, h->stream));
         h->t_convert_ms = elapsed_ms(h->ev0, h->ev1);
         h->values_changed = true;

@@ -200,6 +200,7 @@ struct Coarse {
 // ---------------------------------------------------------------- handle
 struct cbs_system {
     int32_t N = 0, F = 0, n = 0, n_sys = 1;
+    int device = 0;                              // device current at creation (holds every buffer)
     hipStream_t stream = nullptr;
     std::vector<int64_t> cell_off, face_off;     // host
     // level-0 pattern and conversion maps
@@ -280,6 +281,12 @@ void convert_pattern(cbs_system *h);
 void convert_values(cbs_system *h, const double *diag, const double *upper, const double *lower);
 void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double *lam_visc, const double *v_dt,
                   double gamma);
+// allocation-free variant of assemble_luo on the library's fixed scratch
+// (kNoAllocScratchBytes per device; larger systems are refused)
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+size_t assemble_luo_scratch_bytes(int64_t N, int64_t F);
+void assemble_luo_noalloc(cbs_system *h, const double *Q, const double *Sf, const double *lam_visc,
+                          const double *v_dt, double gamma);
 void assemble_pu(cbs_system *h, const double *Sf, const double *fx, const double *d, const double *flux,
                  const double *nu, const double *vol, const double *uu_add, const double *pp_add);
 void check_finite(const double *a, int64_t count, int32_t *dflag, hipStream_t st);

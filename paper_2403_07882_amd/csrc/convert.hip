@@ -10,6 +10,9 @@
 //     element for element (bit-exact), writes fully coalesced.
 #include "cbs_internal.h"
 
+#include <mutex>
+#include <string>
+
 #include <algorithm>
 
 // ------------------------------------------------------------------ scan
@@ -623,6 +626,31 @@ void convert_values(cbs_system *h, const double *diag, const double *upper, cons
     if (read_int(h->dflag.get(), st) & 4) cbs_throw(CBS_ERR_NONFINITE, "non-finite matrix coefficient");
 }
 
+// The four density-based assembly passes on caller-supplied scratch:
+// face_lam[F], prim[5N], acc[4N] (each fully written before it is read) and
+// an int32 flag that must be zero on entry.
+static void assemble_luo_on(cbs_system *h, const double *Q, const double *Sf, const double *lam_visc,
+                            const double *v_dt, double gamma, double *face_lam, double *prim, double *acc,
+                            int32_t *flag) {
+    hipStream_t st = h->stream;
+    hipLaunchKernelGGL(k_cell_prims, dim3(cdiv(h->N, 256)), dim3(256), 0, st, h->N, Q, gamma, prim, flag);
+    if (h->F > 0)
+        hipLaunchKernelGGL(k_face_radius, dim3(cdiv(h->F, 256)), dim3(256), 0, st, h->F, h->la.get(), h->ua.get(), Q,
+                           prim, Sf, lam_visc, gamma, face_lam);
+    hipLaunchKernelGGL(k_cell_faces, dim3(cdiv(h->N, 256)), dim3(256), 0, st, h->N, h->F, h->rp.get(), h->src.get(),
+                       Sf, face_lam, acc);
+    const int64_t nthr = h->nnzb * 5;
+    if (nthr > 0)
+        hipLaunchKernelGGL(k_assemble_luo, dim3(cdiv(nthr, kAsmThreads)), dim3(kAsmThreads), 0, st, h->nnzb, h->N, h->F,
+                           h->src.get(), h->col.get(), prim, Sf, face_lam, acc, v_dt, gamma, h->vals.get(), flag);
+    LAUNCHCHK();
+}
+
+static void luo_flag_errors(int32_t fl) {
+    if (fl & 8) cbs_throw(CBS_ERR_NONFINITE, "a cell state with non-positive density or pressure");
+    if (fl & 4) cbs_throw(CBS_ERR_NONFINITE, "non-finite assembled coefficient");
+}
+
 void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double *lam_visc, const double *v_dt,
                   double gamma) {
     hipStream_t st = h->stream;
@@ -630,23 +658,74 @@ void assemble_luo(cbs_system *h, const double *Q, const double *Sf, const double
     HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
     h->face_lam.ensure(h->F > 0 ? (size_t)h->F : 1);
     h->cell_prim.ensure((size_t)h->N * 5);
-    hipLaunchKernelGGL(k_cell_prims, dim3(cdiv(h->N, 256)), dim3(256), 0, st, h->N, Q, gamma, h->cell_prim.get(),
-                       h->dflag.get());
-    if (h->F > 0)
-        hipLaunchKernelGGL(k_face_radius, dim3(cdiv(h->F, 256)), dim3(256), 0, st, h->F, h->la.get(), h->ua.get(), Q,
-                           h->cell_prim.get(), Sf, lam_visc, gamma, h->face_lam.get());
     h->cell_acc.ensure((size_t)h->N * 4);
-    hipLaunchKernelGGL(k_cell_faces, dim3(cdiv(h->N, 256)), dim3(256), 0, st, h->N, h->F, h->rp.get(), h->src.get(),
-                       Sf, h->face_lam.get(), h->cell_acc.get());
-    const int64_t nthr = h->nnzb * 5;
-    if (nthr > 0)
-        hipLaunchKernelGGL(k_assemble_luo, dim3(cdiv(nthr, kAsmThreads)), dim3(kAsmThreads), 0, st, h->nnzb, h->N, h->F,
-                           h->src.get(), h->col.get(), h->cell_prim.get(), Sf,
-                           h->face_lam.get(), h->cell_acc.get(), v_dt, gamma, h->vals.get(), h->dflag.get());
-    LAUNCHCHK();
-    const int32_t fl = read_int(h->dflag.get(), st);
-    if (fl & 8) cbs_throw(CBS_ERR_NONFINITE, "a cell state with non-positive density or pressure");
-    if (fl & 4) cbs_throw(CBS_ERR_NONFINITE, "non-finite assembled coefficient");
+    assemble_luo_on(h, Q, Sf, lam_visc, v_dt, gamma, h->face_lam.get(), h->cell_prim.get(), h->cell_acc.get(),
+                    h->dflag.get());
+    luo_flag_errors(read_int(h->dflag.get(), st));
+}
+
+// ------------------------------------------- assembly without allocation
+// The density-based assembly for callers that cannot allocate device memory:
+// its per-face and per-cell passes run on a fixed array that the library
+// holds on every device it runs on, for the life of the process.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in symbol); the device address comes from hipGetSymbolAddress, once
+// per device, with that device current.
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+double *scratch_on(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) cbs_throw(CBS_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(hipSetDevice(dev));
+        double *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void **>(&p), HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            cbs_throw(CBS_ERR_HIP, std::string("hipGetSymbolAddress of the assembly scratch failed: ") +
+                                       hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// doubles of each scratch segment, rounded up to 256 bytes
+inline size_t seg(size_t count) { return (count + 31) & ~(size_t)31; }
+}  // namespace
+
+size_t assemble_luo_scratch_bytes(int64_t N, int64_t F) {
+    return (seg(1) + seg((size_t)(F > 0 ? F : 1)) + seg((size_t)N * 5) + seg((size_t)N * 4)) * sizeof(double);
+}
+
+void assemble_luo_noalloc(cbs_system *h, const double *Q, const double *Sf, const double *lam_visc,
+                          const double *v_dt, double gamma) {
+    const size_t need = assemble_luo_scratch_bytes(h->N, h->F);
+    if (need > kNoAllocScratchBytes)
+        cbs_throw(CBS_ERR_ARG, "the system needs " + std::to_string(need) + " bytes of assembly scratch, more than the " +
+                                   std::to_string(kNoAllocScratchBytes) + " the allocation-free assembly holds");
+    if (h->vals.n < (size_t)h->nnzb * 25) cbs_throw(CBS_ERR_STATE, "block-CSR values are not allocated");
+    hipStream_t st = h->stream;
+    double *base = scratch_on(h->device);
+    int32_t *flag = reinterpret_cast<int32_t *>(base);
+    double *face_lam = base + seg(1);
+    double *prim = face_lam + seg((size_t)(h->F > 0 ? h->F : 1));
+    double *acc = prim + seg((size_t)h->N * 5);
+    // the flag keeps the last call's value: clear it with a kernel
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, flag, (int64_t)1, 0);
+    assemble_luo_on(h, Q, Sf, lam_visc, v_dt, gamma, face_lam, prim, acc, flag);
+    int32_t fl = 0;
+    HIPCHK(hipMemcpyAsync(&fl, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    luo_flag_errors(fl);
 }
 
 void assemble_pu(cbs_system *h, const double *Sf, const double *fx, const double *d, const double *flux,
