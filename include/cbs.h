@@ -121,6 +121,14 @@ typedef struct cbs_options {
                                 in one workgroup (one kernel instead of about
                                 five per level); 0 = 256, < 0 = never. Changes
                                 only the order of the row sums       [0] */
+    int32_t schedule;        /* schedule of the block-row kernels (blocks
+                                loaded per step, non-temporal matrix loads):
+                                0 = timed on the level-0 operator at setup
+                                (levels of >= 65,536 block rows); 1..6 force
+                                (unroll, non-temporal) = (1,0), (1,1), (2,0),
+                                (2,1), (4,0), (4,1) on every level in both
+                                precisions. Changes only the order of
+                                the row sums                         [0] */
 } cbs_options;
 
 /* Per-solve statistics (Algorithm amgxFoam: iterations and residuals). */
@@ -130,7 +138,11 @@ typedef struct cbs_stats {
     int32_t levels;              /* AMG levels (1 = no coarsening) */
     int32_t precision_fallback;  /* 1 if a mixed solve escalated to FP64 */
     double rel_res_true;         /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
-    double rel_res_recursive;    /* the Krylov recurrence's estimate at exit */
+    double rel_res_recursive;    /* the Krylov recurrence's estimate where the
+                                    solver stopped, before the true residual is
+                                    recomputed (BiCGStab: the updated r;
+                                    (F)GMRES: the least-squares residual of the
+                                    last cycle) */
     double rel_res_initial;      /* ||b - A x0|| / ||b|| */
     double t_convert_ms;         /* last LDU -> block-CSR value conversion */
     double t_setup_ms;           /* last cbs_setup */

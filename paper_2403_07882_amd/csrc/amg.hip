@@ -1331,7 +1331,7 @@ void amg_setup(cbs_system *h) {
         h->lev.resize(1);
         sell_build(L0.N, L0.rp, L0.col, L0.sell, st);
         level_sell(h, L0, false, nullptr);
-        L0.sell.sched64 = autotune_rows(n, L0.sell, false, L0.sell.v64.get(), st);
+        L0.sell.sched64 = choose_sched(n, L0.sell, false, L0.sell.v64.get(), o.schedule, st);
         L0.sell.sched64.split = row_split_for(L0.sell, L0.nnzb, o.row_split);
         h->op_complexity = 1.0;
         return;
@@ -1481,8 +1481,8 @@ void amg_setup(cbs_system *h) {
     {
         // schedules of the block-row kernels, tuned on level 0, used on every level
         Level &T0 = h->lev[0];
-        const Sched s64 = autotune_rows(n, T0.sell, false, T0.sell.v64.get(), st);
-        const Sched s32 = mixed ? autotune_rows(n, T0.sell, true, T0.sell.v32.get(), st) : Sched{4, 1};
+        const Sched s64 = choose_sched(n, T0.sell, false, T0.sell.v64.get(), o.schedule, st);
+        const Sched s32 = mixed ? choose_sched(n, T0.sell, true, T0.sell.v32.get(), o.schedule, st) : Sched{4, 1};
         for (auto &L : h->lev) {
             L.sell.sched64 = L.sod.sched64 = s64;
             L.sell.sched32 = L.sod.sched32 = s32;
@@ -1694,7 +1694,7 @@ void spmv_user(cbs_system *h, const double *x, double *y, bool transposed) {
             sell_fill(n, U, h->vals.get(), U.v64.get(), h->stream);
         }
         if (tune) {
-            U.sched64 = autotune_rows(n, U, false, U.v64.get(), h->stream);
+            U.sched64 = choose_sched(n, U, false, U.v64.get(), h->opt.schedule, h->stream);
             U.sched64.split = row_split_for(U, h->nnzb, h->opt.row_split);
         }
         launch_rows<double, double>(0, n, U.view(), U.v64.get(), x, nullptr, y, nullptr, 0.0, h->stream);

@@ -238,6 +238,7 @@ void cbs_default_options(cbs_options *o) {
     o->dilu_levels = 2;
     o->row_split = 0;
     o->tail_rows = 0;
+    o->schedule = 0;
 }
 
 int cbs_create_from_ldu(cbs_handle *out, int32_t n_cells, int32_t n_faces, int32_t bdim, const int32_t *lower_addr,
@@ -364,6 +365,7 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
         require(o.row_split == 0 || o.row_split == 1 || o.row_split == 2 || o.row_split == 4 ||
                     o.row_split == 8 || o.row_split == 16,
                 CBS_ERR_ARG, "row_split must be 0, 1, 2, 4, 8 or 16");
+        require(o.schedule >= 0 && o.schedule <= 6, CBS_ERR_ARG, "schedule must be in 0..6");
         const bool keep = o.reuse_aggregates && h->setup_done && h->opt.precision == o.precision &&
                           h->opt.precond == o.precond && h->opt.smoother == o.smoother &&
                           h->opt.coarse_max == o.coarse_max && h->opt.match_passes == o.match_passes &&

@@ -85,6 +85,7 @@ constexpr int kVecThreads = 256;      // threads per element-wise workgroup
 enum {
     S_RHO = 0, S_RHO0, S_ALPHA, S_OMEGA, S_RV, S_TS, S_TT, S_RR, S_BB, S_RES0, S_SS,
     S_RRPREV,               // ||r||^2 one iteration earlier (convergence forecast)
+    S_RREC,                 // the recurrence's ||r||^2 when the solver stopped (statistics)
     S_NSCAL
 };
 
@@ -322,6 +323,8 @@ void launch_restrict_sweep0(int n, int32_t nc, const int32_t *agg_ptr, const int
                             const double *Dinv, double omega, TX *x, TX *c, hipStream_t st);
 // time the schedules of the residual kernel on S (cached per shape)
 Sched autotune_rows(int n, const Sell &S, bool fp32, const void *val, hipStream_t st);
+// the schedule option: 0 = autotune_rows, 1..6 = a forced (unroll, non-temporal) pair
+Sched choose_sched(int n, const Sell &S, bool fp32, const void *val, int32_t forced, hipStream_t st);
 // threads per scalar row of the block-row kernels on a level (row_split option)
 int8_t row_split_for(const Sell &S, int64_t nblocks, int32_t opt_split);
 // sliced-ELL pattern from BCSR (offdiag: without the diagonal blocks), and

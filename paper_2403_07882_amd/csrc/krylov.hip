@@ -659,6 +659,14 @@ void read_state(cbs_system *h, HostView &hv, bool with_scal) {
     HIPCHK(hipStreamSynchronize(st));
 }
 
+// keep the recurrence's ||r||^2 (S_RR) of every system in S_RREC before a
+// true residual overwrites it
+void save_recursive(cbs_system *h) {
+    const int nsys = h->n_sys;
+    HIPCHK(hipMemcpyAsync(h->scal.get() + (size_t)S_RREC * nsys, h->scal.get() + (size_t)S_RR * nsys,
+                          sizeof(double) * nsys, hipMemcpyDeviceToDevice, h->stream));
+}
+
 // true residual r = b - A x of every system -> S_RR
 void true_residual(cbs_system *h, const double *b, const double *x, bool tr) {
     residual64(h, b, x, h->r.get(), tr);
@@ -814,6 +822,7 @@ int bicgstab(cbs_system *h, const double *b, double *x, bool tr, std::vector<int
             }
             if (all_done) {
                 // verify with the true residual; restart systems that fall short
+                save_recursive(h);
                 true_residual(h, b, x, tr);
                 read_state(h, hv, true);
                 std::vector<int32_t> mask(nsys, 0);
@@ -834,7 +843,7 @@ int bicgstab(cbs_system *h, const double *b, double *x, bool tr, std::vector<int
                 continue;
             }
         }
-        if (it >= o.max_iter) break;
+        if (it >= o.max_iter) { save_recursive(h); break; }
         if (check) {
             // Near convergence (every unfinished system flagged by the end of
             // the last iteration) run the iteration in halves: if every
@@ -892,11 +901,17 @@ int fgmres(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> 
     int32_t *iters = iters_ptr(h);
     HIPCHK(hipMemsetAsync(iters, 0, sizeof(int32_t) * nsys, st));
     for (;;) {
+        // the least-squares residual of the last cycle (the first cycle: the
+        // initial true residual, saved below) before the restart replaces it
+        if (!first) save_recursive(h);
         residual64(h, b, x, r, tr);
         dots(h, 2, r, r, b, b, nullptr, nullptr, done_none(h));
         hipLaunchKernelGGL(k_gm_start, GS, BS, 0, st, nsys, m, h->item_off.get(), h->n_items, h->partial.get(),
                            h->scal.get(), h->gvec.get(), h->done.get(), h->flags.get() + 3 * nsys, tol2, first ? 1 : 0);
-        if (first) hipLaunchKernelGGL(k_zero_if_bzero, G, B, 0, st, items, nsys, h->scal.get(), x);
+        if (first) {
+            hipLaunchKernelGGL(k_zero_if_bzero, G, B, 0, st, items, nsys, h->scal.get(), x);
+            save_recursive(h);
+        }
         first = false;
         read_state(h, hv, false);
         bool all_done = true;
@@ -1024,7 +1039,7 @@ int krylov_solve(cbs_system *h, const double *b, double *x, cbs_stats *stv, bool
         HostView hv;
         read_state(h, hv, true);
         for (int s = 0; s < nsys; ++s) {
-            rr_rec[s] = hv.scal[S_RR * nsys + s];
+            rr_rec[s] = hv.scal[S_RREC * nsys + s];
             res0[s] = hv.scal[S_RES0 * nsys + s];
             bbv[s] = hv.scal[S_BB * nsys + s];
         }

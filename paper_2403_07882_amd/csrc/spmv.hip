@@ -1017,6 +1017,14 @@ int8_t row_split_for(const Sell &S, int64_t nblocks, int32_t opt_split) {
     return (int8_t)s;
 }
 
+Sched choose_sched(int n, const Sell &S, bool fp32, const void *val, int32_t forced, hipStream_t st) {
+    if (forced >= 1 && forced <= 6) {
+        static const int8_t unroll[3] = {1, 2, 4};
+        return Sched{unroll[(forced - 1) / 2], (int8_t)((forced - 1) % 2)};
+    }
+    return autotune_rows(n, S, fp32, val, st);
+}
+
 Sched autotune_rows(int n, const Sell &S, bool fp32, const void *val, hipStream_t st) {
     const auto key = std::make_tuple(S.N, S.nent, n, fp32);
     {

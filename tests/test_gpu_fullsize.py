@@ -34,6 +34,51 @@ def _relres_ldu(s, x):
     return float(np.linalg.norm(r) / np.linalg.norm(s["b"]))
 
 
+def test_headline_pressure_velocity_1M_mixed_bicgstab():
+    """The benchmark workload at full size: the 100^3 jittered, randomly
+    renumbered p-U system (Sec. 2.2, Eq. coupl_system), mixed-precision
+    AMG-BiCGStab with the benchmark's options to 1e-8.  Checks: the relative
+    residual recomputed by the oracle's face-loop product; the reported true
+    residual equals it; the Krylov recurrence's residual agrees with the true
+    one within 10 tol; no escalation to FP64; and (reading R5) a verification
+    solve of the same GPU path at 1e-11 lies within 1e-6 of the oracle's own
+    AMG-BiCGStab solution at 1e-12."""
+    t0 = time.time()
+    s = pressure_velocity(100, 100, 100, seed=0)
+    _say("generated 1M p-U system in %.1f s" % (time.time() - t0))
+    tol = 1e-8
+    opt = dict(precision=P.PRECISION_MIXED, solver=P.SOLVER_BICGSTAB, precond=P.PREC_AMG, tol=tol,
+               max_iter=500, omega=0.9, pre_sweeps=2, post_sweeps=2, coarse_max=16, match_passes=2)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(**opt)
+        x, st = sysm.solve(s["b"])
+        _say("gpu 1e-8:", st)
+        assert st["status"] == P.OK and st["precision_fallback"] == 0, st
+        xn = _np(x)
+        rr = _relres_ldu(s, xn)
+        _say("oracle relres %.3e" % rr)
+        assert rr <= tol * 1.0001
+        assert abs(rr - st["rel_res_true"]) <= 1e-3 * tol
+        assert abs(st["rel_res_recursive"] - st["rel_res_true"]) <= 10 * tol
+        sysm.setup(**dict(opt, tol=1e-11, max_iter=2000))
+        xv, stv = sysm.solve(s["b"])
+        _say("gpu 1e-11:", stv)
+        assert stv["status"] == P.OK and stv["precision_fallback"] == 0, stv
+        xv = _np(xv)
+    assert _relres_ldu(s, xv) <= 1e-11 * 1.0001
+    t0 = time.time()
+    A = O.from_system(s)
+    amg = O.AMG(A, coarse_max=16, passes=2, smoother=O.SMOOTH_BJACOBI, nu1=2, nu2=2, omega=0.9)
+    xr, sto = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=amg, tol=1e-12, maxit=2000)
+    _say("oracle AMG-BiCGStab to 1e-12: %d iterations, %.1f s" % (sto["iterations"], time.time() - t0))
+    assert sto["status"] == O.OK and O.relres(A, s["b"], xr) <= 1e-12 * 1.0001
+    nr = np.linalg.norm(xr)
+    e11 = np.linalg.norm(xv - xr) / nr
+    e8 = np.linalg.norm(xn - xr) / nr
+    _say("solution error vs oracle: 1e-11 solve %.3e, 1e-8 solve %.3e (reported)" % (e11, e8))
+    assert e11 <= 1e-6
+
+
 def test_stretched_density_8M_mixed_fgmres():
     """200^3 boundary-layer mesh (aspect ratio up to 1e3), 5x5 blocks, 8M cells:
     mixed-precision AMG-FGMRES(30) to 1e-8."""

@@ -28,6 +28,13 @@ def _say(*a):
 def _np(t):
     return t.detach().cpu().numpy()
 
+def _agree(z, zr, rel):
+    """z against the reference zr: in norm, and element by element relative
+    to the largest reference entry."""
+    assert np.linalg.norm(z - zr) <= rel * np.linalg.norm(zr), (np.linalg.norm(z - zr), np.linalg.norm(zr))
+    assert np.abs(z - zr).max() <= rel * np.abs(zr).max(), (np.abs(z - zr).max(), np.abs(zr).max())
+
+
 
 def _ref_solution(A, b):
     x, st = O.fgmres(A, b, prec=O.PREC_BJACOBI, tol=1e-12, maxit=20000, restart=60)
@@ -188,6 +195,10 @@ def test_amg_solve_pressure_velocity(precision, solver):
         assert st["status"] == P.OK and st["levels"] > 1, st
         assert st["precision_fallback"] == 0, st          # the FP32 hierarchy really ran
         rr, _ = _check_solution(A, s["b"], _np(x), xref, err=1e-5)
+        # residual-norm invariant: the recurrence's residual where the solver
+        # stopped agrees with the true one within 10 tol
+        assert st["rel_res_recursive"] <= 1e-8 * 1.0001, st
+        assert abs(st["rel_res_recursive"] - st["rel_res_true"]) <= 10 * 1e-8, st
         # tighter verification solve for the 1e-6 solution-error bar
         sysm.setup(precond=P.PREC_AMG, precision=precision, solver=solver, tol=1e-11)
         x2, st2 = sysm.solve(s["b"])
@@ -243,6 +254,8 @@ def test_iteration_cap_not_converged():
         x, st = sysm.solve(s["b"])
     assert st["status"] == P.NOT_CONVERGED and st["iterations"] == 2
     assert abs(st["rel_res_true"] - O.relres(O.from_system(s), s["b"], _np(x))) <= 1e-12
+    # two steps of the recurrence: its residual is the true one up to rounding
+    assert abs(st["rel_res_recursive"] - st["rel_res_true"]) <= 1e-8 * st["rel_res_true"], st
 
 
 def test_solve_is_deterministic():
@@ -299,7 +312,7 @@ def test_rap_and_vcycle_match_oracle_given_gpu_aggregates(renumber, split):
         z = _np(sysm.apply_precond(r))
     zr_int = amg.apply(r[order])
     zr = np.empty_like(zr_int); zr[order] = zr_int
-    assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+    _agree(z, zr, 1e-11)
 
 
 @pytest.mark.parametrize("split,pre,post", [(0, 2, 2), (16, 2, 2), (0, 1, 3), (0, 0, 2)])
@@ -325,7 +338,7 @@ def test_mixed_vcycle_matches_fp64_oracle_vcycle(split, pre, post):
     amg = O.AMG(A0, nu1=pre, nu2=post, omega=0.9, aggs=aggs)
     zr_int = amg.apply(r[order])
     zr = np.empty_like(zr_int); zr[order] = zr_int
-    assert np.linalg.norm(z - zr) <= 1e-5 * np.linalg.norm(zr)
+    _agree(z, zr, 1e-5)
 
 
 @pytest.mark.parametrize("renumber", [0, 1])
@@ -373,7 +386,7 @@ def test_values_only_resetup_keeps_the_hierarchy(renumber):
         amg = O.AMG(A0, nu1=1, nu2=1, omega=0.8, aggs=aggs)
         zr_int = amg.apply(r[order])
         zr = np.empty_like(zr_int); zr[order] = zr_int
-        assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+        _agree(z, zr, 1e-11)
         x, st = sysm.solve(s2["b"])
         assert st["status"] == P.OK, st
         assert O.relres(A2, s2["b"], _np(x)) <= 1e-8 * 1.0001
@@ -675,7 +688,7 @@ def _coloured_vcycle_case(s, dilu_levels, smoother):
         z = _np(sysm.apply_precond(r))
     zr_int = amg.apply(r[order])
     zr = np.empty_like(zr_int); zr[order] = zr_int
-    assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+    _agree(z, zr, 1e-11)
     if smoother == P.SMOOTH_ILU0:        # the same cycle with DILU is a different operator
         zd = O.AMG(A0, nu1=1, nu2=1, omega=0.8, aggs=aggs, smoother=O.SMOOTH_DILU, ranks=ranks,
                    dilu_levels=ndilu).apply(r[order])
@@ -718,7 +731,7 @@ def test_ilu0_transposed_vcycle_is_the_ilu0_of_the_transpose(precision):
     zr_int = amg.apply(r[order])
     zr = np.empty_like(zr_int); zr[order] = zr_int
     tol = 1e-11 if precision == P.PRECISION_FP64 else 1e-5
-    assert np.linalg.norm(zt - zr) <= tol * np.linalg.norm(zr)
+    _agree(zt, zr, tol)
 
 
 @pytest.mark.parametrize("smoother", [P.SMOOTH_DILU, P.SMOOTH_SGS, P.SMOOTH_ILU0])
@@ -771,7 +784,7 @@ def test_amg_on_graph_with_long_rows(tail):
     zr_int = O.AMG(A0, nu1=2, nu2=2, omega=0.9, aggs=aggs).apply(r[order])
     zr = np.empty_like(zr_int)
     zr[order] = zr_int
-    assert np.linalg.norm(z - zr) <= 1e-11 * np.linalg.norm(zr)
+    _agree(z, zr, 1e-11)
     assert st["status"] == P.OK and st["precision_fallback"] == 0, st
     _check_solution(A, s["b"], _np(x), xref, tol=1e-9, err=1e-6)
     assert stt["status"] == P.OK, stt
@@ -844,7 +857,7 @@ def test_sgs_preconditioner_matches_oracle(n, sweeps):
         zr_int = O.SGSPrec(A, rank, sweeps=sweeps).apply(r[order])
         zr = np.empty_like(zr_int)
         zr[order] = zr_int
-        assert np.linalg.norm(got - zr) <= 1e-12 * np.linalg.norm(zr)
+        _agree(got, zr, 1e-12)
     assert np.linalg.norm(z - zt) > 1e-6 * np.linalg.norm(z)
 
 
