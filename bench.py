@@ -33,11 +33,19 @@ def seeded_normal(torch, count, dtype, dev, seed):
     g.manual_seed(seed)
     return torch.randn(count, dtype=dtype, device=dev, generator=g)
 
-# HBM bytes per launch on the 100x100x100 p-U system, from FETCH_SIZE and
+# Bytes per launch on the 100x100x100 p-U system, from FETCH_SIZE and
 # WRITE_SIZE counter runs of `bench.py --kernels-only`, each scaled by what the
-# counter reads for a 1 GiB copy (see profiles/); None where not measured for
-# the current kernel code.
+# counter reads for a 1 GiB copy (profiles/level_kernels_pu1M_hbm_counters.md);
+# None where not measured for the current kernel code.  These counters count
+# requests from the L2 to the memory fabric, which the 256 MB Infinity Cache
+# (MALL) in front of HBM serves in part, so they bound HBM traffic from above.
 TRAFFIC_PU1M = {"sweep": 542211430, "spmv_internal": 1129018598, "spmv_caller": 1713295565}
+TRAFFIC_KIND = ("L2-to-memory-fabric bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated); the Infinity "
+                "Cache serves part of them, so HBM itself moves at most this much")
+# Average duration of the same kernels inside timed bench steps (rocprofv3
+# --kernel-trace of the default run, profiles/bench_pu1M_kernel_stats.md);
+# None where not measured for the current kernel code.
+IN_STEP_US_PU1M = {"sweep": 83.84, "spmv_internal": 179.87, "spmv_caller": None}
 
 
 def parse():
@@ -47,7 +55,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mesh", type=int, nargs=3, default=[100, 100, 100])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, nargs=3, default=[80, 80, 80])
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (8M stretched density-based, 64-system batch, 2M adjoint)")
     ap.add_argument("--precond", choices=["amg", "sgs"], default="amg",
                     help="sgs: multicolour symmetric block Gauss-Seidel as the whole preconditioner")
     ap.add_argument("--max-iter", type=int, default=500)
@@ -96,25 +105,77 @@ def sweep_bytes(N, nnzb, n, s=4, dinv=False):
     return (nnzb - N) * (n * n * s + 4) + (N + 1) * 4 + 3 * N * n * s
 
 
-def cpu_baseline(shape):
+def _host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(s, reps_max=3, budget_s=60.0):
+    """The CPU oracle on the same system as the GPU step: LDU -> block CSR,
+    reference AMG setup (block Jacobi V(2,2), omega 0.9, coarse_max 16, two
+    matching passes) and BiCGStab to 1e-8, FP64, with the OpenMP threads of
+    the host.  One warm-up run, then the median of up to three runs (fewer
+    when three would exceed the time budget).  Also one thread: conversion,
+    setup and the first 5 iterations (the full solve would take minutes)."""
+    import ctypes as C
     import oracle as O
-    from workloads import pressure_velocity
-    s = pressure_velocity(*shape, seed=0)
-    A = O.from_system(s)
-    t0 = time.perf_counter()
-    amg = O.AMG(A, coarse_max=16, passes=2, smoother=O.SMOOTH_BJACOBI, nu1=2, nu2=2, omega=0.9)
-    x, st = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=amg, tol=1e-8, maxit=500)
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    O.lib()
+    gomp = C.CDLL("libgomp.so.1")            # the OpenMP runtime liboracle.so runs on
+    threads = int(gomp.omp_get_max_threads())
+
+    def run(maxit=500):
+        t0 = time.perf_counter()
+        A = O.from_system(s)
+        t1 = time.perf_counter()
+        amg = O.AMG(A, coarse_max=16, passes=2, smoother=O.SMOOTH_BJACOBI, nu1=2, nu2=2, omega=0.9)
+        t2 = time.perf_counter()
+        _, st = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=amg, tol=1e-8, maxit=maxit)
+        t3 = time.perf_counter()
+        del amg, A
+        return {"total_s": t3 - t0, "convert_s": t1 - t0, "setup_s": t2 - t1, "solve_s": t3 - t2,
+                "iterations": st["iterations"], "relres": st["relres"]}
+
+    warm = run()
+    log("cpu oracle warm-up: %.2f s (%d iterations)" % (warm["total_s"], warm["iterations"]))
+    reps = reps_max if reps_max * warm["total_s"] <= budget_s else 1
+    runs = [run() for _ in range(reps)]
+    tot = sorted(r["total_s"] for r in runs)
+    med = tot[len(tot) // 2]
+    mid = [r for r in runs if r["total_s"] == med][0]
+    log("cpu oracle: median %.2f s of %d runs, %d threads" % (med, reps, threads))
+    gomp.omp_set_num_threads(1)
+    try:
+        one = run(maxit=5)
+    finally:
+        gomp.omp_set_num_threads(threads)
+    log("cpu oracle, 1 thread: setup %.2f s, %.3f s per iteration" % (one["convert_s"] + one["setup_s"],
+                                                                     one["solve_s"] / max(1, one["iterations"])))
     return {
-        "value": dt * 1e3 * (1_000_000 / s["N"]),
-        "unit": "ms per 1M-cell solve (scaled)",
+        "value": round(med * 1e3, 1),
+        "unit": "ms per solve (LDU conversion + AMG setup + BiCGStab to 1e-8)",
         "cores": threads,
         "kind": "oracle",
-        "sample": "oracle AMG(block-Jacobi V(2,2), omega 0.9)-BiCGStab FP64 setup+solve to 1e-8 on the same "
-                  "pressure-velocity construction at %dx%dx%d (%d cells, %d iterations, %.2f s), "
-                  "scaled linearly to 1M cells" % (*shape, s["N"], st["iterations"], dt),
-        "measured_s": dt,
+        "sample": "the whole bench system (%d cells): oracle LDU -> block CSR, reference AMG setup (block-Jacobi "
+                  "V(2,2), omega 0.9) and BiCGStab to 1e-8 in FP64 on %d OpenMP threads; one warm-up run, then the "
+                  "median of %d runs" % (s["N"], threads, reps),
+        "runs_s": [round(r["total_s"], 3) for r in runs],
+        "iterations": mid["iterations"],
+        "phases_s": {k: round(mid[k], 3) for k in ("convert_s", "setup_s", "solve_s")},
+        "one_thread": {"convert_setup_s": round(one["convert_s"] + one["setup_s"], 3),
+                       "iterations_timed": one["iterations"],
+                       "s_per_iteration": round(one["solve_s"] / max(1, one["iterations"]), 4),
+                       "sample": "1 OpenMP thread: conversion, setup and the first %d BiCGStab iterations on the "
+                                 "same system" % one["iterations"]},
+        "host": _host_cpu(),
     }
 
 
@@ -259,6 +320,125 @@ def assembly_only(args, P, torch, dev):
                       "algorithmic_bytes_pu_assemble": int(pbytes), "pu_ldu_convert_ms": round(pconv_ms, 4)}))
 
 
+def level_kobj(name, ms, nbytes):
+    gb = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gb / HBM_PEAK_GBS, 4), "avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes": int(nbytes)}
+
+
+def measure_system(P, torch, dev, s, opt, steps, key, name, transposed=False):
+    """Upload one generated system (or batch), then time `steps` steps of
+    update_values + setup + solve from x0 = 0 (after one warm-up step), and
+    the level-0 block-Jacobi sweep and FP64 block SpMV alone (HIP events)."""
+    n = s["n"]
+    dv = lambda a: torch.tensor(a, device=dev)
+    la, ua, diag, upper, lower = (dv(s[k]) for k in ("lower_addr", "upper_addr", "diag", "upper", "lower"))
+    b = dv(s["b"]).reshape(-1)
+    x = torch.zeros_like(b)
+    kw = {"cell_off": s["cell_off"], "face_off": s["face_off"]} if "cell_off" in s else {}
+    sysm = P.System(s["N"], n, la, ua, diag, upper, lower, **kw)
+    N, nnzb = s["N"], sysm.info()["nnzb"]
+
+    def step():
+        sysm.update_values(diag, upper, lower)
+        sysm.setup(opt)
+        x.zero_()
+        _, st = sysm.solve(b, x0=x)
+        return st
+
+    step()
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        st = step()
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - t0) * 1e3)
+    sts = st if isinstance(st, list) else [st]
+    its = [q["iterations"] for q in sts]
+    res = {"workload": name, "ms_per_step": round(float(np.median(per)), 3),
+           "step": "update_values + setup + solve", "steps": steps, "step_ms_all": [round(t, 3) for t in per],
+           "iterations": its[0] if len(its) == 1 else {"min": min(its), "max": max(its),
+                                                      "mean": round(float(np.mean(its)), 2)},
+           "setup_ms": round(sts[0]["t_setup_ms"], 3), "solve_ms": round(sts[0]["t_solve_ms"], 3),
+           "status_ok": all(q["status"] == P.OK for q in sts),
+           "precision_fallback": max(q["precision_fallback"] for q in sts),
+           "rel_res_true_max": max(q["rel_res_true"] for q in sts), "levels": sts[0]["levels"]}
+    log("%s: %.1f ms/step, iterations %s, setup %.1f ms, solve %.1f ms" % (key, res["ms_per_step"], res["iterations"],
+                                                                           res["setup_ms"], res["solve_ms"]))
+    timer = KernelTimer(torch, 20)
+    if transposed:
+        g = seeded_normal(torch, N * n, torch.float64, dev, 104)
+        sysm.solve_transpose(g)                          # builds the transposed hierarchy
+        t0 = time.perf_counter()
+        lam, stt = sysm.solve_transpose(g)
+        torch.cuda.synchronize()
+        res["transposed_solve_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        res["transposed_iterations"] = stt["iterations"]
+        xs, _ = sysm.solve(b)
+        gd = torch.empty((N, n, n), dtype=torch.float64, device=dev)
+        gu = torch.empty((s["F"], n, n), dtype=torch.float64, device=dev)
+        gl = torch.empty_like(gu)
+        import ctypes as C
+        L = P.lib()
+        res["gradient_us"] = round(timer(lambda: L.cbs_gradient(
+            sysm.h, C.c_void_p(lam.data_ptr()), C.c_void_p(xs.data_ptr()), C.c_void_p(gd.data_ptr()),
+            C.c_void_p(gu.data_ptr()), C.c_void_p(gl.data_ptr()))) * 1e3, 2)
+        del gd, gu, gl
+        log("%s: transposed solve %.1f ms (%d iterations)" % (key, res["transposed_solve_ms"],
+                                                              res["transposed_iterations"]))
+    lv0 = sysm.get_level(0)
+    sweep, fp32 = level_sweep_call(P, torch, dev, sysm, n)
+    sweep_ms = timer(sweep)
+    res["level0_sweep"] = level_kobj("level-0 block-Jacobi sweep, %s" % ("FP32 row-scaled" if fp32 else "FP64"),
+                                     sweep_ms, sweep_bytes(lv0["N"], lv0["nnzb"], n, 4 if fp32 else 8,
+                                                           dinv=not fp32))
+    spmv_ms = timer(spmv_call(P, torch, dev, sysm, N, n))
+    res["spmv_fp64"] = level_kobj("block SpMV FP64, caller's numbering", spmv_ms, spmv_bytes(N, nnzb, n))
+    log("%s: level-0 sweep %.1f us (%.2f of peak), spmv %.1f us (%.2f)" % (
+        key, sweep_ms * 1e3, res["level0_sweep"]["frac"], spmv_ms * 1e3, res["spmv_fp64"]["frac"]))
+    sysm.close()
+    del la, ua, diag, upper, lower, b, x
+    torch.cuda.empty_cache()
+    return res
+
+
+def other_configs(args, P, torch, dev):
+    """The other synthetic workloads, each in its own launch configuration:
+    the 8M-cell density-based system on a boundary-layer mesh (mixed
+    AMG-FGMRES(30)), the 64-system batch (one batched mixed AMG-BiCGStab
+    solve) and the 2M-cell p-U adjoint (mixed forward and transposed solves,
+    LDU gradient)."""
+    from workloads import jacobian_batch, jacobian_stretched, pressure_velocity
+    out = {}
+    t0 = time.time()
+    s = pressure_velocity(200, 100, 100, seed=0)
+    log("generated 2M p-U in %.1f s" % (time.time() - t0))
+    out["adjoint_pu_2M"] = measure_system(
+        P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, tol=1e-8), 3, "adjoint_pu_2M",
+        "pressure-based p-U 4x4, 200x100x100 jittered renumbered hex mesh (N=%d); mixed AMG-BiCGStab to 1e-8, "
+        "forward and transposed" % s["N"], transposed=True)
+    del s
+    t0 = time.time()
+    s = jacobian_batch(64, seed=0)
+    log("generated the 64-system batch (%d cells) in %.1f s" % (s["N"], time.time() - t0))
+    out["batch_64"] = measure_system(
+        P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, tol=1e-8), 3, "batch_64",
+        "64 density-based 5x5 systems, 10k-500k cells each (N=%d in total); one batched mixed AMG-BiCGStab "
+        "solve to 1e-8 per system" % s["N"])
+    del s
+    t0 = time.time()
+    s = jacobian_stretched(200, 200, 200, seed=0)
+    log("generated 8M stretched in %.1f s" % (time.time() - t0))
+    out["stretched_density_8M"] = measure_system(
+        P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, solver=P.SOLVER_FGMRES, restart=30,
+                                            tol=1e-8), 2, "stretched_density_8M",
+        "density-based 5x5, 200^3 boundary-layer mesh (wall-normal ratio 1.2, aspect ratio up to 1e3, "
+        "N=%d); mixed AMG-FGMRES(30) to 1e-8" % s["N"])
+    del s
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -292,6 +472,7 @@ def main():
     x_fields = torch.empty_like(b_fields)
     b = P.pack_fields(b_fields).reshape(-1)
     x = torch.zeros_like(b)
+    s_host = s                     # host LDU arrays, for the CPU oracle at the end
     del s
     sysm = P.System(N, n, la, ua, diag, upper, lower)
     nnzb = sysm.info()["nnzb"]
@@ -431,11 +612,16 @@ def main():
     log("1 GiB copy: %.1f us, %.0f GB/s" % (copy_ms * 1e3, copy_gbs))
     full = (nx, ny, nz) == (100, 100, 100)
 
-    def kobj(name, ms, nbytes, traffic):
+    def kobj(name, ms, nbytes, key):
         gb = nbytes / (ms * 1e-3) / 1e9
-        return {"bound": "hbm", "kernel": name, "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gb / HBM_PEAK_GBS, 4), "traffic": traffic if full else None,
-                "avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes": int(nbytes)}
+        o = {"bound": "hbm", "kernel": name, "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gb / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_PU1M[key] if full else None,
+             "traffic_kind": TRAFFIC_KIND, "avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes": int(nbytes)}
+        us = IN_STEP_US_PU1M[key] if full else None
+        if us:
+            o["in_step"] = {"avg_launch_us": us, "frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                            "source": "rocprofv3 kernel trace of timed bench steps"}
+        return o
 
     out = {
         "metric": "coupled solve time to 1e-8 rel. residual; block-SpMV GB/s; mixed vs FP64",
@@ -482,18 +668,21 @@ def main():
         "gradient_us": round(grad_ms * 1e3, 2),
         "roofline": kobj("level-0 block-Jacobi sweep, %s (k_rows, internal numbering); the kernel with the "
                          "largest share of the step" % ("FP32 row-scaled off-diagonal" if sweep_fp32 else "FP64"),
-                         sweep_ms, sbytes, TRAFFIC_PU1M["sweep"]),
-        "spmv_fp64": kobj("block SpMV FP64 (k_rows mode 0), internal numbering", spmv_ms, byts,
-                          TRAFFIC_PU1M["spmv_internal"]),
+                         sweep_ms, sbytes, "sweep"),
+        "spmv_fp64": kobj("block SpMV FP64 (k_rows mode 0), internal numbering", spmv_ms, byts, "spmv_internal"),
         "spmv_fp64_caller_numbering": kobj("block SpMV FP64 (k_rows mode 0), caller's random numbering",
-                                           spmv_user_ms, byts, TRAFFIC_PU1M["spmv_caller"]),
+                                           spmv_user_ms, byts, "spmv_caller"),
         "copy_peak": {"achieved": round(copy_gbs, 1), "unit": "GB/s", "kernel": "1 GiB device copy (torch copy_)"},
     }
-    if not args.no_cpu_baseline:
-        log("cpu baseline on %s" % (args.cpu_sample,))
-        out["cpu_baseline"] = cpu_baseline(tuple(args.cpu_sample))
-    print(json.dumps(out), flush=True)
     sysm.close()
+    del la, ua, diag, upper, lower, b, x, b_fields, x_fields, gvec, lam, xsol, r64, z64
+    torch.cuda.empty_cache()
+    if not args.no_extra and full:
+        out["other_configs"] = other_configs(args, P, torch, dev)
+    if not args.no_cpu_baseline:
+        log("cpu baseline on the bench system")
+        out["cpu_baseline"] = cpu_baseline(s_host)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
