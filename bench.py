@@ -73,6 +73,8 @@ def parse():
                          "(0 = library default, -1 = off)")
     ap.add_argument("--row-split", type=int, default=0,
                     help="threads per scalar row on levels under 65,536 block rows (0 = automatic)")
+    ap.add_argument("--scaled-sweeps", type=int, choices=[0, 1], default=1,
+                    help="mixed block-Jacobi sweeps on row-scaled FP32 values (1) or with the FP64 D^-1 (0)")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--assembly", action="store_true",
                     help="only the device assemblies (cbs_assemble_luo, 5x5; cbs_assemble_pu, 4x4) on an "
@@ -208,21 +210,23 @@ class KernelTimer:
         return e0.elapsed_time(e1) / self.reps       # ms
 
 
-def level_sweep_call(P, torch, dev, sysm, n):
-    """Closure running the level-0 smoothing sweep of the current hierarchy on
-    random vectors, and whether it runs in FP32."""
+def level_sweep_call(P, torch, dev, sysm, n, level=0, op=None):
+    """Closure running the smoothing sweep (or, with op, another level kernel)
+    of one level of the current hierarchy on random vectors, and whether it
+    runs in FP32."""
     import ctypes as C
     L = P.lib()
+    op = P.LEVEL_SWEEP if op is None else op
     f = C.c_int32(0)
-    L.cbs_level_apply(sysm.h, 0, P.LEVEL_SWEEP, None, None, None, C.byref(f))
-    n0 = sysm.get_level(0)["N"]
+    L.cbs_level_apply(sysm.h, level, op, None, None, None, C.byref(f))
+    n0 = sysm.get_level(level)["N"]
     dt = torch.float32 if f.value else torch.float64
     bv = seeded_normal(torch, n0 * n, dt, dev, 101)
     xv = seeded_normal(torch, n0 * n, dt, dev, 102)
     yv = torch.empty_like(xv)
 
     def run():
-        rc = L.cbs_level_apply(sysm.h, 0, P.LEVEL_SWEEP, C.c_void_p(bv.data_ptr()), C.c_void_p(xv.data_ptr()),
+        rc = L.cbs_level_apply(sysm.h, level, op, C.c_void_p(bv.data_ptr()), C.c_void_p(xv.data_ptr()),
                                C.c_void_p(yv.data_ptr()), None)
         if rc < 0:
             raise P.CbsError(rc, "cbs_level_apply")
@@ -238,13 +242,16 @@ def spmv_call(P, torch, dev, system, N, n):
 
 
 def kernels_only(args, P, torch, dev, sysm, opt_mixed, N, n, nnzb, la, ua, diag, upper, lower):
-    """Five launches each of the level-0 mixed-precision sweep and the FP64
-    block SpMV on both numberings, then a plain 1 GiB copy (the calibration
-    kernel of the HBM byte counters)."""
+    """Five launches each of the level-0 mixed-precision sweep, the FP64
+    block SpMV on both numberings, and the sweep and residual of levels 1 and
+    2, then a plain 1 GiB copy (the calibration kernel of the HBM byte
+    counters)."""
     sysm.setup(opt_mixed)
     sweep, _ = level_sweep_call(P, torch, dev, sysm, n)
     sys2 = internal_system(P, torch, dev, sysm, N, n, la, ua, diag, upper, lower)
-    for fn in (sweep, spmv_call(P, torch, dev, sysm, N, n), spmv_call(P, torch, dev, sys2, N, n)):
+    coarse = [level_sweep_call(P, torch, dev, sysm, n, level=l, op=op)[0]
+              for l in (1, 2) for op in (P.LEVEL_SWEEP, P.LEVEL_RESIDUAL)]
+    for fn in (sweep, spmv_call(P, torch, dev, sysm, N, n), spmv_call(P, torch, dev, sys2, N, n), *coarse):
         for _ in range(5):
             fn()
         torch.cuda.synchronize()
@@ -256,7 +263,14 @@ def kernels_only(args, P, torch, dev, sysm, opt_mixed, N, n, nnzb, la, ua, diag,
     torch.cuda.synchronize()
     sys2.close()
     lv = sysm.get_level(0)
-    print(json.dumps({"launches_per_kernel": 5, "order": ["sweep", "spmv caller", "spmv internal", "copy"],
+    lvs = [sysm.get_level(l) for l in (1, 2)]
+    print(json.dumps({"launches_per_kernel": 5, "order": ["sweep", "spmv caller", "spmv internal", "level-1 sweep",
+                                                          "level-1 residual", "level-2 sweep", "level-2 residual",
+                                                          "copy"],
+                      "levels_1_2": [{"N": q["N"], "nnzb": q["nnzb"],
+                                      "algorithmic_bytes_sweep": int(sweep_bytes(q["N"], q["nnzb"], n)),
+                                      "algorithmic_bytes_residual": int(q["nnzb"] * (n * n * 4 + 4) + (q["N"] + 1) * 4
+                                                                        + 3 * q["N"] * n * 4)} for q in lvs],
                       "algorithmic_bytes_sweep": int(sweep_bytes(lv["N"], lv["nnzb"], n)),
                       "algorithmic_bytes_spmv": int(spmv_bytes(N, nnzb, n)),
                       "copy_bytes_read": int(a.numel() * 8), "copy_bytes_written": int(a.numel() * 8)}))
@@ -481,7 +495,7 @@ def main():
                   smoother={"dilu": P.SMOOTH_DILU, "sgs": P.SMOOTH_SGS, "ilu0": P.SMOOTH_ILU0}.get(args.smoother, P.SMOOTH_BJACOBI),
                   dilu_levels=args.dilu_levels, pre_sweeps=args.sweeps, post_sweeps=args.sweeps,
                   omega=args.omega, coarse_max=args.coarse_max, match_passes=args.passes,
-                  row_split=args.row_split, tail_rows=args.tail_rows)
+                  row_split=args.row_split, tail_rows=args.tail_rows, scaled_sweeps=args.scaled_sweeps)
     opt_mixed = P.default_options(precision=P.PRECISION_MIXED, **common)
     opt_reuse = P.default_options(precision=P.PRECISION_MIXED, reuse_aggregates=1, **common)
     opt_fp64 = P.default_options(precision=P.PRECISION_FP64, **common)
@@ -644,7 +658,7 @@ def main():
                    "solver": args.solver, "smoother": args.smoother, "dilu_levels": args.dilu_levels,
                    "sweeps": args.sweeps, "omega": args.omega, "coarse_max": args.coarse_max,
                    "match_passes": args.passes, "row_split": args.row_split,
-                   "tail_rows": args.tail_rows},
+                   "tail_rows": args.tail_rows, "scaled_sweeps": args.scaled_sweeps},
         "step_ms_median": round(float(np.median(per_step)), 3),
         "step_ms_all": [round(t, 3) for t in per_step],
         "iterations": st["iterations"],

@@ -129,6 +129,11 @@ typedef struct cbs_options {
                                 (2,1), (4,0), (4,1) on every level in both
                                 precisions. Changes only the order of
                                 the row sums                         [0] */
+    int32_t scaled_sweeps;   /* mixed precision, block-Jacobi levels: sweeps
+                                on the row-scaled values D_i^{-1} A_ij rounded
+                                once to FP32, the FP64 D^{-1} applied only by
+                                the zero-guess sweep (1), or every sweep on
+                                the FP32 A_ij with the FP64 D^{-1} (0)   [1] */
 } cbs_options;
 
 /* Per-solve statistics (Algorithm amgxFoam: iterations and residuals). */

@@ -717,6 +717,79 @@ __global__ void k_perm_vec(int32_t N, int n, const int32_t *__restrict__ ip, con
 }
 
 // ------------------------------------------------------------------ DILU setup
+// Two colours when the block graph is bipartite (the face graph of any hex
+// mesh is): a union-find over the graph's edges in which every node keeps
+// its parent and its parity relative to that parent, packed as
+// 2 * parent + parity; an edge joins its ends with opposite parity.  A larger
+// root hooks under a smaller one by compare-and-swap on the root's word, so
+// every parent has a smaller index than its child and every find ends; an
+// edge whose ends already share a root with equal parity closes an odd cycle
+// and sets the flag (the general colouring below then runs).  A node's colour
+// is its parity relative to the root of its component -- its smallest node --
+// which is its distance parity from that node, whatever order the edges were
+// joined in.  The words are read and written at device scope (L1 bypassed),
+// so a thread sees the hooks that others made.
+__device__ inline int32_t uf_load(const int32_t *a) {
+    return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int32_t uf_find(int32_t *uf, int32_t u, int &par) {
+    int p = 0;
+    for (;;) {
+        const int32_t w = uf_load(uf + u);
+        const int32_t up = w >> 1;
+        if (up == u) break;
+        const int32_t w2 = uf_load(uf + up);
+        const int32_t g = w2 >> 1;
+        if (g == up) {                       // the parent is a root
+            p ^= w & 1;
+            u = up;
+            break;
+        }
+        // path halving: point u at its grandparent (any ancestor with the
+        // parity of the path to it is a valid parent, so racing writes agree)
+        const int32_t pw = (w ^ w2) & 1;
+        __hip_atomic_store(uf + u, 2 * g + pw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        p ^= pw;
+        u = g;
+    }
+    par = p;
+    return u;
+}
+
+__global__ void k_uf_init(int32_t N, int32_t *uf) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) uf[i] = 2 * i;
+}
+
+__global__ void k_uf_hook(int32_t N, const int32_t *rp, const int32_t *col, int32_t *uf, int32_t *flag) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int32_t j = col[k];
+        if (j <= i) continue;                    // each edge once, from its smaller end
+        for (;;) {                               // ends when joined: a failed swap means another root hooked
+            int pu, pv;
+            const int32_t ru = uf_find(uf, i, pu), rv = uf_find(uf, j, pv);
+            if (ru == rv) {
+                if (pu == pv) atomicOr(flag, 1);
+                break;
+            }
+            const int32_t hi = max(ru, rv), lo = min(ru, rv);
+            if (atomicCAS(uf + hi, 2 * hi, 2 * lo + (1 ^ pu ^ pv)) == 2 * hi) break;
+        }
+    }
+}
+
+__global__ void k_uf_colour(int32_t N, int32_t *uf, int32_t *colour, int32_t *counters) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int par;
+    uf_find(uf, i, par);
+    colour[i] = par;
+    if (par) atomicMax(&counters[1], 1);
+}
+
 // Colouring: Jones-Plassmann rounds with a fixed hash priority; a node whose
 // uncoloured neighbours all rank lower takes the smallest colour unused by
 // its coloured neighbours (first fit).  Nodes selected in one round are
@@ -1157,9 +1230,21 @@ void colour_level(cbs_system *h, int l) {
     const dim3 G(cdiv(N, 256)), B(256);
     L.colour.alloc(N > 0 ? N : 1);
     DArr<int32_t> sel(N > 0 ? N : 1), cnt(4);
-    hipLaunchKernelGGL(k_fill_int, G, B, 0, st, L.colour.get(), (int64_t)N, -1);
     HIPCHK(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * 4, st));
-    int32_t done = 0;
+    // two colours if the graph is bipartite (the packed words need N < 2^30)
+    bool bipartite = false;
+    if (N < (1 << 30)) {
+        hipLaunchKernelGGL(k_uf_init, G, B, 0, st, N, sel.get());
+        hipLaunchKernelGGL(k_uf_hook, G, B, 0, st, N, L.rp, L.col, sel.get(), cnt.get() + 3);
+        hipLaunchKernelGGL(k_uf_colour, G, B, 0, st, N, sel.get(), L.colour.get(), cnt.get());
+        LAUNCHCHK();
+        bipartite = read_int(cnt.get() + 3, st) == 0;
+    }
+    int32_t done = bipartite ? N : 0;
+    if (!bipartite) {
+        hipLaunchKernelGGL(k_fill_int, G, B, 0, st, L.colour.get(), (int64_t)N, -1);
+        HIPCHK(hipMemsetAsync(cnt.get(), 0, sizeof(int32_t) * 4, st));
+    }
     for (int round = 0; done < N; ++round) {
         if (round >= 4096) cbs_throw(CBS_ERR_HIP, "colouring did not finish");
         hipLaunchKernelGGL(k_jp_select, G, B, 0, st, N, L.rp, L.col, L.colour.get(), sel.get());
@@ -1327,9 +1412,11 @@ void amg_setup(cbs_system *h) {
             L0.Dinv.ensure((size_t)h->N * n * n);
             blockinv_level(h, 0, L0.v64, L0.Dinv.get());
         }
-        if (o.precond == CBS_PREC_SGS) colour_level(h, 0);
+        const bool sgs = o.precond == CBS_PREC_SGS;
+        if (sgs) colour_level(h, 0);
         h->lev.resize(1);
-        sell_build(L0.N, L0.rp, L0.col, L0.sell, st);
+        sell_build(L0.N, L0.rp, L0.col, L0.sell, st, false, kSlice, sgs ? L0.rows_by_colour.get() : nullptr,
+                   sgs ? &L0.colour_off : nullptr);
         level_sell(h, L0, false, nullptr);
         L0.sell.sched64 = choose_sched(n, L0.sell, false, L0.sell.v64.get(), o.schedule, st);
         L0.sell.sched64.split = row_split_for(L0.sell, L0.nnzb, o.row_split);
@@ -1410,17 +1497,26 @@ void amg_setup(cbs_system *h) {
                (o.dilu_levels < 0 || q < o.dilu_levels) && q + 1 < nlev;
     };
     {
-        struct Pending { Level *L; Sell *S; bool od; };
+        // coloured levels first get their colours: their sliced copy holds
+        // each colour's rows as one run of slices
+        for (int q = 0; q + 1 < nlev; ++q)
+            if (level_uses_dilu(q) && (!reuse || !h->lev[q].colour.get())) colour_level(h, q);
+        pt.mark("colours");
+        struct Pending { Level *L; Sell *S; bool od; bool coloured; };
         std::vector<Pending> todo;
         for (int q = 0; q < nlev; ++q) {
             Level &L = h->lev[q];
             const bool keep_sell = reuse && L.sell.N == L.N && L.sell.soff.get();
             const bool keep_sod = reuse && L.sod.N == L.N && L.sod.soff.get();
-            if ((q == 0 || q + 1 < nlev) && !keep_sell) todo.push_back({&L, &L.sell, false});
-            if (mixed && q + 1 < nlev && !level_uses_dilu(q) && !keep_sod) todo.push_back({&L, &L.sod, true});
+            if ((q == 0 || q + 1 < nlev) && !keep_sell)
+                todo.push_back({&L, &L.sell, false, q + 1 < nlev && level_uses_dilu(q)});
+            if (mixed && o.scaled_sweeps && q + 1 < nlev && !level_uses_dilu(q) && !keep_sod)
+                todo.push_back({&L, &L.sod, true, false});
         }
         for (auto &t : todo)
-            sell_pattern_begin(t.L->N, t.L->rp, t.L->col, *t.S, st, t.od, t.L == &h->lev[0] ? kSlice : kCoarseSlice);
+            sell_pattern_begin(t.L->N, t.L->rp, t.L->col, *t.S, st, t.od, t.L == &h->lev[0] ? kSlice : kCoarseSlice,
+                               t.coloured ? t.L->rows_by_colour.get() : nullptr,
+                               t.coloured ? &t.L->colour_off : nullptr);
         for (size_t k0 = 0; k0 < todo.size(); k0 += kPinnedWords) {
             const size_t k1 = std::min(todo.size(), k0 + kPinnedWords);
             int32_t cnt[kPinnedWords];
@@ -1448,7 +1544,6 @@ void amg_setup(cbs_system *h) {
         L.dilu = q + 1 < nlev && coloured && (o.smoother == CBS_SMOOTH_DILU || o.smoother == CBS_SMOOTH_ILU0);
         L.ilu = L.dilu && o.smoother == CBS_SMOOTH_ILU0;
         L.sgs = q + 1 < nlev && coloured && o.smoother == CBS_SMOOTH_SGS;
-        if (q + 1 < nlev && coloured && (!reuse || !L.colour.get())) colour_level(h, q);
         if (L.ilu) {
             ilu_factor_level(h, q);
         } else if (L.dilu) {
@@ -1467,7 +1562,7 @@ void amg_setup(cbs_system *h) {
         } else {
             L.iluF.release(); L.iluS64.release(); L.iluS32.release(); L.iluS64T.release(); L.iluS32T.release();
         }
-        L.scaled = mixed && q + 1 < nlev && !L.dilu && !L.sgs;
+        L.scaled = mixed && o.scaled_sweeps && q + 1 < nlev && !L.dilu && !L.sgs;
         L.scaledT = false;
         if (L.scaled) {
             L.sod.v32.ensure(L.sod.nent > 0 ? (size_t)L.sod.nent * n * n : 1);

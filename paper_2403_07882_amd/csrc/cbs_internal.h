@@ -98,6 +98,7 @@ enum {
 // width sw[s]).  One wavefront of a block-row kernel then reads kSlice
 // consecutive blocks per step.  BCSR stays the setup-time format.
 constexpr int kSlice = 16;
+constexpr int kMaxColourRanges = 128;     // colours of a coloured smoother (graph colouring limit)
 constexpr int kCoarseSlice = 8;
 
 // Levels with fewer block rows than this are launch- and latency-bound: their
@@ -119,21 +120,29 @@ struct Sched {
 };
 
 struct SellView {
-    int32_t N;
+    int32_t N;              // row positions (rows, or with prow the padded colour ranges)
     const int32_t *soff, *sw, *scol;
     Sched sched;
     int32_t lc;             // log2 of the slice height
+    const int32_t *prow;    // row held at each position (-1: padding); nullptr = identity
 };
 
+// Colour-ordered copies (levels with a coloured smoother): position p holds
+// row prow[p]; colour c occupies positions cpos[c] .. cpos[c] + (its row
+// count), its range padded to whole slices, so one colour's rows are one
+// contiguous run of slices.
 struct Sell {
     int32_t N = 0, nslices = 0, lc = 4;
+    int32_t npos = 0;                     // positions (N when not colour-ordered)
     int64_t nent = 0;
     DArr<int32_t> soff, sw, scol, ssrc;   // ssrc: BCSR slot of each entry, -1 = padding
+    DArr<int32_t> prow;                   // colour-ordered: row of each position
+    std::vector<int32_t> cpos;            // host, colour-ordered: first position of each colour
     DArr<double> v64, v64T;
     DArr<float> v32, v32T;
     Sched sched64{4, 0}, sched32{4, 1};
     SellView view(bool fp32 = false) const {
-        return SellView{N, soff.get(), sw.get(), scol.get(), fp32 ? sched32 : sched64, lc};
+        return SellView{npos, soff.get(), sw.get(), scol.get(), fp32 ? sched32 : sched64, lc, prow.get()};
     }
 };
 
@@ -330,12 +339,15 @@ int8_t row_split_for(const Sell &S, int64_t nblocks, int32_t opt_split);
 // sliced-ELL pattern from BCSR (offdiag: without the diagonal blocks), and
 // values gathered from BCSR values
 void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag = false,
-                int slice = kSlice);
+                int slice = kSlice, const int32_t *rows_by_colour = nullptr,
+                const std::vector<int32_t> *colour_off = nullptr);
 // the same in two halves, so that several patterns share one read-back of
 // their entry counts (S.soff[S.nslices] after begin)
 // slice: slice height, a power of two up to 64
+// rows_by_colour / colour_off (host): build the copy colour-ordered
 void sell_pattern_begin(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag,
-                        int slice = kSlice);
+                        int slice = kSlice, const int32_t *rows_by_colour = nullptr,
+                        const std::vector<int32_t> *colour_off = nullptr);
 void sell_pattern_finish(const int32_t *rp, const int32_t *col, Sell &S, int64_t nent, hipStream_t st,
                          bool offdiag);
 // (with out32: also the FP32 rounding of every value, bit 64 of *flag set for
@@ -362,20 +374,22 @@ void launch_block_apply(int n, int32_t N, const double *Dinv, const double *r, d
 int tail_level_for(const cbs_system *h, size_t tsize);
 template <typename T>
 void launch_tail(cbs_system *h, bool tr, int l0, const T *rfine);
-// block Gauss-Seidel on the rows rows[0..cnt) of one colour, in place:
+// block Gauss-Seidel on the cnt rows of one colour, held at positions
+// p0 .. p0 + cnt of the colour-ordered copy S, in place:
 // x_i = D_i^{-1} (b_i - sum_{j != i} A_ij x_j)
 template <typename T>
-void launch_gs_colour(int n, const SellView &S, const T *val, const int32_t *rows, int32_t cnt, const double *Dinv,
+void launch_gs_colour(int n, const SellView &S, const T *val, int32_t p0, int32_t cnt, const double *Dinv,
                       const T *b, T *x, hipStream_t st);
-// DILU colour sweeps on the rows rows[0..cnt): forward y = E^{-1}(b - A x - L y)
-// (zero_guess: A x omitted), backward z = y - E^{-1} U z, x = x + z
+// DILU colour sweeps on the cnt rows at positions p0 .. p0 + cnt: forward
+// y = E^{-1}(b - A x - L y) (zero_guess: A x omitted; last: also x = x + y,
+// the last colour's whole update), backward z = y - E^{-1} U z, x = x + z
 template <typename T>
-void launch_dilu_fwd(int n, const SellView &S, const T *val, const T *fval, const int32_t *colour, int c,
-                     const int32_t *rows, int32_t cnt, const double *Einv, const T *b, const T *x, T *y,
-                     bool zero_guess, hipStream_t st);
+void launch_dilu_fwd(int n, const SellView &S, const T *val, const T *fval, const int32_t *colour, int c, int32_t p0,
+                     int32_t cnt, const double *Einv, const T *b, T *x, T *y, bool zero_guess, bool last,
+                     hipStream_t st);
 template <typename T>
-void launch_dilu_bwd(int n, const SellView &S, const T *val, const int32_t *colour, int c, const int32_t *rows,
-                     int32_t cnt, const double *Einv, T *yz, T *x, bool zero_guess, hipStream_t st);
+void launch_dilu_bwd(int n, const SellView &S, const T *val, const int32_t *colour, int c, int32_t p0, int32_t cnt,
+                     const double *Einv, T *yz, T *x, bool zero_guess, hipStream_t st);
 
 // AMG setup (amg.hip)
 void amg_setup(cbs_system *h);

@@ -10,6 +10,7 @@
 //     element for element (bit-exact), writes fully coalesced.
 #include "cbs_internal.h"
 
+#include <cstdlib>
 #include <mutex>
 #include <string>
 
@@ -240,6 +241,35 @@ __global__ void k_row_sys(int32_t N, int32_t n_sys, const int64_t *cell_off, int
 // ------------------------------------------------------------------ values
 // One thread per scalar of the block-CSR value array: contiguous writes,
 // block-contiguous reads.  Non-finite inputs raise flag bit 4.
+// Odd block sizes: one thread per row of a destination block (n contiguous
+// values read from the source block, n written to the slot).  Measured on
+// MI355X for n = 5 against one thread per value: 0.64 -> 0.61 ms at 1M cells,
+// 5.8 -> 4.8 ms at 8M.  Writing in source order instead (contiguous reads,
+// each 200-byte block stored at its slot) halved the bandwidth: blocks that
+// do not fill whole cache lines are cheap to gather but not to scatter.
+template <int n>
+__global__ void k_values_rows(int64_t nrows, int32_t N, int32_t F, const int32_t *src, const double *diag,
+                              const double *upper, const double *lower, double *vals, int32_t *flag) {
+    constexpr int nn = n * n;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nrows) return;
+    const int64_t k = g / n;
+    const int r = (int)(g - k * n);
+    const int32_t s = src[k];
+    const double *from = (s < N ? diag + (int64_t)s * nn
+                          : (s < N + F ? upper + (int64_t)(s - N) * nn : lower + (int64_t)(s - N - F) * nn)) + r * n;
+    double v[n];
+#pragma unroll
+    for (int c = 0; c < n; ++c) v[c] = from[c];
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+        bad = bad || !isfinite(v[c]);
+        vals[k * nn + r * n + c] = v[c];
+    }
+    if (bad) atomicOr(flag, 4);
+}
+
 template <int n>
 __global__ void k_values(int64_t total, int32_t N, int32_t F, const int32_t *src, const double *diag,
                          const double *upper, const double *lower, double *vals, int32_t *flag) {
@@ -612,15 +642,24 @@ void convert_values(cbs_system *h, const double *diag, const double *upper, cons
     const int64_t total = h->nnzb * n * n;
     h->vals.ensure(total);
     HIPCHK(hipMemsetAsync(h->dflag.get(), 0, sizeof(int32_t), st));
-    const int64_t nthr = (n * n) % 4 == 0 ? total / 4 : ((n * n) % 2 == 0 ? total / 2 : total);
-    const dim3 g(cdiv(nthr, 256)), b(256);
-    switch (n) {
-        case 1: hipLaunchKernelGGL(k_values<1>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
-        case 2: hipLaunchKernelGGL(k_values<2>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
-        case 3: hipLaunchKernelGGL(k_values<3>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
-        case 4: hipLaunchKernelGGL(k_values<4>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
-        case 5: hipLaunchKernelGGL(k_values<5>, g, b, 0, st, total, h->N, h->F, h->src.get(), diag, upper, lower, h->vals.get(), h->dflag.get()); break;
-        default: cbs_throw(CBS_ERR_ARG, "bdim must be 1..5");
+    const dim3 b(256);
+    const int32_t *sp = h->src.get();
+    double *vp = h->vals.get();
+    int32_t *fp = h->dflag.get();
+    if (n % 2 == 1 && n > 1) {
+        const int64_t nr = h->nnzb * n;
+        const dim3 g(cdiv(nr, 256));
+        if (n == 3) hipLaunchKernelGGL(k_values_rows<3>, g, b, 0, st, nr, h->N, h->F, sp, diag, upper, lower, vp, fp);
+        else hipLaunchKernelGGL(k_values_rows<5>, g, b, 0, st, nr, h->N, h->F, sp, diag, upper, lower, vp, fp);
+    } else {
+        const int64_t nthr = (n * n) % 4 == 0 ? total / 4 : ((n * n) % 2 == 0 ? total / 2 : total);
+        const dim3 g(cdiv(nthr, 256));
+        switch (n) {
+            case 1: hipLaunchKernelGGL(k_values<1>, g, b, 0, st, total, h->N, h->F, sp, diag, upper, lower, vp, fp); break;
+            case 2: hipLaunchKernelGGL(k_values<2>, g, b, 0, st, total, h->N, h->F, sp, diag, upper, lower, vp, fp); break;
+            case 4: hipLaunchKernelGGL(k_values<4>, g, b, 0, st, total, h->N, h->F, sp, diag, upper, lower, vp, fp); break;
+            default: cbs_throw(CBS_ERR_ARG, "bdim must be 1..5");
+        }
     }
     LAUNCHCHK();
     if (read_int(h->dflag.get(), st) & 4) cbs_throw(CBS_ERR_NONFINITE, "non-finite matrix coefficient");

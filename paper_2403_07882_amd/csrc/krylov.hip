@@ -460,16 +460,21 @@ void dilu_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x, bool zero_g
     T *y = vptr<T>(L.vt);
     const int ncol = (int)L.colour_off.size() - 1;
     const SellView S = L.sell.view(sizeof(T) == 4);
+    auto cnt = [&](int c) { return L.colour_off[c + 1] - L.colour_off[c]; };
     for (int c = 0; c < ncol; ++c)
-        launch_dilu_fwd<T>(h->n, S, val, fv, L.colour.get(), c, L.rows_by_colour.get() + L.colour_off[c],
-                           L.colour_off[c + 1] - L.colour_off[c], Einv, b, x, y, zero_guess, h->stream);
-    for (int c = ncol - 1; c >= 0; --c)
-        launch_dilu_bwd<T>(h->n, S, fv ? fv : val, L.colour.get(), c, L.rows_by_colour.get() + L.colour_off[c],
-                           L.colour_off[c + 1] - L.colour_off[c], Einv, y, x, zero_guess, h->stream);
+        launch_dilu_fwd<T>(h->n, S, val, fv, L.colour.get(), c, L.sell.cpos[c], cnt(c), Einv, b, x, y, zero_guess,
+                           c == ncol - 1, h->stream);
+    // the last colour's backward step changes nothing; its forward launch
+    // already made its update
+    for (int c = ncol - 2; c >= 0; --c)
+        launch_dilu_bwd<T>(h->n, S, fv ? fv : val, L.colour.get(), c, L.sell.cpos[c], cnt(c), Einv, y, x,
+                           zero_guess, h->stream);
 }
 
 // One symmetric block Gauss-Seidel step in place: the colour classes in
-// order, then in reverse (the oracle's order: colour first, then row).
+// order, then in reverse (the oracle's order: colour first, then row).  The
+// last colour's second pass is left out: nothing it reads changed since its
+// first, so it would recompute the same values.
 template <typename T>
 void sgs_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x) {
     const T *val = level_vals<T>(L, tr);
@@ -477,11 +482,11 @@ void sgs_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x) {
     const int ncol = (int)L.colour_off.size() - 1;
     const SellView S = L.sell.view(sizeof(T) == 4);
     auto colour = [&](int c) {
-        launch_gs_colour<T>(h->n, S, val, L.rows_by_colour.get() + L.colour_off[c],
-                            L.colour_off[c + 1] - L.colour_off[c], Dinv, b, x, h->stream);
+        launch_gs_colour<T>(h->n, S, val, L.sell.cpos[c], L.colour_off[c + 1] - L.colour_off[c], Dinv, b, x,
+                            h->stream);
     };
     for (int c = 0; c < ncol; ++c) colour(c);
-    for (int c = ncol - 1; c >= 0; --c) colour(c);
+    for (int c = ncol - 2; c >= 0; --c) colour(c);
 }
 
 // x = V(b) with zero initial guess on level l; the result lands in x.  When

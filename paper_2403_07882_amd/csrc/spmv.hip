@@ -104,17 +104,21 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
     constexpr int nn = n * n;
     const int t = threadIdx.x;
     const int lr = t / n, r = t - lr * n;
-    const int32_t i = blockIdx.x * 64 + lr;
+    // position p in the sliced copy holds block row i (colour-ordered copies
+    // map positions to rows; the padding positions of their colour ranges
+    // hold none)
+    const int32_t p = blockIdx.x * 64 + lr;
+    const int32_t i = (S.prow && p < S.N) ? S.prow[p] : p;
+    const bool act = p < S.N && i >= 0;
     // sweep result: to y, or widened to FP64 into y64 (the last sweep of a
     // mixed-precision V-cycle hands its result straight to the FP64 loop)
     auto put = [&](int64_t o, TX v) {
         if (y64) y64[o] = (double)v;
         else y[o] = v;
     };
-    const int32_t N = S.N;
     A acc = 0;
-    if (MODE != 3 && i < N) {
-        const int32_t sl = i >> S.lc, ii = i - (sl << S.lc);
+    if (MODE != 3 && act) {
+        const int32_t sl = p >> S.lc, ii = p - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
         int32_t k = 0;
         for (; k + U <= w; k += U) {
@@ -155,17 +159,17 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
         return (A)v;
     };
     if (MODE == 0) {
-        if (i < N) y[o] = (TX)acc;
+        if (act) y[o] = (TX)acc;
         return;
     }
     A res = 0;
-    if (i < N) res = (A)b[o] - acc;
+    if (act) res = (A)b[o] - acc;
     if (MODE == 1) {
-        if (i < N) y[o] = (TX)res;
+        if (act) y[o] = (TX)res;
         return;
     }
     if (MODE == 4) {
-        if (i < N) {
+        if (act) {
             const A xo = x_own();
             put(o, (TX)(xo + (A)omega * (res - xo)));
         }
@@ -174,7 +178,7 @@ __global__ __launch_bounds__(64 * n) void k_rows(SellView S, const TV *__restric
     __shared__ A sres[64 * n];
     sres[t] = res;
     __syncthreads();
-    if (i < N) {
+    if (act) {
         const double *Di = Dinv + (int64_t)i * nn + r * n;
         double z = 0.0;
 #pragma unroll
@@ -206,11 +210,12 @@ __global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__r
     const int t = threadIdx.x;
     const int lr = t / (n * SP), kr = t - lr * (n * SP);
     const int kk = kr / n, r = kr - kk * n;
-    const int32_t i = blockIdx.x * R + lr;
-    const int32_t N = S.N;
+    const int32_t p = blockIdx.x * R + lr;
+    const int32_t i = (S.prow && p < S.N) ? S.prow[p] : p;
+    const bool act = p < S.N && i >= 0;
     A acc = 0;
-    if (i < N) {
-        const int32_t sl = i >> S.lc, ii = i - (sl << S.lc);
+    if (act) {
+        const int32_t sl = p >> S.lc, ii = p - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
         for (int32_t k = kk; k < w; k += SP) {
             const int64_t e = base + ((int64_t)k << S.lc);
@@ -239,13 +244,13 @@ __global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__r
 #pragma unroll
         for (int q = 0; q < SP; ++q) sum += spart[lr * n * SP + q * n + r];
         if (MODE == 0) {
-            if (i < N) y[o] = (TX)sum;
+            if (act) y[o] = (TX)sum;
         } else {
-            const A res = (i < N) ? (A)b[o] - sum : (A)0;
+            const A res = act ? (A)b[o] - sum : (A)0;
             if (MODE == 1) {
-                if (i < N) y[o] = (TX)res;
+                if (act) y[o] = (TX)res;
             } else if (MODE == 4) {
-                if (i < N) {
+                if (act) {
                     const A xo = x_own(o);
                     put(o, (TX)(xo + (A)omega * (res - xo)));
                 }
@@ -256,7 +261,7 @@ __global__ __launch_bounds__(64 * n) void k_rows_split(SellView S, const TV *__r
     }
     if (MODE != 2) return;
     __syncthreads();
-    if (kk == 0 && i < N) {
+    if (kk == 0 && act) {
         const double *Di = Dinv + (int64_t)i * nn + r * n;
         double z = 0.0;
 #pragma unroll
@@ -330,20 +335,20 @@ void rows_n(int mode, const SellView &S, const TV *val, const TX *x, const TX *b
 // of one colour are not neighbours, so each reads only x of other colours and
 // writes only its own.
 template <int n, typename T>
-__global__ __launch_bounds__(64 * n) void k_gs_colour(SellView S, const T *__restrict__ val,
-                                                      const int32_t *__restrict__ rows, int32_t cnt,
-                                                      const double *__restrict__ Dinv, const T *__restrict__ b,
-                                                      T *x) {
+__global__ __launch_bounds__(64 * n) void k_gs_colour(SellView S, const T *__restrict__ val, int32_t p0,
+                                                      int32_t cnt, const double *__restrict__ Dinv,
+                                                      const T *__restrict__ b, T *x) {
     using A = typename Acc<T>::type;
     constexpr int nn = n * n;
     const int t = threadIdx.x;
     const int lr = t / n, r = t - lr * n;
     const int32_t q = blockIdx.x * 64 + lr;
     const bool act = q < cnt;
-    const int32_t i = act ? rows[q] : 0;
+    const int32_t p = p0 + q;                     // the colour's rows are one run of positions
+    const int32_t i = act ? S.prow[p] : 0;
     A acc = 0;
     if (act) {
-        const int32_t sl = i >> S.lc, ii = i - (sl << S.lc);
+        const int32_t sl = p >> S.lc, ii = p - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
         for (int32_t k = 0; k < w; ++k) {
             const int64_t e = base + ((int64_t)k << S.lc);
@@ -371,23 +376,27 @@ __global__ __launch_bounds__(64 * n) void k_gs_colour(SellView S, const T *__res
 
 // fval: the lower-triangle values when they differ from val (block ILU(0):
 // val = A for the residual, fval = its factor), else nullptr
-template <int n, typename T, bool ZERO>
+// LAST (the last colour, which has no upper neighbours): the backward step
+// leaves its y unchanged, so x_i += y_i is made here and the backward launch
+// of that colour is skipped.  Rows of one colour are not neighbours, so
+// writing x_i here cannot change what another row of the colour reads.
+template <int n, typename T, bool ZERO, bool LAST>
 __global__ __launch_bounds__(64 * n) void k_dilu_fwd(SellView S, const T *__restrict__ val,
                                                      const T *__restrict__ fval,
-                                                     const int32_t *__restrict__ colour, int c,
-                                                     const int32_t *__restrict__ rows, int32_t cnt,
-                                                     const double *__restrict__ Einv, const T *__restrict__ b,
-                                                     const T *__restrict__ x, T *__restrict__ y) {
+                                                     const int32_t *__restrict__ colour, int c, int32_t p0,
+                                                     int32_t cnt, const double *__restrict__ Einv,
+                                                     const T *__restrict__ b, T *x, T *__restrict__ y) {
     using A = typename Acc<T>::type;
     constexpr int nn = n * n;
     const int t = threadIdx.x;
     const int lr = t / n, r = t - lr * n;
     const int32_t q = blockIdx.x * 64 + lr;
     const bool act = q < cnt;
-    const int32_t i = act ? rows[q] : 0;
+    const int32_t p = p0 + q;                     // the colour's rows are one run of positions
+    const int32_t i = act ? S.prow[p] : 0;
     A ax = 0, ay = 0;
     if (act) {
-        const int32_t sl = i >> S.lc, ii = i - (sl << S.lc);
+        const int32_t sl = p >> S.lc, ii = p - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
         for (int32_t k = 0; k < w; ++k) {
             const int64_t e = base + ((int64_t)k << S.lc);
@@ -418,26 +427,28 @@ __global__ __launch_bounds__(64 * n) void k_dilu_fwd(SellView S, const T *__rest
         double z = 0.0;
 #pragma unroll
         for (int cc = 0; cc < n; ++cc) z += Ei[cc] * (double)sres[lr * n + cc];
-        y[(int64_t)i * n + r] = (T)z;
+        const int64_t o = (int64_t)i * n + r;
+        y[o] = (T)z;
+        if (LAST) x[o] = ZERO ? (T)z : (T)((A)x[o] + (A)(T)z);
     }
 }
 
 template <int n, typename T, bool ZERO>
 __global__ __launch_bounds__(64 * n) void k_dilu_bwd(SellView S, const T *__restrict__ val,
-                                                     const int32_t *__restrict__ colour, int c,
-                                                     const int32_t *__restrict__ rows, int32_t cnt,
-                                                     const double *__restrict__ Einv, T *__restrict__ yz,
-                                                     T *__restrict__ x) {
+                                                     const int32_t *__restrict__ colour, int c, int32_t p0,
+                                                     int32_t cnt, const double *__restrict__ Einv,
+                                                     T *__restrict__ yz, T *__restrict__ x) {
     using A = typename Acc<T>::type;
     constexpr int nn = n * n;
     const int t = threadIdx.x;
     const int lr = t / n, r = t - lr * n;
     const int32_t q = blockIdx.x * 64 + lr;
     const bool act = q < cnt;
-    const int32_t i = act ? rows[q] : 0;
+    const int32_t p = p0 + q;
+    const int32_t i = act ? S.prow[p] : 0;
     A au = 0;
     if (act) {
-        const int32_t sl = i >> S.lc, ii = i - (sl << S.lc);
+        const int32_t sl = p >> S.lc, ii = p - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
         for (int32_t k = 0; k < w; ++k) {
             const int64_t e = base + ((int64_t)k << S.lc);
@@ -470,28 +481,31 @@ __global__ __launch_bounds__(64 * n) void k_dilu_bwd(SellView S, const T *__rest
 // offdiag: leave out the diagonal block of each row (counted, not assumed)
 // Slice widths: one thread per (padded) row computes its stored length, the
 // C consecutive lanes of a slice (C divides the wavefront) take the maximum.
-__global__ void k_sell_width(int32_t N, int32_t ns, int32_t C, const int32_t *rp, const int32_t *col, int32_t *sw,
-                             int32_t *cnt, int offdiag) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_sell_width(int32_t npos, int32_t ns, int32_t C, const int32_t *rp, const int32_t *col,
+                             const int32_t *prow, int32_t *sw, int32_t *cnt, int offdiag) {
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = p < npos ? (prow ? prow[p] : p) : -1;
     int32_t len = 0;
-    if (i < N) {
+    if (i >= 0) {
         len = rp[i + 1] - rp[i];
         if (offdiag)
             for (int32_t k = rp[i]; k < rp[i + 1]; ++k) len -= col[k] == i ? 1 : 0;
     }
     for (int o = C >> 1; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
-    const int32_t sl = i / C;
-    if (i - sl * C == 0 && sl < ns) {
+    const int32_t sl = p / C;
+    if (p - sl * C == 0 && sl < ns) {
         sw[sl] = len;
         cnt[sl] = len * C;
     }
 }
 
-__global__ void k_sell_fill_idx(int32_t N, int32_t C, const int32_t *rp, const int32_t *col, const int32_t *soff,
-                                int32_t *scol, int32_t *ssrc, int offdiag) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int32_t sl = i / C, ii = i - sl * C;
+__global__ void k_sell_fill_idx(int32_t npos, int32_t C, const int32_t *rp, const int32_t *col, const int32_t *prow,
+                                const int32_t *soff, int32_t *scol, int32_t *ssrc, int offdiag) {
+    const int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npos) return;
+    const int32_t i = prow ? prow[p] : p;
+    if (i < 0) return;
+    const int32_t sl = p / C, ii = p - sl * C;
     int32_t q = 0;
     for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
         if (offdiag && col[k] == i) continue;
@@ -505,6 +519,24 @@ __global__ void k_sell_fill_idx(int32_t N, int32_t C, const int32_t *rp, const i
 __global__ void k_fill_i32(int64_t m, int32_t *a, int32_t v) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g < m) a[g] = v;
+}
+
+// Colour-ordered positions: the t-th row of the (colour, row)-sorted list
+// goes to position cpos[c] + t - off[c] of its colour c.
+struct ColourRanges {
+    int32_t ncol;
+    int32_t off[kMaxColourRanges + 1], cpos[kMaxColourRanges + 1];
+};
+
+__global__ void k_colour_positions(int32_t N, ColourRanges cr, const int32_t *rows, int32_t *prow) {
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    int lo = 0, hi = cr.ncol - 1;            // colour c with off[c] <= t < off[c+1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cr.off[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    prow[cr.cpos[lo] + (t - cr.off[lo])] = rows[t];
 }
 
 // Values of a sliced copy gathered from block CSR (zeros in padding); with
@@ -664,27 +696,52 @@ template void launch_rows<float, float>(int, int, const SellView &, const float 
                                         const float *, double *);
 
 void sell_pattern_begin(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag,
-                        int slice) {
+                        int slice, const int32_t *rows_by_colour, const std::vector<int32_t> *colour_off) {
     int lc = 0;
     while ((1 << lc) < slice) ++lc;
     if ((1 << lc) != slice || lc > 6) cbs_throw(CBS_ERR_ARG, "slice height must be a power of two up to 64");
     const int32_t C = 1 << lc;
     S.N = N;
     S.lc = lc;
-    S.nslices = (N + C - 1) / C;
+    if (rows_by_colour && colour_off) {
+        const int ncol = (int)colour_off->size() - 1;
+        if (ncol > kMaxColourRanges) cbs_throw(CBS_ERR_ARG, "too many colours");
+        ColourRanges cr{};
+        cr.ncol = ncol;
+        S.cpos.assign(ncol + 1, 0);
+        for (int c = 0; c <= ncol; ++c) {
+            cr.off[c] = (*colour_off)[c];
+            if (c > 0) {
+                const int32_t cnt = (*colour_off)[c] - (*colour_off)[c - 1];
+                S.cpos[c] = S.cpos[c - 1] + (cnt + C - 1) / C * C;
+            }
+            cr.cpos[c] = S.cpos[c];
+        }
+        S.npos = S.cpos[ncol];
+        S.prow.alloc(S.npos > 0 ? S.npos : 1);
+        if (S.npos > 0)
+            hipLaunchKernelGGL(k_fill_i32, dim3(cdiv(S.npos, 256)), dim3(256), 0, st, (int64_t)S.npos, S.prow.get(), -1);
+        if (N > 0)
+            hipLaunchKernelGGL(k_colour_positions, dim3(cdiv(N, 256)), dim3(256), 0, st, N, cr, rows_by_colour,
+                               S.prow.get());
+    } else {
+        S.prow.release();
+        S.cpos.clear();
+        S.npos = N;
+    }
+    S.nslices = (S.npos + C - 1) / C;
     const int32_t ns = S.nslices;
     S.sw.alloc(ns > 0 ? ns : 1);
     S.soff.alloc(ns + 1);
     if (ns > 0)
-        hipLaunchKernelGGL(k_sell_width, dim3(cdiv((int64_t)ns * C, 256)), dim3(256), 0, st, N, ns, C, rp, col,
-                           S.sw.get(), S.soff.get(), offdiag ? 1 : 0);
+        hipLaunchKernelGGL(k_sell_width, dim3(cdiv((int64_t)ns * C, 256)), dim3(256), 0, st, S.npos, ns, C, rp, col,
+                           S.prow.get(), S.sw.get(), S.soff.get(), offdiag ? 1 : 0);
     LAUNCHCHK();
     scan_exclusive(S.soff.get(), S.soff.get(), ns, st);
 }
 
 void sell_pattern_finish(const int32_t *rp, const int32_t *col, Sell &S, int64_t nent, hipStream_t st,
                          bool offdiag) {
-    const int32_t N = S.N;
     S.nent = nent;
     S.scol.alloc(S.nent > 0 ? S.nent : 1);
     S.ssrc.alloc(S.nent > 0 ? S.nent : 1);
@@ -692,14 +749,15 @@ void sell_pattern_finish(const int32_t *rp, const int32_t *col, Sell &S, int64_t
         hipLaunchKernelGGL(k_fill_i32, dim3(cdiv(S.nent, 256)), dim3(256), 0, st, S.nent, S.scol.get(), -1);
         hipLaunchKernelGGL(k_fill_i32, dim3(cdiv(S.nent, 256)), dim3(256), 0, st, S.nent, S.ssrc.get(), -1);
     }
-    if (N > 0)
-        hipLaunchKernelGGL(k_sell_fill_idx, dim3(cdiv(N, 256)), dim3(256), 0, st, N, 1 << S.lc, rp, col,
-                           S.soff.get(), S.scol.get(), S.ssrc.get(), offdiag ? 1 : 0);
+    if (S.npos > 0)
+        hipLaunchKernelGGL(k_sell_fill_idx, dim3(cdiv(S.npos, 256)), dim3(256), 0, st, S.npos, 1 << S.lc, rp, col,
+                           S.prow.get(), S.soff.get(), S.scol.get(), S.ssrc.get(), offdiag ? 1 : 0);
     LAUNCHCHK();
 }
 
-void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag, int slice) {
-    sell_pattern_begin(N, rp, col, S, st, offdiag, slice);
+void sell_build(int32_t N, const int32_t *rp, const int32_t *col, Sell &S, hipStream_t st, bool offdiag, int slice,
+                const int32_t *rows_by_colour, const std::vector<int32_t> *colour_off) {
+    sell_pattern_begin(N, rp, col, S, st, offdiag, slice, rows_by_colour, colour_off);
     sell_pattern_finish(rp, col, S, read_int(S.soff.get() + S.nslices, st), st, offdiag);
 }
 
@@ -915,11 +973,11 @@ void launch_block_apply(int n, int32_t N, const double *Dinv, const double *r, d
 }
 
 template <typename T>
-void launch_gs_colour(int n, const SellView &S, const T *val, const int32_t *rows, int32_t cnt, const double *Dinv,
+void launch_gs_colour(int n, const SellView &S, const T *val, int32_t p0, int32_t cnt, const double *Dinv,
                       const T *b, T *x, hipStream_t st) {
     if (cnt <= 0) return;
     const dim3 g(cdiv(cnt, 64));
-#define GS_C(NN) hipLaunchKernelGGL((k_gs_colour<NN, T>), g, dim3(64 * NN), 0, st, S, val, rows, cnt, Dinv, b, x)
+#define GS_C(NN) hipLaunchKernelGGL((k_gs_colour<NN, T>), g, dim3(64 * NN), 0, st, S, val, p0, cnt, Dinv, b, x)
     switch (n) {
         case 1: GS_C(1); break;
         case 2: GS_C(2); break;
@@ -930,28 +988,27 @@ void launch_gs_colour(int n, const SellView &S, const T *val, const int32_t *row
 #undef GS_C
     LAUNCHCHK();
 }
-template void launch_gs_colour<double>(int, const SellView &, const double *, const int32_t *, int32_t,
-                                       const double *, const double *, double *, hipStream_t);
-template void launch_gs_colour<float>(int, const SellView &, const float *, const int32_t *, int32_t, const double *,
+template void launch_gs_colour<double>(int, const SellView &, const double *, int32_t, int32_t, const double *,
+                                       const double *, double *, hipStream_t);
+template void launch_gs_colour<float>(int, const SellView &, const float *, int32_t, int32_t, const double *,
                                       const float *, float *, hipStream_t);
 
 template <typename T>
-void launch_dilu_fwd(int n, const SellView &S, const T *val, const T *fval, const int32_t *colour, int c,
-                     const int32_t *rows, int32_t cnt, const double *Einv, const T *b, const T *x, T *y,
-                     bool zero_guess, hipStream_t st) {
+void launch_dilu_fwd(int n, const SellView &S, const T *val, const T *fval, const int32_t *colour, int c, int32_t p0,
+                     int32_t cnt, const double *Einv, const T *b, T *x, T *y, bool zero_guess, bool last,
+                     hipStream_t st) {
     if (cnt <= 0) return;
     const dim3 g(cdiv(cnt, 64));
     if (zero_guess && fval) {                  // no residual: only the factor is read
         val = fval;
         fval = nullptr;
     }
-#define DILU_F(NN)                                                                                              \
-    if (zero_guess)                                                                                             \
-        hipLaunchKernelGGL((k_dilu_fwd<NN, T, true>), g, dim3(64 * NN), 0, st, S, val, fval, colour, c, rows, cnt, \
-                           Einv, b, x, y);                                                                      \
-    else                                                                                                        \
-        hipLaunchKernelGGL((k_dilu_fwd<NN, T, false>), g, dim3(64 * NN), 0, st, S, val, fval, colour, c, rows, cnt, \
-                           Einv, b, x, y);
+#define DILU_F1(NN, Z, LA)                                                                                       \
+    hipLaunchKernelGGL((k_dilu_fwd<NN, T, Z, LA>), g, dim3(64 * NN), 0, st, S, val, fval, colour, c, p0, cnt, Einv, \
+                       b, x, y)
+#define DILU_F(NN)                                                                                               \
+    if (zero_guess) { if (last) DILU_F1(NN, true, true); else DILU_F1(NN, true, false); }                         \
+    else { if (last) DILU_F1(NN, false, true); else DILU_F1(NN, false, false); }
     switch (n) {
         case 1: DILU_F(1) break;
         case 2: DILU_F(2) break;
@@ -960,19 +1017,20 @@ void launch_dilu_fwd(int n, const SellView &S, const T *val, const T *fval, cons
         case 5: DILU_F(5) break;
     }
 #undef DILU_F
+#undef DILU_F1
     LAUNCHCHK();
 }
 
 template <typename T>
-void launch_dilu_bwd(int n, const SellView &S, const T *val, const int32_t *colour, int c, const int32_t *rows,
-                     int32_t cnt, const double *Einv, T *yz, T *x, bool zero_guess, hipStream_t st) {
+void launch_dilu_bwd(int n, const SellView &S, const T *val, const int32_t *colour, int c, int32_t p0, int32_t cnt,
+                     const double *Einv, T *yz, T *x, bool zero_guess, hipStream_t st) {
     if (cnt <= 0) return;
     const dim3 g(cdiv(cnt, 64));
 #define DILU_B(NN)                                                                                              \
     if (zero_guess)                                                                                             \
-        hipLaunchKernelGGL((k_dilu_bwd<NN, T, true>), g, dim3(64 * NN), 0, st, S, val, colour, c, rows, cnt, Einv, yz, x); \
+        hipLaunchKernelGGL((k_dilu_bwd<NN, T, true>), g, dim3(64 * NN), 0, st, S, val, colour, c, p0, cnt, Einv, yz, x); \
     else                                                                                                        \
-        hipLaunchKernelGGL((k_dilu_bwd<NN, T, false>), g, dim3(64 * NN), 0, st, S, val, colour, c, rows, cnt, Einv, yz, x);
+        hipLaunchKernelGGL((k_dilu_bwd<NN, T, false>), g, dim3(64 * NN), 0, st, S, val, colour, c, p0, cnt, Einv, yz, x);
     switch (n) {
         case 1: DILU_B(1) break;
         case 2: DILU_B(2) break;
@@ -985,15 +1043,15 @@ void launch_dilu_bwd(int n, const SellView &S, const T *val, const int32_t *colo
 }
 
 template void launch_dilu_fwd<double>(int, const SellView &, const double *, const double *, const int32_t *, int,
-                                      const int32_t *, int32_t, const double *, const double *, const double *,
-                                      double *, bool, hipStream_t);
+                                      int32_t, int32_t, const double *, const double *, double *, double *, bool, bool,
+                                      hipStream_t);
 template void launch_dilu_fwd<float>(int, const SellView &, const float *, const float *, const int32_t *, int,
-                                     const int32_t *, int32_t, const double *, const float *, const float *, float *,
-                                     bool, hipStream_t);
-template void launch_dilu_bwd<double>(int, const SellView &, const double *, const int32_t *, int, const int32_t *,
-                                      int32_t, const double *, double *, double *, bool, hipStream_t);
-template void launch_dilu_bwd<float>(int, const SellView &, const float *, const int32_t *, int, const int32_t *,
-                                     int32_t, const double *, float *, float *, bool, hipStream_t);
+                                     int32_t, int32_t, const double *, const float *, float *, float *, bool, bool,
+                                     hipStream_t);
+template void launch_dilu_bwd<double>(int, const SellView &, const double *, const int32_t *, int, int32_t, int32_t,
+                                      const double *, double *, double *, bool, hipStream_t);
+template void launch_dilu_bwd<float>(int, const SellView &, const float *, const int32_t *, int, int32_t, int32_t,
+                                     const double *, float *, float *, bool, hipStream_t);
 
 // ------------------------------------------------------------------ autotuning
 // The residual kernel (the shape shared by SpMV and the smoother sweeps) is

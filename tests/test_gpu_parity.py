@@ -315,16 +315,18 @@ def test_rap_and_vcycle_match_oracle_given_gpu_aggregates(renumber, split):
     _agree(z, zr, 1e-11)
 
 
-@pytest.mark.parametrize("split,pre,post", [(0, 2, 2), (16, 2, 2), (0, 1, 3), (0, 0, 2)])
-def test_mixed_vcycle_matches_fp64_oracle_vcycle(split, pre, post):
+@pytest.mark.parametrize("split,pre,post,scaled", [(0, 2, 2, 1), (16, 2, 2, 1), (0, 1, 3, 1), (0, 0, 2, 1),
+                                                   (0, 2, 2, 0), (16, 1, 3, 0)])
+def test_mixed_vcycle_matches_fp64_oracle_vcycle(split, pre, post, scaled):
     """The mixed-precision V-cycle (FP32 levels, block-Jacobi sweeps on row-scaled
-    values) is the oracle's FP64 V-cycle on the same hierarchy up to FP32 rounding."""
-    _say("mixed vcycle split", split, "sweeps", pre, post)
+    values, or on the FP32 values with the FP64 D^{-1}) is the oracle's FP64
+    V-cycle on the same hierarchy up to FP32 rounding."""
+    _say("mixed vcycle split", split, "sweeps", pre, post, "scaled", scaled)
     s = pressure_velocity(12, 10, 9, seed=5)
     A = O.from_system(s)
     with P.System.from_dict(s) as sysm:
         sysm.setup(precond=P.PREC_AMG, precision=P.PRECISION_MIXED, coarse_max=8, pre_sweeps=pre,
-                   post_sweeps=post, omega=0.9, row_split=split)
+                   post_sweeps=post, omega=0.9, row_split=split, scaled_sweeps=scaled)
         nlev = sysm.info()["levels"]
         assert nlev >= 3
         lv0 = sysm.get_level(0)
@@ -400,16 +402,17 @@ def _diag_blocks(A):
     return D
 
 
-@pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
-def test_level_kernels_match_oracle(precision):
+@pytest.mark.parametrize("precision,scaled", [(P.PRECISION_FP64, 1), (P.PRECISION_MIXED, 1), (P.PRECISION_MIXED, 0)])
+def test_level_kernels_match_oracle(precision, scaled):
     """cbs_level_apply: the residual and block-Jacobi sweep kernels of every
     smoothed level against the oracle on that level's matrix; in mixed
-    precision the sweep takes the scaled right side Dinv b."""
-    _say("level kernels", precision)
+    precision with row-scaled sweeps the sweep takes the scaled right side
+    Dinv b."""
+    _say("level kernels", precision, scaled)
     s = pressure_velocity(12, 10, 9, seed=6)
     rng = np.random.default_rng(7)
     with P.System.from_dict(s) as sysm:
-        sysm.setup(precond=P.PREC_AMG, precision=precision, coarse_max=8, omega=0.9)
+        sysm.setup(precond=P.PREC_AMG, precision=precision, coarse_max=8, omega=0.9, scaled_sweeps=scaled)
         nlev = sysm.info()["levels"]
         assert nlev >= 3
         for l in range(nlev - 1):
@@ -425,7 +428,7 @@ def test_level_kernels_match_oracle(precision):
             assert np.abs(r - (b - O.spmv(Al, x))).max() <= tol * scale
             Dinv = O.blockinv(_diag_blocks(Al))
             y = _np(sysm.level_apply(l, P.LEVEL_SWEEP, b, x)).astype(np.float64)
-            if precision == P.PRECISION_FP64:
+            if precision == P.PRECISION_FP64 or not scaled:
                 ref = O.bjacobi_sweep(Al, Dinv, b, x, 0.9)
             else:
                 ref = x + 0.9 * (b - np.einsum("kij,kj->ki", Dinv, O.spmv(Al, x)))
@@ -437,7 +440,8 @@ def test_level_kernels_match_oracle(precision):
         with pytest.raises(P.CbsError) as e:
             sysm.level_apply(0, 7, b, x)
         assert e.value.code == P.ERR_ARG
-        sysm.setup(precond=P.PREC_AMG, precision=precision, smoother=P.SMOOTH_DILU, dilu_levels=1, coarse_max=8)
+        sysm.setup(precond=P.PREC_AMG, precision=precision, smoother=P.SMOOTH_DILU, dilu_levels=1, coarse_max=8,
+                   scaled_sweeps=scaled)
         n0 = sysm.get_level(0)["N"]
         z0 = np.zeros((n0, 4))
         with pytest.raises(P.CbsError) as e:
