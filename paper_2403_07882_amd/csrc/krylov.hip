@@ -461,14 +461,17 @@ void dilu_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x, bool zero_g
     const int ncol = (int)L.colour_off.size() - 1;
     const SellView S = L.sell.view(sizeof(T) == 4);
     auto cnt = [&](int c) { return L.colour_off[c + 1] - L.colour_off[c]; };
+    // with two colours the kernels know every neighbour's colour without
+    // reading it: the other one
+    const int32_t *colour = ncol <= 2 ? nullptr : L.colour.get();
     for (int c = 0; c < ncol; ++c)
-        launch_dilu_fwd<T>(h->n, S, val, fv, L.colour.get(), c, L.sell.cpos[c], cnt(c), Einv, b, x, y, zero_guess,
+        launch_dilu_fwd<T>(h->n, S, val, fv, colour, c, L.sell.cpos[c], cnt(c), Einv, b, x, y, zero_guess,
                            c == ncol - 1, h->stream);
     // the last colour's backward step changes nothing; its forward launch
     // already made its update
     for (int c = ncol - 2; c >= 0; --c)
-        launch_dilu_bwd<T>(h->n, S, fv ? fv : val, L.colour.get(), c, L.sell.cpos[c], cnt(c), Einv, y, x,
-                           zero_guess, h->stream);
+        launch_dilu_bwd<T>(h->n, S, fv ? fv : val, colour, c, L.sell.cpos[c], cnt(c), Einv, y, x, zero_guess,
+                           h->stream);
 }
 
 // One symmetric block Gauss-Seidel step in place: the colour classes in

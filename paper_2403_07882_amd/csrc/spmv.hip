@@ -324,6 +324,8 @@ void rows_n(int mode, const SellView &S, const TV *val, const TX *x, const TX *b
 }
 
 // ------------------------------------------------------------------ DILU sweeps
+constexpr int kDiluU = 4;    // blocks in flight per thread in the coloured sweeps
+
 // Multicolour DILU (one launch per colour): rows of colour c depend only on
 // rows of other colours, which earlier launches finished.
 //   forward  y_i = E_i^{-1} (b_i - sum_j A_ij x_j - sum_{colour(j) < c} A_ij y_j)
@@ -350,16 +352,26 @@ __global__ __launch_bounds__(64 * n) void k_gs_colour(SellView S, const T *__res
     if (act) {
         const int32_t sl = p >> S.lc, ii = p - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
-        for (int32_t k = 0; k < w; ++k) {
-            const int64_t e = base + ((int64_t)k << S.lc);
-            const int32_t j = S.scol[e];
-            if (j < 0) break;                      // padding sits at the end of a row
-            if (j == i) continue;
-            T bv[n], xv[n];
-            load_block_row<n, T>(val + e * nn + r * n, bv);
-            load_x<n, T>(x + (int64_t)j * n, xv);
+        // kDiluU blocks in flight per step, summed in column order;
+        // padding (column -1) and the diagonal add nothing
+        for (int32_t k0 = 0; k0 < w; k0 += kDiluU) {
+            int32_t j[kDiluU];
+            T bv[kDiluU][n], xv[kDiluU][n];
 #pragma unroll
-            for (int cc = 0; cc < n; ++cc) acc += (A)bv[cc] * (A)xv[cc];
+            for (int u = 0; u < kDiluU; ++u)
+                j[u] = k0 + u < w ? S.scol[base + ((int64_t)(k0 + u) << S.lc)] : -1;
+#pragma unroll
+            for (int u = 0; u < kDiluU; ++u) {
+                if (j[u] < 0 || j[u] == i) continue;
+                load_block_row<n, T>(val + (base + ((int64_t)(k0 + u) << S.lc)) * nn + r * n, bv[u]);
+                load_x<n, T>(x + (int64_t)j[u] * n, xv[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kDiluU; ++u) {
+                if (j[u] < 0 || j[u] == i) continue;
+#pragma unroll
+                for (int cc = 0; cc < n; ++cc) acc += (A)bv[u][cc] * (A)xv[u][cc];
+            }
         }
     }
     __shared__ A sres[64 * n];
@@ -398,24 +410,39 @@ __global__ __launch_bounds__(64 * n) void k_dilu_fwd(SellView S, const T *__rest
     if (act) {
         const int32_t sl = p >> S.lc, ii = p - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
-        for (int32_t k = 0; k < w; ++k) {
-            const int64_t e = base + ((int64_t)k << S.lc);
-            const int32_t j = S.scol[e];
-            if (j < 0) break;                      // padding sits at the end of a row
-            T bv[n];
-            load_block_row<n, T>(val + e * nn + r * n, bv);
-            if (!ZERO) {
-                T xv[n];
-                load_x<n, T>(x + (int64_t)j * n, xv);
+        // kDiluU blocks in flight per step, summed in column order
+        for (int32_t k0 = 0; k0 < w; k0 += kDiluU) {
+            int32_t j[kDiluU];
+            bool lo[kDiluU];
+            T bv[kDiluU][n], xv[kDiluU][n], yv[kDiluU][n], fv[kDiluU][n];
 #pragma unroll
-                for (int cc = 0; cc < n; ++cc) ax += (A)bv[cc] * (A)xv[cc];
+            for (int u = 0; u < kDiluU; ++u)
+                j[u] = k0 + u < w ? S.scol[base + ((int64_t)(k0 + u) << S.lc)] : -1;
+#pragma unroll
+            for (int u = 0; u < kDiluU; ++u) {
+                // two colours (colour == nullptr): every neighbour of a
+                // colour-1 row precedes it
+                lo[u] = j[u] >= 0 && (colour ? colour[j[u]] < c : (c == 1 && j[u] != i));
+                if (j[u] < 0) continue;
+                const int64_t e = base + ((int64_t)(k0 + u) << S.lc);
+                load_block_row<n, T>(val + e * nn + r * n, bv[u]);
+                if (!ZERO) load_x<n, T>(x + (int64_t)j[u] * n, xv[u]);
+                if (lo[u]) {
+                    load_x<n, T>(y + (int64_t)j[u] * n, yv[u]);
+                    if (fval) load_block_row<n, T>(fval + e * nn + r * n, fv[u]);
+                }
             }
-            if (colour[j] < c) {
-                T yv[n];
-                load_x<n, T>(y + (int64_t)j * n, yv);
-                if (fval) load_block_row<n, T>(fval + e * nn + r * n, bv);
 #pragma unroll
-                for (int cc = 0; cc < n; ++cc) ay += (A)bv[cc] * (A)yv[cc];
+            for (int u = 0; u < kDiluU; ++u) {
+                if (j[u] < 0) continue;
+                if (!ZERO) {
+#pragma unroll
+                    for (int cc = 0; cc < n; ++cc) ax += (A)bv[u][cc] * (A)xv[u][cc];
+                }
+                if (lo[u]) {
+#pragma unroll
+                    for (int cc = 0; cc < n; ++cc) ay += (A)(fval ? fv[u][cc] : bv[u][cc]) * (A)yv[u][cc];
+                }
             }
         }
     }
@@ -450,16 +477,28 @@ __global__ __launch_bounds__(64 * n) void k_dilu_bwd(SellView S, const T *__rest
     if (act) {
         const int32_t sl = p >> S.lc, ii = p - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
-        for (int32_t k = 0; k < w; ++k) {
-            const int64_t e = base + ((int64_t)k << S.lc);
-            const int32_t j = S.scol[e];
-            if (j < 0) break;
-            if (colour[j] <= c) continue;
-            T bv[n], zv[n];
-            load_block_row<n, T>(val + e * nn + r * n, bv);
-            load_x<n, T>(yz + (int64_t)j * n, zv);
+        // kDiluU blocks in flight per step, summed in column order; only
+        // neighbours of later colours count
+        for (int32_t k0 = 0; k0 < w; k0 += kDiluU) {
+            int32_t j[kDiluU];
+            bool up[kDiluU];
+            T bv[kDiluU][n], zv[kDiluU][n];
 #pragma unroll
-            for (int cc = 0; cc < n; ++cc) au += (A)bv[cc] * (A)zv[cc];
+            for (int u = 0; u < kDiluU; ++u)
+                j[u] = k0 + u < w ? S.scol[base + ((int64_t)(k0 + u) << S.lc)] : -1;
+#pragma unroll
+            for (int u = 0; u < kDiluU; ++u) {
+                up[u] = j[u] >= 0 && (colour ? colour[j[u]] > c : (c == 0 && j[u] != i));
+                if (!up[u]) continue;
+                load_block_row<n, T>(val + (base + ((int64_t)(k0 + u) << S.lc)) * nn + r * n, bv[u]);
+                load_x<n, T>(yz + (int64_t)j[u] * n, zv[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kDiluU; ++u) {
+                if (!up[u]) continue;
+#pragma unroll
+                for (int cc = 0; cc < n; ++cc) au += (A)bv[u][cc] * (A)zv[u][cc];
+            }
         }
     }
     __shared__ A su[64 * n];
