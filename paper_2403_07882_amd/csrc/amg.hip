@@ -46,9 +46,17 @@ __device__ inline bool gj_inverse(double (&a)[n][2 * n]) {
         for (int r = k + 1; r < n; ++r)
             if (fabs(a[r][k]) > pv) { pv = fabs(a[r][k]); p = r; }
         if (!(pv > 0.0) || !isfinite(pv)) return false;
-        if (p != k) {
+        // swap rows k and p with compile-time row indices only (selects), so
+        // the array stays in registers
 #pragma unroll
-            for (int c = 0; c < 2 * n; ++c) { double t = a[k][c]; a[k][c] = a[p][c]; a[p][c] = t; }
+        for (int r = k + 1; r < n; ++r) {
+            const bool sw = r == p;
+#pragma unroll
+            for (int c = 0; c < 2 * n; ++c) {
+                const double t = a[k][c];
+                a[k][c] = sw ? a[r][c] : t;
+                a[r][c] = sw ? t : a[r][c];
+            }
         }
         const double piv = a[k][k];
 #pragma unroll
@@ -64,24 +72,44 @@ __device__ inline bool gj_inverse(double (&a)[n][2 * n]) {
     return true;
 }
 
+// One thread inverts one block; the workgroup's blocks pass through LDS,
+// so both the gather of the diagonal blocks (n*n contiguous values each) and
+// the store of the inverses (one contiguous run) are read and written by
+// consecutive lanes.
+constexpr int kInvThreads = 128;
 template <int n>
-__global__ void k_blockinv(int32_t N, const int32_t *__restrict__ dslot, const double *__restrict__ val,
-                           double *__restrict__ Dinv, int32_t *bad) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const double *D = val + (int64_t)dslot[i] * (n * n);
-    double a[n][2 * n];
+__global__ __launch_bounds__(kInvThreads) void k_blockinv(int32_t N, const int32_t *__restrict__ dslot,
+                                                          const double *__restrict__ val, double *__restrict__ Dinv,
+                                                          int32_t *bad) {
+    constexpr int nn = n * n;
+    __shared__ double sh[kInvThreads * nn];
+    __shared__ int32_t ss[kInvThreads];
+    const int32_t i0 = blockIdx.x * kInvThreads;
+    const int cnt = min(kInvThreads, N - i0);
+    const int t = threadIdx.x;
+    if (t < cnt) ss[t] = dslot[i0 + t];
+    __syncthreads();
+    for (int e = t; e < cnt * nn; e += kInvThreads) {
+        const int q = e / nn;
+        sh[e] = val[(int64_t)ss[q] * nn + (e - q * nn)];
+    }
+    __syncthreads();
+    if (t < cnt) {
+        double a[n][2 * n];
 #pragma unroll
-    for (int r = 0; r < n; ++r)
+        for (int r = 0; r < n; ++r)
 #pragma unroll
-        for (int c = 0; c < 2 * n; ++c) a[r][c] = c < n ? D[r * n + c] : (c - n == r ? 1.0 : 0.0);
-    const bool ok = gj_inverse<n>(a);
-    if (!ok) atomicMin(bad, i);
-    double *out = Dinv + (int64_t)i * (n * n);
+            for (int c = 0; c < 2 * n; ++c) a[r][c] = c < n ? sh[t * nn + r * n + c] : (c - n == r ? 1.0 : 0.0);
+        const bool ok = gj_inverse<n>(a);
+        if (!ok) atomicMin(bad, i0 + t);
 #pragma unroll
-    for (int r = 0; r < n; ++r)
+        for (int r = 0; r < n; ++r)
 #pragma unroll
-        for (int c = 0; c < n; ++c) out[r * n + c] = ok ? a[r][n + c] : 0.0;
+            for (int c = 0; c < n; ++c) sh[t * nn + r * n + c] = ok ? a[r][n + c] : 0.0;
+    }
+    __syncthreads();
+    double *out = Dinv + (int64_t)i0 * nn;
+    for (int e = t; e < cnt * nn; e += kInvThreads) out[e] = sh[e];
 }
 
 // per-block transpose: out[k] = in[src_k]^T, src_k = mirror[k] (or k)
@@ -675,19 +703,25 @@ __global__ void k_perm_rows(int32_t N, const int32_t *ip, const int32_t *pos, co
     }
 }
 
-// out block k = in block sk[k]; each thread moves V values (V = 4 or 2 when
-// the block size allows: 32- or 16-byte accesses)
+// out block k = in block sk[k]; each thread moves V values: 4 or 2 when the
+// block size allows (32- or 16-byte accesses), else a whole block row (n
+// values; odd n, whose blocks do not align to 16 bytes)
 template <int n>
 __global__ void k_gather_blocks(int64_t nb, const int32_t *__restrict__ sk, const double *__restrict__ in,
                                 double *__restrict__ out) {
-    constexpr int nn = n * n, V = nn % 4 == 0 ? 4 : (nn % 2 == 0 ? 2 : 1);
+    constexpr int nn = n * n, V = nn % 4 == 0 ? 4 : (nn % 2 == 0 ? 2 : n);
     typedef double dv __attribute__((ext_vector_type(V)));
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nb * (nn / V)) return;
     const int64_t k = g / (nn / V);
     const int64_t e = (g - k * (nn / V)) * V;
-    if constexpr (V == 1) {
-        out[k * nn + e] = in[(int64_t)sk[k] * nn + e];
+    if constexpr (V == n && n % 2 == 1) {
+        const double *src = in + (int64_t)sk[k] * nn + e;
+        double v[n];
+#pragma unroll
+        for (int c = 0; c < n; ++c) v[c] = src[c];
+#pragma unroll
+        for (int c = 0; c < n; ++c) out[k * nn + e + c] = v[c];
     } else {
         *reinterpret_cast<dv *>(out + k * nn + e) = *reinterpret_cast<const dv *>(in + (int64_t)sk[k] * nn + e);
     }
@@ -871,7 +905,8 @@ __global__ void k_colour_starts(int32_t ncol, int32_t nblk, const int32_t *off, 
 
 // E_i = A_ii - sum_{colour(j) < c} A_ij E_j^{-1} A_ji for the rows of colour c
 template <int n>
-__global__ void k_dilu_setup(const int32_t *rows, int32_t cnt, int c, const int32_t *rp, const int32_t *col,
+__global__ __launch_bounds__(128) void k_dilu_setup(const int32_t *rows, int32_t cnt, int c, const int32_t *rp,
+                                                    const int32_t *col,
                              const int32_t *mirror, const int32_t *dslot, const double *val,
                              const int32_t *colour, double *Einv, int32_t *bad) {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -931,7 +966,8 @@ __global__ void k_dilu_setup(const int32_t *rows, int32_t cnt, int c, const int3
 // (updates outside the pattern are dropped).  Row i is written only by its
 // own thread; rows of earlier colours are final and only read.
 template <int n>
-__global__ void k_ilu_setup(const int32_t *rows, int32_t cnt, int c, const int32_t *rp, const int32_t *col,
+__global__ __launch_bounds__(64) void k_ilu_setup(const int32_t *rows, int32_t cnt, int c, const int32_t *rp,
+                                                  const int32_t *col,
                             const int32_t *dslot, const int32_t *colour, double *F, double *Einv, int32_t *bad) {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= cnt) return;
@@ -1015,7 +1051,9 @@ namespace {
 
 template <int n>
 void blockinv_n(int32_t N, const int32_t *dslot, const double *val, double *Dinv, int32_t *bad, hipStream_t st) {
-    hipLaunchKernelGGL(k_blockinv<n>, dim3(cdiv(N, 128)), dim3(128), 0, st, N, dslot, val, Dinv, bad);
+    if (N > 0)
+        hipLaunchKernelGGL(k_blockinv<n>, dim3(cdiv(N, kInvThreads)), dim3(kInvThreads), 0, st, N, dslot, val, Dinv,
+                           bad);
 }
 template <int n>
 void transpose_n(int64_t nb, const int32_t *mirror, const double *in, double *out, hipStream_t st) {
@@ -1062,7 +1100,7 @@ void ilu_setup_n(const int32_t *rows, int32_t cnt, int c, const int32_t *rp, con
 }
 template <int n>
 void gather_blocks_n(int64_t nb, const int32_t *sk, const double *in, double *out, hipStream_t st) {
-    constexpr int nn = n * n, V = nn % 4 == 0 ? 4 : (nn % 2 == 0 ? 2 : 1);
+    constexpr int nn = n * n, V = nn % 4 == 0 ? 4 : (nn % 2 == 0 ? 2 : n);
     const int64_t tot = nb * (nn / V);
     if (tot > 0) hipLaunchKernelGGL(k_gather_blocks<n>, dim3(cdiv(tot, 256)), dim3(256), 0, st, nb, sk, in, out);
 }

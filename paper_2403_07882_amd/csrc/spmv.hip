@@ -580,21 +580,34 @@ __global__ void k_colour_positions(int32_t N, ColourRanges cr, const int32_t *ro
 
 // Values of a sliced copy gathered from block CSR (zeros in padding); with
 // out32, also their FP32 rounding, flagging (bit 64) values FP32 cannot hold.
+// Each thread moves kSellV(n) consecutive values of one block: 4 or 2 when
+// n*n allows, else one block row (odd n).
+__host__ __device__ constexpr int kSellV(int n) { return (n * n) % 4 == 0 ? 4 : ((n * n) % 2 == 0 ? 2 : n); }
+
 template <int n, bool F32>
 __global__ void k_sell_vals(int64_t nent, const int32_t *__restrict__ ssrc, const double *__restrict__ in,
                             double *__restrict__ out, float *__restrict__ out32, int32_t *flag) {
-    constexpr int nn = n * n;
+    constexpr int nn = n * n, V = kSellV(n);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= nent * nn) return;
-    const int64_t e = g / nn;
+    if (g >= nent * (nn / V)) return;
+    const int64_t e = g / (nn / V);
+    const int64_t o = e * nn + (g - e * (nn / V)) * V;     // first value of this thread
     const int32_t k = ssrc[e];
-    const double v = k >= 0 ? in[(int64_t)k * nn + (g - e * nn)] : 0.0;
-    out[g] = v;
-    if constexpr (F32) {
-        const float f = (float)v;
-        out32[g] = f;
-        if (!isfinite(f)) atomicOr(flag, 64);
+    const double *src = in + (int64_t)(k < 0 ? 0 : k) * nn + (o - e * nn);
+    double v[V];
+#pragma unroll
+    for (int c = 0; c < V; ++c) v[c] = k >= 0 ? src[c] : 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+        out[o + c] = v[c];
+        if constexpr (F32) {
+            const float f = (float)v[c];
+            out32[o + c] = f;
+            bad = bad || !isfinite(f);
+        }
     }
+    if (bad) atomicOr(flag, 64);
 }
 
 // Row-scaled FP32 values for the block-Jacobi sweep: entry (i, j) of the
@@ -603,50 +616,57 @@ __global__ void k_sell_vals(int64_t nent, const int32_t *__restrict__ ssrc, cons
 // row, r); padding entries, including the rows that pad the last slice past
 // N, get zeros.
 template <int n>
-__global__ void k_sell_scaled(int32_t N, int32_t nslices, int32_t C, const int32_t *__restrict__ soff,
-                              const int32_t *__restrict__ sw, const int32_t *__restrict__ ssrc,
-                              const double *__restrict__ bvals, const double *__restrict__ Dinv,
-                              float *__restrict__ out, int32_t *flag) {
+__global__ __launch_bounds__(64 * n) void k_sell_scaled(int32_t N, int32_t nslices, int32_t lc,
+                                                        const int32_t *__restrict__ soff,
+                                                        const int32_t *__restrict__ sw,
+                                                        const int32_t *__restrict__ ssrc,
+                                                        const double *__restrict__ bvals,
+                                                        const double *__restrict__ Dinv, float *__restrict__ out,
+                                                        int32_t *flag) {
+    // 64 slice rows per workgroup, n threads each; per entry, thread r stages
+    // row r of the block A_ij in LDS and then forms row r of Dinv_i A_ij from
+    // all of it (each block is read from memory once)
     constexpr int nn = n * n;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (int64_t)nslices * C * n) return;
-    const int32_t i = (int32_t)(g / n);
-    const int r = (int)(g - (int64_t)i * n);
-    const int32_t sl = i / C, ii = i - sl * C;
-    const int64_t base = (int64_t)soff[sl] + ii;
-    const int32_t w = sw[sl];
+    __shared__ double sa[64 * nn];
+    __shared__ int32_t wmax;
+    const int t = threadIdx.x, lr = t / n, r = t - lr * n;
+    const int64_t npos = (int64_t)nslices << lc;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lr;
+    const bool act = i < npos;
+    const int32_t sl = act ? (int32_t)(i >> lc) : 0;
+    const int64_t base = act ? (int64_t)soff[sl] + (i - ((int64_t)sl << lc)) : 0;
+    const int32_t w = act ? sw[sl] : 0;
+    if (t == 0) wmax = 0;
+    __syncthreads();
+    if (r == 0 && w > 0) atomicMax(&wmax, w);
     double d[n];
 #pragma unroll
-    for (int q = 0; q < n; ++q) d[q] = i < N ? Dinv[(int64_t)i * nn + r * n + q] : 0.0;
-    // entries two at a time, the next pair's source slots loaded ahead
-    auto slot = [&](int32_t k) { return (i < N && k < w) ? ssrc[base + (int64_t)k * C] : -1; };
-    int32_t s0 = slot(0), s1 = slot(1);
-    for (int32_t k = 0; k < w; k += 2) {
-        const int32_t src[2] = {s0, s1};
-        s0 = slot(k + 2);
-        s1 = slot(k + 3);
-        double a[2][nn];
+    for (int q = 0; q < n; ++q) d[q] = (act && i < N) ? Dinv[i * nn + r * n + q] : 0.0;
+    __syncthreads();
+    const int32_t W = wmax;
+    bool bad = false;
+    for (int32_t k = 0; k < W; ++k) {
+        const bool has = k < w;
+        const int64_t e = base + ((int64_t)k << lc);
+        const int32_t src = (has && i < N) ? ssrc[e] : -1;
+        const double *p = bvals + (int64_t)(src < 0 ? 0 : src) * nn + r * n;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const double *p = bvals + (int64_t)(src[u] < 0 ? 0 : src[u]) * nn;
-#pragma unroll
-            for (int q = 0; q < nn; ++q) a[u][q] = src[u] < 0 ? 0.0 : p[q];
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (k + u >= w) break;
-            const int64_t e = base + (int64_t)(k + u) * C;
+        for (int c = 0; c < n; ++c) sa[lr * nn + r * n + c] = src < 0 ? 0.0 : p[c];
+        __syncthreads();
+        if (has) {
 #pragma unroll
             for (int c = 0; c < n; ++c) {
                 double acc = 0.0;
 #pragma unroll
-                for (int q = 0; q < n; ++q) acc += d[q] * a[u][q * n + c];
+                for (int q = 0; q < n; ++q) acc += d[q] * sa[lr * nn + q * n + c];
                 const float v = (float)acc;
                 out[e * nn + r * n + c] = v;
-                if (!isfinite(v)) atomicOr(flag, 64);
+                bad = bad || !isfinite(v);
             }
         }
+        __syncthreads();
     }
+    if (bad) atomicOr(flag, 64);
 }
 
 template <typename TX>
@@ -804,13 +824,14 @@ void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipSt
                int32_t *flag) {
     const int64_t tot = S.nent * n * n;
     if (tot <= 0) return;
-    const dim3 g(cdiv(tot, 256)), b(256);
+    const dim3 b(256);
 #define SV(NN)                                                                                                  \
     if (out32)                                                                                                  \
-        hipLaunchKernelGGL((k_sell_vals<NN, true>), g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out, out32, flag); \
+        hipLaunchKernelGGL((k_sell_vals<NN, true>), dim3(cdiv(tot / kSellV(NN), 256)), b, 0, st, S.nent,          \
+                           S.ssrc.get(), bcsr_vals, out, out32, flag);                                          \
     else                                                                                                        \
-        hipLaunchKernelGGL((k_sell_vals<NN, false>), g, b, 0, st, S.nent, S.ssrc.get(), bcsr_vals, out, nullptr,    \
-                           nullptr)
+        hipLaunchKernelGGL((k_sell_vals<NN, false>), dim3(cdiv(tot / kSellV(NN), 256)), b, 0, st, S.nent,         \
+                           S.ssrc.get(), bcsr_vals, out, nullptr, nullptr)
     switch (n) {
         case 1: SV(1); break;
         case 2: SV(2); break;
@@ -824,12 +845,12 @@ void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipSt
 
 void sell_scale(int n, const Sell &S, const double *bcsr_vals, const double *Dinv, float *out, int32_t *flag,
                 hipStream_t st) {
-    const int64_t m = (int64_t)S.nslices * (1 << S.lc) * n;
+    const int64_t npos = (int64_t)S.nslices << S.lc;
     if (S.N <= 0) return;
-    const dim3 g(cdiv(m, 256)), b(256);
+    const dim3 g(cdiv(npos, 64));
 #define SCALE_N(NN)                                                                                           \
-    hipLaunchKernelGGL(k_sell_scaled<NN>, g, b, 0, st, S.N, S.nslices, 1 << S.lc, S.soff.get(), S.sw.get(), S.ssrc.get(), \
-                       bcsr_vals, Dinv, out, flag)
+    hipLaunchKernelGGL(k_sell_scaled<NN>, g, dim3(64 * NN), 0, st, S.N, S.nslices, S.lc, S.soff.get(), S.sw.get(), \
+                       S.ssrc.get(), bcsr_vals, Dinv, out, flag)
     switch (n) {
         case 1: SCALE_N(1); break;
         case 2: SCALE_N(2); break;
