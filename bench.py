@@ -39,13 +39,13 @@ def seeded_normal(torch, count, dtype, dev, seed):
 # None where not measured for the current kernel code.  These counters count
 # requests from the L2 to the memory fabric, which the 256 MB Infinity Cache
 # (MALL) in front of HBM serves in part, so they bound HBM traffic from above.
-TRAFFIC_PU1M = {"sweep": 542211430, "spmv_internal": 1129018598, "spmv_caller": 1713295565}
+TRAFFIC_PU1M = {"sweep": 542258176, "spmv_internal": 1128992973, "spmv_caller": 1713110630}
 TRAFFIC_KIND = ("L2-to-memory-fabric bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated); the Infinity "
                 "Cache serves part of them, so HBM itself moves at most this much")
 # Average duration of the same kernels inside timed bench steps (rocprofv3
 # --kernel-trace of the default run, profiles/bench_pu1M_kernel_stats.md);
 # None where not measured for the current kernel code.
-IN_STEP_US_PU1M = {"sweep": 83.84, "spmv_internal": 179.87, "spmv_caller": None}
+IN_STEP_US_PU1M = {"sweep": 83.79, "spmv_internal": 178.38, "spmv_caller": None}
 
 
 def parse():
@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other workloads (8M stretched density-based, 64-system batch, 2M adjoint)")
+    ap.add_argument("--only", choices=["adjoint_pu_2M", "batch_64", "stretched_density_8M"],
+                    help="measure only this one of the other workloads (for per-workload profiles)")
     ap.add_argument("--precond", choices=["amg", "sgs"], default="amg",
                     help="sgs: multicolour symmetric block Gauss-Seidel as the whole preconditioner")
     ap.add_argument("--max-iter", type=int, default=500)
@@ -417,13 +419,24 @@ def measure_system(P, torch, dev, s, opt, steps, key, name, transposed=False):
     return res
 
 
-def other_configs(args, P, torch, dev):
+def other_configs(args, P, torch, dev, only=None):
     """The other synthetic workloads, each in its own launch configuration:
     the 8M-cell density-based system on a boundary-layer mesh (mixed
     AMG-FGMRES(30)), the 64-system batch (one batched mixed AMG-BiCGStab
     solve) and the 2M-cell p-U adjoint (mixed forward and transposed solves,
     LDU gradient)."""
     from workloads import jacobian_batch, jacobian_stretched, pressure_velocity
+    out = {}
+    if only is None or only == "adjoint_pu_2M":
+        out.update(_adjoint_2M(P, torch, dev, pressure_velocity))
+    if only is None or only == "batch_64":
+        out.update(_batch_64(P, torch, dev, jacobian_batch))
+    if only is None or only == "stretched_density_8M":
+        out.update(_stretched_8M(P, torch, dev, jacobian_stretched))
+    return out
+
+
+def _adjoint_2M(P, torch, dev, pressure_velocity):
     out = {}
     t0 = time.time()
     s = pressure_velocity(200, 100, 100, seed=0)
@@ -432,7 +445,11 @@ def other_configs(args, P, torch, dev):
         P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, tol=1e-8), 3, "adjoint_pu_2M",
         "pressure-based p-U 4x4, 200x100x100 jittered renumbered hex mesh (N=%d); mixed AMG-BiCGStab to 1e-8, "
         "forward and transposed" % s["N"], transposed=True)
-    del s
+    return out
+
+
+def _batch_64(P, torch, dev, jacobian_batch):
+    out = {}
     t0 = time.time()
     s = jacobian_batch(64, seed=0)
     log("generated the 64-system batch (%d cells) in %.1f s" % (s["N"], time.time() - t0))
@@ -440,7 +457,11 @@ def other_configs(args, P, torch, dev):
         P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, tol=1e-8), 3, "batch_64",
         "64 density-based 5x5 systems, 10k-500k cells each (N=%d in total); one batched mixed AMG-BiCGStab "
         "solve to 1e-8 per system" % s["N"])
-    del s
+    return out
+
+
+def _stretched_8M(P, torch, dev, jacobian_stretched):
+    out = {}
     t0 = time.time()
     s = jacobian_stretched(200, 200, 200, seed=0)
     log("generated 8M stretched in %.1f s" % (time.time() - t0))
@@ -449,7 +470,6 @@ def other_configs(args, P, torch, dev):
                                             tol=1e-8), 2, "stretched_density_8M",
         "density-based 5x5, 200^3 boundary-layer mesh (wall-normal ratio 1.2, aspect ratio up to 1e3, "
         "N=%d); mixed AMG-FGMRES(30) to 1e-8" % s["N"])
-    del s
     return out
 
 
@@ -469,6 +489,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.assembly:
         assembly_only(args, P, torch, dev)
+        return
+    if args.only:
+        print(json.dumps(other_configs(args, P, torch, dev, only=args.only)), flush=True)
         return
     nx, ny, nz = args.mesh
     log("generating pressure-velocity system %dx%dx%d" % (nx, ny, nz))
