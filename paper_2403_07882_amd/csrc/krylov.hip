@@ -261,37 +261,52 @@ __global__ void k_gm_add(const Item *__restrict__ items, const double *__restric
 
 // ------------------------------------------------------------------ FGMRES
 // multi-dot: partial[i * n_items + item] = (w, V_i), i = 0..j
+// partials of (V_i, w), i = 0..j; with ww also (w, w) in slot j + 1
 __global__ __launch_bounds__(kVecThreads) void k_mdot(const Item *__restrict__ items, int32_t n_items,
                                                       const int32_t *__restrict__ done, int j, int64_t ld,
                                                       const double *__restrict__ V, const double *__restrict__ w,
-                                                      double *partial) {
+                                                      double *partial, int ww) {
     __shared__ double red[kVecThreads / 64];
     const Item it = items[blockIdx.x];
     const bool act = !done[it.sys];
-    for (int i = 0; i <= j; ++i) {
+    for (int i = 0; i <= j + (ww ? 1 : 0); ++i) {
+        const double *vi = i <= j ? V + i * ld : w;
         double acc = 0.0;
         if (act)
-            for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) acc += w[e] * V[i * ld + e];
+            for (int64_t e = it.beg + threadIdx.x; e < it.end; e += kVecThreads) acc += w[e] * vi[e];
         acc = block_sum(acc, red);
         if (threadIdx.x == 0) partial[(int64_t)i * n_items + blockIdx.x] = acc;
     }
 }
 
-// h_i (per system) = sum of partials; accumulate into H(:, j); store in coef
+// h_i (per system) = sum of partials; accumulate into H(:, j); store in coef.
+// With skip (first pass, which also summed (w, w) in slot j + 1): a system
+// whose w keeps more than a tenth of its norm, ||w - sum h_i V_i||^2 =
+// ||w||^2 - sum h_i^2 > 0.01 ||w||^2, skips the second (re-orthogonalising)
+// pass: skip[s] = 1 (also for a finished system).
 __global__ __launch_bounds__(kFinThreads) void k_mdot_fin(int j, int m,
                                                            const int32_t *__restrict__ item_off, int32_t n_items,
                                                            const double *__restrict__ partial,
                                                            const int32_t *__restrict__ done, double *H, double *coef,
-                                                           int accumulate) {
+                                                           int accumulate, int32_t *skip) {
     const int s = blockIdx.x;
-    if (done[s]) return;
+    if (done[s]) {
+        if (skip && threadIdx.x == 0) skip[s] = 1;
+        return;
+    }
+    double hh = 0.0;
     for (int i = 0; i <= j; ++i) {
         const double hv = sum_items(partial, n_items, i, item_off[s], item_off[s + 1]);
+        hh += hv * hv;
         if (threadIdx.x == 0) {
             double *Hs = H + (int64_t)s * (m + 1) * m;
             Hs[i * m + j] = accumulate ? Hs[i * m + j] + hv : hv;
             coef[(int64_t)s * (m + 1) + i] = hv;
         }
+    }
+    if (skip) {
+        const double ww = sum_items(partial, n_items, j + 1, item_off[s], item_off[s + 1]);
+        if (threadIdx.x == 0) skip[s] = (ww - hh > 0.01 * ww) ? 1 : 0;
     }
 }
 
@@ -933,11 +948,16 @@ int fgmres(cbs_system *h, const double *b, double *x, bool tr, std::vector<int> 
             double *vj = V + j * ld, *zj = flexible ? Z + j * ld : h->ph.get();
             precond_apply(h, vj, zj, tr);
             spmv64(h, zj, w, tr);
-            for (int pass = 0; pass < 2; ++pass) {        // classical Gram-Schmidt, twice
-                hipLaunchKernelGGL(k_mdot, G, B, 0, st, items, h->n_items, h->done.get(), j, ld, V, w, h->partial.get());
+            // classical Gram-Schmidt; a second pass re-orthogonalises the
+            // systems whose w lost more than 90% of its norm in the first
+            int32_t *skip = h->flags.get() + 4 * nsys;
+            for (int pass = 0; pass < 2; ++pass) {
+                const int32_t *mask = pass == 0 ? h->done.get() : skip;
+                hipLaunchKernelGGL(k_mdot, G, B, 0, st, items, h->n_items, mask, j, ld, V, w, h->partial.get(),
+                                   pass == 0 ? 1 : 0);
                 hipLaunchKernelGGL(k_mdot_fin, GS, BS, 0, st, j, m, h->item_off.get(), h->n_items,
-                                   h->partial.get(), h->done.get(), h->H.get(), coef, pass);
-                hipLaunchKernelGGL(k_maxpy, G, B, 0, st, items, h->done.get(), j, m, ld, V, coef, w);
+                                   h->partial.get(), mask, h->H.get(), coef, pass, pass == 0 ? skip : nullptr);
+                hipLaunchKernelGGL(k_maxpy, G, B, 0, st, items, mask, j, m, ld, V, coef, w);
             }
             dots(h, 1, w, w);
             hipLaunchKernelGGL(k_gm_givens, GS, BS, 0, st, nsys, j, m, h->item_off.get(), h->n_items,
