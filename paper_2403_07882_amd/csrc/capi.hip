@@ -89,6 +89,7 @@ int create_common(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const
     h->N = (int32_t)N; h->F = (int32_t)F; h->n = bdim; h->n_sys = n_sys;
     h->stream = (hipStream_t)stream;
     HIPCHK(hipGetDevice(&h->device));
+    HIPCHK(hipDeviceGetAttribute(&h->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
     h->cell_off.assign(cell_off, cell_off + n_sys + 1);
     h->face_off.assign(face_off, face_off + n_sys + 1);
     HIPCHK(hipEventCreate(&h->ev0));

@@ -21,9 +21,10 @@
 namespace {
 
 constexpr int kTailThreads = 1024;
-// LDS for the staged vectors and index arrays; with the two reduction arrays
-// (8 KB in FP32, 16 KB in FP64) a workgroup stays within 64 KB
-constexpr int64_t kTailLdsFloat = 56 * 1024, kTailLdsDouble = 48 * 1024;
+// LDS for the staged vectors and index arrays: what a workgroup may hold
+// (160 KB on gfx950) less the two static reduction arrays (8 KB in FP32,
+// 16 KB in FP64) and 1 KB of margin
+constexpr int64_t kTailLdsReserve = 1024;
 
 template <typename T> struct TAcc { using type = double; };
 template <> struct TAcc<float> { using type = float; };
@@ -411,7 +412,12 @@ int64_t tail_plan(const cbs_system *h, int l0, bool tr, TailArgs<T> *a) {
     return ints_off + nints * 4;
 }
 
-int64_t tail_budget(size_t tsize) { return tsize == sizeof(float) ? kTailLdsFloat : kTailLdsDouble; }
+// dynamic LDS left for the tail: the device's per-workgroup limit (160 KB on
+// gfx950) less the kernel's static reduction arrays and a reserve
+int64_t tail_budget(const cbs_system *h, size_t tsize) {
+    return (int64_t)h->lds_max - 2 * kTailThreads * (int64_t)(tsize == sizeof(float) ? sizeof(float) : sizeof(double)) -
+           kTailLdsReserve;
+}
 
 }  // namespace
 
@@ -428,7 +434,7 @@ int tail_level_for(const cbs_system *h, size_t tsize) {
         // the forward layout is the larger one (scaled levels add a pattern and c)
         const int64_t need = tsize == sizeof(float) ? tail_plan<float>(h, l, false, nullptr)
                                                     : tail_plan<double>(h, l, false, nullptr);
-        if (need <= tail_budget(tsize)) return l;
+        if (need <= tail_budget(h, tsize)) return l;
     }
     return -1;
 }
@@ -442,7 +448,7 @@ void launch_tail(cbs_system *h, bool tr, int l0, const T *rfine) {
     if (l0 < 1 || nl < 0 || nl + 1 > kTailMax) cbs_throw(CBS_ERR_ARG, "V-cycle tail: bad level range");
     TailArgs<T> a{};
     const int64_t lds = tail_plan<T>(h, l0, tr, &a);
-    if (lds > tail_budget(sizeof(T))) cbs_throw(CBS_ERR_ARG, "V-cycle tail: LDS budget exceeded");
+    if (lds > tail_budget(h, sizeof(T))) cbs_throw(CBS_ERR_ARG, "V-cycle tail: LDS budget exceeded");
     for (int k = 0; k <= nl; ++k) {
         Level &L = h->lev[l0 + k];
         TailLvl<T> &d = a.lv[k];
@@ -474,14 +480,23 @@ void launch_tail(cbs_system *h, bool tr, int l0, const T *rfine) {
     a.nsys = h->n_sys;
     const dim3 g(1), b(kTailThreads);
     const size_t shm = (size_t)lds;
+    // more than 64 KB of dynamic LDS is requested explicitly
+#define TAIL_N(NN)                                                                                       \
+    {                                                                                                    \
+        if (shm > 64 * 1024)                                                                             \
+            HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tail<NN, T>),                   \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));           \
+        hipLaunchKernelGGL((k_tail<NN, T>), g, b, shm, h->stream, a);                                    \
+    }
     switch (n) {
-        case 1: hipLaunchKernelGGL((k_tail<1, T>), g, b, shm, h->stream, a); break;
-        case 2: hipLaunchKernelGGL((k_tail<2, T>), g, b, shm, h->stream, a); break;
-        case 3: hipLaunchKernelGGL((k_tail<3, T>), g, b, shm, h->stream, a); break;
-        case 4: hipLaunchKernelGGL((k_tail<4, T>), g, b, shm, h->stream, a); break;
-        case 5: hipLaunchKernelGGL((k_tail<5, T>), g, b, shm, h->stream, a); break;
+        case 1: TAIL_N(1); break;
+        case 2: TAIL_N(2); break;
+        case 3: TAIL_N(3); break;
+        case 4: TAIL_N(4); break;
+        case 5: TAIL_N(5); break;
         default: cbs_throw(CBS_ERR_ARG, "bdim must be 1..5");
     }
+#undef TAIL_N
     LAUNCHCHK();
 }
 template void launch_tail<float>(cbs_system *, bool, int, const float *);

@@ -82,6 +82,17 @@ def test_tail_vcycle_uneven_sweeps(tail, pre, post):
     _agree(z, zr, 1e-5)
 
 
+@pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
+def test_tail_vcycle_beyond_64kb_of_lds(precision):
+    """A tail whose first level holds a few hundred block rows: its staged
+    vectors and patterns need more than 64 KB of LDS (a gfx950 workgroup may
+    hold 160 KB)."""
+    _say("tail vcycle large LDS", precision)
+    s = pressure_velocity(24, 20, 18, seed=44)
+    z, zr = _vcycle_pair(s, ALL, precision, 2, 2)
+    _agree(z, zr, 1e-11 if precision == P.PRECISION_FP64 else 1e-5)
+
+
 def test_tail_vcycle_batch_of_uneven_systems():
     """A batch: the coarsest level holds one dense inverse per system."""
     _say("tail vcycle batch")
