@@ -376,11 +376,13 @@ int tail_level_for(const cbs_system *h, size_t tsize);
 template <typename T>
 void launch_tail(cbs_system *h, bool tr, int l0, const T *rfine);
 // block Gauss-Seidel on the cnt rows of one colour, held at positions
-// p0 .. p0 + cnt of the colour-ordered copy S, in place:
-// x_i = D_i^{-1} (b_i - sum_{j != i} A_ij x_j)
+// p0 .. p0 + cnt of the colour-ordered copy S, in place, with the pivot
+// inverses Dinv (D or E): form 0 x_i = P_i^{-1} (b_i - sum_{j != i} A_ij x_j),
+// form 1 x_i += P_i^{-1} (b_i - sum_j A_ij x_j), form 2 x_i = P_i^{-1} b_i
+// (no matrix read); rz (optional) gets zeros at the rows written
 template <typename T>
 void launch_gs_colour(int n, const SellView &S, const T *val, int32_t p0, int32_t cnt, const double *Dinv,
-                      const T *b, T *x, hipStream_t st);
+                      const T *b, T *x, hipStream_t st, int form = 0, T *rz = nullptr);
 // DILU colour sweeps on the cnt rows at positions p0 .. p0 + cnt: forward
 // y = E^{-1}(b - A x - L y) (zero_guess: A x omitted; last: also x = x + y,
 // the last colour's whole update), backward z = y - E^{-1} U z, x = x + z

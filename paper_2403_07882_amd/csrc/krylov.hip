@@ -507,6 +507,48 @@ void sgs_smooth(cbs_system *h, Level &L, bool tr, const T *b, T *x) {
     for (int c = ncol - 2; c >= 0; --c) colour(c);
 }
 
+// Levels whose colouring has two classes (hex meshes are bipartite).  Colour
+// 0 has no earlier neighbours, so its DILU / ILU(0) pivot is its diagonal
+// block, and with two colours the ILU(0) factor keeps A's off-diagonal
+// blocks.  One DILU or ILU(0) step from x, y_0 = E_0^{-1} r_0, y_1 = E_1^{-1}
+// (r_1 - A_10 y_0), z_0 = y_0 - E_0^{-1} A_01 y_1, is then the same as
+//   x_0 = E_0^{-1} (b_0 - A_01 x_1);  x_1 += E_1^{-1} (b_1 - A_1. x);
+//   x_0 = E_0^{-1} (b_0 - A_01 x_1)
+// and a symmetric Gauss-Seidel step is the same with D for E and the
+// replacement x_1 = D_1^{-1} (b_1 - A_10 x_0).  Both give the same update up
+// to rounding order.  A step's first colour-0 update repeats the last one of
+// the step before (x_1 has not changed since), so `steps` steps take one
+// colour-0 launch more than colour-1 launches.  After them the residual of
+// colour 0 is zero; rz, when given, gets those zeros.
+template <typename T>
+void smooth_two_colour(cbs_system *h, Level &L, bool tr, const T *b, T *x, int steps, bool zero_guess, T *rz) {
+    if (steps <= 0) return;
+    const T *val = level_vals<T>(L, tr);
+    const double *P = L.dilu ? (tr ? L.EinvT.get() : L.Einv.get()) : (tr ? L.DinvT.get() : L.Dinv.get());
+    const SellView S = L.sell.view(sizeof(T) == 4);
+    const int32_t n0 = L.colour_off[1] - L.colour_off[0], n1 = L.colour_off[2] - L.colour_off[1];
+    auto c0 = [&](int form, T *z) { launch_gs_colour<T>(h->n, S, val, L.sell.cpos[0], n0, P, b, x, h->stream, form, z); };
+    auto c1 = [&](int form) { launch_gs_colour<T>(h->n, S, val, L.sell.cpos[1], n1, P, b, x, h->stream, form); };
+    c0(zero_guess ? 2 : 0, nullptr);                 // from zero: every x_1 is still zero
+    for (int s = 0; s < steps; ++s) {
+        // DILU's colour-1 update is a correction of x_1, except from zero
+        c1(L.dilu && !(zero_guess && s == 0) ? 1 : 0);
+        c0(0, s == steps - 1 ? rz : nullptr);
+    }
+}
+
+// the positions [p0, p1) of a colour-ordered copy as a copy of their own
+// (p0 a whole number of slices)
+SellView position_range(SellView S, int32_t p0, int32_t p1) {
+    if (p0 & ((1 << S.lc) - 1)) cbs_throw(CBS_ERR_ARG, "colour range not slice-aligned");
+    const int32_t s0 = p0 >> S.lc;
+    S.N = p1 - p0;
+    S.soff += s0;
+    S.sw += s0;
+    S.prow += p0;
+    return S;
+}
+
 // x = V(b) with zero initial guess on level l; the result lands in x.  When
 // rfine is given, b is not yet formed: it is the restriction of the finer
 // level's residual rfine, which the first kernel of this level computes and
@@ -553,17 +595,29 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
     T *bc = vptr<T>(C.vb), *xc = vptr<T>(C.vx);
     if (L.dilu || L.sgs) {
         if (rfine) restrict_into_b();
-        if (L.sgs || nu1 == 0) launch_fill<T>(m, x, st);    // Gauss-Seidel starts from x = 0
-        for (int s = 0; s < nu1; ++s) {
-            if (L.dilu) dilu_smooth<T>(h, L, tr, b, x, s == 0);
-            else sgs_smooth<T>(h, L, tr, b, x);
+        const bool two = L.colour_off.size() == 3 && L.sell.cpos.size() == 3;
+        if (two && nu1 >= 1) {
+            // colour 0's residual is zero after the steps: only colour 1's is formed
+            smooth_two_colour<T>(h, L, tr, b, x, nu1, true, r);
+            launch_rows<T, T>(1, n, position_range(L.sell.view(fp32), L.sell.cpos[1], L.sell.cpos[2]), val, x, b, r,
+                              nullptr, 0.0, st);
+        } else {
+            if (L.sgs || nu1 == 0) launch_fill<T>(m, x, st);    // Gauss-Seidel starts from x = 0
+            for (int s = 0; s < nu1; ++s) {
+                if (L.dilu) dilu_smooth<T>(h, L, tr, b, x, s == 0);
+                else sgs_smooth<T>(h, L, tr, b, x);
+            }
+            launch_rows<T, T>(1, n, L.sell.view(fp32), val, x, b, r, nullptr, 0.0, st);
         }
-        launch_rows<T, T>(1, n, L.sell.view(fp32), val, x, b, r, nullptr, 0.0, st);
         vcycle<T>(h, tr, l + 1, bc, xc, r);
         launch_prolong<T>(n, L.N, L.agg.get(), xc, x, st);
-        for (int s = 0; s < nu2; ++s) {
-            if (L.dilu) dilu_smooth<T>(h, L, tr, b, x, false);
-            else sgs_smooth<T>(h, L, tr, b, x);
+        if (two) {
+            smooth_two_colour<T>(h, L, tr, b, x, nu2, false, nullptr);
+        } else {
+            for (int s = 0; s < nu2; ++s) {
+                if (L.dilu) dilu_smooth<T>(h, L, tr, b, x, false);
+                else sgs_smooth<T>(h, L, tr, b, x);
+            }
         }
         finish();
         return;
@@ -646,10 +700,17 @@ void precond_apply(cbs_system *h, const double *r, double *z, bool tr) {
         case CBS_PREC_BJACOBI:
             launch_block_apply(n, h->N, tr ? h->lev[0].DinvT.get() : h->lev[0].Dinv.get(), r, z, st);
             return;
-        case CBS_PREC_SGS:
+        case CBS_PREC_SGS: {
+            Level &L0 = h->lev[0];
+            const int steps = std::max(1, h->opt.pre_sweeps);
+            if (L0.colour_off.size() == 3 && L0.sell.cpos.size() == 3) {
+                smooth_two_colour<double>(h, L0, tr, r, z, steps, true, nullptr);
+                return;
+            }
             launch_fill<double>(m, z, st);
-            for (int s = 0; s < std::max(1, h->opt.pre_sweeps); ++s) sgs_smooth<double>(h, h->lev[0], tr, r, z);
+            for (int s = 0; s < steps; ++s) sgs_smooth<double>(h, L0, tr, r, z);
             return;
+        }
         default:
             break;
     }

@@ -333,13 +333,17 @@ constexpr int kDiluU = 4;    // blocks in flight per thread in the coloured swee
 // so x + z = x + M^{-1}(b - A x) with M = (E + L) E^{-1} (E + U).  One
 // thread per (row, r) as in k_rows; E^{-1} (FP64) is applied through LDS.
 // One colour of a block Gauss-Seidel half-sweep, in place: for the rows of
-// colour c (rows[0..cnt)), x_i = D_i^{-1} (b_i - sum_{j != i} A_ij x_j).  Rows
-// of one colour are not neighbours, so each reads only x of other colours and
-// writes only its own.
-template <int n, typename T>
+// colour c (rows[0..cnt)), x_i = P_i^{-1} (b_i - sum_{j != i} A_ij x_j), with
+// the pivot P = D (Gauss-Seidel) or E (DILU).  Rows of one colour are not
+// neighbours, so each reads only x of other colours and writes only its own.
+// FORM 1 is the correction x_i += P_i^{-1} (b_i - sum_j A_ij x_j), the
+// diagonal included; FORM 2 is x_i = P_i^{-1} b_i, for when every neighbour
+// is still zero (no matrix read).  rz, when given, gets zeros at the rows
+// written: their residual, known to vanish.
+template <int n, typename T, int FORM>
 __global__ __launch_bounds__(64 * n) void k_gs_colour(SellView S, const T *__restrict__ val, int32_t p0,
                                                       int32_t cnt, const double *__restrict__ Dinv,
-                                                      const T *__restrict__ b, T *x) {
+                                                      const T *__restrict__ b, T *x, T *__restrict__ rz) {
     using A = typename Acc<T>::type;
     constexpr int nn = n * n;
     const int t = threadIdx.x;
@@ -349,11 +353,11 @@ __global__ __launch_bounds__(64 * n) void k_gs_colour(SellView S, const T *__res
     const int32_t p = p0 + q;                     // the colour's rows are one run of positions
     const int32_t i = act ? S.prow[p] : 0;
     A acc = 0;
-    if (act) {
+    if (act && FORM != 2) {
         const int32_t sl = p >> S.lc, ii = p - (sl << S.lc);
         const int32_t base = S.soff[sl] + ii, w = S.sw[sl];
         // kDiluU blocks in flight per step, summed in column order;
-        // padding (column -1) and the diagonal add nothing
+        // padding (column -1) adds nothing, nor the diagonal outside FORM 1
         for (int32_t k0 = 0; k0 < w; k0 += kDiluU) {
             int32_t j[kDiluU];
             T bv[kDiluU][n], xv[kDiluU][n];
@@ -362,13 +366,13 @@ __global__ __launch_bounds__(64 * n) void k_gs_colour(SellView S, const T *__res
                 j[u] = k0 + u < w ? S.scol[base + ((int64_t)(k0 + u) << S.lc)] : -1;
 #pragma unroll
             for (int u = 0; u < kDiluU; ++u) {
-                if (j[u] < 0 || j[u] == i) continue;
+                if (j[u] < 0 || (FORM == 0 && j[u] == i)) continue;
                 load_block_row<n, T>(val + (base + ((int64_t)(k0 + u) << S.lc)) * nn + r * n, bv[u]);
                 load_x<n, T>(x + (int64_t)j[u] * n, xv[u]);
             }
 #pragma unroll
             for (int u = 0; u < kDiluU; ++u) {
-                if (j[u] < 0 || j[u] == i) continue;
+                if (j[u] < 0 || (FORM == 0 && j[u] == i)) continue;
 #pragma unroll
                 for (int cc = 0; cc < n; ++cc) acc += (A)bv[u][cc] * (A)xv[u][cc];
             }
@@ -382,7 +386,10 @@ __global__ __launch_bounds__(64 * n) void k_gs_colour(SellView S, const T *__res
         double z = 0.0;
 #pragma unroll
         for (int cc = 0; cc < n; ++cc) z += Di[cc] * (double)sres[lr * n + cc];
-        x[(int64_t)i * n + r] = (T)z;
+        const int64_t o = (int64_t)i * n + r;
+        if (FORM == 1) x[o] = (T)((A)x[o] + (A)(T)z);
+        else x[o] = (T)z;
+        if (rz) rz[o] = (T)0;
     }
 }
 
@@ -1034,10 +1041,17 @@ void launch_block_apply(int n, int32_t N, const double *Dinv, const double *r, d
 
 template <typename T>
 void launch_gs_colour(int n, const SellView &S, const T *val, int32_t p0, int32_t cnt, const double *Dinv,
-                      const T *b, T *x, hipStream_t st) {
+                      const T *b, T *x, hipStream_t st, int form, T *rz) {
     if (cnt <= 0) return;
+    if (form < 0 || form > 2) cbs_throw(CBS_ERR_ARG, "Gauss-Seidel colour step: bad form");
     const dim3 g(cdiv(cnt, 64));
-#define GS_C(NN) hipLaunchKernelGGL((k_gs_colour<NN, T>), g, dim3(64 * NN), 0, st, S, val, p0, cnt, Dinv, b, x)
+#define GS_F(NN, FF) hipLaunchKernelGGL((k_gs_colour<NN, T, FF>), g, dim3(64 * NN), 0, st, S, val, p0, cnt, Dinv, b, x, rz)
+#define GS_C(NN)                      \
+    {                                 \
+        if (form == 0) GS_F(NN, 0);   \
+        else if (form == 1) GS_F(NN, 1); \
+        else GS_F(NN, 2);             \
+    }
     switch (n) {
         case 1: GS_C(1); break;
         case 2: GS_C(2); break;
@@ -1046,12 +1060,13 @@ void launch_gs_colour(int n, const SellView &S, const T *val, int32_t p0, int32_
         case 5: GS_C(5); break;
     }
 #undef GS_C
+#undef GS_F
     LAUNCHCHK();
 }
 template void launch_gs_colour<double>(int, const SellView &, const double *, int32_t, int32_t, const double *,
-                                       const double *, double *, hipStream_t);
+                                       const double *, double *, hipStream_t, int, double *);
 template void launch_gs_colour<float>(int, const SellView &, const float *, int32_t, int32_t, const double *,
-                                      const float *, float *, hipStream_t);
+                                      const float *, float *, hipStream_t, int, float *);
 
 template <typename T>
 void launch_dilu_fwd(int n, const SellView &S, const T *val, const T *fval, const int32_t *colour, int c, int32_t p0,
