@@ -182,6 +182,29 @@ __global__ void k_strength(int32_t N, const int32_t *rp, const int32_t *col, con
     }
 }
 
+// The same weights with L lanes per row (coarse levels, whose rows are too
+// long for the unrolled form): each lane takes every L-th block of the row.
+template <int L>
+__global__ void k_strength_lanes(int32_t N, const int32_t *rp, const int32_t *col, const int32_t *mirror,
+                                 const double *nrm, const double *df, double *w) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(t / L), lane = (int32_t)(t - (int64_t)i * L);
+    if (i >= N) return;
+    const double di = df[i];
+    for (int32_t k = rp[i] + lane; k < rp[i + 1]; k += L) {
+        const int32_t j = col[k];
+        if (j == i) { w[k] = 0.0; continue; }
+        const double den = fmax(di, df[j]);
+        w[k] = den > 0.0 ? 0.5 * (nrm[k] + nrm[mirror[k]]) / den : 0.0;
+    }
+}
+
+// lanes per row for a graph of N rows and nnz entries: about one entry each
+inline int lanes_for(int64_t N, int64_t nnz) {
+    const int64_t avg = N > 0 ? (nnz + N - 1) / N : 1;
+    return avg <= 4 ? 4 : avg <= 8 ? 8 : 16;
+}
+
 __global__ void k_diag_norm(int32_t N, const int32_t *dslot, const double *nrm, double *df) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < N) df[i] = nrm[dslot[i]];
@@ -202,21 +225,38 @@ __global__ void k_match_init(int32_t N, const int32_t *row_sys, const int32_t *s
     partner[i] = sys_frozen[row_sys[i]] ? -2 : -1;
 }
 
+// The strongest admissible neighbour of a row: the largest weight, and of
+// equal weights the smallest column.  That order is total, so the L lanes of
+// a row each take every L-th entry and their picks reduce to the same
+// neighbour whatever the order.
+template <int L>
+__device__ inline void best_reduce(double &bw, int32_t &best) {
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) {
+        const double ow = __shfl_xor(bw, o, L);
+        const int32_t ob = __shfl_xor(best, o, L);
+        if (ob >= 0 && (ow > bw || (ow == bw && ob < best))) { bw = ow; best = ob; }
+    }
+}
+
+template <int L>
 __global__ void k_match_pick(int32_t N, const int32_t *rp, const int32_t *col, const double *w,
                              const int32_t *partner, int32_t *cand) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(t / L), lane = (int32_t)(t - (int64_t)i * L);
+    const bool act = i < N;                       // every lane joins the reduction
     int32_t best = -1;
     double bw = 0.0;
-    if (partner[i] == -1) {
-        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+    if (act && partner[i] == -1) {
+        for (int32_t k = rp[i] + lane; k < rp[i + 1]; k += L) {
             const int32_t j = col[k];
             const double wk = w[k];
             if (j == i || partner[j] != -1 || !(wk > 0.0)) continue;
             if (wk > bw || (wk == bw && j < best)) { bw = wk; best = j; }
         }
     }
-    cand[i] = best;
+    best_reduce<L>(bw, best);
+    if (act && lane == 0) cand[i] = best;
 }
 
 __global__ void k_match_confirm(int32_t N, const int32_t *cand, int32_t *partner) {
@@ -226,34 +266,42 @@ __global__ void k_match_confirm(int32_t N, const int32_t *cand, int32_t *partner
     if (j >= 0 && cand[j] == i) partner[i] = j;
 }
 
+template <int L>
 __global__ void k_match_rep(int32_t N, const int32_t *rp, const int32_t *col, const double *w,
                             const int32_t *partner, int32_t *rep, int32_t *root) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int32_t p = partner[i];
-    int32_t r = i;
-    if (p >= 0) {
-        r = min(i, p);
-    } else if (p == -1) {
-        int32_t best = -1;
-        double bw = 0.0;
-        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(t / L), lane = (int32_t)(t - (int64_t)i * L);
+    const bool act = i < N;
+    const int32_t p = act ? partner[i] : -2;
+    int32_t best = -1;
+    double bw = 0.0;
+    if (p == -1) {                                 // unmatched: join the strongest matched neighbour's pair
+        for (int32_t k = rp[i] + lane; k < rp[i + 1]; k += L) {
             const int32_t j = col[k];
             const double wk = w[k];
             if (j == i || partner[j] < 0 || !(wk > 0.0)) continue;
             if (wk > bw || (wk == bw && j < best)) { bw = wk; best = j; }
         }
-        if (best >= 0) r = min(best, partner[best]);
     }
+    best_reduce<L>(bw, best);
+    if (!act || lane != 0) return;
+    int32_t r = i;
+    if (p >= 0) r = min(i, p);
+    else if (p == -1 && best >= 0) r = min(best, partner[best]);
     rep[i] = r;
     root[i] = (r == i) ? 1 : 0;
 }
 
-__global__ void k_match_assign(int32_t N, const int32_t *rep, const int32_t *newid, int32_t *agg) {
+// newid: the exclusive scan of the root flags (N + 1 entries); its total,
+// the aggregate count, goes to *nc
+__global__ void k_match_assign(int32_t N, const int32_t *rep, const int32_t *newid, int32_t *agg, int32_t *nc) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     agg[i] = newid[rep[i]];
+    if (i == 0) *nc = newid[N];
 }
+
+__global__ void k_copy_int(const int32_t *src, int32_t *dst) { *dst = *src; }
 
 __global__ void k_compose(int32_t N, const int32_t *a2, int32_t *agg) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -537,11 +585,14 @@ __device__ inline int32_t bsearch_col(const int32_t *col, int32_t lo, int32_t hi
     return -1;
 }
 
+// L lanes per row, each taking every L-th entry
+template <int L>
 __global__ void k_mirror_search(int32_t N, const int32_t *rp, const int32_t *col, int32_t *mirror,
                                 int32_t *dslot, int32_t *flag) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(t / L), lane = (int32_t)(t - (int64_t)i * L);
     if (i >= N) return;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+    for (int32_t k = rp[i] + lane; k < rp[i + 1]; k += L) {
         const int32_t j = col[k];
         const int32_t m = bsearch_col(col, rp[j], rp[j + 1], i);
         if (m < 0) atomicOr(flag, 16);
@@ -1066,7 +1117,12 @@ void strength_n(int32_t N, const int32_t *rp, const int32_t *col, const int32_t 
     DArr<double> nrm(nnzb > 0 ? nnzb : 1);
     if (nnzb > 0) hipLaunchKernelGGL(k_block_frob<n>, dim3(cdiv(nnzb, 256)), dim3(256), 0, st, nnzb, val, nrm.get());
     hipLaunchKernelGGL(k_diag_norm, dim3(cdiv(N, 256)), dim3(256), 0, st, N, dslot, nrm.get(), df);
-    hipLaunchKernelGGL(k_strength, dim3(cdiv(N, 256)), dim3(256), 0, st, N, rp, col, mirror, nrm.get(), df, w);
+    if (lanes_for(N, nnzb) <= 8) {
+        hipLaunchKernelGGL(k_strength, dim3(cdiv(N, 256)), dim3(256), 0, st, N, rp, col, mirror, nrm.get(), df, w);
+    } else {
+        hipLaunchKernelGGL(k_strength_lanes<16>, dim3(cdiv((int64_t)N * 16, 256)), dim3(256), 0, st, N, rp, col,
+                           mirror, nrm.get(), df, w);
+    }
 }
 template <int n>
 void rap_n(int pass, int32_t nc, int32_t cap, const int32_t *aptr, const int32_t *amem, const int32_t *rp,
@@ -1116,55 +1172,83 @@ struct Graph {
     int32_t N;
     const int32_t *rp, *col;
     const double *w;
+    int lanes;                  // lanes per row of the matching kernels (4, 8 or 16)
 };
 
-// one pass of handshake matching -> agg (size N), returns the aggregate count
-int32_t match_pass(cbs_system *h, const Graph &g, const int32_t *row_sys, const int32_t *sys_frozen, int32_t *agg) {
+// launch a kernel templated on the lanes per row over N rows
+#define LANES_LAUNCH(KER, LN, N, ...)                                                                        \
+    do {                                                                                                     \
+        const int ln_ = (LN);                                                                                \
+        const dim3 gl_(cdiv((int64_t)(N) * ln_, 256)), bl_(256);                                            \
+        if (ln_ == 4) hipLaunchKernelGGL(KER<4>, gl_, bl_, 0, st, __VA_ARGS__);                             \
+        else if (ln_ == 8) hipLaunchKernelGGL(KER<8>, gl_, bl_, 0, st, __VA_ARGS__);                        \
+        else hipLaunchKernelGGL(KER<16>, gl_, bl_, 0, st, __VA_ARGS__);                                     \
+    } while (0)
+
+// one pass of handshake matching -> agg (size N); the aggregate count is left
+// on the device in *nc (N > 0; not read back here)
+void match_pass(cbs_system *h, const Graph &g, const int32_t *row_sys, const int32_t *sys_frozen, int32_t *agg,
+                int32_t *nc) {
     hipStream_t st = h->stream;
     const int32_t N = g.N;
     DArr<int32_t> partner(N), cand(N), rep(N), root(N + 1);
     const dim3 G(cdiv(N, 256)), B(256);
     hipLaunchKernelGGL(k_match_init, G, B, 0, st, N, row_sys, sys_frozen, partner.get());
     for (int r = 0; r < kMatchRounds; ++r) {
-        hipLaunchKernelGGL(k_match_pick, G, B, 0, st, N, g.rp, g.col, g.w, partner.get(), cand.get());
+        LANES_LAUNCH(k_match_pick, g.lanes, N, N, g.rp, g.col, g.w, partner.get(), cand.get());
         hipLaunchKernelGGL(k_match_confirm, G, B, 0, st, N, cand.get(), partner.get());
     }
-    hipLaunchKernelGGL(k_match_rep, G, B, 0, st, N, g.rp, g.col, g.w, partner.get(), rep.get(), root.get());
+    LANES_LAUNCH(k_match_rep, g.lanes, N, N, g.rp, g.col, g.w, partner.get(), rep.get(), root.get());
     LAUNCHCHK();
     scan_exclusive(root.get(), root.get(), N, st);
-    hipLaunchKernelGGL(k_match_assign, G, B, 0, st, N, rep.get(), root.get(), agg);
+    hipLaunchKernelGGL(k_match_assign, G, B, 0, st, N, rep.get(), root.get(), agg, nc);
     LAUNCHCHK();
-    return read_int(root.get() + N, st);
 }
 
-// member lists of each aggregate (ascending)
-void build_members(cbs_system *h, int32_t N, const int32_t *agg, int32_t nc, DArr<int32_t> &aptr,
-                   DArr<int32_t> &amem) {
+// Member lists of each aggregate (ascending) of a map of N rows onto at most
+// N aggregates, sized for N so that they are built before the aggregate
+// count comes back: past the last aggregate every aptr entry holds N.  The
+// largest candidate list of the Galerkin product over the graph rp (the
+// summed row lengths of an aggregate's members) goes to *maxc, which must
+// hold 0.
+void build_members(cbs_system *h, int32_t N, const int32_t *agg, DArr<int32_t> &aptr, DArr<int32_t> &amem,
+                   const int32_t *rp, int32_t *maxc) {
     hipStream_t st = h->stream;
-    aptr.alloc(nc + 1);
+    aptr.alloc(N + 1);
     amem.alloc(N > 0 ? N : 1);
-    DArr<int32_t> fill(nc + 1);
-    hipLaunchKernelGGL(k_fill_int, dim3(cdiv(nc + 1, 256)), dim3(256), 0, st, aptr.get(), (int64_t)nc + 1, 0);
+    DArr<int32_t> fill(N + 1);
+    hipLaunchKernelGGL(k_fill_int, dim3(cdiv(N + 1, 256)), dim3(256), 0, st, aptr.get(), (int64_t)N + 1, 0);
     hipLaunchKernelGGL(k_count_members, dim3(cdiv(N, 256)), dim3(256), 0, st, N, agg, aptr.get());
     LAUNCHCHK();
-    scan_exclusive(aptr.get(), aptr.get(), nc, st);
-    HIPCHK(hipMemcpyAsync(fill.get(), aptr.get(), sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToDevice, st));
+    scan_exclusive(aptr.get(), aptr.get(), N, st);
+    HIPCHK(hipMemcpyAsync(fill.get(), aptr.get(), sizeof(int32_t) * (N + 1), hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_fill_members, dim3(cdiv(N, 256)), dim3(256), 0, st, N, agg, fill.get(), amem.get());
-    hipLaunchKernelGGL(k_sort_members, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, aptr.get(), amem.get());
+    hipLaunchKernelGGL(k_sort_members, dim3(cdiv(N, 256)), dim3(256), 0, st, N, aptr.get(), amem.get());
+    hipLaunchKernelGGL(k_rap_maxc, dim3(cdiv(N, 256)), dim3(256), 0, st, N, aptr.get(), amem.get(), rp, maxc);
     LAUNCHCHK();
 }
 
 // Galerkin pattern + values of the next level.  n_blk = block size of `val`.
 // Returns the coarse block count when it builds the pattern, else -1.
+// maxc: the largest candidate list when known (else < 0: found and read
+// back here).  nz_bound >= 0: a bound on the coarse block count; the pattern
+// is then sized for it and its count not read back (nz_bound is returned),
+// and a candidate overflow sets bit 8 of *late_flag, which the caller reads
+// later.
 int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, const int32_t *amem, const int32_t *rp,
                   const int32_t *col, const double *val, const int32_t *agg, DArr<int32_t> &rpc, DArr<int32_t> &colc,
-                  DArr<double> &valc, bool pattern) {
+                  DArr<double> &valc, bool pattern, int32_t maxc = -1, int64_t nz_bound = -1,
+                  int32_t *late_flag = nullptr) {
     hipStream_t st = h->stream;
-    // largest candidate list of the level -> LDS per wavefront
-    HIPCHK(hipMemsetAsync(h->dflag.get(), 0, 2 * sizeof(int32_t), st));
-    hipLaunchKernelGGL(k_rap_maxc, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, aptr, amem, rp, h->dflag.get() + 1);
-    LAUNCHCHK();
-    const int32_t maxc = read_int(h->dflag.get() + 1, st);
+    const bool late = nz_bound >= 0 && late_flag;
+    int32_t *flag = late ? late_flag : h->dflag.get();
+    if (!late) hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, h->dflag.get(), (int64_t)2, 0);
+    if (maxc < 0) {
+        // largest candidate list of the level -> LDS per wavefront
+        hipLaunchKernelGGL(k_rap_maxc, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, aptr, amem, rp, h->dflag.get() + 1);
+        LAUNCHCHK();
+        maxc = read_int(h->dflag.get() + 1, st);
+    }
     if (maxc > kRapCap)
         cbs_throw(CBS_ERR_ARG, "a coarse row gathers " + std::to_string(maxc) + " blocks (limit " +
                                    std::to_string(kRapCap) + "); lower match_passes");
@@ -1184,13 +1268,20 @@ int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, con
                                rpc.get(), nullptr, nullptr, nullptr);
         else
             NSWITCH(n_blk, rap_n, 0, nc, cap, aptr, amem, rp, col, val, agg, rpc.get(), nullptr, nullptr, nullptr,
-                    h->dflag.get(), st);
+                    flag, st);
         LAUNCHCHK();
         scan_exclusive(rpc.get(), rpc.get(), nc, st);
-        int32_t v[2];
-        read_ints({h->dflag.get(), rpc.get() + nc}, v, st);
-        if (v[0] & 8) cbs_throw(CBS_ERR_ARG, "coarse row candidate overflow");
-        nz = v[1];
+        if (late) {
+            nz = (int32_t)nz_bound;
+        } else {
+            // flag and count side by side: one copy back
+            hipLaunchKernelGGL(k_copy_int, dim3(1), dim3(1), 0, st, rpc.get() + nc, h->dflag.get() + 1);
+            LAUNCHCHK();
+            int32_t v[2];
+            read_array(h->dflag.get(), 2, v, st);
+            if (v[0] & 8) cbs_throw(CBS_ERR_ARG, "coarse row candidate overflow");
+            nz = v[1];
+        }
         colc.alloc(nz > 0 ? nz : 1);
         valc.alloc((size_t)(nz > 0 ? nz : 1) * n_blk * n_blk);
     }
@@ -1201,7 +1292,7 @@ int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, con
                            rpc.get(), colc.get(), valc.get());
     else
         NSWITCH(n_blk, rap_n, 1, nc, cap, aptr, amem, rp, col, val, agg, nullptr, rpc.get(), colc.get(), valc.get(),
-                h->dflag.get(), st);
+                flag, st);
     LAUNCHCHK();
     return nz;
 }
@@ -1210,54 +1301,81 @@ int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, con
 PhaseTimer *g_pt = nullptr;
 inline void gmark(const char *w) { if (g_pt) g_pt->mark(w); }
 
-void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen) {
+// Each pass leaves its aggregate count on the device; the members and the
+// largest Galerkin candidate list that the next step needs are built before
+// that count is read, so one read-back per pass brings both.  The
+// aggregate graphs of the later passes are sized by the level's block count
+// (a bound on theirs) rather than read back; a candidate overflow there sets
+// bit 8 of *deferred.  Leaves L.agg, L.nc, L.maxc and the members
+// L.agg_ptr / L.agg_mem.
+void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen, int32_t *deferred) {
     hipStream_t st = h->stream;
     const int32_t N = L.N;
     const int n = h->n;
+    const int passes = std::max(1, h->opt.match_passes);
     DArr<double> df(N), w(L.nnzb > 0 ? L.nnzb : 1);
+    // device words: [2p] the count of pass p, [2p + 1] the candidate maximum
+    // after it, [2 passes] a spare
+    const int nw_ = 2 * passes + 1;
+    DArr<int32_t> words((size_t)nw_);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, words.get(), (int64_t)nw_, 0);
     NSWITCH(n, strength_n, N, L.rp, L.col, L.mirror, L.dslot, L.v64, L.nnzb, df.get(), w.get(), st);
     LAUNCHCHK();
     gmark("strength");
     L.agg.alloc(N);
-    Graph g{N, L.rp, L.col, w.get()};
-    int32_t nc = match_pass(h, g, L.row_sys.get(), sys_frozen, L.agg.get());
-    gmark("match1");
-    // further passes on the aggregate graph with summed weights
-    DArr<int32_t> grp, gcol, rs, a2, gaptr, gamem;
+    // the current graph (the level's, then each pass's aggregate graph) and
+    // the last pass's map on it
+    DArr<int32_t> grp, gcol, cur_rs;
     DArr<double> gw;
-    DArr<int32_t> cur_rs;                          // row_sys of the current graph
     const int32_t *cur_rp = L.rp, *cur_col = L.col, *cur_rowsys = L.row_sys.get();
     const double *cur_w = w.get();
     int32_t cur_N = N;
-    DArr<int32_t> agg1;                            // last pass's map on the current graph
-    agg1.alloc(N);
-    HIPCHK(hipMemcpyAsync(agg1.get(), L.agg.get(), sizeof(int32_t) * N, hipMemcpyDeviceToDevice, st));
-    for (int p = 1; p < h->opt.match_passes && nc > 1; ++p) {
-        DArr<int32_t> aptr, amem, nrp, ncol, nrs;
+    int cur_lanes = lanes_for(N, L.nnzb);
+    DArr<int32_t> aptr, amem;                      // members of the last pass's map on the current graph
+    int32_t nc = 0, maxc = 0;
+    for (int p = 0; p < passes; ++p) {
+        DArr<int32_t> a(p > 0 ? cur_N : 1);
+        int32_t *map = p == 0 ? L.agg.get() : a.get();
+        Graph g{cur_N, cur_rp, cur_col, cur_w, cur_lanes};
+        match_pass(h, g, cur_rowsys, sys_frozen, map, words.get() + 2 * p);
+        if (p > 0) hipLaunchKernelGGL(k_compose, dim3(cdiv(N, 256)), dim3(256), 0, st, N, map, L.agg.get());
+        LAUNCHCHK();
+        // another pass works on this map's aggregate graph; after the last,
+        // the level's Galerkin product on the composed map
+        const bool more = p + 1 < passes;
+        if (more) build_members(h, cur_N, map, aptr, amem, cur_rp, words.get() + 2 * p + 1);
+        else build_members(h, N, L.agg.get(), L.agg_ptr, L.agg_mem, L.rp, words.get() + 2 * p + 1);
+        int32_t v[2];
+        read_array(words.get() + 2 * p, 2, v, st);
+        nc = v[0];
+        maxc = v[1];
+        gmark(p == 0 ? "match1" : "match2");
+        if (!more || nc <= 1) {
+            if (more) {                            // stopped early: the level's members after all
+                build_members(h, N, L.agg.get(), L.agg_ptr, L.agg_mem, L.rp, words.get() + 2 * passes);
+                maxc = -1;                         // found again by the Galerkin product
+            }
+            break;
+        }
+        DArr<int32_t> nrp, ncol, nrs;
         DArr<double> nw;
-        build_members(h, cur_N, agg1.get(), nc, aptr, amem);
-        gmark("members1");
-        rap_build(h, 1, nc, aptr.get(), amem.get(), cur_rp, cur_col, cur_w, agg1.get(), nrp, ncol, nw, true);
+        const int64_t bound = L.nnzb;
+        rap_build(h, 1, nc, aptr.get(), amem.get(), cur_rp, cur_col, cur_w, map, nrp, ncol, nw, true, maxc, bound,
+                  deferred);
         gmark("wrap");
         hipLaunchKernelGGL(k_zero_diag_w, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, nrp.get(), ncol.get(), nw.get());
         nrs.alloc(nc);
-        hipLaunchKernelGGL(k_inherit_sys, dim3(cdiv(cur_N, 256)), dim3(256), 0, st, cur_N, agg1.get(), cur_rowsys,
+        hipLaunchKernelGGL(k_inherit_sys, dim3(cdiv(cur_N, 256)), dim3(256), 0, st, cur_N, map, cur_rowsys,
                            nrs.get());
         LAUNCHCHK();
-        DArr<int32_t> a(nc);
-        Graph g2{nc, nrp.get(), ncol.get(), nw.get()};
-        const int32_t nc2 = match_pass(h, g2, nrs.get(), sys_frozen, a.get());
-        gmark("match2");
-        hipLaunchKernelGGL(k_compose, dim3(cdiv(N, 256)), dim3(256), 0, st, N, a.get(), L.agg.get());
-        LAUNCHCHK();
-        // the new graph becomes current
+        // the new graph becomes current (about twice the rows' degree)
         grp = std::move(nrp); gcol = std::move(ncol); gw = std::move(nw); cur_rs = std::move(nrs);
         cur_rp = grp.get(); cur_col = gcol.get(); cur_w = gw.get(); cur_rowsys = cur_rs.get();
+        cur_lanes = lanes_for(cur_N, 2 * (int64_t)L.nnzb);
         cur_N = nc;
-        agg1 = std::move(a);
-        nc = nc2;
     }
     L.nc = nc;
+    L.maxc = maxc;
 }
 
 // Multicolour ordering of level l (pattern only).
@@ -1417,8 +1535,9 @@ void amg_setup(cbs_system *h) {
     const bool reuse = o.reuse_aggregates && amg && h->lev.size() > 1 && h->lev[0].agg.get() != nullptr;
     h->transposed_ready = false;
     // errors found by kernels are collected here and read back once at the
-    // end: word 0 holds flag bits (16 asymmetric coarse pattern, 32 singular
-    // coarsest matrix), word 1 + l the first singular block row of level l
+    // end: word 0 holds flag bits (8 aggregate-graph candidate overflow, 16
+    // asymmetric coarse pattern, 32 singular coarsest matrix, 64 FP32
+    // overflow), word 1 + l the first singular block row of level l
     DArr<int32_t> errs((size_t)std::max(1, o.max_levels) + 1);
     int32_t *deferred = errs.get();
     HIPCHK(hipMemsetAsync(errs.get(), 0x7f, sizeof(int32_t) * ((size_t)std::max(1, o.max_levels) + 1), st));
@@ -1477,7 +1596,7 @@ void amg_setup(cbs_system *h) {
         bool last = all_small || l + 1 >= o.max_levels;
         if (!last && !(reuse && L.agg.get() && (int)h->lev.size() > l + 1)) {
             HIPCHK(hipMemcpyAsync(frozen.get(), hfrozen.data(), sizeof(int32_t) * h->n_sys, hipMemcpyHostToDevice, st));
-            aggregate_level(h, L, frozen.get());
+            aggregate_level(h, L, frozen.get(), deferred);
             pt.mark("agg" + std::to_string(l));
             // stall test over the systems still coarsening (frozen rows map 1:1)
             int64_t n_frozen = 0;
@@ -1488,19 +1607,18 @@ void amg_setup(cbs_system *h) {
                 L.agg.release(); L.nc = 0;
                 last = true;
             } else {
-                build_members(h, L.N, L.agg.get(), L.nc, L.agg_ptr, L.agg_mem);
                 if ((int)h->lev.size() > l + 1) h->lev.resize(l + 1);
                 h->lev.emplace_back();
                 Level &C = h->lev[l + 1];
                 Level &F = h->lev[l];
                 C.N = F.nc;
                 C.nnzb = rap_build(h, n, C.N, F.agg_ptr.get(), F.agg_mem.get(), F.rp, F.col, F.v64, F.agg.get(),
-                                   C.o_rp, C.o_col, C.o_v64, true);
+                                   C.o_rp, C.o_col, C.o_v64, true, F.maxc);
                 C.rp = C.o_rp.get(); C.col = C.o_col.get(); C.v64 = C.o_v64.get();
                 C.o_mirror.alloc(C.nnzb); C.o_dslot.alloc(C.N);
                 C.mirror = C.o_mirror.get(); C.dslot = C.o_dslot.get();
-                hipLaunchKernelGGL(k_mirror_search, dim3(cdiv(C.N, 256)), dim3(256), 0, st, C.N, C.rp, C.col, C.mirror,
-                                   C.dslot, deferred);
+                LANES_LAUNCH(k_mirror_search, lanes_for(C.N, C.nnzb), C.N, C.N, C.rp, C.col, C.mirror, C.dslot,
+                             deferred);
                 C.row_sys.alloc(C.N);
                 hipLaunchKernelGGL(k_inherit_sys, dim3(cdiv(F.N, 256)), dim3(256), 0, st, F.N, F.agg.get(),
                                    F.row_sys.get(), C.row_sys.get());
@@ -1514,7 +1632,7 @@ void amg_setup(cbs_system *h) {
             Level &C = h->lev[l + 1];
             Level &F = h->lev[l];
             rap_build(h, n, C.N, F.agg_ptr.get(), F.agg_mem.get(), F.rp, F.col, F.v64, F.agg.get(), C.o_rp, C.o_col,
-                      C.o_v64, false);
+                      C.o_v64, false, F.maxc > 0 ? F.maxc : -1);
             continue;
         }
         // level l is the coarsest
@@ -1670,6 +1788,7 @@ void amg_setup(cbs_system *h) {
     std::vector<int32_t> ev((size_t)nlev + 1);
     for (int32_t k0 = 0; k0 < nlev + 1; k0 += kPinnedWords)
         read_array(errs.get() + k0, std::min<int32_t>(kPinnedWords, nlev + 1 - k0), ev.data() + k0, st);
+    if (ev[0] & 8) cbs_throw(CBS_ERR_ARG, "aggregate graph row candidate overflow");
     if (ev[0] & 16) cbs_throw(CBS_ERR_PATTERN, "coarse pattern is not symmetric");
     for (int q = 0; q + 1 < nlev; ++q)
         if (!h->lev[q].dilu && ev[1 + q] != 0x7f7f7f7f)
@@ -1781,7 +1900,7 @@ void renumber_hierarchy(cbs_system *h, int32_t *deferred) {
         hipLaunchKernelGGL(k_perm_map, G, B, 0, st, N, ip.get(), L.agg.get(), pos[l + 1].get(), aggn.get());
         hipLaunchKernelGGL(k_iota, G, B, 0, st, N, memn.get());
         hipLaunchKernelGGL(k_perm_map, G, B, 0, st, N, ip.get(), L.row_sys.get(), nullptr, rsn.get());
-        hipLaunchKernelGGL(k_mirror_search, G, B, 0, st, N, rpn.get(), coln.get(), mir.get(), dsl.get(), deferred);
+        LANES_LAUNCH(k_mirror_search, lanes_for(N, nnz), N, N, rpn.get(), coln.get(), mir.get(), dsl.get(), deferred);
         LAUNCHCHK();
         if (l == 0) h->perm_sk = std::move(sk);
         L.o_rp = std::move(rpn); L.o_col = std::move(coln); L.o_v64 = std::move(vn);

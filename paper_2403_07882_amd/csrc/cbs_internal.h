@@ -192,6 +192,7 @@ struct Level {
     // transfer to the next level
     DArr<int32_t> agg, agg_ptr, agg_mem;
     int32_t nc = 0;
+    int32_t maxc = 0;                    // largest Galerkin candidate list of the aggregation
     // level vectors in the hierarchy precision (bytes)
     DArr<char> vb, vx, vr, vt, vc;
     // solve-phase matrix copy
