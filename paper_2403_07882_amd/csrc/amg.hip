@@ -326,6 +326,28 @@ __global__ void k_count_members(int32_t N, const int32_t *agg, int32_t *cnt) {
     if (i < N) atomicAdd(&cnt[agg[i]], 1);
 }
 
+// members per aggregate, and the summed row lengths (over the graph rp) of
+// each aggregate's members: its Galerkin candidate count
+__global__ void k_count_members_len(int32_t N, const int32_t *agg, const int32_t *rp, int32_t *cnt, int32_t *len) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int32_t a = agg[i];
+    atomicAdd(&cnt[a], 1);
+    atomicAdd(&len[a], rp[i + 1] - rp[i]);
+}
+
+// *mx = max(*mx, v[0..m)) (grid-stride, 256 threads; one atomic per workgroup)
+__global__ __launch_bounds__(256) void k_max_into(int64_t m, const int32_t *v, int32_t *mx) {
+    __shared__ int32_t sw[4];
+    int32_t b = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+        b = max(b, v[k]);
+    for (int o = 32; o > 0; o >>= 1) b = max(b, __shfl_xor(b, o, 64));
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(mx, max(max(sw[0], sw[1]), max(sw[2], sw[3])));
+}
+
 __global__ void k_fill_members(int32_t N, const int32_t *agg, int32_t *fill, int32_t *mem) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -1216,15 +1238,17 @@ void build_members(cbs_system *h, int32_t N, const int32_t *agg, DArr<int32_t> &
     hipStream_t st = h->stream;
     aptr.alloc(N + 1);
     amem.alloc(N > 0 ? N : 1);
-    DArr<int32_t> fill(N + 1);
+    DArr<int32_t> fill(N + 1), len(N + 1);
     hipLaunchKernelGGL(k_fill_int, dim3(cdiv(N + 1, 256)), dim3(256), 0, st, aptr.get(), (int64_t)N + 1, 0);
-    hipLaunchKernelGGL(k_count_members, dim3(cdiv(N, 256)), dim3(256), 0, st, N, agg, aptr.get());
+    hipLaunchKernelGGL(k_fill_int, dim3(cdiv(N + 1, 256)), dim3(256), 0, st, len.get(), (int64_t)N + 1, 0);
+    hipLaunchKernelGGL(k_count_members_len, dim3(cdiv(N, 256)), dim3(256), 0, st, N, agg, rp, aptr.get(), len.get());
+    hipLaunchKernelGGL(k_max_into, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(N, 256), 256))), dim3(256), 0, st,
+                       (int64_t)N, len.get(), maxc);
     LAUNCHCHK();
     scan_exclusive(aptr.get(), aptr.get(), N, st);
     HIPCHK(hipMemcpyAsync(fill.get(), aptr.get(), sizeof(int32_t) * (N + 1), hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_fill_members, dim3(cdiv(N, 256)), dim3(256), 0, st, N, agg, fill.get(), amem.get());
     hipLaunchKernelGGL(k_sort_members, dim3(cdiv(N, 256)), dim3(256), 0, st, N, aptr.get(), amem.get());
-    hipLaunchKernelGGL(k_rap_maxc, dim3(cdiv(N, 256)), dim3(256), 0, st, N, aptr.get(), amem.get(), rp, maxc);
     LAUNCHCHK();
 }
 

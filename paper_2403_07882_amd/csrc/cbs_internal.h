@@ -119,6 +119,16 @@ struct Sched {
     int8_t split = 1;       // threads sharing one scalar row (1, 2, 4, 8, 16)
 };
 
+// Workgroups are dispatched to the eight XCDs in turn (workgroup b to XCD
+// b mod 8), each XCD with its own L2.  xcd_block maps the dispatch index to
+// a logical one so that each XCD takes one contiguous run of logical
+// workgroups (a bijection on 0..G-1): gathers of neighbouring records then
+// mostly hit the L2 that already holds them.
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t G) {
+    const uint32_t x = b & 7u, k = b >> 3, q = G >> 3, r = G & 7u;
+    return x * q + (x < r ? x : r) + k;
+}
+
 struct SellView {
     int32_t N;              // row positions (rows, or with prow the padded colour ranges)
     const int32_t *soff, *sw, *scol;

@@ -354,7 +354,7 @@ __device__ inline void euler_jac_row(const double *pr, double sx, double sy, dou
 // plus |s| times the viscous radius per unit area.
 __global__ void k_face_radius(int32_t F, const int32_t *la, const int32_t *ua, const double *Q, const double *prim,
                               const double *Sf, const double *lamv, double g, double *lam) {
-    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t f = (int32_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= F) return;
     const int32_t l = la[f], r = ua[f];
     const double *pl = prim + (int64_t)l * 5, *pr = prim + (int64_t)r * 5, *s = Sf + (int64_t)f * 3;
@@ -378,7 +378,7 @@ __global__ void k_face_radius(int32_t F, const int32_t *la, const int32_t *ua, c
 // S lambda, in the row's slot order.
 __global__ void k_cell_faces(int32_t N, int32_t F, const int32_t *rp, const int32_t *src, const double *Sf,
                              const double *lam, double *acc) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double nx = 0.0, ny = 0.0, nz = 0.0, lsum = 0.0;
     for (int32_t k2 = rp[i]; k2 < rp[i + 1]; ++k2) {
@@ -395,58 +395,72 @@ __global__ void k_cell_faces(int32_t N, int32_t F, const int32_t *rp, const int3
     o[0] = nx; o[1] = ny; o[2] = nz; o[3] = lsum;
 }
 
-// Thread t's five values are vals[5t .. 5t+4], so a workgroup's output is one
-// contiguous run: it is staged in LDS and stored with unit stride.
-constexpr int kAsmThreads = 256;
+// One thread per block slot: it gathers the slot's column cell primitives
+// and its face (or cell) data once and writes the block's 25 values, row by
+// row, into LDS; the workgroup's blocks are one contiguous run of the
+// values, stored with unit stride.
+constexpr int kAsmSlots = 128;           // block slots per workgroup of the two slot kernels
 // The block's column cell (the upper slot's neighbour, the lower slot's owner,
 // the diagonal's own cell) is read from the column array, so its primitives
 // load in parallel with the face data instead of after the face addresses.
-__global__ __launch_bounds__(kAsmThreads) void k_assemble_luo(int64_t nnzb, int32_t N, int32_t F,
-                                                              const int32_t *src, const int32_t *col,
-                                                              const double *prim,
-                                                              const double *Sf, const double *lam,
-                                                              const double *cacc, const double *vdt, double g,
-                                                              double *vals, int32_t *flag) {
-    __shared__ double stage[kAsmThreads * 5];
-    const int64_t t0 = (int64_t)blockIdx.x * kAsmThreads;
-    const int64_t t = t0 + threadIdx.x;
-    const bool act = t < nnzb * 5;
-    const int64_t k = act ? t / 5 : 0;
-    const int r = (int)(t - k * 5);
+__global__ __launch_bounds__(kAsmSlots) void k_assemble_luo(int64_t nnzb, int32_t N, int32_t F,
+                                                            const int32_t *src, const int32_t *col,
+                                                            const double *prim,
+                                                            const double *Sf, const double *lam,
+                                                            const double *cacc, const double *vdt, double g,
+                                                            double *vals, int32_t *flag) {
+    __shared__ double stage[kAsmSlots * 25];
+    const int64_t k0 = (int64_t)blockIdx.x * kAsmSlots;
+    const int64_t k = k0 + threadIdx.x;
+    const bool act = k < nnzb;
     const int32_t s = act ? src[k] : 0;
     const int32_t j = act ? col[k] : 0;
-    double out[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (act && s >= N) {
+    const bool face = act && s >= N;
+    double pr[5], sv[3], lf, dt;
+    const double *p = prim + (int64_t)j * 5;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) pr[c] = act ? p[c] : 0.0;
+    if (face) {
         const bool up = s < N + F;
         const int32_t f = up ? s - N : s - N - F;
-        const double *sf = Sf + (int64_t)f * 3;
-        const double lf = lam[f];
         const double sg = up ? 1.0 : -1.0;
-        euler_jac_row(prim + (int64_t)j * 5, sg * sf[0], sg * sf[1], sg * sf[2], g, r, out);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] - (c == r ? lf : 0.0));
-    } else if (act) {
-        const int32_t i = s;
-        const double *a = cacc + (int64_t)i * 4;
-        const double lsum = a[3];
-        euler_jac_row(prim + (int64_t)j * 5, a[0], a[1], a[2], g, r, out);
-        const double dt = vdt ? vdt[i] : 0.0;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] + (c == r ? lsum : 0.0)) + (c == r ? dt : 0.0);
+        const double *sf = Sf + (int64_t)f * 3;
+        sv[0] = sg * sf[0]; sv[1] = sg * sf[1]; sv[2] = sg * sf[2];
+        lf = lam[f];
+        dt = 0.0;
+    } else {
+        const double *a = cacc + (int64_t)(act ? s : 0) * 4;
+        sv[0] = act ? a[0] : 0.0; sv[1] = act ? a[1] : 0.0; sv[2] = act ? a[2] : 0.0;
+        lf = act ? a[3] : 0.0;
+        dt = (act && vdt) ? vdt[s] : 0.0;
     }
     bool bad = false;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        bad = bad || !isfinite(out[c]);
-        stage[threadIdx.x * 5 + c] = out[c];
+    for (int r = 0; r < 5; ++r) {
+        double out[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (act) {
+            euler_jac_row(pr, sv[0], sv[1], sv[2], g, r, out);
+            if (face) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] - (c == r ? lf : 0.0));
+            } else {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) out[c] = 0.5 * (out[c] + (c == r ? lf : 0.0)) + (c == r ? dt : 0.0);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            bad = bad || !isfinite(out[c]);
+            stage[threadIdx.x * 25 + r * 5 + c] = out[c];
+        }
     }
     if (bad) atomicOr(flag, 4);
     __syncthreads();
-    const int64_t total = nnzb * 25, base = t0 * 5;
+    const int64_t total = nnzb * 25, base = k0 * 25;
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        const int64_t e = base + threadIdx.x + j * kAsmThreads;
-        if (e < total) vals[e] = stage[threadIdx.x + j * kAsmThreads];
+    for (int q = 0; q < 25; ++q) {
+        const int64_t e = base + threadIdx.x + q * kAsmSlots;
+        if (e < total) vals[e] = stage[threadIdx.x + q * kAsmSlots];
     }
 }
 
@@ -482,7 +496,7 @@ __global__ void k_pu_cells(int32_t N, int32_t F, const int32_t *rp, const int32_
 // and the diffusion coefficient k_f.
 __global__ void k_pu_faces(int32_t F, const int32_t *la, const int32_t *ua, const double *Sf, const double *fx,
                            const double *dv, const double *nu, const double *acc, double *fc) {
-    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t f = (int32_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (f >= F) return;
     const double *S = Sf + (int64_t)f * 3, *d = dv + (int64_t)f * 3;
     const double Sm = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
@@ -495,7 +509,7 @@ __global__ void k_pu_faces(int32_t F, const int32_t *la, const int32_t *ua, cons
 // Per cell: the pp diagonal, pp_add plus the row's Rhie-Chow coefficients.
 __global__ void k_pu_pp(int32_t N, int32_t F, const int32_t *rp, const int32_t *src, const double *fc,
                         const double *pp_add, double *pp) {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double a = pp_add ? pp_add[i] : 0.0;
     for (int32_t k2 = rp[i]; k2 < rp[i + 1]; ++k2) {
@@ -506,57 +520,58 @@ __global__ void k_pu_pp(int32_t N, int32_t F, const int32_t *rp, const int32_t *
     pp[i] = a;
 }
 
-// One thread per (slot, block row r), four values each, staged in LDS like
-// the density-based kernel.  Row 0 is continuity (pp, pu), rows 1-3 momentum
+// One thread per block slot, its 16 values staged in LDS like the
+// density-based kernel.  Row 0 is continuity (pp, pu), rows 1-3 momentum
 // (up, uu = scalar times I).
-__global__ __launch_bounds__(kAsmThreads) void k_assemble_pu(int64_t nnzb, int32_t N, int32_t F, const int32_t *src,
-                                                             const double *Sf, const double *fx, const double *flux,
-                                                             const double *fc, const double *acc, const double *pp,
-                                                             double *vals, int32_t *flag) {
-    __shared__ double stage[kAsmThreads * 4];
-    const int64_t t0 = (int64_t)blockIdx.x * kAsmThreads;
-    const int64_t t = t0 + threadIdx.x;
-    const bool act = t < nnzb * 4;
-    const int64_t k = act ? t / 4 : 0;
-    const int r = (int)(t - k * 4);
+__global__ __launch_bounds__(kAsmSlots) void k_assemble_pu(int64_t nnzb, int32_t N, int32_t F, const int32_t *src,
+                                                           const double *Sf, const double *fx, const double *flux,
+                                                           const double *fc, const double *acc, const double *pp,
+                                                           double *vals, int32_t *flag) {
+    // one thread per block slot, its 16 values staged in LDS as in
+    // k_assemble_luo
+    __shared__ double stage[kAsmSlots * 16];
+    const int64_t k0 = (int64_t)blockIdx.x * kAsmSlots;
+    const int64_t k = k0 + threadIdx.x;
+    const bool act = k < nnzb;
     const int32_t s = act ? src[k] : 0;
-    double out[4] = {0.0, 0.0, 0.0, 0.0};
+    double out[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) out[e] = 0.0;
     if (act && s >= N) {
         const bool up = s < N + F;
         const int32_t f = up ? s - N : s - N - F;
         const double sg = up ? 1.0 : -1.0, w = up ? fx[f] : 1.0 - fx[f];
         const double *S = Sf + (int64_t)f * 3;
         const double cpl = (1.0 - w) * sg;              // coupling vector (1 - w) sg S
-        if (r == 0) {
-            out[0] = -fc[2 * (int64_t)f];
-            out[1] = cpl * S[0]; out[2] = cpl * S[1]; out[3] = cpl * S[2];
-        } else {
-            out[0] = cpl * S[r - 1];
-            out[r] = -(fmax(-sg * flux[f], 0.0) + fc[2 * (int64_t)f + 1]);
-        }
+        const double c0 = cpl * S[0], c1 = cpl * S[1], c2 = cpl * S[2];
+        const double uu = -(fmax(-sg * flux[f], 0.0) + fc[2 * (int64_t)f + 1]);
+        out[0] = -fc[2 * (int64_t)f];
+        out[1] = c0; out[2] = c1; out[3] = c2;
+        out[4] = c0; out[5] = uu;
+        out[8] = c1; out[10] = uu;
+        out[12] = c2; out[15] = uu;
     } else if (act) {
         const double *a = acc + (int64_t)s * 5;
-        if (r == 0) {
-            out[0] = pp[s];
-            out[1] = a[2]; out[2] = a[3]; out[3] = a[4];
-        } else {
-            out[0] = a[1 + r];
-            out[r] = a[0];
-        }
+        const double a0 = a[0], a2 = a[2], a3 = a[3], a4 = a[4];
+        out[0] = pp[s];
+        out[1] = a2; out[2] = a3; out[3] = a4;
+        out[4] = a2; out[5] = a0;
+        out[8] = a3; out[10] = a0;
+        out[12] = a4; out[15] = a0;
     }
     bool bad = false;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        bad = bad || !isfinite(out[c]);
-        stage[threadIdx.x * 4 + c] = out[c];
+    for (int e = 0; e < 16; ++e) {
+        bad = bad || !isfinite(out[e]);
+        stage[threadIdx.x * 16 + e] = out[e];
     }
     if (bad) atomicOr(flag, 4);
     __syncthreads();
-    const int64_t total = nnzb * 16, base = t0 * 4;
+    const int64_t total = nnzb * 16, base = k0 * 16;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int64_t e = base + threadIdx.x + j * kAsmThreads;
-        if (e < total) vals[e] = stage[threadIdx.x + j * kAsmThreads];
+    for (int q = 0; q < 16; ++q) {
+        const int64_t e = base + threadIdx.x + q * kAsmSlots;
+        if (e < total) vals[e] = stage[threadIdx.x + q * kAsmSlots];
     }
 }
 
@@ -680,7 +695,8 @@ static void assemble_luo_on(cbs_system *h, const double *Q, const double *Sf, co
                        Sf, face_lam, acc);
     const int64_t nthr = h->nnzb * 5;
     if (nthr > 0)
-        hipLaunchKernelGGL(k_assemble_luo, dim3(cdiv(nthr, kAsmThreads)), dim3(kAsmThreads), 0, st, h->nnzb, h->N, h->F,
+        hipLaunchKernelGGL(k_assemble_luo, dim3(cdiv(h->nnzb, kAsmSlots)), dim3(kAsmSlots), 0, st, h->nnzb, h->N,
+                           h->F,
                            h->src.get(), h->col.get(), prim, Sf, face_lam, acc, v_dt, gamma, h->vals.get(), flag);
     LAUNCHCHK();
 }
@@ -784,7 +800,7 @@ void assemble_pu(cbs_system *h, const double *Sf, const double *fx, const double
                        h->face_lam.get(), pp_add, h->cell_prim.get());
     const int64_t nthr = h->nnzb * 4;
     if (nthr > 0)
-        hipLaunchKernelGGL(k_assemble_pu, dim3(cdiv(nthr, kAsmThreads)), dim3(kAsmThreads), 0, st, h->nnzb, h->N, h->F,
+        hipLaunchKernelGGL(k_assemble_pu, dim3(cdiv(h->nnzb, kAsmSlots)), dim3(kAsmSlots), 0, st, h->nnzb, h->N, h->F,
                            h->src.get(), Sf, fx, flux, h->face_lam.get(), h->cell_acc.get(), h->cell_prim.get(),
                            h->vals.get(), h->dflag.get());
     LAUNCHCHK();

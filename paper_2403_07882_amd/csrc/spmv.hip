@@ -622,6 +622,8 @@ __global__ void k_sell_vals(int64_t nent, const int32_t *__restrict__ ssrc, cons
 // through S.ssrc), formed in FP64 and rounded once.  One thread per (slice
 // row, r); padding entries, including the rows that pad the last slice past
 // N, get zeros.
+constexpr int kScaleU = 4;   // entries per row staged together in k_sell_scaled
+
 template <int n>
 __global__ __launch_bounds__(64 * n) void k_sell_scaled(int32_t N, int32_t nslices, int32_t lc,
                                                         const int32_t *__restrict__ soff,
@@ -632,9 +634,11 @@ __global__ __launch_bounds__(64 * n) void k_sell_scaled(int32_t N, int32_t nslic
                                                         int32_t *flag) {
     // 64 slice rows per workgroup, n threads each; per entry, thread r stages
     // row r of the block A_ij in LDS and then forms row r of Dinv_i A_ij from
-    // all of it (each block is read from memory once)
+    // all of it (each block is read from memory once).  kScaleU entries of a
+    // row are staged at a time, so their loads are in flight together.
     constexpr int nn = n * n;
-    __shared__ double sa[64 * nn];
+    constexpr int U = kScaleU;
+    __shared__ double sa[U * 64 * nn];
     __shared__ int32_t wmax;
     const int t = threadIdx.x, lr = t / n, r = t - lr * n;
     const int64_t npos = (int64_t)nslices << lc;
@@ -652,20 +656,34 @@ __global__ __launch_bounds__(64 * n) void k_sell_scaled(int32_t N, int32_t nslic
     __syncthreads();
     const int32_t W = wmax;
     bool bad = false;
-    for (int32_t k = 0; k < W; ++k) {
-        const bool has = k < w;
-        const int64_t e = base + ((int64_t)k << lc);
-        const int32_t src = (has && i < N) ? ssrc[e] : -1;
-        const double *p = bvals + (int64_t)(src < 0 ? 0 : src) * nn + r * n;
+    for (int32_t k0 = 0; k0 < W; k0 += U) {
+        int32_t src[U];
 #pragma unroll
-        for (int c = 0; c < n; ++c) sa[lr * nn + r * n + c] = src < 0 ? 0.0 : p[c];
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = base + ((int64_t)(k0 + u) << lc);
+            src[u] = (k0 + u < w && i < N) ? ssrc[e] : -1;
+        }
+        double a[U][n];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double *p = bvals + (int64_t)(src[u] < 0 ? 0 : src[u]) * nn + r * n;
+#pragma unroll
+            for (int c = 0; c < n; ++c) a[u][c] = src[u] < 0 ? 0.0 : p[c];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < n; ++c) sa[(u * 64 + lr) * nn + r * n + c] = a[u][c];
         __syncthreads();
-        if (has) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 + u >= w) continue;
+            const int64_t e = base + ((int64_t)(k0 + u) << lc);
 #pragma unroll
             for (int c = 0; c < n; ++c) {
                 double acc = 0.0;
 #pragma unroll
-                for (int q = 0; q < n; ++q) acc += d[q] * sa[lr * nn + q * n + c];
+                for (int q = 0; q < n; ++q) acc += d[q] * sa[(u * 64 + lr) * nn + q * n + c];
                 const float v = (float)acc;
                 out[e * nn + r * n + c] = v;
                 bad = bad || !isfinite(v);
