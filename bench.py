@@ -45,7 +45,7 @@ TRAFFIC_KIND = ("L2-to-memory-fabric bytes per launch (FETCH_SIZE + WRITE_SIZE, 
 # Average duration of the same kernels inside timed bench steps (rocprofv3
 # --kernel-trace of the default run, profiles/bench_pu1M_kernel_stats.md);
 # None where not measured for the current kernel code.
-IN_STEP_US_PU1M = {"sweep": 83.79, "spmv_internal": 178.38, "spmv_caller": None}
+IN_STEP_US_PU1M = {"sweep": 83.73, "spmv_internal": 178.97, "spmv_caller": None}
 
 
 def parse():
@@ -90,6 +90,15 @@ def parse():
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def _method_name(args):
+    """The solve the headline step runs, e.g. 'mixed AMG-BiCGStab'."""
+    solver = {"bicgstab": "BiCGStab", "fgmres": "FGMRES(30)", "gmres": "GMRES(30)"}[args.solver]
+    if args.precond == "sgs":
+        return "FP64 %s + symmetric Gauss-Seidel" % solver
+    smoother = "" if args.smoother == "bjacobi" else " (%s smoother)" % args.smoother.upper()
+    return "mixed AMG-%s%s" % (solver, smoother)
 
 
 def spmv_bytes(N, nnzb, n, s=8):
@@ -674,8 +683,8 @@ def main():
         "dtype": "f64 outer / f32 AMG",
         "data": "synthetic",
         "config": {"workload": "pressure-based coupled p-U 4x4, %dx%dx%d jittered hex mesh, cells "
-                               "randomly renumbered (N=%d, F=%d, nnzb=%d); mixed AMG-BiCGStab to 1e-8"
-                               % (nx, ny, nz, N, F, nnzb),
+                               "randomly renumbered (N=%d, F=%d, nnzb=%d); %s to 1e-8"
+                               % (nx, ny, nz, N, F, nnzb, _method_name(args)),
                    "step": "pack fields + update_values + setup + solve + unpack fields",
                    "precond": args.precond, "max_iter": args.max_iter,
                    "solver": args.solver, "smoother": args.smoother, "dilu_levels": args.dilu_levels,
