@@ -470,35 +470,71 @@ def test_renumbering_keeps_the_solution():
             assert O.relres(O.transpose(A), s["b"], _np(lam)) <= 1e-10 * 1.0001
 
 
-def test_aggregation_properties():
+# coarsening ratio N / nc of one, two and three matching passes on a hex box
+_RATIO = {1: (1.6, 2.5), 2: (3.0, 6.0), 3: (5.0, 12.0)}
+
+
+@pytest.mark.parametrize("passes", [1, 2, 3])
+def test_aggregation_properties(passes):
+    """Every aggregate is non-empty and connected in the matrix graph (all of
+    them), and the coarsening ratio is that of `passes` pairwise passes.  One
+    pass joins a matched pair and unmatched neighbours of its two members, so
+    its aggregates hold at most 2 + 2 (d - 1) rows for d the largest
+    off-diagonal row degree; after more passes (on aggregate graphs of larger
+    degree) no aggregate exceeds eight times the mean size.  The V-cycle
+    built on these aggregates matches the oracle's."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    _say("aggregation passes", passes)
     s = jacobian_box(16, 16, 16, seed=0)
+    N, n = int(s["N"]), int(s["n"])
     with P.System.from_dict(s) as sysm:
-        sysm.setup(precond=P.PREC_AMG, match_passes=2)
+        sysm.setup(precond=P.PREC_AMG, match_passes=passes, coarse_max=8)
+        nlev = sysm.info()["levels"]
         lv = sysm.get_level(0)
         agg_int = _np(lv["agg"])
         order = _np(lv["order"])
+        A0 = O.BCSR(N, n, _np(lv["row_ptr"]), _np(lv["col"]), _np(lv["vals"]))
+        aggs = [_np(sysm.get_level(l)["agg"]) for l in range(nlev - 1)]
+        r = np.random.default_rng(8).standard_normal((N, n))
+        z = _np(sysm.apply_precond(r))
     agg = np.empty_like(agg_int)
     agg[order] = agg_int                       # back to the caller's cell numbering
-    nc = agg.max() + 1
-    sizes = np.bincount(agg)
-    assert sizes.min() >= 1 and nc < s["N"] / 2.5
-    # every aggregate is connected in the matrix graph (checked on a sample)
+    nc = int(agg.max()) + 1
+    sizes = np.bincount(agg, minlength=nc)
+    assert sizes.min() >= 1
+    lo, hi = _RATIO[passes]
+    assert lo <= N / nc <= hi, N / nc
     A = O.from_system(s)
     rows = np.repeat(np.arange(A.N), np.diff(A.row_ptr))
-    nbr = {}
-    for i, j in zip(rows, A.col):
-        nbr.setdefault(i, set()).add(j)
-    mem = {}
-    for i, I in enumerate(agg):
-        mem.setdefault(I, []).append(i)
-    for I in list(mem)[:500]:
-        ms = set(mem[I]); seen, st_ = set(), [mem[I][0]]
-        while st_:
-            u = st_.pop()
-            if u in seen:
-                continue
-            seen.add(u); st_.extend(v for v in nbr[u] if v in ms)
-        assert seen == ms
+    off = rows != A.col
+    d = int(np.bincount(rows[off], minlength=N).max())
+    bound = 2 + 2 * (d - 1) if passes == 1 else 8 * N / nc
+    assert sizes.max() <= bound, (sizes.max(), bound)
+    # connected: the graph of the edges inside aggregates has one component per aggregate
+    inside = off & (agg[rows] == agg[A.col])
+    g = coo_matrix((np.ones(int(inside.sum())), (rows[inside], A.col[inside])), shape=(N, N))
+    ncomp, _ = connected_components(g, directed=False)
+    assert ncomp == nc, (ncomp, nc)
+    amg = O.AMG(A0, nu1=2, nu2=2, omega=0.9, aggs=aggs)
+    zr_int = amg.apply(r[order])
+    zr = np.empty_like(zr_int); zr[order] = zr_int
+    _agree(z, zr, 1e-11)                       # FP64 hierarchy (the default precision)
+
+
+def test_aggregation_of_a_pair_stops_after_one_pass():
+    """Two cells (coarse_max 1): the first matching pass leaves one aggregate,
+    so the second pass is skipped and the level's members and Galerkin
+    product are built on the first pass's map alone."""
+    s = jacobian_box(2, 1, 1, seed=3)
+    A = O.from_system(s)
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, coarse_max=1, match_passes=2, tol=1e-12)
+        assert sysm.info()["levels"] == 2
+        assert np.array_equal(np.sort(_np(sysm.get_level(0)["agg"])), [0, 0])
+        x, st = sysm.solve(s["b"])
+    assert st["status"] == P.OK
+    assert O.relres(A, s["b"], _np(x)) <= 1e-12 * 1.0001
 
 
 # ------------------------------------------------------------------ adjoint
