@@ -34,6 +34,7 @@
 #ifndef CBS_H
 #define CBS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -252,6 +253,28 @@ int cbs_assemble_luo_noalloc(cbs_handle h, const double *Q, const double *Sf, co
 int cbs_assemble_pu(cbs_handle h, const double *Sf, const double *fx, const double *d, const double *flux,
                     const double *nu_eff, const double *vol, const double *uu_add, const double *pp_add);
 
+/* Device memory of a handle through the caller's allocator (for example a
+ * framework's caching allocator).  The library keeps its own cache of blocks
+ * on top of it, keyed by stream and allocator: alloc is called only when no
+ * cached block of the handle's stream fits, and free when blocks are given
+ * back (at cbs_destroy of the handle).  alloc(ctx, bytes, stream) returns a
+ * device pointer aligned to 256 bytes, or NULL (the call that needed it then
+ * fails with CBS_ERR_OOM); free(ctx, ptr, stream) releases one.  stream is
+ * the handle's stream, the only stream the memory is used on.  Both run on
+ * the thread that called into the library. */
+typedef struct cbs_allocator {
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *ptr, void *stream);
+    void *ctx;
+} cbs_allocator;
+
+/* Allocations of h from this call on go through *a (NULL: back to hipMalloc
+ * / hipFree).  Blocks made earlier stay with the allocator that made them
+ * and are given back to it.  *a is copied; its functions and ctx must stay
+ * valid until cbs_destroy(h) returns.  Errors: CBS_ERR_ARG (NULL handle, or
+ * an allocator with alloc or free missing). */
+int cbs_set_allocator(cbs_handle h, const cbs_allocator *a /* host, may be NULL */);
+
 /* Build the preconditioner: block-diagonal inverses (FP64), and for AMG the
  * pairwise-matching aggregation, Galerkin coarse operators P^T A P with
  * piecewise-constant P, FP32 level copies (mixed precision) and the dense
@@ -265,6 +288,14 @@ int cbs_setup(cbs_handle h, const cbs_options *opt /* host */);
  * b = 0 returns x = 0 with 0 iterations.  Returns CBS_NOT_CONVERGED (x
  * written) at the iteration cap. */
 int cbs_solve(cbs_handle h, const double *b, double *x, cbs_stats *st /* host */);
+
+/* The batched solve of a handle from cbs_create_batch_from_ldu: the same
+ * call as cbs_solve, spelled for batches.  b and x are the systems'
+ * vectors concatenated in system order (x[cell_off[s]*n ..] is system s);
+ * st_array (host, may be NULL) receives n_sys stats, one per system, each
+ * system stopping at its own tolerance.  Returns CBS_NOT_CONVERGED when any
+ * system stops at the iteration cap (every x written). */
+int cbs_solve_batch(cbs_handle h, const double *b, double *x, cbs_stats *st_array /* host */);
 
 /* Solve the transposed system A^T lambda = g with the same options and
  * aggregates (the adjoint solve of L(x(A,b))).  Same argument rules as
@@ -326,6 +357,14 @@ int cbs_get_info(cbs_handle h, int32_t *n_cells /* host */, int32_t *n_faces /* 
                  int32_t *n_sys /* host */);
 int cbs_get_bcsr(cbs_handle h, int32_t *row_ptr, int32_t *col, double *vals,
                  int32_t *diag_slot, int32_t *upper_slot, int32_t *lower_slot);
+
+/* The transpose-slot map of the level-0 block CSR, mirror[nnzb] (device
+ * array of the caller): mirror[k] is the slot of block (j, i) for the block
+ * (i, j) in slot k.  It is what the transposed product and solve read A^T
+ * through (Eq. discretBackward's adjoint): mirror[upper_slot[f]] =
+ * lower_slot[f], mirror[lower_slot[f]] = upper_slot[f], and a diagonal slot
+ * is its own mirror. */
+int cbs_get_mirror(cbs_handle h, int32_t *mirror);
 
 /* Level l of the AMG hierarchy (after cbs_setup): n_rows, nnzb (host) and,
  * into caller device arrays when non-NULL, its block CSR (FP64 values) in

@@ -53,6 +53,34 @@ class Stats(C.Structure):
 
 
 # (name, restype, argtypes) of every exported entry point
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    """cbs_allocator: alloc(ctx, bytes, stream), free(ctx, ptr, stream), ctx."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
+def torch_allocator():
+    """An Allocator that takes the library's device memory from PyTorch's
+    caching allocator (torch.cuda.caching_allocator_alloc on the handle's
+    stream).  Keep the returned object alive as long as the handle."""
+    torch = _torch()
+    dev = torch.cuda.current_device()
+
+    def _alloc(ctx, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+        except RuntimeError:                 # out of memory: the library reports CBS_ERR_OOM
+            return None
+
+    def _free(ctx, ptr, stream):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
+
+
 _VP, _I32, _I64, _D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
 SIGNATURES = [
     ("cbs_default_options", None, [C.POINTER(Options)]),
@@ -65,6 +93,7 @@ SIGNATURES = [
     ("cbs_assemble_pu", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cbs_setup", C.c_int, [_VP, C.POINTER(Options)]),
     ("cbs_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
+    ("cbs_solve_batch", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
     ("cbs_solve_transpose", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
     ("cbs_gradient", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     ("cbs_spmv", C.c_int, [_VP, _VP, _VP, _I32]),
@@ -76,6 +105,8 @@ SIGNATURES = [
     ("cbs_get_info", C.c_int, [_VP, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I64),
                                C.POINTER(_I32), C.POINTER(_I32)]),
     ("cbs_get_bcsr", C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("cbs_get_mirror", C.c_int, [_VP, _VP]),
+    ("cbs_set_allocator", C.c_int, [_VP, C.POINTER(Allocator)]),
     ("cbs_get_level", C.c_int, [_VP, _I32, C.POINTER(_I32), C.POINTER(_I64), _VP, _VP, _VP, _VP, _VP, _VP]),
     ("cbs_destroy", C.c_int, [_VP]),
     ("cbs_error_string", C.c_char_p, [C.c_int]),
@@ -174,10 +205,12 @@ class System:
     ``System(N, n, lower_addr, upper_addr, diag, upper, lower)``: LDU arrays
     (numpy or torch; copied to the device).  Batched: pass ``cell_off`` and
     ``face_off`` (host int64 offsets) with per-system local face addresses.
+    ``allocator="torch"`` takes the device memory of setup and solve from
+    PyTorch's caching allocator (cbs_set_allocator) instead of hipMalloc.
     """
 
     def __init__(self, N, n, lower_addr, upper_addr, diag, upper, lower,
-                 cell_off=None, face_off=None):
+                 cell_off=None, face_off=None, allocator=None):
         torch = _torch()
         L = lib()
         self.n = int(n)
@@ -206,17 +239,23 @@ class System:
                                              _stream_ptr())
         _check(rc, "cbs_create")
         self.h = h
+        self._allocator = None
+        if allocator is not None:
+            if allocator != "torch":
+                raise ValueError("allocator must be None or 'torch'")
+            self._allocator = torch_allocator()
+            _check(L.cbs_set_allocator(self.h, C.byref(self._allocator)), "cbs_set_allocator")
         self.options: Optional[Options] = None
         # bumped by every call that changes the matrix or its preconditioner;
         # the autograd backward refuses a System whose generation moved
         self.generation = 0
 
     @classmethod
-    def from_dict(cls, s):
+    def from_dict(cls, s, **kw):
         if "cell_off" in s:
             return cls(s["N"], s["n"], s["lower_addr"], s["upper_addr"], s["diag"], s["upper"],
-                       s["lower"], cell_off=s["cell_off"], face_off=s["face_off"])
-        return cls(s["N"], s["n"], s["lower_addr"], s["upper_addr"], s["diag"], s["upper"], s["lower"])
+                       s["lower"], cell_off=s["cell_off"], face_off=s["face_off"], **kw)
+        return cls(s["N"], s["n"], s["lower_addr"], s["upper_addr"], s["diag"], s["upper"], s["lower"], **kw)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -292,6 +331,12 @@ class System:
         x, st, _ = self._solve(lib().cbs_solve, "cbs_solve", b, x0)
         return x, st
 
+    def solve_batch(self, b, x0=None):
+        """cbs_solve_batch: the systems' vectors concatenated; returns (x on
+        the device, a list of n_sys stats dicts)."""
+        x, st, _ = self._solve(lib().cbs_solve_batch, "cbs_solve_batch", b, x0)
+        return x, (st if isinstance(st, list) else [st])
+
     def solve_transpose(self, g, x0=None):
         x, st, _ = self._solve(lib().cbs_solve_transpose, "cbs_solve_transpose", g, x0)
         return x, st
@@ -357,6 +402,14 @@ class System:
                "cbs_get_bcsr")
         return {"row_ptr": rp, "col": col, "vals": vals, "diag_slot": ds,
                 "upper_slot": us[:F], "lower_slot": ls[:F]}
+
+    def get_mirror(self):
+        """The level-0 transpose-slot map mirror[nnzb] (device int32)."""
+        torch = _torch()
+        nnzb = self.info()["nnzb"]
+        m = torch.empty(max(nnzb, 1), dtype=torch.int32, device="cuda")
+        _check(lib().cbs_get_mirror(self.h, _ptr(m)), "cbs_get_mirror")
+        return m[:nnzb]
 
     def get_level(self, level):
         torch = _torch()

@@ -125,38 +125,68 @@ int create_common(cbs_handle *out, int32_t n_sys, const int64_t *cell_off, const
 namespace {
 thread_local hipStream_t g_alloc_stream = nullptr;
 
+// the allocator a block came from (all null: hipMalloc / hipFree)
+struct AllocHook {
+    void *(*alloc)(void *, size_t, void *) = nullptr;
+    void (*free)(void *, void *, void *) = nullptr;
+    void *ctx = nullptr;
+    bool operator==(const AllocHook &o) const { return alloc == o.alloc && free == o.free && ctx == o.ctx; }
+};
+thread_local AllocHook g_alloc_hook;
+
 struct CachedBlock {
     void *p;
     size_t bytes;
     hipStream_t st;
+    AllocHook hook;
 };
 std::mutex g_mem_mu;
 std::multimap<size_t, CachedBlock> g_free_blocks;
-std::unordered_map<void *, size_t> g_live_blocks;
+std::unordered_map<void *, std::pair<size_t, AllocHook>> g_live_blocks;
+
+void release_block(const CachedBlock &b) {
+    if (b.hook.free) b.hook.free(b.hook.ctx, b.p, reinterpret_cast<void *>(b.st));
+    else (void)hipFree(b.p);
+}
 }  // namespace
 
 hipStream_t alloc_stream() { return g_alloc_stream; }
-void set_alloc_stream(hipStream_t st) { g_alloc_stream = st; }
+void set_alloc_stream(hipStream_t st) {
+    g_alloc_stream = st;
+    g_alloc_hook = AllocHook{};
+}
+// the handle's stream and allocator for the allocations of the current call
+static void set_alloc_handle(const cbs_system *h) {
+    g_alloc_stream = h->stream;
+    g_alloc_hook = AllocHook{h->alloc.alloc, h->alloc.free, h->alloc.ctx};
+}
 
 void *dev_alloc(size_t bytes) {
     bytes = (bytes + 511) & ~(size_t)511;
     {
         std::lock_guard<std::mutex> lk(g_mem_mu);
         for (auto it = g_free_blocks.lower_bound(bytes); it != g_free_blocks.end() && it->first <= 2 * bytes; ++it) {
-            if (it->second.st != g_alloc_stream) continue;
+            if (it->second.st != g_alloc_stream || !(it->second.hook == g_alloc_hook)) continue;
             void *p = it->second.p;
-            g_live_blocks[p] = it->first;
+            g_live_blocks[p] = {it->first, it->second.hook};
             g_free_blocks.erase(it);
             return p;
         }
     }
     void *q = nullptr;
-    if (hipMalloc(&q, bytes) != hipSuccess || !q) {
+    if (g_alloc_hook.alloc) {
+        q = g_alloc_hook.alloc(g_alloc_hook.ctx, bytes, reinterpret_cast<void *>(g_alloc_stream));
+        if (!q) cbs_throw(CBS_ERR_OOM, "the handle's allocator refused " + std::to_string(bytes) + " bytes");
+        if (reinterpret_cast<uintptr_t>(q) & 255) {
+            g_alloc_hook.free(g_alloc_hook.ctx, q, reinterpret_cast<void *>(g_alloc_stream));
+            cbs_throw(CBS_ERR_ARG, "the handle's allocator returned memory not aligned to 256 bytes");
+        }
+    } else if (hipMalloc(&q, bytes) != hipSuccess || !q) {
         (void)hipGetLastError();
         cbs_throw(CBS_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
     std::lock_guard<std::mutex> lk(g_mem_mu);
-    g_live_blocks[q] = bytes;
+    g_live_blocks[q] = {bytes, g_alloc_hook};
     return q;
 }
 
@@ -165,16 +195,17 @@ void dev_free(void *p) {
     std::lock_guard<std::mutex> lk(g_mem_mu);
     auto it = g_live_blocks.find(p);
     if (it == g_live_blocks.end()) return;
-    g_free_blocks.emplace(it->second, CachedBlock{p, it->second, g_alloc_stream});
+    g_free_blocks.emplace(it->second.first, CachedBlock{p, it->second.first, g_alloc_stream, it->second.second});
     g_live_blocks.erase(it);
 }
 
-// return the cached blocks of one stream to HIP (the stream must be idle)
+// return the cached blocks of one stream to the allocators that made them
+// (the stream must be idle)
 static void dev_cache_trim(hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_mem_mu);
     for (auto it = g_free_blocks.begin(); it != g_free_blocks.end();) {
         if (it->second.st == st) {
-            (void)hipFree(it->second.p);
+            release_block(it->second);
             it = g_free_blocks.erase(it);
         } else {
             ++it;
@@ -265,7 +296,7 @@ int cbs_create_batch_from_ldu(cbs_handle *out, int32_t n_sys, const int64_t *cel
 int cbs_update_values(cbs_handle h, const double *diag, const double *upper, const double *lower) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         require(diag != nullptr && (h->F == 0 || (upper && lower)), CBS_ERR_ARG, "value arrays are NULL");
         HIPCHK(hipEventRecord(h->ev0, h->stream));
         convert_values(h, diag, upper, lower);
@@ -285,7 +316,7 @@ int cbs_assemble_luo(cbs_handle h, const double *Q, const double *Sf, const doub
                      double gamma) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         require(h->n == 5, CBS_ERR_ARG, "the density-based assembly needs 5 x 5 blocks");
         require(Q != nullptr && (h->F == 0 || Sf != nullptr), CBS_ERR_ARG, "state or face arrays are NULL");
         require(gamma > 1.0, CBS_ERR_ARG, "gamma must exceed 1");
@@ -307,7 +338,7 @@ int cbs_assemble_luo_noalloc(cbs_handle h, const double *Q, const double *Sf, co
                              const double *v_dt, double gamma) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         require(h->n == 5, CBS_ERR_ARG, "the density-based assembly needs 5 x 5 blocks");
         require(Q != nullptr && (h->F == 0 || Sf != nullptr), CBS_ERR_ARG, "state or face arrays are NULL");
         require(gamma > 1.0, CBS_ERR_ARG, "gamma must exceed 1");
@@ -329,7 +360,7 @@ int cbs_assemble_pu(cbs_handle h, const double *Sf, const double *fx, const doub
                     const double *nu_eff, const double *vol, const double *uu_add, const double *pp_add) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         require(h->n == 4, CBS_ERR_ARG, "the pressure-based assembly needs 4 x 4 blocks");
         require(vol != nullptr && (h->F == 0 || (Sf && fx && d && flux && nu_eff)), CBS_ERR_ARG,
                 "face or cell arrays are NULL");
@@ -350,7 +381,7 @@ int cbs_assemble_pu(cbs_handle h, const double *Sf, const double *fx, const doub
 int cbs_setup(cbs_handle h, const cbs_options *opt) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         cbs_options o;
         if (opt) o = *opt; else cbs_default_options(&o);
         require(o.solver == CBS_SOLVER_BICGSTAB || o.solver == CBS_SOLVER_FGMRES || o.solver == CBS_SOLVER_GMRES,
@@ -423,15 +454,23 @@ static int solve_common(cbs_handle h, const double *b, double *x, cbs_stats *st,
 int cbs_solve(cbs_handle h, const double *b, double *x, cbs_stats *st) {
     return guarded([&] {
         require(h != nullptr && b != nullptr && x != nullptr, CBS_ERR_ARG, "NULL argument");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         return solve_common(h, b, x, st, false);
+    });
+}
+
+int cbs_solve_batch(cbs_handle h, const double *b, double *x, cbs_stats *st_array) {
+    return guarded([&] {
+        require(h != nullptr && b != nullptr && x != nullptr, CBS_ERR_ARG, "NULL argument");
+        set_alloc_handle(h);
+        return solve_common(h, b, x, st_array, false);
     });
 }
 
 int cbs_solve_transpose(cbs_handle h, const double *g, double *lambda, cbs_stats *st) {
     return guarded([&] {
         require(h != nullptr && g != nullptr && lambda != nullptr, CBS_ERR_ARG, "NULL argument");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         return solve_common(h, g, lambda, st, true);
     });
 }
@@ -439,7 +478,7 @@ int cbs_solve_transpose(cbs_handle h, const double *g, double *lambda, cbs_stats
 int cbs_gradient(cbs_handle h, const double *lambda, const double *x, double *gd, double *gu, double *gl) {
     return guarded([&] {
         require(h != nullptr && lambda && x && gd && (h->F == 0 || (gu && gl)), CBS_ERR_ARG, "NULL argument");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         gradient(h, lambda, x, gd, gu, gl);
         HIPCHK(hipStreamSynchronize(h->stream));
         return CBS_OK;
@@ -449,7 +488,7 @@ int cbs_gradient(cbs_handle h, const double *lambda, const double *x, double *gd
 int cbs_spmv(cbs_handle h, const double *x, double *y, int32_t transpose) {
     return guarded([&] {
         require(h != nullptr && x && y, CBS_ERR_ARG, "NULL argument");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         spmv_user(h, x, y, transpose != 0);
         return CBS_OK;
     });
@@ -458,7 +497,7 @@ int cbs_spmv(cbs_handle h, const double *x, double *y, int32_t transpose) {
 int cbs_apply_precond(cbs_handle h, const double *r, double *z) {
     return guarded([&] {
         require(h != nullptr && r && z, CBS_ERR_ARG, "NULL argument");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
         if (h->renumbered) {
             const int64_t m = (int64_t)h->N * h->n;
@@ -477,7 +516,7 @@ int cbs_apply_precond(cbs_handle h, const double *r, double *z) {
 int cbs_apply_precond_transpose(cbs_handle h, const double *r, double *z) {
     return guarded([&] {
         require(h != nullptr && r && z, CBS_ERR_ARG, "NULL argument");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
         amg_build_transposed(h);
         if (h->renumbered) {
@@ -497,7 +536,7 @@ int cbs_apply_precond_transpose(cbs_handle h, const double *r, double *z) {
 int cbs_level_apply(cbs_handle h, int32_t level, int32_t op, const void *b, const void *x, void *y, int32_t *fp32) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         require(h->setup_done && !h->values_changed, CBS_ERR_STATE, "cbs_setup must follow create/update_values");
         require(h->opt.precond == CBS_PREC_AMG, CBS_ERR_STATE, "level kernels need the AMG preconditioner");
         require(level >= 0 && level + 1 < (int32_t)h->lev.size(), CBS_ERR_ARG,
@@ -557,7 +596,7 @@ int cbs_get_info(cbs_handle h, int32_t *n_cells, int32_t *n_faces, int32_t *bdim
                  int32_t *n_sys) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         if (n_cells) *n_cells = h->N;
         if (n_faces) *n_faces = h->F;
         if (bdim) *bdim = h->n;
@@ -572,7 +611,7 @@ int cbs_get_bcsr(cbs_handle h, int32_t *row_ptr, int32_t *col, double *vals, int
                  int32_t *lower_slot) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         hipStream_t st = h->stream;
         const size_t bs = (size_t)h->n * h->n;
         if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, h->rp.get(), sizeof(int32_t) * (h->N + 1), hipMemcpyDeviceToDevice, st));
@@ -588,11 +627,23 @@ int cbs_get_bcsr(cbs_handle h, int32_t *row_ptr, int32_t *col, double *vals, int
     });
 }
 
+int cbs_get_mirror(cbs_handle h, int32_t *mirror) {
+    return guarded([&] {
+        require(h != nullptr && mirror != nullptr, CBS_ERR_ARG, "NULL argument");
+        set_alloc_handle(h);
+        if (h->nnzb > 0)
+            HIPCHK(hipMemcpyAsync(mirror, h->mirror.get(), sizeof(int32_t) * h->nnzb, hipMemcpyDeviceToDevice,
+                                  h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return CBS_OK;
+    });
+}
+
 int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows, int64_t *nnzb, int32_t *row_ptr, int32_t *col,
                   double *vals, int32_t *agg, int32_t *colour, int32_t *order) {
     return guarded([&] {
         require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         require(h->setup_done, CBS_ERR_STATE, "no hierarchy before cbs_setup");
         require(level >= 0 && level < (int32_t)h->lev.size(), CBS_ERR_ARG, "level out of range");
         Level &L = h->lev[level];
@@ -621,10 +672,19 @@ int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows, int64_t *nnzb, i
     });
 }
 
+int cbs_set_allocator(cbs_handle h, const cbs_allocator *a) {
+    return guarded([&] {
+        require(h != nullptr, CBS_ERR_ARG, "handle is NULL");
+        require(!a || (a->alloc && a->free), CBS_ERR_ARG, "allocator needs both alloc and free");
+        h->alloc = a ? *a : cbs_allocator{};
+        return CBS_OK;
+    });
+}
+
 int cbs_destroy(cbs_handle h) {
     return guarded([&] {
         if (!h) return CBS_OK;
-        set_alloc_stream(h->stream);
+        set_alloc_handle(h);
         hipStream_t st = h->stream;
         delete h;
         dev_cache_trim(st);

@@ -223,6 +223,7 @@ struct cbs_system {
     int32_t N = 0, F = 0, n = 0, n_sys = 1;
     int device = 0;                              // device current at creation (holds every buffer)
     int lds_max = 64 * 1024;                     // LDS bytes one workgroup may hold on that device
+    cbs_allocator alloc{};                       // the caller's allocator (all null: hipMalloc)
     hipStream_t stream = nullptr;
     std::vector<int64_t> cell_off, face_off;     // host
     // level-0 pattern and conversion maps

@@ -72,6 +72,9 @@ def test_argument_errors_without_gpu():
         lambda: L.cbs_setup(None, C.byref(o)),
         lambda: L.cbs_solve(None, None, None, C.byref(st)),
         lambda: L.cbs_solve_transpose(None, None, None, C.byref(st)),
+        lambda: L.cbs_solve_batch(None, None, None, C.byref(st)),
+        lambda: L.cbs_get_mirror(None, None),
+        lambda: L.cbs_set_allocator(None, None),
         lambda: L.cbs_apply_precond(None, None, None),
         lambda: L.cbs_apply_precond_transpose(None, None, None),
         lambda: L.cbs_spmv(None, None, None, 0),

@@ -67,6 +67,12 @@ def test_conversion_bitexact(case):
         assert np.array_equal(_np(g["diag_slot"]), ds)
         assert np.array_equal(_np(g["upper_slot"]), us)
         assert np.array_equal(_np(g["lower_slot"]), ls)
+        # the transpose-slot map: each face's two blocks swap, a diagonal
+        # block stays; with the oracle's slot maps this fixes every entry
+        m = _np(sysm.get_mirror())
+        assert m.size == A.col.size
+        assert np.array_equal(m[us], ls) and np.array_equal(m[ls], us) and np.array_equal(m[ds], ds)
+        assert np.array_equal(m[m], np.arange(m.size))
 
 
 def test_conversion_values_update_bitexact():
@@ -625,6 +631,9 @@ def test_batched_solve_matches_solo_solves():
         with P.System.from_dict(cat) as bs:
             bs.setup(precond=P.PREC_AMG, precision=precision, tol=1e-8)
             x, stats = bs.solve(cat["b"])
+            xb, statsb = bs.solve_batch(cat["b"])          # the batch spelling: the same solve
+        assert np.array_equal(_np(xb), _np(x))
+        assert [s_["iterations"] for s_ in statsb] == [s_["iterations"] for s_ in stats]
         xn = _np(x)
         assert len(stats) == len(systems)
         for k, s in enumerate(systems):
@@ -745,6 +754,36 @@ def test_two_colour_levels_several_steps(pre, post, smoother, precision):
     1's residual is formed after the pre-smoothing.  Several steps, uneven
     and zero counts, both precisions, against the oracle's cycle."""
     _coloured_vcycle_case(pressure_velocity(12, 10, 9, seed=5), 1, smoother, pre, post, precision)
+
+
+def test_torch_allocator_serves_the_library():
+    """cbs_set_allocator with PyTorch's caching allocator: setup and solve take
+    their device memory from it (torch's count of allocated bytes grows by
+    the hierarchy while the handle lives and falls back at cbs_destroy), and
+    the solution is bit for bit the one of the library's own hipMalloc
+    blocks."""
+    _say("torch allocator")
+    s = pressure_velocity(16, 14, 12, seed=12)
+    res, held, left = {}, {}, {}
+    for alloc in (None, "torch"):
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        sysm = P.System.from_dict(s, allocator=alloc)
+        sysm.setup(precond=P.PREC_AMG, precision=P.PRECISION_MIXED, tol=1e-9)
+        x, st = sysm.solve(s["b"])
+        lam, _ = sysm.solve_transpose(s["b"])
+        torch.cuda.synchronize()
+        held[alloc] = torch.cuda.memory_allocated() - base
+        res[alloc] = (_np(x), _np(lam), st["iterations"])
+        del x, lam
+        sysm.close()
+        torch.cuda.synchronize()
+        left[alloc] = torch.cuda.memory_allocated() - base
+        del sysm
+    assert held["torch"] - held[None] > 4 << 20, held          # the hierarchy and Krylov vectors
+    assert left["torch"] == left[None], left                    # all of it given back at cbs_destroy
+    assert np.array_equal(res["torch"][0], res[None][0]) and np.array_equal(res["torch"][1], res[None][1])
+    assert res["torch"][2] == res[None][2]
 
 
 def test_ilu0_vcycle_on_a_graph_with_triangles():
