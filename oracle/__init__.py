@@ -25,6 +25,8 @@ OK, NOT_CONVERGED = 0, 1
 ERR_ARG, ERR_PATTERN, ERR_SINGULAR, ERR_BREAKDOWN = -1, -2, -3, -4
 
 PREC_NONE, PREC_BJACOBI, PREC_AMG, PREC_SGS = 0, 1, 2, 3
+# the AMG V-cycle in FP32 emulation (row-scaled or unscaled sweeps), with an AMG handle
+PREC_AMG_FP32, PREC_AMG_FP32_UNSCALED = 4, 5
 SMOOTH_BJACOBI, SMOOTH_DILU, SMOOTH_SGS, SMOOTH_ILU0 = 0, 1, 2, 3
 
 
@@ -90,6 +92,7 @@ def _declare(L):
         "orc_amg_levels": (ci, [vp]),
         "orc_amg_level_info": (None, [vp, ci, C.POINTER(ci), C.POINTER(cl)]),
         "orc_amg_apply": (None, [vp, _f64p, _f64p]),
+        "orc_amg_apply_fp32": (ci, [vp, _f64p, _f64p, ci]),
         "orc_bicgstab": (ci, [ci, ci, _i32p, _i32p, _f64p, ci, vp, _f64p, _f64p, cd, ci,
                               C.POINTER(ci), C.POINTER(cd)]),
         "orc_fgmres": (ci, [ci, ci, _i32p, _i32p, _f64p, ci, vp, _f64p, _f64p, cd, ci, ci,
@@ -387,6 +390,17 @@ class AMG:
     def apply(self, r):
         z = np.empty(self.A.N * self.A.n)
         lib().orc_amg_apply(self.h, _c64(r).ravel(), z)
+        return z.reshape(self.A.N, self.A.n)
+
+    def apply_fp32(self, r, scaled=True):
+        """The same V-cycle in FP32 emulation (orc_amg_apply_fp32): float
+        level values, vectors and sums, FP64 block inverses and coarsest
+        solve; ``scaled``: sweeps on the row-scaled values.  A study tool,
+        not a parity target.  Block-Jacobi hierarchies only."""
+        z = np.empty(self.A.N * self.A.n)
+        rc = lib().orc_amg_apply_fp32(self.h, _c64(r).ravel(), z, int(bool(scaled)))
+        if rc != OK:
+            raise OracleError(rc, "amg_apply_fp32")
         return z.reshape(self.A.N, self.A.n)
 
 

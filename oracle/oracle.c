@@ -746,6 +746,11 @@ typedef struct {
     double omega;
     olevel L[MAXLEV];
     double *LU; int *piv; int m;   /* coarsest level, dense LU */
+    /* FP32 emulation (orc_amg_apply_fp32), built on first use: per level
+     * the values rounded to float, the row-scaled values fl(D_i^{-1} A_ij)
+     * (diagonal blocks zero) and float work vectors */
+    int f32_ready;
+    float *fval[MAXLEV], *fsval[MAXLEV], *fb[MAXLEV], *fx[MAXLEV], *fr[MAXLEV], *fc[MAXLEV], *ft[MAXLEV];
 } oamg;
 
 static void free_level(olevel *l)
@@ -758,7 +763,11 @@ void orc_amg_free(void *h)
 {
     oamg *A = (oamg *)h;
     if (!A) return;
-    for (int l = 0; l < A->nlev; l++) free_level(&A->L[l]);
+    for (int l = 0; l < A->nlev; l++) {
+        free_level(&A->L[l]);
+        free(A->fval[l]); free(A->fsval[l]); free(A->fb[l]); free(A->fx[l]); free(A->fr[l]); free(A->fc[l]);
+        free(A->ft[l]);
+    }
     free(A->LU); free(A->piv); free(A);
 }
 
@@ -941,6 +950,154 @@ void orc_amg_apply(void *h, const double *r, double *z)
 }
 
 /* ------------------------------------------------------------------ */
+/* Mixed-precision emulation of the block-Jacobi V-cycle: the same     */
+/* cycle as vcycle() with explicit float casts, for studying how an     */
+/* FP32 hierarchy inside an FP64 Krylov loop behaves (stagnation), not  */
+/* as a parity target.  The casts follow the mixed-precision readings:  */
+/* level matrices are rounded once to float (RNE); the block inverses   */
+/* D_i^{-1} and the coarsest solve stay FP64; every vector, sum and     */
+/* update is float.  scaled = 1: the sweeps use the row-scaled blocks   */
+/* S_ij = fl(D_i^{-1} A_ij) (formed in FP64, rounded once) against      */
+/* c = fl(D^{-1} b):  x <- x + w (c - x - sum_{j != i} S_ij x_j);       */
+/* scaled = 0: x <- x + w fl(D^{-1} fl(b - A x)) with the FP32 A.        */
+/* The first sweep starts from x = 0.                                   */
+/* ------------------------------------------------------------------ */
+static void f32_prepare(oamg *A)
+{
+    int n = A->n;
+    long bs = (long)n * n;
+    for (int l = 0; l < A->nlev; l++) {
+        olevel *c = &A->L[l];
+        long nnz = c->rp[c->N], m = (long)c->N * n;
+        A->fval[l] = (float *)malloc(sizeof(float) * (nnz * bs + 1));
+        for (long k = 0; k < nnz * bs; k++) A->fval[l][k] = (float)c->val[k];
+        A->fb[l] = (float *)calloc(m + 1, sizeof(float));
+        A->fx[l] = (float *)calloc(m + 1, sizeof(float));
+        A->fr[l] = (float *)calloc(m + 1, sizeof(float));
+        A->fc[l] = (float *)calloc(m + 1, sizeof(float));
+        A->ft[l] = (float *)calloc(m + 1, sizeof(float));
+        if (!c->Dinv) continue;                       /* the coarsest level */
+        A->fsval[l] = (float *)calloc(nnz * bs + 1, sizeof(float));
+        for (int i = 0; i < c->N; i++)
+            for (int k = c->rp[i]; k < c->rp[i + 1]; k++) {
+                if (c->col[k] == i) continue;
+                const double *D = c->Dinv + (long)i * bs, *Aij = c->val + (long)k * bs;
+                for (int r = 0; r < n; r++)
+                    for (int q = 0; q < n; q++) {
+                        double s = 0.0;
+                        for (int t = 0; t < n; t++) s += D[r * n + t] * Aij[t * n + q];
+                        A->fsval[l][(long)k * bs + r * n + q] = (float)s;
+                    }
+            }
+    }
+    A->f32_ready = 1;
+}
+
+/* y = fl(D^{-1} v) per block row, the product in FP64 */
+static void f32_block_apply(int N, int n, const double *Dinv, const float *v, float *y)
+{
+    long bs = (long)n * n;
+    for (int i = 0; i < N; i++)
+        for (int r = 0; r < n; r++) {
+            double s = 0.0;
+            for (int q = 0; q < n; q++) s += Dinv[(long)i * bs + r * n + q] * (double)v[(long)i * n + q];
+            y[(long)i * n + r] = (float)s;
+        }
+}
+
+/* r = b - A x in float (FP32 values, float sums in row order) */
+static void f32_residual(int N, int n, const int *rp, const int *col, const float *val, const float *b,
+                         const float *x, float *r)
+{
+    long bs = (long)n * n;
+    for (int i = 0; i < N; i++)
+        for (int q = 0; q < n; q++) {
+            float s = 0.0f;
+            for (int k = rp[i]; k < rp[i + 1]; k++)
+                for (int t = 0; t < n; t++) s += val[(long)k * bs + q * n + t] * x[(long)col[k] * n + t];
+            r[(long)i * n + q] = b[(long)i * n + q] - s;
+        }
+}
+
+static void f32_vcycle(oamg *A, int l, int scaled)
+{
+    olevel *c = &A->L[l];
+    int n = A->n;
+    long m = (long)c->N * n, bs = (long)n * n;
+    float *b = A->fb[l], *x = A->fx[l], *r = A->fr[l], *cc = A->fc[l], *t = A->ft[l];
+    const float w = (float)A->omega;
+    if (l == A->nlev - 1) {                           /* FP64 dense solve of the float right side */
+        double *y = (double *)malloc(sizeof(double) * (m + 1));
+        for (long k = 0; k < m; k++) y[k] = (double)b[k];
+        lu_solve(A->m, A->LU, A->piv, y);
+        for (long k = 0; k < m; k++) x[k] = (float)y[k];
+        free(y);
+        return;
+    }
+    f32_block_apply(c->N, n, c->Dinv, b, cc);          /* c = fl(D^{-1} b) */
+    for (long k = 0; k < m; k++) x[k] = 0.0f;
+    int nsweep = A->nu1 + A->nu2;
+    for (int s = 0; s < nsweep; s++) {
+        if (s == A->nu1) {                            /* the coarse-grid correction between the two */
+            f32_residual(c->N, n, c->rp, c->col, A->fval[l], b, x, r);
+            olevel *d = &A->L[l + 1];
+            float *bc = A->fb[l + 1];
+            for (long k = 0; k < (long)d->N * n; k++) bc[k] = 0.0f;
+            for (int i = 0; i < c->N; i++)
+                for (int q = 0; q < n; q++) bc[(long)c->agg[i] * n + q] += r[(long)i * n + q];
+            f32_vcycle(A, l + 1, scaled);
+            const float *e = A->fx[l + 1];
+            for (int i = 0; i < c->N; i++)
+                for (int q = 0; q < n; q++) x[(long)i * n + q] += e[(long)c->agg[i] * n + q];
+        }
+        if (scaled) {
+            for (int i = 0; i < c->N; i++)
+                for (int q = 0; q < n; q++) {
+                    float sx = 0.0f;
+                    for (int k = c->rp[i]; k < c->rp[i + 1]; k++) {
+                        if (c->col[k] == i) continue;
+                        for (int p = 0; p < n; p++)
+                            sx += A->fsval[l][(long)k * bs + q * n + p] * x[(long)c->col[k] * n + p];
+                    }
+                    t[(long)i * n + q] = x[(long)i * n + q] + w * (cc[(long)i * n + q] - x[(long)i * n + q] - sx);
+                }
+        } else {
+            f32_residual(c->N, n, c->rp, c->col, A->fval[l], b, x, r);
+            f32_block_apply(c->N, n, c->Dinv, r, t);
+            for (long k = 0; k < m; k++) t[k] = x[k] + w * t[k];
+        }
+        memcpy(x, t, sizeof(float) * m);
+    }
+    if (nsweep == A->nu1) {                           /* no post-smoothing: the correction still comes */
+        f32_residual(c->N, n, c->rp, c->col, A->fval[l], b, x, r);
+        olevel *d = &A->L[l + 1];
+        float *bc = A->fb[l + 1];
+        for (long k = 0; k < (long)d->N * n; k++) bc[k] = 0.0f;
+        for (int i = 0; i < c->N; i++)
+            for (int q = 0; q < n; q++) bc[(long)c->agg[i] * n + q] += r[(long)i * n + q];
+        f32_vcycle(A, l + 1, scaled);
+        const float *e = A->fx[l + 1];
+        for (int i = 0; i < c->N; i++)
+            for (int q = 0; q < n; q++) x[(long)i * n + q] += e[(long)c->agg[i] * n + q];
+    }
+}
+
+/* z = fl-emulated V-cycle of fl(r), widened to FP64.  Block-Jacobi
+ * hierarchies only (ORC_ERR_ARG for DILU, Gauss-Seidel or ILU(0) levels). */
+int orc_amg_apply_fp32(void *h, const double *r, double *z, int scaled)
+{
+    oamg *A = (oamg *)h;
+    for (int l = 0; l + 1 < A->nlev; l++)
+        if (!A->L[l].Dinv || A->L[l].rank) return ORC_ERR_ARG;
+    if (!A->f32_ready) f32_prepare(A);
+    long m = (long)A->L[0].N * A->n;
+    for (long k = 0; k < m; k++) A->fb[0][k] = (float)r[k];
+    f32_vcycle(A, 0, scaled);
+    for (long k = 0; k < m; k++) z[k] = (double)A->fx[0][k];
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Symmetric block Gauss-Seidel as the whole preconditioner: the        */
 /* GMRES + SGS configuration of the CRM runs (Sec. 4.1, Fig.            */
 /* CRM_speedup).  z = `sweeps` symmetric steps from z = 0 in the order  */
@@ -987,9 +1144,13 @@ void orc_sgs_prec_apply(void *h, const double *r, double *z)
 /* ------------------------------------------------------------------ */
 /* a12: preconditioned Krylov solvers                                  */
 /* ------------------------------------------------------------------ */
+int orc_amg_apply_fp32(void *h, const double *r, double *z, int scaled);
+
 typedef struct {
     int kind;          /* 0 identity, 1 block-Jacobi, 2 AMG V-cycle,
-                          3 symmetric Gauss-Seidel (handle in `amg`) */
+                          3 symmetric Gauss-Seidel (handle in `amg`),
+                          4 / 5 the AMG V-cycle in FP32 emulation with
+                          row-scaled / unscaled sweeps */
     int N, n;
     double *Dinv;
     void *amg;
@@ -1002,18 +1163,25 @@ static void prec_apply(const oprec *P, const double *r, double *z)
     else if (P->kind == 1) {
         for (int i = 0; i < P->N; i++) blk_mv(P->n, P->Dinv + (long)i * bs, r + (long)i * P->n, z + (long)i * P->n);
     } else if (P->kind == 3) orc_sgs_prec_apply(P->amg, r, z);
+    else if (P->kind == 4 || P->kind == 5) orc_amg_apply_fp32(P->amg, r, z, P->kind == 4);
     else orc_amg_apply(P->amg, r, z);
 }
 
 static int prec_init(oprec *P, int kind, void *amg, int N, int n, const int *rp, const int *col, const double *val)
 {
     P->kind = kind; P->N = N; P->n = n; P->Dinv = NULL; P->amg = amg;
-    if (kind < 0 || kind > 3) return ORC_ERR_ARG;
+    if (kind < 0 || kind > 5) return ORC_ERR_ARG;
     if (kind == 1) {
         P->Dinv = (double *)malloc(sizeof(double) * ((long)N * n * n + 1));
         if (diag_inverse(N, n, rp, col, val, P->Dinv)) { free(P->Dinv); P->Dinv = NULL; return ORC_ERR_SINGULAR; }
     }
-    if ((kind == 2 || kind == 3) && !amg) return ORC_ERR_ARG;
+    if (kind >= 2 && !amg) return ORC_ERR_ARG;
+    if (kind >= 4) {                   /* block-Jacobi hierarchies only */
+        oamg *H = (oamg *)amg;
+        if (H->n != n || H->L[0].N != N) return ORC_ERR_ARG;
+        for (int l = 0; l + 1 < H->nlev; l++)
+            if (!H->L[l].Dinv || H->L[l].rank) return ORC_ERR_ARG;
+    }
     if (kind == 3 && (((osgs *)amg)->N != N || ((osgs *)amg)->n != n)) return ORC_ERR_ARG;
     return ORC_OK;
 }

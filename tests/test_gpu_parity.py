@@ -326,7 +326,10 @@ def test_rap_and_vcycle_match_oracle_given_gpu_aggregates(renumber, split):
 def test_mixed_vcycle_matches_fp64_oracle_vcycle(split, pre, post, scaled):
     """The mixed-precision V-cycle (FP32 levels, block-Jacobi sweeps on row-scaled
     values, or on the FP32 values with the FP64 D^{-1}) is the oracle's FP64
-    V-cycle on the same hierarchy up to FP32 rounding."""
+    V-cycle on the same hierarchy up to FP32 rounding: within 1e-5, and no
+    further from it than four times the oracle's own FP32 emulation of the
+    same form (whose distance from the FP64 cycle is the rounding the
+    algorithm itself incurs)."""
     _say("mixed vcycle split", split, "sweeps", pre, post, "scaled", scaled)
     s = pressure_velocity(12, 10, 9, seed=5)
     A = O.from_system(s)
@@ -347,6 +350,12 @@ def test_mixed_vcycle_matches_fp64_oracle_vcycle(split, pre, post, scaled):
     zr_int = amg.apply(r[order])
     zr = np.empty_like(zr_int); zr[order] = zr_int
     _agree(z, zr, 1e-5)
+    ze_int = amg.apply_fp32(r[order], scaled=bool(scaled))
+    ze = np.empty_like(ze_int); ze[order] = ze_int
+    d_gpu, d_emu = np.linalg.norm(z - zr), np.linalg.norm(ze - zr)
+    _say("  distance from the FP64 cycle: GPU %.3e, FP32 emulation %.3e" % (d_gpu / np.linalg.norm(zr),
+                                                                          d_emu / np.linalg.norm(zr)))
+    assert 0.0 < d_emu and d_gpu <= 4.0 * d_emu, (d_gpu, d_emu)
 
 
 @pytest.mark.parametrize("renumber", [0, 1])
