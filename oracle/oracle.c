@@ -21,7 +21,10 @@
  *     Gauss-Seidel, or aggregation AMG smoothed by block Jacobi, DILU or
  *     symmetric Gauss-Seidel (the solver families named in Sec. 2.3 and used
  *     in Sec. 4.1), plus the transposed solve and the LDU gradient of
- *     L(x(A, b)).
+ *     L(x(A, b));
+ *   - an emulation of the block-Jacobi V-cycle with FP32 level values and
+ *     vectors inside the FP64 loop (the mixed-precision form the paper does
+ *     not treat), for studying that form, not as a parity target.
  *
  * Readings where the paper is silent (each also listed in the design notes):
  *   R1  upper[f] = A(lower_addr[f], upper_addr[f]);
@@ -35,7 +38,8 @@
  * aggregation heuristic (orc_match) has no unique answer: "parity unpinned"
  * for its exact output; only its properties are tested.
  *
- * Everything is FP64, sequential except for OpenMP loops over rows.
+ * Everything is FP64 (the FP32 emulation aside, which casts to float on
+ * purpose), sequential except for OpenMP loops over rows.
  */
 #include <math.h>
 #include <stdint.h>
