@@ -1342,7 +1342,7 @@ void aggregate_level(cbs_system *h, Level &L, const int32_t *sys_frozen, int32_t
     // after it, [2 passes] a spare
     const int nw_ = 2 * passes + 1;
     DArr<int32_t> words((size_t)nw_);
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, words.get(), (int64_t)nw_, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(cdiv(nw_, 64)), dim3(64), 0, st, words.get(), (int64_t)nw_, 0);
     NSWITCH(n, strength_n, N, L.rp, L.col, L.mirror, L.dslot, L.v64, L.nnzb, df.get(), w.get(), st);
     LAUNCHCHK();
     gmark("strength");
