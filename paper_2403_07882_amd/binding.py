@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -258,11 +259,17 @@ class System:
         return cls(s["N"], s["n"], s["lower_addr"], s["upper_addr"], s["diag"], s["upper"], s["lower"], **kw)
 
     def close(self):
-        if getattr(self, "h", None) is not None and self.h.value:
-            lib().cbs_destroy(self.h)
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
             self.h = None
+            lib().cbs_destroy(h)
 
-    __del__ = close
+    def __del__(self):
+        # at interpreter exit the module state (and the runtime behind an
+        # allocator callback) may already be gone; the process end frees
+        # the device memory then
+        if not sys.is_finalizing():
+            self.close()
 
     def __enter__(self):
         return self
