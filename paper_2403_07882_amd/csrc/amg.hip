@@ -800,6 +800,15 @@ __global__ void k_gather_blocks(int64_t nb, const int32_t *__restrict__ sk, cons
     }
 }
 
+// a[e] = sk[a[e]] for the non-negative entries (a slot map of the internal
+// numbering turned into one of the caller's block CSR)
+__global__ void k_compose_slots(int64_t m, const int32_t *sk, int32_t *a) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const int32_t v = a[e];
+    if (v >= 0) a[e] = sk[v];
+}
+
 // out[i'] = map[ip[i']], renamed through pos_c when given
 __global__ void k_perm_map(int32_t N, const int32_t *ip, const int32_t *map, const int32_t *pos_c, int32_t *out) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1505,7 +1514,8 @@ void level_sell(cbs_system *h, Level &L, bool mixed, int32_t *f32flag) {
     const size_t tot = (size_t)L.sell.nent * n * n;
     L.sell.v64.ensure(tot > 0 ? tot : 1);
     if (mixed) L.sell.v32.ensure(tot > 0 ? tot : 1);
-    sell_fill(n, L.sell, L.v64, L.sell.v64.get(), st, mixed ? L.sell.v32.get() : nullptr, f32flag);
+    sell_fill(n, L.sell, L.lazy_vals ? h->vals.get() : L.v64, L.sell.v64.get(), st, mixed ? L.sell.v32.get() : nullptr,
+              f32flag);
 }
 
 std::vector<int64_t> level_sys_off(cbs_system *h, Level &L) {
@@ -1531,11 +1541,12 @@ void alloc_level_vectors(cbs_system *h, Level &L, bool mixed) {
 
 }  // namespace
 
-void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv, int32_t *bad_slot) {
+void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv, int32_t *bad_slot,
+                    const int32_t *dslot) {
     Level &L = h->lev[l];
     int32_t *slot = bad_slot ? bad_slot : h->dflag.get();
     HIPCHK(hipMemsetAsync(slot, 0x7f, sizeof(int32_t), h->stream));
-    NSWITCH(h->n, blockinv_n, L.N, L.dslot, vals, Dinv, slot, h->stream);
+    NSWITCH(h->n, blockinv_n, L.N, dslot ? dslot : L.dslot, vals, Dinv, slot, h->stream);
     LAUNCHCHK();
     if (bad_slot) return;                        // the caller checks later
     const int32_t bad = read_int(h->dflag.get(), h->stream);
@@ -1666,16 +1677,18 @@ void amg_setup(cbs_system *h) {
         break;
     }
     const int nlev = (int)h->lev.size();
-    if (!reuse && o.renumber && nlev > 1) renumber_hierarchy(h, deferred);
+    auto level_uses_dilu = [&](int q) {
+        return (o.smoother == CBS_SMOOTH_DILU || o.smoother == CBS_SMOOTH_SGS || o.smoother == CBS_SMOOTH_ILU0) &&
+               (o.dilu_levels < 0 || q < o.dilu_levels) && q + 1 < nlev;
+    };
+    // a block-Jacobi level 0 keeps no values of its own in the internal
+    // numbering: its copies and inverses read the caller's block CSR
+    if (!reuse && o.renumber && nlev > 1) renumber_hierarchy(h, deferred, !level_uses_dilu(0));
     pt.mark("renumber");
 
     // sliced patterns of the solve phase: the full one of every smoothed level
     // (and level 0), the off-diagonal one of the mixed block-Jacobi levels;
     // new patterns share one read-back of their entry counts
-    auto level_uses_dilu = [&](int q) {
-        return (o.smoother == CBS_SMOOTH_DILU || o.smoother == CBS_SMOOTH_SGS || o.smoother == CBS_SMOOTH_ILU0) &&
-               (o.dilu_levels < 0 || q < o.dilu_levels) && q + 1 < nlev;
-    };
     {
         // coloured levels first get their colours: their sliced copy holds
         // each colour's rows as one run of slices
@@ -1711,6 +1724,13 @@ void amg_setup(cbs_system *h) {
             for (size_t k = k0; k < k1; ++k)
                 sell_pattern_finish(todo[k].L->rp, todo[k].L->col, *todo[k].S, cnt[k - k0], st, todo[k].od);
         }
+        // the copies of a level 0 without its own values point into the caller's block CSR
+        for (auto &t : todo)
+            if (t.L->lazy_vals && t.S->nent > 0) {
+                hipLaunchKernelGGL(k_compose_slots, dim3(cdiv(t.S->nent, 256)), dim3(256), 0, st, t.S->nent,
+                                   h->perm_sk.get(), t.S->ssrc.get());
+                LAUNCHCHK();
+            }
         pt.mark("patterns");
     }
 
@@ -1730,10 +1750,24 @@ void amg_setup(cbs_system *h) {
             dilu_factor_level(h, q);
         } else if (q + 1 < nlev) {                  // block Jacobi and Gauss-Seidel: D^{-1}
             L.Dinv.ensure((size_t)L.N * n * n);
-            blockinv_level(h, q, L.v64, L.Dinv.get(), errs.get() + 1 + q);
+            if (L.lazy_vals) blockinv_level(h, q, h->vals.get(), L.Dinv.get(), errs.get() + 1 + q, L.dslot_src.get());
+            else blockinv_level(h, q, L.v64, L.Dinv.get(), errs.get() + 1 + q);
         }
         pt.mark("smoother" + std::to_string(q));
-        if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, deferred);
+        L.scaled = mixed && o.scaled_sweeps && q + 1 < nlev && !L.dilu && !L.sgs;
+        L.scaledT = false;
+        if (L.scaled) {
+            // the full and the row-scaled off-diagonal copy in one pass over the values
+            const size_t tot = (size_t)L.sell.nent * n * n;
+            L.sell.v64.ensure(tot > 0 ? tot : 1);
+            L.sell.v32.ensure(tot > 0 ? tot : 1);
+            L.sod.v32.ensure(L.sod.nent > 0 ? (size_t)L.sod.nent * n * n : 1);
+            sell_fill_scaled(n, L.sell, L.sod, L.lazy_vals ? h->vals.get() : L.v64, L.Dinv.get(), L.sell.v64.get(),
+                             L.sell.v32.get(), L.sod.v32.get(), deferred, st);
+        } else {
+            if (q == 0 || q + 1 < nlev) level_sell(h, L, mixed, deferred);
+            L.sod = Sell();
+        }
         if (L.ilu) {
             const size_t tot = (size_t)L.sell.nent * n * n;
             L.iluS64.ensure(tot > 0 ? tot : 1);
@@ -1741,14 +1775,6 @@ void amg_setup(cbs_system *h) {
             sell_fill(n, L.sell, L.iluF.get(), L.iluS64.get(), st, mixed ? L.iluS32.get() : nullptr, deferred);
         } else {
             L.iluF.release(); L.iluS64.release(); L.iluS32.release(); L.iluS64T.release(); L.iluS32T.release();
-        }
-        L.scaled = mixed && o.scaled_sweeps && q + 1 < nlev && !L.dilu && !L.sgs;
-        L.scaledT = false;
-        if (L.scaled) {
-            L.sod.v32.ensure(L.sod.nent > 0 ? (size_t)L.sod.nent * n * n : 1);
-            sell_scale(n, L.sod, L.v64, L.Dinv.get(), L.sod.v32.get(), deferred, st);
-        } else {
-            L.sod = Sell();
         }
         alloc_level_vectors(h, L, mixed);
         pt.mark("sell" + std::to_string(q));
@@ -1835,7 +1861,13 @@ void amg_build_transposed(cbs_system *h) {
         Level &L = h->lev[q];
         L.o_v64T.ensure((size_t)L.nnzb * n * n);
         L.v64T = L.o_v64T.get();
-        NSWITCH(n, transpose_n, L.nnzb, L.mirror, L.v64, L.v64T, st);
+        // (a level 0 without its own values: A^T in the caller's slots, which
+        // its copies' slot maps point to)
+        if (L.lazy_vals) {
+            NSWITCH(n, transpose_n, L.nnzb, h->mirror.get(), h->vals.get(), L.v64T, st);
+        } else {
+            NSWITCH(n, transpose_n, L.nnzb, L.mirror, L.v64, L.v64T, st);
+        }
         if (L.sell.soff.get()) {
             const size_t tot = (size_t)L.sell.nent * n * n;
             L.sell.v64T.ensure(tot > 0 ? tot : 1);
@@ -1876,7 +1908,7 @@ void amg_build_transposed(cbs_system *h) {
 
 // Permute every level but the coarsest into the aggregation-tree order;
 // pattern errors go to the flag word `deferred`.
-void renumber_hierarchy(cbs_system *h, int32_t *deferred) {
+void renumber_hierarchy(cbs_system *h, int32_t *deferred, bool lazy0) {
     hipStream_t st = h->stream;
     const int n = h->n;
     const int nlev = (int)h->lev.size();
@@ -1909,7 +1941,8 @@ void renumber_hierarchy(cbs_system *h, int32_t *deferred) {
         const dim3 G(cdiv(N, 256)), B(256);
         DArr<int32_t> ip(N), rpn(N + 1), coln(nnz), sk(nnz), aggn(N), memn(N), rsn(N), mir(nnz), dsl(N);
         if (l == 0) gmark("alloc0");
-        DArr<double> vn((size_t)nnz * n * n);
+        const bool lazy = l == 0 && lazy0;
+        DArr<double> vn(lazy ? 0 : (size_t)nnz * n * n);
         hipLaunchKernelGGL(k_invert, G, B, 0, st, N, pos[l].get(), ip.get());
         hipLaunchKernelGGL(k_perm_len, G, B, 0, st, N, ip.get(), L.rp, rpn.get());
         LAUNCHCHK();
@@ -1920,16 +1953,25 @@ void renumber_hierarchy(cbs_system *h, int32_t *deferred) {
         else
             hipLaunchKernelGGL(k_perm_rows<32>, G, B, 0, st, N, ip.get(), pos[l].get(), L.rp, L.col, rpn.get(),
                                coln.get(), sk.get());
-        NSWITCH(n, gather_blocks_n, nnz, sk.get(), L.v64, vn.get(), st);
+        if (!lazy) {
+            NSWITCH(n, gather_blocks_n, nnz, sk.get(), L.v64, vn.get(), st);
+        }
         hipLaunchKernelGGL(k_perm_map, G, B, 0, st, N, ip.get(), L.agg.get(), pos[l + 1].get(), aggn.get());
         hipLaunchKernelGGL(k_iota, G, B, 0, st, N, memn.get());
         hipLaunchKernelGGL(k_perm_map, G, B, 0, st, N, ip.get(), L.row_sys.get(), nullptr, rsn.get());
         LANES_LAUNCH(k_mirror_search, lanes_for(N, nnz), N, N, rpn.get(), coln.get(), mir.get(), dsl.get(), deferred);
         LAUNCHCHK();
+        L.lazy_vals = lazy;
+        if (lazy) {                                    // caller slots of the internal diagonal blocks
+            L.dslot_src.alloc(N);
+            HIPCHK(hipMemcpyAsync(L.dslot_src.get(), dsl.get(), sizeof(int32_t) * N, hipMemcpyDeviceToDevice, st));
+            hipLaunchKernelGGL(k_compose_slots, G, B, 0, st, (int64_t)N, sk.get(), L.dslot_src.get());
+            LAUNCHCHK();
+        }
         if (l == 0) h->perm_sk = std::move(sk);
         L.o_rp = std::move(rpn); L.o_col = std::move(coln); L.o_v64 = std::move(vn);
         L.o_mirror = std::move(mir); L.o_dslot = std::move(dsl);
-        L.rp = L.o_rp.get(); L.col = L.o_col.get(); L.v64 = L.o_v64.get();
+        L.rp = L.o_rp.get(); L.col = L.o_col.get(); L.v64 = lazy ? nullptr : L.o_v64.get();
         L.mirror = L.o_mirror.get(); L.dslot = L.o_dslot.get();
         L.agg = std::move(aggn); L.agg_ptr = std::move(new_aptr[l]); L.agg_mem = std::move(memn);
         L.row_sys = std::move(rsn);
@@ -1940,9 +1982,26 @@ void renumber_hierarchy(cbs_system *h, int32_t *deferred) {
 }
 
 // Level-0 values in the internal numbering after a coefficient update.
+// (a level 0 without its own copy gets one here: the Galerkin product of
+// level 1 in the re-setup reads the internal numbering)
 void refresh_level0_values(cbs_system *h) {
     Level &L0 = h->lev[0];
+    if (L0.lazy_vals) {
+        L0.o_v64.ensure((size_t)h->nnzb * h->n * h->n);
+        L0.v64 = L0.o_v64.get();
+    }
     NSWITCH(h->n, gather_blocks_n, h->nnzb, h->perm_sk.get(), h->vals.get(), L0.o_v64.get(), h->stream);
+    LAUNCHCHK();
+}
+
+void level0_values_into(cbs_system *h, double *out) {
+    Level &L0 = h->lev[0];
+    if (!L0.lazy_vals) {
+        HIPCHK(hipMemcpyAsync(out, L0.v64, sizeof(double) * (size_t)h->nnzb * h->n * h->n, hipMemcpyDeviceToDevice,
+                              h->stream));
+        return;
+    }
+    NSWITCH(h->n, gather_blocks_n, h->nnzb, h->perm_sk.get(), h->vals.get(), out, h->stream);
     LAUNCHCHK();
 }
 

@@ -653,7 +653,10 @@ int cbs_get_level(cbs_handle h, int32_t level, int32_t *n_rows, int64_t *nnzb, i
         const size_t bs = (size_t)h->n * h->n;
         if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, L.rp, sizeof(int32_t) * (L.N + 1), hipMemcpyDeviceToDevice, st));
         if (col) HIPCHK(hipMemcpyAsync(col, L.col, sizeof(int32_t) * L.nnzb, hipMemcpyDeviceToDevice, st));
-        if (vals) HIPCHK(hipMemcpyAsync(vals, L.v64, sizeof(double) * L.nnzb * bs, hipMemcpyDeviceToDevice, st));
+        if (vals) {
+            if (level == 0) level0_values_into(h, vals);
+            else HIPCHK(hipMemcpyAsync(vals, L.v64, sizeof(double) * L.nnzb * bs, hipMemcpyDeviceToDevice, st));
+        }
         if (agg && L.agg.get()) HIPCHK(hipMemcpyAsync(agg, L.agg.get(), sizeof(int32_t) * L.N, hipMemcpyDeviceToDevice, st));
         if (colour && L.colour.get())
             HIPCHK(hipMemcpyAsync(colour, L.colour.get(), sizeof(int32_t) * L.N, hipMemcpyDeviceToDevice, st));

@@ -199,6 +199,14 @@ struct Level {
     DArr<double> Einv, EinvT;
     // internal renumbering: order[i'] = row of the original numbering
     DArr<int32_t> order;
+    // level 0 without its own values in the internal numbering (a
+    // block-Jacobi level 0): its sliced copies and block inverses read the
+    // caller's block CSR (h->vals) through slot maps composed with the
+    // renumbering (the patterns' ssrc, and dslot_src for the diagonal
+    // blocks); v64 is then null, or after a values-only re-setup the
+    // internal copy the Galerkin product of level 1 reads
+    bool lazy_vals = false;
+    DArr<int32_t> dslot_src;
     // transfer to the next level
     DArr<int32_t> agg, agg_ptr, agg_mem;
     int32_t nc = 0;
@@ -371,6 +379,11 @@ void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipSt
 // from the block-CSR values; an entry FP32 cannot hold sets bit 64 of *flag
 void sell_scale(int n, const Sell &S, const double *bcsr_vals, const double *Dinv, float *out, int32_t *flag,
                 hipStream_t st);
+// sell_fill (FP64 + FP32) of the full pattern F and sell_scale of the
+// off-diagonal pattern O of the same level in one pass over the values
+// (F and O built with the same slice height, not colour-ordered)
+void sell_fill_scaled(int n, const Sell &F, const Sell &O, const double *bcsr_vals, const double *Dinv,
+                      double *f64, float *f32, float *o32, int32_t *flag, hipStream_t st);
 template <typename TX>
 void launch_restrict(int n, int32_t nc, const int32_t *agg_ptr, const int32_t *agg_mem,
                      const TX *r, TX *bc, hipStream_t st);
@@ -409,13 +422,18 @@ void launch_dilu_bwd(int n, const SellView &S, const T *val, const int32_t *colo
 // AMG setup (amg.hip)
 void amg_setup(cbs_system *h);
 void amg_build_transposed(cbs_system *h);
-void renumber_hierarchy(cbs_system *h, int32_t *deferred);
+// lazy0: keep no internal copy of the level-0 values (see Level::lazy_vals)
+void renumber_hierarchy(cbs_system *h, int32_t *deferred, bool lazy0);
+// level-0 values in the internal numbering into out[nnzb * n * n]
+void level0_values_into(cbs_system *h, double *out);
 void refresh_level0_values(cbs_system *h);
 void permute_vec(cbs_system *h, const double *in, double *out, bool to_internal);
 void spmv_user(cbs_system *h, const double *x, double *y, bool transposed);
 // block-diagonal inverses of level l; with bad_slot the first singular block
 // row is left there for the caller to check, else it is checked here
-void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv, int32_t *bad_slot = nullptr);
+// (dslot: slots of the diagonal blocks in vals, default the level's own)
+void blockinv_level(cbs_system *h, int l, const double *vals, double *Dinv, int32_t *bad_slot = nullptr,
+                    const int32_t *dslot = nullptr);
 
 // Krylov (krylov.hip)
 int krylov_solve(cbs_system *h, const double *b, double *x, cbs_stats *st, bool transposed);

@@ -694,6 +694,100 @@ __global__ __launch_bounds__(64 * n) void k_sell_scaled(int32_t N, int32_t nslic
     if (bad) atomicOr(flag, 64);
 }
 
+// Both sliced copies of a mixed block-Jacobi level in one pass over its
+// FP64 block-CSR values: the full pattern F (FP64 values and their FP32
+// rounding, as k_sell_vals) and the off-diagonal pattern O (FP32 of
+// Dinv_i A_ij, as k_sell_scaled).  F and O share their slices (the same
+// rows at the same positions); every row holds its diagonal block, so
+// O's slot of a block is F's slot less one once the diagonal has passed,
+// and F's padding slots past a row's end cover O's.  One thread per (slice
+// row, r), kScaleU entries staged in LDS at a time.
+template <int n>
+__global__ __launch_bounds__(64 * n) void k_sell_fill_scaled(int32_t N, int32_t nslices, int32_t lc,
+                                                             const int32_t *__restrict__ fsoff,
+                                                             const int32_t *__restrict__ fsw,
+                                                             const int32_t *__restrict__ fscol,
+                                                             const int32_t *__restrict__ fssrc,
+                                                             const int32_t *__restrict__ osoff,
+                                                             const int32_t *__restrict__ osw,
+                                                             const double *__restrict__ bvals,
+                                                             const double *__restrict__ Dinv,
+                                                             double *__restrict__ f64, float *__restrict__ f32,
+                                                             float *__restrict__ o32, int32_t *flag) {
+    constexpr int nn = n * n;
+    constexpr int U = kScaleU;
+    __shared__ double sa[U * 64 * nn];
+    __shared__ int32_t wmax;
+    const int t = threadIdx.x, lr = t / n, r = t - lr * n;
+    const int64_t npos = (int64_t)nslices << lc;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lr;
+    const bool act = i < npos;
+    const int32_t sl = act ? (int32_t)(i >> lc) : 0;
+    const int64_t ii = act ? i - ((int64_t)sl << lc) : 0;
+    const int64_t fbase = act ? (int64_t)fsoff[sl] + ii : 0, obase = act ? (int64_t)osoff[sl] + ii : 0;
+    const int32_t w = act ? fsw[sl] : 0, wo = act ? osw[sl] : 0;
+    if (t == 0) wmax = 0;
+    __syncthreads();
+    if (r == 0 && w > 0) atomicMax(&wmax, w);
+    double d[n];
+#pragma unroll
+    for (int q = 0; q < n; ++q) d[q] = (act && i < N) ? Dinv[i * nn + r * n + q] : 0.0;
+    __syncthreads();
+    const int32_t W = wmax;
+    bool bad = false;
+    int32_t passed = 0;                                // 1 once this row's diagonal block has gone by
+    for (int32_t k0 = 0; k0 < W; k0 += U) {
+        int32_t src[U], cj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = fbase + ((int64_t)(k0 + u) << lc);
+            const bool in = k0 + u < w && i < N;
+            src[u] = in ? fssrc[e] : -1;
+            cj[u] = in ? fscol[e] : -1;
+        }
+        double a[U][n];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double *p = bvals + (int64_t)(src[u] < 0 ? 0 : src[u]) * nn + r * n;
+#pragma unroll
+            for (int c = 0; c < n; ++c) a[u][c] = src[u] < 0 ? 0.0 : p[c];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < n; ++c) sa[(u * 64 + lr) * nn + r * n + c] = a[u][c];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k0 + u >= w) continue;
+            const int64_t e = fbase + ((int64_t)(k0 + u) << lc);
+#pragma unroll
+            for (int c = 0; c < n; ++c) {
+                f64[e * nn + r * n + c] = a[u][c];
+                const float v = (float)a[u][c];
+                f32[e * nn + r * n + c] = v;
+                bad = bad || !isfinite(v);
+            }
+            const bool diag = cj[u] == (int32_t)i;
+            if (diag) { passed = 1; continue; }
+            const int32_t jo = k0 + u - passed;
+            if (jo >= wo) continue;
+            const int64_t eo = obase + ((int64_t)jo << lc);
+#pragma unroll
+            for (int c = 0; c < n; ++c) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < n; ++q) acc += d[q] * sa[(u * 64 + lr) * nn + q * n + c];
+                const float v = (float)acc;
+                o32[eo * nn + r * n + c] = v;
+                bad = bad || !isfinite(v);
+            }
+        }
+        __syncthreads();
+    }
+    if (bad) atomicOr(flag, 64);
+}
+
 template <typename TX>
 __global__ void k_restrict(int32_t nc, int n, const int32_t *__restrict__ aptr, const int32_t *__restrict__ amem,
                            const TX *__restrict__ r, TX *__restrict__ bc) {
@@ -865,6 +959,28 @@ void sell_fill(int n, const Sell &S, const double *bcsr_vals, double *out, hipSt
         case 5: SV(5); break;
     }
 #undef SV
+    LAUNCHCHK();
+}
+
+void sell_fill_scaled(int n, const Sell &F, const Sell &O, const double *bcsr_vals, const double *Dinv,
+                      double *f64, float *f32, float *o32, int32_t *flag, hipStream_t st) {
+    if (F.N <= 0) return;
+    if (F.lc != O.lc || F.nslices != O.nslices || F.prow.get() || O.prow.get())
+        cbs_throw(CBS_ERR_ARG, "sliced copies do not share their slices");
+    const int64_t npos = (int64_t)F.nslices << F.lc;
+    const dim3 g(cdiv(npos, 64));
+#define FS_N(NN)                                                                                               \
+    hipLaunchKernelGGL(k_sell_fill_scaled<NN>, g, dim3(64 * NN), 0, st, F.N, F.nslices, F.lc, F.soff.get(),     \
+                       F.sw.get(), F.scol.get(), F.ssrc.get(), O.soff.get(), O.sw.get(), bcsr_vals, Dinv, f64, \
+                       f32, o32, flag)
+    switch (n) {
+        case 1: FS_N(1); break;
+        case 2: FS_N(2); break;
+        case 3: FS_N(3); break;
+        case 4: FS_N(4); break;
+        case 5: FS_N(5); break;
+    }
+#undef FS_N
     LAUNCHCHK();
 }
 
