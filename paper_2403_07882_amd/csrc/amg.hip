@@ -24,7 +24,10 @@ void build_row_sys(cbs_system *h, Level &L0);
 
 namespace {
 
-constexpr int kRapWaves = 4;
+// wavefronts per workgroup of the Galerkin kernel: each takes a coarse row
+// of its own, and one per workgroup keeps the workgroup barriers from
+// making each wait for the slowest row (4 per workgroup was 10-20% slower)
+constexpr int kRapWaves = 1;
 constexpr int kRapCap = 4096;     // largest candidate list a coarse row may gather
 // Coarse rows with at most kRapSmall candidates (pairwise aggregates of short
 // rows) take a thread each instead of a wavefront: kRapSmallTpb threads per
