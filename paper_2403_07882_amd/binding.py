@@ -264,11 +264,11 @@ class System:
             self.h = None
             lib().cbs_destroy(h)
 
-    def __del__(self):
-        # at interpreter exit the module state (and the runtime behind an
-        # allocator callback) may already be gone; the process end frees
-        # the device memory then
-        if not sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter exit the module state (this module's globals, and
+        # the runtime behind an allocator callback) may already be gone, so
+        # the check is bound here; the process end frees the device memory
+        if getattr(self, "h", None) is not None and not _finalizing():
             self.close()
 
     def __enter__(self):

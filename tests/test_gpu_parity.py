@@ -6,6 +6,8 @@ oracle's arithmetic; solves to the relative residual 1e-8 (recomputed by the
 oracle's own SpMV on the GPU's x) and a solution error <= 1e-6 relative to
 an oracle solve at 1e-12.
 """
+import os
+import subprocess
 import sys
 
 import numpy as np
@@ -18,6 +20,8 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 import paper_2403_07882_amd as P  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _say(*a):
@@ -793,6 +797,25 @@ def test_torch_allocator_serves_the_library():
     assert left["torch"] == left[None], left                    # all of it given back at cbs_destroy
     assert np.array_equal(res["torch"][0], res[None][0]) and np.array_equal(res["torch"][1], res[None][1])
     assert res["torch"][2] == res[None][2]
+
+
+def test_open_systems_at_interpreter_exit():
+    """A System left open (with either allocator) when the interpreter exits
+    is released by the process end: no error from its finaliser."""
+    _say("open systems at exit")
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_2403_07882_amd as P\n"
+        "from workloads import pressure_velocity\n"
+        "s = pressure_velocity(6, 5, 4, seed=3)\n"
+        "keep = [P.System.from_dict(s), P.System.from_dict(s, allocator='torch')]\n"
+        "for k in keep: k.setup(precond=P.PREC_AMG)\n"
+        "x, st = keep[1].solve(s['b'])\n"
+        "print('solved', st['status'])\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "solved 0" in r.stdout
+    assert "Exception ignored" not in r.stderr and "Traceback" not in r.stderr, r.stderr[-2000:]
 
 
 def test_ilu0_vcycle_on_a_graph_with_triangles():
