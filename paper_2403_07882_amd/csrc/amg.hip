@@ -36,6 +36,11 @@ constexpr int kRapSmall = 48;
 constexpr int kRapSmallCount = 64;   // the counting pass keeps no values: longer lists fit
 constexpr int32_t kRapSmallRows = 16384;
 constexpr int kRapSmallTpb = 64;
+// slots per thread of the first launch, counting pass and fill pass (the
+// fill keeps a sum beside each column: 12 bytes a slot against 4)
+constexpr int kRapCountSlots = 32;
+constexpr int kRapSlots = 24;
+constexpr int kRapListGroups = 1024;   // workgroups of a launch over queued rows
 constexpr int kMatchRounds = 4;
 
 // ------------------------------------------------------------------ block inverse
@@ -550,11 +555,17 @@ __global__ __launch_bounds__(64 * kRapWaves) void k_rap(int32_t nc, int32_t cap,
     }
 }
 
-// Thread-per-coarse-row Galerkin product for short candidate lists (at most
-// CAP).  The distinct coarse columns are kept sorted (slot layout
-// [slot][thread] in LDS); PASS 0 counts them, PASS 1 (scalar values only,
-// n = 1) writes the columns and the sums, added in candidate order like k_rap.
-template <int PASS, int CAP>
+// Thread-per-coarse-row Galerkin product for short candidate lists.  The
+// distinct coarse columns are kept sorted (slot layout [slot][thread] in
+// LDS); PASS 0 counts them, PASS 1 (scalar values only, n = 1) writes the
+// columns and the sums, added in candidate order like k_rap.  The slots per
+// thread set the LDS of a workgroup and so how many fit on a CU.  Most rows
+// need few: with LIST false the kernel takes every row with CAP slots and
+// leaves a row that needs more to a LIST launch with more slots, which runs
+// over the rows queued in longq (*nlong of them).  PASS 0 queues a row at its
+// (CAP+1)-th distinct column; PASS 1 skips the rows whose count exceeds CAP,
+// which k_queue_long queued from the counts.
+template <int PASS, int CAP, bool LIST>
 __global__ __launch_bounds__(kRapSmallTpb) void k_rap_small(int32_t nc, const int32_t *__restrict__ aptr,
                                                             const int32_t *__restrict__ amem,
                                                             const int32_t *__restrict__ rp,
@@ -562,41 +573,52 @@ __global__ __launch_bounds__(kRapSmallTpb) void k_rap_small(int32_t nc, const in
                                                             const double *__restrict__ w,
                                                             const int32_t *__restrict__ agg, int32_t *cnt,
                                                             const int32_t *__restrict__ rpc, int32_t *colc,
-                                                            double *wc) {
+                                                            double *wc, int32_t *longq, int32_t *nlong) {
     __shared__ int32_t sJ[CAP * kRapSmallTpb];
     __shared__ double sS[PASS ? CAP * kRapSmallTpb : 1];
     const int t = threadIdx.x;
-    const int32_t I = blockIdx.x * kRapSmallTpb + t;
-    if (I >= nc) return;
-    int nd = 0;
-    for (int32_t m = aptr[I]; m < aptr[I + 1]; ++m) {
-        const int32_t i = amem[m];
-        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-            const int32_t J = agg[col[k]];
-            int p = 0;
-            while (p < nd && sJ[p * kRapSmallTpb + t] < J) ++p;
-            if (p < nd && sJ[p * kRapSmallTpb + t] == J) {
-                if (PASS) sS[p * kRapSmallTpb + t] += w[k];
-                continue;
+    const int32_t rows = LIST ? *nlong : nc;
+    for (int32_t q = blockIdx.x * kRapSmallTpb + t; q < rows; q += gridDim.x * kRapSmallTpb) {
+        const int32_t I = LIST ? longq[q] : q;
+        if (PASS == 1 && !LIST && rpc[I + 1] - rpc[I] > CAP) continue;
+        int nd = 0;
+        bool over = false;
+        for (int32_t m = aptr[I]; m < aptr[I + 1] && !over; ++m) {
+            const int32_t i = amem[m];
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const int32_t J = agg[col[k]];
+                int p = 0;
+                while (p < nd && sJ[p * kRapSmallTpb + t] < J) ++p;
+                if (p < nd && sJ[p * kRapSmallTpb + t] == J) {
+                    if (PASS) sS[p * kRapSmallTpb + t] += w[k];
+                    continue;
+                }
+                if (PASS == 0 && !LIST && nd == CAP) { over = true; break; }
+                for (int r = nd; r > p; --r) {
+                    sJ[r * kRapSmallTpb + t] = sJ[(r - 1) * kRapSmallTpb + t];
+                    if (PASS) sS[r * kRapSmallTpb + t] = sS[(r - 1) * kRapSmallTpb + t];
+                }
+                sJ[p * kRapSmallTpb + t] = J;
+                if (PASS) sS[p * kRapSmallTpb + t] = w[k];
+                ++nd;
             }
-            for (int q = nd; q > p; --q) {
-                sJ[q * kRapSmallTpb + t] = sJ[(q - 1) * kRapSmallTpb + t];
-                if (PASS) sS[q * kRapSmallTpb + t] = sS[(q - 1) * kRapSmallTpb + t];
-            }
-            sJ[p * kRapSmallTpb + t] = J;
-            if (PASS) sS[p * kRapSmallTpb + t] = w[k];
-            ++nd;
+        }
+        if (PASS == 0) {
+            if (over) longq[atomicAdd(nlong, 1)] = I;
+            else cnt[I] = nd;
+            continue;
+        }
+        const int32_t base = rpc[I];
+        for (int d = 0; d < nd; ++d) {
+            colc[base + d] = sJ[d * kRapSmallTpb + t];
+            wc[base + d] = sS[d * kRapSmallTpb + t];
         }
     }
-    if (PASS == 0) {
-        cnt[I] = nd;
-        return;
-    }
-    const int32_t base = rpc[I];
-    for (int d = 0; d < nd; ++d) {
-        colc[base + d] = sJ[d * kRapSmallTpb + t];
-        wc[base + d] = sS[d * kRapSmallTpb + t];
-    }
+}
+
+__global__ void k_queue_long(int32_t nc, const int32_t *rpc, int32_t cap, int32_t *longq, int32_t *nlong) {
+    const int32_t I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < nc && rpc[I + 1] - rpc[I] > cap) longq[atomicAdd(nlong, 1)] = I;
 }
 
 __device__ inline int32_t bsearch_col(const int32_t *col, int32_t lo, int32_t hi, int32_t j) {
@@ -709,6 +731,94 @@ __global__ __launch_bounds__(256) void k_coarse_inverse(const int32_t *rp, const
     for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
         const int r = (int)(e / m), c = (int)(e % m);
         invT[off[s] + (int64_t)c * m + r] = x[e];
+    }
+}
+
+// The same Gauss-Jordan elimination with the augmented matrix [A | I] in LDS
+// (row r at r * W, W = 2m + 1: the odd stride keeps a column's entries in
+// different banks), for systems whose m fits.  One wavefront finds each
+// pivot: the largest |a_rk| over rows r >= k, the first such row on ties
+// (the serial scan's choice; NaN entries below the diagonal are passed over,
+// a NaN diagonal makes the matrix singular).  Columns of A left of the pivot
+// are dead once eliminated and are not updated, so each step is one pass
+// that swaps and scales the pivot row, then one that eliminates the other
+// rows; the inverse is the same as the global-memory kernel's.
+template <int n>
+__global__ __launch_bounds__(256) void k_coarse_inverse_lds(const int32_t *rp, const int32_t *col, const double *val,
+                                                            const int64_t *roff_blk, const int64_t *off,
+                                                            const int32_t *msz, double *inv, double *invT,
+                                                            int32_t *flag) {
+    extern __shared__ double ci_lds[];
+    const int s = blockIdx.x;
+    const int m = msz[s], W = 2 * m + 1;
+    const int64_t r0 = roff_blk[s];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    constexpr int nw = 4;                          // wavefronts of the workgroup
+    __shared__ int piv_row;
+    __shared__ double piv_abs, piv_d;
+    for (int e = t; e < m * W; e += blockDim.x) {
+        const int r = e / W, j = e - r * W;
+        ci_lds[e] = (j == m + r) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int nb = m / n;
+    for (int bi = t; bi < nb; bi += blockDim.x) {
+        const int64_t i = r0 + bi;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int bj = (int)(col[k] - r0);
+            for (int r = 0; r < n; ++r)
+                for (int c = 0; c < n; ++c)
+                    ci_lds[(bi * n + r) * W + bj * n + c] = val[(int64_t)k * n * n + r * n + c];
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < m; ++k) {
+        if (wv == 0) {
+            double bv = -1.0;
+            int br = m;
+            for (int r = k + lane; r < m; r += 64) {
+                const double v = fabs(ci_lds[r * W + k]);
+                if (v > bv) { bv = v; br = r; }     // NaN is never greater
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o, 64);
+                const int orow = __shfl_xor(br, o, 64);
+                if (ov > bv || (ov == bv && orow < br)) { bv = ov; br = orow; }
+            }
+            if (lane == 0) {
+                const double dk = ci_lds[k * W + k];
+                piv_abs = dk != dk ? dk : bv;
+                piv_row = br < m ? br : k;
+                piv_d = ci_lds[(br < m ? br : k) * W + k];
+            }
+        }
+        __syncthreads();
+        const double pa = piv_abs;
+        if (!(pa > 0.0) || !isfinite(pa)) {        // the same value in every thread
+            if (t == 0) atomicOr(flag, 32);
+            return;
+        }
+        const int p = piv_row;
+        const double d = piv_d;
+        for (int j = k + t; j < 2 * m; j += blockDim.x) {
+            const double vp = ci_lds[p * W + j], vk = ci_lds[k * W + j];
+            ci_lds[k * W + j] = vp / d;
+            if (p != k) ci_lds[p * W + j] = vk;
+        }
+        __syncthreads();
+        for (int r = wv; r < m; r += nw) {
+            if (r == k) continue;
+            const double f = ci_lds[r * W + k];
+            for (int j = k + 1 + lane; j < 2 * m; j += 64) ci_lds[r * W + j] -= f * ci_lds[k * W + j];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < m * m; e += blockDim.x) {
+        const int r = e / m, c = e - r * m;
+        const double v = ci_lds[r * W + m + c];
+        inv[off[s] + e] = v;
+        invT[off[s] + (int64_t)c * m + r] = v;
     }
 }
 
@@ -1194,12 +1304,21 @@ void gather_blocks_n(int64_t nb, const int32_t *sk, const double *in, double *ou
     const int64_t tot = nb * (nn / V);
     if (tot > 0) hipLaunchKernelGGL(k_gather_blocks<n>, dim3(cdiv(tot, 256)), dim3(256), 0, st, nb, sk, in, out);
 }
+// lds > 0: the augmented matrices of every system fit in that much LDS
 template <int n>
 void coarse_inverse_n(int32_t n_sys, const int32_t *rp, const int32_t *col, const double *val, const int64_t *roffb,
                       const int64_t *off, const int32_t *msz, double *work, double *inv, double *invT, int32_t *flag,
-                      hipStream_t st) {
-    hipLaunchKernelGGL(k_coarse_inverse<n>, dim3(n_sys), dim3(256), 0, st, rp, col, val, roffb, off, msz, work, inv,
-                       invT, flag);
+                      size_t lds, hipStream_t st) {
+    if (lds > 0) {
+        if (lds > 64 * 1024)
+            HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_coarse_inverse_lds<n>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_coarse_inverse_lds<n>, dim3(n_sys), dim3(256), lds, st, rp, col, val, roffb, off, msz,
+                           inv, invT, flag);
+    } else {
+        hipLaunchKernelGGL(k_coarse_inverse<n>, dim3(n_sys), dim3(256), 0, st, rp, col, val, roffb, off, msz, work,
+                           inv, invT, flag);
+    }
 }
 
 struct Graph {
@@ -1297,12 +1416,27 @@ int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, con
     const bool small = many && maxc <= kRapSmall, small_count = many && maxc <= kRapSmallCount;
     const dim3 gs(cdiv(nc, kRapSmallTpb)), bs(kRapSmallTpb);
     int32_t nz = -1;
+    // every row first takes the first launch's slots; when some row may need
+    // more, the rows that do are queued for a second launch with the
+    // kernel's limit (nlong[0]: rows of the counting pass, nlong[1]: of the
+    // fill pass; both use longq, one after the other)
+    const bool split_count = maxc > kRapCountSlots, split_fill = maxc > kRapSlots;
+    const dim3 gl(std::min<int32_t>(cdiv(nc, kRapSmallTpb), kRapListGroups));
+    DArr<int32_t> longq, nlong;
+    if ((split_count || split_fill) && small_count && nc > 0) {
+        longq.alloc(nc);
+        nlong.alloc(2);
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, nlong.get(), (int64_t)2, 0);
+    }
     if (pattern) {
         rpc.alloc(nc + 1);
-        if (small_count && nc > 0)
-            hipLaunchKernelGGL((k_rap_small<0, kRapSmallCount>), gs, bs, 0, st, nc, aptr, amem, rp, col, nullptr, agg,
-                               rpc.get(), nullptr, nullptr, nullptr);
-        else
+        if (small_count && nc > 0) {
+            hipLaunchKernelGGL((k_rap_small<0, kRapCountSlots, false>), gs, bs, 0, st, nc, aptr, amem, rp, col,
+                               nullptr, agg, rpc.get(), nullptr, nullptr, nullptr, longq.get(), nlong.get());
+            if (split_count)
+                hipLaunchKernelGGL((k_rap_small<0, kRapSmallCount, true>), gl, bs, 0, st, nc, aptr, amem, rp, col,
+                                   nullptr, agg, rpc.get(), nullptr, nullptr, nullptr, longq.get(), nlong.get());
+        } else
             NSWITCH(n_blk, rap_n, 0, nc, cap, aptr, amem, rp, col, val, agg, rpc.get(), nullptr, nullptr, nullptr,
                     flag, st);
         LAUNCHCHK();
@@ -1323,10 +1457,18 @@ int32_t rap_build(cbs_system *h, int n_blk, int32_t nc, const int32_t *aptr, con
     }
     // the fill pass visits the candidates the counting pass (or the first
     // build of this pattern) already fitted into cap, so it cannot overflow
-    if (small && n_blk == 1 && nc > 0)
-        hipLaunchKernelGGL((k_rap_small<1, kRapSmall>), gs, bs, 0, st, nc, aptr, amem, rp, col, val, agg, nullptr,
-                           rpc.get(), colc.get(), valc.get());
-    else
+    // (the small fill follows the small count of this call)
+    if (small && small_count && pattern && n_blk == 1 && nc > 0) {
+        int32_t *nlong_fill = nlong.get() ? nlong.get() + 1 : nullptr;
+        if (split_fill)
+            hipLaunchKernelGGL(k_queue_long, dim3(cdiv(nc, 256)), dim3(256), 0, st, nc, rpc.get(), kRapSlots,
+                               longq.get(), nlong_fill);
+        hipLaunchKernelGGL((k_rap_small<1, kRapSlots, false>), gs, bs, 0, st, nc, aptr, amem, rp, col, val, agg,
+                           nullptr, rpc.get(), colc.get(), valc.get(), longq.get(), nlong_fill);
+        if (split_fill)
+            hipLaunchKernelGGL((k_rap_small<1, kRapSmall, true>), gl, bs, 0, st, nc, aptr, amem, rp, col, val, agg,
+                               nullptr, rpc.get(), colc.get(), valc.get(), longq.get(), nlong_fill);
+    } else
         NSWITCH(n_blk, rap_n, 1, nc, cap, aptr, amem, rp, col, val, agg, nullptr, rpc.get(), colc.get(), valc.get(),
                 flag, st);
     LAUNCHCHK();
@@ -1829,13 +1971,17 @@ void amg_setup(cbs_system *h) {
     C.invT.ensure(off[h->n_sys] > 0 ? off[h->n_sys] : 1);
     C.off.ensure(h->n_sys + 1); C.m.ensure(h->n_sys); C.roff.ensure(h->n_sys);
     DArr<int64_t> droffb(h->n_sys);
-    DArr<double> work(off[h->n_sys] > 0 ? off[h->n_sys] : 1);
+    // [A | I] of the largest system in LDS (beside the kernel's few static
+    // words), else the elimination runs in global memory
+    const size_t ci_lds = sizeof(double) * (size_t)maxm * (2 * (size_t)maxm + 1);
+    const bool ci_in_lds = maxm > 0 && ci_lds + 1024 <= (size_t)h->lds_max;
+    DArr<double> work(ci_in_lds ? 1 : (off[h->n_sys] > 0 ? off[h->n_sys] : 1));
     HIPCHK(hipMemcpyAsync(C.off.get(), off.data(), sizeof(int64_t) * (h->n_sys + 1), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(C.m.get(), msz.data(), sizeof(int32_t) * h->n_sys, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(C.roff.get(), roff.data(), sizeof(int64_t) * h->n_sys, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(droffb.get(), roffb.data(), sizeof(int64_t) * h->n_sys, hipMemcpyHostToDevice, st));
     NSWITCH(n, coarse_inverse_n, h->n_sys, Lc.rp, Lc.col, Lc.v64, droffb.get(), C.off.get(), C.m.get(), work.get(),
-            C.inv.get(), C.invT.get(), deferred, st);
+            C.inv.get(), C.invT.get(), deferred, ci_in_lds ? ci_lds : 0, st);
     LAUNCHCHK();
     // one read-back of every error the setup kernels recorded
     std::vector<int32_t> ev((size_t)nlev + 1);
