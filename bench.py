@@ -77,6 +77,9 @@ def parse():
                     help="threads per scalar row on levels under 65,536 block rows (0 = automatic)")
     ap.add_argument("--scaled-sweeps", type=int, choices=[0, 1], default=1,
                     help="mixed block-Jacobi sweeps on row-scaled FP32 values (1) or with the FP64 D^-1 (0)")
+    ap.add_argument("--w-levels", type=int, default=1,
+                    help="AMG cycle: W-cycle on this many finest levels (the next level's cycle runs twice), "
+                         "0 = V-cycle")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--assembly", action="store_true",
                     help="only the device assemblies (cbs_assemble_luo, 5x5; cbs_assemble_pu, 4x4) on an "
@@ -527,7 +530,8 @@ def main():
                   smoother={"dilu": P.SMOOTH_DILU, "sgs": P.SMOOTH_SGS, "ilu0": P.SMOOTH_ILU0}.get(args.smoother, P.SMOOTH_BJACOBI),
                   dilu_levels=args.dilu_levels, pre_sweeps=args.sweeps, post_sweeps=args.sweeps,
                   omega=args.omega, coarse_max=args.coarse_max, match_passes=args.passes,
-                  row_split=args.row_split, tail_rows=args.tail_rows, scaled_sweeps=args.scaled_sweeps)
+                  row_split=args.row_split, tail_rows=args.tail_rows, scaled_sweeps=args.scaled_sweeps,
+                  w_levels=args.w_levels)
     opt_mixed = P.default_options(precision=P.PRECISION_MIXED, **common)
     opt_reuse = P.default_options(precision=P.PRECISION_MIXED, reuse_aggregates=1, **common)
     opt_fp64 = P.default_options(precision=P.PRECISION_FP64, **common)
@@ -690,7 +694,7 @@ def main():
                    "solver": args.solver, "smoother": args.smoother, "dilu_levels": args.dilu_levels,
                    "sweeps": args.sweeps, "omega": args.omega, "coarse_max": args.coarse_max,
                    "match_passes": args.passes, "row_split": args.row_split,
-                   "tail_rows": args.tail_rows, "scaled_sweeps": args.scaled_sweeps},
+                   "tail_rows": args.tail_rows, "scaled_sweeps": args.scaled_sweeps, "w_levels": args.w_levels},
         "step_ms_median": round(float(np.median(per_step)), 3),
         "step_ms_all": [round(t, 3) for t in per_step],
         "iterations": st["iterations"],

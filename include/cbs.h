@@ -135,6 +135,17 @@ typedef struct cbs_options {
                                 once to FP32, the FP64 D^{-1} applied only by
                                 the zero-guess sweep (1), or every sweep on
                                 the FP32 A_ij with the FP64 D^{-1} (0)   [1] */
+    int32_t w_levels;        /* AMG cycle shape (Sec. 2.3 names the multigrid
+                                cycle, not its shape): on each of the
+                                w_levels finest levels the coarse correction
+                                runs the next level's cycle twice, the second
+                                run starting from the first one's result (a
+                                W-cycle on those levels); a level whose next
+                                level is the coarsest runs it once, since
+                                that level is solved exactly. 0 = V-cycle;
+                                beyond the depth: every level (W-cycle).
+                                The single-workgroup tail starts below these
+                                levels                               [0] */
 } cbs_options;
 
 /* Per-solve statistics (Algorithm amgxFoam: iterations and residuals). */

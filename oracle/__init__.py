@@ -93,6 +93,7 @@ def _declare(L):
         "orc_amg_level_info": (None, [vp, ci, C.POINTER(ci), C.POINTER(cl)]),
         "orc_amg_apply": (None, [vp, _f64p, _f64p]),
         "orc_amg_apply_fp32": (ci, [vp, _f64p, _f64p, ci]),
+        "orc_amg_set_cycle": (ci, [vp, ci]),
         "orc_bicgstab": (ci, [ci, ci, _i32p, _i32p, _f64p, ci, vp, _f64p, _f64p, cd, ci,
                               C.POINTER(ci), C.POINTER(cd)]),
         "orc_fgmres": (ci, [ci, ci, _i32p, _i32p, _f64p, ci, vp, _f64p, _f64p, cd, ci, ci,
@@ -344,11 +345,13 @@ class AMG:
     """Reference aggregation-AMG hierarchy with a V-cycle preconditioner.
 
     ``aggs``: optional list of aggregate maps (one per coarsened level) to
-    impose a hierarchy; ``ranks``: optional DILU orderings per smoothed level.
+    impose a hierarchy; ``ranks``: optional DILU orderings per smoothed level;
+    ``w_levels``: the coarse correction of each of the w_levels finest levels
+    runs the next level's cycle twice (a W-cycle there; 0 = V-cycle).
     """
 
     def __init__(self, A: BCSR, coarse_max=32, passes=2, smoother=SMOOTH_BJACOBI,
-                 nu1=1, nu2=1, omega=0.8, aggs=None, ranks=None, dilu_levels=-1):
+                 nu1=1, nu2=1, omega=0.8, aggs=None, ranks=None, dilu_levels=-1, w_levels=0):
         self._keep = []
         aggp, nag = None, 0
         if aggs is not None:
@@ -369,6 +372,9 @@ class AMG:
                                       aggp, nag, rk, nrk, int(dilu_levels))
         if not self.h:
             raise OracleError(ERR_SINGULAR, "amg_create")
+        rc = lib().orc_amg_set_cycle(self.h, int(w_levels))
+        if rc != OK:
+            raise OracleError(rc, "amg_set_cycle")
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -747,6 +747,7 @@ typedef struct {
 
 typedef struct {
     int n, nlev, smoother, nu1, nu2, dilu_levels;
+    int w_levels;            /* cycle shape: W on the w_levels finest levels */
     double omega;
     olevel L[MAXLEV];
     double *LU; int *piv; int m;   /* coarsest level, dense LU */
@@ -926,7 +927,14 @@ static void smooth(oamg *A, olevel *c, const double *b, double *x)
 
 /* x = V(b) on level l, zero initial guess:
  * pre-smooth nu1, residual, restrict, recurse, prolong, post-smooth nu2. */
-static void vcycle(oamg *A, int l, const double *b, double *x)
+/* The multigrid cycle on level l, in the textbook recursive form: smooth
+ * (from x = 0 when `zero`, else from the x given), form the residual,
+ * restrict it, correct with the next level's cycle, prolong the correction,
+ * smooth again.  The correction is one cycle of the next level (a V-cycle),
+ * or on the w_levels finest levels two, the second starting from the first
+ * one's result (a W-cycle there).  The coarsest level is solved exactly, so
+ * a level just above it always takes one. */
+static void vcycle(oamg *A, int l, const double *b, double *x, int zero)
 {
     olevel *c = &A->L[l];
     int n = A->n;
@@ -936,13 +944,14 @@ static void vcycle(oamg *A, int l, const double *b, double *x)
         lu_solve(A->m, A->LU, A->piv, x);
         return;
     }
-    memset(x, 0, sizeof(double) * m);
+    if (zero) memset(x, 0, sizeof(double) * m);
     for (int s = 0; s < A->nu1; s++) smooth(A, c, b, x);
     orc_spmv_bcsr(c->N, n, c->rp, c->col, c->val, x, c->r);
     for (long k = 0; k < m; k++) c->r[k] = b[k] - c->r[k];
     olevel *d = &A->L[l + 1];
     orc_restrict(c->N, n, c->agg, c->r, c->nc, d->b);
-    vcycle(A, l + 1, d->b, d->x);
+    vcycle(A, l + 1, d->b, d->x, 1);
+    if (l < A->w_levels && l + 2 < A->nlev) vcycle(A, l + 1, d->b, d->x, 0);
     orc_prolong_add(c->N, n, c->agg, d->x, x);
     for (int s = 0; s < A->nu2; s++) smooth(A, c, b, x);
 }
@@ -950,7 +959,15 @@ static void vcycle(oamg *A, int l, const double *b, double *x)
 void orc_amg_apply(void *h, const double *r, double *z)
 {
     oamg *A = (oamg *)h;
-    vcycle(A, 0, r, z);
+    vcycle(A, 0, r, z, 1);
+}
+
+/* Cycle shape of orc_amg_apply (0 = V-cycle, the default). */
+int orc_amg_set_cycle(void *h, int w_levels)
+{
+    if (w_levels < 0) return ORC_ERR_ARG;
+    ((oamg *)h)->w_levels = w_levels;
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------ */
@@ -1087,10 +1104,12 @@ static void f32_vcycle(oamg *A, int l, int scaled)
 }
 
 /* z = fl-emulated V-cycle of fl(r), widened to FP64.  Block-Jacobi
- * hierarchies only (ORC_ERR_ARG for DILU, Gauss-Seidel or ILU(0) levels). */
+ * hierarchies and V-cycles only (ORC_ERR_ARG for DILU, Gauss-Seidel or
+ * ILU(0) levels, or a W-cycle shape). */
 int orc_amg_apply_fp32(void *h, const double *r, double *z, int scaled)
 {
     oamg *A = (oamg *)h;
+    if (A->w_levels > 0) return ORC_ERR_ARG;       /* V-cycles only */
     for (int l = 0; l + 1 < A->nlev; l++)
         if (!A->L[l].Dinv || A->L[l].rank) return ORC_ERR_ARG;
     if (!A->f32_ready) f32_prepare(A);

@@ -272,6 +272,7 @@ void cbs_default_options(cbs_options *o) {
     o->tail_rows = 0;
     o->schedule = 0;
     o->scaled_sweeps = 1;
+    o->w_levels = 0;
 }
 
 int cbs_create_from_ldu(cbs_handle *out, int32_t n_cells, int32_t n_faces, int32_t bdim, const int32_t *lower_addr,
@@ -400,6 +401,7 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
                 CBS_ERR_ARG, "row_split must be 0, 1, 2, 4, 8 or 16");
         require(o.schedule >= 0 && o.schedule <= 6, CBS_ERR_ARG, "schedule must be in 0..6");
         require(o.scaled_sweeps == 0 || o.scaled_sweeps == 1, CBS_ERR_ARG, "scaled_sweeps must be 0 or 1");
+        require(o.w_levels >= 0, CBS_ERR_ARG, "w_levels must be >= 0");
         const bool keep = o.reuse_aggregates && h->setup_done && h->opt.precision == o.precision &&
                           h->opt.precond == o.precond && h->opt.smoother == o.smoother &&
                           h->opt.coarse_max == o.coarse_max && h->opt.match_passes == o.match_passes &&

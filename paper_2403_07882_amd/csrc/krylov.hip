@@ -555,9 +555,14 @@ SellView position_range(SellView S, int32_t p0, int32_t p1) {
 // stores into b (fused into the zero-guess sweep when there is one).  On
 // level 0 of a mixed-precision cycle, b64 is the FP64 right side (rounded
 // into b by the first kernel) and the result goes widened to x64 instead.
+//
+// zero = false (levels below the finest only, rfine null): x holds a start
+// and b the level's right side, both left by an earlier cycle on this level,
+// whose zero-guess sweep also left c = D^{-1} b behind.  This is the second
+// run of a W-cycle's coarse correction.
 template <typename T>
 void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const double *b64 = nullptr,
-            double *x64 = nullptr) {
+            double *x64 = nullptr, bool zero = true) {
     hipStream_t st = h->stream;
     const cbs_options &o = h->opt;
     const int n = h->n;
@@ -576,6 +581,15 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
     auto restrict_into_b = [&] {
         const Level &F = h->lev[l - 1];
         launch_restrict<T>(n, L.N, F.agg_ptr.get(), F.agg_mem.get(), rfine, b, st);
+    };
+    if (!zero && (rfine || b64 || l == 0 || l == nlev - 1 || l == tail_level_for(h, sizeof(T))))
+        cbs_throw(CBS_ERR_ARG, "V-cycle from a start: not on this level");
+    // the coarse correction: the next level's cycle, twice on the w_levels
+    // finest levels (the second run from the first one's result), once where
+    // the next level is the coarsest (solved exactly)
+    auto coarse = [&](T *bc, T *xc, const T *r) {
+        vcycle<T>(h, tr, l + 1, bc, xc, r);
+        if (l < o.w_levels && l + 2 < nlev) vcycle<T>(h, tr, l + 1, bc, xc, nullptr, nullptr, nullptr, false);
     };
     if (rfine && l == tail_level_for(h, sizeof(T))) {        // the rest of the cycle in one workgroup
         launch_tail<T>(h, tr, l, rfine);
@@ -598,18 +612,18 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
         const bool two = L.colour_off.size() == 3 && L.sell.cpos.size() == 3;
         if (two && nu1 >= 1) {
             // colour 0's residual is zero after the steps: only colour 1's is formed
-            smooth_two_colour<T>(h, L, tr, b, x, nu1, true, r);
+            smooth_two_colour<T>(h, L, tr, b, x, nu1, zero, r);
             launch_rows<T, T>(1, n, position_range(L.sell.view(fp32), L.sell.cpos[1], L.sell.cpos[2]), val, x, b, r,
                               nullptr, 0.0, st);
         } else {
-            if (L.sgs || nu1 == 0) launch_fill<T>(m, x, st);    // Gauss-Seidel starts from x = 0
+            if (zero && (L.sgs || nu1 == 0)) launch_fill<T>(m, x, st);    // Gauss-Seidel starts from x = 0
             for (int s = 0; s < nu1; ++s) {
-                if (L.dilu) dilu_smooth<T>(h, L, tr, b, x, s == 0);
+                if (L.dilu) dilu_smooth<T>(h, L, tr, b, x, zero && s == 0);
                 else sgs_smooth<T>(h, L, tr, b, x);
             }
             launch_rows<T, T>(1, n, L.sell.view(fp32), val, x, b, r, nullptr, 0.0, st);
         }
-        vcycle<T>(h, tr, l + 1, bc, xc, r);
+        coarse(bc, xc, r);
         launch_prolong<T>(n, L.N, L.agg.get(), xc, x, st);
         if (two) {
             smooth_two_colour<T>(h, L, tr, b, x, nu2, false, nullptr);
@@ -622,9 +636,10 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
         finish();
         return;
     }
-    const int switches = (nu1 >= 1 ? nu1 - 1 : 0) + nu2;
+    const int switches = zero ? (nu1 >= 1 ? nu1 - 1 : 0) + nu2 : nu1 + nu2;
     T *cur = (switches % 2 == 0) ? x : tmp;
     T *oth = (cur == x) ? tmp : x;
+    if (!zero && cur != x) launch_cast<T, T>(m, x, cur, st);
     // FP32 sweeps run on the row-scaled values Dinv A (D^{-T} A^T in the
     // transposed solve) against c = Dinv b, which the zero-guess sweep leaves
     // behind
@@ -640,7 +655,12 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
         else
             launch_rows<T, T>(2, n, L.sell.view(fp32), val, from, b, to, Dinv, o.omega, st, nullptr, pagg, pe, y64);
     };
-    if (nu1 >= 1) {
+    if (!zero) {
+        for (int s = 0; s < nu1; ++s) {
+            sweep(cur, oth, nullptr, nullptr, nullptr);
+            std::swap(cur, oth);
+        }
+    } else if (nu1 >= 1) {
         if (fuse_in) {
             if constexpr (fp32)
                 launch_cast_sweep0(n, L.N, b64, b, Dinv, o.omega, cur, c, st);
@@ -661,7 +681,7 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
         launch_fill<T>(m, cur, st);
     }
     launch_rows<T, T>(1, n, L.sell.view(fp32), val, cur, b, r, Dinv, o.omega, st);
-    vcycle<T>(h, tr, l + 1, bc, xc, r);
+    coarse(bc, xc, r);
     // On large levels the extra aggregate-map gathers cost more than the
     // separate prolongation pass; on small ones the saved launch wins.
     const bool fuse_pro = nu2 > 0 && L.N < kSmallLevelRows;

@@ -1145,6 +1145,7 @@ void launch_cast(int64_t m, const TA *a, TB *b, hipStream_t st) {
 template void launch_cast<double, float>(int64_t, const double *, float *, hipStream_t);
 template void launch_cast<float, double>(int64_t, const float *, double *, hipStream_t);
 template void launch_cast<double, double>(int64_t, const double *, double *, hipStream_t);
+template void launch_cast<float, float>(int64_t, const float *, float *, hipStream_t);
 
 void launch_coarse_solve(cbs_system *h, bool transposed, const void *b, void *x, bool fp32) {
     Coarse &C = h->coarse;

@@ -426,7 +426,8 @@ int tail_level_for(const cbs_system *h, size_t tsize) {
     if (nlev < 2 || h->opt.precond != CBS_PREC_AMG) return -1;
     const int32_t lim = h->opt.tail_rows == 0 ? kTailRowsDefault : h->opt.tail_rows;
     if (lim < 0) return -1;
-    for (int l = 1; l < nlev; ++l) {
+    // a level whose cycle runs twice (W-cycle) keeps its per-step kernels
+    for (int l = std::max(1, h->opt.w_levels + 1); l < nlev; ++l) {
         if (h->lev[l].N > lim || nlev - l > kTailMax) continue;
         bool dilu = false;                           // DILU and Gauss-Seidel levels keep their own kernels
         for (int q = l; q + 1 < nlev; ++q) dilu = dilu || h->lev[q].dilu || h->lev[q].sgs;

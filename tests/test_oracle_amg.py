@@ -158,3 +158,74 @@ def test_amg_hierarchy_shape_and_coarse_max():
     assert info[-1][0] <= 32
     for (N0, _), (N1, _) in zip(info, info[1:]):
         assert N1 < N0 / 2.5           # two passes of pairwise matching
+
+
+def _dense_blocks(Ad, n):
+    D = np.zeros_like(Ad)
+    for i in range(Ad.shape[0] // n):
+        D[i * n:(i + 1) * n, i * n:(i + 1) * n] = Ad[i * n:(i + 1) * n, i * n:(i + 1) * n]
+    return D
+
+
+def test_three_level_w_cycle_operator_closed_form():
+    # Textbook W-cycle on level 0 of a three-level hierarchy, V(1,1) with
+    # damped block Jacobi and an exact solve on level 2.  The level-1 cycle
+    # has error propagation E1 = S1 (I - P1 A2^{-1} P1^T A1) S1; running it
+    # twice, the second from the first one's result, leaves E1^2, so the
+    # level-0 coarse correction applies B1 = (I - E1^2) A1^{-1} and the cycle
+    # is E0 = S0 (I - P0 B1 P0^T A0) S0, M^{-1} = (I - E0) A0^{-1}.
+    s = jacobian_box(5, 4, 3, n=3, seed=7)
+    A = O.from_system(s)
+    n, w = 3, 0.7
+    agg0, nc0 = O.match(A.N, A.row_ptr, A.col, O.strength(A))
+    A1 = O.rap(A, agg0, nc0)
+    agg1, nc1 = O.match(A1.N, A1.row_ptr, A1.col, O.strength(A1))
+    assert 1 < nc1 < nc0 < A.N
+    Ad, A1d = A.dense(), A1.dense()
+    P0, P1 = _P(agg0, nc0, n), _P(agg1, nc1, n)
+    assert np.allclose(A1d, P0.T @ Ad @ P0, rtol=1e-13, atol=1e-13)
+    A2d = P1.T @ A1d @ P1
+    I0, I1 = np.eye(Ad.shape[0]), np.eye(A1d.shape[0])
+    S0 = I0 - w * np.linalg.solve(_dense_blocks(Ad, n), Ad)
+    S1 = I1 - w * np.linalg.solve(_dense_blocks(A1d, n), A1d)
+    E1 = S1 @ (I1 - P1 @ np.linalg.solve(A2d, P1.T @ A1d)) @ S1
+    A0i, A1i = np.linalg.inv(Ad), np.linalg.inv(A1d)
+    r = np.random.default_rng(5).standard_normal(Ad.shape[0])
+
+    def cycle_op(E1k):
+        B1 = (I1 - E1k) @ A1i
+        E0 = S0 @ (I0 - P0 @ B1 @ P0.T @ Ad) @ S0
+        return (I0 - E0) @ A0i
+
+    zw = O.AMG(A, nu1=1, nu2=1, omega=w, aggs=[agg0, agg1], w_levels=1).apply(r.reshape(-1, n)).ravel()
+    zv = O.AMG(A, nu1=1, nu2=1, omega=w, aggs=[agg0, agg1]).apply(r.reshape(-1, n)).ravel()
+    refw, refv = cycle_op(E1 @ E1) @ r, cycle_op(E1) @ r
+    sc = np.abs(refw).max()
+    assert np.abs(zw - refw).max() <= 1e-11 * sc
+    assert np.abs(zv - refv).max() <= 1e-11 * sc
+    assert np.abs(refw - refv).max() > 1e-3 * sc          # the two shapes differ here
+    # w_levels beyond the hierarchy changes nothing: level 1 sits above the
+    # coarsest, whose exact solve is taken once
+    z2 = O.AMG(A, nu1=1, nu2=1, omega=w, aggs=[agg0, agg1], w_levels=5).apply(r.reshape(-1, n)).ravel()
+    assert np.array_equal(z2, zw)
+
+
+def test_w_cycle_above_the_coarsest_level_is_the_v_cycle():
+    s = pressure_velocity(4, 4, 2, seed=3)
+    A = O.from_system(s)
+    agg, nc = O.match(A.N, A.row_ptr, A.col, O.strength(A))
+    r = np.random.default_rng(2).standard_normal((A.N, 4))
+    zv = O.AMG(A, nu1=2, nu2=2, omega=0.9, aggs=[agg]).apply(r)
+    zw = O.AMG(A, nu1=2, nu2=2, omega=0.9, aggs=[agg], w_levels=1).apply(r)
+    assert np.array_equal(zv, zw)
+
+
+def test_w_cycle_preconditioned_solve():
+    s = pressure_velocity(16, 16, 16, seed=0)
+    A = O.from_system(s)
+    kw = dict(coarse_max=16, passes=2, nu1=2, nu2=2, omega=0.9)
+    xv, stv = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=O.AMG(A, **kw), tol=1e-10)
+    xw, stw = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=O.AMG(A, w_levels=1, **kw), tol=1e-10)
+    assert O.relres(A, s["b"], xw) <= 1e-10
+    assert stw["iterations"] <= stv["iterations"]
+    assert O.AMG(A, w_levels=1, **kw).levels >= 3
