@@ -39,13 +39,16 @@ def seeded_normal(torch, count, dtype, dev, seed):
 # None where not measured for the current kernel code.  These counters count
 # requests from the L2 to the memory fabric, which the 256 MB Infinity Cache
 # (MALL) in front of HBM serves in part, so they bound HBM traffic from above.
-TRAFFIC_PU1M = {"sweep": 542258176, "spmv_internal": 1128992973, "spmv_caller": 1713110630}
+TRAFFIC_PU1M = {"sweep": 542250086, "sweep_l1": 228149376, "spmv_internal": 1128992973,
+                "spmv_caller": 1713110630}
 TRAFFIC_KIND = ("L2-to-memory-fabric bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated); the Infinity "
                 "Cache serves part of them, so HBM itself moves at most this much")
 # Average duration of the same kernels inside timed bench steps (rocprofv3
-# --kernel-trace of the default run, profiles/bench_pu1M_kernel_stats.md);
-# None where not measured for the current kernel code.
-IN_STEP_US_PU1M = {"sweep": 83.73, "spmv_internal": 178.97, "spmv_caller": None}
+# --kernel-trace of the default run, W-cycle on level 0,
+# profiles/bench_pu1M_kernel_stats.md); None where not measured for the
+# current kernel code.
+IN_STEP_US_PU1M = {"sweep": 84.38, "sweep_l1": 42.38, "spmv_internal": 180.80, "spmv_caller": None}
+IN_STEP_W_LEVELS = 1
 
 
 def parse():
@@ -135,10 +138,11 @@ def _host_cpu():
     return {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(), "model": model}
 
 
-def cpu_baseline(s, reps_max=3, budget_s=60.0):
+def cpu_baseline(s, w_levels=0, reps_max=3, budget_s=60.0):
     """The CPU oracle on the same system as the GPU step: LDU -> block CSR,
     reference AMG setup (block Jacobi V(2,2), omega 0.9, coarse_max 16, two
-    matching passes) and BiCGStab to 1e-8, FP64, with the OpenMP threads of
+    matching passes, the GPU step's cycle shape: W-cycle on the w_levels
+    finest levels) and BiCGStab to 1e-8, FP64, with the OpenMP threads of
     the host.  One warm-up run, then the median of up to three runs (fewer
     when three would exceed the time budget).  Also one thread: conversion,
     setup and the first 5 iterations (the full solve would take minutes)."""
@@ -152,7 +156,8 @@ def cpu_baseline(s, reps_max=3, budget_s=60.0):
         t0 = time.perf_counter()
         A = O.from_system(s)
         t1 = time.perf_counter()
-        amg = O.AMG(A, coarse_max=16, passes=2, smoother=O.SMOOTH_BJACOBI, nu1=2, nu2=2, omega=0.9)
+        amg = O.AMG(A, coarse_max=16, passes=2, smoother=O.SMOOTH_BJACOBI, nu1=2, nu2=2, omega=0.9,
+                    w_levels=w_levels)
         t2 = time.perf_counter()
         _, st = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=amg, tol=1e-8, maxit=maxit)
         t3 = time.perf_counter()
@@ -181,8 +186,9 @@ def cpu_baseline(s, reps_max=3, budget_s=60.0):
         "cores": threads,
         "kind": "oracle",
         "sample": "the whole bench system (%d cells): oracle LDU -> block CSR, reference AMG setup (block-Jacobi "
-                  "V(2,2), omega 0.9) and BiCGStab to 1e-8 in FP64 on %d OpenMP threads; one warm-up run, then the "
-                  "median of %d runs" % (s["N"], threads, reps),
+                  "V(2,2), omega 0.9, %s) and BiCGStab to 1e-8 in FP64 on %d OpenMP threads; one warm-up run, then "
+                  "the median of %d runs" % (s["N"], "W-cycle on the %d finest levels" % w_levels if w_levels
+                                             else "V-cycle", threads, reps),
         "runs_s": [round(r["total_s"], 3) for r in runs],
         "iterations": mid["iterations"],
         "phases_s": {k: round(mid[k], 3) for k in ("convert_s", "setup_s", "solve_s")},
@@ -436,50 +442,53 @@ def other_configs(args, P, torch, dev, only=None):
     the 8M-cell density-based system on a boundary-layer mesh (mixed
     AMG-FGMRES(30)), the 64-system batch (one batched mixed AMG-BiCGStab
     solve) and the 2M-cell p-U adjoint (mixed forward and transposed solves,
-    LDU gradient)."""
+    LDU gradient).  The p-U system takes the main run's cycle shape; the two
+    density-based workloads run V-cycles, since a W-cycle on level 0 leaves
+    their iteration counts unchanged (3 per batch system, 80 on the stretched
+    mesh) and only adds work."""
     from workloads import jacobian_batch, jacobian_stretched, pressure_velocity
     out = {}
     if only is None or only == "adjoint_pu_2M":
-        out.update(_adjoint_2M(P, torch, dev, pressure_velocity))
+        out.update(_adjoint_2M(P, torch, dev, pressure_velocity, args.w_levels))
     if only is None or only == "batch_64":
-        out.update(_batch_64(P, torch, dev, jacobian_batch))
+        out.update(_batch_64(P, torch, dev, jacobian_batch, 0))
     if only is None or only == "stretched_density_8M":
-        out.update(_stretched_8M(P, torch, dev, jacobian_stretched))
+        out.update(_stretched_8M(P, torch, dev, jacobian_stretched, 0))
     return out
 
 
-def _adjoint_2M(P, torch, dev, pressure_velocity):
+def _adjoint_2M(P, torch, dev, pressure_velocity, wl):
     out = {}
     t0 = time.time()
     s = pressure_velocity(200, 100, 100, seed=0)
     log("generated 2M p-U in %.1f s" % (time.time() - t0))
     out["adjoint_pu_2M"] = measure_system(
-        P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, tol=1e-8), 3, "adjoint_pu_2M",
+        P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, tol=1e-8, w_levels=wl), 3, "adjoint_pu_2M",
         "pressure-based p-U 4x4, 200x100x100 jittered renumbered hex mesh (N=%d); mixed AMG-BiCGStab to 1e-8, "
         "forward and transposed" % s["N"], transposed=True)
     return out
 
 
-def _batch_64(P, torch, dev, jacobian_batch):
+def _batch_64(P, torch, dev, jacobian_batch, wl):
     out = {}
     t0 = time.time()
     s = jacobian_batch(64, seed=0)
     log("generated the 64-system batch (%d cells) in %.1f s" % (s["N"], time.time() - t0))
     out["batch_64"] = measure_system(
-        P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, tol=1e-8), 3, "batch_64",
+        P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, tol=1e-8, w_levels=wl), 3, "batch_64",
         "64 density-based 5x5 systems, 10k-500k cells each (N=%d in total); one batched mixed AMG-BiCGStab "
         "solve to 1e-8 per system" % s["N"])
     return out
 
 
-def _stretched_8M(P, torch, dev, jacobian_stretched):
+def _stretched_8M(P, torch, dev, jacobian_stretched, wl):
     out = {}
     t0 = time.time()
     s = jacobian_stretched(200, 200, 200, seed=0)
     log("generated 8M stretched in %.1f s" % (time.time() - t0))
     out["stretched_density_8M"] = measure_system(
         P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, solver=P.SOLVER_FGMRES, restart=30,
-                                            tol=1e-8), 2, "stretched_density_8M",
+                                            tol=1e-8, w_levels=wl), 2, "stretched_density_8M",
         "density-based 5x5, 200^3 boundary-layer mesh (wall-normal ratio 1.2, aspect ratio up to 1e3, "
         "N=%d); mixed AMG-FGMRES(30) to 1e-8" % s["N"])
     return out
@@ -643,6 +652,11 @@ def main():
     sbytes = sweep_bytes(lv0["N"], lv0["nnzb"], n, 4 if sweep_fp32 else 8, dinv=not sweep_fp32)
     sweep_gbs = sbytes / (sweep_ms * 1e-3) / 1e9
     log("level-0 sweep (%s): %.1f us, %.0f GB/s" % ("fp32" if sweep_fp32 else "fp64", sweep_ms * 1e3, sweep_gbs))
+    lv1 = sysm.get_level(1)
+    sweep1, _ = level_sweep_call(P, torch, dev, sysm, n, level=1)
+    sweep1_ms = timer(sweep1)
+    sbytes1 = sweep_bytes(lv1["N"], lv1["nnzb"], n, 4 if sweep_fp32 else 8, dinv=not sweep_fp32)
+    log("level-1 sweep: %.1f us, %.0f GB/s" % (sweep1_ms * 1e3, sbytes1 / (sweep1_ms * 1e-3) / 1e9))
     byts = spmv_bytes(N, nnzb, n)
     spmv_user_ms = timer(spmv_call(P, torch, dev, sysm, N, n))
     gbs_user = byts / (spmv_user_ms * 1e-3) / 1e9
@@ -662,12 +676,14 @@ def main():
     log("1 GiB copy: %.1f us, %.0f GB/s" % (copy_ms * 1e3, copy_gbs))
     full = (nx, ny, nz) == (100, 100, 100)
 
+    sweep_desc = "FP32 row-scaled off-diagonal" if sweep_fp32 else "FP64"
+
     def kobj(name, ms, nbytes, key):
         gb = nbytes / (ms * 1e-3) / 1e9
         o = {"bound": "hbm", "kernel": name, "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(gb / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_PU1M[key] if full else None,
              "traffic_kind": TRAFFIC_KIND, "avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes": int(nbytes)}
-        us = IN_STEP_US_PU1M[key] if full else None
+        us = IN_STEP_US_PU1M[key] if full and args.w_levels == IN_STEP_W_LEVELS else None
         if us:
             o["in_step"] = {"avg_launch_us": us, "frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                             "source": "rocprofv3 kernel trace of timed bench steps"}
@@ -716,9 +732,17 @@ def main():
         "transposed_solve_ms": round(adj_ms, 3),
         "transposed_iterations": st_t.iterations,
         "gradient_us": round(grad_ms * 1e3, 2),
-        "roofline": kobj("level-0 block-Jacobi sweep, %s (k_rows, internal numbering); the kernel with the "
-                         "largest share of the step" % ("FP32 row-scaled off-diagonal" if sweep_fp32 else "FP64"),
-                         sweep_ms, sbytes, "sweep"),
+        # the W-cycle visits level 1 twice per cycle: its sweep then has the
+        # largest share of the step (17% against 15% for level 0's)
+        "roofline": (kobj("level-1 block-Jacobi sweep, %s (k_rows, %d block rows, %d blocks); the kernel launch "
+                          "with the largest share of the step" % (sweep_desc, lv1["N"], lv1["nnzb"]),
+                          sweep1_ms, sbytes1, "sweep_l1") if args.w_levels >= 1 else
+                     kobj("level-0 block-Jacobi sweep, %s (k_rows, internal numbering); the kernel launch with the "
+                          "largest share of the step" % sweep_desc, sweep_ms, sbytes, "sweep")),
+        ("level0_sweep" if args.w_levels >= 1 else "level1_sweep"):
+            (kobj("level-0 block-Jacobi sweep, %s (k_rows, internal numbering)" % sweep_desc, sweep_ms, sbytes,
+                  "sweep") if args.w_levels >= 1 else
+             kobj("level-1 block-Jacobi sweep, %s (k_rows)" % sweep_desc, sweep1_ms, sbytes1, "sweep_l1")),
         "spmv_fp64": kobj("block SpMV FP64 (k_rows mode 0), internal numbering", spmv_ms, byts, "spmv_internal"),
         "spmv_fp64_caller_numbering": kobj("block SpMV FP64 (k_rows mode 0), caller's random numbering",
                                            spmv_user_ms, byts, "spmv_caller"),
@@ -731,7 +755,7 @@ def main():
         out["other_configs"] = other_configs(args, P, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline on the bench system")
-        out["cpu_baseline"] = cpu_baseline(s_host)
+        out["cpu_baseline"] = cpu_baseline(s_host, args.w_levels)
     print(json.dumps(out), flush=True)
 
 
