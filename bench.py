@@ -77,7 +77,7 @@ def parse():
                     help="V-cycle tail in one workgroup from levels of at most this many block rows "
                          "(0 = library default, -1 = off)")
     ap.add_argument("--row-split", type=int, default=0,
-                    help="threads per scalar row on levels under 65,536 block rows (0 = automatic)")
+                    help="threads per scalar row on levels under 32,768 block rows (0 = automatic)")
     ap.add_argument("--scaled-sweeps", type=int, choices=[0, 1], default=1,
                     help="mixed block-Jacobi sweeps on row-scaled FP32 values (1) or with the FP64 D^-1 (0)")
     ap.add_argument("--w-levels", type=int, default=1,

@@ -112,7 +112,7 @@ typedef struct cbs_options {
                                 levels use it, coarser ones damped block
                                 Jacobi; < 0 = every level            [2] */
     int32_t row_split;       /* block-row kernels on levels of fewer than
-                                65,536 block rows: threads that share one
+                                32,768 block rows: threads that share one
                                 scalar row (1, 2, 4, 8 or 16); 0 = chosen from
                                 the level's mean row length. Changes only the
                                 order of the row sums                [0] */

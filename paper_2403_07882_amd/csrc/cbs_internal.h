@@ -105,6 +105,10 @@ constexpr int kCoarseSlice = 8;
 // block-row kernels split rows over several threads, and their first
 // post-smoothing sweep absorbs the prolongation.
 constexpr int32_t kSmallLevelRows = 65536;
+// levels below this many block rows split each scalar row over several
+// threads (k_rows_split); larger ones, where one thread per scalar row
+// already fills the chip, keep k_rows
+constexpr int32_t kSplitLevelRows = 32768;
 
 // V-cycle tail (tail.hip): default block-row limit of its first level, and the
 // most levels (coarsest included) it takes

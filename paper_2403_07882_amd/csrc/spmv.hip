@@ -1272,12 +1272,14 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int32_t, int64_t, int, bool>, Sched> g_tune_cache;
 }  // namespace
 
-// Levels of fewer than kSmallLevelRows block rows split each row over several
+// Levels of fewer than kSplitLevelRows block rows split each row over several
 // threads; automatic choice from the mean row length (nblocks / N, stored
 // blocks only): the largest power of two (at most 16) that still leaves every
-// thread about three blocks.
+// thread about three blocks.  (Level 2 of the 1M-cell p-U system, 47,807
+// rows, runs its sweep in 13.1 us with one thread per scalar row against
+// 14.1 us split four ways.)
 int8_t row_split_for(const Sell &S, int64_t nblocks, int32_t opt_split) {
-    if (S.N <= 0 || S.N >= kSmallLevelRows) return 1;
+    if (S.N <= 0 || S.N >= kSplitLevelRows) return 1;
     if (opt_split > 0) return (int8_t)opt_split;
     const double w = (double)nblocks / S.N;
     int s = 1;
