@@ -44,11 +44,12 @@ TRAFFIC_PU1M = {"sweep": 542250086, "sweep_l1": 228149376, "spmv_internal": 1128
 TRAFFIC_KIND = ("L2-to-memory-fabric bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated); the Infinity "
                 "Cache serves part of them, so HBM itself moves at most this much")
 # Average duration of the same kernels inside timed bench steps (rocprofv3
-# --kernel-trace of the default run, W-cycle on level 0,
+# --kernel-trace of the default run: W-cycle on level 0, sweeps 1/2,
+# coarse damping 1.4,
 # profiles/bench_pu1M_kernel_stats.md); None where not measured for the
 # current kernel code.
-IN_STEP_US_PU1M = {"sweep": 84.38, "sweep_l1": 42.38, "spmv_internal": 180.80, "spmv_caller": None}
-IN_STEP_W_LEVELS = 1
+IN_STEP_US_PU1M = {"sweep": 84.32, "sweep_l1": 42.54, "spmv_internal": 182.65, "spmv_caller": None}
+IN_STEP_CYCLE = (1, 1.4, 1, 2)          # w_levels, coarse_omega, pre and post sweeps of that run
 
 
 def parse():
@@ -67,7 +68,8 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=500)
     ap.add_argument("--smoother", choices=["dilu", "sgs", "ilu0", "bjacobi"], default="bjacobi")
     ap.add_argument("--dilu-levels", type=int, default=2)
-    ap.add_argument("--sweeps", type=int, default=2)
+    ap.add_argument("--pre-sweeps", type=int, default=1)
+    ap.add_argument("--post-sweeps", type=int, default=2)
     ap.add_argument("--omega", type=float, default=0.9)
     ap.add_argument("--coarse-max", type=int, default=16)
     ap.add_argument("--passes", type=int, default=2)
@@ -83,6 +85,8 @@ def parse():
     ap.add_argument("--w-levels", type=int, default=1,
                     help="AMG cycle: W-cycle on this many finest levels (the next level's cycle runs twice), "
                          "0 = V-cycle")
+    ap.add_argument("--coarse-omega", type=float, default=1.4,
+                    help="block-Jacobi damping below level 0 (0 = --omega on every level)")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--assembly", action="store_true",
                     help="only the device assemblies (cbs_assemble_luo, 5x5; cbs_assemble_pu, 4x4) on an "
@@ -138,11 +142,11 @@ def _host_cpu():
     return {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(), "model": model}
 
 
-def cpu_baseline(s, w_levels=0, reps_max=3, budget_s=60.0):
+def cpu_baseline(s, cyc, reps_max=3, budget_s=60.0):
     """The CPU oracle on the same system as the GPU step: LDU -> block CSR,
-    reference AMG setup (block Jacobi V(2,2), omega 0.9, coarse_max 16, two
-    matching passes, the GPU step's cycle shape: W-cycle on the w_levels
-    finest levels) and BiCGStab to 1e-8, FP64, with the OpenMP threads of
+    reference AMG setup (block Jacobi, coarse_max 16, two matching passes,
+    and the GPU step's cycle: its sweeps, dampings and W levels) and
+    BiCGStab to 1e-8, FP64, with the OpenMP threads of
     the host.  One warm-up run, then the median of up to three runs (fewer
     when three would exceed the time budget).  Also one thread: conversion,
     setup and the first 5 iterations (the full solve would take minutes)."""
@@ -156,8 +160,9 @@ def cpu_baseline(s, w_levels=0, reps_max=3, budget_s=60.0):
         t0 = time.perf_counter()
         A = O.from_system(s)
         t1 = time.perf_counter()
-        amg = O.AMG(A, coarse_max=16, passes=2, smoother=O.SMOOTH_BJACOBI, nu1=2, nu2=2, omega=0.9,
-                    w_levels=w_levels)
+        amg = O.AMG(A, coarse_max=16, passes=2, smoother=O.SMOOTH_BJACOBI, nu1=cyc["pre_sweeps"],
+                    nu2=cyc["post_sweeps"], omega=cyc["omega"], w_levels=cyc["w_levels"],
+                    coarse_omega=cyc["coarse_omega"])
         t2 = time.perf_counter()
         _, st = O.bicgstab(A, s["b"], prec=O.PREC_AMG, amg=amg, tol=1e-8, maxit=maxit)
         t3 = time.perf_counter()
@@ -186,9 +191,11 @@ def cpu_baseline(s, w_levels=0, reps_max=3, budget_s=60.0):
         "cores": threads,
         "kind": "oracle",
         "sample": "the whole bench system (%d cells): oracle LDU -> block CSR, reference AMG setup (block-Jacobi "
-                  "V(2,2), omega 0.9, %s) and BiCGStab to 1e-8 in FP64 on %d OpenMP threads; one warm-up run, then "
-                  "the median of %d runs" % (s["N"], "W-cycle on the %d finest levels" % w_levels if w_levels
-                                             else "V-cycle", threads, reps),
+                  "sweeps %d/%d, omega %g, coarse omega %g, %s) and BiCGStab to 1e-8 in FP64 on %d OpenMP "
+                  "threads; one warm-up run, then the median of %d runs"
+                  % (s["N"], cyc["pre_sweeps"], cyc["post_sweeps"], cyc["omega"], cyc["coarse_omega"],
+                     "W-cycle on the %d finest levels" % cyc["w_levels"] if cyc["w_levels"] else "V-cycle",
+                     threads, reps),
         "runs_s": [round(r["total_s"], 3) for r in runs],
         "iterations": mid["iterations"],
         "phases_s": {k: round(mid[k], 3) for k in ("convert_s", "setup_s", "solve_s")},
@@ -449,7 +456,9 @@ def other_configs(args, P, torch, dev, only=None):
     from workloads import jacobian_batch, jacobian_stretched, pressure_velocity
     out = {}
     if only is None or only == "adjoint_pu_2M":
-        out.update(_adjoint_2M(P, torch, dev, pressure_velocity, args.w_levels))
+        out.update(_adjoint_2M(P, torch, dev, pressure_velocity, dict(
+            w_levels=args.w_levels, coarse_omega=args.coarse_omega, pre_sweeps=args.pre_sweeps,
+            post_sweeps=args.post_sweeps, omega=args.omega)))
     if only is None or only == "batch_64":
         out.update(_batch_64(P, torch, dev, jacobian_batch, 0))
     if only is None or only == "stretched_density_8M":
@@ -457,13 +466,13 @@ def other_configs(args, P, torch, dev, only=None):
     return out
 
 
-def _adjoint_2M(P, torch, dev, pressure_velocity, wl):
+def _adjoint_2M(P, torch, dev, pressure_velocity, cyc):
     out = {}
     t0 = time.time()
     s = pressure_velocity(200, 100, 100, seed=0)
     log("generated 2M p-U in %.1f s" % (time.time() - t0))
     out["adjoint_pu_2M"] = measure_system(
-        P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, tol=1e-8, w_levels=wl), 3, "adjoint_pu_2M",
+        P, torch, dev, s, P.default_options(precision=P.PRECISION_MIXED, tol=1e-8, **cyc), 3, "adjoint_pu_2M",
         "pressure-based p-U 4x4, 200x100x100 jittered renumbered hex mesh (N=%d); mixed AMG-BiCGStab to 1e-8, "
         "forward and transposed" % s["N"], transposed=True)
     return out
@@ -537,10 +546,10 @@ def main():
     common = dict(solver={"fgmres": P.SOLVER_FGMRES, "gmres": P.SOLVER_GMRES}.get(args.solver, P.SOLVER_BICGSTAB),
                   precond=P.PREC_SGS if args.precond == "sgs" else P.PREC_AMG, tol=1e-8, max_iter=args.max_iter,
                   smoother={"dilu": P.SMOOTH_DILU, "sgs": P.SMOOTH_SGS, "ilu0": P.SMOOTH_ILU0}.get(args.smoother, P.SMOOTH_BJACOBI),
-                  dilu_levels=args.dilu_levels, pre_sweeps=args.sweeps, post_sweeps=args.sweeps,
+                  dilu_levels=args.dilu_levels, pre_sweeps=args.pre_sweeps, post_sweeps=args.post_sweeps,
                   omega=args.omega, coarse_max=args.coarse_max, match_passes=args.passes,
                   row_split=args.row_split, tail_rows=args.tail_rows, scaled_sweeps=args.scaled_sweeps,
-                  w_levels=args.w_levels)
+                  w_levels=args.w_levels, coarse_omega=args.coarse_omega)
     opt_mixed = P.default_options(precision=P.PRECISION_MIXED, **common)
     opt_reuse = P.default_options(precision=P.PRECISION_MIXED, reuse_aggregates=1, **common)
     opt_fp64 = P.default_options(precision=P.PRECISION_FP64, **common)
@@ -683,7 +692,8 @@ def main():
         o = {"bound": "hbm", "kernel": name, "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(gb / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_PU1M[key] if full else None,
              "traffic_kind": TRAFFIC_KIND, "avg_launch_us": round(ms * 1e3, 2), "algorithmic_bytes": int(nbytes)}
-        us = IN_STEP_US_PU1M[key] if full and args.w_levels == IN_STEP_W_LEVELS else None
+        cyc = (args.w_levels, args.coarse_omega, args.pre_sweeps, args.post_sweeps)
+        us = IN_STEP_US_PU1M[key] if full and cyc == IN_STEP_CYCLE else None
         if us:
             o["in_step"] = {"avg_launch_us": us, "frac": round(nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                             "source": "rocprofv3 kernel trace of timed bench steps"}
@@ -708,7 +718,8 @@ def main():
                    "step": "pack fields + update_values + setup + solve + unpack fields",
                    "precond": args.precond, "max_iter": args.max_iter,
                    "solver": args.solver, "smoother": args.smoother, "dilu_levels": args.dilu_levels,
-                   "sweeps": args.sweeps, "omega": args.omega, "coarse_max": args.coarse_max,
+                   "pre_sweeps": args.pre_sweeps, "post_sweeps": args.post_sweeps, "omega": args.omega,
+                   "coarse_omega": args.coarse_omega, "coarse_max": args.coarse_max,
                    "match_passes": args.passes, "row_split": args.row_split,
                    "tail_rows": args.tail_rows, "scaled_sweeps": args.scaled_sweeps, "w_levels": args.w_levels},
         "step_ms_median": round(float(np.median(per_step)), 3),
@@ -755,7 +766,9 @@ def main():
         out["other_configs"] = other_configs(args, P, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline on the bench system")
-        out["cpu_baseline"] = cpu_baseline(s_host, args.w_levels)
+        out["cpu_baseline"] = cpu_baseline(s_host, dict(
+            w_levels=args.w_levels, coarse_omega=args.coarse_omega, pre_sweeps=args.pre_sweeps,
+            post_sweeps=args.post_sweeps, omega=args.omega))
     print(json.dumps(out), flush=True)
 
 

@@ -146,6 +146,9 @@ typedef struct cbs_options {
                                 beyond the depth: every level (W-cycle).
                                 The single-workgroup tail starts below these
                                 levels                               [0] */
+    double coarse_omega;     /* block-Jacobi damping on every level below the
+                                finest; 0 = omega there too (the paper
+                                leaves the damping open)             [0] */
 } cbs_options;
 
 /* Per-solve statistics (Algorithm amgxFoam: iterations and residuals). */

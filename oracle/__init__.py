@@ -93,7 +93,7 @@ def _declare(L):
         "orc_amg_level_info": (None, [vp, ci, C.POINTER(ci), C.POINTER(cl)]),
         "orc_amg_apply": (None, [vp, _f64p, _f64p]),
         "orc_amg_apply_fp32": (ci, [vp, _f64p, _f64p, ci]),
-        "orc_amg_set_cycle": (ci, [vp, ci]),
+        "orc_amg_set_cycle": (ci, [vp, ci, C.c_double]),
         "orc_bicgstab": (ci, [ci, ci, _i32p, _i32p, _f64p, ci, vp, _f64p, _f64p, cd, ci,
                               C.POINTER(ci), C.POINTER(cd)]),
         "orc_fgmres": (ci, [ci, ci, _i32p, _i32p, _f64p, ci, vp, _f64p, _f64p, cd, ci, ci,
@@ -347,11 +347,13 @@ class AMG:
     ``aggs``: optional list of aggregate maps (one per coarsened level) to
     impose a hierarchy; ``ranks``: optional DILU orderings per smoothed level;
     ``w_levels``: the coarse correction of each of the w_levels finest levels
-    runs the next level's cycle twice (a W-cycle there; 0 = V-cycle).
+    runs the next level's cycle twice (a W-cycle there; 0 = V-cycle);
+    ``coarse_omega``: block-Jacobi damping below level 0 (0 = ``omega``).
     """
 
     def __init__(self, A: BCSR, coarse_max=32, passes=2, smoother=SMOOTH_BJACOBI,
-                 nu1=1, nu2=1, omega=0.8, aggs=None, ranks=None, dilu_levels=-1, w_levels=0):
+                 nu1=1, nu2=1, omega=0.8, aggs=None, ranks=None, dilu_levels=-1, w_levels=0,
+                 coarse_omega=0.0):
         self._keep = []
         aggp, nag = None, 0
         if aggs is not None:
@@ -372,7 +374,7 @@ class AMG:
                                       aggp, nag, rk, nrk, int(dilu_levels))
         if not self.h:
             raise OracleError(ERR_SINGULAR, "amg_create")
-        rc = lib().orc_amg_set_cycle(self.h, int(w_levels))
+        rc = lib().orc_amg_set_cycle(self.h, int(w_levels), float(coarse_omega))
         if rc != OK:
             raise OracleError(rc, "amg_set_cycle")
 

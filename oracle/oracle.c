@@ -749,6 +749,7 @@ typedef struct {
     int n, nlev, smoother, nu1, nu2, dilu_levels;
     int w_levels;            /* cycle shape: W on the w_levels finest levels */
     double omega;
+    double omega_c;          /* damping below level 0; 0 = omega */
     olevel L[MAXLEV];
     double *LU; int *piv; int m;   /* coarsest level, dense LU */
     /* FP32 emulation (orc_amg_apply_fp32), built on first use: per level
@@ -912,7 +913,8 @@ static void smooth(oamg *A, olevel *c, const double *b, double *x)
     if (c->Dinv && c->rank) {
         orc_sgs_sweep(c->N, n, c->rp, c->col, c->val, c->Dinv, c->rank, b, x);
     } else if (c->Dinv) {
-        orc_bjacobi_sweep(c->N, n, c->rp, c->col, c->val, c->Dinv, b, x, c->r, A->omega);
+        const double w = (c != &A->L[0] && A->omega_c > 0.0) ? A->omega_c : A->omega;
+        orc_bjacobi_sweep(c->N, n, c->rp, c->col, c->val, c->Dinv, b, x, c->r, w);
         memcpy(x, c->r, sizeof(double) * m);
     } else {
         double *d = (double *)malloc(sizeof(double) * (m + 1));
@@ -962,11 +964,14 @@ void orc_amg_apply(void *h, const double *r, double *z)
     vcycle(A, 0, r, z, 1);
 }
 
-/* Cycle shape of orc_amg_apply (0 = V-cycle, the default). */
-int orc_amg_set_cycle(void *h, int w_levels)
+/* Cycle shape of orc_amg_apply (w_levels = 0: V-cycle, the default) and the
+ * block-Jacobi damping of the levels below level 0 (omega_c = 0: the
+ * hierarchy's omega on every level). */
+int orc_amg_set_cycle(void *h, int w_levels, double omega_c)
 {
-    if (w_levels < 0) return ORC_ERR_ARG;
+    if (w_levels < 0 || !(omega_c >= 0.0)) return ORC_ERR_ARG;
     ((oamg *)h)->w_levels = w_levels;
+    ((oamg *)h)->omega_c = omega_c;
     return ORC_OK;
 }
 
@@ -1104,12 +1109,12 @@ static void f32_vcycle(oamg *A, int l, int scaled)
 }
 
 /* z = fl-emulated V-cycle of fl(r), widened to FP64.  Block-Jacobi
- * hierarchies and V-cycles only (ORC_ERR_ARG for DILU, Gauss-Seidel or
- * ILU(0) levels, or a W-cycle shape). */
+ * hierarchies and V-cycles with one damping only (ORC_ERR_ARG for DILU,
+ * Gauss-Seidel or ILU(0) levels, a W-cycle shape or a coarse damping). */
 int orc_amg_apply_fp32(void *h, const double *r, double *z, int scaled)
 {
     oamg *A = (oamg *)h;
-    if (A->w_levels > 0) return ORC_ERR_ARG;       /* V-cycles only */
+    if (A->w_levels > 0 || A->omega_c > 0.0) return ORC_ERR_ARG;   /* V-cycles, one omega */
     for (int l = 0; l + 1 < A->nlev; l++)
         if (!A->L[l].Dinv || A->L[l].rank) return ORC_ERR_ARG;
     if (!A->f32_ready) f32_prepare(A);

@@ -37,7 +37,7 @@ class Options(C.Structure):
         ("max_levels", C.c_int32), ("reuse_aggregates", C.c_int32), ("check_every", C.c_int32),
         ("renumber", C.c_int32), ("dilu_levels", C.c_int32), ("row_split", C.c_int32),
         ("tail_rows", C.c_int32), ("schedule", C.c_int32), ("scaled_sweeps", C.c_int32),
-        ("w_levels", C.c_int32),
+        ("w_levels", C.c_int32), ("coarse_omega", C.c_double),
     ]
 
 

@@ -273,6 +273,7 @@ void cbs_default_options(cbs_options *o) {
     o->schedule = 0;
     o->scaled_sweeps = 1;
     o->w_levels = 0;
+    o->coarse_omega = 0.0;
 }
 
 int cbs_create_from_ldu(cbs_handle *out, int32_t n_cells, int32_t n_faces, int32_t bdim, const int32_t *lower_addr,
@@ -402,6 +403,7 @@ int cbs_setup(cbs_handle h, const cbs_options *opt) {
         require(o.schedule >= 0 && o.schedule <= 6, CBS_ERR_ARG, "schedule must be in 0..6");
         require(o.scaled_sweeps == 0 || o.scaled_sweeps == 1, CBS_ERR_ARG, "scaled_sweeps must be 0 or 1");
         require(o.w_levels >= 0, CBS_ERR_ARG, "w_levels must be >= 0");
+        require(o.coarse_omega >= 0.0, CBS_ERR_ARG, "coarse_omega must be >= 0 (0: omega on every level)");
         const bool keep = o.reuse_aggregates && h->setup_done && h->opt.precision == o.precision &&
                           h->opt.precond == o.precond && h->opt.smoother == o.smoother &&
                           h->opt.coarse_max == o.coarse_max && h->opt.match_passes == o.match_passes &&
@@ -553,7 +555,7 @@ int cbs_level_apply(cbs_handle h, int32_t level, int32_t op, const void *b, cons
         require(op == CBS_LEVEL_RESIDUAL || (!L.dilu && !L.sgs), CBS_ERR_STATE,
                 "a DILU or Gauss-Seidel level has no block-Jacobi sweep");
         const int n = h->n;
-        const double w = h->opt.omega;
+        const double w = level_omega(h->opt, level);
         hipStream_t st = h->stream;
         if (mixed) {
             const float *bb = static_cast<const float *>(b), *xx = static_cast<const float *>(x);

@@ -110,6 +110,12 @@ constexpr int32_t kSmallLevelRows = 65536;
 // already fills the chip, keep k_rows
 constexpr int32_t kSplitLevelRows = 32768;
 
+// block-Jacobi damping of level l: omega on level 0, coarse_omega (when set)
+// below it
+inline double level_omega(const cbs_options &o, int l) {
+    return (l > 0 && o.coarse_omega > 0.0) ? o.coarse_omega : o.omega;
+}
+
 // V-cycle tail (tail.hip): default block-row limit of its first level, and the
 // most levels (coarsest included) it takes
 constexpr int32_t kTailRowsDefault = 256;

@@ -570,6 +570,7 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
     Level &L = h->lev[l];
     const int64_t m = (int64_t)L.N * n;
     const int nu1 = std::max(0, o.pre_sweeps), nu2 = std::max(0, o.post_sweeps);
+    const double om = level_omega(o, l);
     constexpr bool fp32 = sizeof(T) == sizeof(float);
     const bool bj = l < nlev - 1 && !L.dilu && !L.sgs;
     const bool fuse_in = fp32 && b64 && bj && nu1 >= 1;
@@ -650,10 +651,10 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
     // y64: write the result widened to FP64 there instead of into `to`
     auto sweep = [&](T *from, T *to, const int32_t *pagg, const T *pe, double *y64) {
         if (scaled)
-            launch_rows<T, T>(4, n, L.sod.view(true), sval, from, c, to, nullptr, o.omega, st, nullptr, pagg, pe,
+            launch_rows<T, T>(4, n, L.sod.view(true), sval, from, c, to, nullptr, om, st, nullptr, pagg, pe,
                               y64);
         else
-            launch_rows<T, T>(2, n, L.sell.view(fp32), val, from, b, to, Dinv, o.omega, st, nullptr, pagg, pe, y64);
+            launch_rows<T, T>(2, n, L.sell.view(fp32), val, from, b, to, Dinv, om, st, nullptr, pagg, pe, y64);
     };
     if (!zero) {
         for (int s = 0; s < nu1; ++s) {
@@ -663,12 +664,12 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
     } else if (nu1 >= 1) {
         if (fuse_in) {
             if constexpr (fp32)
-                launch_cast_sweep0(n, L.N, b64, b, Dinv, o.omega, cur, c, st);
+                launch_cast_sweep0(n, L.N, b64, b, Dinv, om, cur, c, st);
         } else if (rfine) {
             launch_restrict_sweep0<T>(n, L.N, h->lev[l - 1].agg_ptr.get(), h->lev[l - 1].agg_mem.get(), rfine, b,
-                                      Dinv, o.omega, cur, c, st);
+                                      Dinv, om, cur, c, st);
         } else {
-            launch_rows<T, T>(3, n, L.sell.view(fp32), val, cur, b, cur, Dinv, o.omega, st, c);
+            launch_rows<T, T>(3, n, L.sell.view(fp32), val, cur, b, cur, Dinv, om, st, c);
         }
         for (int s = 1; s < nu1; ++s) {
             sweep(cur, oth, nullptr, nullptr, nullptr);
@@ -677,10 +678,10 @@ void vcycle(cbs_system *h, bool tr, int l, T *b, T *x, const T *rfine, const dou
     } else {
         if (rfine) restrict_into_b();
         if (scaled && nu2 > 0)   // c only; oth is scratch here
-            launch_rows<T, T>(3, n, L.sell.view(true), val, oth, b, oth, Dinv, o.omega, st, c);
+            launch_rows<T, T>(3, n, L.sell.view(true), val, oth, b, oth, Dinv, om, st, c);
         launch_fill<T>(m, cur, st);
     }
-    launch_rows<T, T>(1, n, L.sell.view(fp32), val, cur, b, r, Dinv, o.omega, st);
+    launch_rows<T, T>(1, n, L.sell.view(fp32), val, cur, b, r, Dinv, om, st);
     coarse(bc, xc, r);
     // On large levels the extra aggregate-map gathers cost more than the
     // separate prolongation pass; on small ones the saved launch wins.

@@ -474,7 +474,7 @@ void launch_tail(cbs_system *h, bool tr, int l0, const T *rfine) {
     a.coff = C.off.get();
     a.cm = C.m.get();
     a.croff = C.roff.get();
-    a.omega = h->opt.omega;
+    a.omega = level_omega(h->opt, l0);             // every tail level is below level 0
     a.nl = nl;
     a.nu1 = std::max(0, h->opt.pre_sweeps);
     a.nu2 = std::max(0, h->opt.post_sweeps);

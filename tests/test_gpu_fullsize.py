@@ -37,8 +37,9 @@ def _relres_ldu(s, x):
 def test_headline_pressure_velocity_1M_mixed_bicgstab():
     """The benchmark workload at full size: the 100^3 jittered, randomly
     renumbered p-U system (Sec. 2.2, Eq. coupl_system), mixed-precision
-    AMG-BiCGStab with the benchmark's options (W-cycle on level 0) to 1e-8,
-    and the same with a V-cycle.  Checks: the relative
+    AMG-BiCGStab with the benchmark's options (W-cycle on level 0, one pre-
+    and two post-sweeps, damping 1.4 below level 0) to 1e-8, and with the
+    library's default V(2,2)-cycle.  Checks: the relative
     residual recomputed by the oracle's face-loop product; the reported true
     residual equals it; the Krylov recurrence's residual agrees with the true
     one within 10 tol; no escalation to FP64; and (reading R5) a verification
@@ -49,10 +50,11 @@ def test_headline_pressure_velocity_1M_mixed_bicgstab():
     _say("generated 1M p-U system in %.1f s" % (time.time() - t0))
     tol = 1e-8
     opt = dict(precision=P.PRECISION_MIXED, solver=P.SOLVER_BICGSTAB, precond=P.PREC_AMG, tol=tol,
-               max_iter=500, omega=0.9, pre_sweeps=2, post_sweeps=2, coarse_max=16, match_passes=2, w_levels=1)
+               max_iter=500, omega=0.9, pre_sweeps=1, post_sweeps=2, coarse_max=16, match_passes=2, w_levels=1,
+               coarse_omega=1.4)
     with P.System.from_dict(s) as sysm:
         for wl in (0, 1):
-            sysm.setup(**dict(opt, w_levels=wl))
+            sysm.setup(**(opt if wl else dict(opt, w_levels=0, pre_sweeps=2, coarse_omega=0.0)))
             x, st = sysm.solve(s["b"])
             _say("gpu 1e-8, w_levels %d:" % wl, st)
             assert st["status"] == P.OK and st["precision_fallback"] == 0, st
@@ -82,15 +84,16 @@ def test_headline_pressure_velocity_1M_mixed_bicgstab():
 
 
 def test_headline_w_cycle_elementwise():
-    """One mixed-precision W-cycle (the benchmark's preconditioner) on the
+    """One mixed-precision cycle with the benchmark's options (W on level 0,
+    sweeps 1/2, damping 1.4 below level 0) on the
     1M-cell p-U system against the oracle's FP64 W-cycle on the GPU's
     hierarchy, element by element: at this size level 1 (about 215,000 block
     rows) runs its second cycle through the tuned large-level kernels."""
     s = pressure_velocity(100, 100, 100, seed=0)
     N, n = int(s["N"]), int(s["n"])
     with P.System.from_dict(s) as sysm:
-        sysm.setup(precision=P.PRECISION_MIXED, precond=P.PREC_AMG, omega=0.9, pre_sweeps=2, post_sweeps=2,
-                   coarse_max=16, match_passes=2, w_levels=1)
+        sysm.setup(precision=P.PRECISION_MIXED, precond=P.PREC_AMG, omega=0.9, pre_sweeps=1, post_sweeps=2,
+                   coarse_max=16, match_passes=2, w_levels=1, coarse_omega=1.4)
         nlev = sysm.info()["levels"]
         assert sysm.get_level(1)["N"] >= 65536
         lv0 = sysm.get_level(0)
@@ -99,7 +102,7 @@ def test_headline_w_cycle_elementwise():
         aggs = [_np(sysm.get_level(l)["agg"]) for l in range(nlev - 1)]
         r = np.random.default_rng(11).standard_normal((N, n))
         z = _np(sysm.apply_precond(r))
-    zr_int = O.AMG(A0, nu1=2, nu2=2, omega=0.9, aggs=aggs, w_levels=1).apply(r[order])
+    zr_int = O.AMG(A0, nu1=1, nu2=2, omega=0.9, aggs=aggs, w_levels=1, coarse_omega=1.4).apply(r[order])
     zr = np.empty_like(zr_int)
     zr[order] = zr_int
     d = np.abs(z - zr).max() / np.abs(zr).max()

@@ -52,14 +52,15 @@ _ORACLE_SMOOTHER = {P.SMOOTH_BJACOBI: O.SMOOTH_BJACOBI, P.SMOOTH_DILU: O.SMOOTH_
 
 
 def _cycle_pair(s, w_levels, precision=P.PRECISION_FP64, pre=2, post=2, omega=0.9, tail=0,
-                smoother=P.SMOOTH_BJACOBI, dilu_levels=2, transpose=False, seed=0):
+                smoother=P.SMOOTH_BJACOBI, dilu_levels=2, transpose=False, seed=0, coarse_omega=0.0):
     """GPU cycle z = M r (or M^T r) and the oracle's cycle of the same shape
     on the GPU's level-0 numbering, aggregates and colours (on A^T for the
     transposed one); also the oracle's V-cycle, to show the shapes differ."""
     N, n = int(s["N"]), int(s["n"])
     with P.System.from_dict(s) as sysm:
         sysm.setup(precond=P.PREC_AMG, precision=precision, coarse_max=8, pre_sweeps=pre, post_sweeps=post,
-                   omega=omega, tail_rows=tail, smoother=smoother, dilu_levels=dilu_levels, w_levels=w_levels)
+                   omega=omega, tail_rows=tail, smoother=smoother, dilu_levels=dilu_levels, w_levels=w_levels,
+                   coarse_omega=coarse_omega)
         nlev = sysm.info()["levels"]
         assert nlev >= 4, nlev
         lv0 = sysm.get_level(0)
@@ -75,7 +76,7 @@ def _cycle_pair(s, w_levels, precision=P.PRECISION_FP64, pre=2, post=2, omega=0.
         r = np.random.default_rng(seed).standard_normal((N, n))
         z = _np(sysm.apply_precond(r, transpose=transpose))
     Aref = O.transpose(A0) if transpose else A0
-    kw = dict(nu1=pre, nu2=post, omega=omega, aggs=aggs)
+    kw = dict(nu1=pre, nu2=post, omega=omega, aggs=aggs, coarse_omega=coarse_omega)
     if smoother != P.SMOOTH_BJACOBI:
         kw.update(smoother=_ORACLE_SMOOTHER[smoother], ranks=ranks, dilu_levels=ndilu)
     out = []
@@ -202,3 +203,41 @@ def test_w_levels_out_of_range_is_refused():
     with P.System.from_dict(s) as sysm:
         with pytest.raises(P.CbsError):
             sysm.setup(precond=P.PREC_AMG, w_levels=-1)
+
+
+@pytest.mark.parametrize("tail", [-1, 0])
+@pytest.mark.parametrize("w_levels", [0, 1])
+@pytest.mark.parametrize("precision", [P.PRECISION_FP64, P.PRECISION_MIXED])
+def test_coarse_damping_matches_oracle(precision, w_levels, tail):
+    """coarse_omega: the block-Jacobi damping of every level below level 0
+    (the per-step kernels, the zero-guess sweeps fused into the restriction
+    and the one-workgroup tail), against the oracle's cycle with the same
+    two dampings."""
+    _say("coarse damping", precision, "w_levels", w_levels, "tail", tail)
+    s = pressure_velocity(14, 12, 11, seed=69)
+    z, zr, _ = _cycle_pair(s, w_levels, precision, tail=tail, coarse_omega=1.3)
+    _agree(z, zr, _tol(precision))
+    z1, _, _ = _cycle_pair(s, w_levels, precision, tail=tail)
+    assert np.linalg.norm(z1 - zr) > 1e3 * _tol(precision) * np.linalg.norm(zr)   # the damping is applied
+
+
+def test_coarse_damping_level_kernel():
+    """cbs_level_apply's sweep on a coarse level uses coarse_omega, on level 0
+    omega: y = x + w D^{-1} (b - A x) against the oracle's sweep."""
+    s = pressure_velocity(12, 10, 9, seed=70)
+    n = int(s["n"])
+    with P.System.from_dict(s) as sysm:
+        sysm.setup(precond=P.PREC_AMG, coarse_max=8, omega=0.8, coarse_omega=1.25)
+        rng = np.random.default_rng(3)
+        for lev, w in ((0, 0.8), (1, 1.25)):
+            lv = sysm.get_level(lev)
+            N = lv["N"]
+            A = O.BCSR(N, n, _np(lv["row_ptr"]), _np(lv["col"]), _np(lv["vals"]))
+            b = rng.standard_normal((N, n)); x = rng.standard_normal((N, n))
+            y = _np(sysm.level_apply(lev, P.LEVEL_SWEEP, b, x))
+            rows = np.repeat(np.arange(N), np.diff(A.row_ptr))
+            D = A.vals.reshape(-1, n, n)[rows == A.col]
+            yr = O.bjacobi_sweep(A, O.blockinv(D), b, x, w)
+            _agree(y, yr.reshape(N, n), 1e-13)
+        with pytest.raises(P.CbsError):
+            sysm.setup(precond=P.PREC_AMG, coarse_omega=-1.0)

@@ -229,3 +229,41 @@ def test_w_cycle_preconditioned_solve():
     assert O.relres(A, s["b"], xw) <= 1e-10
     assert stw["iterations"] <= stv["iterations"]
     assert O.AMG(A, w_levels=1, **kw).levels >= 3
+
+
+def test_coarse_damping_closed_form():
+    # The same three-level hierarchy with damping w0 on level 0 and w1 below
+    # it: S0 = I - w0 D0^{-1} A0, S1 = I - w1 D1^{-1} A1, for the V- and the
+    # W-cycle.  A cycle that used w0 everywhere (or w1 everywhere) fails it.
+    s = jacobian_box(5, 4, 3, n=3, seed=9)
+    A = O.from_system(s)
+    n, w0, w1 = 3, 0.7, 1.2
+    agg0, nc0 = O.match(A.N, A.row_ptr, A.col, O.strength(A))
+    A1 = O.rap(A, agg0, nc0)
+    agg1, nc1 = O.match(A1.N, A1.row_ptr, A1.col, O.strength(A1))
+    Ad, A1d = A.dense(), A1.dense()
+    P0, P1 = _P(agg0, nc0, n), _P(agg1, nc1, n)
+    A2d = P1.T @ A1d @ P1
+    I0, I1 = np.eye(Ad.shape[0]), np.eye(A1d.shape[0])
+    A0i, A1i = np.linalg.inv(Ad), np.linalg.inv(A1d)
+    r = np.random.default_rng(6).standard_normal(Ad.shape[0])
+
+    def cycle_op(wa, wb, twice):
+        S0 = I0 - wa * np.linalg.solve(_dense_blocks(Ad, n), Ad)
+        S1 = I1 - wb * np.linalg.solve(_dense_blocks(A1d, n), A1d)
+        E1 = S1 @ (I1 - P1 @ np.linalg.solve(A2d, P1.T @ A1d)) @ S1
+        B1 = (I1 - (E1 @ E1 if twice else E1)) @ A1i
+        E0 = S0 @ (I0 - P0 @ B1 @ P0.T @ Ad) @ S0
+        return (I0 - E0) @ A0i
+
+    for wl in (0, 1):
+        z = O.AMG(A, nu1=1, nu2=1, omega=w0, aggs=[agg0, agg1], w_levels=wl,
+                  coarse_omega=w1).apply(r.reshape(-1, n)).ravel()
+        ref = cycle_op(w0, w1, wl == 1) @ r
+        sc = np.abs(ref).max()
+        assert np.abs(z - ref).max() <= 1e-11 * sc
+        assert np.abs(cycle_op(w0, w0, wl == 1) @ r - ref).max() > 1e-3 * sc
+        assert np.abs(cycle_op(w1, w1, wl == 1) @ r - ref).max() > 1e-3 * sc
+    # coarse_omega 0 is the hierarchy's omega on every level
+    z0 = O.AMG(A, nu1=1, nu2=1, omega=w0, aggs=[agg0, agg1], coarse_omega=0.0).apply(r.reshape(-1, n))
+    assert np.array_equal(z0, O.AMG(A, nu1=1, nu2=1, omega=w0, aggs=[agg0, agg1]).apply(r.reshape(-1, n)))
