@@ -6,13 +6,16 @@ Workload: the pressure-based coupled (p, Ux, Uy, Uz) 4x4 system on a
 internal faces; seeded synthetic input).  One step = the whole hot path on
 resident device data: LDU -> block-CSR value conversion, AMG setup (FP32
 hierarchy, FP64 block inverses and coarse solve) and the mixed-precision
-AMG-BiCGStab solve to ||b - A x|| / ||b|| <= 1e-8 from x0 = 0.
+AMG-BiCGStab solve to ||b - A x|| / ||b|| <= 1e-8 from x0 = 0.  The AMG
+cycle: W on level 0, one pre- and two post-smoothing block-Jacobi sweeps,
+damping 0.9 on level 0 and 1.4 below it (each a command-line option).
 
 Also reported: the plain FP64 GPU path on the same system (mixed vs FP64),
-the values-only re-setup + solve variant, the level-0 smoothing sweep (the
-kernel with the largest share of the step) and the FP64 block SpMV against
-the HBM roofline next to a measured copy peak, and the CPU oracle timed on a
-bounded sample of the same workload.
+the values-only re-setup + solve variant, the level-1 smoothing sweep (the
+kernel launch with the largest share of the step with a W-cycle; the level-0
+sweep with a V-cycle), the other level's sweep and the FP64 block SpMV
+against the HBM roofline next to a measured copy peak, the CPU oracle timed
+on the same system, and three other workloads.
 """
 from __future__ import annotations
 
